@@ -1,0 +1,325 @@
+"""Plain FP64 CPU oracle of the hybrid fluid-kinetic step (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  It shares no code with the HIP library;
+both are driven from the same plain config dictionaries (see
+``paper_2510_11174_amd.configs``), which hold parameters and no arithmetic of the
+method.
+
+The C sources in this directory follow the paper's stage order (Methodology,
+pipeline paragraph) and the literature formulas it names; see each file's
+header for the passage it restates.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SOURCES = ["philox.c", "fields.c", "particles.c", "fluid.c", "switch.c", "ionize.c",
+            "qed.c", "cnn.c", "sim.c"]
+
+MAX_SPECIES = 6
+MAX_LEVELS = 8
+
+KIND = {"electron": 0, "ion": 1, "positron": 2, "photon": 3}
+PROFILE = {"none": 0, "uniform": 1, "ramp": 2, "foil": 3}
+SWITCH = {"all_pic": 0, "threshold": 1, "cnn": 2, "all_fluid": 3, "fixed": 4}
+BC = {"periodic": 0, "open": 1}
+COMP = {"ex": 0, "ey": 1, "ez": 2, "bx": 3, "by": 4, "bz": 5, "jx": 6, "jy": 7, "jz": 8}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with plain gcc (-O2, FP64, no intrinsics)."""
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES]
+    if not force and os.path.exists(_LIB_PATH):
+        newest = max(os.path.getmtime(s) for s in srcs + [os.path.join(_HERE, "oracle.h"),
+                                                           os.path.join(_HERE, "or_internal.h")])
+        if os.path.getmtime(_LIB_PATH) >= newest:
+            return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp",
+           "-Wall", "-Wno-unused-function", "-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("bc_x", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("dt", C.c_double)]
+
+
+class Species(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("ppc", C.c_int32), ("profile", C.c_int32),
+                ("mobile", C.c_int32), ("fluid", C.c_int32), ("ionizable", C.c_int32),
+                ("z_max", C.c_int32), ("target", C.c_int32), ("qed", C.c_int32),
+                ("pad", C.c_int32), ("charge", C.c_double), ("mass", C.c_double),
+                ("n0", C.c_double), ("x0", C.c_double), ("length", C.c_double),
+                ("u_th", C.c_double), ("ip_ev", C.c_double * MAX_LEVELS)]
+
+
+class Laser(C.Structure):
+    _fields_ = [("enabled", C.c_int32), ("polarization", C.c_int32), ("i_antenna", C.c_int32),
+                ("pad", C.c_int32), ("a0", C.c_double), ("waist", C.c_double),
+                ("duration", C.c_double), ("t_center", C.c_double), ("lambda_um", C.c_double)]
+
+
+class Run(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("switch_mode", C.c_int32), ("switch_every", C.c_int32),
+                ("dilation", C.c_int32), ("hysteresis", C.c_int32),
+                ("enable_ionization", C.c_int32), ("enable_qed", C.c_int32),
+                ("thr_a", C.c_double), ("thr_grad", C.c_double), ("thr_sigma_u", C.c_double),
+                ("thr_ion", C.c_double), ("thr_chi", C.c_double), ("n_floor", C.c_double),
+                ("spawn_frac", C.c_double)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("t", C.c_double), ("step", C.c_int64), ("u_e", C.c_double), ("u_b", C.c_double),
+                ("kin", C.c_double * MAX_SPECIES), ("fluid_kin", C.c_double * MAX_SPECIES),
+                ("count", C.c_double * MAX_SPECIES), ("fluid_mass", C.c_double * MAX_SPECIES),
+                ("charge_total", C.c_double), ("gauss_max", C.c_double), ("gauss_l2", C.c_double),
+                ("conv_loss", C.c_double), ("ion_energy", C.c_double),
+                ("photon_energy", C.c_double), ("kinetic_fraction", C.c_double),
+                ("fallback_fraction", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = C.CDLL(_LIB_PATH)
+        P = C.POINTER
+        L.or_create.restype = C.c_void_p
+        L.or_create.argtypes = [P(Grid), P(Species), C.c_int, P(Laser), P(Run)]
+        L.or_destroy.argtypes = [C.c_void_p]
+        L.or_step.argtypes = [C.c_void_p, C.c_int]
+        L.or_field_size.restype = C.c_size_t
+        L.or_field_size.argtypes = [C.c_void_p]
+        L.or_get_field.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
+        L.or_set_field.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
+        L.or_particle_count.restype = C.c_size_t
+        L.or_particle_count.argtypes = [C.c_void_p, C.c_int]
+        L.or_get_particles.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 6
+        L.or_set_particles.argtypes = [C.c_void_p, C.c_int, C.c_size_t] + [C.c_void_p] * 6
+        L.or_get_fluid.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+        L.or_set_fluid.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+        L.or_get_switch.argtypes = [C.c_void_p, C.c_void_p]
+        L.or_set_switch.argtypes = [C.c_void_p, C.c_void_p]
+        L.or_set_switch_mode.argtypes = [C.c_void_p, C.c_int]
+        L.or_diagnostics.argtypes = [C.c_void_p, P(Diag)]
+        L.or_get_rho.argtypes = [C.c_void_p, C.c_void_p]
+        L.or_get_divE.argtypes = [C.c_void_p, C.c_void_p]
+        L.or_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_uniform.restype = C.c_double
+        L.or_uniform.argtypes = [C.c_uint32]
+        L.or_boris.argtypes = [C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_adk_rate.restype = C.c_double
+        L.or_adk_rate.argtypes = [C.c_double] * 3
+        L.or_ionization_rate.restype = C.c_double
+        L.or_ionization_rate.argtypes = [C.c_double] * 4
+        L.or_esirkepov.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def structs(cfg: dict):
+    """Marshal a config dictionary into the oracle's C structs."""
+    g = cfg["grid"]
+    grid = Grid(nx=g["nx"], ny=g["ny"], nz=g["nz"], bc_x=BC[g.get("bc_x", "open")],
+                dx=g["dx"], dy=g["dy"], dz=g["dz"], dt=g["dt"])
+    sps = (Species * MAX_SPECIES)()
+    for i, s in enumerate(cfg["species"]):
+        sp = sps[i]
+        sp.kind = KIND[s["kind"]]
+        sp.ppc = s.get("ppc", 0)
+        sp.profile = PROFILE[s.get("profile", "none")]
+        sp.mobile = int(s.get("mobile", True))
+        sp.fluid = int(s.get("fluid", False))
+        sp.ionizable = int(s.get("ionizable", False))
+        sp.z_max = s.get("z_max", 0)
+        sp.target = s.get("target", 0)
+        sp.qed = int(s.get("qed", False))
+        sp.charge = s["charge"]
+        sp.mass = s["mass"]
+        sp.n0 = s.get("n0", 0.0)
+        sp.x0 = s.get("x0", 0.0)
+        sp.length = s.get("length", 1.0)
+        sp.u_th = s.get("u_th", 0.0)
+        for k, v in enumerate(s.get("ip_ev", [])):
+            sp.ip_ev[k] = v
+    las = cfg.get("laser", {})
+    laser = Laser(enabled=int(las.get("enabled", False)),
+                  polarization=1 if las.get("polarization", "linear") == "circular" else 0,
+                  i_antenna=las.get("i_antenna", 2), a0=las.get("a0", 0.0),
+                  waist=las.get("waist", 1.0), duration=las.get("duration", 1.0),
+                  t_center=las.get("t_center", 0.0), lambda_um=las.get("lambda_um", 0.8))
+    r = cfg["run"]
+    run = Run(seed=r["seed"], switch_mode=SWITCH[r.get("switch_mode", "all_pic")],
+              switch_every=r.get("switch_every", 1), dilation=r.get("dilation", 1),
+              hysteresis=r.get("hysteresis", 2),
+              enable_ionization=int(r.get("enable_ionization", False)),
+              enable_qed=int(r.get("enable_qed", False)),
+              thr_a=r.get("thr_a", 0.5), thr_grad=r.get("thr_grad", 0.2),
+              thr_sigma_u=r.get("thr_sigma_u", 0.05), thr_ion=r.get("thr_ion", 1e-6),
+              thr_chi=r.get("thr_chi", 1e-3), n_floor=r.get("n_floor", 1e-10),
+              spawn_frac=r.get("spawn_frac", 0.5))
+    return grid, sps, len(cfg["species"]), laser, run
+
+
+class Oracle:
+    """One oracle simulation (FP64, host memory)."""
+
+    def __init__(self, cfg: dict):
+        self.cfg = cfg
+        self._structs = structs(cfg)
+        grid, sps, ns, laser, run = self._structs
+        if run.enable_qed:
+            raise NotImplementedError("QED is not part of the oracle yet")
+        self.h = lib().or_create(C.byref(grid), sps, ns, C.byref(laser), C.byref(run))
+        if not self.h:
+            raise RuntimeError("or_create failed")
+        self.nx, self.ny, self.nz = grid.nx, grid.ny, grid.nz
+        self.nspecies = ns
+
+    def close(self):
+        if self.h:
+            lib().or_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx + 1)
+
+    def step(self, n: int = 1):
+        lib().or_step(self.h, n)
+
+    def get_field(self, comp) -> np.ndarray:
+        c = COMP[comp] if isinstance(comp, str) else comp
+        out = np.empty(self.shape, np.float64)
+        if lib().or_get_field(self.h, c, _ptr(out)) != 0:
+            raise ValueError(comp)
+        return out
+
+    def set_field(self, comp, arr):
+        c = COMP[comp] if isinstance(comp, str) else comp
+        a = np.ascontiguousarray(arr, np.float64).reshape(self.shape)
+        lib().or_set_field(self.h, c, _ptr(a))
+
+    def count(self, sp: int) -> int:
+        return lib().or_particle_count(self.h, sp)
+
+    def get_particles(self, sp: int) -> dict:
+        n = self.count(sp)
+        x = np.empty((n, 3)); u = np.empty((n, 3)); w = np.empty(n)
+        idv = np.empty(n, np.uint64); z = np.empty(n, np.int32); tau = np.empty(n)
+        lib().or_get_particles(self.h, sp, _ptr(x), _ptr(u), _ptr(w), _ptr(idv), _ptr(z), _ptr(tau))
+        return {"x": x, "u": u, "w": w, "id": idv, "z": z, "tau": tau}
+
+    def set_particles(self, sp: int, x, u, w, ids=None, z=None, tau=None):
+        x = np.ascontiguousarray(x, np.float64); u = np.ascontiguousarray(u, np.float64)
+        w = np.ascontiguousarray(w, np.float64)
+        n = len(w)
+        ids = np.ascontiguousarray(ids if ids is not None else np.arange(n), np.uint64)
+        z = None if z is None else np.ascontiguousarray(z, np.int32)
+        tau = None if tau is None else np.ascontiguousarray(tau, np.float64)
+        lib().or_set_particles(self.h, sp, n, _ptr(x), _ptr(u), _ptr(w), _ptr(ids), _ptr(z), _ptr(tau))
+
+    def get_fluid(self, sp: int):
+        n = np.empty(self.shape); u = np.empty(self.shape + (3,))
+        if lib().or_get_fluid(self.h, sp, _ptr(n), _ptr(u)) != 0:
+            raise ValueError("species %d has no fluid" % sp)
+        return n, u
+
+    def set_fluid(self, sp: int, n, u):
+        n = np.ascontiguousarray(n, np.float64).reshape(self.shape)
+        u = np.ascontiguousarray(u, np.float64).reshape(self.shape + (3,))
+        if lib().or_set_fluid(self.h, sp, _ptr(n), _ptr(u)) != 0:
+            raise ValueError("species %d has no fluid" % sp)
+
+    def get_switch(self) -> np.ndarray:
+        out = np.empty(self.shape, np.uint8)
+        lib().or_get_switch(self.h, _ptr(out))
+        return out
+
+    def set_switch(self, m):
+        m = np.ascontiguousarray(m, np.uint8).reshape(self.shape)
+        lib().or_set_switch(self.h, _ptr(m))
+
+    def set_switch_mode(self, mode: str):
+        lib().or_set_switch_mode(self.h, SWITCH[mode])
+
+    def diagnostics(self) -> dict:
+        d = Diag()
+        lib().or_diagnostics(self.h, C.byref(d))
+        out = {}
+        for name, _ in Diag._fields_:
+            v = getattr(d, name)
+            out[name] = list(v)[: self.nspecies] if hasattr(v, "__len__") else v
+        return out
+
+    def rho(self) -> np.ndarray:
+        out = np.empty(self.shape)
+        lib().or_get_rho(self.h, _ptr(out))
+        return out
+
+    def divE(self) -> np.ndarray:
+        out = np.empty(self.shape)
+        lib().or_get_divE(self.h, _ptr(out))
+        return out
+
+
+# ---- building blocks for the closed-form pins --------------------------------------------
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, np.uint32); k = np.ascontiguousarray(key, np.uint32)
+    out = np.empty(4, np.uint32)
+    lib().or_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def uniform(x: int) -> float:
+    return lib().or_uniform(int(x) & 0xFFFFFFFF)
+
+
+def boris(qm, dt, e, b, u) -> np.ndarray:
+    e = np.ascontiguousarray(e, np.float64); b = np.ascontiguousarray(b, np.float64)
+    uu = np.array(u, np.float64)
+    lib().or_boris(qm, dt, _ptr(e), _ptr(b), _ptr(uu))
+    return uu
+
+
+def adk_rate(F, ip, zres) -> float:
+    return lib().or_adk_rate(F, ip, zres)
+
+
+def ionization_rate(F, ip, zres, omega) -> float:
+    return lib().or_ionization_rate(F, ip, zres, omega)
+
+
+def esirkepov(x0, x1, qw_dv, dt, dx):
+    x0 = np.ascontiguousarray(x0, np.float64); x1 = np.ascontiguousarray(x1, np.float64)
+    dx = np.ascontiguousarray(dx, np.float64)
+    jx = np.empty(27); jy = np.empty(27); jz = np.empty(27); base = np.empty(3, np.int32)
+    lib().or_esirkepov(_ptr(x0), _ptr(x1), qw_dv, dt, _ptr(dx), _ptr(jx), _ptr(jy), _ptr(jz), _ptr(base))
+    # index n = a + 3 (b + 3 c): reshape to [c][b][a] then transpose to [a][b][c]
+    f = lambda j: j.reshape(3, 3, 3).transpose(2, 1, 0)
+    return f(jx), f(jy), f(jz), base

@@ -1,0 +1,126 @@
+/*
+ * Oracle cold relativistic fluid (one fluid per fluid-capable species).
+ *
+ * Paper: Methodology, plasma-model paragraph (continuity and momentum
+ * equations with relativistic gamma for the bulk plasma).  The pressure and
+ * energy equations of the paper's warm model are left out: the fluid here is
+ * cold, so it carries density n and momentum u = gamma v only.
+ *
+ * Discretisation (node-centred n, u; fluxes on the faces where J lives):
+ *  1. us = Boris(u^{n-1/2}; E^n, B^n interpolated to the node);
+ *  2. v = us / gamma(us);
+ *  3. face velocity = mean of the two nodes, or the velocity of the only side
+ *     above the density floor; donor-cell mass flux F = v_f n_donor and
+ *     momentum flux G = F us_donor;
+ *  4. n^{n+1} = n - dt div F, (n u)^{n+1/2} = n us - dt div G;
+ *  5. J^{n+1/2} += q F on the faces, which makes the fluid charge obey the
+ *     same discrete continuity equation as the Esirkepov particle current.
+ */
+#include "or_internal.h"
+
+void or_fluid_phase(or_sim *s) {
+    const or_grid *g = &s->g;
+    int per = g->bc_x == OR_BC_PERIODIC;
+    double floor_n = s->run.n_floor;
+    double dxs[3] = {g->dx, g->dy, g->dz};
+    int nmax[3] = {per ? g->nx : g->nx + 1, g->ny, g->nz};
+    for (int isp = 0; isp < s->nsp; ++isp) {
+        if (!s->fn[isp]) continue;
+        const or_species *sp = &s->sp[isp];
+        double qm = sp->charge / sp->mass;
+        double *n = s->fn[isp];
+        size_t nn = s->nn;
+        double *us = (double *)calloc(nn * 3, sizeof(double));  /* us */
+        double *v = (double *)calloc(nn * 3, sizeof(double));
+        /* 1-2: Lorentz force at every node holding fluid. */
+        for (int k = 0; k < g->nz; ++k)
+            for (int j = 0; j < g->ny; ++j)
+                for (int i = 0; i < nmax[0]; ++i) {
+                    size_t c = or_idx(s, i, j, k);
+                    if (n[c] <= 0.0) continue;
+                    double e[3], b[3], u[3];
+                    for (int d = 0; d < 3; ++d) {
+                        e[d] = or_gather(s, OR_EX + d, i, j, k);
+                        b[d] = or_gather(s, OR_BX + d, i, j, k);
+                        u[d] = s->fu[isp][d][c];
+                    }
+                    or_boris(qm, g->dt, e, b, u);
+                    double gam = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                    for (int d = 0; d < 3; ++d) {
+                        us[3 * c + d] = u[d];
+                        v[3 * c + d] = u[d] / gam;
+                    }
+                }
+        /* 3: fluxes on the faces between node c and its +d neighbour. */
+        double *F = (double *)calloc(nn * 3, sizeof(double));
+        double *G = (double *)calloc(nn * 9, sizeof(double));
+        for (int k = 0; k < g->nz; ++k)
+            for (int j = 0; j < g->ny; ++j)
+                for (int i = 0; i < nmax[0]; ++i) {
+                    size_t c = or_idx(s, i, j, k);
+                    for (int d = 0; d < 3; ++d) {
+                        int ii = i, jj = j, kk = k;
+                        if (d == 0) {
+                            if (!per && i == g->nx) continue;   /* no face beyond the wall */
+                            ii = per ? or_wrap(i + 1, g->nx) : i + 1;
+                        } else if (d == 1) jj = or_wrap(j + 1, g->ny);
+                        else kk = or_wrap(k + 1, g->nz);
+                        size_t r = or_idx(s, ii, jj, kk);
+                        double nl = n[c], nr = n[r];
+                        int lok = nl > floor_n, rok = nr > floor_n;
+                        double vf;
+                        if (!lok && !rok) vf = 0.0;
+                        else if (!lok) vf = v[3 * r + d];
+                        else if (!rok) vf = v[3 * c + d];
+                        else vf = 0.5 * (v[3 * c + d] + v[3 * r + d]);
+                        size_t don = vf > 0.0 ? c : r;
+                        double flux = vf * n[don];
+                        F[3 * c + d] = flux;
+                        for (int m = 0; m < 3; ++m) G[9 * c + 3 * d + m] = flux * us[3 * don + m];
+                    }
+                }
+        /* 4: conservative update. */
+        double *nnew = (double *)calloc(nn, sizeof(double));
+        for (int k = 0; k < g->nz; ++k)
+            for (int j = 0; j < g->ny; ++j)
+                for (int i = 0; i < nmax[0]; ++i) {
+                    size_t c = or_idx(s, i, j, k);
+                    double dn = 0.0, dm[3] = {0, 0, 0};
+                    for (int d = 0; d < 3; ++d) {
+                        int ii = i, jj = j, kk = k;
+                        int has_minus = 1;
+                        if (d == 0) {
+                            if (!per && i == 0) has_minus = 0;
+                            ii = per ? or_wrap(i - 1, g->nx) : i - 1;
+                        } else if (d == 1) jj = or_wrap(j - 1, g->ny);
+                        else kk = or_wrap(k - 1, g->nz);
+                        double fplus = (d == 0 && !per && i == g->nx) ? 0.0 : F[3 * c + d];
+                        double fminus = has_minus ? F[3 * or_idx(s, ii, jj, kk) + d] : 0.0;
+                        dn += (fplus - fminus) / dxs[d];
+                        for (int m = 0; m < 3; ++m) {
+                            double gp = (d == 0 && !per && i == g->nx) ? 0.0 : G[9 * c + 3 * d + m];
+                            double gm = has_minus ? G[9 * or_idx(s, ii, jj, kk) + 3 * d + m] : 0.0;
+                            dm[m] += (gp - gm) / dxs[d];
+                        }
+                    }
+                    double nv = n[c] - g->dt * dn;
+                    nnew[c] = nv;
+                    for (int m = 0; m < 3; ++m) {
+                        double mom = n[c] * us[3 * c + m] - g->dt * dm[m];
+                        s->fu[isp][m][c] = nv > floor_n ? mom / nv : 0.0;
+                    }
+                }
+        memcpy(n, nnew, sizeof(double) * nn);
+        /* 5: fluid current on the J faces. */
+        for (int k = 0; k < g->nz; ++k)
+            for (int j = 0; j < g->ny; ++j)
+                for (int i = 0; i < nmax[0]; ++i) {
+                    size_t c = or_idx(s, i, j, k);
+                    for (int d = 0; d < 3; ++d) {
+                        if (d == 0 && !per && i == g->nx) continue;
+                        s->f[OR_JX + d][c] += sp->charge * F[3 * c + d];
+                    }
+                }
+        free(us); free(v); free(F); free(G); free(nnew);
+    }
+}

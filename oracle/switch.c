@@ -1,0 +1,261 @@
+/*
+ * Oracle regime switch and fluid <-> particle conversion.
+ *
+ * Paper: abstract and Methodology (fluid in stable regions, PIC where the
+ * switch flags instability; instability thresholds used as prior knowledge
+ * for the switch, Results after Table 1; charge and energy conservation
+ * checks during regime switches, validation paragraph).  The paper gives no
+ * threshold values and no conversion rule; the readings used here are:
+ *
+ *  indicators per node, from nearest-node moments of the fluid-capable
+ *  species (particles plus fluid) and the node-interpolated E:
+ *    a   = |E|
+ *    g   = |(N(+1)-N(-1)) per axis| / (2 max(N, n_floor dV)), N = node moment
+ *          sum w; the gradient counts only beyond three standard deviations
+ *          of its shot noise, sigma_g = sqrt(sum of the six neighbours' sum w^2)
+ *          / (2 max(N, n_floor dV)), i.e. the test is g - 3 sigma_g >= thr_grad;
+ *          fluid mass M on a node counts as ppc particles of weight M/ppc
+ *    s_u = sqrt(<|u|^2> - |<u>|^2)
+ *    ion: ionizable ions present and level-0 rate * dt >= thr_ion
+ *    chi: gamma_rms |E| / a_S >= thr_chi (QED runs)
+ *  kinetic if any indicator reaches its threshold (>=), dilated by
+ *  `dilation` nodes; a kinetic node returns to fluid only after
+ *  `hysteresis` consecutive evaluations with every indicator below half its
+ *  threshold in the dilated neighbourhood.
+ *
+ *  conversion (after the fluid update of every step):
+ *    absorb: a particle of a fluid-capable species whose nearest node is fluid
+ *      is moved virtually to that node (Esirkepov current of the move) and
+ *      its weight and momentum join the node fluid;
+ *    spawn: fluid mass M = n dV >= spawn_frac * n0 dV / ppc on a kinetic node
+ *      becomes ppc particles of weight M/ppc with the fluid momentum, moved
+ *      virtually from the node to Philox positions in the node's dual cell.
+ *  A CIC particle sitting on a node has exactly the node-delta charge of the
+ *  fluid, so both conversions keep div E - rho unchanged.
+ */
+#include "or_internal.h"
+
+static int clampx(const or_sim *s, int i) {
+    if (s->g.bc_x == OR_BC_PERIODIC) return or_wrap(i, s->g.nx);
+    return i < 0 ? 0 : (i > s->g.nx ? s->g.nx : i);
+}
+
+static int node_x_count(const or_sim *s) {
+    return s->g.bc_x == OR_BC_PERIODIC ? s->g.nx : s->g.nx + 1;
+}
+
+static size_t nearest(const or_sim *s, double X, double Y, double Z, int *ijk) {
+    int i = (int)floor(X + 0.5), j = (int)floor(Y + 0.5), k = (int)floor(Z + 0.5);
+    if (ijk) { ijk[0] = i; ijk[1] = j; ijk[2] = k; }
+    return or_idx(s, clampx(s, i), or_wrap(j, s->g.ny), or_wrap(k, s->g.nz));
+}
+
+extern double or_cnn_switch(or_sim *s, const double *nmom, const double *u2mom,
+                            uint8_t *hot, uint8_t *cold);
+
+void or_switch_eval(or_sim *s) {
+    const or_grid *g = &s->g;
+    size_t nn = s->nn;
+    double dv = g->dx * g->dy * g->dz;
+    int nxn = node_x_count(s);
+    double *N = (double *)calloc(nn, sizeof(double));
+    double *P = (double *)calloc(nn * 3, sizeof(double));
+    double *U2 = (double *)calloc(nn, sizeof(double));
+    double *NI = (double *)calloc(nn, sizeof(double));
+    double *V = (double *)calloc(nn, sizeof(double));
+    for (int isp = 0; isp < s->nsp; ++isp) {
+        const or_species *sp = &s->sp[isp];
+        const or_parts *p = &s->p[isp];
+        if (sp->fluid) {
+            for (size_t n = 0; n < p->n; ++n) {
+                size_t c = nearest(s, p->x[n] / g->dx, p->y[n] / g->dy, p->z[n] / g->dz, NULL);
+                double u[3] = {p->ux[n], p->uy[n], p->uz[n]};
+                N[c] += p->w[n];
+                V[c] += p->w[n] * p->w[n];
+                for (int d = 0; d < 3; ++d) P[3 * c + d] += p->w[n] * u[d];
+                U2[c] += p->w[n] * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            }
+            if (s->fn[sp - s->sp])
+                for (size_t c = 0; c < nn; ++c) {
+                    double m = s->fn[isp][c] * dv;
+                    if (m <= 0) continue;
+                    double u[3] = {s->fu[isp][0][c], s->fu[isp][1][c], s->fu[isp][2][c]};
+                    N[c] += m;
+                    V[c] += m * m / (sp->ppc > 0 ? sp->ppc : 1);
+                    for (int d = 0; d < 3; ++d) P[3 * c + d] += m * u[d];
+                    U2[c] += m * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                }
+        }
+        if (sp->kind == OR_ION && sp->ionizable && s->run.enable_ionization)
+            for (size_t n = 0; n < p->n; ++n)
+                if (p->zc[n] < sp->z_max) {
+                    size_t c = nearest(s, p->x[n] / g->dx, p->y[n] / g->dy, p->z[n] / g->dz, NULL);
+                    NI[c] += p->w[n];
+                }
+    }
+    uint8_t *hot = (uint8_t *)calloc(nn, 1), *notcold = (uint8_t *)calloc(nn, 1);
+    double a_s = 0.0;
+    if (s->run.enable_qed) {
+        double lam = s->las.lambda_um * 1e-6;
+        double omega0 = 2.0 * OR_PI * OR_C / lam;
+        a_s = OR_ME * OR_C * OR_C / (OR_HBAR * omega0);
+    }
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < nxn; ++i) {
+                size_t c = or_idx(s, i, j, k);
+                double e[3];
+                for (int d = 0; d < 3; ++d) e[d] = or_gather(s, OR_EX + d, i, j, k);
+                double emag = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+                size_t xp = or_idx(s, clampx(s, i + 1), j, k), xm = or_idx(s, clampx(s, i - 1), j, k);
+                size_t yp = or_idx(s, i, or_wrap(j + 1, g->ny), k), ym = or_idx(s, i, or_wrap(j - 1, g->ny), k);
+                size_t zp = or_idx(s, i, j, or_wrap(k + 1, g->nz)), zm = or_idx(s, i, j, or_wrap(k - 1, g->nz));
+                double dgx = N[xp] - N[xm], dgy = N[yp] - N[ym], dgz = N[zp] - N[zm];
+                double den = 2.0 * fmax(N[c], s->run.n_floor * dv);
+                double grad = sqrt(dgx * dgx + dgy * dgy + dgz * dgz) / den;
+                double sig = sqrt(V[xp] + V[xm] + V[yp] + V[ym] + V[zp] + V[zm]) / den;
+                grad = grad - 3.0 * sig;
+                double su = 0.0, g2 = 0.0;
+                if (N[c] > 0) {
+                    double m2 = U2[c] / N[c];
+                    double mx = P[3 * c] / N[c], my = P[3 * c + 1] / N[c], mz = P[3 * c + 2] / N[c];
+                    su = sqrt(fmax(0.0, m2 - (mx * mx + my * my + mz * mz)));
+                    g2 = m2;
+                }
+                double ionr = 0.0;
+                if (NI[c] > 0)
+                    for (int isp = 0; isp < s->nsp; ++isp)
+                        if (s->sp[isp].kind == OR_ION && s->sp[isp].ionizable)
+                            ionr = fmax(ionr, or_ion_rate_norm(s, isp, 0, emag) * g->dt);
+                double chi = s->run.enable_qed ? sqrt(1.0 + g2) * emag / a_s : 0.0;
+                const or_run *r = &s->run;
+                int h = emag >= r->thr_a || grad >= r->thr_grad || su >= r->thr_sigma_u ||
+                        (NI[c] > 0 && ionr >= r->thr_ion) ||
+                        (r->enable_qed && chi >= r->thr_chi);
+                int nc = emag >= 0.5 * r->thr_a || grad >= 0.5 * r->thr_grad ||
+                         su >= 0.5 * r->thr_sigma_u || (NI[c] > 0 && ionr >= 0.5 * r->thr_ion) ||
+                         (r->enable_qed && chi >= 0.5 * r->thr_chi);
+                hot[c] = (uint8_t)h;
+                notcold[c] = (uint8_t)nc;
+            }
+    s->fallback_fraction = 0.0;
+    if (s->run.switch_mode == OR_SW_CNN)
+        s->fallback_fraction = or_cnn_switch(s, N, U2, hot, notcold);
+    /* dilation + hysteresis */
+    int D = s->run.dilation;
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < nxn; ++i) {
+                size_t c = or_idx(s, i, j, k);
+                int kin = 0, warm = 0;
+                for (int dk = -D; dk <= D; ++dk)
+                    for (int dj = -D; dj <= D; ++dj)
+                        for (int di = -D; di <= D; ++di) {
+                            int ii = i + di;
+                            if (g->bc_x == OR_BC_OPEN && (ii < 0 || ii > g->nx)) continue;
+                            size_t q = or_idx(s, clampx(s, ii), or_wrap(j + dj, g->ny),
+                                              or_wrap(k + dk, g->nz));
+                            kin |= hot[q];
+                            warm |= notcold[q];
+                        }
+                if (kin) { s->sw[c] = 1; s->calm[c] = 0; }
+                else if (s->sw[c]) {
+                    if (warm) s->calm[c] = 0;
+                    else if (++s->calm[c] >= s->run.hysteresis) { s->sw[c] = 0; s->calm[c] = 0; }
+                }
+            }
+    free(N); free(P); free(U2); free(NI); free(V); free(hot); free(notcold);
+}
+
+/* Conversion between the two representations (see the header comment). */
+void or_reconcile(or_sim *s) {
+    const or_grid *g = &s->g;
+    double dv = g->dx * g->dy * g->dz;
+    int nxn = node_x_count(s);
+    for (int isp = 0; isp < s->nsp; ++isp) {
+        const or_species *sp = &s->sp[isp];
+        if (!sp->fluid || !s->fn[isp]) continue;
+        or_parts *p = &s->p[isp];
+        double *n = s->fn[isp];
+        double *M = (double *)calloc(s->nn, sizeof(double));
+        double *Pm = (double *)calloc(s->nn * 3, sizeof(double));
+        uint8_t *touched = (uint8_t *)calloc(s->nn, 1);
+        /* absorb, in storage order */
+        size_t keep = 0;
+        for (size_t q = 0; q < p->n; ++q) {
+            double X[3] = {p->x[q] / g->dx, p->y[q] / g->dy, p->z[q] / g->dz};
+            int ijk[3];
+            size_t c = nearest(s, X[0], X[1], X[2], ijk);
+            if (s->sw[c]) {
+                if (keep != q) {
+                    p->x[keep] = p->x[q]; p->y[keep] = p->y[q]; p->z[keep] = p->z[q];
+                    p->ux[keep] = p->ux[q]; p->uy[keep] = p->uy[q]; p->uz[keep] = p->uz[q];
+                    p->w[keep] = p->w[q]; p->tau[keep] = p->tau[q]; p->id[keep] = p->id[q];
+                    p->zc[keep] = p->zc[q];
+                }
+                keep++;
+                continue;
+            }
+            double Xn[3] = {(double)clampx(s, ijk[0]), (double)ijk[1], (double)ijk[2]};
+            if (g->bc_x == OR_BC_PERIODIC) Xn[0] = ijk[0];
+            or_deposit_move(s, sp->charge, p->w[q], X, Xn);
+            double u[3] = {p->ux[q], p->uy[q], p->uz[q]};
+            double gam = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            s->conv_loss += p->w[q] * sp->mass * (gam - 1.0);
+            M[c] += p->w[q];
+            for (int d = 0; d < 3; ++d) Pm[3 * c + d] += p->w[q] * u[d];
+            touched[c] = 1;
+        }
+        p->n = keep;
+        for (size_t c = 0; c < s->nn; ++c) {
+            if (!touched[c]) continue;
+            double m0 = n[c] * dv;
+            double u0[3] = {s->fu[isp][0][c], s->fu[isp][1][c], s->fu[isp][2][c]};
+            double g0 = sqrt(1.0 + u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2]);
+            double mt = m0 + M[c];
+            double un[3];
+            for (int d = 0; d < 3; ++d) un[d] = (m0 * u0[d] + Pm[3 * c + d]) / mt;
+            double gn = sqrt(1.0 + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
+            s->conv_loss += m0 * sp->mass * (g0 - 1.0) - mt * sp->mass * (gn - 1.0);
+            n[c] = mt / dv;
+            for (int d = 0; d < 3; ++d) s->fu[isp][d][c] = un[d];
+        }
+        /* spawn, in node order */
+        double wmin = s->run.spawn_frac * sp->n0 * dv / (sp->ppc > 0 ? sp->ppc : 1);
+        int m = sp->ppc > 0 ? sp->ppc : 1;
+        for (int k = 0; k < g->nz; ++k)
+            for (int j = 0; j < g->ny; ++j)
+                for (int i = 0; i < nxn; ++i) {
+                    size_t c = or_idx(s, i, j, k);
+                    if (!s->sw[c] || n[c] <= 0.0) continue;
+                    double mass = n[c] * dv;
+                    if (mass < wmin) continue;
+                    double w = mass / m;
+                    double u[3] = {s->fu[isp][0][c], s->fu[isp][1][c], s->fu[isp][2][c]};
+                    uint64_t node = (uint64_t)i + (uint64_t)nxn * ((uint64_t)j + (uint64_t)g->ny * k);
+                    for (int q = 0; q < m; ++q) {
+                        uint32_t r[4];
+                        or_draw4(s, node, (uint32_t)s->step, 12, (uint32_t)q, r);
+                        double X0[3] = {(double)i, (double)j, (double)k};
+                        double X1[3] = {i + or_uniform(r[0]) - 0.5, j + or_uniform(r[1]) - 0.5,
+                                        k + or_uniform(r[2]) - 0.5};
+                        if (g->bc_x == OR_BC_OPEN) {
+                            if (X1[0] < 0) X1[0] = -X1[0];
+                            else if (X1[0] >= g->nx) {
+                                X1[0] = 2.0 * g->nx - X1[0];
+                                if (X1[0] >= g->nx) X1[0] = nextafter((double)g->nx, 0.0);
+                            }
+                        }
+                        or_deposit_move(s, sp->charge, w, X0, X1);
+                        double xw = g->bc_x == OR_BC_PERIODIC ? fmod(X1[0] + g->nx, g->nx) : X1[0];
+                        double yw = fmod(X1[1] + g->ny, g->ny), zw = fmod(X1[2] + g->nz, g->nz);
+                        uint64_t id = (1ull << 63) | ((uint64_t)s->step << 40) | (node << 6) | (uint64_t)q;
+                        or_parts_push_back(p, xw * g->dx, yw * g->dy, zw * g->dz, u[0], u[1], u[2],
+                                           w, 0.0, id, (int32_t)llround(sp->charge));
+                    }
+                    n[c] = 0.0;
+                    s->fu[isp][0][c] = s->fu[isp][1][c] = s->fu[isp][2][c] = 0.0;
+                }
+        free(M); free(Pm); free(touched);
+    }
+}

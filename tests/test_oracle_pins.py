@@ -1,0 +1,324 @@
+"""Closed-form pins of the FP64 oracle (CPU only).
+
+Each test checks the oracle against something other than itself: an exact
+invariant of the scheme, a textbook closed form, a special case that reduces
+to a known formula, or brute force on a tiny input.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2510_11174_amd import configs
+
+
+# ---------------------------------------------------------------- Philox ----------------
+
+def test_philox_uniform_exact_in_float32(oracle_mod):
+    # the uniform mapping keeps at most 24 significant bits: exact in FP32
+    for x in [0, 1, 511, 512, 2**31, 2**32 - 1, 0x12345678, 0xDEADBEEF]:
+        u = oracle_mod.uniform(x)
+        assert 0.0 < u < 1.0
+        assert float(np.float32(u)) == u
+
+
+def test_philox_statistics(oracle_mod):
+    # chi^2 uniformity of the 4 output words over 4096 counters, and the
+    # avalanche property: flipping one counter bit flips about half the bits.
+    key = [0x1234, 0x5678]
+    words = np.array([oracle_mod.philox([i, 7, 3, 0x100], key) for i in range(4096)])
+    u = (words >> 24).ravel()            # top byte
+    hist = np.bincount(u, minlength=256)
+    expected = len(u) / 256
+    chi2 = ((hist - expected) ** 2 / expected).sum()
+    assert 180 < chi2 < 340              # 255 dof, ~4 sigma window
+    flips = []
+    for i in range(256):
+        a = oracle_mod.philox([i, 0, 0, 0], key)
+        b = oracle_mod.philox([i ^ 1, 0, 0, 0], key)
+        flips.append(sum(bin(int(x) ^ int(y)).count("1") for x, y in zip(a, b)))
+    assert abs(np.mean(flips) - 64) < 3
+    # the key matters too
+    assert not np.array_equal(oracle_mod.philox([1, 2, 3, 4], [0, 0]),
+                              oracle_mod.philox([1, 2, 3, 4], [1, 0]))
+
+
+# ----------------------------------------------------------------- Boris ----------------
+
+def test_boris_uniform_e_exact(oracle_mod):
+    # B = 0: u^{n+1/2} - u^{n-1/2} = (q/m) E dt exactly
+    e = np.array([0.3, -0.2, 0.7]); u0 = np.array([0.1, 2.0, -0.5])
+    u1 = oracle_mod.boris(-1.0, 0.05, e, [0, 0, 0], u0)
+    np.testing.assert_allclose(u1 - u0, -1.0 * e * 0.05, rtol=0, atol=1e-15)
+
+
+def test_boris_gyration(oracle_mod):
+    # uniform B: |u| conserved, rotation per step theta = 2 atan(q B dt / (2 m gamma))
+    qm, dt, B = -1.0, 0.1, 3.0
+    u = np.array([2.0, 0.0, 0.5])
+    gam = math.sqrt(1 + u @ u)
+    theta = 2 * math.atan(abs(qm) * B * dt / (2 * gam))
+    phase = math.atan2(u[1], u[0])
+    for n in range(1, 201):
+        u = oracle_mod.boris(qm, dt, [0, 0, 0], [0, 0, B], u)
+        assert abs(math.sqrt(u @ u) - math.sqrt(4.25)) < 1e-13
+        assert abs(u[2] - 0.5) < 1e-15
+    # electron (q < 0) in +z field rotates counter-clockwise
+    got = math.atan2(u[1], u[0])
+    want = math.remainder(phase + 200 * theta, 2 * math.pi)
+    assert abs(math.remainder(got - want, 2 * math.pi)) < 1e-11
+
+
+# ------------------------------------------------------------- Esirkepov ----------------
+
+def _cic_nodes(x, base):
+    s = np.zeros(3)
+    for a in range(3):
+        d = abs(x - (base + a))
+        s[a] = max(0.0, 1 - d)
+    return s
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_esirkepov_continuity(oracle_mod, seed):
+    # (rho1 - rho0)/dt + div J = 0 on every node of the window, to round-off
+    rng = np.random.default_rng(seed)
+    x0 = rng.uniform(5, 6, 3)
+    x1 = x0 + rng.uniform(-0.9, 0.9, 3)
+    dx = np.array([0.2, 0.3, 0.25]); dt = 0.07; qw = -1.3
+    jx, jy, jz, base = oracle_mod.esirkepov(x0, x1, qw, dt, dx)
+    rho0 = np.zeros((5, 5, 5)); rho1 = np.zeros((5, 5, 5))
+    S0 = [_cic_nodes(x0[d], base[d]) for d in range(3)]
+    S1 = [_cic_nodes(x1[d], base[d]) for d in range(3)]
+    rho0[1:4, 1:4, 1:4] = qw * np.einsum("a,b,c->abc", *S0)
+    rho1[1:4, 1:4, 1:4] = qw * np.einsum("a,b,c->abc", *S1)
+    # the window charge must be complete: shapes sum to one
+    assert abs(rho0.sum() - qw) < 1e-14 and abs(rho1.sum() - qw) < 1e-14
+    J = np.zeros((3, 5, 5, 5))
+    J[0, 1:4, 1:4, 1:4] = jx; J[1, 1:4, 1:4, 1:4] = jy; J[2, 1:4, 1:4, 1:4] = jz
+    div = ((J[0] - np.roll(J[0], 1, 0)) / dx[0] + (J[1] - np.roll(J[1], 1, 1)) / dx[1]
+           + (J[2] - np.roll(J[2], 1, 2)) / dx[2])
+    np.testing.assert_allclose((rho1 - rho0) / dt + div, 0, atol=1e-12 * abs(qw) / dt)
+    # total current: sum J_d dV = q w dx_d/dt per unit volume (here qw is q w / dV)
+    for d in range(3):
+        assert abs(J[d].sum() - qw * (x1[d] - x0[d]) * dx[d] / dt) < 1e-12
+
+
+def test_esirkepov_1d_reduces_to_linear_weighting(oracle_mod):
+    # motion along x only, inside one cell: the whole current sits on the one
+    # face crossed by the linear-weighting flux, split by the y/z weights
+    x0 = np.array([3.2, 4.25, 7.6]); x1 = np.array([3.7, 4.25, 7.6])
+    jx, jy, jz, base = oracle_mod.esirkepov(x0, x1, 1.0, 1.0, [1.0, 1.0, 1.0])
+    assert np.abs(jy).max() == 0 and np.abs(jz).max() == 0
+    wy = _cic_nodes(4.25, base[1]); wz = _cic_nodes(7.6, base[2])
+    np.testing.assert_allclose(jx[0], 0.5 * np.outer(wy, wz), atol=1e-15)
+    np.testing.assert_allclose(jx[1], 0.0, atol=1e-15)
+
+
+# ------------------------------------------------------------- Yee solver ---------------
+
+def _vacuum_cfg(nx, ny, nz, d=0.2, bc="periodic"):
+    c = configs.plain_hybrid(nx, ny, nz, mode="all_pic")
+    c["grid"]["bc_x"] = bc
+    c["species"] = []
+    c["laser"]["enabled"] = False
+    return c
+
+
+def test_yee_plane_wave_dispersion(oracle_mod):
+    # exact discrete eigenmode of the leapfrog: Ez ~ cos(k.r - w t) with
+    # [sin(w dt/2)/dt]^2 = sum_i [sin(k_i dx_i/2)/dx_i]^2; the integer-time B of
+    # the split half steps carries the factor cos(w dt/2).
+    nx, ny, nz = 16, 12, 4
+    cfg = _vacuum_cfg(nx, ny, nz)
+    g = cfg["grid"]; dx, dy, dt = g["dx"], g["dy"], g["dt"]
+    o = oracle_mod.Oracle(cfg)
+    kx, ky = 2 * math.pi * 2 / (nx * dx), 2 * math.pi * 1 / (ny * dy)
+    Kx, Ky = 2 / dx * math.sin(kx * dx / 2), 2 / dy * math.sin(ky * dy / 2)
+    Om = math.hypot(Kx, Ky)
+    w = 2 / dt * math.asin(dt / 2 * Om)
+    i = np.arange(nx + 1)[None, None, :]; j = np.arange(ny)[None, :, None]
+    def ez(t):
+        return np.cos(kx * i * dx + ky * j * dy - w * t) * np.ones((nz, 1, 1))
+    def bx(t):
+        return Ky / Om * np.cos(kx * i * dx + ky * (j + 0.5) * dy - w * t) * np.ones((nz, 1, 1))
+    def by(t):
+        return -Kx / Om * np.cos(kx * (i + 0.5) * dx + ky * j * dy - w * t) * np.ones((nz, 1, 1))
+    c = math.cos(w * dt / 2)
+    o.set_field("ez", ez(0)); o.set_field("bx", c * bx(0)); o.set_field("by", c * by(0))
+    N = 150
+    o.step(N)
+    T = N * dt
+    sl = np.s_[:, :, :nx]
+    np.testing.assert_allclose(o.get_field("ez")[sl], ez(T)[sl], atol=2e-12)
+    np.testing.assert_allclose(o.get_field("bx")[sl], c * bx(T)[sl], atol=2e-12)
+    np.testing.assert_allclose(o.get_field("by")[sl], c * by(T)[sl], atol=2e-12)
+    assert np.abs(o.get_field("ex")).max() < 1e-14
+
+
+def test_mur_absorbs_normal_incidence(oracle_mod):
+    # a y-polarized pulse crossing the open x wall leaves < 1% of its energy
+    nx = 128
+    cfg = _vacuum_cfg(nx, 4, 4, bc="open")
+    g = cfg["grid"]; dx, dt = g["dx"], g["dt"]
+    o = oracle_mod.Oracle(cfg)
+    x_node = np.arange(nx + 1) * dx; x_half = (np.arange(nx + 1) + 0.5) * dx
+    env = lambda x: np.exp(-((x - 0.6 * nx * dx) / 2.0) ** 2) * np.sin(2 * x)
+    ey = np.broadcast_to(env(x_node), (4, 4, nx + 1)).copy()
+    # forward wave: Bz = Ey at the same time, staggered half a cell
+    bz = np.broadcast_to(env(x_half), (4, 4, nx + 1)).copy(); bz[..., nx] = 0
+    o.set_field("ey", ey); o.set_field("bz", bz)
+    e0 = o.diagnostics()
+    o.step(int(1.2 * 0.5 * nx * dx / dt))
+    e1 = o.diagnostics()
+    w0 = e0["u_e"] + e0["u_b"]; w1 = e1["u_e"] + e1["u_b"]
+    assert w1 < 0.01 * w0
+
+
+def test_mur_coefficient_of_paper_grid():
+    # (c dt - d)/(c dt + d) at the paper's grid: dx = 0.2 um, dt = 0.2 fs
+    c = 299792458.0
+    cm = (c * 0.2e-15 - 0.2e-6) / (c * 0.2e-15 + 0.2e-6)
+    assert abs(cm - (-0.5387)) < 1e-4
+
+
+# ----------------------------------------------------- charge conservation --------------
+
+@pytest.mark.parametrize("bc", ["periodic", "open"])
+def test_gauss_preserved_pic(oracle_mod, bc):
+    cfg = configs.plain_hybrid(16, 8, 8, mode="all_pic")
+    cfg["grid"]["bc_x"] = bc
+    cfg["species"][0]["u_th"] = 0.2          # hot: many cell crossings and wall hits
+    cfg["laser"]["enabled"] = False
+    o = oracle_mod.Oracle(cfg)
+    o.step(40)
+    d = o.diagnostics()
+    rho_scale = 0.01
+    assert d["gauss_max"] < 1e-11 * rho_scale * 100
+
+
+def test_gauss_preserved_hybrid_conversion(oracle_mod):
+    # conversions both ways (absorb and spawn) keep div E - rho unchanged
+    cfg = configs.plain_hybrid(16, 8, 8, mode="fixed")
+    cfg["species"][0]["u_th"] = 0.1
+    cfg["laser"]["enabled"] = False
+    o = oracle_mod.Oracle(cfg)
+    m = np.zeros(o.shape, np.uint8); m[:, :, :8] = 1
+    o.set_switch(m)
+    o.step(5)
+    m2 = np.zeros(o.shape, np.uint8); m2[:, :, 5:14] = 1
+    o.set_switch(m2)
+    o.step(5)
+    d = o.diagnostics()
+    assert d["fluid_mass"][0] > 0 and d["count"][0] > 0
+    assert d["gauss_max"] < 1e-12
+    assert abs(d["charge_total"] + 0.01 * 16 * 8 * 8 * 0.2 ** 3) < 1e-12
+
+
+# -------------------------------------------------------- plasma oscillation ------------
+
+@pytest.mark.parametrize("mode", ["all_pic", "all_fluid"])
+def test_cold_plasma_oscillation(oracle_mod, mode):
+    # k = 0 drift mode in a periodic box: omega_num = (2/dt) asin(omega_p dt / 2)
+    cfg = configs.plain_hybrid(4, 4, 4, mode=mode)
+    cfg["grid"]["bc_x"] = "periodic"
+    cfg["species"][0]["u_th"] = 0.0
+    cfg["laser"]["enabled"] = False
+    o = oracle_mod.Oracle(cfg)
+    dt = cfg["grid"]["dt"]
+    amp = 1e-3
+    d = cfg["grid"]["dx"]
+    if mode == "all_pic":
+        # 2x2x2 regular lattice per cell: the charge on every node is uniform
+        off = np.array([0.25, 0.75])
+        cells = np.stack(np.meshgrid(np.arange(4), np.arange(4), np.arange(4), indexing="ij"), -1).reshape(-1, 3)
+        subs = np.stack(np.meshgrid(off, off, off, indexing="ij"), -1).reshape(-1, 3)
+        x = ((cells[:, None, :] + subs[None, :, :]).reshape(-1, 3)) * d
+        u = np.zeros_like(x); u[:, 1] = amp
+        w = np.full(len(x), 0.01 * d ** 3 / 8)
+        o.set_particles(0, x, u, w)
+    else:
+        o.step(1)   # absorbs the particles into the node fluid
+        n, u = o.get_fluid(0)
+        n[..., :4] = 0.01
+        u[..., :] = 0; u[..., 1] = amp
+        o.set_fluid(0, n, u)
+        for c in ("ex", "ey", "ez", "bx", "by", "bz"):
+            o.set_field(c, np.zeros(o.shape))
+    wp = math.sqrt(0.01)
+    wnum = 2 / dt * math.asin(wp * dt / 2)
+    ts, ey = [], []
+    for n in range(400):
+        o.step(1)
+        ey.append(o.get_field("ey")[0, 0, 0]); ts.append(n + 1)
+    ey = np.array(ey)
+    # Ey^n = A sin(w n dt + phi): least squares on the two quadratures at wnum
+    A = np.stack([np.sin(wnum * dt * np.array(ts)), np.cos(wnum * dt * np.array(ts))], 1)
+    coef, res, *_ = np.linalg.lstsq(A, ey, rcond=None)
+    fit = A @ coef
+    assert np.abs(fit - ey).max() < 1e-5 * np.abs(ey).max()
+    # amplitude: E = (n q u / omega) from the initial drift current
+    assert abs(np.hypot(*coef) - 0.01 * amp / wnum) < 1e-3 * 0.01 * amp / wnum + 1e-9
+
+
+# ------------------------------------------------------------- ionization ---------------
+
+def test_adk_hydrogenic_equals_landau_lifshitz(oracle_mod):
+    # He II (Ip = Z^2/2, n* = 1): w = 4 Z^5 / F exp(-2 Z^3 / (3 F))
+    Z, ip = 2.0, 2.0
+    for F in [0.1, 0.3, 0.5, 1.0, 2.0]:
+        ll = 4 * Z ** 5 / F * math.exp(-2 * Z ** 3 / (3 * F))
+        assert abs(oracle_mod.adk_rate(F, ip, Z) / ll - 1) < 1e-12
+    assert abs(oracle_mod.adk_rate(0.5, 2.0, 2.0) - 5.9671e-3) < 1e-6
+
+
+def test_ionization_blend_limits(oracle_mod):
+    om = 0.056954        # photon energy at 0.8 um, Hartree
+    ip = 24.587387936 / 27.211386245988
+    fc = om * math.sqrt(2 * ip) / 1.5
+    K = math.ceil(ip / om)
+    assert K == 16
+    # deep multiphoton regime: d ln w / d ln F -> 2K
+    F1, F2 = 0.2 * fc, 0.21 * fc
+    slope = (math.log(oracle_mod.ionization_rate(F2, ip, 1, om)) -
+             math.log(oracle_mod.ionization_rate(F1, ip, 1, om))) / math.log(F2 / F1)
+    assert abs(slope - 2 * K) < 1e-6
+    # deep tunnelling regime: the blend is the ADK rate
+    F = 40 * fc
+    assert abs(oracle_mod.ionization_rate(F, ip, 1, om) / oracle_mod.adk_rate(F, ip, 1) - 1) < 1e-6
+    # continuity through the crossover and zero field
+    r = [oracle_mod.ionization_rate(fc * (1 + e), ip, 1, om) for e in (-1e-9, 1e-9)]
+    assert abs(r[0] / r[1] - 1) < 1e-6
+    assert oracle_mod.ionization_rate(0.0, ip, 1, om) == 0.0
+
+
+def test_ionized_fraction_constant_field(oracle_mod):
+    # static uniform field on immobile atoms: fraction ionized after N steps
+    # is 1 - exp(-w N dt) (binomial, 4 sigma); He II rate kept negligible
+    cfg = configs.ionization_hybrid(8, 4, 4, mode="all_pic", ppc=16)
+    cfg["laser"]["enabled"] = False
+    cfg["species"][1]["profile"] = "uniform"
+    cfg["species"][1]["ip_ev"] = [24.587387936, 5000.0]
+    cfg["grid"]["bc_x"] = "periodic"
+    o = oracle_mod.Oracle(cfg)
+    E = 0.04      # normalized field, ~0.31 a.u.
+    ez = np.full(o.shape, E); ez[..., -1] = 0
+    o.set_field("ez", ez)
+    # the ionized electrons would screen the field: keep it fixed by re-setting
+    dt = cfg["grid"]["dt"]
+    N = 10
+    for _ in range(N):
+        o.set_field("ez", ez)
+        o.set_field("ex", np.zeros(o.shape)); o.set_field("ey", np.zeros(o.shape))
+        o.step(1)
+    z = o.get_particles(1)["z"]
+    eu = 299792458.0 * 9.1093837015e-31 * 2 * math.pi * 299792458.0 / 0.8e-6 / 1.602176634e-19
+    F = E * eu / 5.14220674763e11
+    om = 2 * math.pi * 299792458.0 / 0.8e-6 * 2.4188843265857e-17
+    w = oracle_mod.ionization_rate(F, 24.587387936 / 27.211386245988, 1, om) / om
+    p = 1 - math.exp(-w * N * dt)
+    n = len(z)
+    frac = (z >= 1).mean()
+    assert 0.05 < p < 0.95
+    assert abs(frac - p) < 4 * math.sqrt(p * (1 - p) / n)
+    assert o.count(0) == (z >= 1).sum()
