@@ -1,0 +1,219 @@
+/*
+ * hk.h - C ABI of the MI355X hybrid fluid-kinetic laser-plasma step.
+ *
+ * Paper: "Machine Learning-Integrated Hybrid Fluid-Kinetic Framework for QED
+ * Laser-Plasma Simulations" (arXiv 2510.11174).  The calls follow the
+ * paper's statement of the problem (Methodology, pipeline paragraph): set up
+ * plasma parameters and fields (hk_create), run the time loop of laser
+ * excitation, ionization, particle movement, fluid changes and field updates
+ * (hk_step), switch between fluid and kinetic treatment per region
+ * (hk_switch_map / hk_set_switch_map / hk_set_switch_mode) and report the
+ * conservation checks and energies (hk_diagnostics; validation and
+ * post-processing paragraphs).
+ *
+ * Units: normalized laser units, c = omega0 = m_e = e = 1.  Lengths in
+ * c/omega0, times in 1/omega0, densities in n_c, fields in m_e c omega0 / e.
+ *
+ * Grid and layout.  nx * ny * nz cells, y and z periodic, x periodic or open
+ * (Mur-absorbing fields, reflecting particles).  Every grid array exchanged
+ * through this ABI has the canonical shape (nz, ny, nx + 1), x fastest:
+ * element (i, j, k) sits at i + (nx + 1) * (j + ny * k).  Yee staggering in
+ * cell units: Ex (i+1/2, j, k), Ey (i, j+1/2, k), Ez (i, j, k+1/2),
+ * Bx (i, j+1/2, k+1/2), By (i+1/2, j, k+1/2), Bz (i+1/2, j+1/2, k); J as E;
+ * nodes (rho, fluid, switch map) at (i, j, k).  Unused samples (the last x
+ * plane of half-staggered components, or the last plane when x is periodic)
+ * read as zero.
+ *
+ * Precision.  The library is built twice from one source: libhk_f32.so
+ * (fields and particles in FP32; FP64 optical depth and diagnostics) and
+ * libhk_f64.so (everything FP64).  hk_real_size() tells which one is loaded.
+ * Exchange buffers are FP64 on the host in both builds except hk_get_field /
+ * hk_set_field, which move the build's own real type (4 or 8 bytes).
+ *
+ * Memory ownership.  Device state is owned by the library.  It is allocated
+ * through hk_run_desc.alloc/free when given (for example a caching allocator
+ * of the host framework), else with hipMalloc.  Work is enqueued on
+ * hk_run_desc.stream (a hipStream_t, NULL = default stream).  Host pointers
+ * passed to any call are borrowed for the duration of that call only.
+ *
+ * Errors.  Every int-returning call returns HK_OK (0) or a negative code.
+ * hk_last_error() returns a message for the last failure of that context.
+ * The library never aborts or prints.  After HK_EDEVICE, HK_ENUMERIC or
+ * HK_EOVERFLOW the context is poisoned: later calls return HK_ESTATE until
+ * hk_destroy.  A context is not thread safe; separate contexts are
+ * independent.
+ */
+#ifndef HK_H
+#define HK_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HK_MAX_SPECIES 6
+#define HK_MAX_LEVELS 8
+
+enum hk_status {
+    HK_OK = 0,
+    HK_EINVAL = -1,    /* bad argument or size mismatch; nothing written */
+    HK_ENOMEM = -2,    /* device or host allocation failed */
+    HK_EDEVICE = -3,   /* HIP runtime error (poisons the context) */
+    HK_ENUMERIC = -4,  /* non-finite field or momentum, CFL breach (poisons) */
+    HK_EOVERFLOW = -5, /* particle storage could not grow (poisons) */
+    HK_ESTATE = -6,    /* context poisoned, or call not valid in this state */
+    HK_EIO = -7,       /* file I/O */
+    HK_ENOTSUP = -8    /* feature not built into this library */
+};
+
+enum hk_bc { HK_BC_PERIODIC = 0, HK_BC_OPEN = 1 };
+enum hk_kind { HK_ELECTRON = 0, HK_ION = 1, HK_POSITRON = 2, HK_PHOTON = 3 };
+enum hk_profile { HK_PROF_NONE = 0, HK_PROF_UNIFORM = 1, HK_PROF_RAMP = 2, HK_PROF_FOIL = 3 };
+enum hk_switch_mode {
+    HK_SW_ALL_PIC = 0,    /* every node kinetic, no fluid (the reference run) */
+    HK_SW_THRESHOLD = 1,  /* physics-threshold switch */
+    HK_SW_CNN = 2,        /* learned switch with threshold fallback */
+    HK_SW_ALL_FLUID = 3,  /* every node fluid */
+    HK_SW_FIXED = 4       /* map set by hk_set_switch_map, never re-evaluated */
+};
+enum hk_comp { HK_EX = 0, HK_EY, HK_EZ, HK_BX, HK_BY, HK_BZ, HK_JX, HK_JY, HK_JZ, HK_NCOMP };
+
+/* Grid: cells, x boundary, cell sizes and time step (1/omega0). */
+typedef struct {
+    int32_t nx, ny, nz, bc_x;
+    double dx, dy, dz, dt;
+} hk_grid_desc;
+
+/* One species.  Particles are created in every cell whose centre has
+ * density > 0 (ppc per cell, Philox positions and Gaussian momenta).
+ * kind HK_ION uses `charge` as the initial charge state; `ionizable` ions
+ * ionize level by level up to z_max with potentials ip_ev[level] (eV) and put
+ * the freed electrons into species `target`.  `fluid` species may be held as
+ * a cold fluid in fluid nodes.  `mobile` = 0 freezes the species (no push, no
+ * current).  `qed`: photon emission (leptons) or pair creation (photons). */
+typedef struct {
+    int32_t kind, ppc, profile, mobile;
+    int32_t fluid, ionizable, z_max, target;
+    int32_t qed, pad;
+    double charge, mass;       /* e units, m_e units */
+    double n0, x0, length;     /* peak density; ramp start/length or foil start/thickness */
+    double u_th;               /* Gaussian momentum spread per component (m_e c) */
+    double ip_ev[HK_MAX_LEVELS];
+} hk_species_desc;
+
+/* Laser antenna: a current sheet on node plane i_antenna radiating a
+ * Gaussian pulse, E = a0 exp(-((t - t_center)/duration)^2) exp(-r^2/waist^2)
+ * times sin t (y) and, for circular polarization, cos t (z).  t_center <= 0
+ * means 2 * duration.  lambda_um fixes the SI scale used by ionization and
+ * QED rates. */
+typedef struct {
+    int32_t enabled, polarization;   /* 0 linear (E along y), 1 circular */
+    int32_t i_antenna, pad;
+    double a0, waist, duration, t_center, lambda_um;
+} hk_laser_desc;
+
+typedef void *(*hk_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*hk_free_fn)(void *ptr, void *ctx);
+
+/* Run control.  Thresholds of the switch criterion (kinetic when any is
+ * reached): |E| >= thr_a; density gradient beyond its shot noise >= thr_grad;
+ * momentum spread >= thr_sigma_u; ionization probability per step >= thr_ion;
+ * estimated quantum parameter >= thr_chi.  `dilation` widens the kinetic
+ * region by that many nodes; a kinetic node returns to fluid after
+ * `hysteresis` calm evaluations.  Fluid below n_floor has no velocity.
+ * Fluid mass >= spawn_frac * n0 dV / ppc on a kinetic node becomes particles. */
+typedef struct {
+    uint64_t seed;
+    int32_t switch_mode, switch_every;
+    int32_t dilation, hysteresis;
+    int32_t enable_ionization, enable_qed;
+    double thr_a, thr_grad, thr_sigma_u, thr_ion, thr_chi;
+    double n_floor;
+    double spawn_frac;
+    void *stream;          /* hipStream_t or NULL */
+    hk_alloc_fn alloc;     /* optional device allocator */
+    hk_free_fn free;
+    void *alloc_ctx;
+} hk_run_desc;
+
+/* FP64 diagnostics (energies in m_e c^2 n_c (c/omega0)^3). */
+typedef struct {
+    double t;
+    int64_t step;
+    double u_e, u_b;                       /* field energies */
+    double kin[HK_MAX_SPECIES];            /* particle kinetic energy per species */
+    double fluid_kin[HK_MAX_SPECIES];      /* fluid kinetic energy per species */
+    double count[HK_MAX_SPECIES];          /* macro-particles per species */
+    double fluid_mass[HK_MAX_SPECIES];     /* sum n dV per fluid species */
+    double charge_total;                   /* particles + fluids */
+    double gauss_max, gauss_l2;            /* change of div E - rho since step 0 */
+    double conv_loss;                      /* kinetic energy lost by absorption */
+    double ion_energy;                     /* ionization potential energy spent */
+    double photon_energy;                  /* photon energy (particles + ledger) */
+    double kinetic_fraction;               /* kinetic nodes / all nodes */
+    double fallback_fraction;              /* CNN nodes that fell back to threshold */
+} hk_diag;
+
+/* Host-side particle arrays, FP64 regardless of the build: x[3n] absolute
+ * positions, u[3n] momenta, w[n] weights, id[n], z[n] charge state (ions),
+ * tau[n] optical depth (QED species).  Any pointer may be NULL on get. */
+typedef struct {
+    size_t n;
+    double *x, *u, *w;
+    uint64_t *id;
+    int32_t *z;
+    double *tau;
+} hk_particles;
+
+typedef struct hk_sim hk_sim;
+
+/* Build the context: validates the descriptors (HK_EINVAL), allocates device
+ * state, initialises species on the device and zeroes the fields. */
+int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspecies,
+              const hk_laser_desc *laser, const hk_run_desc *run, hk_sim **out);
+void hk_destroy(hk_sim *sim);
+
+/* Advance nsteps time steps on the run stream; returns after they complete. */
+int hk_step(hk_sim *sim, int nsteps);
+
+/* Switch map: n must be (nx+1)*ny*nz bytes; 1 kinetic, 0 fluid. */
+int hk_switch_map(hk_sim *sim, uint8_t *out, size_t n);
+int hk_set_switch_map(hk_sim *sim, const uint8_t *in, size_t n);  /* implies FIXED */
+int hk_set_switch_mode(hk_sim *sim, int mode);
+
+int hk_diagnostics(hk_sim *sim, hk_diag *out);
+
+/* Field component `comp` (hk_comp) in the canonical layout; bytes must be
+ * (nx+1)*ny*nz*hk_real_size(). */
+int hk_get_field(hk_sim *sim, int comp, void *host_out, size_t bytes);
+int hk_set_field(hk_sim *sim, int comp, const void *host_in, size_t bytes);
+
+/* Node charge density and discrete div E (FP64, canonical layout, n values). */
+int hk_get_rho(hk_sim *sim, double *host_out, size_t n);
+int hk_get_divE(hk_sim *sim, double *host_out, size_t n);
+
+int hk_particle_count(hk_sim *sim, int species, size_t *n);
+/* out->n must equal hk_particle_count; particles come in storage order. */
+int hk_get_particles(hk_sim *sim, int species, const hk_particles *out);
+/* Replaces the species' particles (positions must lie inside the box). */
+int hk_set_particles(hk_sim *sim, int species, const hk_particles *in);
+
+/* Cold fluid of a fluid species: n[(nx+1)*ny*nz], u[3*(nx+1)*ny*nz]. */
+int hk_get_fluid(hk_sim *sim, int species, double *n, double *u, size_t nodes);
+int hk_set_fluid(hk_sim *sim, int species, const double *n, const double *u, size_t nodes);
+
+/* Accumulated device time per kernel group (ms): 0 switch, 1 particles,
+ * 2 fluid, 3 conversion, 4 fields, 5 sort/merge, 6 other.  Timing is
+ * collected only when enabled (it adds events around each group). */
+int hk_enable_timing(hk_sim *sim, int on);
+int hk_timers(hk_sim *sim, double *ms, int n);
+
+int hk_real_size(void);
+const char *hk_strerror(int code);
+const char *hk_last_error(const hk_sim *sim);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -155,25 +155,30 @@ static const double OR_OFF[OR_NCOMP][3] = {
     {0, 0.5, 0.5}, {0.5, 0, 0.5}, {0.5, 0.5, 0}, /* B */
     {0.5, 0, 0}, {0, 0.5, 0}, {0, 0, 0.5}};      /* J */
 
-/* Trilinear (CIC) interpolation of one staggered component at cell-unit
- * position (X, Y, Z).  Open x: half-plane components are extended past the
- * walls by their value on the nearest plane. */
-double or_gather(const or_sim *s, int comp, double X, double Y, double Z) {
+/* Trilinear (CIC) interpolation of one staggered component at the position
+ * cell c + offset o (cell units).  Open x: half-plane components are extended
+ * past the walls by their value on the nearest plane. */
+double or_gather(const or_sim *s, int comp, const int c[3], const double o[3]) {
     const or_grid *g = &s->g;
-    double ux = X - OR_OFF[comp][0], uy = Y - OR_OFF[comp][1], uz = Z - OR_OFF[comp][2];
-    int i0 = (int)floor(ux), j0 = (int)floor(uy), k0 = (int)floor(uz);
-    double fx = ux - i0, fy = uy - j0, fz = uz - k0;
+    int i0[3];
+    double f[3];
+    for (int d = 0; d < 3; ++d) {
+        double u = o[d] - OR_OFF[comp][d];     /* in [-0.5, 1) */
+        int fl = (int)floor(u);
+        i0[d] = c[d] + fl;
+        f[d] = u - fl;
+    }
     int half = OR_OFF[comp][0] != 0.0;
     double acc = 0.0;
-    for (int c = 0; c < 2; ++c)
+    for (int cc = 0; cc < 2; ++cc)
         for (int b = 0; b < 2; ++b)
             for (int a = 0; a < 2; ++a) {
-                int i = i0 + a;
+                int i = i0[0] + a;
                 if (g->bc_x == OR_BC_PERIODIC) i = or_wrap(i, g->nx);
                 else if (half) i = i < 0 ? 0 : (i > g->nx - 1 ? g->nx - 1 : i);
                 else i = i < 0 ? 0 : (i > g->nx ? g->nx : i);
-                int j = or_wrap(j0 + b, g->ny), k = or_wrap(k0 + c, g->nz);
-                double wgt = (a ? fx : 1 - fx) * (b ? fy : 1 - fy) * (c ? fz : 1 - fz);
+                int j = or_wrap(i0[1] + b, g->ny), k = or_wrap(i0[2] + cc, g->nz);
+                double wgt = (a ? f[0] : 1 - f[0]) * (b ? f[1] : 1 - f[1]) * (cc ? f[2] : 1 - f[2]);
                 acc += wgt * s->f[comp][or_idx(s, i, j, k)];
             }
     return acc;

@@ -39,9 +39,11 @@ void or_fluid_phase(or_sim *s) {
                     size_t c = or_idx(s, i, j, k);
                     if (n[c] <= 0.0) continue;
                     double e[3], b[3], u[3];
+                    int nc[3] = {i, j, k};
+                    double z0[3] = {0, 0, 0};
                     for (int d = 0; d < 3; ++d) {
-                        e[d] = or_gather(s, OR_EX + d, i, j, k);
-                        b[d] = or_gather(s, OR_BX + d, i, j, k);
+                        e[d] = or_gather(s, OR_EX + d, nc, z0);
+                        b[d] = or_gather(s, OR_BX + d, nc, z0);
                         u[d] = s->fu[isp][d][c];
                     }
                     or_boris(qm, g->dt, e, b, u);

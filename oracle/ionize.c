@@ -71,7 +71,8 @@ void or_ionize_particle(or_sim *s, int isp, size_t i, double emag) {
         p->zc[i] = lev + 1;
         or_spawn e;
         e.species = sp->target;
-        e.x = p->x[i]; e.y = p->y[i]; e.z = p->z[i];
+        e.ci = p->ci[i]; e.cj = p->cj[i]; e.ck = p->ck[i];
+        e.ox = p->ox[i]; e.oy = p->oy[i]; e.oz = p->oz[i];
         e.ux = p->ux[i]; e.uy = p->uy[i]; e.uz = p->uz[i];
         e.w = p->w[i];
         e.tau = 0.0;

@@ -8,7 +8,8 @@
 
 typedef struct {
     size_t n, cap;
-    double *x, *y, *z;        /* position, c/omega0 */
+    int32_t *ci, *cj, *ck;    /* cell holding the particle */
+    double *ox, *oy, *oz;     /* offset inside that cell, [0,1) in cell units */
     double *ux, *uy, *uz;     /* momentum u = gamma v (photons: k) */
     double *w;                /* weight: number of real particles / n_c */
     double *tau;              /* remaining optical depth (QED) */
@@ -18,7 +19,8 @@ typedef struct {
 
 typedef struct {           /* one spawn event, appended after the particle phase */
     int species;
-    double x, y, z, ux, uy, uz, w, tau;
+    int32_t ci, cj, ck;
+    double ox, oy, oz, ux, uy, uz, w, tau;
     uint64_t id;
     int32_t zc;
 } or_spawn;
@@ -75,20 +77,23 @@ void or_draw4(const or_sim *s, uint64_t id, uint32_t step, uint32_t tag, uint32_
 void or_yee_b_half(or_sim *s);
 void or_yee_e_full(or_sim *s);
 void or_antenna(or_sim *s, double t);
-double or_gather(const or_sim *s, int comp, double X, double Y, double Z);
+double or_gather(const or_sim *s, int comp, const int c[3], const double o[3]);
 void or_divE(const or_sim *s, double *out);
 /* particles.c */
 void or_parts_reserve(or_parts *p, size_t cap);
-void or_parts_push_back(or_parts *p, double x, double y, double z, double ux, double uy,
-                        double uz, double w, double tau, uint64_t id, int32_t zc);
+void or_parts_push_back(or_parts *p, int32_t ci, int32_t cj, int32_t ck, double ox,
+                        double oy, double oz, double ux, double uy, double uz, double w,
+                        double tau, uint64_t id, int32_t zc);
 void or_parts_remove(or_parts *p, size_t i);
 void or_init_species(or_sim *s, int sp);
 void or_particle_phase(or_sim *s);
-void or_deposit_move(or_sim *s, double q, double w, const double X0[3],
+void or_deposit_move(or_sim *s, double q, double w, const int cell[3], const double X0[3],
                      const double X1[3]);
 void or_rho(const or_sim *s, double *rho);
 void or_spawn_flush(or_sim *s);
 void or_spawn_add(or_sim *s, const or_spawn *e);
+void or_carry(const or_sim *s, int c[3], double X[3]);
+void or_reflect_x(const or_sim *s, int ci, double *X, double *ux);
 /* fluid.c */
 void or_fluid_phase(or_sim *s);
 /* switch.c */

@@ -17,18 +17,21 @@ void or_parts_reserve(or_parts *p, size_t cap) {
     size_t c = p->cap ? p->cap : 64;
     while (c < cap) c *= 2;
 #define GROW(f, T) p->f = (T *)realloc(p->f, sizeof(T) * c)
-    GROW(x, double); GROW(y, double); GROW(z, double);
+    GROW(ci, int32_t); GROW(cj, int32_t); GROW(ck, int32_t);
+    GROW(ox, double); GROW(oy, double); GROW(oz, double);
     GROW(ux, double); GROW(uy, double); GROW(uz, double);
     GROW(w, double); GROW(tau, double); GROW(id, uint64_t); GROW(zc, int32_t);
 #undef GROW
     p->cap = c;
 }
 
-void or_parts_push_back(or_parts *p, double x, double y, double z, double ux, double uy,
-                        double uz, double w, double tau, uint64_t id, int32_t zc) {
+void or_parts_push_back(or_parts *p, int32_t ci, int32_t cj, int32_t ck, double ox,
+                        double oy, double oz, double ux, double uy, double uz, double w,
+                        double tau, uint64_t id, int32_t zc) {
     or_parts_reserve(p, p->n + 1);
     size_t i = p->n++;
-    p->x[i] = x; p->y[i] = y; p->z[i] = z;
+    p->ci[i] = ci; p->cj[i] = cj; p->ck[i] = ck;
+    p->ox[i] = ox; p->oy[i] = oy; p->oz[i] = oz;
     p->ux[i] = ux; p->uy[i] = uy; p->uz[i] = uz;
     p->w[i] = w; p->tau[i] = tau; p->id[i] = id; p->zc[i] = zc;
 }
@@ -37,7 +40,7 @@ void or_parts_push_back(or_parts *p, double x, double y, double z, double ux, do
 void or_parts_remove(or_parts *p, size_t i) {
     size_t m = p->n - i - 1;
 #define SHIFT(f) memmove(p->f + i, p->f + i + 1, sizeof(*p->f) * m)
-    SHIFT(x); SHIFT(y); SHIFT(z); SHIFT(ux); SHIFT(uy); SHIFT(uz);
+    SHIFT(ci); SHIFT(cj); SHIFT(ck); SHIFT(ox); SHIFT(oy); SHIFT(oz); SHIFT(ux); SHIFT(uy); SHIFT(uz);
     SHIFT(w); SHIFT(tau); SHIFT(id); SHIFT(zc);
 #undef SHIFT
     p->n--;
@@ -76,16 +79,14 @@ void or_init_species(or_sim *s, int isp) {
                     uint32_t rp[4], rm[4];
                     or_draw4(s, id, 0, 1, 0, rp);
                     or_draw4(s, id, 0, 2, 0, rm);
-                    double x = (i + or_uniform(rp[0])) * g->dx;
-                    double y = (j + or_uniform(rp[1])) * g->dy;
-                    double z = (k + or_uniform(rp[2])) * g->dz;
                     double r0 = or_uniform(rm[0]), r1 = or_uniform(rm[1]);
                     double r2 = or_uniform(rm[2]), r3 = or_uniform(rm[3]);
                     double m0 = sqrt(-2.0 * log(r0)), m1 = sqrt(-2.0 * log(r2));
                     double ux = sp->u_th * m0 * cos(2.0 * OR_PI * r1);
                     double uy = sp->u_th * m0 * sin(2.0 * OR_PI * r1);
                     double uz = sp->u_th * m1 * cos(2.0 * OR_PI * r3);
-                    or_parts_push_back(p, x, y, z, ux, uy, uz, n * dv / sp->ppc, 0.0, id,
+                    or_parts_push_back(p, i, j, k, or_uniform(rp[0]), or_uniform(rp[1]),
+                                       or_uniform(rp[2]), ux, uy, uz, n * dv / sp->ppc, 0.0, id,
                                        (int32_t)llround(sp->charge));
                 }
             }
@@ -172,10 +173,12 @@ void or_esirkepov(const double x0[3], const double x1[3], double qw_dv, double d
         }
 }
 
-/* Add the Esirkepov current of a move X0 -> X1 (cell units, X1 unwrapped in
- * periodic directions) to the grid J.  The last face of each x row carries
- * the total, which is zero; entries outside an open x box are zero too. */
-void or_deposit_move(or_sim *s, double q, double w, const double X0[3], const double X1[3]) {
+/* Add the Esirkepov current of a move X0 -> X1 to the grid J.  X0 and X1 are
+ * positions relative to the node `cell` (cell units; X1 may leave [0,1) by
+ * less than one cell).  The last face of each x row carries the total, which
+ * is zero; entries outside an open x box are zero too. */
+void or_deposit_move(or_sim *s, double q, double w, const int cell[3], const double X0[3],
+                     const double X1[3]) {
     const or_grid *g = &s->g;
     double dv = g->dx * g->dy * g->dz;
     double dx[3] = {g->dx, g->dy, g->dz};
@@ -187,14 +190,13 @@ void or_deposit_move(or_sim *s, double q, double w, const double X0[3], const do
         for (int b = 0; b < 3; ++b)
             for (int c = 0; c < 3; ++c) {
                 int n = a + 3 * (b + 3 * c);
-                int i = base[0] + a;
-                int j = or_wrap(base[1] + b, g->ny), k = or_wrap(base[2] + c, g->nz);
-                /* x faces: a = 2 is the closing face (total zero) */
-                if (a < 2) {
-                    int ii = per ? or_wrap(i, g->nx) : i;
-                    if (per || (ii >= 0 && ii < g->nx)) s->f[OR_JX][or_idx(s, ii, j, k)] += jx[n];
-                }
+                int i = cell[0] + base[0] + a;
+                int j = or_wrap(cell[1] + base[1] + b, g->ny);
+                int k = or_wrap(cell[2] + base[2] + c, g->nz);
                 int ii = per ? or_wrap(i, g->nx) : i;
+                /* x faces: a = 2 is the closing face (total zero) */
+                if (a < 2 && (per || (ii >= 0 && ii < g->nx)))
+                    s->f[OR_JX][or_idx(s, ii, j, k)] += jx[n];
                 if (per || (ii >= 0 && ii <= g->nx)) {
                     if (b < 2) s->f[OR_JY][or_idx(s, ii, j, k)] += jy[n];
                     if (c < 2) s->f[OR_JZ][or_idx(s, ii, j, k)] += jz[n];
@@ -212,9 +214,8 @@ void or_rho(const or_sim *s, double *rho) {
         const or_parts *p = &s->p[isp];
         if (s->sp[isp].kind == OR_PHOTON) continue;
         for (size_t n = 0; n < p->n; ++n) {
-            double X = p->x[n] / g->dx, Y = p->y[n] / g->dy, Z = p->z[n] / g->dz;
-            int i0 = (int)floor(X), j0 = (int)floor(Y), k0 = (int)floor(Z);
-            double fx = X - i0, fy = Y - j0, fz = Z - k0;
+            int i0 = p->ci[n], j0 = p->cj[n], k0 = p->ck[n];
+            double fx = p->ox[n], fy = p->oy[n], fz = p->oz[n];
             double q = s->sp[isp].kind == OR_ION ? (double)p->zc[n] : s->sp[isp].charge;
             for (int c = 0; c < 2; ++c)
                 for (int b = 0; b < 2; ++b)
@@ -252,19 +253,47 @@ void or_spawn_flush(or_sim *s) {
     qsort(s->ev, s->nev, sizeof(or_spawn), cmp_spawn);
     for (size_t n = 0; n < s->nev; ++n) {
         or_spawn *e = &s->ev[n];
-        or_parts_push_back(&s->p[e->species], e->x, e->y, e->z, e->ux, e->uy, e->uz, e->w,
-                           e->tau, e->id, e->zc);
+        or_parts_push_back(&s->p[e->species], e->ci, e->cj, e->ck, e->ox, e->oy, e->oz,
+                           e->ux, e->uy, e->uz, e->w, e->tau, e->id, e->zc);
     }
     s->nev = 0;
 }
 
-/* Nearest node of a cell-unit position (open x clamps to the wall planes). */
-static size_t nearest_node(const or_sim *s, double X, double Y, double Z) {
+/* Nearest node of a particle (open x clamps to the wall planes). */
+static size_t nearest_node(const or_sim *s, const or_parts *p, size_t n) {
     const or_grid *g = &s->g;
-    int i = (int)floor(X + 0.5), j = (int)floor(Y + 0.5), k = (int)floor(Z + 0.5);
+    int i = p->ci[n] + (p->ox[n] >= 0.5), j = p->cj[n] + (p->oy[n] >= 0.5);
+    int k = p->ck[n] + (p->oz[n] >= 0.5);
     if (g->bc_x == OR_BC_PERIODIC) i = or_wrap(i, g->nx);
-    else i = i < 0 ? 0 : (i > g->nx ? g->nx : i);
+    else i = i > g->nx ? g->nx : i;
     return or_idx(s, i, or_wrap(j, g->ny), or_wrap(k, g->nz));
+}
+
+/* Carry a position relative to cell c into [0,1) offsets of its new cell. */
+void or_carry(const or_sim *s, int c[3], double X[3]) {
+    const or_grid *g = &s->g;
+    for (int d = 0; d < 3; ++d) {
+        int f = (int)floor(X[d]);
+        c[d] += f;
+        X[d] -= f;
+    }
+    if (g->bc_x == OR_BC_PERIODIC) c[0] = or_wrap(c[0], g->nx);
+    c[1] = or_wrap(c[1], g->ny);
+    c[2] = or_wrap(c[2], g->nz);
+}
+
+/* Specular reflection at the open x walls of a position X (relative to cell
+ * index ci) after a move: the normal momentum changes sign. */
+void or_reflect_x(const or_sim *s, int ci, double *X, double *ux) {
+    const or_grid *g = &s->g;
+    if (g->bc_x != OR_BC_OPEN) return;
+    double a = ci + *X;                          /* absolute, cell units */
+    if (a < 0.0) { *X = -a - ci; *ux = -*ux; }
+    else if (a >= g->nx) {
+        *X = (2.0 * g->nx - a) - ci;
+        *ux = -*ux;
+        if (ci + *X >= g->nx) *X = nextafter(1.0, 0.0) + (g->nx - 1 - ci);
+    }
 }
 
 /* One pass over every charged particle in species then storage order:
@@ -274,20 +303,21 @@ static size_t nearest_node(const or_sim *s, double X, double Y, double Z) {
 void or_particle_phase(or_sim *s) {
     const or_grid *g = &s->g;
     int hybrid = s->run.switch_mode != OR_SW_ALL_PIC;
-    double Lx = g->nx, Ly = g->ny, Lz = g->nz;   /* cell units */
+    double dxs[3] = {g->dx, g->dy, g->dz};
     for (int isp = 0; isp < s->nsp; ++isp) {
         const or_species *sp = &s->sp[isp];
         if (sp->kind == OR_PHOTON) continue;
         or_parts *p = &s->p[isp];
         size_t n0 = p->n;
         for (size_t n = 0; n < n0; ++n) {
-            double X0[3] = {p->x[n] / g->dx, p->y[n] / g->dy, p->z[n] / g->dz};
-            int kinetic = !hybrid || s->sw[nearest_node(s, X0[0], X0[1], X0[2])];
+            int kinetic = !hybrid || s->sw[nearest_node(s, p, n)];
             if (!sp->mobile && !kinetic) continue;
+            int c[3] = {p->ci[n], p->cj[n], p->ck[n]};
+            double X0[3] = {p->ox[n], p->oy[n], p->oz[n]};
             double e[3], b[3];
             for (int d = 0; d < 3; ++d) {
-                e[d] = or_gather(s, OR_EX + d, X0[0], X0[1], X0[2]);
-                b[d] = or_gather(s, OR_BX + d, X0[0], X0[1], X0[2]);
+                e[d] = or_gather(s, OR_EX + d, c, X0);
+                b[d] = or_gather(s, OR_BX + d, c, X0);
             }
             if (sp->kind == OR_ION && sp->ionizable && s->run.enable_ionization && kinetic)
                 or_ionize_particle(s, isp, n, sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]));
@@ -298,21 +328,13 @@ void or_particle_phase(or_sim *s) {
             double u[3] = {p->ux[n], p->uy[n], p->uz[n]};
             or_boris(q / sp->mass, g->dt, e, b, u);
             double gam = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            double X1[3] = {X0[0] + g->dt * u[0] / gam / g->dx,
-                            X0[1] + g->dt * u[1] / gam / g->dy,
-                            X0[2] + g->dt * u[2] / gam / g->dz};
-            if (g->bc_x == OR_BC_OPEN) {
-                if (X1[0] < 0.0) { X1[0] = -X1[0]; u[0] = -u[0]; }
-                else if (X1[0] >= Lx) {
-                    X1[0] = 2.0 * Lx - X1[0]; u[0] = -u[0];
-                    if (X1[0] >= Lx) X1[0] = nextafter(Lx, 0.0);
-                }
-            }
-            if (q != 0.0) or_deposit_move(s, q, p->w[n], X0, X1);
-            if (g->bc_x == OR_BC_PERIODIC) X1[0] = fmod(X1[0] + Lx, Lx);
-            X1[1] = fmod(X1[1] + Ly, Ly);
-            X1[2] = fmod(X1[2] + Lz, Lz);
-            p->x[n] = X1[0] * g->dx; p->y[n] = X1[1] * g->dy; p->z[n] = X1[2] * g->dz;
+            double X1[3];
+            for (int d = 0; d < 3; ++d) X1[d] = X0[d] + g->dt * u[d] / gam / dxs[d];
+            or_reflect_x(s, c[0], &X1[0], &u[0]);
+            if (q != 0.0) or_deposit_move(s, q, p->w[n], c, X0, X1);
+            or_carry(s, c, X1);
+            p->ci[n] = c[0]; p->cj[n] = c[1]; p->ck[n] = c[2];
+            p->ox[n] = X1[0]; p->oy[n] = X1[1]; p->oz[n] = X1[2];
             p->ux[n] = u[0]; p->uy[n] = u[1]; p->uz[n] = u[2];
         }
     }

@@ -54,7 +54,7 @@ void or_destroy(or_sim *s) {
     for (int c = 0; c < OR_NCOMP; ++c) free(s->f[c]);
     for (int i = 0; i < s->nsp; ++i) {
         or_parts *p = &s->p[i];
-        free(p->x); free(p->y); free(p->z); free(p->ux); free(p->uy); free(p->uz);
+        free(p->ci); free(p->cj); free(p->ck); free(p->ox); free(p->oy); free(p->oz); free(p->ux); free(p->uy); free(p->uz);
         free(p->w); free(p->tau); free(p->id); free(p->zc);
         free(s->fn[i]);
         for (int d = 0; d < 3; ++d) free(s->fu[i][d]);
@@ -124,7 +124,11 @@ int or_get_particles(const or_sim *s, int sp, double *x, double *u, double *w, u
     if (sp < 0 || sp >= s->nsp) return -1;
     const or_parts *p = &s->p[sp];
     for (size_t n = 0; n < p->n; ++n) {
-        if (x) { x[3 * n] = p->x[n]; x[3 * n + 1] = p->y[n]; x[3 * n + 2] = p->z[n]; }
+        if (x) {
+            x[3 * n] = (p->ci[n] + p->ox[n]) * s->g.dx;
+            x[3 * n + 1] = (p->cj[n] + p->oy[n]) * s->g.dy;
+            x[3 * n + 2] = (p->ck[n] + p->oz[n]) * s->g.dz;
+        }
         if (u) { u[3 * n] = p->ux[n]; u[3 * n + 1] = p->uy[n]; u[3 * n + 2] = p->uz[n]; }
         if (w) w[n] = p->w[n];
         if (id) id[n] = p->id[n];
@@ -140,10 +144,20 @@ int or_set_particles(or_sim *s, int sp, size_t n, const double *x, const double 
     or_parts *p = &s->p[sp];
     p->n = 0;
     or_parts_reserve(p, n);
-    for (size_t q = 0; q < n; ++q)
-        or_parts_push_back(p, x[3 * q], x[3 * q + 1], x[3 * q + 2], u[3 * q], u[3 * q + 1],
+    double dxs[3] = {s->g.dx, s->g.dy, s->g.dz};
+    for (size_t q = 0; q < n; ++q) {
+        /* absolute position -> cell index + offset (same rule as the library) */
+        int c[3];
+        double o[3];
+        for (int d = 0; d < 3; ++d) {
+            double X = x[3 * q + d] / dxs[d];
+            c[d] = (int)floor(X);
+            o[d] = X - c[d];
+        }
+        or_parts_push_back(p, c[0], c[1], c[2], o[0], o[1], o[2], u[3 * q], u[3 * q + 1],
                            u[3 * q + 2], w[q], tau ? tau[q] : 0.0, id ? id[q] : q,
                            z ? z[q] : (int32_t)llround(s->sp[sp].charge));
+    }
     s->have_gauss0 = 0;
     return 0;
 }

@@ -44,10 +44,13 @@ static int node_x_count(const or_sim *s) {
     return s->g.bc_x == OR_BC_PERIODIC ? s->g.nx : s->g.nx + 1;
 }
 
-static size_t nearest(const or_sim *s, double X, double Y, double Z, int *ijk) {
-    int i = (int)floor(X + 0.5), j = (int)floor(Y + 0.5), k = (int)floor(Z + 0.5);
-    if (ijk) { ijk[0] = i; ijk[1] = j; ijk[2] = k; }
-    return or_idx(s, clampx(s, i), or_wrap(j, s->g.ny), or_wrap(k, s->g.nz));
+/* Nearest node of particle n; rel receives the node's offset (0 or 1 per
+ * axis) relative to the particle's cell. */
+static size_t nearest(const or_sim *s, const or_parts *p, size_t n, int *rel) {
+    int r[3] = {p->ox[n] >= 0.5, p->oy[n] >= 0.5, p->oz[n] >= 0.5};
+    if (rel) { rel[0] = r[0]; rel[1] = r[1]; rel[2] = r[2]; }
+    return or_idx(s, clampx(s, p->ci[n] + r[0]), or_wrap(p->cj[n] + r[1], s->g.ny),
+                  or_wrap(p->ck[n] + r[2], s->g.nz));
 }
 
 extern double or_cnn_switch(or_sim *s, const double *nmom, const double *u2mom,
@@ -68,7 +71,7 @@ void or_switch_eval(or_sim *s) {
         const or_parts *p = &s->p[isp];
         if (sp->fluid) {
             for (size_t n = 0; n < p->n; ++n) {
-                size_t c = nearest(s, p->x[n] / g->dx, p->y[n] / g->dy, p->z[n] / g->dz, NULL);
+                size_t c = nearest(s, p, n, NULL);
                 double u[3] = {p->ux[n], p->uy[n], p->uz[n]};
                 N[c] += p->w[n];
                 V[c] += p->w[n] * p->w[n];
@@ -89,7 +92,7 @@ void or_switch_eval(or_sim *s) {
         if (sp->kind == OR_ION && sp->ionizable && s->run.enable_ionization)
             for (size_t n = 0; n < p->n; ++n)
                 if (p->zc[n] < sp->z_max) {
-                    size_t c = nearest(s, p->x[n] / g->dx, p->y[n] / g->dy, p->z[n] / g->dz, NULL);
+                    size_t c = nearest(s, p, n, NULL);
                     NI[c] += p->w[n];
                 }
     }
@@ -105,7 +108,9 @@ void or_switch_eval(or_sim *s) {
             for (int i = 0; i < nxn; ++i) {
                 size_t c = or_idx(s, i, j, k);
                 double e[3];
-                for (int d = 0; d < 3; ++d) e[d] = or_gather(s, OR_EX + d, i, j, k);
+                int node[3] = {i, j, k};
+                double z0[3] = {0, 0, 0};
+                for (int d = 0; d < 3; ++d) e[d] = or_gather(s, OR_EX + d, node, z0);
                 double emag = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
                 size_t xp = or_idx(s, clampx(s, i + 1), j, k), xm = or_idx(s, clampx(s, i - 1), j, k);
                 size_t yp = or_idx(s, i, or_wrap(j + 1, g->ny), k), ym = or_idx(s, i, or_wrap(j - 1, g->ny), k);
@@ -183,12 +188,12 @@ void or_reconcile(or_sim *s) {
         /* absorb, in storage order */
         size_t keep = 0;
         for (size_t q = 0; q < p->n; ++q) {
-            double X[3] = {p->x[q] / g->dx, p->y[q] / g->dy, p->z[q] / g->dz};
-            int ijk[3];
-            size_t c = nearest(s, X[0], X[1], X[2], ijk);
+            int rel[3];
+            size_t c = nearest(s, p, q, rel);
             if (s->sw[c]) {
                 if (keep != q) {
-                    p->x[keep] = p->x[q]; p->y[keep] = p->y[q]; p->z[keep] = p->z[q];
+                    p->ci[keep] = p->ci[q]; p->cj[keep] = p->cj[q]; p->ck[keep] = p->ck[q];
+                    p->ox[keep] = p->ox[q]; p->oy[keep] = p->oy[q]; p->oz[keep] = p->oz[q];
                     p->ux[keep] = p->ux[q]; p->uy[keep] = p->uy[q]; p->uz[keep] = p->uz[q];
                     p->w[keep] = p->w[q]; p->tau[keep] = p->tau[q]; p->id[keep] = p->id[q];
                     p->zc[keep] = p->zc[q];
@@ -196,9 +201,10 @@ void or_reconcile(or_sim *s) {
                 keep++;
                 continue;
             }
-            double Xn[3] = {(double)clampx(s, ijk[0]), (double)ijk[1], (double)ijk[2]};
-            if (g->bc_x == OR_BC_PERIODIC) Xn[0] = ijk[0];
-            or_deposit_move(s, sp->charge, p->w[q], X, Xn);
+            int cell[3] = {p->ci[q], p->cj[q], p->ck[q]};
+            double X[3] = {p->ox[q], p->oy[q], p->oz[q]};
+            double Xn[3] = {(double)rel[0], (double)rel[1], (double)rel[2]};
+            or_deposit_move(s, sp->charge, p->w[q], cell, X, Xn);
             double u[3] = {p->ux[q], p->uy[q], p->uz[q]};
             double gam = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
             s->conv_loss += p->w[q] * sp->mass * (gam - 1.0);
@@ -236,22 +242,19 @@ void or_reconcile(or_sim *s) {
                     for (int q = 0; q < m; ++q) {
                         uint32_t r[4];
                         or_draw4(s, node, (uint32_t)s->step, 12, (uint32_t)q, r);
-                        double X0[3] = {(double)i, (double)j, (double)k};
-                        double X1[3] = {i + or_uniform(r[0]) - 0.5, j + or_uniform(r[1]) - 0.5,
-                                        k + or_uniform(r[2]) - 0.5};
-                        if (g->bc_x == OR_BC_OPEN) {
-                            if (X1[0] < 0) X1[0] = -X1[0];
-                            else if (X1[0] >= g->nx) {
-                                X1[0] = 2.0 * g->nx - X1[0];
-                                if (X1[0] >= g->nx) X1[0] = nextafter((double)g->nx, 0.0);
-                            }
-                        }
-                        or_deposit_move(s, sp->charge, w, X0, X1);
-                        double xw = g->bc_x == OR_BC_PERIODIC ? fmod(X1[0] + g->nx, g->nx) : X1[0];
-                        double yw = fmod(X1[1] + g->ny, g->ny), zw = fmod(X1[2] + g->nz, g->nz);
+                        /* move from the node to node + (r - 1/2) in each axis */
+                        int cell[3] = {i, j, k};
+                        double X0[3] = {0.0, 0.0, 0.0};
+                        double X1[3] = {or_uniform(r[0]) - 0.5, or_uniform(r[1]) - 0.5,
+                                        or_uniform(r[2]) - 0.5};
+                        double ux = u[0];
+                        or_reflect_x(s, i, &X1[0], &ux);
+                        or_deposit_move(s, sp->charge, w, cell, X0, X1);
+                        or_carry(s, cell, X1);
                         uint64_t id = (1ull << 63) | ((uint64_t)s->step << 40) | (node << 6) | (uint64_t)q;
-                        or_parts_push_back(p, xw * g->dx, yw * g->dy, zw * g->dz, u[0], u[1], u[2],
-                                           w, 0.0, id, (int32_t)llround(sp->charge));
+                        or_parts_push_back(p, cell[0], cell[1], cell[2], X1[0], X1[1], X1[2],
+                                           u[0], u[1], u[2], w, 0.0, id,
+                                           (int32_t)llround(sp->charge));
                     }
                     n[c] = 0.0;
                     s->fu[isp][0][c] = s->fu[isp][1][c] = s->fu[isp][2][c] = 0.0;
