@@ -1,0 +1,891 @@
+// C ABI of the hybrid fluid-kinetic step: context, device memory, the step
+// schedule and the host-side accessors.  Every arithmetic step of the method
+// runs in the kernels of k_*.hip; this file only orders launches, owns memory
+// and moves data across the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hk_internal.h"
+
+// launchers defined in the kernel files
+void launch_init_species_cols(const GridP &g, const hk_species_desc &d, uint64_t seed, PArr out,
+                              const int *xcol, const double *wcol, int ncol, int has_z,
+                              int has_tau, hipStream_t s);
+void launch_count_groups(const GridP &g, PArr src, const long long *off, const int *cnt,
+                         const int *cap, int ngroups, int *newcnt, hipStream_t s);
+void launch_scatter_groups(const GridP &g, PArr src, const long long *off, const int *cnt,
+                           const int *cap, int ngroups, PArr dst, const long long *doff,
+                           int *dfill, int has_z, int has_tau, hipStream_t s);
+void launch_merge_inbox(const GridP &g, const SpecP &sp, PArr inbox, const int *inbox_n,
+                        long long max_n, PArr dst, int *cnt, int *fail_n, PArr fail,
+                        hipStream_t s);
+void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, const int *cnt_in, PArr out,
+                       int *cnt_out, PArr inbox, int *inbox_n, int inbox_cap, real *const f[9],
+                       int *err, hipStream_t s);
+void launch_ionize_static(const GridP &g, const SpecP &sp, PArr a, const int *cnt,
+                          real *const f[9], const uint8_t *sw, int hybrid, const IonP *ion,
+                          PArr eout, int *eout_n, int eout_cap, uint64_t seed, int step,
+                          double *ledger, int *err, hipStream_t s);
+void launch_rho_tiles(const GridP &g, const SpecP &sp, PArr a, const int *cnt, double *rho,
+                      hipStream_t s);
+
+namespace {
+
+// Physical constants (CODATA 2018) for the SI scale of ionization and QED.
+constexpr double PHYS_C = 299792458.0, PHYS_ME = 9.1093837015e-31, PHYS_QE = 1.602176634e-19;
+constexpr double PHYS_HBAR = 1.054571817e-34, PHYS_EA = 5.14220674763e11;
+constexpr double PHYS_TA = 2.4188843265857e-17, PHYS_HARTREE_EV = 27.211386245988;
+constexpr double PI = 3.14159265358979323846;
+
+struct DevSpecies {
+    hk_species_desc d{};
+    int has_z = 0, has_tau = 0;
+    PArr buf[2]{};
+    int cur = 0;
+    long long capacity = 0;
+    long long *off = nullptr;  // device [ntiles]
+    int *cap = nullptr;        // device [ntiles]
+    int *cnt[2] = {nullptr, nullptr};
+    std::vector<long long> h_off;
+    std::vector<int> h_cap;
+    PArr inbox{}, fail{};
+    int inbox_cap = 0;
+    long long *g_off0 = nullptr;  // device {0}
+    int *g_capmax = nullptr;      // device {INT_MAX}
+    real *fn = nullptr, *fu[3] = {nullptr, nullptr, nullptr};  // cold fluid
+    IonP *ion = nullptr;          // device rate constants
+    long long reserve_hint = 0;   // expected peak count (ionization targets)
+};
+
+}  // namespace
+
+struct hk_sim {
+    GridP g{};
+    hk_grid_desc gd{};
+    hk_laser_desc las{};
+    hk_run_desc run{};
+    int nsp = 0;
+    DevSpecies sp[HK_MAX_SPECIES];
+    hipStream_t s = nullptr;
+    real *fblock = nullptr;      // the 9 field arrays, contiguous
+    real *f[9]{};
+    real *mur_old = nullptr;
+    uint8_t *sw = nullptr, *calm = nullptr, *hot = nullptr, *notcold = nullptr;
+    float *mom = nullptr;        // switch moments
+    real *fluid_scratch = nullptr;
+    double *gauss0 = nullptr, *tmp_a = nullptr, *tmp_b = nullptr;
+    double *dsum = nullptr;      // diagnostic accumulators
+    double *ledger = nullptr;    // [0] conversion loss, [1] ionization, [2] photons
+    int *status = nullptr;       // [0] error bits, [1 + 2s] inbox count, [2 + 2s] fail count
+    int *h_status = nullptr;     // pinned
+    int have_gauss0 = 0;
+    int64_t step = 0;
+    double t = 0;
+    int poisoned = 0;
+    std::string err;
+    std::vector<void *> allocs;
+    bool timing = false;
+    double timers[8]{};
+    hipEvent_t ev[9]{};
+    double fallback_fraction = 0;
+};
+
+namespace {
+
+int fail(hk_sim *S, int code, const char *fmt, ...) {
+    if (S) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        S->err = buf;
+        if (code == HK_EDEVICE || code == HK_ENUMERIC || code == HK_EOVERFLOW) S->poisoned = 1;
+    }
+    return code;
+}
+
+#define HIPCHK(S, x)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (x);                                                              \
+        if (e_ != hipSuccess) return fail(S, HK_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+void *dalloc(hk_sim *S, size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (S->run.alloc) p = S->run.alloc(bytes, S->run.alloc_ctx);
+    else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    if (p) {
+        S->allocs.push_back(p);
+        launch_zero(p, bytes, S->s);
+    }
+    return p;
+}
+
+void dfree(hk_sim *S, void *p) {
+    if (!p) return;
+    auto it = std::find(S->allocs.begin(), S->allocs.end(), p);
+    if (it != S->allocs.end()) S->allocs.erase(it);
+    if (S->run.free) S->run.free(p, S->run.alloc_ctx);
+    else (void)hipFree(p);
+}
+
+bool alloc_parr(hk_sim *S, PArr &a, long long n, int has_z, int has_tau) {
+    a = PArr{};
+    if (n <= 0) n = 1;
+    a.cell = (int *)dalloc(S, sizeof(int) * n);
+    a.rx = (real *)dalloc(S, sizeof(real) * n);
+    a.ry = (real *)dalloc(S, sizeof(real) * n);
+    a.rz = (real *)dalloc(S, sizeof(real) * n);
+    a.ux = (real *)dalloc(S, sizeof(real) * n);
+    a.uy = (real *)dalloc(S, sizeof(real) * n);
+    a.uz = (real *)dalloc(S, sizeof(real) * n);
+    a.w = (real *)dalloc(S, sizeof(real) * n);
+    a.id = (uint64_t *)dalloc(S, sizeof(uint64_t) * n);
+    if (has_z) a.zc = (int *)dalloc(S, sizeof(int) * n);
+    if (has_tau) a.tau = (double *)dalloc(S, sizeof(double) * n);
+    return a.cell && a.rx && a.ry && a.rz && a.ux && a.uy && a.uz && a.w && a.id &&
+           (!has_z || a.zc) && (!has_tau || a.tau);
+}
+
+void free_parr(hk_sim *S, PArr &a) {
+    void *ps[] = {a.cell, a.rx, a.ry, a.rz, a.ux, a.uy, a.uz, a.w, a.id, a.zc, a.tau};
+    for (void *p : ps) dfree(S, p);
+    a = PArr{};
+}
+
+SpecP specp(const DevSpecies &d) {
+    SpecP p{};
+    p.kind = d.d.kind;
+    p.mobile = d.d.mobile;
+    p.fluid = d.d.fluid;
+    p.ionizable = d.d.ionizable;
+    p.z_max = d.d.z_max;
+    p.qed = d.d.qed;
+    p.has_z = d.has_z;
+    p.has_tau = d.has_tau;
+    p.q = (real)d.d.charge;
+    p.m = (real)d.d.mass;
+    p.qm = d.d.mass > 0 ? (real)(d.d.charge / d.d.mass) : (real)0;
+    p.off = d.off;
+    p.cap = d.cap;
+    return p;
+}
+
+double profile(const hk_species_desc &d, double x) {
+    switch (d.profile) {
+    case HK_PROF_UNIFORM: return d.n0;
+    case HK_PROF_RAMP: return x < d.x0 ? 0.0 : d.n0 * std::min(1.0, (x - d.x0) / d.length);
+    case HK_PROF_FOIL: return (x >= d.x0 && x < d.x0 + d.length) ? d.n0 : 0.0;
+    default: return 0.0;
+    }
+}
+
+// Re-bin a species from its current bins plus up to two unbinned lists into a
+// fresh layout whose per-tile capacity leaves headroom for growth.
+int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, int nlists) {
+    DevSpecies &D = S->sp[isp];
+    const GridP &g = S->g;
+    const int nt = g.ntiles;
+    int *newcnt = (int *)dalloc(S, sizeof(int) * nt);
+    if (!newcnt) return fail(S, HK_ENOMEM, "rebuild: counts");
+    PArr cur = D.buf[D.cur];
+    if (use_tiles && D.capacity > 0)
+        launch_count_groups(g, cur, D.off, D.cnt[D.cur], D.cap, nt, newcnt, S->s);
+    for (int l = 0; l < nlists; ++l)
+        launch_count_groups(g, lists[l], D.g_off0, list_n[l], D.g_capmax, 1, newcnt, S->s);
+    std::vector<int> h(nt);
+    HIPCHK(S, hipMemcpyAsync(h.data(), newcnt, sizeof(int) * nt, hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    // capacity: 25% headroom plus one wavefront, at least the reserve hint share
+    long long hint_per_tile = D.reserve_hint > 0 ? (D.reserve_hint + nt - 1) / nt : 0;
+    std::vector<long long> off(nt);
+    std::vector<int> cap(nt);
+    long long total = 0;
+    for (int t = 0; t < nt; ++t) {
+        long long c = (long long)h[t] + h[t] / 4 + 64;
+        long long hc = hint_per_tile + hint_per_tile / 8 + 64;
+        c = std::max(c, std::min<long long>(hc, INT_MAX / 2));
+        c = (c + 63) & ~63LL;
+        off[t] = total;
+        cap[t] = (int)c;
+        total += c;
+    }
+    PArr nb[2];
+    if (!alloc_parr(S, nb[0], total, D.has_z, D.has_tau) ||
+        !alloc_parr(S, nb[1], total, D.has_z, D.has_tau))
+        return fail(S, HK_ENOMEM, "rebuild: %lld particle slots", total);
+    long long *doff = (long long *)dalloc(S, sizeof(long long) * nt);
+    int *dcap = (int *)dalloc(S, sizeof(int) * nt);
+    int *dfill = (int *)dalloc(S, sizeof(int) * nt);
+    int *c0 = (int *)dalloc(S, sizeof(int) * nt), *c1 = (int *)dalloc(S, sizeof(int) * nt);
+    if (!doff || !dcap || !dfill || !c0 || !c1) return fail(S, HK_ENOMEM, "rebuild: tables");
+    HIPCHK(S, hipMemcpyAsync(doff, off.data(), sizeof(long long) * nt, hipMemcpyHostToDevice, S->s));
+    HIPCHK(S, hipMemcpyAsync(dcap, cap.data(), sizeof(int) * nt, hipMemcpyHostToDevice, S->s));
+    if (use_tiles && D.capacity > 0)
+        launch_scatter_groups(g, cur, D.off, D.cnt[D.cur], D.cap, nt, nb[0], doff, dfill,
+                              D.has_z, D.has_tau, S->s);
+    for (int l = 0; l < nlists; ++l)
+        launch_scatter_groups(g, lists[l], D.g_off0, list_n[l], D.g_capmax, 1, nb[0], doff,
+                              dfill, D.has_z, D.has_tau, S->s);
+    HIPCHK(S, hipMemcpyAsync(c0, dfill, sizeof(int) * nt, hipMemcpyDeviceToDevice, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    free_parr(S, D.buf[0]);
+    free_parr(S, D.buf[1]);
+    dfree(S, D.off); dfree(S, D.cap); dfree(S, D.cnt[0]); dfree(S, D.cnt[1]);
+    dfree(S, newcnt); dfree(S, dfill);
+    D.buf[0] = nb[0];
+    D.buf[1] = nb[1];
+    D.cur = 0;
+    D.off = doff;
+    D.cap = dcap;
+    D.cnt[0] = c0;
+    D.cnt[1] = c1;
+    D.capacity = total;
+    D.h_off = off;
+    D.h_cap = cap;
+    return HK_OK;
+}
+
+int ensure_inbox(hk_sim *S, int isp, long long need) {
+    DevSpecies &D = S->sp[isp];
+    if (need <= D.inbox_cap) return HK_OK;
+    long long c = std::max<long long>(need, 2LL * D.inbox_cap);
+    c = std::min<long long>(c, INT_MAX / 2);
+    free_parr(S, D.inbox);
+    free_parr(S, D.fail);
+    if (!alloc_parr(S, D.inbox, c, D.has_z, D.has_tau) || !alloc_parr(S, D.fail, c, D.has_z, D.has_tau))
+        return fail(S, HK_ENOMEM, "inbox of %lld", c);
+    D.inbox_cap = (int)c;
+    int capv[1] = {(int)INT_MAX};
+    HIPCHK(S, hipMemcpyAsync(D.g_capmax, capv, sizeof(int), hipMemcpyHostToDevice, S->s));
+    return HK_OK;
+}
+
+int build_ion_table(hk_sim *S, int isp) {
+    DevSpecies &D = S->sp[isp];
+    IonP P{};
+    double omega0 = 2.0 * PI * PHYS_C / (S->las.lambda_um * 1e-6);
+    double eunit = PHYS_ME * PHYS_C * omega0 / PHYS_QE;
+    P.field_au = eunit / PHYS_EA;
+    P.omega_au = omega0 * PHYS_TA;
+    P.rate_norm = 1.0 / P.omega_au;
+    P.dt_au = S->gd.dt / P.omega_au;
+    P.z_max = D.d.z_max;
+    P.target = D.d.target;
+    for (int l = 0; l < D.d.z_max && l < HK_MAX_LEVELS; ++l) {
+        IonLevel &L = P.lev[l];
+        L.ip_au = D.d.ip_ev[l] / PHYS_HARTREE_EV;
+        L.zres = l + 1;
+        double ns = L.zres / std::sqrt(2.0 * L.ip_au);
+        L.c2 = std::pow(2.0, 2.0 * ns) / (ns * std::tgamma(2.0 * ns));
+        L.k3 = std::pow(2.0 * L.ip_au, 1.5);
+        L.expo = 2.0 * ns - 1.0;
+        L.fc = P.omega_au * std::sqrt(2.0 * L.ip_au) / 1.5;
+        L.wfc = L.c2 * L.ip_au * std::pow(2.0 * L.k3 / L.fc, L.expo) * std::exp(-2.0 * L.k3 / (3.0 * L.fc));
+        L.K2 = 2.0 * std::ceil(L.ip_au / P.omega_au);
+    }
+    D.ion = (IonP *)dalloc(S, sizeof(IonP));
+    if (!D.ion) return fail(S, HK_ENOMEM, "ion table");
+    HIPCHK(S, hipMemcpyAsync(D.ion, &P, sizeof(IonP), hipMemcpyHostToDevice, S->s));
+    return HK_OK;
+}
+
+int init_species(hk_sim *S, int isp) {
+    DevSpecies &D = S->sp[isp];
+    const GridP &g = S->g;
+    const hk_species_desc &d = D.d;
+    D.g_off0 = (long long *)dalloc(S, sizeof(long long));
+    D.g_capmax = (int *)dalloc(S, sizeof(int));
+    if (!D.g_off0 || !D.g_capmax) return fail(S, HK_ENOMEM, "species tables");
+    std::vector<int> xcol;
+    std::vector<double> wcol;
+    double dv = g.ddx * g.ddy * g.ddz;
+    if (d.ppc > 0 && d.profile != HK_PROF_NONE)
+        for (int i = 0; i < g.nx; ++i) {
+            double n = profile(d, (i + 0.5) * g.ddx);
+            if (n > 0) { xcol.push_back(i); wcol.push_back(n * dv / d.ppc); }
+        }
+    long long total = (long long)xcol.size() * g.ny * g.nz * std::max(d.ppc, 0);
+    int rc = ensure_inbox(S, isp, std::max<long long>(total, 1 << 16));
+    if (rc) return rc;
+    if (total > 0) {
+        int *dx = (int *)dalloc(S, sizeof(int) * xcol.size());
+        double *dw = (double *)dalloc(S, sizeof(double) * wcol.size());
+        if (!dx || !dw) return fail(S, HK_ENOMEM, "init columns");
+        HIPCHK(S, hipMemcpyAsync(dx, xcol.data(), sizeof(int) * xcol.size(), hipMemcpyHostToDevice, S->s));
+        HIPCHK(S, hipMemcpyAsync(dw, wcol.data(), sizeof(double) * wcol.size(), hipMemcpyHostToDevice, S->s));
+        launch_init_species_cols(g, d, S->run.seed, D.inbox, dx, dw, (int)xcol.size(), D.has_z,
+                                 D.has_tau, S->s);
+        int n32 = (int)total;
+        HIPCHK(S, hipMemcpyAsync(S->status + 1 + 2 * isp, &n32, sizeof(int), hipMemcpyHostToDevice, S->s));
+        HIPCHK(S, hipStreamSynchronize(S->s));
+        dfree(S, dx);
+        dfree(S, dw);
+    }
+    int *ln = S->status + 1 + 2 * isp;
+    PArr lists[1] = {D.inbox};
+    rc = rebuild(S, isp, false, lists, &ln, total > 0 ? 1 : 0);
+    if (rc) return rc;
+    HIPCHK(S, hipMemsetAsync(S->status + 1 + 2 * isp, 0, sizeof(int), S->s));
+    return HK_OK;
+}
+
+void time_mark(hk_sim *S, int slot) {
+    if (S->timing) (void)hipEventRecord(S->ev[slot], S->s);
+}
+
+int check_status(hk_sim *S) {
+    HIPCHK(S, hipMemcpyAsync(S->h_status, S->status, sizeof(int) * (1 + 2 * HK_MAX_SPECIES),
+                             hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    int e = S->h_status[0];
+    if (e & ERR_NONFINITE) return fail(S, HK_ENUMERIC, "non-finite momentum at step %lld", (long long)S->step);
+    if (e & ERR_CFL) return fail(S, HK_ENUMERIC, "particle moved a cell or more at step %lld", (long long)S->step);
+    if (e & ERR_INBOX) return fail(S, HK_EOVERFLOW, "particle inbox overflow at step %lld", (long long)S->step);
+    if (e & ERR_TILE) return fail(S, HK_EDEVICE, "particle outside its tile at step %lld", (long long)S->step);
+    return HK_OK;
+}
+
+int gauss_snapshot(hk_sim *S);
+
+// Inbox size of a species: the particles one step can send past full bins
+// (a quarter of the capacity; bins keep 25% headroom) plus every electron the
+// ions targeting it can free in one step.
+long long inbox_need(hk_sim *S, int isp) {
+    long long need = std::max<long long>(S->sp[isp].capacity / 4, 1 << 16);
+    for (int j = 0; j < S->nsp; ++j)
+        if (S->sp[j].d.ionizable && S->sp[j].d.target == isp && S->run.enable_ionization)
+            need += S->sp[j].capacity * std::max(1, S->sp[j].d.z_max);
+    return need;
+}
+
+// Merge every species' inbox into its next bins; re-bin when bins are full.
+int merge_all(hk_sim *S) {
+    for (int isp = 0; isp < S->nsp; ++isp) {
+        DevSpecies &D = S->sp[isp];
+        if (D.capacity == 0) continue;
+        SpecP P = specp(D);
+        int *inbox_n = S->status + 1 + 2 * isp, *fail_n = S->status + 2 + 2 * isp;
+        launch_merge_inbox(S->g, P, D.inbox, inbox_n, D.inbox_cap, D.buf[D.cur], D.cnt[D.cur],
+                           fail_n, D.fail, S->s);
+    }
+    int rc = check_status(S);
+    if (rc) return rc;
+    for (int isp = 0; isp < S->nsp; ++isp) {
+        DevSpecies &D = S->sp[isp];
+        int nfail = S->h_status[2 + 2 * isp];
+        if (nfail > 0) {
+            int *ln = S->status + 2 + 2 * isp;
+            PArr lists[1] = {D.fail};
+            rc = rebuild(S, isp, true, lists, &ln, 1);
+            if (rc) return rc;
+        }
+        HIPCHK(S, hipMemsetAsync(S->status + 1 + 2 * isp, 0, 2 * sizeof(int), S->s));
+        if (nfail > 0 && D.d.mobile) {
+            rc = ensure_inbox(S, isp, inbox_need(S, isp));
+            if (rc) return rc;
+        }
+    }
+    return HK_OK;
+}
+
+int one_step(hk_sim *S) {
+    hipStream_t s = S->s;
+    const GridP &g = S->g;
+    const int mode = S->run.switch_mode;
+    const int hybrid = mode != HK_SW_ALL_PIC;
+    time_mark(S, 0);
+    // 1. switch evaluation (added with the fluid and switch kernels)
+    time_mark(S, 1);
+    // 2. J = 0, antenna current at t^{n+1/2}
+    launch_zero(S->f[HK_JX], sizeof(real) * 3 * (size_t)g.nn, s);
+    launch_antenna(g, S->las, S->t + 0.5 * g.ddt, S->f[HK_JY], S->f[HK_JZ], s);
+    // 3. particles (mobile species push into the next bins; immobile ions ionize in place)
+    for (int isp = 0; isp < S->nsp; ++isp) {
+        DevSpecies &D = S->sp[isp];
+        if (D.capacity == 0) continue;
+        SpecP P = specp(D);
+        if (D.d.kind == HK_PHOTON) continue;
+        if (D.d.mobile) {
+            int nxt = 1 - D.cur;
+            launch_zero(D.cnt[nxt], sizeof(int) * g.ntiles, s);
+            launch_push_tiles(g, P, D.buf[D.cur], D.cnt[D.cur], D.buf[nxt], D.cnt[nxt], D.inbox,
+                              S->status + 1 + 2 * isp, D.inbox_cap, S->f, S->status, s);
+        } else if (D.d.ionizable && S->run.enable_ionization) {
+            DevSpecies &T = S->sp[D.d.target];
+            launch_ionize_static(g, P, D.buf[D.cur], D.cnt[D.cur], S->f, S->sw, hybrid, D.ion,
+                                 T.inbox, S->status + 1 + 2 * D.d.target, T.inbox_cap,
+                                 S->run.seed, (int)S->step, S->ledger + 1, S->status, s);
+        }
+    }
+    for (int isp = 0; isp < S->nsp; ++isp) {
+        DevSpecies &D = S->sp[isp];
+        if (D.capacity && D.d.mobile && D.d.kind != HK_PHOTON) D.cur = 1 - D.cur;
+    }
+    time_mark(S, 2);
+    time_mark(S, 3);
+    time_mark(S, 4);
+    // 6. merge newborn and overflow particles into their bins
+    int rc = merge_all(S);
+    if (rc) return rc;
+    time_mark(S, 5);
+    // 7. fields
+    launch_yee_b_half(g, S->f, s);
+    launch_yee_e_full(g, S->f, S->mur_old, s);
+    launch_yee_b_half(g, S->f, s);
+    time_mark(S, 6);
+    S->step++;
+    S->t = S->step * g.ddt;
+    if (S->timing) {
+        HIPCHK(S, hipEventSynchronize(S->ev[6]));
+        const int map[6] = {0, 1, 6, 6, 5, 4};  // event interval -> timer slot
+        for (int i = 0; i < 6; ++i) {
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, S->ev[i], S->ev[i + 1]);
+            S->timers[map[i]] += ms;
+        }
+    }
+    (void)hybrid;
+    return HK_OK;
+}
+
+int rho_total(hk_sim *S, double *rho) {
+    launch_zero(rho, sizeof(double) * (size_t)S->g.nn, S->s);
+    for (int isp = 0; isp < S->nsp; ++isp) {
+        DevSpecies &D = S->sp[isp];
+        if (D.d.kind == HK_PHOTON) continue;
+        SpecP P = specp(D);
+        if (D.capacity) launch_rho_tiles(S->g, P, D.buf[D.cur], D.cnt[D.cur], rho, S->s);
+        if (D.fn) launch_fluid_rho(S->g, P, D.fn, rho, S->s);
+    }
+    return HK_OK;
+}
+
+int gauss_snapshot(hk_sim *S) {
+    launch_divE(S->g, S->f, S->gauss0, S->s);
+    rho_total(S, S->tmp_a);
+    launch_sub(S->g.nn, S->gauss0, S->tmp_a, S->s);   // gauss0 = divE - rho
+    S->have_gauss0 = 1;
+    return HK_OK;
+}
+
+bool check_grid(const hk_grid_desc *g) {
+    return g && g->nx >= 4 && g->ny >= 2 && g->nz >= 2 && g->dx > 0 && g->dy > 0 && g->dz > 0 &&
+           g->dt > 0 && (g->bc_x == HK_BC_OPEN || g->bc_x == HK_BC_PERIODIC) &&
+           (long long)g->nx * g->ny * g->nz < (1LL << 31) &&
+           g->dt < 1.0 / std::sqrt(1.0 / (g->dx * g->dx) + 1.0 / (g->dy * g->dy) + 1.0 / (g->dz * g->dz));
+}
+
+}  // namespace
+
+// ====================================================================== ABI ===============
+
+extern "C" {
+
+int hk_real_size(void) { return HK_REAL_BYTES; }
+
+const char *hk_strerror(int code) {
+    switch (code) {
+    case HK_OK: return "ok";
+    case HK_EINVAL: return "invalid argument";
+    case HK_ENOMEM: return "out of memory";
+    case HK_EDEVICE: return "device error";
+    case HK_ENUMERIC: return "numerical failure";
+    case HK_EOVERFLOW: return "particle storage overflow";
+    case HK_ESTATE: return "context poisoned or call invalid in this state";
+    case HK_EIO: return "i/o error";
+    case HK_ENOTSUP: return "not supported by this library";
+    default: return "unknown error";
+    }
+}
+
+const char *hk_last_error(const hk_sim *sim) { return sim ? sim->err.c_str() : "no context"; }
+
+int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspecies,
+              const hk_laser_desc *laser, const hk_run_desc *run, hk_sim **out) {
+    if (!out) return HK_EINVAL;
+    *out = nullptr;
+    if (!check_grid(grid) || !laser || !run || nspecies < 0 || nspecies > HK_MAX_SPECIES ||
+        (nspecies > 0 && !species))
+        return HK_EINVAL;
+    if (run->switch_mode < HK_SW_ALL_PIC || run->switch_mode > HK_SW_FIXED) return HK_EINVAL;
+    if (laser->enabled && (laser->i_antenna < 1 || laser->i_antenna >= grid->nx || laser->duration <= 0 ||
+                           laser->waist <= 0 || laser->lambda_um <= 0))
+        return HK_EINVAL;
+    for (int i = 0; i < nspecies; ++i) {
+        const hk_species_desc &d = species[i];
+        if (d.kind < HK_ELECTRON || d.kind > HK_PHOTON || d.ppc < 0 || d.ppc > 64) return HK_EINVAL;
+        if (d.kind != HK_PHOTON && d.mass <= 0) return HK_EINVAL;
+        if (d.ionizable && (d.kind != HK_ION || d.z_max < 1 || d.z_max > HK_MAX_LEVELS ||
+                            d.target < 0 || d.target >= nspecies || d.mobile))
+            return HK_EINVAL;
+    }
+    if (run->enable_qed) return HK_ENOTSUP;
+    if (run->switch_mode != HK_SW_ALL_PIC) return HK_ENOTSUP;
+    hk_sim *S = new hk_sim();
+    S->gd = *grid;
+    S->las = *laser;
+    S->run = *run;
+    S->nsp = nspecies;
+    S->s = (hipStream_t)run->stream;
+    GridP &g = S->g;
+    g.nx = grid->nx; g.ny = grid->ny; g.nz = grid->nz; g.sx = grid->nx + 1;
+    g.bcx = grid->bc_x;
+    g.ntx = (g.nx + TILE - 1) / TILE; g.nty = (g.ny + TILE - 1) / TILE; g.ntz = (g.nz + TILE - 1) / TILE;
+    g.ntiles = g.ntx * g.nty * g.ntz;
+    g.nn = (long long)g.sx * g.ny * g.nz;
+    g.dx = (real)grid->dx; g.dy = (real)grid->dy; g.dz = (real)grid->dz; g.dt = (real)grid->dt;
+    g.ddx = grid->dx; g.ddy = grid->dy; g.ddz = grid->dz; g.ddt = grid->dt;
+    int rc = HK_OK;
+    S->fblock = (real *)dalloc(S, sizeof(real) * 9 * (size_t)g.nn);
+    S->mur_old = (real *)dalloc(S, sizeof(real) * 8 * (size_t)g.ny * g.nz);
+    S->sw = (uint8_t *)dalloc(S, (size_t)g.nn);
+    S->calm = (uint8_t *)dalloc(S, (size_t)g.nn);
+    S->gauss0 = (double *)dalloc(S, sizeof(double) * (size_t)g.nn);
+    S->tmp_a = (double *)dalloc(S, sizeof(double) * (size_t)g.nn);
+    S->tmp_b = (double *)dalloc(S, sizeof(double) * (size_t)g.nn);
+    S->dsum = (double *)dalloc(S, sizeof(double) * 64);
+    S->ledger = (double *)dalloc(S, sizeof(double) * 8);
+    S->status = (int *)dalloc(S, sizeof(int) * (1 + 2 * HK_MAX_SPECIES));
+    if (hipHostMalloc((void **)&S->h_status, sizeof(int) * (1 + 2 * HK_MAX_SPECIES), 0) != hipSuccess)
+        S->h_status = nullptr;
+    if (!S->fblock || !S->mur_old || !S->sw || !S->calm || !S->gauss0 || !S->tmp_a || !S->tmp_b ||
+        !S->dsum || !S->ledger || !S->status || !S->h_status) {
+        hk_destroy(S);
+        return HK_ENOMEM;
+    }
+    for (int c = 0; c < 9; ++c) S->f[c] = S->fblock + (size_t)c * g.nn;
+    (void)hipMemsetAsync(S->sw, run->switch_mode == HK_SW_ALL_FLUID ? 0 : 1, (size_t)g.nn, S->s);
+    for (int i = 0; i < nspecies; ++i) {
+        DevSpecies &D = S->sp[i];
+        D.d = species[i];
+        D.has_z = D.d.kind == HK_ION;
+        D.has_tau = 0;
+    }
+    // ionization targets: reserve bins for the electrons the ions can free
+    for (int i = 0; i < nspecies; ++i)
+        if (species[i].ionizable && run->enable_ionization) {
+            double dv = grid->dx * grid->dy * grid->dz;
+            long long ions = 0;
+            for (int x = 0; x < grid->nx; ++x)
+                if (profile(species[i], (x + 0.5) * grid->dx) > 0) ions += (long long)grid->ny * grid->nz * species[i].ppc;
+            (void)dv;
+            S->sp[species[i].target].reserve_hint += ions * species[i].z_max;
+        }
+    for (int i = 0; i < nspecies && rc == HK_OK; ++i) rc = init_species(S, i);
+    for (int i = 0; i < nspecies && rc == HK_OK; ++i)
+        if (species[i].ionizable && run->enable_ionization) rc = build_ion_table(S, i);
+    for (int i = 0; i < nspecies && rc == HK_OK; ++i) rc = ensure_inbox(S, i, inbox_need(S, i));
+    if (rc == HK_OK && hipStreamSynchronize(S->s) != hipSuccess) rc = HK_EDEVICE;
+    if (rc != HK_OK) {
+        hk_destroy(S);
+        return rc;
+    }
+    for (int i = 0; i < 9; ++i) (void)hipEventCreate(&S->ev[i]);
+    *out = S;
+    return HK_OK;
+}
+
+void hk_destroy(hk_sim *S) {
+    if (!S) return;
+    if (S->s) (void)hipStreamSynchronize(S->s);
+    else (void)hipDeviceSynchronize();
+    std::vector<void *> all = S->allocs;
+    for (void *p : all) dfree(S, p);
+    if (S->h_status) (void)hipHostFree(S->h_status);
+    for (int i = 0; i < 9; ++i)
+        if (S->ev[i]) (void)hipEventDestroy(S->ev[i]);
+    delete S;
+}
+
+int hk_step(hk_sim *S, int nsteps) {
+    if (!S || nsteps < 0) return HK_EINVAL;
+    if (S->poisoned) return fail(S, HK_ESTATE, "context poisoned: %s", S->err.c_str());
+    if (!S->have_gauss0) {
+        int rc = gauss_snapshot(S);
+        if (rc) return rc;
+    }
+    for (int n = 0; n < nsteps; ++n) {
+        int rc = one_step(S);
+        if (rc) return rc;
+    }
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    return HK_OK;
+}
+
+int hk_set_switch_mode(hk_sim *S, int mode) {
+    if (!S || mode < HK_SW_ALL_PIC || mode > HK_SW_FIXED) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    if (mode != HK_SW_ALL_PIC) return fail(S, HK_ENOTSUP, "hybrid modes not built");
+    S->run.switch_mode = mode;
+    return HK_OK;
+}
+
+int hk_switch_map(hk_sim *S, uint8_t *out, size_t n) {
+    if (!S || !out || n != (size_t)S->g.nn) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    HIPCHK(S, hipMemcpyAsync(out, S->sw, n, hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    return HK_OK;
+}
+
+int hk_set_switch_map(hk_sim *S, const uint8_t *in, size_t n) {
+    if (!S || !in || n != (size_t)S->g.nn) return HK_EINVAL;
+    return fail(S, HK_ENOTSUP, "hybrid modes not built");
+}
+
+int hk_get_field(hk_sim *S, int comp, void *host_out, size_t bytes) {
+    if (!S || !host_out || comp < 0 || comp >= HK_NCOMP || bytes != sizeof(real) * (size_t)S->g.nn)
+        return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    HIPCHK(S, hipMemcpyAsync(host_out, S->f[comp], bytes, hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    return HK_OK;
+}
+
+int hk_set_field(hk_sim *S, int comp, const void *host_in, size_t bytes) {
+    if (!S || !host_in || comp < 0 || comp >= HK_NCOMP || bytes != sizeof(real) * (size_t)S->g.nn)
+        return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    HIPCHK(S, hipMemcpyAsync(S->f[comp], host_in, bytes, hipMemcpyHostToDevice, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    S->have_gauss0 = 0;
+    return HK_OK;
+}
+
+int hk_get_rho(hk_sim *S, double *host_out, size_t n) {
+    if (!S || !host_out || n != (size_t)S->g.nn) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    rho_total(S, S->tmp_a);
+    HIPCHK(S, hipMemcpyAsync(host_out, S->tmp_a, sizeof(double) * n, hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    return HK_OK;
+}
+
+int hk_get_divE(hk_sim *S, double *host_out, size_t n) {
+    if (!S || !host_out || n != (size_t)S->g.nn) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    launch_divE(S->g, S->f, S->tmp_a, S->s);
+    HIPCHK(S, hipMemcpyAsync(host_out, S->tmp_a, sizeof(double) * n, hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    return HK_OK;
+}
+
+int hk_particle_count(hk_sim *S, int isp, size_t *n) {
+    if (!S || !n || isp < 0 || isp >= S->nsp) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    DevSpecies &D = S->sp[isp];
+    *n = 0;
+    if (D.capacity == 0) return HK_OK;
+    const int nt = S->g.ntiles;
+    std::vector<int> cnt(nt);
+    HIPCHK(S, hipMemcpyAsync(cnt.data(), D.cnt[D.cur], sizeof(int) * nt, hipMemcpyDeviceToHost, S->s));
+    std::vector<int> cells((size_t)D.capacity);
+    HIPCHK(S, hipMemcpyAsync(cells.data(), D.buf[D.cur].cell, sizeof(int) * D.capacity,
+                             hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    size_t tot = 0;
+    for (int t = 0; t < nt; ++t) {
+        int m = std::min(cnt[t], D.h_cap[t]);
+        for (int p = 0; p < m; ++p) tot += cells[D.h_off[t] + p] >= 0;
+    }
+    *n = tot;
+    return HK_OK;
+}
+
+int hk_get_particles(hk_sim *S, int isp, const hk_particles *out) {
+    if (!S || !out || isp < 0 || isp >= S->nsp) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    size_t n = 0;
+    int rc = hk_particle_count(S, isp, &n);
+    if (rc) return rc;
+    if (out->n != n) return fail(S, HK_EINVAL, "hk_get_particles: n = %zu, have %zu", out->n, n);
+    DevSpecies &D = S->sp[isp];
+    if (n == 0) return HK_OK;
+    const long long C = D.capacity;
+    const int nt = S->g.ntiles;
+    std::vector<int> cnt(nt), cell(C), zc(D.has_z ? C : 0);
+    std::vector<real> r[7];
+    for (auto &v : r) v.resize(C);
+    std::vector<uint64_t> id(C);
+    std::vector<double> tau(D.has_tau ? C : 0);
+    const PArr &a = D.buf[D.cur];
+    hipStream_t s = S->s;
+    HIPCHK(S, hipMemcpyAsync(cnt.data(), D.cnt[D.cur], sizeof(int) * nt, hipMemcpyDeviceToHost, s));
+    HIPCHK(S, hipMemcpyAsync(cell.data(), a.cell, sizeof(int) * C, hipMemcpyDeviceToHost, s));
+    real *src[7] = {a.rx, a.ry, a.rz, a.ux, a.uy, a.uz, a.w};
+    for (int k = 0; k < 7; ++k)
+        HIPCHK(S, hipMemcpyAsync(r[k].data(), src[k], sizeof(real) * C, hipMemcpyDeviceToHost, s));
+    HIPCHK(S, hipMemcpyAsync(id.data(), a.id, sizeof(uint64_t) * C, hipMemcpyDeviceToHost, s));
+    if (D.has_z) HIPCHK(S, hipMemcpyAsync(zc.data(), a.zc, sizeof(int) * C, hipMemcpyDeviceToHost, s));
+    if (D.has_tau) HIPCHK(S, hipMemcpyAsync(tau.data(), a.tau, sizeof(double) * C, hipMemcpyDeviceToHost, s));
+    HIPCHK(S, hipStreamSynchronize(s));
+    const GridP &g = S->g;
+    size_t q = 0;
+    for (int t = 0; t < nt; ++t) {
+        int m = std::min(cnt[t], D.h_cap[t]);
+        for (int p = 0; p < m; ++p) {
+            long long i = D.h_off[t] + p;
+            int c = cell[i];
+            if (c < 0) continue;
+            int ci = c % g.nx, cj = (c / g.nx) % g.ny, ck = c / (g.nx * g.ny);
+            if (out->x) {
+                out->x[3 * q] = (ci + (double)r[0][i]) * g.ddx;
+                out->x[3 * q + 1] = (cj + (double)r[1][i]) * g.ddy;
+                out->x[3 * q + 2] = (ck + (double)r[2][i]) * g.ddz;
+            }
+            if (out->u) {
+                out->u[3 * q] = r[3][i]; out->u[3 * q + 1] = r[4][i]; out->u[3 * q + 2] = r[5][i];
+            }
+            if (out->w) out->w[q] = r[6][i];
+            if (out->id) out->id[q] = id[i];
+            if (out->z) out->z[q] = D.has_z ? zc[i] : (int32_t)std::llround(D.d.charge);
+            if (out->tau) out->tau[q] = D.has_tau ? tau[i] : 0.0;
+            ++q;
+        }
+    }
+    return HK_OK;
+}
+
+int hk_set_particles(hk_sim *S, int isp, const hk_particles *in) {
+    if (!S || !in || isp < 0 || isp >= S->nsp || (in->n > 0 && (!in->x || !in->u || !in->w)))
+        return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    DevSpecies &D = S->sp[isp];
+    const GridP &g = S->g;
+    const size_t n = in->n;
+    std::vector<int> cell(n), zc(n);
+    std::vector<real> r[7];
+    for (auto &v : r) v.resize(n);
+    std::vector<uint64_t> id(n);
+    std::vector<double> tau(n, 0.0);
+    const double dxs[3] = {g.ddx, g.ddy, g.ddz};
+    const int dims[3] = {g.nx, g.ny, g.nz};
+    for (size_t q = 0; q < n; ++q) {
+        int c[3];
+        for (int d = 0; d < 3; ++d) {
+            double X = in->x[3 * q + d] / dxs[d];
+            c[d] = (int)std::floor(X);
+            if (c[d] < 0 || c[d] >= dims[d]) return fail(S, HK_EINVAL, "particle %zu outside the box", q);
+            r[d][q] = (real)(X - c[d]);
+            if (r[d][q] >= (real)1) r[d][q] = std::nextafter((real)1, (real)0);
+        }
+        cell[q] = c[0] + g.nx * (c[1] + g.ny * c[2]);
+        for (int d = 0; d < 3; ++d) r[3 + d][q] = (real)in->u[3 * q + d];
+        r[6][q] = (real)in->w[q];
+        id[q] = in->id ? in->id[q] : q;
+        zc[q] = in->z ? in->z[q] : (int)std::llround(D.d.charge);
+        if (in->tau) tau[q] = in->tau[q];
+    }
+    int rc = ensure_inbox(S, isp, (long long)n + 1024);
+    if (rc) return rc;
+    const PArr &a = D.inbox;
+    hipStream_t s = S->s;
+    if (n) {
+        HIPCHK(S, hipMemcpyAsync(a.cell, cell.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+        real *dst[7] = {a.rx, a.ry, a.rz, a.ux, a.uy, a.uz, a.w};
+        for (int k = 0; k < 7; ++k)
+            HIPCHK(S, hipMemcpyAsync(dst[k], r[k].data(), sizeof(real) * n, hipMemcpyHostToDevice, s));
+        HIPCHK(S, hipMemcpyAsync(a.id, id.data(), sizeof(uint64_t) * n, hipMemcpyHostToDevice, s));
+        if (D.has_z) HIPCHK(S, hipMemcpyAsync(a.zc, zc.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+        if (D.has_tau) HIPCHK(S, hipMemcpyAsync(a.tau, tau.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+    }
+    int n32 = (int)n;
+    HIPCHK(S, hipMemcpyAsync(S->status + 1 + 2 * isp, &n32, sizeof(int), hipMemcpyHostToDevice, s));
+    int *ln = S->status + 1 + 2 * isp;
+    PArr lists[1] = {D.inbox};
+    rc = rebuild(S, isp, false, lists, &ln, 1);
+    if (rc) return rc;
+    HIPCHK(S, hipMemsetAsync(S->status + 1 + 2 * isp, 0, sizeof(int), s));
+    HIPCHK(S, hipStreamSynchronize(s));
+    rc = ensure_inbox(S, isp, inbox_need(S, isp));
+    S->have_gauss0 = 0;
+    return rc;
+}
+
+int hk_get_fluid(hk_sim *S, int isp, double *n, double *u, size_t nodes) {
+    if (!S || !n || !u || isp < 0 || isp >= S->nsp || nodes != (size_t)S->g.nn) return HK_EINVAL;
+    return fail(S, HK_ENOTSUP, "no fluid in this context");
+}
+
+int hk_set_fluid(hk_sim *S, int isp, const double *n, const double *u, size_t nodes) {
+    if (!S || !n || !u || isp < 0 || isp >= S->nsp || nodes != (size_t)S->g.nn) return HK_EINVAL;
+    return fail(S, HK_ENOTSUP, "no fluid in this context");
+}
+
+int hk_enable_timing(hk_sim *S, int on) {
+    if (!S) return HK_EINVAL;
+    S->timing = on != 0;
+    for (double &t : S->timers) t = 0;
+    return HK_OK;
+}
+
+int hk_timers(hk_sim *S, double *ms, int n) {
+    if (!S || !ms || n < 0) return HK_EINVAL;
+    for (int i = 0; i < n && i < 8; ++i) ms[i] = S->timers[i];
+    return HK_OK;
+}
+
+int hk_diagnostics(hk_sim *S, hk_diag *d) {
+    if (!S || !d) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    hipStream_t s = S->s;
+    const GridP &g = S->g;
+    if (!S->have_gauss0) gauss_snapshot(S);
+    std::memset(d, 0, sizeof(*d));
+    launch_zero(S->dsum, sizeof(double) * 64, s);
+    launch_field_energy(g, S->f, S->dsum, s);
+    for (int isp = 0; isp < S->nsp; ++isp) {
+        DevSpecies &D = S->sp[isp];
+        SpecP P = specp(D);
+        if (D.capacity) launch_particle_sums(g, P, D.buf[D.cur], D.cnt[D.cur], S->dsum + 2 + 3 * isp, s);
+        if (D.fn) launch_fluid_sums(g, P, D.fn, D.fu[0], D.fu[1], D.fu[2], S->dsum + 20 + 3 * isp, s);
+    }
+    // Gauss: (divE - rho) now minus (divE - rho) at the snapshot
+    launch_divE(g, S->f, S->tmp_a, s);
+    rho_total(S, S->tmp_b);
+    launch_gauss(g, S->tmp_a, S->tmp_b, S->gauss0, S->las.enabled ? S->las.i_antenna : -1,
+                 S->dsum + 40, s);
+    launch_count_kinetic(g, S->sw, S->dsum + 44, s);
+    double h[64], led[8];
+    HIPCHK(S, hipMemcpyAsync(h, S->dsum, sizeof(double) * 64, hipMemcpyDeviceToHost, s));
+    HIPCHK(S, hipMemcpyAsync(led, S->ledger, sizeof(double) * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(S, hipStreamSynchronize(s));
+    d->t = S->t;
+    d->step = S->step;
+    d->u_e = h[0];
+    d->u_b = h[1];
+    for (int isp = 0; isp < S->nsp; ++isp) {
+        d->kin[isp] = h[2 + 3 * isp];
+        d->count[isp] = h[3 + 3 * isp];
+        d->charge_total += h[4 + 3 * isp];
+        d->fluid_kin[isp] = h[20 + 3 * isp];
+        d->fluid_mass[isp] = h[21 + 3 * isp];
+        d->charge_total += h[22 + 3 * isp];
+    }
+    d->gauss_l2 = h[41] > 0 ? std::sqrt(h[40] / h[41]) : 0.0;
+    uint64_t mb;
+    std::memcpy(&mb, &h[42], 8);
+    double mx;
+    std::memcpy(&mx, &mb, 8);
+    d->gauss_max = mx;
+    d->kinetic_fraction = h[45] > 0 ? h[44] / h[45] : 0.0;
+    d->conv_loss = led[0];
+    d->ion_energy = led[1];
+    d->photon_energy = led[2];
+    d->fallback_fraction = S->fallback_fraction;
+    return HK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,167 @@
+// Internal declarations of the MI355X hybrid-step library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hk.h"
+
+#ifdef HK_DOUBLE
+typedef double real;
+#define HK_REAL_BYTES 8
+#else
+typedef float real;
+#define HK_REAL_BYTES 4
+#endif
+
+// Particles are binned in cubic tiles of TILE^3 cells; one workgroup owns a tile.
+#define TILE 8
+#define TLOG 3
+
+// Grid parameters passed by value to every kernel.
+struct GridP {
+    int nx, ny, nz, sx;         // sx = nx + 1: x extent of every grid array
+    int bcx;                    // HK_BC_PERIODIC / HK_BC_OPEN
+    int ntx, nty, ntz, ntiles;  // tiles per axis
+    long long nn;               // nodes in the canonical layout: sx * ny * nz
+    real dx, dy, dz, dt;
+    double ddx, ddy, ddz, ddt;  // the same in FP64 (set-up, antenna, diagnostics)
+};
+
+__host__ __device__ inline long long gidx(const GridP &g, int i, int j, int k) {
+    return (long long)i + (long long)g.sx * ((long long)j + (long long)g.ny * (long long)k);
+}
+__host__ __device__ inline int wrapi(int i, int n) {
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// ---------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): counter (id lo, id hi, step, tag<<8|draw),
+// key (seed lo, seed hi).  Ten rounds; the key advances by the Weyl constants
+// between rounds.
+__host__ __device__ inline void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                         uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t a = (uint64_t)0xD2511F53u * c0;
+        uint64_t b = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
+        uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)b;
+        c3 = (uint32_t)a;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+__host__ __device__ inline void draw4(uint64_t seed, uint64_t id, uint32_t step, uint32_t tag,
+                                      uint32_t draw, uint32_t out[4]) {
+    philox10((uint32_t)id, (uint32_t)(id >> 32), step, (tag << 8) | draw, (uint32_t)seed,
+             (uint32_t)(seed >> 32), out);
+}
+
+// Uniform in (0,1) with 24 significant bits: exact in FP32 and FP64 alike.
+__host__ __device__ inline real u01(uint32_t x) {
+    return ((real)(x >> 9) + (real)0.5) * (real)(1.0 / 8388608.0);
+}
+__host__ __device__ inline double u01d(uint32_t x) {
+    return ((double)(x >> 9) + 0.5) * (1.0 / 8388608.0);
+}
+
+// Philox tags (one stream per purpose).
+enum { TAG_POS = 1, TAG_MOM = 2, TAG_ION = 3, TAG_CONV = 12, TAG_EMIT = 16, TAG_EMIT_TAU = 17,
+       TAG_PAIR = 18, TAG_PAIR_TAU = 19, TAG_DROP = 24 };
+
+// ---------------------------------------------------------------------------------------
+// Particle storage: structure of arrays, binned per tile.  Tile t owns slots
+// [off[t], off[t] + cap[t]) in both buffers; cnt[t] particles are valid
+// (a slot whose cell is < 0 is a hole).  cell is the global linear cell index
+// i + nx (j + ny k); r* are offsets in [0,1) inside that cell.
+struct PArr {
+    int *cell;
+    real *rx, *ry, *rz, *ux, *uy, *uz, *w;
+    uint64_t *id;
+    int *zc;      // ion charge state (ions only)
+    double *tau;  // optical depth (QED species only)
+};
+
+// Per-species state visible to kernels.
+struct SpecP {
+    int kind, mobile, fluid, ionizable, z_max, qed, has_z, has_tau;
+    real q, m, qm;
+    const long long *off;
+    const int *cap;
+};
+
+struct Ctx;  // host context (hk_api.cpp)
+
+// Error flags raised by kernels (bitmask in a device int).
+enum { ERR_NONFINITE = 1, ERR_CFL = 2, ERR_INBOX = 4, ERR_TILE = 8 };
+
+// Device-side rate tables for ionization (per species, per level).
+struct IonLevel {
+    double ip_au, zres, c2, k3, expo, fc, wfc, K2;  // constants of the ADK/MPI blend
+};
+struct IonP {
+    double field_au;   // atomic field units per normalized field unit
+    double rate_norm;  // normalized rate per atomic rate (1 / (omega0 t_a))
+    double dt_au;      // unused in kernels: kept for the host
+    double omega_au;
+    int z_max;
+    int target;
+    IonLevel lev[HK_MAX_LEVELS];
+};
+
+// ----------------------------------------------------------------- launchers ------------
+// fields (k_fields.hip)
+void launch_zero(void *p, size_t bytes, hipStream_t s);
+void launch_yee_b_half(const GridP &g, real *const f[9], hipStream_t s);
+void launch_yee_e_full(const GridP &g, real *const f[9], real *mur_old, hipStream_t s);
+void launch_antenna(const GridP &g, const hk_laser_desc &L, double t, real *jy, real *jz,
+                    hipStream_t s);
+void launch_divE(const GridP &g, real *const f[9], double *out, hipStream_t s);
+
+// particles (k_particles.hip): declared in hk_api.cpp where they are used
+
+// diagnostics (k_diag.hip)
+void launch_field_energy(const GridP &g, real *const f[9], double *out2, hipStream_t s);
+void launch_particle_sums(const GridP &g, const SpecP &sp, PArr a, const int *cnt,
+                          double *out3, hipStream_t s);
+void launch_gauss(const GridP &g, const double *dive, const double *rho, const double *g0,
+                  int skip_plane, double *out2, hipStream_t s);
+void launch_fluid_sums(const GridP &g, const SpecP &sp, const real *n, const real *ux,
+                       const real *uy, const real *uz, double *out3, hipStream_t s);
+void launch_count_kinetic(const GridP &g, const uint8_t *sw, double *out, hipStream_t s);
+void launch_sub(long long n, double *a, const double *b, hipStream_t s);
+
+// fluid (k_fluid.hip)
+void launch_fluid(const GridP &g, const SpecP &sp, real *n, real *ux, real *uy, real *uz,
+                  real *const f[9], real *scratch, real n_floor, hipStream_t s);
+void launch_fluid_rho(const GridP &g, const SpecP &sp, const real *n, double *rho,
+                      hipStream_t s);
+
+// switch and conversion (k_switch.hip)
+struct SwitchP {
+    real thr_a, thr_grad, thr_su, thr_ion, thr_chi, n_floor;
+    int dilation, hysteresis, enable_qed, enable_ion;
+    double a_s;   // QED normalized Schwinger field
+};
+void launch_moments(const GridP &g, const SpecP &sp, PArr a, const int *cnt, float *mom,
+                    hipStream_t s);
+void launch_fluid_moments(const GridP &g, const SpecP &sp, const real *n, const real *ux,
+                          const real *uy, const real *uz, float *mom, hipStream_t s);
+void launch_indicators(const GridP &g, const SwitchP &P, const float *mom, real *const f[9],
+                       const IonP *ion, int n_ion_species, uint8_t *hot, uint8_t *notcold,
+                       hipStream_t s);
+void launch_dilate(const GridP &g, const SwitchP &P, const uint8_t *hot, const uint8_t *notcold,
+                   uint8_t *sw, uint8_t *calm, hipStream_t s);
+void launch_absorb(const GridP &g, const SpecP &sp, PArr a, const int *cnt, const uint8_t *sw,
+                   real *const f[9], double *macc, hipStream_t s);
+void launch_absorb_finish(const GridP &g, const SpecP &sp, const double *macc, real *n,
+                          real *ux, real *uy, real *uz, double *ledger, hipStream_t s);
+void launch_spawn(const GridP &g, const SpecP &sp, const uint8_t *sw, real *n, real *ux,
+                  real *uy, real *uz, real *const f[9], real wmin, int ppc, uint64_t seed,
+                  int step, PArr inbox, int *inbox_n, int inbox_cap, int *err, hipStream_t s);

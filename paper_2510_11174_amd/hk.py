@@ -1,0 +1,333 @@
+"""ctypes binding of the hybrid-step C ABI (include/hk.h).
+
+Argument marshalling only: every step of the method runs in the gfx950
+kernels of libhk_f32.so / libhk_f64.so.  PyTorch supplies the HIP stream and,
+through allocator callbacks, the device memory (its caching allocator).
+Loading fails loudly when the library has not been built; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from .build import lib_path
+
+MAX_SPECIES = 6
+MAX_LEVELS = 8
+KIND = {"electron": 0, "ion": 1, "positron": 2, "photon": 3}
+PROFILE = {"none": 0, "uniform": 1, "ramp": 2, "foil": 3}
+SWITCH = {"all_pic": 0, "threshold": 1, "cnn": 2, "all_fluid": 3, "fixed": 4}
+BC = {"periodic": 0, "open": 1}
+COMP = {"ex": 0, "ey": 1, "ez": 2, "bx": 3, "by": 4, "bz": 5, "jx": 6, "jy": 7, "jz": 8}
+STATUS = {0: "HK_OK", -1: "HK_EINVAL", -2: "HK_ENOMEM", -3: "HK_EDEVICE", -4: "HK_ENUMERIC",
+          -5: "HK_EOVERFLOW", -6: "HK_ESTATE", -7: "HK_EIO", -8: "HK_ENOTSUP"}
+
+
+class HKError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("bc_x", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("dt", C.c_double)]
+
+
+class SpeciesDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("ppc", C.c_int32), ("profile", C.c_int32),
+                ("mobile", C.c_int32), ("fluid", C.c_int32), ("ionizable", C.c_int32),
+                ("z_max", C.c_int32), ("target", C.c_int32), ("qed", C.c_int32),
+                ("pad", C.c_int32), ("charge", C.c_double), ("mass", C.c_double),
+                ("n0", C.c_double), ("x0", C.c_double), ("length", C.c_double),
+                ("u_th", C.c_double), ("ip_ev", C.c_double * MAX_LEVELS)]
+
+
+class LaserDesc(C.Structure):
+    _fields_ = [("enabled", C.c_int32), ("polarization", C.c_int32), ("i_antenna", C.c_int32),
+                ("pad", C.c_int32), ("a0", C.c_double), ("waist", C.c_double),
+                ("duration", C.c_double), ("t_center", C.c_double), ("lambda_um", C.c_double)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class RunDesc(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("switch_mode", C.c_int32), ("switch_every", C.c_int32),
+                ("dilation", C.c_int32), ("hysteresis", C.c_int32),
+                ("enable_ionization", C.c_int32), ("enable_qed", C.c_int32),
+                ("thr_a", C.c_double), ("thr_grad", C.c_double), ("thr_sigma_u", C.c_double),
+                ("thr_ion", C.c_double), ("thr_chi", C.c_double), ("n_floor", C.c_double),
+                ("spawn_frac", C.c_double), ("stream", C.c_void_p), ("alloc", ALLOC_FN),
+                ("free", FREE_FN), ("alloc_ctx", C.c_void_p)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("t", C.c_double), ("step", C.c_int64), ("u_e", C.c_double), ("u_b", C.c_double),
+                ("kin", C.c_double * MAX_SPECIES), ("fluid_kin", C.c_double * MAX_SPECIES),
+                ("count", C.c_double * MAX_SPECIES), ("fluid_mass", C.c_double * MAX_SPECIES),
+                ("charge_total", C.c_double), ("gauss_max", C.c_double), ("gauss_l2", C.c_double),
+                ("conv_loss", C.c_double), ("ion_energy", C.c_double),
+                ("photon_energy", C.c_double), ("kinetic_fraction", C.c_double),
+                ("fallback_fraction", C.c_double)]
+
+
+class Particles(C.Structure):
+    _fields_ = [("n", C.c_size_t), ("x", C.c_void_p), ("u", C.c_void_p), ("w", C.c_void_p),
+                ("id", C.c_void_p), ("z", C.c_void_p), ("tau", C.c_void_p)]
+
+
+ABI_SYMBOLS = ["hk_create", "hk_destroy", "hk_step", "hk_switch_map", "hk_set_switch_map",
+               "hk_set_switch_mode", "hk_diagnostics", "hk_get_field", "hk_set_field",
+               "hk_get_rho", "hk_get_divE", "hk_particle_count", "hk_get_particles",
+               "hk_set_particles", "hk_get_fluid", "hk_set_fluid", "hk_enable_timing",
+               "hk_timers", "hk_real_size", "hk_strerror", "hk_last_error"]
+
+_libs: dict = {}
+
+
+def load(prec: str = "f32"):
+    """Load (once) the C-ABI library of the given precision ('f32' or 'f64')."""
+    if prec in _libs:
+        return _libs[prec]
+    path = lib_path(prec)
+    if not os.path.exists(path):
+        raise RuntimeError("HIP library %s is not built (run __graft_entry__.build())" % path)
+    L = C.CDLL(path)
+    P = C.POINTER
+    vp = C.c_void_p
+    L.hk_create.argtypes = [P(GridDesc), P(SpeciesDesc), C.c_int, P(LaserDesc), P(RunDesc), P(vp)]
+    L.hk_destroy.argtypes = [vp]
+    L.hk_destroy.restype = None
+    L.hk_step.argtypes = [vp, C.c_int]
+    L.hk_switch_map.argtypes = [vp, vp, C.c_size_t]
+    L.hk_set_switch_map.argtypes = [vp, vp, C.c_size_t]
+    L.hk_set_switch_mode.argtypes = [vp, C.c_int]
+    L.hk_diagnostics.argtypes = [vp, P(Diag)]
+    L.hk_get_field.argtypes = [vp, C.c_int, vp, C.c_size_t]
+    L.hk_set_field.argtypes = [vp, C.c_int, vp, C.c_size_t]
+    L.hk_get_rho.argtypes = [vp, vp, C.c_size_t]
+    L.hk_get_divE.argtypes = [vp, vp, C.c_size_t]
+    L.hk_particle_count.argtypes = [vp, C.c_int, P(C.c_size_t)]
+    L.hk_get_particles.argtypes = [vp, C.c_int, P(Particles)]
+    L.hk_set_particles.argtypes = [vp, C.c_int, P(Particles)]
+    L.hk_get_fluid.argtypes = [vp, C.c_int, vp, vp, C.c_size_t]
+    L.hk_set_fluid.argtypes = [vp, C.c_int, vp, vp, C.c_size_t]
+    L.hk_enable_timing.argtypes = [vp, C.c_int]
+    L.hk_timers.argtypes = [vp, vp, C.c_int]
+    L.hk_real_size.restype = C.c_int
+    L.hk_strerror.restype = C.c_char_p
+    L.hk_strerror.argtypes = [C.c_int]
+    L.hk_last_error.restype = C.c_char_p
+    L.hk_last_error.argtypes = [vp]
+    _libs[prec] = L
+    return L
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def descriptors(cfg: dict):
+    """Marshal a config dictionary (see configs.py) into the ABI descriptors."""
+    g = cfg["grid"]
+    grid = GridDesc(nx=g["nx"], ny=g["ny"], nz=g["nz"], bc_x=BC[g.get("bc_x", "open")],
+                    dx=g["dx"], dy=g["dy"], dz=g["dz"], dt=g["dt"])
+    sps = (SpeciesDesc * MAX_SPECIES)()
+    for i, s in enumerate(cfg["species"]):
+        sp = sps[i]
+        sp.kind = KIND[s["kind"]]
+        sp.ppc = s.get("ppc", 0)
+        sp.profile = PROFILE[s.get("profile", "none")]
+        sp.mobile = int(s.get("mobile", True))
+        sp.fluid = int(s.get("fluid", False))
+        sp.ionizable = int(s.get("ionizable", False))
+        sp.z_max = s.get("z_max", 0)
+        sp.target = s.get("target", 0)
+        sp.qed = int(s.get("qed", False))
+        sp.charge = s["charge"]
+        sp.mass = s["mass"]
+        sp.n0 = s.get("n0", 0.0)
+        sp.x0 = s.get("x0", 0.0)
+        sp.length = s.get("length", 1.0)
+        sp.u_th = s.get("u_th", 0.0)
+        for k, v in enumerate(s.get("ip_ev", [])):
+            sp.ip_ev[k] = v
+    las = cfg.get("laser", {})
+    laser = LaserDesc(enabled=int(las.get("enabled", False)),
+                      polarization=1 if las.get("polarization", "linear") == "circular" else 0,
+                      i_antenna=las.get("i_antenna", 2), a0=las.get("a0", 0.0),
+                      waist=las.get("waist", 1.0), duration=las.get("duration", 1.0),
+                      t_center=las.get("t_center", 0.0), lambda_um=las.get("lambda_um", 0.8))
+    r = cfg["run"]
+    run = RunDesc(seed=r["seed"], switch_mode=SWITCH[r.get("switch_mode", "all_pic")],
+                  switch_every=r.get("switch_every", 1), dilation=r.get("dilation", 1),
+                  hysteresis=r.get("hysteresis", 2),
+                  enable_ionization=int(r.get("enable_ionization", False)),
+                  enable_qed=int(r.get("enable_qed", False)), thr_a=r.get("thr_a", 0.5),
+                  thr_grad=r.get("thr_grad", 0.2), thr_sigma_u=r.get("thr_sigma_u", 0.05),
+                  thr_ion=r.get("thr_ion", 1e-6), thr_chi=r.get("thr_chi", 1e-3),
+                  n_floor=r.get("n_floor", 1e-10), spawn_frac=r.get("spawn_frac", 0.5))
+    return grid, sps, len(cfg["species"]), laser, run
+
+
+class _TorchMemory:
+    """Device memory and stream from PyTorch's caching allocator."""
+
+    def __init__(self):
+        import torch
+        self.torch = torch
+        self.device = torch.cuda.current_device()
+        self.stream = torch.cuda.current_stream()
+
+        def _alloc(nbytes, ctx):
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream))
+
+        def _free(ptr, ctx):
+            try:
+                torch.cuda.caching_allocator_delete(int(ptr))
+            except Exception:      # interpreter shutdown: torch already torn down
+                pass
+
+        self.alloc = ALLOC_FN(_alloc)
+        self.free = FREE_FN(_free)
+
+
+class Sim:
+    """One simulation context on the current GPU."""
+
+    def __init__(self, cfg: dict, precision: str = "f32", torch_memory: bool = True):
+        self.lib = load(precision)
+        self.cfg = cfg
+        self.precision = precision
+        self.real = np.float32 if self.lib.hk_real_size() == 4 else np.float64
+        grid, sps, ns, laser, run = descriptors(cfg)
+        self._mem = None
+        if torch_memory:
+            self._mem = _TorchMemory()
+            run.stream = self._mem.stream.cuda_stream
+            run.alloc = self._mem.alloc
+            run.free = self._mem.free
+        self._keep = (grid, sps, laser, run)
+        h = C.c_void_p()
+        rc = self.lib.hk_create(C.byref(grid), sps, ns, C.byref(laser), C.byref(run), C.byref(h))
+        if rc != 0:
+            raise HKError(rc, self.lib.hk_strerror(rc).decode())
+        self.h = h
+        self.nx, self.ny, self.nz = grid.nx, grid.ny, grid.nz
+        self.nspecies = ns
+
+    # -- helpers
+    def _check(self, rc):
+        if rc != 0:
+            raise HKError(rc, self.lib.hk_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hk_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx + 1)
+
+    @property
+    def nodes(self):
+        return (self.nx + 1) * self.ny * self.nz
+
+    # -- ABI calls
+    def step(self, n: int = 1):
+        self._check(self.lib.hk_step(self.h, n))
+
+    def get_field(self, comp) -> np.ndarray:
+        c = COMP[comp] if isinstance(comp, str) else comp
+        out = np.empty(self.shape, self.real)
+        self._check(self.lib.hk_get_field(self.h, c, _ptr(out), out.nbytes))
+        return out
+
+    def set_field(self, comp, arr):
+        c = COMP[comp] if isinstance(comp, str) else comp
+        a = np.ascontiguousarray(arr, self.real).reshape(self.shape)
+        self._check(self.lib.hk_set_field(self.h, c, _ptr(a), a.nbytes))
+
+    def count(self, sp: int) -> int:
+        n = C.c_size_t()
+        self._check(self.lib.hk_particle_count(self.h, sp, C.byref(n)))
+        return n.value
+
+    def get_particles(self, sp: int) -> dict:
+        n = self.count(sp)
+        x = np.empty((n, 3)); u = np.empty((n, 3)); w = np.empty(n)
+        idv = np.empty(n, np.uint64); z = np.empty(n, np.int32); tau = np.empty(n)
+        p = Particles(n=n, x=_ptr(x), u=_ptr(u), w=_ptr(w), id=_ptr(idv), z=_ptr(z), tau=_ptr(tau))
+        self._check(self.lib.hk_get_particles(self.h, sp, C.byref(p)))
+        return {"x": x, "u": u, "w": w, "id": idv, "z": z, "tau": tau}
+
+    def set_particles(self, sp: int, x, u, w, ids=None, z=None, tau=None):
+        x = np.ascontiguousarray(x, np.float64); u = np.ascontiguousarray(u, np.float64)
+        w = np.ascontiguousarray(w, np.float64)
+        n = len(w)
+        ids = np.ascontiguousarray(ids if ids is not None else np.arange(n), np.uint64)
+        z = None if z is None else np.ascontiguousarray(z, np.int32)
+        tau = None if tau is None else np.ascontiguousarray(tau, np.float64)
+        p = Particles(n=n, x=_ptr(x), u=_ptr(u), w=_ptr(w), id=_ptr(ids), z=_ptr(z), tau=_ptr(tau))
+        self._check(self.lib.hk_set_particles(self.h, sp, C.byref(p)))
+
+    def get_fluid(self, sp: int):
+        n = np.empty(self.shape); u = np.empty(self.shape + (3,))
+        self._check(self.lib.hk_get_fluid(self.h, sp, _ptr(n), _ptr(u), self.nodes))
+        return n, u
+
+    def set_fluid(self, sp: int, n, u):
+        n = np.ascontiguousarray(n, np.float64).reshape(self.shape)
+        u = np.ascontiguousarray(u, np.float64).reshape(self.shape + (3,))
+        self._check(self.lib.hk_set_fluid(self.h, sp, _ptr(n), _ptr(u), self.nodes))
+
+    def get_switch(self) -> np.ndarray:
+        out = np.empty(self.shape, np.uint8)
+        self._check(self.lib.hk_switch_map(self.h, _ptr(out), out.size))
+        return out
+
+    def set_switch(self, m):
+        m = np.ascontiguousarray(m, np.uint8).reshape(self.shape)
+        self._check(self.lib.hk_set_switch_map(self.h, _ptr(m), m.size))
+
+    def set_switch_mode(self, mode: str):
+        self._check(self.lib.hk_set_switch_mode(self.h, SWITCH[mode]))
+
+    def diagnostics(self) -> dict:
+        d = Diag()
+        self._check(self.lib.hk_diagnostics(self.h, C.byref(d)))
+        out = {}
+        for name, _ in Diag._fields_:
+            v = getattr(d, name)
+            out[name] = list(v)[: self.nspecies] if hasattr(v, "__len__") else v
+        return out
+
+    def rho(self) -> np.ndarray:
+        out = np.empty(self.shape)
+        self._check(self.lib.hk_get_rho(self.h, _ptr(out), out.size))
+        return out
+
+    def divE(self) -> np.ndarray:
+        out = np.empty(self.shape)
+        self._check(self.lib.hk_get_divE(self.h, _ptr(out), out.size))
+        return out
+
+    def enable_timing(self, on=True):
+        self._check(self.lib.hk_enable_timing(self.h, int(on)))
+
+    def timers(self) -> np.ndarray:
+        out = np.zeros(8)
+        self._check(self.lib.hk_timers(self.h, _ptr(out), 8))
+        return out
