@@ -204,8 +204,9 @@ int hk_get_fluid(hk_sim *sim, int species, double *n, double *u, size_t nodes);
 int hk_set_fluid(hk_sim *sim, int species, const double *n, const double *u, size_t nodes);
 
 /* Accumulated device time per kernel group (ms): 0 switch, 1 particles,
- * 2 fluid, 3 conversion, 4 fields, 5 sort/merge, 6 other.  Timing is
- * collected only when enabled (it adds events around each group). */
+ * 2 fluid, 3 conversion, 4 fields, 5 sort/merge, 6 other; slot 7 counts the
+ * particle re-binnings since creation.  Timing is collected only when enabled
+ * (it adds events around each group). */
 int hk_enable_timing(hk_sim *sim, int on);
 int hk_timers(hk_sim *sim, double *ms, int n);
 

@@ -19,23 +19,47 @@
 void launch_init_species_cols(const GridP &g, const hk_species_desc &d, uint64_t seed, PArr out,
                               const int *xcol, const double *wcol, int ncol, int has_z,
                               int has_tau, hipStream_t s);
-void launch_count_groups(const GridP &g, PArr src, const long long *off, const int *cnt,
-                         const int *cap, int ngroups, int *newcnt, hipStream_t s);
-void launch_scatter_groups(const GridP &g, PArr src, const long long *off, const int *cnt,
-                           const int *cap, int ngroups, PArr dst, const long long *doff,
-                           int *dfill, int has_z, int has_tau, hipStream_t s);
+void launch_count_groups(const GridP &g, PArr src, const long long *off, const int *nf,
+                         const int *nb, const int *cap, int ngroups, long long maxn, int *newcnt,
+                         hipStream_t s);
+void launch_scatter_groups(const GridP &g, PArr src, const long long *off, const int *nf,
+                           const int *nb, const int *cap, int ngroups, long long maxn, PArr dst,
+                           const long long *doff, int *dfill, int has_z, int has_tau,
+                           hipStream_t s);
 void launch_merge_inbox(const GridP &g, const SpecP &sp, PArr inbox, const int *inbox_n,
-                        long long max_n, PArr dst, int *cnt, int *fail_n, PArr fail,
-                        hipStream_t s);
-void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, const int *cnt_in, PArr out,
-                       int *cnt_out, PArr inbox, int *inbox_n, int inbox_cap, real *const f[9],
-                       int *err, hipStream_t s);
-void launch_ionize_static(const GridP &g, const SpecP &sp, PArr a, const int *cnt,
+                        long long max_n, PArr dst, const int *nf, int *nb, int *fail_n, PArr fail,
+                        int *err, hipStream_t s);
+void launch_migrate(const GridP &g, const SpecP &sp, PArr mig, const long long *moff,
+                    const int *mcnt, PArr dst, const int *nf, int *nb, int *fail_n, PArr fail,
+                    int fail_cap, int *err, hipStream_t s);
+void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
+                       int *nf_out, PArr mig, const long long *moff, const int *mcap, int *mcnt,
+                       PArr inbox, int *inbox_n, int inbox_cap, real *const f[9], int *err,
+                       hipStream_t s);
+void launch_ionize_static(const GridP &g, const SpecP &sp, PArr a, Bins b, int *active,
                           real *const f[9], const uint8_t *sw, int hybrid, const IonP *ion,
                           PArr eout, int *eout_n, int eout_cap, uint64_t seed, int step,
                           double *ledger, int *err, hipStream_t s);
-void launch_rho_tiles(const GridP &g, const SpecP &sp, PArr a, const int *cnt, double *rho,
-                      hipStream_t s);
+void launch_count_active(const GridP &g, const SpecP &sp, PArr a, Bins b, int zmax, int *active,
+                         hipStream_t s);
+void launch_rho_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, double *rho, hipStream_t s);
+void launch_moments_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, int ion_only,
+                          int zmax, real *mom, hipStream_t s);
+void launch_fluid_moments_nodes(const GridP &g, real inv_ppc, const real *n, const real *ux,
+                                const real *uy, const real *uz, real *mom, hipStream_t s);
+void launch_indicators_nodes(const GridP &g, const SwitchP &P, const real *mom, real *const f[9],
+                             const IonP *const *ions, int nion, uint8_t *hot, uint8_t *notcold,
+                             hipStream_t s);
+void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, const uint8_t *notcold,
+                         uint8_t *sw, uint8_t *calm, hipStream_t s);
+void launch_absorb_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, const uint8_t *sw,
+                         real *const f[9], double *macc, double *ledger, hipStream_t s);
+void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n, real *ux,
+                                real *uy, real *uz, double *ledger, hipStream_t s);
+void launch_spawn_nodes(const GridP &g, const SpecP &sp, const uint8_t *sw, real *n, real *ux,
+                        real *uy, real *uz, real *const f[9], real wmin, int m, uint64_t seed,
+                        int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
+                        hipStream_t s);
 
 namespace {
 
@@ -53,9 +77,14 @@ struct DevSpecies {
     long long capacity = 0;
     long long *off = nullptr;  // device [ntiles]
     int *cap = nullptr;        // device [ntiles]
-    int *cnt[2] = {nullptr, nullptr};
+    int *nf[2] = {nullptr, nullptr}, *nb[2] = {nullptr, nullptr};  // bin front / back counts
     std::vector<long long> h_off;
     std::vector<int> h_cap;
+    int max_cap = 0;
+    PArr mig{};                // per-tile mover regions
+    long long *moff = nullptr;
+    int *mcap = nullptr, *mcnt = nullptr;
+    int *active = nullptr;     // immobile ionizable ions: ions below z_max per tile
     PArr inbox{}, fail{};
     int inbox_cap = 0;
     long long *g_off0 = nullptr;  // device {0}
@@ -79,12 +108,14 @@ struct hk_sim {
     real *f[9]{};
     real *mur_old = nullptr;
     uint8_t *sw = nullptr, *calm = nullptr, *hot = nullptr, *notcold = nullptr;
-    float *mom = nullptr;        // switch moments
+    real *mom = nullptr;         // switch moments (7 grid arrays)
+    double *macc = nullptr;      // absorbed mass and momentum (4 grid arrays)
     real *fluid_scratch = nullptr;
     double *gauss0 = nullptr, *tmp_a = nullptr, *tmp_b = nullptr;
     double *dsum = nullptr;      // diagnostic accumulators
     double *ledger = nullptr;    // [0] conversion loss, [1] ionization, [2] photons
-    int *status = nullptr;       // [0] error bits, [1 + 2s] inbox count, [2 + 2s] fail count
+    int *status = nullptr;       // [0] error bits, [1 + 2s] inbox count, [2 + 2s] fail count,
+                                 // [13] spawns deferred for lack of inbox room
     int *h_status = nullptr;     // pinned
     int have_gauss0 = 0;
     int64_t step = 0;
@@ -164,6 +195,9 @@ void free_parr(hk_sim *S, PArr &a) {
     a = PArr{};
 }
 
+Bins bins(const DevSpecies &d, int which) { return Bins{d.nf[which], d.nb[which]}; }
+Bins cur_bins(const DevSpecies &d) { return bins(d, d.cur); }
+
 SpecP specp(const DevSpecies &d) {
     SpecP p{};
     p.kind = d.d.kind;
@@ -191,69 +225,102 @@ double profile(const hk_species_desc &d, double x) {
     }
 }
 
-// Re-bin a species from its current bins plus up to two unbinned lists into a
-// fresh layout whose per-tile capacity leaves headroom for growth.
-int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, int nlists) {
+// Re-bin a species from its current bins plus unbinned lists into a fresh
+// layout whose per-tile capacity leaves headroom for density changes.
+// list_max[l] bounds the entries of list l (its capacity).
+int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const long long *list_max,
+            int nlists) {
     DevSpecies &D = S->sp[isp];
+    S->timers[7] += 1;   // re-bin count (reported with the timers)
     const GridP &g = S->g;
     const int nt = g.ntiles;
     int *newcnt = (int *)dalloc(S, sizeof(int) * nt);
     if (!newcnt) return fail(S, HK_ENOMEM, "rebuild: counts");
     PArr cur = D.buf[D.cur];
     if (use_tiles && D.capacity > 0)
-        launch_count_groups(g, cur, D.off, D.cnt[D.cur], D.cap, nt, newcnt, S->s);
+        launch_count_groups(g, cur, D.off, D.nf[D.cur], D.nb[D.cur], D.cap, nt, D.max_cap, newcnt, S->s);
     for (int l = 0; l < nlists; ++l)
-        launch_count_groups(g, lists[l], D.g_off0, list_n[l], D.g_capmax, 1, newcnt, S->s);
+        launch_count_groups(g, lists[l], D.g_off0, list_n[l], nullptr, D.g_capmax, 1, list_max[l],
+                            newcnt, S->s);
     std::vector<int> h(nt);
     HIPCHK(S, hipMemcpyAsync(h.data(), newcnt, sizeof(int) * nt, hipMemcpyDeviceToHost, S->s));
     HIPCHK(S, hipStreamSynchronize(S->s));
-    // capacity: 25% headroom plus one wavefront, at least the reserve hint share
+    // capacity: 50% headroom plus 128 slots, at least the reserve hint share
     long long hint_per_tile = D.reserve_hint > 0 ? (D.reserve_hint + nt - 1) / nt : 0;
-    std::vector<long long> off(nt);
-    std::vector<int> cap(nt);
-    long long total = 0;
+    std::vector<long long> off(nt), moff(nt);
+    std::vector<int> cap(nt), mcap(nt);
+    long long total = 0, mtotal = 0;
+    int maxc = 0;
     for (int t = 0; t < nt; ++t) {
-        long long c = (long long)h[t] + h[t] / 4 + 64;
-        long long hc = hint_per_tile + hint_per_tile / 8 + 64;
-        c = std::max(c, std::min<long long>(hc, INT_MAX / 2));
+        long long c = (long long)h[t] + h[t] / 2 + 128;
+        long long hc = hint_per_tile + hint_per_tile / 4 + 128;
+        c = std::max(c, std::min<long long>(hc, INT_MAX / 4));
         c = (c + 63) & ~63LL;
         off[t] = total;
         cap[t] = (int)c;
         total += c;
+        maxc = std::max(maxc, (int)c);
+        long long m = (c / 4 + 63) & ~63LL;
+        moff[t] = mtotal;
+        mcap[t] = (int)m;
+        mtotal += m;
     }
-    PArr nb[2];
-    if (!alloc_parr(S, nb[0], total, D.has_z, D.has_tau) ||
-        !alloc_parr(S, nb[1], total, D.has_z, D.has_tau))
+    PArr nbuf[2], nmig;
+    if (!alloc_parr(S, nbuf[0], total, D.has_z, D.has_tau) ||
+        !alloc_parr(S, nbuf[1], total, D.has_z, D.has_tau) ||
+        !alloc_parr(S, nmig, D.d.mobile ? mtotal : 1, D.has_z, D.has_tau))
         return fail(S, HK_ENOMEM, "rebuild: %lld particle slots", total);
     long long *doff = (long long *)dalloc(S, sizeof(long long) * nt);
+    long long *dmoff = (long long *)dalloc(S, sizeof(long long) * nt);
     int *dcap = (int *)dalloc(S, sizeof(int) * nt);
+    int *dmcap = (int *)dalloc(S, sizeof(int) * nt);
+    int *dmcnt = (int *)dalloc(S, sizeof(int) * nt);
     int *dfill = (int *)dalloc(S, sizeof(int) * nt);
-    int *c0 = (int *)dalloc(S, sizeof(int) * nt), *c1 = (int *)dalloc(S, sizeof(int) * nt);
-    if (!doff || !dcap || !dfill || !c0 || !c1) return fail(S, HK_ENOMEM, "rebuild: tables");
+    int *f1 = (int *)dalloc(S, sizeof(int) * nt), *b0 = (int *)dalloc(S, sizeof(int) * nt),
+        *b1 = (int *)dalloc(S, sizeof(int) * nt);
+    if (!doff || !dmoff || !dcap || !dmcap || !dmcnt || !dfill || !f1 || !b0 || !b1)
+        return fail(S, HK_ENOMEM, "rebuild: tables");
     HIPCHK(S, hipMemcpyAsync(doff, off.data(), sizeof(long long) * nt, hipMemcpyHostToDevice, S->s));
+    HIPCHK(S, hipMemcpyAsync(dmoff, moff.data(), sizeof(long long) * nt, hipMemcpyHostToDevice, S->s));
     HIPCHK(S, hipMemcpyAsync(dcap, cap.data(), sizeof(int) * nt, hipMemcpyHostToDevice, S->s));
+    HIPCHK(S, hipMemcpyAsync(dmcap, mcap.data(), sizeof(int) * nt, hipMemcpyHostToDevice, S->s));
     if (use_tiles && D.capacity > 0)
-        launch_scatter_groups(g, cur, D.off, D.cnt[D.cur], D.cap, nt, nb[0], doff, dfill,
-                              D.has_z, D.has_tau, S->s);
+        launch_scatter_groups(g, cur, D.off, D.nf[D.cur], D.nb[D.cur], D.cap, nt, D.max_cap, nbuf[0],
+                              doff, dfill, D.has_z, D.has_tau, S->s);
     for (int l = 0; l < nlists; ++l)
-        launch_scatter_groups(g, lists[l], D.g_off0, list_n[l], D.g_capmax, 1, nb[0], doff,
-                              dfill, D.has_z, D.has_tau, S->s);
-    HIPCHK(S, hipMemcpyAsync(c0, dfill, sizeof(int) * nt, hipMemcpyDeviceToDevice, S->s));
+        launch_scatter_groups(g, lists[l], D.g_off0, list_n[l], nullptr, D.g_capmax, 1, list_max[l],
+                              nbuf[0], doff, dfill, D.has_z, D.has_tau, S->s);
     HIPCHK(S, hipStreamSynchronize(S->s));
     free_parr(S, D.buf[0]);
     free_parr(S, D.buf[1]);
-    dfree(S, D.off); dfree(S, D.cap); dfree(S, D.cnt[0]); dfree(S, D.cnt[1]);
-    dfree(S, newcnt); dfree(S, dfill);
-    D.buf[0] = nb[0];
-    D.buf[1] = nb[1];
+    free_parr(S, D.mig);
+    int *olds[] = {D.nf[0], D.nf[1], D.nb[0], D.nb[1], D.cap, D.mcap, D.mcnt};
+    for (int *q : olds) dfree(S, q);
+    dfree(S, D.off); dfree(S, D.moff);
+    dfree(S, newcnt);
+    D.buf[0] = nbuf[0];
+    D.buf[1] = nbuf[1];
+    D.mig = nmig;
     D.cur = 0;
     D.off = doff;
     D.cap = dcap;
-    D.cnt[0] = c0;
-    D.cnt[1] = c1;
+    D.moff = dmoff;
+    D.mcap = dmcap;
+    D.mcnt = dmcnt;
+    D.nf[0] = dfill;   // the scatter fill counts are the new front counts
+    D.nf[1] = f1;
+    D.nb[0] = b0;
+    D.nb[1] = b1;
     D.capacity = total;
+    D.max_cap = maxc;
     D.h_off = off;
     D.h_cap = cap;
+    if (D.d.ionizable) {
+        dfree(S, D.active);
+        D.active = (int *)dalloc(S, sizeof(int) * nt);
+        if (!D.active) return fail(S, HK_ENOMEM, "rebuild: active counts");
+        launch_count_active(g, specp(D), D.buf[0], cur_bins(D), D.d.z_max, D.active, S->s);
+    }
     return HK_OK;
 }
 
@@ -335,7 +402,8 @@ int init_species(hk_sim *S, int isp) {
     }
     int *ln = S->status + 1 + 2 * isp;
     PArr lists[1] = {D.inbox};
-    rc = rebuild(S, isp, false, lists, &ln, total > 0 ? 1 : 0);
+    long long lmax[1] = {total};
+    rc = rebuild(S, isp, false, lists, &ln, lmax, total > 0 ? 1 : 0);
     if (rc) return rc;
     HIPCHK(S, hipMemsetAsync(S->status + 1 + 2 * isp, 0, sizeof(int), S->s));
     return HK_OK;
@@ -346,7 +414,7 @@ void time_mark(hk_sim *S, int slot) {
 }
 
 int check_status(hk_sim *S) {
-    HIPCHK(S, hipMemcpyAsync(S->h_status, S->status, sizeof(int) * (1 + 2 * HK_MAX_SPECIES),
+    HIPCHK(S, hipMemcpyAsync(S->h_status, S->status, sizeof(int) * 16,
                              hipMemcpyDeviceToHost, S->s));
     HIPCHK(S, hipStreamSynchronize(S->s));
     int e = S->h_status[0];
@@ -364,21 +432,25 @@ int gauss_snapshot(hk_sim *S);
 // ions targeting it can free in one step.
 long long inbox_need(hk_sim *S, int isp) {
     long long need = std::max<long long>(S->sp[isp].capacity / 4, 1 << 16);
+    if (S->sp[isp].d.fluid && S->run.switch_mode != HK_SW_ALL_PIC)
+        need += std::min<long long>(S->g.nn * std::max(1, S->sp[isp].d.ppc),
+                                    std::max<long long>(S->sp[isp].capacity, 1 << 20));
     for (int j = 0; j < S->nsp; ++j)
         if (S->sp[j].d.ionizable && S->sp[j].d.target == isp && S->run.enable_ionization)
             need += S->sp[j].capacity * std::max(1, S->sp[j].d.z_max);
     return need;
 }
 
-// Merge every species' inbox into its next bins; re-bin when bins are full.
+// Append every species' inbox to the back of its current bins; re-bin when
+// bins are full.  Reads the device status once (one host synchronisation).
 int merge_all(hk_sim *S) {
     for (int isp = 0; isp < S->nsp; ++isp) {
         DevSpecies &D = S->sp[isp];
         if (D.capacity == 0) continue;
         SpecP P = specp(D);
         int *inbox_n = S->status + 1 + 2 * isp, *fail_n = S->status + 2 + 2 * isp;
-        launch_merge_inbox(S->g, P, D.inbox, inbox_n, D.inbox_cap, D.buf[D.cur], D.cnt[D.cur],
-                           fail_n, D.fail, S->s);
+        launch_merge_inbox(S->g, P, D.inbox, inbox_n, D.inbox_cap, D.buf[D.cur], D.nf[D.cur],
+                           D.nb[D.cur], fail_n, D.fail, S->status, S->s);
     }
     int rc = check_status(S);
     if (rc) return rc;
@@ -388,7 +460,8 @@ int merge_all(hk_sim *S) {
         if (nfail > 0) {
             int *ln = S->status + 2 + 2 * isp;
             PArr lists[1] = {D.fail};
-            rc = rebuild(S, isp, true, lists, &ln, 1);
+            long long lmax[1] = {D.inbox_cap};
+            rc = rebuild(S, isp, true, lists, &ln, lmax, 1);
             if (rc) return rc;
         }
         HIPCHK(S, hipMemsetAsync(S->status + 1 + 2 * isp, 0, 2 * sizeof(int), S->s));
@@ -400,13 +473,80 @@ int merge_all(hk_sim *S) {
     return HK_OK;
 }
 
+SwitchP switch_params(const hk_sim *S) {
+    SwitchP P{};
+    P.thr_a = (real)S->run.thr_a;
+    P.thr_grad = (real)S->run.thr_grad;
+    P.thr_su = (real)S->run.thr_sigma_u;
+    P.thr_ion = (real)S->run.thr_ion;
+    P.thr_chi = (real)S->run.thr_chi;
+    P.n_floor = (real)S->run.n_floor;
+    P.dilation = S->run.dilation;
+    P.hysteresis = S->run.hysteresis;
+    P.enable_qed = S->run.enable_qed;
+    P.enable_ion = S->run.enable_ionization;
+    if (S->run.enable_qed) {
+        double omega0 = 2.0 * PI * PHYS_C / (S->las.lambda_um * 1e-6);
+        P.a_s = PHYS_ME * PHYS_C * PHYS_C / (PHYS_HBAR * omega0);
+    }
+    return P;
+}
+
+// Threshold criterion: nearest-node moments, indicators, dilation, hysteresis.
+void switch_eval(hk_sim *S) {
+    hipStream_t s = S->s;
+    const GridP &g = S->g;
+    launch_zero(S->mom, sizeof(real) * 7 * (size_t)g.nn, s);
+    const IonP *ions[4];
+    int nion = 0;
+    for (int isp = 0; isp < S->nsp; ++isp) {
+        DevSpecies &D = S->sp[isp];
+        SpecP P = specp(D);
+        if (D.d.fluid && D.capacity) launch_moments_tiles(g, P, D.buf[D.cur], cur_bins(D), 0, 0, S->mom, s);
+        if (D.d.fluid && D.fn)
+            launch_fluid_moments_nodes(g, (real)(1.0 / std::max(1, D.d.ppc)), D.fn, D.fu[0], D.fu[1],
+                                       D.fu[2], S->mom, s);
+        if (D.d.ionizable && S->run.enable_ionization && D.capacity) {
+            launch_moments_tiles(g, P, D.buf[D.cur], cur_bins(D), 1, D.d.z_max, S->mom, s);
+            if (nion < 4) ions[nion++] = D.ion;
+        }
+    }
+    SwitchP P = switch_params(S);
+    launch_indicators_nodes(g, P, S->mom, S->f, ions, nion, S->hot, S->notcold, s);
+    launch_dilate_nodes(g, P, S->hot, S->notcold, S->sw, S->calm, s);
+}
+
+// Fluid <-> particle conversion for every fluid species with a fluid array.
+void reconcile(hk_sim *S) {
+    hipStream_t s = S->s;
+    const GridP &g = S->g;
+    for (int isp = 0; isp < S->nsp; ++isp) {
+        DevSpecies &D = S->sp[isp];
+        if (!D.d.fluid || !D.fn) continue;
+        SpecP P = specp(D);
+        if (D.capacity) {
+            launch_absorb_tiles(g, P, D.buf[D.cur], cur_bins(D), S->sw, S->f, S->macc, S->ledger, s);
+            launch_absorb_finish_nodes(g, P.m, S->macc, D.fn, D.fu[0], D.fu[1], D.fu[2], S->ledger, s);
+        }
+        double dv = g.ddx * g.ddy * g.ddz;
+        int m = std::max(1, D.d.ppc);
+        real wmin = (real)(S->run.spawn_frac * D.d.n0 * dv / m);
+        launch_spawn_nodes(g, P, S->sw, D.fn, D.fu[0], D.fu[1], D.fu[2], S->f, wmin, m, S->run.seed,
+                           (int)S->step, D.inbox, S->status + 1 + 2 * isp, D.inbox_cap,
+                           S->status + 13, s);
+    }
+}
+
 int one_step(hk_sim *S) {
     hipStream_t s = S->s;
     const GridP &g = S->g;
     const int mode = S->run.switch_mode;
     const int hybrid = mode != HK_SW_ALL_PIC;
     time_mark(S, 0);
-    // 1. switch evaluation (added with the fluid and switch kernels)
+    // 1. switch evaluation
+    if ((mode == HK_SW_THRESHOLD || mode == HK_SW_CNN) &&
+        S->step % std::max(1, S->run.switch_every) == 0)
+        switch_eval(S);
     time_mark(S, 1);
     // 2. J = 0, antenna current at t^{n+1/2}
     launch_zero(S->f[HK_JX], sizeof(real) * 3 * (size_t)g.nn, s);
@@ -419,13 +559,16 @@ int one_step(hk_sim *S) {
         if (D.d.kind == HK_PHOTON) continue;
         if (D.d.mobile) {
             int nxt = 1 - D.cur;
-            launch_zero(D.cnt[nxt], sizeof(int) * g.ntiles, s);
-            launch_push_tiles(g, P, D.buf[D.cur], D.cnt[D.cur], D.buf[nxt], D.cnt[nxt], D.inbox,
-                              S->status + 1 + 2 * isp, D.inbox_cap, S->f, S->status, s);
+            launch_zero(D.nb[nxt], sizeof(int) * g.ntiles, s);
+            launch_push_tiles(g, P, D.buf[D.cur], cur_bins(D), D.buf[nxt], D.nf[nxt], D.mig, D.moff,
+                              D.mcap, D.mcnt, D.inbox, S->status + 1 + 2 * isp, D.inbox_cap, S->f,
+                              S->status, s);
+            launch_migrate(g, P, D.mig, D.moff, D.mcnt, D.buf[nxt], D.nf[nxt], D.nb[nxt],
+                           S->status + 2 + 2 * isp, D.fail, D.inbox_cap, S->status, s);
         } else if (D.d.ionizable && S->run.enable_ionization) {
             DevSpecies &T = S->sp[D.d.target];
-            launch_ionize_static(g, P, D.buf[D.cur], D.cnt[D.cur], S->f, S->sw, hybrid, D.ion,
-                                 T.inbox, S->status + 1 + 2 * D.d.target, T.inbox_cap,
+            launch_ionize_static(g, P, D.buf[D.cur], cur_bins(D), D.active, S->f, S->sw, hybrid,
+                                 D.ion, T.inbox, S->status + 1 + 2 * D.d.target, T.inbox_cap,
                                  S->run.seed, (int)S->step, S->ledger + 1, S->status, s);
         }
     }
@@ -434,11 +577,24 @@ int one_step(hk_sim *S) {
         if (D.capacity && D.d.mobile && D.d.kind != HK_PHOTON) D.cur = 1 - D.cur;
     }
     time_mark(S, 2);
-    time_mark(S, 3);
-    time_mark(S, 4);
-    // 6. merge newborn and overflow particles into their bins
+    // 4. newborn and overflow particles join their bins
     int rc = merge_all(S);
     if (rc) return rc;
+    time_mark(S, 3);
+    // 5. cold fluid, 6. conversion
+    if (hybrid) {
+        for (int isp = 0; isp < S->nsp; ++isp) {
+            DevSpecies &D = S->sp[isp];
+            if (D.fn) launch_fluid(g, specp(D), D.fn, D.fu[0], D.fu[1], D.fu[2], S->f,
+                                   S->fluid_scratch, (real)S->run.n_floor, s);
+        }
+    }
+    time_mark(S, 4);
+    if (hybrid) {
+        reconcile(S);
+        rc = merge_all(S);
+        if (rc) return rc;
+    }
     time_mark(S, 5);
     // 7. fields
     launch_yee_b_half(g, S->f, s);
@@ -449,14 +605,37 @@ int one_step(hk_sim *S) {
     S->t = S->step * g.ddt;
     if (S->timing) {
         HIPCHK(S, hipEventSynchronize(S->ev[6]));
-        const int map[6] = {0, 1, 6, 6, 5, 4};  // event interval -> timer slot
+        const int map[6] = {0, 1, 5, 2, 3, 4};  // event interval -> timer slot
         for (int i = 0; i < 6; ++i) {
             float ms = 0;
             (void)hipEventElapsedTime(&ms, S->ev[i], S->ev[i + 1]);
             S->timers[map[i]] += ms;
         }
     }
-    (void)hybrid;
+    return HK_OK;
+}
+
+// Fluid arrays exist for fluid species whenever the mode is not all-PIC.
+int ensure_fluid(hk_sim *S) {
+    const GridP &g = S->g;
+    if (!S->mom) {
+        S->mom = (real *)dalloc(S, sizeof(real) * 7 * (size_t)g.nn);
+        S->macc = (double *)dalloc(S, sizeof(double) * 4 * (size_t)g.nn);
+        S->hot = (uint8_t *)dalloc(S, (size_t)g.nn);
+        S->notcold = (uint8_t *)dalloc(S, (size_t)g.nn);
+        S->fluid_scratch = (real *)dalloc(S, sizeof(real) * 18 * (size_t)g.nn);
+        if (!S->mom || !S->macc || !S->hot || !S->notcold || !S->fluid_scratch)
+            return fail(S, HK_ENOMEM, "switch arrays");
+    }
+    for (int isp = 0; isp < S->nsp; ++isp) {
+        DevSpecies &D = S->sp[isp];
+        if (!D.d.fluid || D.fn) continue;
+        D.fn = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
+        for (int d = 0; d < 3; ++d) D.fu[d] = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
+        if (!D.fn || !D.fu[0] || !D.fu[1] || !D.fu[2]) return fail(S, HK_ENOMEM, "fluid arrays");
+        int rc = ensure_inbox(S, isp, inbox_need(S, isp));
+        if (rc) return rc;
+    }
     return HK_OK;
 }
 
@@ -466,7 +645,7 @@ int rho_total(hk_sim *S, double *rho) {
         DevSpecies &D = S->sp[isp];
         if (D.d.kind == HK_PHOTON) continue;
         SpecP P = specp(D);
-        if (D.capacity) launch_rho_tiles(S->g, P, D.buf[D.cur], D.cnt[D.cur], rho, S->s);
+        if (D.capacity) launch_rho_tiles(S->g, P, D.buf[D.cur], cur_bins(D), rho, S->s);
         if (D.fn) launch_fluid_rho(S->g, P, D.fn, rho, S->s);
     }
     return HK_OK;
@@ -532,7 +711,10 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
             return HK_EINVAL;
     }
     if (run->enable_qed) return HK_ENOTSUP;
-    if (run->switch_mode != HK_SW_ALL_PIC) return HK_ENOTSUP;
+    if (run->switch_mode == HK_SW_CNN) return HK_ENOTSUP;
+    if (run->switch_every < 0 || run->dilation < 0 || run->dilation > 4 || run->hysteresis < 1 ||
+        run->hysteresis > 255)
+        return HK_EINVAL;
     hk_sim *S = new hk_sim();
     S->gd = *grid;
     S->las = *laser;
@@ -557,8 +739,8 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
     S->tmp_b = (double *)dalloc(S, sizeof(double) * (size_t)g.nn);
     S->dsum = (double *)dalloc(S, sizeof(double) * 64);
     S->ledger = (double *)dalloc(S, sizeof(double) * 8);
-    S->status = (int *)dalloc(S, sizeof(int) * (1 + 2 * HK_MAX_SPECIES));
-    if (hipHostMalloc((void **)&S->h_status, sizeof(int) * (1 + 2 * HK_MAX_SPECIES), 0) != hipSuccess)
+    S->status = (int *)dalloc(S, sizeof(int) * 16);
+    if (hipHostMalloc((void **)&S->h_status, sizeof(int) * 16, 0) != hipSuccess)
         S->h_status = nullptr;
     if (!S->fblock || !S->mur_old || !S->sw || !S->calm || !S->gauss0 || !S->tmp_a || !S->tmp_b ||
         !S->dsum || !S->ledger || !S->status || !S->h_status) {
@@ -587,6 +769,7 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
     for (int i = 0; i < nspecies && rc == HK_OK; ++i)
         if (species[i].ionizable && run->enable_ionization) rc = build_ion_table(S, i);
     for (int i = 0; i < nspecies && rc == HK_OK; ++i) rc = ensure_inbox(S, i, inbox_need(S, i));
+    if (rc == HK_OK && run->switch_mode != HK_SW_ALL_PIC) rc = ensure_fluid(S);
     if (rc == HK_OK && hipStreamSynchronize(S->s) != hipSuccess) rc = HK_EDEVICE;
     if (rc != HK_OK) {
         hk_destroy(S);
@@ -627,8 +810,19 @@ int hk_step(hk_sim *S, int nsteps) {
 int hk_set_switch_mode(hk_sim *S, int mode) {
     if (!S || mode < HK_SW_ALL_PIC || mode > HK_SW_FIXED) return HK_EINVAL;
     if (S->poisoned) return HK_ESTATE;
-    if (mode != HK_SW_ALL_PIC) return fail(S, HK_ENOTSUP, "hybrid modes not built");
+    if (mode == HK_SW_CNN) return fail(S, HK_ENOTSUP, "learned switch not built");
+    if (mode == HK_SW_ALL_PIC) {
+        for (int i = 0; i < S->nsp; ++i)
+            if (S->sp[i].fn) return fail(S, HK_ESTATE, "fluid present: cannot return to all-PIC");
+    }
     S->run.switch_mode = mode;
+    if (mode != HK_SW_ALL_PIC) {
+        int rc = ensure_fluid(S);
+        if (rc) return rc;
+    }
+    if (mode == HK_SW_ALL_PIC || mode == HK_SW_ALL_FLUID)
+        HIPCHK(S, hipMemsetAsync(S->sw, mode == HK_SW_ALL_PIC ? 1 : 0, (size_t)S->g.nn, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
     return HK_OK;
 }
 
@@ -642,7 +836,14 @@ int hk_switch_map(hk_sim *S, uint8_t *out, size_t n) {
 
 int hk_set_switch_map(hk_sim *S, const uint8_t *in, size_t n) {
     if (!S || !in || n != (size_t)S->g.nn) return HK_EINVAL;
-    return fail(S, HK_ENOTSUP, "hybrid modes not built");
+    if (S->poisoned) return HK_ESTATE;
+    S->run.switch_mode = HK_SW_FIXED;
+    int rc = ensure_fluid(S);
+    if (rc) return rc;
+    HIPCHK(S, hipMemcpyAsync(S->sw, in, n, hipMemcpyHostToDevice, S->s));
+    HIPCHK(S, hipMemsetAsync(S->calm, 0, n, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    return HK_OK;
 }
 
 int hk_get_field(hk_sim *S, int comp, void *host_out, size_t bytes) {
@@ -682,47 +883,56 @@ int hk_get_divE(hk_sim *S, double *host_out, size_t n) {
     return HK_OK;
 }
 
-int hk_particle_count(hk_sim *S, int isp, size_t *n) {
-    if (!S || !n || isp < 0 || isp >= S->nsp) return HK_EINVAL;
-    if (S->poisoned) return HK_ESTATE;
-    DevSpecies &D = S->sp[isp];
-    *n = 0;
+// Host copy of the valid slots of a species' current bins, in storage order.
+int valid_slots(hk_sim *S, DevSpecies &D, std::vector<long long> &slots) {
+    slots.clear();
     if (D.capacity == 0) return HK_OK;
     const int nt = S->g.ntiles;
-    std::vector<int> cnt(nt);
-    HIPCHK(S, hipMemcpyAsync(cnt.data(), D.cnt[D.cur], sizeof(int) * nt, hipMemcpyDeviceToHost, S->s));
-    std::vector<int> cells((size_t)D.capacity);
+    std::vector<int> nf(nt), nb(nt), cells((size_t)D.capacity);
+    HIPCHK(S, hipMemcpyAsync(nf.data(), D.nf[D.cur], sizeof(int) * nt, hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipMemcpyAsync(nb.data(), D.nb[D.cur], sizeof(int) * nt, hipMemcpyDeviceToHost, S->s));
     HIPCHK(S, hipMemcpyAsync(cells.data(), D.buf[D.cur].cell, sizeof(int) * D.capacity,
                              hipMemcpyDeviceToHost, S->s));
     HIPCHK(S, hipStreamSynchronize(S->s));
-    size_t tot = 0;
     for (int t = 0; t < nt; ++t) {
-        int m = std::min(cnt[t], D.h_cap[t]);
-        for (int p = 0; p < m; ++p) tot += cells[D.h_off[t] + p] >= 0;
+        int c = D.h_cap[t];
+        int f = std::min(nf[t], c), b = std::min(nb[t], c - f);
+        for (int p = 0; p < f + b; ++p) {
+            long long i = D.h_off[t] + (p < f ? p : c - b + (p - f));
+            if (cells[i] >= 0) slots.push_back(i);
+        }
     }
-    *n = tot;
+    return HK_OK;
+}
+
+int hk_particle_count(hk_sim *S, int isp, size_t *n) {
+    if (!S || !n || isp < 0 || isp >= S->nsp) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    std::vector<long long> slots;
+    int rc = valid_slots(S, S->sp[isp], slots);
+    if (rc) return rc;
+    *n = slots.size();
     return HK_OK;
 }
 
 int hk_get_particles(hk_sim *S, int isp, const hk_particles *out) {
     if (!S || !out || isp < 0 || isp >= S->nsp) return HK_EINVAL;
     if (S->poisoned) return HK_ESTATE;
-    size_t n = 0;
-    int rc = hk_particle_count(S, isp, &n);
-    if (rc) return rc;
-    if (out->n != n) return fail(S, HK_EINVAL, "hk_get_particles: n = %zu, have %zu", out->n, n);
     DevSpecies &D = S->sp[isp];
+    std::vector<long long> slots;
+    int rc = valid_slots(S, D, slots);
+    if (rc) return rc;
+    const size_t n = slots.size();
+    if (out->n != n) return fail(S, HK_EINVAL, "hk_get_particles: n = %zu, have %zu", out->n, n);
     if (n == 0) return HK_OK;
     const long long C = D.capacity;
-    const int nt = S->g.ntiles;
-    std::vector<int> cnt(nt), cell(C), zc(D.has_z ? C : 0);
+    std::vector<int> cell(C), zc(D.has_z ? C : 0);
     std::vector<real> r[7];
     for (auto &v : r) v.resize(C);
     std::vector<uint64_t> id(C);
     std::vector<double> tau(D.has_tau ? C : 0);
     const PArr &a = D.buf[D.cur];
     hipStream_t s = S->s;
-    HIPCHK(S, hipMemcpyAsync(cnt.data(), D.cnt[D.cur], sizeof(int) * nt, hipMemcpyDeviceToHost, s));
     HIPCHK(S, hipMemcpyAsync(cell.data(), a.cell, sizeof(int) * C, hipMemcpyDeviceToHost, s));
     real *src[7] = {a.rx, a.ry, a.rz, a.ux, a.uy, a.uz, a.w};
     for (int k = 0; k < 7; ++k)
@@ -732,28 +942,22 @@ int hk_get_particles(hk_sim *S, int isp, const hk_particles *out) {
     if (D.has_tau) HIPCHK(S, hipMemcpyAsync(tau.data(), a.tau, sizeof(double) * C, hipMemcpyDeviceToHost, s));
     HIPCHK(S, hipStreamSynchronize(s));
     const GridP &g = S->g;
-    size_t q = 0;
-    for (int t = 0; t < nt; ++t) {
-        int m = std::min(cnt[t], D.h_cap[t]);
-        for (int p = 0; p < m; ++p) {
-            long long i = D.h_off[t] + p;
-            int c = cell[i];
-            if (c < 0) continue;
-            int ci = c % g.nx, cj = (c / g.nx) % g.ny, ck = c / (g.nx * g.ny);
-            if (out->x) {
-                out->x[3 * q] = (ci + (double)r[0][i]) * g.ddx;
-                out->x[3 * q + 1] = (cj + (double)r[1][i]) * g.ddy;
-                out->x[3 * q + 2] = (ck + (double)r[2][i]) * g.ddz;
-            }
-            if (out->u) {
-                out->u[3 * q] = r[3][i]; out->u[3 * q + 1] = r[4][i]; out->u[3 * q + 2] = r[5][i];
-            }
-            if (out->w) out->w[q] = r[6][i];
-            if (out->id) out->id[q] = id[i];
-            if (out->z) out->z[q] = D.has_z ? zc[i] : (int32_t)std::llround(D.d.charge);
-            if (out->tau) out->tau[q] = D.has_tau ? tau[i] : 0.0;
-            ++q;
+    for (size_t q = 0; q < n; ++q) {
+        const long long i = slots[q];
+        int c = cell[i];
+        int ci = c % g.nx, cj = (c / g.nx) % g.ny, ck = c / (g.nx * g.ny);
+        if (out->x) {
+            out->x[3 * q] = (ci + (double)r[0][i]) * g.ddx;
+            out->x[3 * q + 1] = (cj + (double)r[1][i]) * g.ddy;
+            out->x[3 * q + 2] = (ck + (double)r[2][i]) * g.ddz;
         }
+        if (out->u) {
+            out->u[3 * q] = r[3][i]; out->u[3 * q + 1] = r[4][i]; out->u[3 * q + 2] = r[5][i];
+        }
+        if (out->w) out->w[q] = r[6][i];
+        if (out->id) out->id[q] = id[i];
+        if (out->z) out->z[q] = D.has_z ? zc[i] : (int32_t)std::llround(D.d.charge);
+        if (out->tau) out->tau[q] = D.has_tau ? tau[i] : 0.0;
     }
     return HK_OK;
 }
@@ -805,7 +1009,8 @@ int hk_set_particles(hk_sim *S, int isp, const hk_particles *in) {
     HIPCHK(S, hipMemcpyAsync(S->status + 1 + 2 * isp, &n32, sizeof(int), hipMemcpyHostToDevice, s));
     int *ln = S->status + 1 + 2 * isp;
     PArr lists[1] = {D.inbox};
-    rc = rebuild(S, isp, false, lists, &ln, 1);
+    long long lmax[1] = {(long long)n};
+    rc = rebuild(S, isp, false, lists, &ln, lmax, 1);
     if (rc) return rc;
     HIPCHK(S, hipMemsetAsync(S->status + 1 + 2 * isp, 0, sizeof(int), s));
     HIPCHK(S, hipStreamSynchronize(s));
@@ -816,18 +1021,46 @@ int hk_set_particles(hk_sim *S, int isp, const hk_particles *in) {
 
 int hk_get_fluid(hk_sim *S, int isp, double *n, double *u, size_t nodes) {
     if (!S || !n || !u || isp < 0 || isp >= S->nsp || nodes != (size_t)S->g.nn) return HK_EINVAL;
-    return fail(S, HK_ENOTSUP, "no fluid in this context");
+    if (S->poisoned) return HK_ESTATE;
+    DevSpecies &D = S->sp[isp];
+    if (!D.fn) return fail(S, HK_EINVAL, "species %d has no fluid", isp);
+    std::vector<real> h[4];
+    real *src[4] = {D.fn, D.fu[0], D.fu[1], D.fu[2]};
+    for (int q = 0; q < 4; ++q) {
+        h[q].resize(nodes);
+        HIPCHK(S, hipMemcpyAsync(h[q].data(), src[q], sizeof(real) * nodes, hipMemcpyDeviceToHost, S->s));
+    }
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    for (size_t c = 0; c < nodes; ++c) {
+        n[c] = h[0][c];
+        for (int d = 0; d < 3; ++d) u[3 * c + d] = h[1 + d][c];
+    }
+    return HK_OK;
 }
 
 int hk_set_fluid(hk_sim *S, int isp, const double *n, const double *u, size_t nodes) {
     if (!S || !n || !u || isp < 0 || isp >= S->nsp || nodes != (size_t)S->g.nn) return HK_EINVAL;
-    return fail(S, HK_ENOTSUP, "no fluid in this context");
+    if (S->poisoned) return HK_ESTATE;
+    DevSpecies &D = S->sp[isp];
+    if (!D.fn) return fail(S, HK_EINVAL, "species %d has no fluid", isp);
+    std::vector<real> h[4];
+    for (int q = 0; q < 4; ++q) h[q].resize(nodes);
+    for (size_t c = 0; c < nodes; ++c) {
+        h[0][c] = (real)n[c];
+        for (int d = 0; d < 3; ++d) h[1 + d][c] = (real)u[3 * c + d];
+    }
+    real *dst[4] = {D.fn, D.fu[0], D.fu[1], D.fu[2]};
+    for (int q = 0; q < 4; ++q)
+        HIPCHK(S, hipMemcpyAsync(dst[q], h[q].data(), sizeof(real) * nodes, hipMemcpyHostToDevice, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    S->have_gauss0 = 0;
+    return HK_OK;
 }
 
 int hk_enable_timing(hk_sim *S, int on) {
     if (!S) return HK_EINVAL;
     S->timing = on != 0;
-    for (double &t : S->timers) t = 0;
+    for (int i = 0; i < 7; ++i) S->timers[i] = 0;
     return HK_OK;
 }
 
@@ -849,7 +1082,7 @@ int hk_diagnostics(hk_sim *S, hk_diag *d) {
     for (int isp = 0; isp < S->nsp; ++isp) {
         DevSpecies &D = S->sp[isp];
         SpecP P = specp(D);
-        if (D.capacity) launch_particle_sums(g, P, D.buf[D.cur], D.cnt[D.cur], S->dsum + 2 + 3 * isp, s);
+        if (D.capacity) launch_particle_sums(g, P, D.buf[D.cur], cur_bins(D), S->dsum + 2 + 3 * isp, s);
         if (D.fn) launch_fluid_sums(g, P, D.fn, D.fu[0], D.fu[1], D.fu[2], S->dsum + 20 + 3 * isp, s);
     }
     // Gauss: (divE - rho) now minus (divE - rho) at the snapshot

@@ -88,6 +88,12 @@ struct PArr {
     double *tau;  // optical depth (QED species only)
 };
 
+// Occupancy of one buffer's bins: tile t holds nf[t] particles from the front
+// of its region and nb[t] from the back (arrivals from other tiles).
+struct Bins {
+    const int *nf, *nb;
+};
+
 // Per-species state visible to kernels.
 struct SpecP {
     int kind, mobile, fluid, ionizable, z_max, qed, has_z, has_tau;
@@ -96,7 +102,16 @@ struct SpecP {
     const int *cap;
 };
 
-struct Ctx;  // host context (hk_api.cpp)
+__device__ inline int bin_count(const SpecP &sp, const Bins &b, int t, int &nf, int &nbv) {
+    const int cap = sp.cap[t];
+    nf = min(b.nf[t], cap);
+    nbv = min(b.nb[t], cap - nf);
+    return nf + nbv;
+}
+// Slot of the p-th valid particle of tile t.
+__device__ inline long long bin_slot(const SpecP &sp, int t, int p, int nf, int nbv) {
+    return sp.off[t] + (p < nf ? p : sp.cap[t] - nbv + (p - nf));
+}
 
 // Error flags raised by kernels (bitmask in a device int).
 enum { ERR_NONFINITE = 1, ERR_CFL = 2, ERR_INBOX = 4, ERR_TILE = 8 };
@@ -128,8 +143,8 @@ void launch_divE(const GridP &g, real *const f[9], double *out, hipStream_t s);
 
 // diagnostics (k_diag.hip)
 void launch_field_energy(const GridP &g, real *const f[9], double *out2, hipStream_t s);
-void launch_particle_sums(const GridP &g, const SpecP &sp, PArr a, const int *cnt,
-                          double *out3, hipStream_t s);
+void launch_particle_sums(const GridP &g, const SpecP &sp, PArr a, Bins b, double *out3,
+                          hipStream_t s);
 void launch_gauss(const GridP &g, const double *dive, const double *rho, const double *g0,
                   int skip_plane, double *out2, hipStream_t s);
 void launch_fluid_sums(const GridP &g, const SpecP &sp, const real *n, const real *ux,

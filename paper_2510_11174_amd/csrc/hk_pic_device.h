@@ -1,0 +1,208 @@
+// Device helpers shared by the particle and conversion kernels (internal).
+#pragma once
+#include "hk_internal.h"
+
+namespace hkdev {
+
+constexpr int FT = TILE + 2;       // field tile edge: cells -1 .. TILE
+constexpr int FT3 = FT * FT * FT;
+constexpr int JT = TILE + 3;       // current tile edge: nodes -1 .. TILE+1
+constexpr int JT3 = JT * JT * JT;
+
+__device__ inline int tile_of(const GridP &g, int cell) {
+    int ci = cell % g.nx, r = cell / g.nx;
+    int cj = r % g.ny, ck = r / g.ny;
+    return (ci >> TLOG) + g.ntx * ((cj >> TLOG) + g.nty * (ck >> TLOG));
+}
+
+// CIC weights of a node-type (o) and a half-type (o - 1/2) sample along one
+// axis, as an LDS index (field tile origin at cell -1) and fraction.
+struct AxisW {
+    int in_, ih;
+    real fn, fh;
+};
+__device__ inline AxisW axis_weights(int l, real o) {
+    AxisW a;
+    a.in_ = l + 1;
+    a.fn = o;
+    if (o >= (real)0.5) { a.ih = l + 1; a.fh = o - (real)0.5; }
+    else { a.ih = l; a.fh = o + (real)0.5; }
+    return a;
+}
+
+__device__ inline real tri(const real *F, int i, int j, int k, real fx, real fy, real fz) {
+    const int b = i + FT * (j + FT * k);
+    real acc = 0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                real wgt = (a ? fx : 1 - fx) * (bb ? fy : 1 - fy) * (c ? fz : 1 - fz);
+                acc += wgt * F[b + a + FT * (bb + FT * c)];
+            }
+    return acc;
+}
+
+// Esirkepov shape factors along one axis for a move from offset o to X1 = o +
+// delta (relative to the old cell), written in terms of the displacement so
+// that slow particles keep full relative precision.  Window nodes base..base+2
+// relative to the old cell; base is -1 when the particle crossed downwards.
+struct AxisS {
+    int base;
+    real S0[3], DS[3];
+};
+__device__ inline AxisS axis_shapes(real o, real X1) {
+    AxisS s;
+    if (X1 >= (real)1) {                // crossed up: nodes 0, 1, 2
+        real e = X1 - (real)1;
+        s.base = 0;
+        s.S0[0] = (real)1 - o; s.S0[1] = o; s.S0[2] = 0;
+        s.DS[0] = -((real)1 - o); s.DS[1] = ((real)1 - e) - o; s.DS[2] = e;
+    } else if (X1 < (real)0) {          // crossed down: nodes -1, 0, 1
+        real e = -X1;
+        s.base = -1;
+        s.S0[0] = 0; s.S0[1] = (real)1 - o; s.S0[2] = o;
+        s.DS[0] = e; s.DS[1] = o - e; s.DS[2] = -o;
+    } else {                            // stayed: nodes 0, 1, 2
+        real d = X1 - o;
+        s.base = 0;
+        s.S0[0] = (real)1 - o; s.S0[1] = o; s.S0[2] = 0;
+        s.DS[0] = -d; s.DS[1] = d; s.DS[2] = 0;
+    }
+    return s;
+}
+
+// Deposit the Esirkepov current of one particle into the LDS J tile.  (lx, ly,
+// lz) is the old cell inside the tile; cx = q w / dV * dx / dt (per axis).
+__device__ inline void esirkepov_lds(real *sJ, int lx, int ly, int lz, const AxisS &X,
+                                     const AxisS &Y, const AxisS &Z, real cx, real cy, real cz) {
+    const real third = (real)(1.0 / 3.0), half = (real)0.5;
+    const int ox = lx + X.base + 1, oy = ly + Y.base + 1, oz = lz + Z.base + 1;
+    // Jx on faces a = 0, 1 (prefix of W_x along x)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            real fyz = Y.S0[b] * Z.S0[c] + half * Y.DS[b] * Z.S0[c] + half * Y.S0[b] * Z.DS[c] +
+                       third * Y.DS[b] * Z.DS[c];
+            real acc = 0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                acc -= cx * (X.DS[a] * fyz);
+                if (acc != (real)0)
+                    atomicAdd(&sJ[0 * JT3 + (ox + a) + JT * ((oy + b) + JT * (oz + c))], acc);
+            }
+        }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            real fxz = X.S0[a] * Z.S0[c] + half * X.DS[a] * Z.S0[c] + half * X.S0[a] * Z.DS[c] +
+                       third * X.DS[a] * Z.DS[c];
+            real acc = 0;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                acc -= cy * (Y.DS[b] * fxz);
+                if (acc != (real)0)
+                    atomicAdd(&sJ[1 * JT3 + (ox + a) + JT * ((oy + b) + JT * (oz + c))], acc);
+            }
+        }
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            real fxy = X.S0[a] * Y.S0[b] + half * X.DS[a] * Y.S0[b] + half * X.S0[a] * Y.DS[b] +
+                       third * X.DS[a] * Y.DS[b];
+            real acc = 0;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                acc -= cz * (Z.DS[c] * fxy);
+                if (acc != (real)0)
+                    atomicAdd(&sJ[2 * JT3 + (ox + a) + JT * ((oy + b) + JT * (oz + c))], acc);
+            }
+        }
+}
+
+// Current accumulator type of the LDS tile.  On gfx950 an LDS float atomic
+// add is serialized per lane (about 3 cycles per active lane) while a 64-bit
+// integer add costs a few cycles per wavefront, so the FP32 build deposits
+// the current in 64-bit fixed point: each workgroup picks a scale from its
+// largest |q w| so that one particle's largest contribution is 2^40 units;
+// integer sums are exact and independent of order.  The FP64 build keeps
+// FP64 atomics (it is the precision reference, not the fast path).
+#ifdef HK_DOUBLE
+typedef double jacc_t;
+__device__ inline void jadd(jacc_t *p, real v, real) { atomicAdd(p, v); }
+__device__ inline double jval(jacc_t v, double) { return v; }
+#else
+typedef unsigned long long jacc_t;
+__device__ inline void jadd(jacc_t *p, real v, real inv_scale) {
+    long long q = llrintf(v * inv_scale);
+    if (q) atomicAdd(p, (unsigned long long)q);
+}
+__device__ inline double jval(jacc_t v, double scale) { return (double)(long long)v * scale; }
+#endif
+constexpr float JFIX_UNITS = 1099511627776.0f;   // 2^40
+
+// Esirkepov current of one particle added to an LDS tile of accumulators.
+__device__ inline void esirkepov_acc(jacc_t *sJ, int lx, int ly, int lz, const AxisS &X,
+                                     const AxisS &Y, const AxisS &Z, real cx, real cy, real cz,
+                                     real inv_scale) {
+    const real third = (real)(1.0 / 3.0), half = (real)0.5;
+    const int ox = lx + X.base + 1, oy = ly + Y.base + 1, oz = lz + Z.base + 1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            real fyz = Y.S0[b] * Z.S0[c] + half * Y.DS[b] * Z.S0[c] + half * Y.S0[b] * Z.DS[c] +
+                       third * Y.DS[b] * Z.DS[c];
+            real acc = 0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                acc -= cx * (X.DS[a] * fyz);
+                if (acc != (real)0)
+                    jadd(&sJ[0 * JT3 + (ox + a) + JT * ((oy + b) + JT * (oz + c))], acc, inv_scale);
+            }
+        }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            real fxz = X.S0[a] * Z.S0[c] + half * X.DS[a] * Z.S0[c] + half * X.S0[a] * Z.DS[c] +
+                       third * X.DS[a] * Z.DS[c];
+            real acc = 0;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                acc -= cy * (Y.DS[b] * fxz);
+                if (acc != (real)0)
+                    jadd(&sJ[1 * JT3 + (ox + a) + JT * ((oy + b) + JT * (oz + c))], acc, inv_scale);
+            }
+        }
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            real fxy = X.S0[a] * Y.S0[b] + half * X.DS[a] * Y.S0[b] + half * X.S0[a] * Y.DS[b] +
+                       third * X.DS[a] * Y.DS[b];
+            real acc = 0;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                acc -= cz * (Z.DS[c] * fxy);
+                if (acc != (real)0)
+                    jadd(&sJ[2 * JT3 + (ox + a) + JT * ((oy + b) + JT * (oz + c))], acc, inv_scale);
+            }
+        }
+}
+
+__device__ inline real below_one() {
+#ifdef HK_DOUBLE
+    return 0.99999999999999988898;
+#else
+    return 0.99999994f;
+#endif
+}
+
+
+}  // namespace hkdev

@@ -61,13 +61,13 @@ k_field_energy(GridP g, const real *Ex, const real *Ey, const real *Ez, const re
 
 // out[0] kinetic energy, out[1] count, out[2] charge
 __global__ void __launch_bounds__(BS)
-k_particle_sums(GridP g, SpecP sp, PArr a, const int *cnt, double *out) {
+k_particle_sums(GridP g, SpecP sp, PArr a, Bins bins, double *out) {
     const int t = blockIdx.x;
-    const int n = min(cnt[t], sp.cap[t]);
-    const long long base = sp.off[t];
+    int nf, nbv;
+    const int n = bin_count(sp, bins, t, nf, nbv);
     double ke = 0, num = 0, ch = 0;
     for (int p = threadIdx.x; p < n; p += BS) {
-        long long ip = base + p;
+        long long ip = bin_slot(sp, t, p, nf, nbv);
         if (a.cell[ip] < 0) continue;
         double ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip], w = a.w[ip];
         double u2 = ux * ux + uy * uy + uz * uz;
@@ -162,9 +162,9 @@ void launch_field_energy(const GridP &g, real *const f[9], double *out2, hipStre
     k_field_energy<<<blocks(g.nn), BS, 0, s>>>(g, f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY],
                                                f[HK_BZ], out2);
 }
-void launch_particle_sums(const GridP &g, const SpecP &sp, PArr a, const int *cnt, double *out3,
+void launch_particle_sums(const GridP &g, const SpecP &sp, PArr a, Bins b, double *out3,
                           hipStream_t s) {
-    k_particle_sums<<<g.ntiles, BS, 0, s>>>(g, sp, a, cnt, out3);
+    k_particle_sums<<<g.ntiles, BS, 0, s>>>(g, sp, a, b, out3);
 }
 void launch_fluid_sums(const GridP &g, const SpecP &sp, const real *n, const real *ux,
                        const real *uy, const real *uz, double *out3, hipStream_t s) {

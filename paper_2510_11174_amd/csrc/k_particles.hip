@@ -11,25 +11,21 @@
 // cell-relative offsets.  One workgroup owns one tile: it stages the tile's
 // E and B (plus one guard cell) in LDS, gathers from LDS, pushes, deposits the
 // Esirkepov current into an LDS J tile (guard 1 below, 2 above) with LDS
-// atomics, flushes that tile to HBM with one global atomic per sample, and
-// writes each pushed particle straight into its destination bin of the next
-// buffer (wave-aggregated slot reservation for particles that stay).  Every
-// particle byte is read once and written once per step.
+// atomics and flushes that tile to HBM with one global atomic per sample.
+// Particles that stay in the tile are written to the front of the tile's bin
+// in the next buffer, ranked by an LDS counter, so the hot loop issues no
+// global atomic with a return value (those cost a round trip to the memory
+// side on a multi-die GPU).  Particles that leave go to the tile's mover
+// region, also ranked in LDS; a migrate kernel then appends them to the back
+// of their destination bins.  Every particle byte is read once and written
+// once per step, movers twice.
 #include "hk_internal.h"
+#include "hk_pic_device.h"
 
 namespace {
 
+using namespace hkdev;
 constexpr int BS = 256;
-constexpr int FT = TILE + 2;       // field tile edge: cells -1 .. TILE
-constexpr int FT3 = FT * FT * FT;
-constexpr int JT = TILE + 3;       // current tile edge: nodes -1 .. TILE+1
-constexpr int JT3 = JT * JT * JT;
-
-__device__ inline int tile_of(const GridP &g, int cell) {
-    int ci = cell % g.nx, r = cell / g.nx;
-    int cj = r % g.ny, ck = r / g.ny;
-    return (ci >> TLOG) + g.ntx * ((cj >> TLOG) + g.nty * (ck >> TLOG));
-}
 
 __device__ inline void copy_particle(const PArr &s, long long i, const PArr &d, long long j,
                                      int has_z, int has_tau) {
@@ -76,186 +72,150 @@ k_init(GridP g, int ppc, double u_th, double charge, uint64_t seed, const int *_
     if (has_tau) out.tau[tid] = 0.0;
 }
 
+// --------------------------------------------------------- wave helpers ------------------
+// Reserve `add` slots per active lane in ctr[key]: lanes of a wave that share a
+// key are ranked by ballot and served by one atomic (up to four distinct keys
+// per wave); the rest fall back to one atomic per lane.  Every lane calls it.
+__device__ inline int wave_reserve(int *ctr, int key, bool active) {
+    const int lane = __lane_id();
+    const uint64_t lt = (1ull << lane) - 1ull;
+    uint64_t pending = __ballot(active);
+    int slot = 0;
+    for (int it = 0; it < 4 && pending; ++it) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int k = __shfl(key, leader);
+        const uint64_t grp = __ballot(active && key == k) & pending;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&ctr[k], __popcll(grp));
+        base = __shfl(base, leader);
+        if ((grp >> lane) & 1ull) slot = base + __popcll(grp & lt);
+        pending &= ~grp;
+    }
+    if ((pending >> lane) & 1ull) slot = atomicAdd(&ctr[key], 1);
+    return slot;
+}
+
 // --------------------------------------------------------- count / scatter ---------------
-// Source bins: nsrc groups, group s holds slots [off[s], off[s] + min(cnt[s], cap[s])).
+// Source groups: group s holds slots [off[s], off[s] + nf[s]) and
+// [off[s] + cap[s] - nb[s], off[s] + cap[s]) (nb may be null: front only).
+__device__ inline int group_count(const long long *off, const int *nf, const int *nb,
+                                  const int *cap, int s, int &f, int &b) {
+    const int c = cap[s];
+    f = min(nf[s], c);
+    b = nb ? min(nb[s], c - f) : 0;
+    return f + b;
+}
+
 __global__ void __launch_bounds__(BS)
-k_count(GridP g, PArr src, const long long *__restrict__ off, const int *__restrict__ cnt,
-        const int *__restrict__ cap, int *__restrict__ newcnt) {
-    int s = blockIdx.x;
-    int n = min(cnt[s], cap[s]);
-    long long b = off[s];
-    for (int p = threadIdx.x; p < n; p += BS) {
-        int cell = src.cell[b + p];
-        if (cell >= 0) atomicAdd(&newcnt[tile_of(g, cell)], 1);
+k_count(GridP g, PArr src, const long long *__restrict__ off, const int *__restrict__ nf,
+        const int *__restrict__ nb, const int *__restrict__ cap, int *__restrict__ newcnt) {
+    const int s = blockIdx.x;
+    int f, b;
+    const int n = group_count(off, nf, nb, cap, s, f, b);
+    const int c = cap[s];
+    const int stride = gridDim.y * BS;
+    for (int p0 = blockIdx.y * BS; p0 < n; p0 += stride) {
+        const int p = p0 + threadIdx.x;
+        int cell = -1;
+        if (p < n) cell = src.cell[off[s] + (p < f ? p : c - b + (p - f))];
+        const bool ok = cell >= 0;
+        wave_reserve(newcnt, ok ? tile_of(g, cell) : 0, ok);
     }
 }
 
 __global__ void __launch_bounds__(BS)
-k_scatter(GridP g, PArr src, const long long *__restrict__ off, const int *__restrict__ cnt,
-          const int *__restrict__ cap, PArr dst, const long long *__restrict__ doff,
-          int *__restrict__ dfill, int has_z, int has_tau) {
-    int s = blockIdx.x;
-    int n = min(cnt[s], cap[s]);
-    long long b = off[s];
-    for (int p = threadIdx.x; p < n; p += BS) {
-        int cell = src.cell[b + p];
-        if (cell < 0) continue;
-        int t = tile_of(g, cell);
-        int slot = atomicAdd(&dfill[t], 1);
-        copy_particle(src, b + p, dst, doff[t] + slot, has_z, has_tau);
+k_scatter(GridP g, PArr src, const long long *__restrict__ off, const int *__restrict__ nf,
+          const int *__restrict__ nb, const int *__restrict__ cap, PArr dst,
+          const long long *__restrict__ doff, int *__restrict__ dfill, int has_z, int has_tau) {
+    const int s = blockIdx.x;
+    int f, b;
+    const int n = group_count(off, nf, nb, cap, s, f, b);
+    const int c = cap[s];
+    const int stride = gridDim.y * BS;
+    for (int p0 = blockIdx.y * BS; p0 < n; p0 += stride) {
+        const int p = p0 + threadIdx.x;
+        long long i = 0;
+        int cell = -1;
+        if (p < n) {
+            i = off[s] + (p < f ? p : c - b + (p - f));
+            cell = src.cell[i];
+        }
+        const bool ok = cell >= 0;
+        const int t = ok ? tile_of(g, cell) : 0;
+        const int slot = wave_reserve(dfill, t, ok);
+        if (ok) copy_particle(src, i, dst, doff[t] + slot, has_z, has_tau);
     }
 }
 
-// Inbox particles join their bins; those that do not fit go to `fail`.
+// Append a list of particles to the back of their bins; those that do not
+// fit go to `fail` (and force a re-bin).  Grid-stride over the list.
 __global__ void __launch_bounds__(BS)
-k_merge(GridP g, SpecP sp, PArr inbox, const int *__restrict__ inbox_n, PArr dst,
-        int *__restrict__ cnt, int *__restrict__ fail_n, PArr fail) {
-    const long long n = *inbox_n;
-    for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < n;
-         i += (long long)gridDim.x * BS) {
-        int cell = inbox.cell[i];
-        if (cell < 0) continue;
-        int t = tile_of(g, cell);
-        int slot = atomicAdd(&cnt[t], 1);
-        if (slot < sp.cap[t]) {
-            copy_particle(inbox, i, dst, sp.off[t] + slot, sp.has_z, sp.has_tau);
+k_merge(GridP g, SpecP sp, PArr inbox, const int *__restrict__ inbox_n, int inbox_cap, PArr dst,
+        const int *__restrict__ nf, int *__restrict__ nb, int *__restrict__ fail_n, PArr fail,
+        int fail_cap, int *__restrict__ err) {
+    const int n = min(*inbox_n, inbox_cap);
+    for (int p0 = blockIdx.x * BS; p0 < n; p0 += gridDim.x * BS) {
+        const int i = p0 + threadIdx.x;
+        const int cell = i < n ? inbox.cell[i] : -1;
+        const bool ok = cell >= 0;
+        const int t = ok ? tile_of(g, cell) : 0;
+        const int slot = wave_reserve(nb, t, ok);
+        if (!ok) continue;
+        if (nf[t] + slot < sp.cap[t]) {
+            copy_particle(inbox, i, dst, sp.off[t] + sp.cap[t] - 1 - slot, sp.has_z, sp.has_tau);
         } else {
             int k = atomicAdd(fail_n, 1);
-            copy_particle(inbox, i, fail, k, sp.has_z, sp.has_tau);
+            if (k < fail_cap) copy_particle(inbox, i, fail, k, sp.has_z, sp.has_tau);
+            else atomicOr(err, ERR_INBOX);
+        }
+    }
+}
+
+// Movers of tile t (its region of the mover buffer) join the back of their
+// destination bins in the next buffer.
+__global__ void __launch_bounds__(BS)
+k_migrate(GridP g, SpecP sp, PArr mig, const long long *__restrict__ moff,
+          const int *__restrict__ mcnt, PArr dst, const int *__restrict__ nf, int *__restrict__ nb,
+          int *__restrict__ fail_n, PArr fail, int fail_cap, int *__restrict__ err) {
+    const int t = blockIdx.x;
+    const int n = mcnt[t];
+    const long long b0 = moff[t];
+    for (int p0 = 0; p0 < n; p0 += BS) {
+        const int p = p0 + threadIdx.x;
+        const int cell = p < n ? mig.cell[b0 + p] : -1;
+        const bool ok = cell >= 0;
+        const int d = ok ? tile_of(g, cell) : 0;
+        const int slot = wave_reserve(nb, d, ok);
+        if (!ok) continue;
+        if (nf[d] + slot < sp.cap[d]) {
+            copy_particle(mig, b0 + p, dst, sp.off[d] + sp.cap[d] - 1 - slot, sp.has_z, sp.has_tau);
+        } else {
+            int k = atomicAdd(fail_n, 1);
+            if (k < fail_cap) copy_particle(mig, b0 + p, fail, k, sp.has_z, sp.has_tau);
+            else atomicOr(err, ERR_INBOX);
         }
     }
 }
 
 // ------------------------------------------------------------- the push -----------------
-// CIC weights of a node-type (o) and a half-type (o - 1/2) sample along one
-// axis, as an LDS index (field tile origin at cell -1) and fraction.
-struct AxisW {
-    int in_, ih;
-    real fn, fh;
-};
-__device__ inline AxisW axis_weights(int l, real o) {
-    AxisW a;
-    a.in_ = l + 1;
-    a.fn = o;
-    if (o >= (real)0.5) { a.ih = l + 1; a.fh = o - (real)0.5; }
-    else { a.ih = l; a.fh = o + (real)0.5; }
-    return a;
-}
-
-__device__ inline real tri(const real *F, int i, int j, int k, real fx, real fy, real fz) {
-    const int b = i + FT * (j + FT * k);
-    real acc = 0;
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                real wgt = (a ? fx : 1 - fx) * (bb ? fy : 1 - fy) * (c ? fz : 1 - fz);
-                acc += wgt * F[b + a + FT * (bb + FT * c)];
-            }
-    return acc;
-}
-
-// Esirkepov shape factors along one axis for a move from offset o to X1 = o +
-// delta (relative to the old cell), written in terms of the displacement so
-// that slow particles keep full relative precision.  Window nodes base..base+2
-// relative to the old cell; base is -1 when the particle crossed downwards.
-struct AxisS {
-    int base;
-    real S0[3], DS[3];
-};
-__device__ inline AxisS axis_shapes(real o, real X1) {
-    AxisS s;
-    if (X1 >= (real)1) {                // crossed up: nodes 0, 1, 2
-        real e = X1 - (real)1;
-        s.base = 0;
-        s.S0[0] = (real)1 - o; s.S0[1] = o; s.S0[2] = 0;
-        s.DS[0] = -((real)1 - o); s.DS[1] = ((real)1 - e) - o; s.DS[2] = e;
-    } else if (X1 < (real)0) {          // crossed down: nodes -1, 0, 1
-        real e = -X1;
-        s.base = -1;
-        s.S0[0] = 0; s.S0[1] = (real)1 - o; s.S0[2] = o;
-        s.DS[0] = e; s.DS[1] = o - e; s.DS[2] = -o;
-    } else {                            // stayed: nodes 0, 1, 2
-        real d = X1 - o;
-        s.base = 0;
-        s.S0[0] = (real)1 - o; s.S0[1] = o; s.S0[2] = 0;
-        s.DS[0] = -d; s.DS[1] = d; s.DS[2] = 0;
-    }
-    return s;
-}
-
-// Deposit the Esirkepov current of one particle into the LDS J tile.  (lx, ly,
-// lz) is the old cell inside the tile; cx = q w / dV * dx / dt (per axis).
-__device__ inline void esirkepov_lds(real *sJ, int lx, int ly, int lz, const AxisS &X,
-                                     const AxisS &Y, const AxisS &Z, real cx, real cy, real cz) {
-    const real third = (real)(1.0 / 3.0), half = (real)0.5;
-    const int ox = lx + X.base + 1, oy = ly + Y.base + 1, oz = lz + Z.base + 1;
-    // Jx on faces a = 0, 1 (prefix of W_x along x)
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            real fyz = Y.S0[b] * Z.S0[c] + half * Y.DS[b] * Z.S0[c] + half * Y.S0[b] * Z.DS[c] +
-                       third * Y.DS[b] * Z.DS[c];
-            real acc = 0;
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                acc -= cx * (X.DS[a] * fyz);
-                if (acc != (real)0)
-                    atomicAdd(&sJ[0 * JT3 + (ox + a) + JT * ((oy + b) + JT * (oz + c))], acc);
-            }
-        }
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            real fxz = X.S0[a] * Z.S0[c] + half * X.DS[a] * Z.S0[c] + half * X.S0[a] * Z.DS[c] +
-                       third * X.DS[a] * Z.DS[c];
-            real acc = 0;
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                acc -= cy * (Y.DS[b] * fxz);
-                if (acc != (real)0)
-                    atomicAdd(&sJ[1 * JT3 + (ox + a) + JT * ((oy + b) + JT * (oz + c))], acc);
-            }
-        }
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            real fxy = X.S0[a] * Y.S0[b] + half * X.DS[a] * Y.S0[b] + half * X.S0[a] * Y.DS[b] +
-                       third * X.DS[a] * Y.DS[b];
-            real acc = 0;
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                acc -= cz * (Z.DS[c] * fxy);
-                if (acc != (real)0)
-                    atomicAdd(&sJ[2 * JT3 + (ox + a) + JT * ((oy + b) + JT * (oz + c))], acc);
-            }
-        }
-}
-
-__device__ inline real below_one() {
-#ifdef HK_DOUBLE
-    return 0.99999999999999988898;
-#else
-    return 0.99999994f;
-#endif
-}
-
 __global__ void __launch_bounds__(BS)
-k_push(GridP g, SpecP sp, PArr in, const int *__restrict__ cnt_in, PArr out,
-       int *__restrict__ cnt_out, PArr inbox, int *__restrict__ inbox_n, int inbox_cap,
-       const real *__restrict__ Ex, const real *__restrict__ Ey, const real *__restrict__ Ez,
-       const real *__restrict__ Bx, const real *__restrict__ By, const real *__restrict__ Bz,
-       real *__restrict__ Jx, real *__restrict__ Jy, real *__restrict__ Jz, int *__restrict__ err) {
+k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_out, PArr mig,
+       const long long *__restrict__ moff, const int *__restrict__ mcap, int *__restrict__ mcnt,
+       PArr inbox, int *__restrict__ inbox_n, int inbox_cap, const real *__restrict__ Ex,
+       const real *__restrict__ Ey, const real *__restrict__ Ez, const real *__restrict__ Bx,
+       const real *__restrict__ By, const real *__restrict__ Bz, real *__restrict__ Jx,
+       real *__restrict__ Jy, real *__restrict__ Jz, int *__restrict__ err) {
     __shared__ real sF[6 * FT3];
-    __shared__ real sJ[3 * JT3];
+    __shared__ jacc_t sJ[3 * JT3];
+    __shared__ int s_stay, s_move;
+    __shared__ unsigned s_wmax;
     const int t = blockIdx.x;
-    const int n = min(cnt_in[t], sp.cap[t]);
-    if (n <= 0) return;
+    int nfi, nbi;
+    const int n = bin_count(sp, bin_in, t, nfi, nbi);
+    if (n <= 0) {
+        if (threadIdx.x == 0) { nf_out[t] = 0; mcnt[t] = 0; }
+        return;
+    }
     const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
     const int per = g.bcx == HK_BC_PERIODIC;
@@ -279,36 +239,60 @@ k_push(GridP g, SpecP sp, PArr in, const int *__restrict__ cnt_in, PArr out,
         sF[5 * FT3 + e] = Bz[ch];
     }
     for (int e = threadIdx.x; e < 3 * JT3; e += BS) sJ[e] = 0;
+    if (threadIdx.x == 0) { s_stay = 0; s_move = 0; s_wmax = 0; }
+    __syncthreads();
+    // fixed-point scale of the tile: largest weight (non-negative floats
+    // order like their bit patterns)
+    {
+        float wm = 0.f;
+        for (int p = threadIdx.x; p < n; p += BS) {
+            long long ip = bin_slot(sp, t, p, nfi, nbi);
+            if (in.cell[ip] >= 0) wm = fmaxf(wm, fabsf((float)in.w[ip]));
+        }
+        for (int o = 32; o > 0; o >>= 1) wm = fmaxf(wm, __shfl_down(wm, o));
+        if ((threadIdx.x & 63) == 0) atomicMax(&s_wmax, __float_as_uint(wm));
+    }
     __syncthreads();
 
-    const long long base = sp.off[t];
     const real dv = g.dx * g.dy * g.dz;
     const real hq = (real)0.5 * sp.qm * g.dt;
     const int lane = __lane_id();
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const long long obase = sp.off[t];
+    const long long mbase = moff[t];
+    const int mlim = mcap[t];
+    const real cdx = g.dx / g.dt, cdy = g.dy / g.dt, cdz = g.dz / g.dt;
+    // one particle's largest current contribution is |q| w / dV * max(dx,dy,dz) / dt
+    const double jmax = (double)fabsf((float)sp.q) * (double)__uint_as_float(s_wmax) / (double)dv *
+                        (double)fmaxf(fmaxf((float)cdx, (float)cdy), (float)cdz);
+    const double jscale = jmax > 0.0 ? jmax / (double)JFIX_UNITS : 1.0;
+    const real inv_scale = (real)(1.0 / jscale);
     for (int p0 = 0; p0 < n; p0 += BS) {
         const int p = p0 + threadIdx.x;
-        int cell = p < n ? in.cell[base + p] : -1;
+        long long ip = 0;
+        int cell = -1;
+        if (p < n) {
+            ip = bin_slot(sp, t, p, nfi, nbi);
+            cell = in.cell[ip];
+        }
         bool valid = cell >= 0;
         int ncell = -1, ntile = -1;
         real nrx = 0, nry = 0, nrz = 0, ux = 0, uy = 0, uz = 0, w = 0;
         uint64_t id = 0;
         int zc = 0;
         double tau = 0;
+        int ci = 0, cj = 0, ck = 0, lx = 0, ly = 0, lz = 0;
         if (valid) {
-            const long long ip = base + p;
-            const int ci = cell % g.nx, rr = cell / g.nx;
-            const int cj = rr % g.ny, ck = rr / g.ny;
-            const int lx = ci - ox, ly = cj - oy, lz = ck - oz;
+            ci = cell % g.nx;
+            const int rr = cell / g.nx;
+            cj = rr % g.ny; ck = rr / g.ny;
+            lx = ci - ox; ly = cj - oy; lz = ck - oz;
             if ((unsigned)lx >= TILE || (unsigned)ly >= TILE || (unsigned)lz >= TILE) {
                 atomicOr(err, ERR_TILE);
                 valid = false;
             }
         }
         if (valid) {
-            const long long ip = base + p;
-            const int ci = cell % g.nx, rr = cell / g.nx;
-            const int cj = rr % g.ny, ck = rr / g.ny;
-            const int lx = ci - ox, ly = cj - oy, lz = ck - oz;
             const real rx = in.rx[ip], ry = in.ry[ip], rz = in.rz[ip];
             ux = in.ux[ip]; uy = in.uy[ip]; uz = in.uz[ip];
             w = in.w[ip];
@@ -356,9 +340,8 @@ k_push(GridP g, SpecP sp, PArr in, const int *__restrict__ cnt_in, PArr out,
                 // Esirkepov deposit of J^{n+1/2}
                 if (sp.q != (real)0) {
                     AxisS SX = axis_shapes(rx, X1), SY = axis_shapes(ry, Y1), SZ = axis_shapes(rz, Z1);
-                    real qw = sp.q * w / dv;
-                    esirkepov_lds(sJ, lx, ly, lz, SX, SY, SZ, qw * g.dx / g.dt, qw * g.dy / g.dt,
-                                  qw * g.dz / g.dt);
+                    const real qw = sp.q * w / dv;
+                    esirkepov_acc(sJ, lx, ly, lz, SX, SY, SZ, qw * cdx, qw * cdy, qw * cdz, inv_scale);
                 }
                 // new cell and offsets
                 int fx = X1 >= (real)1 ? 1 : (X1 < (real)0 ? -1 : 0);
@@ -376,35 +359,30 @@ k_push(GridP g, SpecP sp, PArr in, const int *__restrict__ cnt_in, PArr out,
                 ntile = (ni >> TLOG) + g.ntx * ((nj >> TLOG) + g.nty * (nk >> TLOG));
             }
         }
-        // slot reservation: one global atomic per wave and destination tile
-        // (lanes sharing a destination are ranked with ballot / popcount)
+        // ranks from LDS counters: one LDS atomic per wave for each class
         const bool stay = valid && ntile == t;
-        const uint64_t lt = (1ull << lane) - 1ull;
-        const uint64_t m = __ballot(stay);
-        int wbase = 0;
-        if (lane == 0 && m) wbase = atomicAdd(&cnt_out[t], __popcll(m));
-        wbase = __shfl(wbase, 0);
-        int slot = stay ? wbase + __popcll(m & lt) : 0;
-        uint64_t mv = __ballot(valid && !stay);
-        while (mv) {
-            const int leader = __ffsll((long long)mv) - 1;
-            const int dest = __shfl(ntile, leader);
-            const uint64_t grp = __ballot(valid && !stay && ntile == dest);
-            int b = 0;
-            if (lane == leader) b = atomicAdd(&cnt_out[dest], __popcll(grp));
-            b = __shfl(b, leader);
-            if ((grp >> lane) & 1ull) slot = b + __popcll(grp & lt);
-            mv &= ~grp;
+        const bool move = valid && ntile != t;
+        const uint64_t ms = __ballot(stay), mm = __ballot(move);
+        int bs = 0, bm = 0;
+        if (lane == 0) {
+            if (ms) bs = atomicAdd(&s_stay, __popcll(ms));
+            if (mm) bm = atomicAdd(&s_move, __popcll(mm));
         }
+        bs = __shfl(bs, 0);
+        bm = __shfl(bm, 0);
         if (valid) {
             PArr dst = out;
             long long j;
-            if (slot < sp.cap[ntile]) j = sp.off[ntile] + slot;
+            if (stay) j = obase + bs + __popcll(ms & lt);
             else {
-                int k = atomicAdd(inbox_n, 1);
-                if (k >= inbox_cap) { atomicOr(err, ERR_INBOX); continue; }
-                dst = inbox;
-                j = k;
+                const int k = bm + __popcll(mm & lt);
+                if (k < mlim) { dst = mig; j = mbase + k; }
+                else {
+                    const int q = atomicAdd(inbox_n, 1);
+                    if (q >= inbox_cap) { atomicOr(err, ERR_INBOX); continue; }
+                    dst = inbox;
+                    j = q;
+                }
             }
             dst.cell[j] = ncell;
             dst.rx[j] = nrx; dst.ry[j] = nry; dst.rz[j] = nrz;
@@ -416,6 +394,10 @@ k_push(GridP g, SpecP sp, PArr in, const int *__restrict__ cnt_in, PArr out,
         }
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        nf_out[t] = s_stay;          // stayers never exceed the bin: they were in it
+        mcnt[t] = min(s_move, mlim);
+    }
     // flush the LDS current tile (nodes ox-1 .. ox+TILE+1) to HBM
     for (int e = threadIdx.x; e < JT3; e += BS) {
         int a = e % JT, b = (e / JT) % JT, c = e / (JT * JT);
@@ -425,7 +407,8 @@ k_push(GridP g, SpecP sp, PArr in, const int *__restrict__ cnt_in, PArr out,
         if (per) { gi = wrapi(gi, g.nx); okx = okn = true; }
         else { okx = gi >= 0 && gi <= g.nx - 1; okn = gi >= 0 && gi <= g.nx; }
         long long c0 = gidx(g, gi < 0 ? 0 : gi, gj, gk);
-        real vx = sJ[e], vy = sJ[JT3 + e], vz = sJ[2 * JT3 + e];
+        real vx = (real)jval(sJ[e], jscale), vy = (real)jval(sJ[JT3 + e], jscale),
+             vz = (real)jval(sJ[2 * JT3 + e], jscale);
         if (okx && vx != (real)0) atomicAdd(&Jx[c0], vx);
         if (okn && vy != (real)0) atomicAdd(&Jy[c0], vy);
         if (okn && vz != (real)0) atomicAdd(&Jz[c0], vz);
@@ -434,7 +417,8 @@ k_push(GridP g, SpecP sp, PArr in, const int *__restrict__ cnt_in, PArr out,
 
 // --------------------------------------------------- immobile-ion ionization ---------------
 // ADK tunnelling blended with the multiphoton continuation by a sigmoid in the
-// Keldysh parameter; rates in FP64 (atomic units).
+// Keldysh parameter; rates in FP64 (atomic units).  active[t] counts the ions
+// of tile t below full ionization; tiles with none are skipped.
 __device__ inline double adk(const IonLevel &L, double F) {
     return L.c2 * L.ip_au * pow(2.0 * L.k3 / F, L.expo) * exp(-2.0 * L.k3 / (3.0 * F));
 }
@@ -447,15 +431,16 @@ __device__ inline double blended_rate(const IonLevel &L, double F, double omega)
 }
 
 __global__ void __launch_bounds__(BS)
-k_ionize_static(GridP g, SpecP sp, PArr a, const int *__restrict__ cnt, const real *__restrict__ Ex,
-                const real *__restrict__ Ey, const real *__restrict__ Ez,
-                const uint8_t *__restrict__ sw, int hybrid, const IonP *__restrict__ ion,
-                PArr eout, int *__restrict__ eout_n, int eout_cap, uint64_t seed, int step,
+k_ionize_static(GridP g, SpecP sp, PArr a, Bins bins, int *__restrict__ active,
+                const real *__restrict__ Ex, const real *__restrict__ Ey, const real *__restrict__ Ez,
+                const uint8_t *__restrict__ sw, int hybrid, const IonP *__restrict__ ion, PArr eout,
+                int *__restrict__ eout_n, int eout_cap, uint64_t seed, int step,
                 double *__restrict__ ledger, int *__restrict__ err) {
     __shared__ real sF[3 * FT3];
     const int t = blockIdx.x;
-    const int n = min(cnt[t], sp.cap[t]);
-    if (n <= 0) return;
+    int nf, nbv;
+    const int n = bin_count(sp, bins, t, nf, nbv);
+    if (n <= 0 || active[t] <= 0) return;
     const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
     const int per = g.bcx == HK_BC_PERIODIC;
@@ -474,10 +459,10 @@ k_ionize_static(GridP g, SpecP sp, PArr a, const int *__restrict__ cnt, const re
         sF[2 * FT3 + e] = Ez[gidx(g, in_, gj, gk)];
     }
     __syncthreads();
-    const long long base = sp.off[t];
     const double omega = ion->omega_au;
+    int done = 0;
     for (int p = threadIdx.x; p < n; p += BS) {
-        const long long ip = base + p;
+        const long long ip = bin_slot(sp, t, p, nf, nbv);
         int cell = a.cell[ip];
         if (cell < 0) continue;
         int zc = a.zc[ip];
@@ -520,20 +505,39 @@ k_ionize_static(GridP g, SpecP sp, PArr a, const int *__restrict__ cnt, const re
             eout.id[k] = (1ull << 62) | ((uint64_t)lev << 56) | pid;
             atomicAdd(ledger, (double)a.w[ip] * ion->lev[lev].ip_au * 27.211386245988 / 510998.95);
         }
-        if (zc != z0) a.zc[ip] = zc;
+        if (zc != z0) {
+            a.zc[ip] = zc;
+            if (zc >= ion->z_max) done++;
+        }
     }
+    if (done) atomicSub(&active[t], done);
+}
+
+// Ions below full ionization per tile.
+__global__ void __launch_bounds__(BS)
+k_count_active(GridP g, SpecP sp, PArr a, Bins bins, int zmax, int *__restrict__ active) {
+    const int t = blockIdx.x;
+    int nf, nbv;
+    const int n = bin_count(sp, bins, t, nf, nbv);
+    int c = 0;
+    for (int p = threadIdx.x; p < n; p += BS) {
+        const long long ip = bin_slot(sp, t, p, nf, nbv);
+        if (a.cell[ip] >= 0 && a.zc[ip] < zmax) c++;
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&active[t], c);
 }
 
 // ----------------------------------------------------------- charge density ---------------
 __global__ void __launch_bounds__(BS)
-k_rho(GridP g, SpecP sp, PArr a, const int *__restrict__ cnt, double *__restrict__ rho) {
+k_rho(GridP g, SpecP sp, PArr a, Bins bins, double *__restrict__ rho) {
     const int t = blockIdx.x;
-    const int n = min(cnt[t], sp.cap[t]);
-    const long long base = sp.off[t];
+    int nf, nbv;
+    const int n = bin_count(sp, bins, t, nf, nbv);
     const double dv = g.ddx * g.ddy * g.ddz;
     const int per = g.bcx == HK_BC_PERIODIC;
     for (int p = threadIdx.x; p < n; p += BS) {
-        const long long ip = base + p;
+        const long long ip = bin_slot(sp, t, p, nf, nbv);
         int cell = a.cell[ip];
         if (cell < 0) continue;
         const int ci = cell % g.nx, rr = cell / g.nx;
@@ -565,45 +569,66 @@ void launch_init_species_cols(const GridP &g, const hk_species_desc &d, uint64_t
                                         out, has_z, has_tau);
 }
 
-void launch_count_groups(const GridP &g, PArr src, const long long *off, const int *cnt,
-                         const int *cap, int ngroups, int *newcnt, hipStream_t s) {
-    if (ngroups == 0) return;
-    k_count<<<ngroups, BS, 0, s>>>(g, src, off, cnt, cap, newcnt);
+// maxn bounds the entries of the largest group (sets the grid's x extent)
+void launch_count_groups(const GridP &g, PArr src, const long long *off, const int *nf,
+                         const int *nb, const int *cap, int ngroups, long long maxn, int *newcnt,
+                         hipStream_t s) {
+    if (ngroups == 0 || maxn == 0) return;
+    unsigned bx = blocks(maxn);
+    if (bx > 4096u) bx = 4096u;
+    k_count<<<dim3(ngroups, bx), BS, 0, s>>>(g, src, off, nf, nb, cap, newcnt);
 }
 
-void launch_scatter_groups(const GridP &g, PArr src, const long long *off, const int *cnt,
-                           const int *cap, int ngroups, PArr dst, const long long *doff,
-                           int *dfill, int has_z, int has_tau, hipStream_t s) {
-    if (ngroups == 0) return;
-    k_scatter<<<ngroups, BS, 0, s>>>(g, src, off, cnt, cap, dst, doff, dfill, has_z, has_tau);
+void launch_scatter_groups(const GridP &g, PArr src, const long long *off, const int *nf,
+                           const int *nb, const int *cap, int ngroups, long long maxn, PArr dst,
+                           const long long *doff, int *dfill, int has_z, int has_tau,
+                           hipStream_t s) {
+    if (ngroups == 0 || maxn == 0) return;
+    unsigned bx = blocks(maxn);
+    if (bx > 4096u) bx = 4096u;
+    k_scatter<<<dim3(ngroups, bx), BS, 0, s>>>(g, src, off, nf, nb, cap, dst, doff, dfill, has_z,
+                                               has_tau);
 }
 
+// The fail list has the inbox's capacity (max_n).
 void launch_merge_inbox(const GridP &g, const SpecP &sp, PArr inbox, const int *inbox_n,
-                        long long max_n, PArr dst, int *cnt, int *fail_n, PArr fail,
-                        hipStream_t s) {
+                        long long max_n, PArr dst, const int *nf, int *nb, int *fail_n, PArr fail,
+                        int *err, hipStream_t s) {
     if (max_n == 0) return;
-    unsigned nb = blocks(max_n);
-    k_merge<<<nb < 1024u ? nb : 1024u, BS, 0, s>>>(g, sp, inbox, inbox_n, dst, cnt, fail_n, fail);
+    unsigned nb_ = blocks(max_n);
+    k_merge<<<nb_ < 1024u ? nb_ : 1024u, BS, 0, s>>>(g, sp, inbox, inbox_n, (int)max_n, dst, nf, nb,
+                                                     fail_n, fail, (int)max_n, err);
 }
 
-void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, const int *cnt_in, PArr out,
-                       int *cnt_out, PArr inbox, int *inbox_n, int inbox_cap, real *const f[9],
-                       int *err, hipStream_t s) {
-    k_push<<<g.ntiles, BS, 0, s>>>(g, sp, in, cnt_in, out, cnt_out, inbox, inbox_n, inbox_cap,
-                                   f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ],
-                                   f[HK_JX], f[HK_JY], f[HK_JZ], err);
+void launch_migrate(const GridP &g, const SpecP &sp, PArr mig, const long long *moff,
+                    const int *mcnt, PArr dst, const int *nf, int *nb, int *fail_n, PArr fail,
+                    int fail_cap, int *err, hipStream_t s) {
+    k_migrate<<<g.ntiles, BS, 0, s>>>(g, sp, mig, moff, mcnt, dst, nf, nb, fail_n, fail, fail_cap, err);
 }
 
-void launch_ionize_static(const GridP &g, const SpecP &sp, PArr a, const int *cnt,
+void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
+                       int *nf_out, PArr mig, const long long *moff, const int *mcap, int *mcnt,
+                       PArr inbox, int *inbox_n, int inbox_cap, real *const f[9], int *err,
+                       hipStream_t s) {
+    k_push<<<g.ntiles, BS, 0, s>>>(g, sp, in, bin_in, out, nf_out, mig, moff, mcap, mcnt, inbox,
+                                   inbox_n, inbox_cap, f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX],
+                                   f[HK_BY], f[HK_BZ], f[HK_JX], f[HK_JY], f[HK_JZ], err);
+}
+
+void launch_ionize_static(const GridP &g, const SpecP &sp, PArr a, Bins b, int *active,
                           real *const f[9], const uint8_t *sw, int hybrid, const IonP *ion,
                           PArr eout, int *eout_n, int eout_cap, uint64_t seed, int step,
                           double *ledger, int *err, hipStream_t s) {
-    k_ionize_static<<<g.ntiles, BS, 0, s>>>(g, sp, a, cnt, f[HK_EX], f[HK_EY], f[HK_EZ], sw,
-                                            hybrid, ion, eout, eout_n, eout_cap, seed, step,
-                                            ledger, err);
+    k_ionize_static<<<g.ntiles, BS, 0, s>>>(g, sp, a, b, active, f[HK_EX], f[HK_EY], f[HK_EZ], sw,
+                                            hybrid, ion, eout, eout_n, eout_cap, seed, step, ledger,
+                                            err);
 }
 
-void launch_rho_tiles(const GridP &g, const SpecP &sp, PArr a, const int *cnt, double *rho,
-                      hipStream_t s) {
-    k_rho<<<g.ntiles, BS, 0, s>>>(g, sp, a, cnt, rho);
+void launch_count_active(const GridP &g, const SpecP &sp, PArr a, Bins b, int zmax, int *active,
+                         hipStream_t s) {
+    k_count_active<<<g.ntiles, BS, 0, s>>>(g, sp, a, b, zmax, active);
+}
+
+void launch_rho_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, double *rho, hipStream_t s) {
+    k_rho<<<g.ntiles, BS, 0, s>>>(g, sp, a, b, rho);
 }

@@ -1,0 +1,466 @@
+// Regime switch and fluid <-> particle conversion for gfx950.
+//
+// Paper: abstract and Methodology (fluid in stable regions, PIC where the
+// switch flags kinetic behaviour; instability thresholds as prior knowledge,
+// Results after Table 1; charge and energy checks during regime switches,
+// validation paragraph).  The paper gives neither threshold values nor a
+// conversion rule; the definitions implemented here are:
+//   indicators per node from nearest-node moments of the fluid species
+//   (particles and fluid) and the node-interpolated E:
+//     |E|; density gradient beyond three standard deviations of its shot
+//     noise; momentum spread; ionization probability per step; quantum
+//     parameter estimate.  Kinetic if any reaches its threshold, dilated by
+//     `dilation` nodes; back to fluid after `hysteresis` calm evaluations.
+//   absorb: a fluid-species particle whose nearest node is fluid moves
+//     virtually to that node (Esirkepov current of the move) and joins the
+//     node fluid; spawn: enough fluid mass on a kinetic node becomes ppc
+//     particles that move virtually from the node to Philox positions in
+//     its dual cell.  A CIC particle on a node carries exactly the node
+//     charge of the fluid, so div E - rho is unchanged by both.
+#include "hk_internal.h"
+#include "hk_pic_device.h"
+
+namespace {
+
+using namespace hkdev;
+constexpr int BS = 256;
+constexpr int NT = TILE + 1;          // node tile edge: nearest nodes 0 .. TILE
+constexpr int NT3 = NT * NT * NT;
+
+__device__ inline void decompose(const GridP &g, long long c, int &i, int &j, int &k) {
+    i = (int)(c % g.sx);
+    long long r = c / g.sx;
+    j = (int)(r % g.ny);
+    k = (int)(r / g.ny);
+}
+
+// Nearest node of a particle (cell + offset), wrapped in periodic directions.
+__device__ inline long long nearest_node(const GridP &g, int ci, int cj, int ck, real rx, real ry,
+                                         real rz, int &di, int &dj, int &dk) {
+    di = rx >= (real)0.5; dj = ry >= (real)0.5; dk = rz >= (real)0.5;
+    int i = ci + di, j = cj + dj, k = ck + dk;
+    if (g.bcx == HK_BC_PERIODIC && i == g.nx) i = 0;
+    if (j == g.ny) j = 0;
+    if (k == g.nz) k = 0;
+    return gidx(g, i, j, k);
+}
+
+// ---------------------------------------------------------------- moments -----------------
+// mom layout (7 grid arrays): N = sum w, V = sum w^2, P (3), U2 = sum w |u|^2, NI.
+__global__ void __launch_bounds__(BS)
+k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__restrict__ mom) {
+    __shared__ real sm[6 * NT3];
+    const int t = blockIdx.x;
+    int nf, nbv;
+    const int n = bin_count(sp, bins, t, nf, nbv);
+    if (n <= 0) return;
+    for (int e = threadIdx.x; e < 6 * NT3; e += BS) sm[e] = 0;
+    __syncthreads();
+    const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
+    const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
+    for (int p = threadIdx.x; p < n; p += BS) {
+        const long long ip = bin_slot(sp, t, p, nf, nbv);
+        int cell = a.cell[ip];
+        if (cell < 0) continue;
+        const int ci = cell % g.nx, rr = cell / g.nx;
+        const int cj = rr % g.ny, ck = rr / g.ny;
+        const int lx = ci - ox + (a.rx[ip] >= (real)0.5), ly = cj - oy + (a.ry[ip] >= (real)0.5),
+                  lz = ck - oz + (a.rz[ip] >= (real)0.5);
+        if ((unsigned)lx > TILE || (unsigned)ly > TILE || (unsigned)lz > TILE) continue;
+        const int e = lx + NT * (ly + NT * lz);
+        real w = a.w[ip];
+        if (ion_only) {
+            if (a.zc[ip] < zmax) atomicAdd(&sm[e], w);
+            continue;
+        }
+        real ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip];
+        atomicAdd(&sm[e], w);
+        atomicAdd(&sm[NT3 + e], w * w);
+        atomicAdd(&sm[2 * NT3 + e], w * ux);
+        atomicAdd(&sm[3 * NT3 + e], w * uy);
+        atomicAdd(&sm[4 * NT3 + e], w * uz);
+        atomicAdd(&sm[5 * NT3 + e], w * (ux * ux + uy * uy + uz * uz));
+    }
+    __syncthreads();
+    const int per = g.bcx == HK_BC_PERIODIC;
+    for (int e = threadIdx.x; e < NT3; e += BS) {
+        int aa = e % NT, b = (e / NT) % NT, c = e / (NT * NT);
+        int gi = ox + aa, gj = wrapi(oy + b, g.ny), gk = wrapi(oz + c, g.nz);
+        if (per) gi = wrapi(gi, g.nx);
+        else if (gi > g.nx) continue;
+        long long node = gidx(g, gi, gj, gk);
+        if (ion_only) {
+            if (sm[e] != (real)0) atomicAdd(&mom[6 * g.nn + node], sm[e]);
+            continue;
+        }
+        for (int q = 0; q < 6; ++q)
+            if (sm[q * NT3 + e] != (real)0) atomicAdd(&mom[q * g.nn + node], sm[q * NT3 + e]);
+    }
+}
+
+__global__ void __launch_bounds__(BS)
+k_fluid_moments(GridP g, real inv_ppc, const real *__restrict__ n, const real *__restrict__ ux,
+                const real *__restrict__ uy, const real *__restrict__ uz, real *__restrict__ mom) {
+    long long c = (long long)blockIdx.x * BS + threadIdx.x;
+    if (c >= g.nn) return;
+    real m = n[c] * (g.dx * g.dy * g.dz);
+    if (!(m > (real)0)) return;
+    real a = ux[c], b = uy[c], d = uz[c];
+    const long long nn = g.nn;
+    mom[c] += m;
+    mom[nn + c] += m * m * inv_ppc;
+    mom[2 * nn + c] += m * a;
+    mom[3 * nn + c] += m * b;
+    mom[4 * nn + c] += m * d;
+    mom[5 * nn + c] += m * (a * a + b * b + d * d);
+}
+
+// ------------------------------------------------------------- indicators -----------------
+__device__ inline real node_field(const GridP &g, const real *F, int i, int j, int k, int hx, int hy,
+                                  int hz) {
+    const int per = g.bcx == HK_BC_PERIODIC;
+    int i0 = hx ? i - 1 : i, j0 = hy ? j - 1 : j, k0 = hz ? k - 1 : k;
+    real acc = 0;
+    for (int c = 0; c < (hz ? 2 : 1); ++c)
+        for (int b = 0; b < (hy ? 2 : 1); ++b)
+            for (int a = 0; a < (hx ? 2 : 1); ++a) {
+                int ii = i0 + a;
+                if (per) ii = wrapi(ii, g.nx);
+                else if (hx) ii = ii < 0 ? 0 : (ii > g.nx - 1 ? g.nx - 1 : ii);
+                real wgt = (hx ? (real)0.5 : (real)1) * (hy ? (real)0.5 : (real)1) * (hz ? (real)0.5 : (real)1);
+                acc += wgt * F[gidx(g, ii, wrapi(j0 + b, g.ny), wrapi(k0 + c, g.nz))];
+            }
+    return acc;
+}
+
+__device__ inline double adk_rate(const IonLevel &L, double F) {
+    return L.c2 * L.ip_au * pow(2.0 * L.k3 / F, L.expo) * exp(-2.0 * L.k3 / (3.0 * F));
+}
+__device__ inline double ion_rate(const IonP *ion, int lev, double F) {
+    if (F <= 0.0) return 0.0;
+    const IonLevel &L = ion->lev[lev];
+    double gk = ion->omega_au * sqrt(2.0 * L.ip_au) / F;
+    double sig = 1.0 / (1.0 + exp(-(gk - 1.5) / 0.1));
+    double wm = L.wfc * pow(fmin(F, L.fc) / L.fc, L.K2);
+    return (sig * wm + (1.0 - sig) * adk_rate(L, F)) * ion->rate_norm;
+}
+
+struct IonSet {
+    const IonP *p[4];
+    int n;
+};
+
+__global__ void __launch_bounds__(BS)
+k_indicators(GridP g, SwitchP P, const real *__restrict__ mom, const real *__restrict__ Ex,
+             const real *__restrict__ Ey, const real *__restrict__ Ez, IonSet ions,
+             uint8_t *__restrict__ hot, uint8_t *__restrict__ notcold) {
+    long long c = (long long)blockIdx.x * BS + threadIdx.x;
+    if (c >= g.nn) return;
+    int i, j, k;
+    decompose(g, c, i, j, k);
+    const int per = g.bcx == HK_BC_PERIODIC;
+    const int nxn = per ? g.nx : g.nx + 1;
+    if (i >= nxn) { hot[c] = 0; notcold[c] = 0; return; }
+    const long long nn = g.nn;
+    const real dv = g.dx * g.dy * g.dz;
+    real ex = node_field(g, Ex, i, j, k, 1, 0, 0), ey = node_field(g, Ey, i, j, k, 0, 1, 0);
+    real ez = node_field(g, Ez, i, j, k, 0, 0, 1);
+    real emag = sqrt(ex * ex + ey * ey + ez * ez);
+    auto cx = [&](int ii) { return per ? wrapi(ii, g.nx) : (ii < 0 ? 0 : (ii > g.nx ? g.nx : ii)); };
+    long long xp = gidx(g, cx(i + 1), j, k), xm = gidx(g, cx(i - 1), j, k);
+    long long yp = gidx(g, i, wrapi(j + 1, g.ny), k), ym = gidx(g, i, wrapi(j - 1, g.ny), k);
+    long long zp = gidx(g, i, j, wrapi(k + 1, g.nz)), zm = gidx(g, i, j, wrapi(k - 1, g.nz));
+    const real *N = mom, *V = mom + nn;
+    real dgx = N[xp] - N[xm], dgy = N[yp] - N[ym], dgz = N[zp] - N[zm];
+    real den = 2 * fmax(N[c], P.n_floor * dv);
+    real grad = sqrt(dgx * dgx + dgy * dgy + dgz * dgz) / den;
+    real sig = sqrt(V[xp] + V[xm] + V[yp] + V[ym] + V[zp] + V[zm]) / den;
+    grad = grad - 3 * sig;
+    real su = 0, g2 = 0;
+    real Nc = N[c];
+    if (Nc > 0) {
+        real m2 = mom[5 * nn + c] / Nc;
+        real mx = mom[2 * nn + c] / Nc, my = mom[3 * nn + c] / Nc, mz = mom[4 * nn + c] / Nc;
+        su = sqrt(fmax((real)0, m2 - (mx * mx + my * my + mz * mz)));
+        g2 = m2;
+    }
+    real NI = mom[6 * nn + c];
+    double ionr = 0.0;
+    if (NI > 0)
+        for (int s = 0; s < ions.n; ++s)
+            ionr = fmax(ionr, ion_rate(ions.p[s], 0, (double)emag * ions.p[s]->field_au) * g.ddt);
+    double chi = P.enable_qed ? sqrt(1.0 + (double)g2) * (double)emag / P.a_s : 0.0;
+    bool h = emag >= P.thr_a || grad >= P.thr_grad || su >= P.thr_su ||
+             (NI > 0 && ionr >= (double)P.thr_ion) || (P.enable_qed && chi >= (double)P.thr_chi);
+    bool nc = emag >= (real)0.5 * P.thr_a || grad >= (real)0.5 * P.thr_grad ||
+              su >= (real)0.5 * P.thr_su || (NI > 0 && ionr >= 0.5 * (double)P.thr_ion) ||
+              (P.enable_qed && chi >= 0.5 * (double)P.thr_chi);
+    hot[c] = h;
+    notcold[c] = nc;
+}
+
+__global__ void __launch_bounds__(BS)
+k_dilate(GridP g, SwitchP P, const uint8_t *__restrict__ hot, const uint8_t *__restrict__ notcold,
+         uint8_t *__restrict__ sw, uint8_t *__restrict__ calm) {
+    long long c = (long long)blockIdx.x * BS + threadIdx.x;
+    if (c >= g.nn) return;
+    int i, j, k;
+    decompose(g, c, i, j, k);
+    const int per = g.bcx == HK_BC_PERIODIC;
+    const int nxn = per ? g.nx : g.nx + 1;
+    if (i >= nxn) return;
+    const int D = P.dilation;
+    int kin = 0, warm = 0;
+    for (int dk = -D; dk <= D; ++dk)
+        for (int dj = -D; dj <= D; ++dj)
+            for (int di = -D; di <= D; ++di) {
+                int ii = i + di;
+                if (!per && (ii < 0 || ii > g.nx)) continue;
+                if (per) ii = wrapi(ii, g.nx);
+                long long q = gidx(g, ii, wrapi(j + dj, g.ny), wrapi(k + dk, g.nz));
+                kin |= hot[q];
+                warm |= notcold[q];
+            }
+    if (kin) { sw[c] = 1; calm[c] = 0; }
+    else if (sw[c]) {
+        if (warm) calm[c] = 0;
+        else {
+            int cc = calm[c] + 1;
+            if (cc >= P.hysteresis) { sw[c] = 0; calm[c] = 0; }
+            else calm[c] = (uint8_t)cc;
+        }
+    }
+}
+
+// --------------------------------------------------------------- conversion ---------------
+// Esirkepov current of a move, added straight to HBM (used by spawns).
+__device__ inline void esirkepov_global(const GridP &g, real *Jx, real *Jy, real *Jz, int ci, int cj,
+                                        int ck, const AxisS &X, const AxisS &Y, const AxisS &Z,
+                                        real cx, real cy, real cz) {
+    const real third = (real)(1.0 / 3.0), half = (real)0.5;
+    const int per = g.bcx == HK_BC_PERIODIC;
+    for (int c = 0; c < 3; ++c)
+        for (int b = 0; b < 3; ++b)
+            for (int a = 0; a < 3; ++a) {
+                int i = ci + X.base + a;
+                int j = wrapi(cj + Y.base + b, g.ny), k = wrapi(ck + Z.base + c, g.nz);
+                int ii = per ? wrapi(i, g.nx) : i;
+                bool okx = per || (ii >= 0 && ii < g.nx), okn = per || (ii >= 0 && ii <= g.nx);
+                long long q = gidx(g, ii < 0 ? 0 : ii, j, k);
+                if (a < 2 && okx) {
+                    real acc = 0;
+                    for (int a2 = 0; a2 <= a; ++a2)
+                        acc -= cx * (X.DS[a2] * (Y.S0[b] * Z.S0[c] + half * Y.DS[b] * Z.S0[c] +
+                                                 half * Y.S0[b] * Z.DS[c] + third * Y.DS[b] * Z.DS[c]));
+                    if (acc != (real)0) atomicAdd(&Jx[q], acc);
+                }
+                if (b < 2 && okn) {
+                    real acc = 0;
+                    for (int b2 = 0; b2 <= b; ++b2)
+                        acc -= cy * (Y.DS[b2] * (X.S0[a] * Z.S0[c] + half * X.DS[a] * Z.S0[c] +
+                                                 half * X.S0[a] * Z.DS[c] + third * X.DS[a] * Z.DS[c]));
+                    if (acc != (real)0) atomicAdd(&Jy[q], acc);
+                }
+                if (c < 2 && okn) {
+                    real acc = 0;
+                    for (int c2 = 0; c2 <= c; ++c2)
+                        acc -= cz * (Z.DS[c2] * (X.S0[a] * Y.S0[b] + half * X.DS[a] * Y.S0[b] +
+                                                 half * X.S0[a] * Y.DS[b] + third * X.DS[a] * Y.DS[b]));
+                    if (acc != (real)0) atomicAdd(&Jz[q], acc);
+                }
+            }
+}
+
+__device__ inline void block_add_d(double v, double *out) {
+    __shared__ double red[BS / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0;
+        for (int i = 0; i < BS / 64; ++i) s += red[i];
+        if (s != 0.0) atomicAdd(out, s);
+    }
+    __syncthreads();
+}
+
+// macc layout (4 grid arrays, FP64): M = sum w, P (3) = sum w u.
+__global__ void __launch_bounds__(BS)
+k_absorb(GridP g, SpecP sp, PArr a, Bins bins, const uint8_t *__restrict__ sw,
+         real *__restrict__ Jx, real *__restrict__ Jy, real *__restrict__ Jz, double *__restrict__ macc,
+         double *__restrict__ ledger) {
+    __shared__ real sJ[3 * JT3];
+    __shared__ int any;
+    const int t = blockIdx.x;
+    int nf, nbv;
+    const int n = bin_count(sp, bins, t, nf, nbv);
+    if (n <= 0) return;
+    for (int e = threadIdx.x; e < 3 * JT3; e += BS) sJ[e] = 0;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
+    const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
+    const real dv = g.dx * g.dy * g.dz;
+    const long long nn = g.nn;
+    double ke = 0;
+    for (int p = threadIdx.x; p < n; p += BS) {
+        const long long ip = bin_slot(sp, t, p, nf, nbv);
+        int cell = a.cell[ip];
+        if (cell < 0) continue;
+        const int ci = cell % g.nx, rr = cell / g.nx;
+        const int cj = rr % g.ny, ck = rr / g.ny;
+        const real rx = a.rx[ip], ry = a.ry[ip], rz = a.rz[ip];
+        int di, dj, dk;
+        long long node = nearest_node(g, ci, cj, ck, rx, ry, rz, di, dj, dk);
+        if (sw[node]) continue;
+        const int lx = ci - ox, ly = cj - oy, lz = ck - oz;
+        if ((unsigned)lx >= TILE || (unsigned)ly >= TILE || (unsigned)lz >= TILE) continue;
+        const real w = a.w[ip];
+        AxisS SX = axis_shapes(rx, (real)di), SY = axis_shapes(ry, (real)dj), SZ = axis_shapes(rz, (real)dk);
+        real qw = sp.q * w / dv;
+        esirkepov_lds(sJ, lx, ly, lz, SX, SY, SZ, qw * g.dx / g.dt, qw * g.dy / g.dt, qw * g.dz / g.dt);
+        any = 1;
+        double ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip];
+        ke += (double)w * (double)sp.m * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
+        atomicAdd(&macc[node], (double)w);
+        atomicAdd(&macc[nn + node], (double)w * ux);
+        atomicAdd(&macc[2 * nn + node], (double)w * uy);
+        atomicAdd(&macc[3 * nn + node], (double)w * uz);
+        a.cell[ip] = -1;
+    }
+    block_add_d(ke, ledger);
+    if (!any) return;
+    const int per = g.bcx == HK_BC_PERIODIC;
+    for (int e = threadIdx.x; e < JT3; e += BS) {
+        int aa = e % JT, b = (e / JT) % JT, c = e / (JT * JT);
+        int gi = ox - 1 + aa;
+        int gj = wrapi(oy - 1 + b, g.ny), gk = wrapi(oz - 1 + c, g.nz);
+        bool okx, okn;
+        if (per) { gi = wrapi(gi, g.nx); okx = okn = true; }
+        else { okx = gi >= 0 && gi <= g.nx - 1; okn = gi >= 0 && gi <= g.nx; }
+        long long c0 = gidx(g, gi < 0 ? 0 : gi, gj, gk);
+        real vx = sJ[e], vy = sJ[JT3 + e], vz = sJ[2 * JT3 + e];
+        if (okx && vx != (real)0) atomicAdd(&Jx[c0], vx);
+        if (okn && vy != (real)0) atomicAdd(&Jy[c0], vy);
+        if (okn && vz != (real)0) atomicAdd(&Jz[c0], vz);
+    }
+}
+
+__global__ void __launch_bounds__(BS)
+k_absorb_finish(GridP g, real mass, double *__restrict__ macc, real *__restrict__ n,
+                real *__restrict__ ux, real *__restrict__ uy, real *__restrict__ uz,
+                double *__restrict__ ledger) {
+    long long c = (long long)blockIdx.x * BS + threadIdx.x;
+    double d = 0;
+    if (c < g.nn && macc[c] > 0.0) {
+        const long long nn = g.nn;
+        const double dv = g.ddx * g.ddy * g.ddz;
+        double m0 = (double)n[c] * dv;
+        double u0[3] = {ux[c], uy[c], uz[c]};
+        double g0 = sqrt(1.0 + u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2]);
+        double mt = m0 + macc[c];
+        double un[3];
+        for (int q = 0; q < 3; ++q) un[q] = (m0 * u0[q] + macc[(1 + q) * nn + c]) / mt;
+        double gn = sqrt(1.0 + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
+        d = m0 * (double)mass * (g0 - 1.0) - mt * (double)mass * (gn - 1.0);
+        n[c] = (real)(mt / dv);
+        ux[c] = (real)un[0]; uy[c] = (real)un[1]; uz[c] = (real)un[2];
+        for (int q = 0; q < 4; ++q) macc[q * nn + c] = 0.0;
+    }
+    block_add_d(d, ledger);
+}
+
+__global__ void __launch_bounds__(BS)
+k_spawn(GridP g, SpecP sp, const uint8_t *__restrict__ sw, real *__restrict__ n, real *__restrict__ ux,
+        real *__restrict__ uy, real *__restrict__ uz, real *__restrict__ Jx, real *__restrict__ Jy,
+        real *__restrict__ Jz, real wmin, int m, uint64_t seed, int step, PArr inbox,
+        int *__restrict__ inbox_n, int inbox_cap, int *__restrict__ deferred) {
+    long long c = (long long)blockIdx.x * BS + threadIdx.x;
+    if (c >= g.nn) return;
+    int i, j, k;
+    decompose(g, c, i, j, k);
+    const int per = g.bcx == HK_BC_PERIODIC;
+    const int nxn = per ? g.nx : g.nx + 1;
+    if (i >= nxn || !sw[c]) return;
+    const real nc = n[c];
+    if (!(nc > (real)0)) return;
+    const real dv = g.dx * g.dy * g.dz;
+    const real mass = nc * dv;
+    if (mass < wmin) return;
+    int k0 = atomicAdd(inbox_n, m);
+    if (k0 + m > inbox_cap) {
+        // no room this step: the node stays fluid; void the reserved slots
+        for (int q = k0; q < inbox_cap && q < k0 + m; ++q) inbox.cell[q] = -1;
+        atomicAdd(deferred, 1);
+        return;
+    }
+    const real w = mass / (real)m;
+    const real u[3] = {ux[c], uy[c], uz[c]};
+    const uint64_t node = (uint64_t)i + (uint64_t)nxn * ((uint64_t)j + (uint64_t)g.ny * k);
+    const real qw = sp.q * w / dv;
+    for (int q = 0; q < m; ++q) {
+        uint32_t r[4];
+        draw4(seed, node, (uint32_t)step, TAG_CONV, (uint32_t)q, r);
+        real X1[3] = {u01(r[0]) - (real)0.5, u01(r[1]) - (real)0.5, u01(r[2]) - (real)0.5};
+        if (!per && ((i == 0 && X1[0] < (real)0) || (i == g.nx && X1[0] >= (real)0))) X1[0] = -X1[0];
+        AxisS SX = axis_shapes((real)0, X1[0]), SY = axis_shapes((real)0, X1[1]),
+              SZ = axis_shapes((real)0, X1[2]);
+        esirkepov_global(g, Jx, Jy, Jz, i, j, k, SX, SY, SZ, qw * g.dx / g.dt, qw * g.dy / g.dt,
+                         qw * g.dz / g.dt);
+        int cc[3] = {i, j, k};
+        for (int d = 0; d < 3; ++d)
+            if (X1[d] < (real)0) { cc[d] -= 1; X1[d] += (real)1; }
+        if (per) cc[0] = wrapi(cc[0], g.nx);
+        cc[1] = wrapi(cc[1], g.ny);
+        cc[2] = wrapi(cc[2], g.nz);
+        const long long s = k0 + q;
+        inbox.cell[s] = cc[0] + g.nx * (cc[1] + g.ny * cc[2]);
+        inbox.rx[s] = X1[0]; inbox.ry[s] = X1[1]; inbox.rz[s] = X1[2];
+        inbox.ux[s] = u[0]; inbox.uy[s] = u[1]; inbox.uz[s] = u[2];
+        inbox.w[s] = w;
+        inbox.id[s] = (1ull << 63) | ((uint64_t)step << 40) | (node << 6) | (uint64_t)q;
+        if (sp.has_z) inbox.zc[s] = (int)sp.q;
+        if (sp.has_tau) inbox.tau[s] = 0.0;
+    }
+    n[c] = 0; ux[c] = 0; uy[c] = 0; uz[c] = 0;
+}
+
+inline unsigned blocks(long long n) { return (unsigned)((n + BS - 1) / BS); }
+
+}  // namespace
+
+void launch_moments_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, int ion_only,
+                          int zmax, real *mom, hipStream_t s) {
+    k_moments<<<g.ntiles, BS, 0, s>>>(g, sp, a, b, ion_only, zmax, mom);
+}
+void launch_fluid_moments_nodes(const GridP &g, real inv_ppc, const real *n, const real *ux,
+                                const real *uy, const real *uz, real *mom, hipStream_t s) {
+    k_fluid_moments<<<blocks(g.nn), BS, 0, s>>>(g, inv_ppc, n, ux, uy, uz, mom);
+}
+void launch_indicators_nodes(const GridP &g, const SwitchP &P, const real *mom, real *const f[9],
+                             const IonP *const *ions, int nion, uint8_t *hot, uint8_t *notcold,
+                             hipStream_t s) {
+    IonSet set{};
+    set.n = nion < 4 ? nion : 4;
+    for (int q = 0; q < set.n; ++q) set.p[q] = ions[q];
+    k_indicators<<<blocks(g.nn), BS, 0, s>>>(g, P, mom, f[HK_EX], f[HK_EY], f[HK_EZ], set, hot, notcold);
+}
+void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, const uint8_t *notcold,
+                         uint8_t *sw, uint8_t *calm, hipStream_t s) {
+    k_dilate<<<blocks(g.nn), BS, 0, s>>>(g, P, hot, notcold, sw, calm);
+}
+void launch_absorb_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, const uint8_t *sw,
+                         real *const f[9], double *macc, double *ledger, hipStream_t s) {
+    k_absorb<<<g.ntiles, BS, 0, s>>>(g, sp, a, b, sw, f[HK_JX], f[HK_JY], f[HK_JZ], macc, ledger);
+}
+void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n, real *ux,
+                                real *uy, real *uz, double *ledger, hipStream_t s) {
+    k_absorb_finish<<<blocks(g.nn), BS, 0, s>>>(g, mass, macc, n, ux, uy, uz, ledger);
+}
+void launch_spawn_nodes(const GridP &g, const SpecP &sp, const uint8_t *sw, real *n, real *ux,
+                        real *uy, real *uz, real *const f[9], real wmin, int m, uint64_t seed,
+                        int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
+                        hipStream_t s) {
+    k_spawn<<<blocks(g.nn), BS, 0, s>>>(g, sp, sw, n, ux, uy, uz, f[HK_JX], f[HK_JY], f[HK_JZ], wmin,
+                                        m, seed, step, inbox, inbox_n, inbox_cap, deferred);
+}

@@ -1,0 +1,168 @@
+"""GPU parity of the hybrid parts (cold fluid, threshold switch, fluid <->
+particle conversion) and of field ionization, against the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2510_11174_amd import configs
+from tests.parity import field_errors, match_particles, particle_errors, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2510_11174_amd import hk as hkmod
+    return hkmod
+
+
+def _pair(hk, oracle_mod, cfg, prec):
+    print("case:", cfg.get("name"), cfg["run"]["switch_mode"], prec, flush=True)
+    return hk.Sim(cfg, precision=prec), oracle_mod.Oracle(cfg)
+
+
+def _dx(cfg):
+    g = cfg["grid"]
+    return [g["dx"], g["dy"], g["dz"]]
+
+
+def _box(cfg):
+    g = cfg["grid"]
+    return [g["nx"] * g["dx"], g["ny"] * g["dy"], g["nz"] * g["dz"]]
+
+
+def _fluid_err(g, o, sp=0):
+    ng, ug = g.get_fluid(sp)
+    no, uo = o.get_fluid(sp)
+    return rel_l2(ng, no), rel_l2(ug, uo)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_all_fluid_steps(hk, oracle_mod, prec):
+    # absorb everything at step 0, then the cold fluid alone with the laser
+    cfg = configs.plain_hybrid(16, 8, 8, mode="all_fluid")
+    cfg["species"][0]["u_th"] = 0.05
+    g, o = _pair(hk, oracle_mod, cfg, prec)
+    g.step(1); o.step(1)
+    assert g.count(0) == 0 and o.count(0) == 0
+    en, eu = _fluid_err(g, o)
+    errs = field_errors(g, o)
+    print("after absorb: n %.1e u %.1e" % (en, eu), {k: "%.1e" % v for k, v in errs.items()})
+    tol = 1e-5 if prec == "f32" else 1e-12
+    assert en <= tol and eu <= tol and max(errs.values()) <= tol
+    g.step(30); o.step(30)
+    en, eu = _fluid_err(g, o)
+    errs = field_errors(g, o, ["ex", "ey", "ez", "bx", "by", "bz"])
+    print("31 steps: n %.1e u %.1e" % (en, eu), {k: "%.1e" % v for k, v in errs.items()})
+    tol = 1e-4 if prec == "f32" else 1e-11
+    assert en <= tol and eu <= tol and max(errs.values()) <= tol
+    d = g.diagnostics()
+    assert d["gauss_max"] <= (1e-6 if prec == "f32" else 1e-13)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_fixed_map_conversions(hk, oracle_mod, prec):
+    # half kinetic, then a shifted half: both conversions, Gauss unchanged
+    cfg = configs.plain_hybrid(16, 8, 8, mode="fixed")
+    cfg["species"][0]["u_th"] = 0.1
+    cfg["laser"]["enabled"] = False
+    g, o = _pair(hk, oracle_mod, cfg, prec)
+    m = np.zeros(o.shape, np.uint8); m[:, :, :8] = 1
+    g.set_switch(m); o.set_switch(m)
+    g.step(3); o.step(3)
+    m2 = np.zeros(o.shape, np.uint8); m2[:, :, 5:14] = 1
+    g.set_switch(m2); o.set_switch(m2)
+    g.step(3); o.step(3)
+    pg, po = g.get_particles(0), o.get_particles(0)
+    pos, mom, w = particle_errors(pg, po, _dx(cfg), _box(cfg))
+    en, eu = _fluid_err(g, o)
+    errs = field_errors(g, o)
+    print("pos %.1e mom %.1e w %.1e n %.1e u %.1e" % (pos, mom, w, en, eu),
+          {k: "%.1e" % v for k, v in errs.items()})
+    tol = 1e-5 if prec == "f32" else 1e-12
+    assert pos <= tol and mom <= tol and w <= tol
+    assert en <= 10 * tol and eu <= 10 * tol and max(errs.values()) <= 10 * tol
+    dg, do = g.diagnostics(), o.diagnostics()
+    assert dg["gauss_max"] <= (1e-6 if prec == "f32" else 1e-13)
+    assert abs(dg["conv_loss"] - do["conv_loss"]) <= (1e-5 if prec == "f32" else 1e-12) * abs(do["conv_loss"]) + 1e-18
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_threshold_hybrid_plain(hk, oracle_mod, prec):
+    # the plain-plasma workload under the threshold switch: maps, fluid, fields
+    cfg = configs.plain_hybrid(32, 16, 16, mode="threshold")
+    g, o = _pair(hk, oracle_mod, cfg, prec)
+    for n in range(0, 80, 20):
+        g.step(20); o.step(20)
+        mg, mo = g.get_switch(), o.get_switch()
+        frac = (mg != mo).mean()
+        print("step %d kinetic %.3f / %.3f mismatch %.2e" % (n + 20, mg.mean(), mo.mean(), frac))
+        assert frac <= (1e-3 if prec == "f32" else 0.0)
+    errs = field_errors(g, o, ["ex", "ey", "ez", "bx", "by", "bz"])
+    vec = {f: rel_l2(np.stack([g.get_field(f + c) for c in "xyz"]),
+                     np.stack([o.get_field(f + c) for c in "xyz"])) for f in "eb"}
+    print({k: "%.1e" % v for k, v in errs.items()}, vec)
+    assert max(vec.values()) <= (1e-3 if prec == "f32" else 1e-10)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("mode", ["all_pic", "threshold"])
+def test_ionization_events(hk, oracle_mod, prec, mode):
+    # ionizing helium (a0 = 10): which atoms ionize, and to which level, is
+    # compared atom by atom through the shared Philox counters
+    cfg = configs.ionization_hybrid(32, 16, 16, mode=mode, ppc=4)
+    g, o = _pair(hk, oracle_mod, cfg, prec)
+    g.step(60); o.step(60)
+    ig, io = g.get_particles(1), o.get_particles(1)
+    a, b = match_particles(ig, io)
+    zdiff = int((ig["z"][a] != io["z"][b]).sum())
+    n = len(a)
+    print("atoms %d ionized gpu %d oracle %d level mismatches %d electrons %d / %d" % (
+        n, (ig["z"] > 0).sum(), (io["z"] > 0).sum(), zdiff, g.count(0), o.count(0)))
+    assert (io["z"] > 0).sum() > 0.1 * n
+    # near-threshold draws may resolve differently in FP32 (|r - P| ~ 1e-6 P)
+    assert zdiff <= (max(2, 1e-4 * n) if prec == "f32" else 0)
+    if prec == "f64":
+        eg, eo = g.get_particles(0), o.get_particles(0)
+        pos, mom, w = particle_errors(eg, eo, _dx(cfg), _box(cfg))
+        assert pos <= 1e-10 and mom <= 1e-10
+    dg, do = g.diagnostics(), o.diagnostics()
+    assert abs(dg["ion_energy"] - do["ion_energy"]) <= 1e-3 * do["ion_energy"]
+
+
+@pytest.mark.parametrize("mode", ["all_pic", "all_fluid"])
+def test_plasma_oscillation_gpu(hk, mode):
+    # k = 0 drift mode: omega_num = (2/dt) asin(omega_p dt / 2) on the GPU
+    cfg = configs.plain_hybrid(8, 8, 8, mode=mode)
+    cfg["grid"]["bc_x"] = "periodic"
+    cfg["species"][0]["u_th"] = 0.0
+    cfg["laser"]["enabled"] = False
+    g = hk.Sim(cfg, precision="f64")
+    dt = cfg["grid"]["dt"]; d = cfg["grid"]["dx"]; amp = 1e-3
+    if mode == "all_pic":
+        off = np.array([0.25, 0.75])
+        cells = np.stack(np.meshgrid(*[np.arange(8)] * 3, indexing="ij"), -1).reshape(-1, 3)
+        subs = np.stack(np.meshgrid(off, off, off, indexing="ij"), -1).reshape(-1, 3)
+        x = (cells[:, None, :] + subs[None]).reshape(-1, 3) * d
+        u = np.zeros_like(x); u[:, 1] = amp
+        g.set_particles(0, x, u, np.full(len(x), 0.01 * d ** 3 / 8))
+    else:
+        g.step(1)
+        n, u = g.get_fluid(0)
+        n[..., :8] = 0.01; u[...] = 0; u[..., 1] = amp
+        g.set_fluid(0, n, u)
+        for c in ("ex", "ey", "ez", "bx", "by", "bz"):
+            g.set_field(c, np.zeros(g.shape))
+    wnum = 2 / dt * math.asin(0.1 * dt / 2)
+    ey = []
+    for _ in range(300):
+        g.step(1)
+        ey.append(g.get_field("ey")[0, 0, 0])
+    t = np.arange(1, 301) * dt
+    A = np.stack([np.sin(wnum * t), np.cos(wnum * t)], 1)
+    coef, *_ = np.linalg.lstsq(A, np.array(ey), rcond=None)
+    assert np.abs(A @ coef - ey).max() < 1e-5 * np.abs(ey).max()
