@@ -203,10 +203,14 @@ int hk_set_particles(hk_sim *sim, int species, const hk_particles *in);
 int hk_get_fluid(hk_sim *sim, int species, double *n, double *u, size_t nodes);
 int hk_set_fluid(hk_sim *sim, int species, const double *n, const double *u, size_t nodes);
 
-/* Accumulated device time per kernel group (ms): 0 switch, 1 particles,
- * 2 fluid, 3 conversion, 4 fields, 5 sort/merge, 6 other; slot 7 counts the
- * particle re-binnings since creation.  Timing is collected only when enabled
- * (it adds events around each group). */
+/* Timers since the last hk_enable_timing(sim, 1), collected with HIP events
+ * on the run stream (they add synchronisation, so timed runs are slower):
+ *   0 switch evaluation, 1 particle phase (push, migrate, ionization),
+ *   2 fluid, 3 conversion, 4 fields, 5 inbox merge and re-binning (ms);
+ *   6 the push kernel alone (ms), 7 re-binnings since creation,
+ *   8 push launches, 9 particles pushed, 10 tiles pushed (counts).
+ * hk_timers copies min(n, HK_NTIMERS) values. */
+#define HK_NTIMERS 12
 int hk_enable_timing(hk_sim *sim, int on);
 int hk_timers(hk_sim *sim, double *ms, int n);
 

@@ -35,7 +35,7 @@ void launch_migrate(const GridP &g, const SpecP &sp, PArr mig, const long long *
 void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
                        int *nf_out, PArr mig, const long long *moff, const int *mcap, int *mcnt,
                        PArr inbox, int *inbox_n, int inbox_cap, real *const f[9], int *err,
-                       hipStream_t s);
+                       unsigned long long *stats, const unsigned *wmax_bits, hipStream_t s);
 void launch_ionize_static(const GridP &g, const SpecP &sp, PArr a, Bins b, int *active,
                           real *const f[9], const uint8_t *sw, int hybrid, const IonP *ion,
                           PArr eout, int *eout_n, int eout_cap, uint64_t seed, int step,
@@ -59,7 +59,7 @@ void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n
 void launch_spawn_nodes(const GridP &g, const SpecP &sp, const uint8_t *sw, real *n, real *ux,
                         real *uy, real *uz, real *const f[9], real wmin, int m, uint64_t seed,
                         int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
-                        hipStream_t s);
+                        unsigned *wmax_bits, hipStream_t s);
 
 namespace {
 
@@ -124,8 +124,15 @@ struct hk_sim {
     std::string err;
     std::vector<void *> allocs;
     bool timing = false;
-    double timers[8]{};
-    hipEvent_t ev[9]{};
+    double timers[HK_NTIMERS]{};
+    // timing events: recorded without waiting, resolved when the timers are read
+    std::vector<hipEvent_t> ev_free;
+    struct Span { hipEvent_t a, b; int slot; };
+    std::vector<Span> spans;
+    hipEvent_t last_mark = nullptr;
+    unsigned long long *dstat = nullptr;   // [0] particles pushed, [1] tiles pushed
+    unsigned *wmax = nullptr;       // per species: bound on |w| (FP32 bits), never lowered
+    unsigned long long stat0[2]{};  // device counters when timing was enabled
     double fallback_fraction = 0;
 };
 
@@ -324,6 +331,19 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     return HK_OK;
 }
 
+// Raise species isp's weight bound to at least w (host side).
+int raise_wmax(hk_sim *S, int isp, double w) {
+    unsigned cur = 0;
+    HIPCHK(S, hipMemcpyAsync(&cur, S->wmax + isp, sizeof(unsigned), hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    float f = (float)std::fabs(w);
+    f = std::nextafter(f, INFINITY);   // round up: a bound, not an estimate
+    unsigned bits;
+    std::memcpy(&bits, &f, 4);
+    if (bits > cur) HIPCHK(S, hipMemcpyAsync(S->wmax + isp, &bits, sizeof(unsigned), hipMemcpyHostToDevice, S->s));
+    return HK_OK;
+}
+
 int ensure_inbox(hk_sim *S, int isp, long long need) {
     DevSpecies &D = S->sp[isp];
     if (need <= D.inbox_cap) return HK_OK;
@@ -386,6 +406,10 @@ int init_species(hk_sim *S, int isp) {
     long long total = (long long)xcol.size() * g.ny * g.nz * std::max(d.ppc, 0);
     int rc = ensure_inbox(S, isp, std::max<long long>(total, 1 << 16));
     if (rc) return rc;
+    double wm = 0;
+    for (double w : wcol) wm = std::max(wm, w);
+    rc = raise_wmax(S, isp, wm);
+    if (rc) return rc;
     if (total > 0) {
         int *dx = (int *)dalloc(S, sizeof(int) * xcol.size());
         double *dw = (double *)dalloc(S, sizeof(double) * wcol.size());
@@ -409,8 +433,41 @@ int init_species(hk_sim *S, int isp) {
     return HK_OK;
 }
 
+hipEvent_t ev_get(hk_sim *S) {
+    hipEvent_t e = nullptr;
+    if (!S->ev_free.empty()) { e = S->ev_free.back(); S->ev_free.pop_back(); }
+    else (void)hipEventCreate(&e);
+    (void)hipEventRecord(e, S->s);
+    return e;
+}
+
+// Accumulate every recorded span into the timers and recycle the events.
+void ev_resolve(hk_sim *S) {
+    if (S->spans.empty()) return;
+    (void)hipEventSynchronize(S->spans.back().b);
+    std::vector<hipEvent_t> used;
+    for (auto &sp : S->spans) {
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, sp.a, sp.b);
+        S->timers[sp.slot] += ms;
+        used.push_back(sp.a);
+        used.push_back(sp.b);
+    }
+    S->spans.clear();
+    std::sort(used.begin(), used.end());
+    used.erase(std::unique(used.begin(), used.end()), used.end());
+    for (hipEvent_t e : used)
+        if (e != S->last_mark) S->ev_free.push_back(e);
+}
+
+// Group timing: the interval since the previous mark is charged to `slot`
+// (slot < 0 starts a new sequence).
 void time_mark(hk_sim *S, int slot) {
-    if (S->timing) (void)hipEventRecord(S->ev[slot], S->s);
+    if (!S->timing) return;
+    hipEvent_t e = ev_get(S);
+    if (slot >= 0 && S->last_mark) S->spans.push_back({S->last_mark, e, slot});
+    S->last_mark = e;
+    if (S->spans.size() > 2048) ev_resolve(S);
 }
 
 int check_status(hk_sim *S) {
@@ -533,7 +590,7 @@ void reconcile(hk_sim *S) {
         real wmin = (real)(S->run.spawn_frac * D.d.n0 * dv / m);
         launch_spawn_nodes(g, P, S->sw, D.fn, D.fu[0], D.fu[1], D.fu[2], S->f, wmin, m, S->run.seed,
                            (int)S->step, D.inbox, S->status + 1 + 2 * isp, D.inbox_cap,
-                           S->status + 13, s);
+                           S->status + 13, S->wmax + isp, s);
     }
 }
 
@@ -542,12 +599,12 @@ int one_step(hk_sim *S) {
     const GridP &g = S->g;
     const int mode = S->run.switch_mode;
     const int hybrid = mode != HK_SW_ALL_PIC;
-    time_mark(S, 0);
+    time_mark(S, -1);
     // 1. switch evaluation
     if ((mode == HK_SW_THRESHOLD || mode == HK_SW_CNN) &&
         S->step % std::max(1, S->run.switch_every) == 0)
         switch_eval(S);
-    time_mark(S, 1);
+    time_mark(S, 0);
     // 2. J = 0, antenna current at t^{n+1/2}
     launch_zero(S->f[HK_JX], sizeof(real) * 3 * (size_t)g.nn, s);
     launch_antenna(g, S->las, S->t + 0.5 * g.ddt, S->f[HK_JY], S->f[HK_JZ], s);
@@ -560,9 +617,14 @@ int one_step(hk_sim *S) {
         if (D.d.mobile) {
             int nxt = 1 - D.cur;
             launch_zero(D.nb[nxt], sizeof(int) * g.ntiles, s);
+            hipEvent_t pa = S->timing ? ev_get(S) : nullptr;
             launch_push_tiles(g, P, D.buf[D.cur], cur_bins(D), D.buf[nxt], D.nf[nxt], D.mig, D.moff,
                               D.mcap, D.mcnt, D.inbox, S->status + 1 + 2 * isp, D.inbox_cap, S->f,
-                              S->status, s);
+                              S->status, S->dstat, S->wmax + isp, s);
+            if (S->timing) {
+                S->spans.push_back({pa, ev_get(S), 6});
+                S->timers[8] += 1;
+            }
             launch_migrate(g, P, D.mig, D.moff, D.mcnt, D.buf[nxt], D.nf[nxt], D.nb[nxt],
                            S->status + 2 + 2 * isp, D.fail, D.inbox_cap, S->status, s);
         } else if (D.d.ionizable && S->run.enable_ionization) {
@@ -576,11 +638,11 @@ int one_step(hk_sim *S) {
         DevSpecies &D = S->sp[isp];
         if (D.capacity && D.d.mobile && D.d.kind != HK_PHOTON) D.cur = 1 - D.cur;
     }
-    time_mark(S, 2);
+    time_mark(S, 1);
     // 4. newborn and overflow particles join their bins
     int rc = merge_all(S);
     if (rc) return rc;
-    time_mark(S, 3);
+    time_mark(S, 5);
     // 5. cold fluid, 6. conversion
     if (hybrid) {
         for (int isp = 0; isp < S->nsp; ++isp) {
@@ -589,29 +651,20 @@ int one_step(hk_sim *S) {
                                    S->fluid_scratch, (real)S->run.n_floor, s);
         }
     }
-    time_mark(S, 4);
+    time_mark(S, 2);
     if (hybrid) {
         reconcile(S);
         rc = merge_all(S);
         if (rc) return rc;
     }
-    time_mark(S, 5);
+    time_mark(S, 3);
     // 7. fields
     launch_yee_b_half(g, S->f, s);
     launch_yee_e_full(g, S->f, S->mur_old, s);
     launch_yee_b_half(g, S->f, s);
-    time_mark(S, 6);
+    time_mark(S, 4);
     S->step++;
     S->t = S->step * g.ddt;
-    if (S->timing) {
-        HIPCHK(S, hipEventSynchronize(S->ev[6]));
-        const int map[6] = {0, 1, 5, 2, 3, 4};  // event interval -> timer slot
-        for (int i = 0; i < 6; ++i) {
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, S->ev[i], S->ev[i + 1]);
-            S->timers[map[i]] += ms;
-        }
-    }
     return HK_OK;
 }
 
@@ -740,10 +793,12 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
     S->dsum = (double *)dalloc(S, sizeof(double) * 64);
     S->ledger = (double *)dalloc(S, sizeof(double) * 8);
     S->status = (int *)dalloc(S, sizeof(int) * 16);
+    S->dstat = (unsigned long long *)dalloc(S, sizeof(unsigned long long) * 4);
+    S->wmax = (unsigned *)dalloc(S, sizeof(unsigned) * HK_MAX_SPECIES);
     if (hipHostMalloc((void **)&S->h_status, sizeof(int) * 16, 0) != hipSuccess)
         S->h_status = nullptr;
     if (!S->fblock || !S->mur_old || !S->sw || !S->calm || !S->gauss0 || !S->tmp_a || !S->tmp_b ||
-        !S->dsum || !S->ledger || !S->status || !S->h_status) {
+        !S->dsum || !S->ledger || !S->status || !S->h_status || !S->dstat || !S->wmax) {
         hk_destroy(S);
         return HK_ENOMEM;
     }
@@ -767,7 +822,14 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
         }
     for (int i = 0; i < nspecies && rc == HK_OK; ++i) rc = init_species(S, i);
     for (int i = 0; i < nspecies && rc == HK_OK; ++i)
-        if (species[i].ionizable && run->enable_ionization) rc = build_ion_table(S, i);
+        if (species[i].ionizable && run->enable_ionization) {
+            rc = build_ion_table(S, i);
+            unsigned b = 0;
+            if (rc == HK_OK && hipMemcpy(&b, S->wmax + i, 4, hipMemcpyDeviceToHost) != hipSuccess) rc = HK_EDEVICE;
+            float f;
+            std::memcpy(&f, &b, 4);
+            if (rc == HK_OK) rc = raise_wmax(S, species[i].target, f);
+        }
     for (int i = 0; i < nspecies && rc == HK_OK; ++i) rc = ensure_inbox(S, i, inbox_need(S, i));
     if (rc == HK_OK && run->switch_mode != HK_SW_ALL_PIC) rc = ensure_fluid(S);
     if (rc == HK_OK && hipStreamSynchronize(S->s) != hipSuccess) rc = HK_EDEVICE;
@@ -775,7 +837,6 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
         hk_destroy(S);
         return rc;
     }
-    for (int i = 0; i < 9; ++i) (void)hipEventCreate(&S->ev[i]);
     *out = S;
     return HK_OK;
 }
@@ -787,8 +848,9 @@ void hk_destroy(hk_sim *S) {
     std::vector<void *> all = S->allocs;
     for (void *p : all) dfree(S, p);
     if (S->h_status) (void)hipHostFree(S->h_status);
-    for (int i = 0; i < 9; ++i)
-        if (S->ev[i]) (void)hipEventDestroy(S->ev[i]);
+    ev_resolve(S);
+    for (hipEvent_t e : S->ev_free) (void)hipEventDestroy(e);
+    if (S->last_mark) (void)hipEventDestroy(S->last_mark);
     delete S;
 }
 
@@ -994,6 +1056,10 @@ int hk_set_particles(hk_sim *S, int isp, const hk_particles *in) {
     }
     int rc = ensure_inbox(S, isp, (long long)n + 1024);
     if (rc) return rc;
+    double wm = 0;
+    for (size_t q = 0; q < n; ++q) wm = std::max(wm, std::fabs(in->w[q]));
+    rc = raise_wmax(S, isp, wm);
+    if (rc) return rc;
     const PArr &a = D.inbox;
     hipStream_t s = S->s;
     if (n) {
@@ -1059,14 +1125,26 @@ int hk_set_fluid(hk_sim *S, int isp, const double *n, const double *u, size_t no
 
 int hk_enable_timing(hk_sim *S, int on) {
     if (!S) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    ev_resolve(S);
     S->timing = on != 0;
-    for (int i = 0; i < 7; ++i) S->timers[i] = 0;
+    for (int i = 0; i < HK_NTIMERS; ++i)
+        if (i != 7) S->timers[i] = 0;
+    HIPCHK(S, hipMemcpyAsync(S->stat0, S->dstat, sizeof(S->stat0), hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
     return HK_OK;
 }
 
 int hk_timers(hk_sim *S, double *ms, int n) {
     if (!S || !ms || n < 0) return HK_EINVAL;
-    for (int i = 0; i < n && i < 8; ++i) ms[i] = S->timers[i];
+    if (S->poisoned) return HK_ESTATE;
+    ev_resolve(S);
+    unsigned long long now[2];
+    HIPCHK(S, hipMemcpyAsync(now, S->dstat, sizeof(now), hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    S->timers[9] = (double)(now[0] - S->stat0[0]);
+    S->timers[10] = (double)(now[1] - S->stat0[1]);
+    for (int i = 0; i < n && i < HK_NTIMERS; ++i) ms[i] = S->timers[i];
     return HK_OK;
 }
 

@@ -9,6 +9,16 @@ constexpr int FT3 = FT * FT * FT;
 constexpr int JT = TILE + 3;       // current tile edge: nodes -1 .. TILE+1
 constexpr int JT3 = JT * JT * JT;
 
+// cell -> (i, j, k) without integer division: (c + 1/2) / n is at least
+// 1/(2n) away from an integer, far beyond the FP64 rounding of the product.
+__device__ inline void cell_ijk(const GridP &g, int cell, int &i, int &j, int &k) {
+    const double inx = 1.0 / (double)g.nx, iny = 1.0 / (double)g.ny;
+    int r = (int)(((double)cell + 0.5) * inx);
+    i = cell - r * g.nx;
+    k = (int)(((double)r + 0.5) * iny);
+    j = r - k * g.ny;
+}
+
 __device__ inline int tile_of(const GridP &g, int cell) {
     int ci = cell % g.nx, r = cell / g.nx;
     int cj = r % g.ny, ck = r / g.ny;
@@ -138,8 +148,14 @@ __device__ inline void jadd(jacc_t *p, real v, real) { atomicAdd(p, v); }
 __device__ inline double jval(jacc_t v, double) { return v; }
 #else
 typedef unsigned long long jacc_t;
+// round-to-nearest float -> int64 for |x| < 2^51: adding 1.5 * 2^52 leaves
+// the integer in the low mantissa bits of the double
+__device__ inline long long round_to_i64(double x) {
+    const double magic = 6755399441055744.0;
+    return __double_as_longlong(x + magic) - __double_as_longlong(magic);
+}
 __device__ inline void jadd(jacc_t *p, real v, real inv_scale) {
-    long long q = llrintf(v * inv_scale);
+    long long q = round_to_i64((double)(v * inv_scale));
     if (q) atomicAdd(p, (unsigned long long)q);
 }
 __device__ inline double jval(jacc_t v, double scale) { return (double)(long long)v * scale; }

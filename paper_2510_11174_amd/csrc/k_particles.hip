@@ -198,17 +198,19 @@ k_migrate(GridP g, SpecP sp, PArr mig, const long long *__restrict__ moff,
 }
 
 // ------------------------------------------------------------- the push -----------------
-__global__ void __launch_bounds__(BS)
+constexpr int PBS = 512;   // push workgroup: 8 waves share one tile
+
+__global__ void __launch_bounds__(PBS)
 k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_out, PArr mig,
        const long long *__restrict__ moff, const int *__restrict__ mcap, int *__restrict__ mcnt,
        PArr inbox, int *__restrict__ inbox_n, int inbox_cap, const real *__restrict__ Ex,
        const real *__restrict__ Ey, const real *__restrict__ Ez, const real *__restrict__ Bx,
        const real *__restrict__ By, const real *__restrict__ Bz, real *__restrict__ Jx,
-       real *__restrict__ Jy, real *__restrict__ Jz, int *__restrict__ err) {
+       real *__restrict__ Jy, real *__restrict__ Jz, int *__restrict__ err,
+       unsigned long long *__restrict__ stats, const unsigned *__restrict__ wmax_bits) {
     __shared__ real sF[6 * FT3];
     __shared__ jacc_t sJ[3 * JT3];
     __shared__ int s_stay, s_move;
-    __shared__ unsigned s_wmax;
     const int t = blockIdx.x;
     int nfi, nbi;
     const int n = bin_count(sp, bin_in, t, nfi, nbi);
@@ -220,7 +222,7 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
     const int per = g.bcx == HK_BC_PERIODIC;
 
-    for (int e = threadIdx.x; e < FT3; e += BS) {
+    for (int e = threadIdx.x; e < FT3; e += PBS) {
         int a = e % FT, b = (e / FT) % FT, c = e / (FT * FT);
         int gi = ox - 1 + a;
         int gj = wrapi(oy - 1 + b, g.ny), gk = wrapi(oz - 1 + c, g.nz);
@@ -238,20 +240,8 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
         sF[4 * FT3 + e] = By[ch];
         sF[5 * FT3 + e] = Bz[ch];
     }
-    for (int e = threadIdx.x; e < 3 * JT3; e += BS) sJ[e] = 0;
-    if (threadIdx.x == 0) { s_stay = 0; s_move = 0; s_wmax = 0; }
-    __syncthreads();
-    // fixed-point scale of the tile: largest weight (non-negative floats
-    // order like their bit patterns)
-    {
-        float wm = 0.f;
-        for (int p = threadIdx.x; p < n; p += BS) {
-            long long ip = bin_slot(sp, t, p, nfi, nbi);
-            if (in.cell[ip] >= 0) wm = fmaxf(wm, fabsf((float)in.w[ip]));
-        }
-        for (int o = 32; o > 0; o >>= 1) wm = fmaxf(wm, __shfl_down(wm, o));
-        if ((threadIdx.x & 63) == 0) atomicMax(&s_wmax, __float_as_uint(wm));
-    }
+    for (int e = threadIdx.x; e < 3 * JT3; e += PBS) sJ[e] = 0;
+    if (threadIdx.x == 0) { s_stay = 0; s_move = 0; }
     __syncthreads();
 
     const real dv = g.dx * g.dy * g.dz;
@@ -262,12 +252,15 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
     const long long mbase = moff[t];
     const int mlim = mcap[t];
     const real cdx = g.dx / g.dt, cdy = g.dy / g.dt, cdz = g.dz / g.dt;
-    // one particle's largest current contribution is |q| w / dV * max(dx,dy,dz) / dt
-    const double jmax = (double)fabsf((float)sp.q) * (double)__uint_as_float(s_wmax) / (double)dv *
+    const real dtdx = g.dt / g.dx, dtdy = g.dt / g.dy, dtdz = g.dt / g.dz;
+    // fixed-point scale: one particle's largest current contribution is
+    // |q| w / dV * max(dx,dy,dz) / dt, with w bounded by the species' weight
+    // bound (never lowered; raised by every kernel that creates particles)
+    const double jmax = (double)fabsf((float)sp.q) * (double)__uint_as_float(*wmax_bits) / (double)dv *
                         (double)fmaxf(fmaxf((float)cdx, (float)cdy), (float)cdz);
     const double jscale = jmax > 0.0 ? jmax / (double)JFIX_UNITS : 1.0;
     const real inv_scale = (real)(1.0 / jscale);
-    for (int p0 = 0; p0 < n; p0 += BS) {
+    for (int p0 = 0; p0 < n; p0 += PBS) {
         const int p = p0 + threadIdx.x;
         long long ip = 0;
         int cell = -1;
@@ -283,9 +276,7 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
         double tau = 0;
         int ci = 0, cj = 0, ck = 0, lx = 0, ly = 0, lz = 0;
         if (valid) {
-            ci = cell % g.nx;
-            const int rr = cell / g.nx;
-            cj = rr % g.ny; ck = rr / g.ny;
+            cell_ijk(g, cell, ci, cj, ck);
             lx = ci - ox; ly = cj - oy; lz = ck - oz;
             if ((unsigned)lx >= TILE || (unsigned)ly >= TILE || (unsigned)lz >= TILE) {
                 atomicOr(err, ERR_TILE);
@@ -310,9 +301,11 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
             // Boris rotation
             real umx = ux + hq * ex, umy = uy + hq * ey, umz = uz + hq * ez;
             real gm = sqrt((real)1 + umx * umx + umy * umy + umz * umz);
-            real tx_ = hq * bx / gm, ty_ = hq * by / gm, tz_ = hq * bz / gm;
+            const real igm = hq / gm;
+            real tx_ = bx * igm, ty_ = by * igm, tz_ = bz * igm;
             real t2 = tx_ * tx_ + ty_ * ty_ + tz_ * tz_;
-            real sx = 2 * tx_ / (1 + t2), sy = 2 * ty_ / (1 + t2), sz = 2 * tz_ / (1 + t2);
+            const real is = (real)2 / (1 + t2);
+            real sx = tx_ * is, sy = ty_ * is, sz = tz_ * is;
             real upx = umx + (umy * tz_ - umz * ty_);
             real upy = umy + (umz * tx_ - umx * tz_);
             real upz = umz + (umx * ty_ - umy * tx_);
@@ -321,9 +314,10 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
             real uqz = umz + (upx * sy - upy * sx);
             ux = uqx + hq * ex; uy = uqy + hq * ey; uz = uqz + hq * ez;
             real gam = sqrt((real)1 + ux * ux + uy * uy + uz * uz);
-            real X1 = rx + g.dt * ux / gam / g.dx;
-            real Y1 = ry + g.dt * uy / gam / g.dy;
-            real Z1 = rz + g.dt * uz / gam / g.dz;
+            const real igam = (real)1 / gam;
+            real X1 = rx + dtdx * ux * igam;
+            real Y1 = ry + dtdy * uy * igam;
+            real Z1 = rz + dtdz * uz * igam;
             // specular reflection at the open x walls
             if (!per) {
                 if (ci == 0 && X1 < (real)0) { X1 = -X1; ux = -ux; }
@@ -397,9 +391,11 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
     if (threadIdx.x == 0) {
         nf_out[t] = s_stay;          // stayers never exceed the bin: they were in it
         mcnt[t] = min(s_move, mlim);
+        atomicAdd(&stats[0], (unsigned long long)(s_stay + s_move));   // particles pushed
+        atomicAdd(&stats[1], 1ull);                                    // tiles with particles
     }
     // flush the LDS current tile (nodes ox-1 .. ox+TILE+1) to HBM
-    for (int e = threadIdx.x; e < JT3; e += BS) {
+    for (int e = threadIdx.x; e < JT3; e += PBS) {
         int a = e % JT, b = (e / JT) % JT, c = e / (JT * JT);
         int gi = ox - 1 + a;
         int gj = wrapi(oy - 1 + b, g.ny), gk = wrapi(oz - 1 + c, g.nz);
@@ -609,10 +605,11 @@ void launch_migrate(const GridP &g, const SpecP &sp, PArr mig, const long long *
 void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
                        int *nf_out, PArr mig, const long long *moff, const int *mcap, int *mcnt,
                        PArr inbox, int *inbox_n, int inbox_cap, real *const f[9], int *err,
-                       hipStream_t s) {
-    k_push<<<g.ntiles, BS, 0, s>>>(g, sp, in, bin_in, out, nf_out, mig, moff, mcap, mcnt, inbox,
-                                   inbox_n, inbox_cap, f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX],
-                                   f[HK_BY], f[HK_BZ], f[HK_JX], f[HK_JY], f[HK_JZ], err);
+                       unsigned long long *stats, const unsigned *wmax_bits, hipStream_t s) {
+    k_push<<<g.ntiles, PBS, 0, s>>>(g, sp, in, bin_in, out, nf_out, mig, moff, mcap, mcnt, inbox,
+                                    inbox_n, inbox_cap, f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX],
+                                    f[HK_BY], f[HK_BZ], f[HK_JX], f[HK_JY], f[HK_JZ], err, stats,
+                                    wmax_bits);
 }
 
 void launch_ionize_static(const GridP &g, const SpecP &sp, PArr a, Bins b, int *active,

@@ -47,39 +47,78 @@ __device__ inline long long nearest_node(const GridP &g, int ci, int cj, int ck,
 
 // ---------------------------------------------------------------- moments -----------------
 // mom layout (7 grid arrays): N = sum w, V = sum w^2, P (3), U2 = sum w |u|^2, NI.
+// Nearest-node sums of one tile's particles in LDS.  The FP32 build adds
+// fixed-point integers (2^40 units per the tile's largest contribution of
+// each quantity, found in a first pass): LDS integer atomics are far cheaper
+// than float ones on this GPU and the sums become independent of the order.
+__device__ inline real tile_moment_term(int q, real w, real ux, real uy, real uz) {
+    switch (q) {
+        case 0: return w;
+        case 1: return w * w;
+        case 2: return w * ux;
+        case 3: return w * uy;
+        case 4: return w * uz;
+        default: return w * (ux * ux + uy * uy + uz * uz);
+    }
+}
+
 __global__ void __launch_bounds__(BS)
 k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__restrict__ mom) {
-    __shared__ real sm[6 * NT3];
+    __shared__ jacc_t sm[6 * NT3];
+    __shared__ unsigned smax[6];
     const int t = blockIdx.x;
     int nf, nbv;
     const int n = bin_count(sp, bins, t, nf, nbv);
     if (n <= 0) return;
-    for (int e = threadIdx.x; e < 6 * NT3; e += BS) sm[e] = 0;
+    const int nq = ion_only ? 1 : 6;
+    for (int e = threadIdx.x; e < nq * NT3; e += BS) sm[e] = 0;
+    if (threadIdx.x < 6) smax[threadIdx.x] = 0;
     __syncthreads();
+    // pass 1: largest |term| per quantity (bit patterns of non-negative
+    // floats order like unsigned integers)
+    float lmax[6] = {0, 0, 0, 0, 0, 0};
+    for (int p = threadIdx.x; p < n; p += BS) {
+        const long long ip = bin_slot(sp, t, p, nf, nbv);
+        if (a.cell[ip] < 0) continue;
+        const real w = a.w[ip];
+        if (ion_only) {
+            if (a.zc[ip] < zmax) lmax[0] = fmaxf(lmax[0], fabsf((float)w));
+            continue;
+        }
+        const real ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip];
+        for (int q = 0; q < 6; ++q) lmax[q] = fmaxf(lmax[q], fabsf((float)tile_moment_term(q, w, ux, uy, uz)));
+    }
+    for (int q = 0; q < nq; ++q) {
+        float v = lmax[q];
+        for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+        if ((threadIdx.x & 63) == 0 && v > 0.f) atomicMax(&smax[q], __float_as_uint(v));
+    }
+    __syncthreads();
+    real inv[6], scl[6];
+    for (int q = 0; q < 6; ++q) {
+        const float m = __uint_as_float(smax[q]) * 1.0001f;
+        inv[q] = m > 0.f ? (real)(JFIX_UNITS / m) : (real)0;
+        scl[q] = (real)((double)m / (double)JFIX_UNITS);
+    }
     const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
     for (int p = threadIdx.x; p < n; p += BS) {
         const long long ip = bin_slot(sp, t, p, nf, nbv);
         int cell = a.cell[ip];
         if (cell < 0) continue;
-        const int ci = cell % g.nx, rr = cell / g.nx;
-        const int cj = rr % g.ny, ck = rr / g.ny;
+        int ci, cj, ck;
+        cell_ijk(g, cell, ci, cj, ck);
         const int lx = ci - ox + (a.rx[ip] >= (real)0.5), ly = cj - oy + (a.ry[ip] >= (real)0.5),
                   lz = ck - oz + (a.rz[ip] >= (real)0.5);
         if ((unsigned)lx > TILE || (unsigned)ly > TILE || (unsigned)lz > TILE) continue;
         const int e = lx + NT * (ly + NT * lz);
-        real w = a.w[ip];
+        const real w = a.w[ip];
         if (ion_only) {
-            if (a.zc[ip] < zmax) atomicAdd(&sm[e], w);
+            if (a.zc[ip] < zmax) jadd(&sm[e], w, inv[0]);
             continue;
         }
-        real ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip];
-        atomicAdd(&sm[e], w);
-        atomicAdd(&sm[NT3 + e], w * w);
-        atomicAdd(&sm[2 * NT3 + e], w * ux);
-        atomicAdd(&sm[3 * NT3 + e], w * uy);
-        atomicAdd(&sm[4 * NT3 + e], w * uz);
-        atomicAdd(&sm[5 * NT3 + e], w * (ux * ux + uy * uy + uz * uz));
+        const real ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip];
+        for (int q = 0; q < 6; ++q) jadd(&sm[q * NT3 + e], tile_moment_term(q, w, ux, uy, uz), inv[q]);
     }
     __syncthreads();
     const int per = g.bcx == HK_BC_PERIODIC;
@@ -90,11 +129,11 @@ k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__
         else if (gi > g.nx) continue;
         long long node = gidx(g, gi, gj, gk);
         if (ion_only) {
-            if (sm[e] != (real)0) atomicAdd(&mom[6 * g.nn + node], sm[e]);
+            if (sm[e] != 0) atomicAdd(&mom[6 * g.nn + node], (real)jval(sm[e], scl[0]));
             continue;
         }
         for (int q = 0; q < 6; ++q)
-            if (sm[q * NT3 + e] != (real)0) atomicAdd(&mom[q * g.nn + node], sm[q * NT3 + e]);
+            if (sm[q * NT3 + e] != 0) atomicAdd(&mom[q * g.nn + node], (real)jval(sm[q * NT3 + e], scl[q]));
     }
 }
 
@@ -374,7 +413,8 @@ __global__ void __launch_bounds__(BS)
 k_spawn(GridP g, SpecP sp, const uint8_t *__restrict__ sw, real *__restrict__ n, real *__restrict__ ux,
         real *__restrict__ uy, real *__restrict__ uz, real *__restrict__ Jx, real *__restrict__ Jy,
         real *__restrict__ Jz, real wmin, int m, uint64_t seed, int step, PArr inbox,
-        int *__restrict__ inbox_n, int inbox_cap, int *__restrict__ deferred) {
+        int *__restrict__ inbox_n, int inbox_cap, int *__restrict__ deferred,
+        unsigned *__restrict__ wmax_bits) {
     long long c = (long long)blockIdx.x * BS + threadIdx.x;
     if (c >= g.nn) return;
     int i, j, k;
@@ -395,6 +435,7 @@ k_spawn(GridP g, SpecP sp, const uint8_t *__restrict__ sw, real *__restrict__ n,
         return;
     }
     const real w = mass / (real)m;
+    if (__float_as_uint(fabsf((float)w)) > *wmax_bits) atomicMax(wmax_bits, __float_as_uint(fabsf((float)w)));
     const real u[3] = {ux[c], uy[c], uz[c]};
     const uint64_t node = (uint64_t)i + (uint64_t)nxn * ((uint64_t)j + (uint64_t)g.ny * k);
     const real qw = sp.q * w / dv;
@@ -460,7 +501,7 @@ void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n
 void launch_spawn_nodes(const GridP &g, const SpecP &sp, const uint8_t *sw, real *n, real *ux,
                         real *uy, real *uz, real *const f[9], real wmin, int m, uint64_t seed,
                         int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
-                        hipStream_t s) {
+                        unsigned *wmax_bits, hipStream_t s) {
     k_spawn<<<blocks(g.nn), BS, 0, s>>>(g, sp, sw, n, ux, uy, uz, f[HK_JX], f[HK_JY], f[HK_JZ], wmin,
-                                        m, seed, step, inbox, inbox_n, inbox_cap, deferred);
+                                        m, seed, step, inbox, inbox_n, inbox_cap, deferred, wmax_bits);
 }

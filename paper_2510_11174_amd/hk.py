@@ -22,6 +22,10 @@ PROFILE = {"none": 0, "uniform": 1, "ramp": 2, "foil": 3}
 SWITCH = {"all_pic": 0, "threshold": 1, "cnn": 2, "all_fluid": 3, "fixed": 4}
 BC = {"periodic": 0, "open": 1}
 COMP = {"ex": 0, "ey": 1, "ez": 2, "bx": 3, "by": 4, "bz": 5, "jx": 6, "jy": 7, "jz": 8}
+NTIMERS = 12
+TIMER_NAMES = ["switch_ms", "particles_ms", "fluid_ms", "conversion_ms", "fields_ms", "merge_ms",
+               "push_kernel_ms", "rebins", "push_launches", "particles_pushed", "tiles_pushed",
+               "unused"]
 STATUS = {0: "HK_OK", -1: "HK_EINVAL", -2: "HK_ENOMEM", -3: "HK_EDEVICE", -4: "HK_ENUMERIC",
           -5: "HK_EOVERFLOW", -6: "HK_ESTATE", -7: "HK_EIO", -8: "HK_ENOTSUP"}
 
@@ -327,7 +331,7 @@ class Sim:
     def enable_timing(self, on=True):
         self._check(self.lib.hk_enable_timing(self.h, int(on)))
 
-    def timers(self) -> np.ndarray:
-        out = np.zeros(8)
-        self._check(self.lib.hk_timers(self.h, _ptr(out), 8))
-        return out
+    def timers(self) -> dict:
+        out = np.zeros(NTIMERS)
+        self._check(self.lib.hk_timers(self.h, _ptr(out), NTIMERS))
+        return dict(zip(TIMER_NAMES, out.tolist()))
