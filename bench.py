@@ -4,13 +4,17 @@
 Workload: the ionizing-helium case (128 x 64 x 64 cells, dx = 0.1, 8 particles
 per cell, neutral He 0.1 n_c with a 10-lambda up-ramp, a0 = 10 linear pulse,
 waist 6 lambda, duration 15, ADK/multiphoton ionization, threshold switch).
-The same seed runs twice on the same GPU: hybrid (threshold switch) and
-all-PIC (every node kinetic).  After W untimed warm-up steps, K steps are timed
-with a device synchronisation on both sides.
+The same seed runs on the same GPU as hybrid (threshold switch) and as all-PIC
+(every node kinetic).  Each mode first runs W untimed warm-up steps on a
+throwaway simulation; then a fresh simulation runs steps 0..K from t = 0 under
+the clock (device synchronisation on both sides; the field snapshot at K/2 is
+taken outside the clock).  An untimed repeat of the all-PIC run measures the
+run-to-run floor of the field comparison (FP32 atomics sum in varying order).
 
 The JSON line reports hybrid steps/s (value), all-PIC steps/s, the speed-up,
-particle pushes/s, the field relative L2 and energy difference between the two
-runs at the end, the push kernel's achieved HBM rate against the roofline
+particle pushes/s, the field relative L2 of hybrid vs all-PIC (and of the
+all-PIC repeat) at K/2 and K, the energy difference at K, the push kernel's
+achieved HBM rate against the roofline
 (algorithmic bytes: 60 B per particle push plus 36 B per cell of every tile
 with particles, over the kernel's own time from HIP events on the library
 stream), and the FP64 CPU oracle timed on a bounded sample of the same physics.
@@ -32,27 +36,87 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_PUSH = 60            # read offsets, u, w, cell (32 B); write offsets, u, cell (28 B)
 BYTES_PER_TILE_CELL = 36       # E, B gather (24 B) + J flush (12 B) per cell of a kinetic tile
 TILE_CELLS = 512
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_push_traffic_ionization_128x64x64.txt")
+PUSH_SOURCES = ("paper_2510_11174_amd/csrc/k_particles.hip", "paper_2510_11174_amd/csrc/hk_pic_device.h",
+                "paper_2510_11174_amd/csrc/hk_internal.h")
 
 
-def run_gpu(cfg, steps, warmup, precision):
+def push_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in PUSH_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per k_push launch (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
+    calibration) recorded in profiles/, or None if missing or taken on other kernel sources."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.split("=", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("source_hash") != push_source_hash():
+            return None
+        return float(kv["bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mib=1024, reps=5):
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "reps": reps}))
+
+
+def run_gpu(cfg, steps, precision, timing=True, snap_at=None):
+    """Run `steps` steps of a fresh simulation from t = 0.  The clock covers the
+    steps only (device synchronisation on both sides of each timed segment); a
+    field snapshot at step `snap_at` is taken outside the clock."""
     import numpy as np
     import torch
 
     from paper_2510_11174_amd import hk
     sim = hk.Sim(cfg, precision=precision)
-    sim.step(warmup)
-    torch.cuda.synchronize()
-    sim.enable_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    sim.enable_timing(timing)
+    segs = [steps] if not snap_at else [snap_at, steps - snap_at]
+    seconds = 0.0
+    snaps = {}
+    done = 0
+    for n in segs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(n)
+        torch.cuda.synchronize()
+        seconds += time.perf_counter() - t0
+        done += n
+        snaps[done] = {c: sim.get_field(c).astype(np.float64) for c in ("ex", "ey", "ez", "bx", "by", "bz")}
     tm = sim.timers()
     d = sim.diagnostics()
-    fields = {c: sim.get_field(c).astype(np.float64) for c in ("ex", "ey", "ez", "bx", "by", "bz")}
+    kin = d["kinetic_fraction"]
     sim.close()
-    return {"seconds": t1 - t0, "timers": tm, "diag": d, "fields": fields}
+    return {"seconds": seconds, "timers": tm, "diag": d, "snaps": snaps, "kinetic_fraction": kin}
+
+
+def warm_up(cfg, steps, precision):
+    """Untimed warm-up: the same configuration on a throwaway simulation."""
+    import torch
+
+    from paper_2510_11174_amd import hk
+    sim = hk.Sim(cfg, precision=precision)
+    sim.step(steps)
+    torch.cuda.synchronize()
+    sim.close()
 
 
 def total_energy(d):
@@ -60,7 +124,7 @@ def total_energy(d):
             + d["ion_energy"] + d["photon_energy"])
 
 
-def cpu_baseline(warm=60, timed=60):
+def cpu_baseline(warm=60, timed=50):
     """FP64 oracle on a 64 x 32 x 32 crop of the same physics (threshold switch),
     single thread; steps/s scaled to the full grid by the cell ratio."""
     import oracle
@@ -83,49 +147,77 @@ def cpu_baseline(warm=60, timed=60):
             "pushes_per_s": n * timed / dt}
 
 
+def field_l2(x, y):
+    import numpy as np
+    num = math.sqrt(sum(float(np.sum((x[c] - y[c]) ** 2)) for c in x))
+    den = math.sqrt(sum(float(np.sum(y[c] ** 2)) for c in y))
+    return num / den if den > 0 else 0.0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=800)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--modes", default="threshold,all_pic",
+                    help="comma list of switch modes to run (profiling runs may pick one)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the multi-GPU path (domain decomposition) is not "
               "part of this build; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     from paper_2510_11174_amd import configs
+    if args.calibrate_copy:
+        copy_calibration()
+        return
 
     W, K = args.warmup, args.steps
+    half = K // 2 if K >= 2 else None
+    modes = [m for m in args.modes.split(",") if m]
+    if any(m not in ("threshold", "all_pic") for m in modes) or not modes:
+        print("--modes takes threshold and/or all_pic", file=sys.stderr)
+        sys.exit(2)
     res = {}
-    for mode in ("threshold", "all_pic"):
+    for mode in modes:
         cfg = configs.ionization_hybrid(mode=mode)
-        print("bench: %s %s warmup %d steps %d" % (cfg["name"], mode, W, K), file=sys.stderr,
+        print("bench: %s %s warm-up %d, timed steps 0-%d" % (cfg["name"], mode, W, K), file=sys.stderr,
               flush=True)
-        res[mode] = run_gpu(cfg, K, W, args.precision)
+        if W > 0:
+            warm_up(cfg, W, args.precision)
+        res[mode] = run_gpu(cfg, K, args.precision, snap_at=half)
+    if len(res) < 2:
+        r = next(iter(res.values()))
+        print(json.dumps({"mode": modes[0], "steps_per_s": K / r["seconds"], "timers": r["timers"]}))
+        return
     h, p = res["threshold"], res["all_pic"]
+    # the same all-PIC run again: FP32 atomics make the sums order dependent,
+    # so two identical runs differ; this is the floor of any comparison
+    print("bench: all-PIC repeat (run-to-run floor)", file=sys.stderr, flush=True)
+    p2 = run_gpu(configs.ionization_hybrid(mode="all_pic"), K, args.precision, timing=False, snap_at=half)
     hyb_sps = K / h["seconds"]
     pic_sps = K / p["seconds"]
-    num = math.sqrt(sum(float(np.sum((h["fields"][c] - p["fields"][c]) ** 2)) for c in h["fields"]))
-    den = math.sqrt(sum(float(np.sum(p["fields"][c] ** 2)) for c in p["fields"]))
-    field_l2 = num / den if den > 0 else 0.0
+    l2 = {s: field_l2(h["snaps"][s], p["snaps"][s]) for s in p["snaps"]}
+    floor = {s: field_l2(p2["snaps"][s], p["snaps"][s]) for s in p["snaps"]}
     e_h, e_p = total_energy(h["diag"]), total_energy(p["diag"])
     drift = abs(e_h - e_p) / abs(e_p) if e_p else 0.0
+    traffic = measured_traffic()
 
-    def roof(r):
+    def roof(r, with_traffic):
         tm = r["timers"]
         ms = tm["push_kernel_ms"]
         alg = BYTES_PER_PUSH * tm["particles_pushed"] + BYTES_PER_TILE_CELL * TILE_CELLS * tm["tiles_pushed"]
         launches = max(tm["push_launches"], 1)
         achieved = alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic if with_traffic else None,
                 "kernel": "k_push", "avg_launch_ms": round(ms / launches, 4),
                 "alg_bytes_per_launch": round(alg / launches)}
 
@@ -143,18 +235,20 @@ def main():
         "dtype": "f32" if args.precision == "f32" else "f64",
         "data": "synthetic",
         "config": {"workload": "ionizing helium 128x64x64, dx 0.1, 8 ppc, a0 10, threshold switch "
-                               "vs all-PIC, steps %d-%d" % (W, W + K),
+                               "vs all-PIC, steps 0-%d from t = 0" % K,
                    "grid": [128, 64, 64], "ppc": 8, "switch": "threshold"},
         "allpic_steps_per_s": round(pic_sps, 2),
         "speedup_vs_allpic": round(hyb_sps / pic_sps, 3),
         "pushes_per_s": round(h["timers"]["particles_pushed"] / h["seconds"], 1),
         "allpic_pushes_per_s": round(p["timers"]["particles_pushed"] / p["seconds"], 1),
-        "field_rel_l2_vs_allpic": field_l2,
+        "cell_steps_per_s": round(128 * 64 * 64 * hyb_sps, 1),
+        "field_rel_l2_vs_allpic": {str(k): v for k, v in l2.items()},
+        "field_rel_l2_allpic_repeat": {str(k): v for k, v in floor.items()},
         "energy_diff_vs_allpic": drift,
-        "field_err_ok": field_l2 <= 1e-3,
-        "kinetic_fraction": h["diag"]["kinetic_fraction"],
-        "roofline": roof(p),
-        "roofline_hybrid": roof(h),
+        "field_err_ok": l2[K] <= max(1e-3, floor[K]),
+        "kinetic_fraction_end": h["kinetic_fraction"],
+        "roofline": roof(p, True),
+        "roofline_hybrid": roof(h, False),
         "timers_hybrid_ms_per_step": {k: round(v / K, 4) for k, v in h["timers"].items() if k.endswith("_ms")},
         "timers_allpic_ms_per_step": {k: round(v / K, 4) for k, v in p["timers"].items() if k.endswith("_ms")},
         "rebins": {"hybrid": h["timers"]["rebins"], "all_pic": p["timers"]["rebins"]},

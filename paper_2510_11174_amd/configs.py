@@ -29,9 +29,11 @@ def _grid(nx, ny, nz, d, cfl=0.95, bc_x="open"):
 
 
 def _run(seed, mode="threshold", **kw):
+    # thr_sigma_u = 0.02: at 0.05 the ionizing-helium run converts warm electrons
+    # (spread 0.02-0.05) to cold fluid and its fields drift far from all-PIC
     r = {"seed": seed, "switch_mode": mode, "switch_every": 1, "dilation": 1, "hysteresis": 2,
          "enable_ionization": False, "enable_qed": False, "thr_a": 0.5, "thr_grad": 0.2,
-         "thr_sigma_u": 0.05, "thr_ion": 1e-6, "thr_chi": 1e-3, "n_floor": 1e-10,
+         "thr_sigma_u": 0.02, "thr_ion": 1e-6, "thr_chi": 1e-3, "n_floor": 1e-10,
          "spawn_frac": 0.5}
     r.update(kw)
     return r

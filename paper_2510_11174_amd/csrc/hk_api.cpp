@@ -15,52 +15,6 @@
 
 #include "hk_internal.h"
 
-// launchers defined in the kernel files
-void launch_init_species_cols(const GridP &g, const hk_species_desc &d, uint64_t seed, PArr out,
-                              const int *xcol, const double *wcol, int ncol, int has_z,
-                              int has_tau, hipStream_t s);
-void launch_count_groups(const GridP &g, PArr src, const long long *off, const int *nf,
-                         const int *nb, const int *cap, int ngroups, long long maxn, int *newcnt,
-                         hipStream_t s);
-void launch_scatter_groups(const GridP &g, PArr src, const long long *off, const int *nf,
-                           const int *nb, const int *cap, int ngroups, long long maxn, PArr dst,
-                           const long long *doff, int *dfill, int has_z, int has_tau,
-                           hipStream_t s);
-void launch_merge_inbox(const GridP &g, const SpecP &sp, PArr inbox, const int *inbox_n,
-                        long long max_n, PArr dst, const int *nf, int *nb, int *fail_n, PArr fail,
-                        int *err, hipStream_t s);
-void launch_migrate(const GridP &g, const SpecP &sp, PArr mig, const long long *moff,
-                    const int *mcnt, PArr dst, const int *nf, int *nb, int *fail_n, PArr fail,
-                    int fail_cap, int *err, hipStream_t s);
-void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
-                       int *nf_out, PArr mig, const long long *moff, const int *mcap, int *mcnt,
-                       PArr inbox, int *inbox_n, int inbox_cap, real *const f[9], int *err,
-                       unsigned long long *stats, const unsigned *wmax_bits, hipStream_t s);
-void launch_ionize_static(const GridP &g, const SpecP &sp, PArr a, Bins b, int *active,
-                          real *const f[9], const uint8_t *sw, int hybrid, const IonP *ion,
-                          PArr eout, int *eout_n, int eout_cap, uint64_t seed, int step,
-                          double *ledger, int *err, hipStream_t s);
-void launch_count_active(const GridP &g, const SpecP &sp, PArr a, Bins b, int zmax, int *active,
-                         hipStream_t s);
-void launch_rho_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, double *rho, hipStream_t s);
-void launch_moments_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, int ion_only,
-                          int zmax, real *mom, hipStream_t s);
-void launch_fluid_moments_nodes(const GridP &g, real inv_ppc, const real *n, const real *ux,
-                                const real *uy, const real *uz, real *mom, hipStream_t s);
-void launch_indicators_nodes(const GridP &g, const SwitchP &P, const real *mom, real *const f[9],
-                             const IonP *const *ions, int nion, uint8_t *hot, uint8_t *notcold,
-                             hipStream_t s);
-void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, const uint8_t *notcold,
-                         uint8_t *sw, uint8_t *calm, hipStream_t s);
-void launch_absorb_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, const uint8_t *sw,
-                         real *const f[9], double *macc, double *ledger, hipStream_t s);
-void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n, real *ux,
-                                real *uy, real *uz, double *ledger, hipStream_t s);
-void launch_spawn_nodes(const GridP &g, const SpecP &sp, const uint8_t *sw, real *n, real *ux,
-                        real *uy, real *uz, real *const f[9], real wmin, int m, uint64_t seed,
-                        int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
-                        unsigned *wmax_bits, hipStream_t s);
-
 namespace {
 
 // Physical constants (CODATA 2018) for the SI scale of ionization and QED.
@@ -92,6 +46,9 @@ struct DevSpecies {
     real *fn = nullptr, *fu[3] = {nullptr, nullptr, nullptr};  // cold fluid
     IonP *ion = nullptr;          // device rate constants
     long long reserve_hint = 0;   // expected peak count (ionization targets)
+    unsigned *umax2 = nullptr;    // device [ntiles]: bound on |u|^2 (float bits) since the
+                                  // last switch evaluation, raised by push, ionization, spawn
+    bool umax_ok = false;         // false: particles changed outside those kernels
 };
 
 }  // namespace
@@ -117,6 +74,7 @@ struct hk_sim {
     int *status = nullptr;       // [0] error bits, [1 + 2s] inbox count, [2 + 2s] fail count,
                                  // [13] spawns deferred for lack of inbox room
     int *h_status = nullptr;     // pinned
+    hipEvent_t status_ev = nullptr;  // recorded after the status copy to h_status
     int have_gauss0 = 0;
     int64_t step = 0;
     double t = 0;
@@ -252,14 +210,20 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     std::vector<int> h(nt);
     HIPCHK(S, hipMemcpyAsync(h.data(), newcnt, sizeof(int) * nt, hipMemcpyDeviceToHost, S->s));
     HIPCHK(S, hipStreamSynchronize(S->s));
-    // capacity: 50% headroom plus 128 slots, at least the reserve hint share
+    // capacity: twice the larger of the tile's count and the species' mean
+    // count per tile, plus 256 slots, at least the reserve hint share.  Local
+    // density spikes (a laser snow-plough) then rarely overflow a bin; spare
+    // slots cost memory only, never traffic (kernels touch occupied slots).
     long long hint_per_tile = D.reserve_hint > 0 ? (D.reserve_hint + nt - 1) / nt : 0;
+    long long hsum = 0;
+    for (int t = 0; t < nt; ++t) hsum += h[t];
+    const long long mean = (hsum + nt - 1) / nt;
     std::vector<long long> off(nt), moff(nt);
     std::vector<int> cap(nt), mcap(nt);
     long long total = 0, mtotal = 0;
     int maxc = 0;
     for (int t = 0; t < nt; ++t) {
-        long long c = (long long)h[t] + h[t] / 2 + 128;
+        long long c = 2 * std::max<long long>(h[t], mean) + 256;
         long long hc = hint_per_tile + hint_per_tile / 4 + 128;
         c = std::max(c, std::min<long long>(hc, INT_MAX / 4));
         c = (c + 63) & ~63LL;
@@ -381,6 +345,25 @@ int build_ion_table(hk_sim *S, int isp) {
         L.fc = P.omega_au * std::sqrt(2.0 * L.ip_au) / 1.5;
         L.wfc = L.c2 * L.ip_au * std::pow(2.0 * L.k3 / L.fc, L.expo) * std::exp(-2.0 * L.k3 / (3.0 * L.fc));
         L.K2 = 2.0 * std::ceil(L.ip_au / P.omega_au);
+        // Below F_skip the blended rate is under max(w_MPI, w_ADK), which rises
+        // monotonically up to the ADK maximum at F = 2 k3 / (3 expo); keep the
+        // step probability under 1e-9, far below the smallest uniform draw
+        // (2^-24), so skipping the rate there changes no event.
+        auto bound = [&](double F) {
+            double wm = L.wfc * std::pow(std::fmin(F, L.fc) / L.fc, L.K2);
+            double wa = L.c2 * L.ip_au * std::pow(2.0 * L.k3 / F, L.expo) * std::exp(-2.0 * L.k3 / (3.0 * F));
+            return std::fmax(wm, wa) * P.rate_norm * S->gd.dt;
+        };
+        double lo = 1e-12, hi = std::fmin(1.0, 2.0 * L.k3 / (3.0 * std::fmax(L.expo, 1e-3)));
+        if (!(bound(lo) < 1e-9)) L.fskip = 0.0;
+        else if (bound(hi) < 1e-9) L.fskip = hi;
+        else {
+            for (int it = 0; it < 200; ++it) {
+                double mid = std::sqrt(lo * hi);
+                if (bound(mid) < 1e-9) lo = mid; else hi = mid;
+            }
+            L.fskip = lo;
+        }
     }
     D.ion = (IonP *)dalloc(S, sizeof(IonP));
     if (!D.ion) return fail(S, HK_ENOMEM, "ion table");
@@ -394,7 +377,10 @@ int init_species(hk_sim *S, int isp) {
     const hk_species_desc &d = D.d;
     D.g_off0 = (long long *)dalloc(S, sizeof(long long));
     D.g_capmax = (int *)dalloc(S, sizeof(int));
-    if (!D.g_off0 || !D.g_capmax) return fail(S, HK_ENOMEM, "species tables");
+    D.umax2 = (unsigned *)dalloc(S, sizeof(unsigned) * g.ntiles);
+    if (!D.g_off0 || !D.g_capmax || !D.umax2) return fail(S, HK_ENOMEM, "species tables");
+    launch_zero(D.umax2, sizeof(unsigned) * g.ntiles, S->s);
+    D.umax_ok = false;
     std::vector<int> xcol;
     std::vector<double> wcol;
     double dv = g.ddx * g.ddy * g.ddz;
@@ -470,10 +456,7 @@ void time_mark(hk_sim *S, int slot) {
     if (S->spans.size() > 2048) ev_resolve(S);
 }
 
-int check_status(hk_sim *S) {
-    HIPCHK(S, hipMemcpyAsync(S->h_status, S->status, sizeof(int) * 16,
-                             hipMemcpyDeviceToHost, S->s));
-    HIPCHK(S, hipStreamSynchronize(S->s));
+int status_error(hk_sim *S) {
     int e = S->h_status[0];
     if (e & ERR_NONFINITE) return fail(S, HK_ENUMERIC, "non-finite momentum at step %lld", (long long)S->step);
     if (e & ERR_CFL) return fail(S, HK_ENUMERIC, "particle moved a cell or more at step %lld", (long long)S->step);
@@ -498,9 +481,11 @@ long long inbox_need(hk_sim *S, int isp) {
     return need;
 }
 
-// Append every species' inbox to the back of its current bins; re-bin when
-// bins are full.  Reads the device status once (one host synchronisation).
-int merge_all(hk_sim *S) {
+// Append every species' inbox to the back of its current bins and start the
+// copy of the device status to the host (merge_launch); work that does not
+// touch the particle bins may be enqueued before merge_finish waits for the
+// status, re-bins species whose bins were full and clears the counters.
+int merge_launch(hk_sim *S) {
     for (int isp = 0; isp < S->nsp; ++isp) {
         DevSpecies &D = S->sp[isp];
         if (D.capacity == 0) continue;
@@ -509,8 +494,16 @@ int merge_all(hk_sim *S) {
         launch_merge_inbox(S->g, P, D.inbox, inbox_n, D.inbox_cap, D.buf[D.cur], D.nf[D.cur],
                            D.nb[D.cur], fail_n, D.fail, S->status, S->s);
     }
-    int rc = check_status(S);
+    HIPCHK(S, hipMemcpyAsync(S->h_status, S->status, sizeof(int) * 16, hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipEventRecord(S->status_ev, S->s));
+    return HK_OK;
+}
+
+int merge_finish(hk_sim *S) {
+    HIPCHK(S, hipEventSynchronize(S->status_ev));
+    int rc = status_error(S);
     if (rc) return rc;
+    bool rebinned = false;
     for (int isp = 0; isp < S->nsp; ++isp) {
         DevSpecies &D = S->sp[isp];
         int nfail = S->h_status[2 + 2 * isp];
@@ -520,13 +513,19 @@ int merge_all(hk_sim *S) {
             long long lmax[1] = {D.inbox_cap};
             rc = rebuild(S, isp, true, lists, &ln, lmax, 1);
             if (rc) return rc;
-        }
-        HIPCHK(S, hipMemsetAsync(S->status + 1 + 2 * isp, 0, 2 * sizeof(int), S->s));
-        if (nfail > 0 && D.d.mobile) {
-            rc = ensure_inbox(S, isp, inbox_need(S, isp));
-            if (rc) return rc;
+            rebinned = true;
         }
     }
+    // inbox and fail counters of every species (status[1 .. 2 nsp])
+    launch_zero(S->status + 1, sizeof(int) * 2 * HK_MAX_SPECIES, S->s);
+    if (rebinned)
+        for (int isp = 0; isp < S->nsp; ++isp) {
+            DevSpecies &D = S->sp[isp];
+            if (S->h_status[2 + 2 * isp] > 0 && D.d.mobile) {
+                rc = ensure_inbox(S, isp, inbox_need(S, isp));
+                if (rc) return rc;
+            }
+        }
     return HK_OK;
 }
 
@@ -553,20 +552,36 @@ SwitchP switch_params(const hk_sim *S) {
 void switch_eval(hk_sim *S) {
     hipStream_t s = S->s;
     const GridP &g = S->g;
-    launch_zero(S->mom, sizeof(real) * 7 * (size_t)g.nn, s);
+    // fluid moments first: the first fluid species overwrites the arrays
+    int first = 1;
+    for (int isp = 0; isp < S->nsp; ++isp) {
+        DevSpecies &D = S->sp[isp];
+        if (!D.d.fluid || !D.fn) continue;
+        launch_fluid_moments_nodes(g, (real)(1.0 / std::max(1, D.d.ppc)), D.fn, D.fu[0], D.fu[1],
+                                   D.fu[2], S->mom, first, s);
+        first = 0;
+    }
+    if (first) launch_zero(S->mom, sizeof(real) * 7 * (size_t)g.nn, s);
     const IonP *ions[4];
     int nion = 0;
     for (int isp = 0; isp < S->nsp; ++isp) {
         DevSpecies &D = S->sp[isp];
         SpecP P = specp(D);
-        if (D.d.fluid && D.capacity) launch_moments_tiles(g, P, D.buf[D.cur], cur_bins(D), 0, 0, S->mom, s);
-        if (D.d.fluid && D.fn)
-            launch_fluid_moments_nodes(g, (real)(1.0 / std::max(1, D.d.ppc)), D.fn, D.fu[0], D.fu[1],
-                                       D.fu[2], S->mom, s);
+        if (D.d.fluid && D.capacity)
+            launch_moments_tiles(g, P, D.buf[D.cur], cur_bins(D), 0, 0, S->mom, S->wmax + isp,
+                                 D.d.mobile && D.umax_ok ? D.umax2 : nullptr, nullptr, s);
         if (D.d.ionizable && S->run.enable_ionization && D.capacity) {
-            launch_moments_tiles(g, P, D.buf[D.cur], cur_bins(D), 1, D.d.z_max, S->mom, s);
+            launch_moments_tiles(g, P, D.buf[D.cur], cur_bins(D), 1, D.d.z_max, S->mom, S->wmax + isp,
+                                 nullptr, D.d.mobile ? nullptr : D.active, s);
             if (nion < 4) ions[nion++] = D.ion;
         }
+    }
+    // the |u|^2 bounds start again from here
+    for (int isp = 0; isp < S->nsp; ++isp) {
+        DevSpecies &D = S->sp[isp];
+        if (!D.d.fluid || !D.d.mobile) continue;
+        launch_zero(D.umax2, sizeof(unsigned) * g.ntiles, s);
+        D.umax_ok = true;
     }
     SwitchP P = switch_params(S);
     launch_indicators_nodes(g, P, S->mom, S->f, ions, nion, S->hot, S->notcold, s);
@@ -590,7 +605,7 @@ void reconcile(hk_sim *S) {
         real wmin = (real)(S->run.spawn_frac * D.d.n0 * dv / m);
         launch_spawn_nodes(g, P, S->sw, D.fn, D.fu[0], D.fu[1], D.fu[2], S->f, wmin, m, S->run.seed,
                            (int)S->step, D.inbox, S->status + 1 + 2 * isp, D.inbox_cap,
-                           S->status + 13, S->wmax + isp, s);
+                           S->status + 13, S->wmax + isp, D.umax2, s);
     }
 }
 
@@ -620,7 +635,7 @@ int one_step(hk_sim *S) {
             hipEvent_t pa = S->timing ? ev_get(S) : nullptr;
             launch_push_tiles(g, P, D.buf[D.cur], cur_bins(D), D.buf[nxt], D.nf[nxt], D.mig, D.moff,
                               D.mcap, D.mcnt, D.inbox, S->status + 1 + 2 * isp, D.inbox_cap, S->f,
-                              S->status, S->dstat, S->wmax + isp, s);
+                              S->status, S->dstat, S->wmax + isp, D.umax2, s);
             if (S->timing) {
                 S->spans.push_back({pa, ev_get(S), 6});
                 S->timers[8] += 1;
@@ -631,7 +646,7 @@ int one_step(hk_sim *S) {
             DevSpecies &T = S->sp[D.d.target];
             launch_ionize_static(g, P, D.buf[D.cur], cur_bins(D), D.active, S->f, S->sw, hybrid,
                                  D.ion, T.inbox, S->status + 1 + 2 * D.d.target, T.inbox_cap,
-                                 S->run.seed, (int)S->step, S->ledger + 1, S->status, s);
+                                 S->run.seed, (int)S->step, S->ledger + 1, S->status, T.umax2, s);
         }
     }
     for (int isp = 0; isp < S->nsp; ++isp) {
@@ -639,30 +654,33 @@ int one_step(hk_sim *S) {
         if (D.capacity && D.d.mobile && D.d.kind != HK_PHOTON) D.cur = 1 - D.cur;
     }
     time_mark(S, 1);
-    // 4. newborn and overflow particles join their bins
-    int rc = merge_all(S);
+    // 4. newborn and overflow particles join their bins; 5. cold fluid (it
+    // does not read the bins, so it runs while the host waits for the status);
+    // 6. conversion; 7. fields (likewise before the second status wait)
+    int rc = merge_launch(S);
     if (rc) return rc;
-    time_mark(S, 5);
-    // 5. cold fluid, 6. conversion
     if (hybrid) {
         for (int isp = 0; isp < S->nsp; ++isp) {
             DevSpecies &D = S->sp[isp];
             if (D.fn) launch_fluid(g, specp(D), D.fn, D.fu[0], D.fu[1], D.fu[2], S->f,
                                    S->fluid_scratch, (real)S->run.n_floor, s);
         }
-    }
-    time_mark(S, 2);
-    if (hybrid) {
-        reconcile(S);
-        rc = merge_all(S);
+        time_mark(S, 2);
+        rc = merge_finish(S);
         if (rc) return rc;
+        time_mark(S, 5);
+        reconcile(S);
+        rc = merge_launch(S);
+        if (rc) return rc;
+        time_mark(S, 3);
     }
-    time_mark(S, 3);
-    // 7. fields
     launch_yee_b_half(g, S->f, s);
     launch_yee_e_full(g, S->f, S->mur_old, s);
     launch_yee_b_half(g, S->f, s);
     time_mark(S, 4);
+    rc = merge_finish(S);
+    if (rc) return rc;
+    time_mark(S, 5);
     S->step++;
     S->t = S->step * g.ddt;
     return HK_OK;
@@ -676,7 +694,7 @@ int ensure_fluid(hk_sim *S) {
         S->macc = (double *)dalloc(S, sizeof(double) * 4 * (size_t)g.nn);
         S->hot = (uint8_t *)dalloc(S, (size_t)g.nn);
         S->notcold = (uint8_t *)dalloc(S, (size_t)g.nn);
-        S->fluid_scratch = (real *)dalloc(S, sizeof(real) * 18 * (size_t)g.nn);
+        S->fluid_scratch = (real *)dalloc(S, sizeof(real) * 7 * (size_t)g.nn);
         if (!S->mom || !S->macc || !S->hot || !S->notcold || !S->fluid_scratch)
             return fail(S, HK_ENOMEM, "switch arrays");
     }
@@ -797,8 +815,11 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
     S->wmax = (unsigned *)dalloc(S, sizeof(unsigned) * HK_MAX_SPECIES);
     if (hipHostMalloc((void **)&S->h_status, sizeof(int) * 16, 0) != hipSuccess)
         S->h_status = nullptr;
+    if (hipEventCreateWithFlags(&S->status_ev, hipEventDisableTiming) != hipSuccess)
+        S->status_ev = nullptr;
     if (!S->fblock || !S->mur_old || !S->sw || !S->calm || !S->gauss0 || !S->tmp_a || !S->tmp_b ||
-        !S->dsum || !S->ledger || !S->status || !S->h_status || !S->dstat || !S->wmax) {
+        !S->dsum || !S->ledger || !S->status || !S->h_status || !S->dstat || !S->wmax ||
+        !S->status_ev) {
         hk_destroy(S);
         return HK_ENOMEM;
     }
@@ -851,6 +872,7 @@ void hk_destroy(hk_sim *S) {
     ev_resolve(S);
     for (hipEvent_t e : S->ev_free) (void)hipEventDestroy(e);
     if (S->last_mark) (void)hipEventDestroy(S->last_mark);
+    if (S->status_ev) (void)hipEventDestroy(S->status_ev);
     delete S;
 }
 
@@ -1030,6 +1052,7 @@ int hk_set_particles(hk_sim *S, int isp, const hk_particles *in) {
     if (S->poisoned) return HK_ESTATE;
     DevSpecies &D = S->sp[isp];
     const GridP &g = S->g;
+    D.umax_ok = false;   // momenta set from the host: the next evaluation scans them
     const size_t n = in->n;
     std::vector<int> cell(n), zc(n);
     std::vector<real> r[7];

@@ -119,6 +119,7 @@ enum { ERR_NONFINITE = 1, ERR_CFL = 2, ERR_INBOX = 4, ERR_TILE = 8 };
 // Device-side rate tables for ionization (per species, per level).
 struct IonLevel {
     double ip_au, zres, c2, k3, expo, fc, wfc, K2;  // constants of the ADK/MPI blend
+    double fskip;  // fields below this give a step probability under the smallest draw
 };
 struct IonP {
     double field_au;   // atomic field units per normalized field unit
@@ -164,19 +165,52 @@ struct SwitchP {
     int dilation, hysteresis, enable_qed, enable_ion;
     double a_s;   // QED normalized Schwinger field
 };
-void launch_moments(const GridP &g, const SpecP &sp, PArr a, const int *cnt, float *mom,
-                    hipStream_t s);
-void launch_fluid_moments(const GridP &g, const SpecP &sp, const real *n, const real *ux,
-                          const real *uy, const real *uz, float *mom, hipStream_t s);
-void launch_indicators(const GridP &g, const SwitchP &P, const float *mom, real *const f[9],
-                       const IonP *ion, int n_ion_species, uint8_t *hot, uint8_t *notcold,
+
+// particle, switch and conversion launchers (k_particles.hip, k_switch.hip)
+void launch_init_species_cols(const GridP &g, const hk_species_desc &d, uint64_t seed, PArr out,
+                              const int *xcol, const double *wcol, int ncol, int has_z,
+                              int has_tau, hipStream_t s);
+void launch_count_groups(const GridP &g, PArr src, const long long *off, const int *nf,
+                         const int *nb, const int *cap, int ngroups, long long maxn, int *newcnt,
+                         hipStream_t s);
+void launch_scatter_groups(const GridP &g, PArr src, const long long *off, const int *nf,
+                           const int *nb, const int *cap, int ngroups, long long maxn, PArr dst,
+                           const long long *doff, int *dfill, int has_z, int has_tau,
+                           hipStream_t s);
+void launch_merge_inbox(const GridP &g, const SpecP &sp, PArr inbox, const int *inbox_n,
+                        long long max_n, PArr dst, const int *nf, int *nb, int *fail_n, PArr fail,
+                        int *err, hipStream_t s);
+void launch_migrate(const GridP &g, const SpecP &sp, PArr mig, const long long *moff,
+                    const int *mcnt, PArr dst, const int *nf, int *nb, int *fail_n, PArr fail,
+                    int fail_cap, int *err, hipStream_t s);
+void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
+                       int *nf_out, PArr mig, const long long *moff, const int *mcap, int *mcnt,
+                       PArr inbox, int *inbox_n, int inbox_cap, real *const f[9], int *err,
+                       unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
                        hipStream_t s);
-void launch_dilate(const GridP &g, const SwitchP &P, const uint8_t *hot, const uint8_t *notcold,
-                   uint8_t *sw, uint8_t *calm, hipStream_t s);
-void launch_absorb(const GridP &g, const SpecP &sp, PArr a, const int *cnt, const uint8_t *sw,
-                   real *const f[9], double *macc, hipStream_t s);
-void launch_absorb_finish(const GridP &g, const SpecP &sp, const double *macc, real *n,
-                          real *ux, real *uy, real *uz, double *ledger, hipStream_t s);
-void launch_spawn(const GridP &g, const SpecP &sp, const uint8_t *sw, real *n, real *ux,
-                  real *uy, real *uz, real *const f[9], real wmin, int ppc, uint64_t seed,
-                  int step, PArr inbox, int *inbox_n, int inbox_cap, int *err, hipStream_t s);
+void launch_ionize_static(const GridP &g, const SpecP &sp, PArr a, Bins b, int *active,
+                          real *const f[9], const uint8_t *sw, int hybrid, const IonP *ion,
+                          PArr eout, int *eout_n, int eout_cap, uint64_t seed, int step,
+                          double *ledger, int *err, unsigned *umax2, hipStream_t s);
+void launch_count_active(const GridP &g, const SpecP &sp, PArr a, Bins b, int zmax, int *active,
+                         hipStream_t s);
+void launch_rho_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, double *rho, hipStream_t s);
+void launch_moments_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, int ion_only,
+                          int zmax, real *mom, const unsigned *wmax_bits, const unsigned *umax2,
+                          const int *active, hipStream_t s);
+void launch_fluid_moments_nodes(const GridP &g, real inv_ppc, const real *n, const real *ux,
+                                const real *uy, const real *uz, real *mom, int first,
+                                hipStream_t s);
+void launch_indicators_nodes(const GridP &g, const SwitchP &P, const real *mom, real *const f[9],
+                             const IonP *const *ions, int nion, uint8_t *hot, uint8_t *notcold,
+                             hipStream_t s);
+void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, const uint8_t *notcold,
+                         uint8_t *sw, uint8_t *calm, hipStream_t s);
+void launch_absorb_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, const uint8_t *sw,
+                         real *const f[9], double *macc, double *ledger, hipStream_t s);
+void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n, real *ux,
+                                real *uy, real *uz, double *ledger, hipStream_t s);
+void launch_spawn_nodes(const GridP &g, const SpecP &sp, const uint8_t *sw, real *n, real *ux,
+                        real *uy, real *uz, real *const f[9], real wmin, int m, uint64_t seed,
+                        int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
+                        unsigned *wmax_bits, unsigned *umax2, hipStream_t s);

@@ -207,10 +207,12 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
        const real *__restrict__ Ey, const real *__restrict__ Ez, const real *__restrict__ Bx,
        const real *__restrict__ By, const real *__restrict__ Bz, real *__restrict__ Jx,
        real *__restrict__ Jy, real *__restrict__ Jz, int *__restrict__ err,
-       unsigned long long *__restrict__ stats, const unsigned *__restrict__ wmax_bits) {
+       unsigned long long *__restrict__ stats, const unsigned *__restrict__ wmax_bits,
+       unsigned *__restrict__ umax2) {
     __shared__ real sF[6 * FT3];
     __shared__ jacc_t sJ[3 * JT3];
     __shared__ int s_stay, s_move;
+    __shared__ unsigned s_u2;
     const int t = blockIdx.x;
     int nfi, nbi;
     const int n = bin_count(sp, bin_in, t, nfi, nbi);
@@ -241,11 +243,12 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
         sF[5 * FT3 + e] = Bz[ch];
     }
     for (int e = threadIdx.x; e < 3 * JT3; e += PBS) sJ[e] = 0;
-    if (threadIdx.x == 0) { s_stay = 0; s_move = 0; }
+    if (threadIdx.x == 0) { s_stay = 0; s_move = 0; s_u2 = 0; }
     __syncthreads();
 
     const real dv = g.dx * g.dy * g.dz;
     const real hq = (real)0.5 * sp.qm * g.dt;
+    float u2max = 0.f;   // largest |u|^2 pushed by this thread
     const int lane = __lane_id();
     const uint64_t lt = (1ull << lane) - 1ull;
     const long long obase = sp.off[t];
@@ -331,6 +334,7 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
                 atomicOr(err, isfinite(ux + uy + uz) ? ERR_CFL : ERR_NONFINITE);
                 valid = false;
             } else {
+                u2max = fmaxf(u2max, (float)(ux * ux + uy * uy + uz * uz));
                 // Esirkepov deposit of J^{n+1/2}
                 if (sp.q != (real)0) {
                     AxisS SX = axis_shapes(rx, X1), SY = axis_shapes(ry, Y1), SZ = axis_shapes(rz, Z1);
@@ -387,8 +391,13 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
             if (sp.has_tau) dst.tau[j] = tau;
         }
     }
+    // per-tile bound on |u|^2 of the pushed particles (non-negative float bits
+    // order like unsigned integers); read by the next switch evaluation
+    for (int o = 32; o > 0; o >>= 1) u2max = fmaxf(u2max, __shfl_xor(u2max, o));
+    if (lane == 0 && u2max > 0.f) atomicMax(&s_u2, __float_as_uint(u2max));
     __syncthreads();
     if (threadIdx.x == 0) {
+        if (s_u2) atomicMax(&umax2[t], s_u2);
         nf_out[t] = s_stay;          // stayers never exceed the bin: they were in it
         mcnt[t] = min(s_move, mlim);
         atomicAdd(&stats[0], (unsigned long long)(s_stay + s_move));   // particles pushed
@@ -431,7 +440,7 @@ k_ionize_static(GridP g, SpecP sp, PArr a, Bins bins, int *__restrict__ active,
                 const real *__restrict__ Ex, const real *__restrict__ Ey, const real *__restrict__ Ez,
                 const uint8_t *__restrict__ sw, int hybrid, const IonP *__restrict__ ion, PArr eout,
                 int *__restrict__ eout_n, int eout_cap, uint64_t seed, int step,
-                double *__restrict__ ledger, int *__restrict__ err) {
+                double *__restrict__ ledger, int *__restrict__ err, unsigned *__restrict__ umax2) {
     __shared__ real sF[3 * FT3];
     const int t = blockIdx.x;
     int nf, nbv;
@@ -456,55 +465,91 @@ k_ionize_static(GridP g, SpecP sp, PArr a, Bins bins, int *__restrict__ active,
     }
     __syncthreads();
     const double omega = ion->omega_au;
+    const int zmax = ion->z_max;
+    const int lane = __lane_id();
     int done = 0;
-    for (int p = threadIdx.x; p < n; p += BS) {
-        const long long ip = bin_slot(sp, t, p, nf, nbv);
-        int cell = a.cell[ip];
-        if (cell < 0) continue;
-        int zc = a.zc[ip];
-        if (zc >= ion->z_max) continue;
-        const int ci = cell % g.nx, rr = cell / g.nx;
-        const int cj = rr % g.ny, ck = rr / g.ny;
-        const real rx = a.rx[ip], ry = a.ry[ip], rz = a.rz[ip];
-        if (hybrid) {
-            int ni = ci + (rx >= (real)0.5), nj = cj + (ry >= (real)0.5), nk = ck + (rz >= (real)0.5);
-            if (per) ni = wrapi(ni, g.nx);
-            if (nj >= g.ny) nj -= g.ny;
-            if (nk >= g.nz) nk -= g.nz;
-            if (!sw[gidx(g, ni, nj, nk)]) continue;
+    // uniform trip count so that every lane of a wave takes part in the
+    // event-slot scan below
+    for (int p0 = 0; p0 < n; p0 += BS) {
+        const int p = p0 + threadIdx.x;
+        long long ip = 0;
+        int z0 = 0, nev = 0, cell = -1;
+        real rx = 0, ry = 0, rz = 0;
+        if (p < n) {
+            ip = bin_slot(sp, t, p, nf, nbv);
+            cell = a.cell[ip];
+            if (cell >= 0) z0 = a.zc[ip];
+        }
+        bool live = cell >= 0 && z0 < zmax;
+        int ci = 0, cj = 0, ck = 0;
+        if (live) {
+            cell_ijk(g, cell, ci, cj, ck);
+            rx = a.rx[ip]; ry = a.ry[ip]; rz = a.rz[ip];
+            if (hybrid) {
+                int ni = ci + (rx >= (real)0.5), nj = cj + (ry >= (real)0.5), nk = ck + (rz >= (real)0.5);
+                if (per) ni = wrapi(ni, g.nx);
+                if (nj >= g.ny) nj -= g.ny;
+                if (nk >= g.nz) nk -= g.nz;
+                if (!sw[gidx(g, ni, nj, nk)]) live = false;
+            }
         }
         const int lx = ci - ox, ly = cj - oy, lz = ck - oz;
-        if ((unsigned)lx >= TILE || (unsigned)ly >= TILE || (unsigned)lz >= TILE) {
+        if (live && ((unsigned)lx >= TILE || (unsigned)ly >= TILE || (unsigned)lz >= TILE)) {
             atomicOr(err, ERR_TILE);
-            continue;
+            live = false;
         }
-        AxisW X = axis_weights(lx, rx), Y = axis_weights(ly, ry), Z = axis_weights(lz, rz);
-        double ex = tri(sF + 0 * FT3, X.ih, Y.in_, Z.in_, X.fh, Y.fn, Z.fn);
-        double ey = tri(sF + 1 * FT3, X.in_, Y.ih, Z.in_, X.fn, Y.fh, Z.fn);
-        double ez = tri(sF + 2 * FT3, X.in_, Y.in_, Z.ih, X.fn, Y.fn, Z.fh);
-        double F = sqrt(ex * ex + ey * ey + ez * ez) * ion->field_au;
-        const uint64_t pid = a.id[ip];
-        int z0 = zc;
-        for (int lev = zc; lev < ion->z_max; ++lev) {
-            double wr = blended_rate(ion->lev[lev], F, omega) * ion->rate_norm;
-            double P = -expm1(-wr * g.ddt);
-            uint32_t r[4];
-            draw4(seed, pid, (uint32_t)step, TAG_ION + (uint32_t)lev, 0, r);
-            if (!(u01d(r[0]) < P)) break;
-            zc = lev + 1;
-            int k = atomicAdd(eout_n, 1);
-            if (k >= eout_cap) { atomicOr(err, ERR_INBOX); break; }
-            eout.cell[k] = cell;
-            eout.rx[k] = rx; eout.ry[k] = ry; eout.rz[k] = rz;
-            eout.ux[k] = a.ux[ip]; eout.uy[k] = a.uy[ip]; eout.uz[k] = a.uz[ip];
-            eout.w[k] = a.w[ip];
-            eout.id[k] = (1ull << 62) | ((uint64_t)lev << 56) | pid;
-            atomicAdd(ledger, (double)a.w[ip] * ion->lev[lev].ip_au * 27.211386245988 / 510998.95);
+        uint64_t pid = 0;
+        if (live) {
+            AxisW X = axis_weights(lx, rx), Y = axis_weights(ly, ry), Z = axis_weights(lz, rz);
+            double ex = tri(sF + 0 * FT3, X.ih, Y.in_, Z.in_, X.fh, Y.fn, Z.fn);
+            double ey = tri(sF + 1 * FT3, X.in_, Y.ih, Z.in_, X.fn, Y.fh, Z.fn);
+            double ez = tri(sF + 2 * FT3, X.in_, Y.in_, Z.ih, X.fn, Y.fn, Z.fh);
+            double F = sqrt(ex * ex + ey * ey + ez * ez) * ion->field_au;
+            pid = a.id[ip];
+            // levels ionize in sequence; below fskip the probability is under
+            // the smallest uniform draw, so no event is possible
+            for (int lev = z0; lev < zmax; ++lev) {
+                if (F < ion->lev[lev].fskip) break;
+                double wr = blended_rate(ion->lev[lev], F, omega) * ion->rate_norm;
+                double P = -expm1(-wr * g.ddt);
+                uint32_t r[4];
+                draw4(seed, pid, (uint32_t)step, TAG_ION + (uint32_t)lev, 0, r);
+                if (!(u01d(r[0]) < P)) break;
+                nev++;
+            }
         }
-        if (zc != z0) {
-            a.zc[ip] = zc;
-            if (zc >= ion->z_max) done++;
+        // one slot reservation per wave: inclusive scan of the event counts
+        int incl = nev;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o);
+            if (lane >= o) incl += v;
         }
+        const int tot = __shfl(incl, 63);
+        if (tot == 0) continue;
+        int base = 0;
+        if (lane == 63) base = atomicAdd(eout_n, tot);
+        base = __shfl(base, 63);
+        double led = 0.0;
+        if (nev) {
+            const real ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip], w = a.w[ip];
+            const float u2 = (float)(ux * ux + uy * uy + uz * uz);
+            if (u2 > 0.f) atomicMax(&umax2[t], __float_as_uint(u2));   // newborns keep the ion's u
+            for (int e = 0; e < nev; ++e) {
+                const int k = base + incl - nev + e;
+                const int lev = z0 + e;
+                if (k >= eout_cap) { atomicOr(err, ERR_INBOX); break; }
+                eout.cell[k] = cell;
+                eout.rx[k] = rx; eout.ry[k] = ry; eout.rz[k] = rz;
+                eout.ux[k] = ux; eout.uy[k] = uy; eout.uz[k] = uz;
+                eout.w[k] = w;
+                eout.id[k] = (1ull << 62) | ((uint64_t)lev << 56) | pid;
+                led += (double)w * ion->lev[lev].ip_au * 27.211386245988 / 510998.95;
+            }
+            a.zc[ip] = z0 + nev;
+            if (z0 + nev >= zmax) done++;
+        }
+        for (int o = 32; o > 0; o >>= 1) led += __shfl_xor(led, o);
+        if (lane == 0) atomicAdd(ledger, led);
     }
     if (done) atomicSub(&active[t], done);
 }
@@ -605,20 +650,21 @@ void launch_migrate(const GridP &g, const SpecP &sp, PArr mig, const long long *
 void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
                        int *nf_out, PArr mig, const long long *moff, const int *mcap, int *mcnt,
                        PArr inbox, int *inbox_n, int inbox_cap, real *const f[9], int *err,
-                       unsigned long long *stats, const unsigned *wmax_bits, hipStream_t s) {
+                       unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
+                       hipStream_t s) {
     k_push<<<g.ntiles, PBS, 0, s>>>(g, sp, in, bin_in, out, nf_out, mig, moff, mcap, mcnt, inbox,
                                     inbox_n, inbox_cap, f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX],
                                     f[HK_BY], f[HK_BZ], f[HK_JX], f[HK_JY], f[HK_JZ], err, stats,
-                                    wmax_bits);
+                                    wmax_bits, umax2);
 }
 
 void launch_ionize_static(const GridP &g, const SpecP &sp, PArr a, Bins b, int *active,
                           real *const f[9], const uint8_t *sw, int hybrid, const IonP *ion,
                           PArr eout, int *eout_n, int eout_cap, uint64_t seed, int step,
-                          double *ledger, int *err, hipStream_t s) {
+                          double *ledger, int *err, unsigned *umax2, hipStream_t s) {
     k_ionize_static<<<g.ntiles, BS, 0, s>>>(g, sp, a, b, active, f[HK_EX], f[HK_EY], f[HK_EZ], sw,
                                             hybrid, ion, eout, eout_n, eout_cap, seed, step, ledger,
-                                            err);
+                                            err, umax2);
 }
 
 void launch_count_active(const GridP &g, const SpecP &sp, PArr a, Bins b, int zmax, int *active,

@@ -48,9 +48,13 @@ __device__ inline long long nearest_node(const GridP &g, int ci, int cj, int ck,
 // ---------------------------------------------------------------- moments -----------------
 // mom layout (7 grid arrays): N = sum w, V = sum w^2, P (3), U2 = sum w |u|^2, NI.
 // Nearest-node sums of one tile's particles in LDS.  The FP32 build adds
-// fixed-point integers (2^40 units per the tile's largest contribution of
-// each quantity, found in a first pass): LDS integer atomics are far cheaper
-// than float ones on this GPU and the sums become independent of the order.
+// fixed-point integers (2^40 units per a bound on each quantity's largest
+// contribution): LDS integer atomics are far cheaper than float ones on this
+// GPU, and the sums become independent of the order.  The bounds come from
+// the species' weight bound and a per-tile bound on |u|^2 that every kernel
+// changing momenta raises (push, ionization, spawn); the largest over the
+// tile and its neighbours covers particles that changed tile since.  Without
+// such a bound (umax2 == nullptr) a first pass over the tile finds it.
 __device__ inline real tile_moment_term(int q, real w, real ux, real uy, real uz) {
     switch (q) {
         case 0: return w;
@@ -62,45 +66,65 @@ __device__ inline real tile_moment_term(int q, real w, real ux, real uy, real uz
     }
 }
 
+// fixed-point add with saturation: a term above its bound (a bound that was
+// not raised) cannot leave the exact range of the conversion
+__device__ inline void madd(jacc_t *p, real v, real inv) {
+#ifdef HK_DOUBLE
+    jadd(p, v, inv);
+#else
+    const float x = fminf(fmaxf(v * inv, -1e15f), 1e15f);
+    const long long q = round_to_i64((double)x);
+    if (q) atomicAdd(p, (unsigned long long)q);
+#endif
+}
+
 __global__ void __launch_bounds__(BS)
-k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__restrict__ mom) {
+k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__restrict__ mom,
+          const unsigned *__restrict__ wmax_bits, const unsigned *__restrict__ umax2,
+          const int *__restrict__ active) {
     __shared__ jacc_t sm[6 * NT3];
-    __shared__ unsigned smax[6];
+    __shared__ unsigned s_u2;
     const int t = blockIdx.x;
     int nf, nbv;
     const int n = bin_count(sp, bins, t, nf, nbv);
     if (n <= 0) return;
+    if (ion_only && active && active[t] <= 0) return;   // every ion of the tile at z_max
     const int nq = ion_only ? 1 : 6;
     for (int e = threadIdx.x; e < nq * NT3; e += BS) sm[e] = 0;
-    if (threadIdx.x < 6) smax[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_u2 = 0;
     __syncthreads();
-    // pass 1: largest |term| per quantity (bit patterns of non-negative
-    // floats order like unsigned integers)
-    float lmax[6] = {0, 0, 0, 0, 0, 0};
-    for (int p = threadIdx.x; p < n; p += BS) {
-        const long long ip = bin_slot(sp, t, p, nf, nbv);
-        if (a.cell[ip] < 0) continue;
-        const real w = a.w[ip];
-        if (ion_only) {
-            if (a.zc[ip] < zmax) lmax[0] = fmaxf(lmax[0], fabsf((float)w));
-            continue;
+    const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
+    if (!ion_only) {
+        if (umax2) {
+            if (threadIdx.x < 27) {
+                const int dx = threadIdx.x % 3 - 1, dy = (threadIdx.x / 3) % 3 - 1, dz = threadIdx.x / 9 - 1;
+                int nx_ = tx + dx;
+                const int ny_ = wrapi(ty + dy, g.nty), nz_ = wrapi(tz + dz, g.ntz);
+                if (g.bcx == HK_BC_PERIODIC) nx_ = wrapi(nx_, g.ntx);
+                if (nx_ >= 0 && nx_ < g.ntx) atomicMax(&s_u2, umax2[nx_ + g.ntx * (ny_ + g.nty * nz_)]);
+            }
+        } else {
+            float l = 0.f;
+            for (int p = threadIdx.x; p < n; p += BS) {
+                const long long ip = bin_slot(sp, t, p, nf, nbv);
+                if (a.cell[ip] < 0) continue;
+                const real ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip];
+                l = fmaxf(l, (float)(ux * ux + uy * uy + uz * uz));
+            }
+            for (int o = 32; o > 0; o >>= 1) l = fmaxf(l, __shfl_xor(l, o));
+            if ((threadIdx.x & 63) == 0 && l > 0.f) atomicMax(&s_u2, __float_as_uint(l));
         }
-        const real ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip];
-        for (int q = 0; q < 6; ++q) lmax[q] = fmaxf(lmax[q], fabsf((float)tile_moment_term(q, w, ux, uy, uz)));
+        __syncthreads();
     }
-    for (int q = 0; q < nq; ++q) {
-        float v = lmax[q];
-        for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-        if ((threadIdx.x & 63) == 0 && v > 0.f) atomicMax(&smax[q], __float_as_uint(v));
-    }
-    __syncthreads();
+    // bounds of |term| per quantity, with a margin for the FP32 products
+    const double wb = (double)__uint_as_float(*wmax_bits) * 1.001;
+    const double ub2 = (double)__uint_as_float(s_u2) * 1.001;
+    const double bound[6] = {wb, wb * wb, wb * sqrt(ub2), wb * sqrt(ub2), wb * sqrt(ub2), wb * ub2};
     real inv[6], scl[6];
     for (int q = 0; q < 6; ++q) {
-        const float m = __uint_as_float(smax[q]) * 1.0001f;
-        inv[q] = m > 0.f ? (real)(JFIX_UNITS / m) : (real)0;
-        scl[q] = (real)((double)m / (double)JFIX_UNITS);
+        inv[q] = bound[q] > 0.0 ? (real)((double)JFIX_UNITS / bound[q]) : (real)0;
+        scl[q] = (real)(bound[q] / (double)JFIX_UNITS);
     }
-    const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
     for (int p = threadIdx.x; p < n; p += BS) {
         const long long ip = bin_slot(sp, t, p, nf, nbv);
@@ -114,11 +138,11 @@ k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__
         const int e = lx + NT * (ly + NT * lz);
         const real w = a.w[ip];
         if (ion_only) {
-            if (a.zc[ip] < zmax) jadd(&sm[e], w, inv[0]);
+            if (a.zc[ip] < zmax) madd(&sm[e], w, inv[0]);
             continue;
         }
         const real ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip];
-        for (int q = 0; q < 6; ++q) jadd(&sm[q * NT3 + e], tile_moment_term(q, w, ux, uy, uz), inv[q]);
+        for (int q = 0; q < 6; ++q) madd(&sm[q * NT3 + e], tile_moment_term(q, w, ux, uy, uz), inv[q]);
     }
     __syncthreads();
     const int per = g.bcx == HK_BC_PERIODIC;
@@ -137,21 +161,35 @@ k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__
     }
 }
 
+// Fluid part of the moments.  `first`: the first fluid species overwrites all
+// seven arrays (zero where it has no mass), so no separate clearing pass is
+// needed before the particle moments are added.
 __global__ void __launch_bounds__(BS)
 k_fluid_moments(GridP g, real inv_ppc, const real *__restrict__ n, const real *__restrict__ ux,
-                const real *__restrict__ uy, const real *__restrict__ uz, real *__restrict__ mom) {
+                const real *__restrict__ uy, const real *__restrict__ uz, real *__restrict__ mom,
+                int first) {
     long long c = (long long)blockIdx.x * BS + threadIdx.x;
     if (c >= g.nn) return;
     real m = n[c] * (g.dx * g.dy * g.dz);
-    if (!(m > (real)0)) return;
-    real a = ux[c], b = uy[c], d = uz[c];
     const long long nn = g.nn;
-    mom[c] += m;
-    mom[nn + c] += m * m * inv_ppc;
-    mom[2 * nn + c] += m * a;
-    mom[3 * nn + c] += m * b;
-    mom[4 * nn + c] += m * d;
-    mom[5 * nn + c] += m * (a * a + b * b + d * d);
+    real v[6] = {0, 0, 0, 0, 0, 0};
+    if (m > (real)0) {
+        real a = ux[c], b = uy[c], d = uz[c];
+        v[0] = m;
+        v[1] = m * m * inv_ppc;
+        v[2] = m * a;
+        v[3] = m * b;
+        v[4] = m * d;
+        v[5] = m * (a * a + b * b + d * d);
+    } else if (!first) {
+        return;
+    }
+    if (first) {
+        for (int q = 0; q < 6; ++q) mom[q * nn + c] = v[q];
+        mom[6 * nn + c] = 0;
+    } else {
+        for (int q = 0; q < 6; ++q) mom[q * nn + c] += v[q];
+    }
 }
 
 // ------------------------------------------------------------- indicators -----------------
@@ -334,11 +372,22 @@ k_absorb(GridP g, SpecP sp, PArr a, Bins bins, const uint8_t *__restrict__ sw,
     int nf, nbv;
     const int n = bin_count(sp, bins, t, nf, nbv);
     if (n <= 0) return;
+    const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
+    const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
+    const int per = g.bcx == HK_BC_PERIODIC;
+    // a tile whose nearest nodes (0 .. TILE per axis) are all kinetic absorbs nothing
+    int fluid_node = 0;
+    for (int e = threadIdx.x; e < NT3; e += BS) {
+        int aa = e % NT, b = (e / NT) % NT, c = e / (NT * NT);
+        int gi = ox + aa, gj = wrapi(oy + b, g.ny), gk = wrapi(oz + c, g.nz);
+        if (per) gi = wrapi(gi, g.nx);
+        else if (gi > g.nx) continue;
+        fluid_node |= !sw[gidx(g, gi, gj, gk)];
+    }
+    if (!__syncthreads_or(fluid_node)) return;
     for (int e = threadIdx.x; e < 3 * JT3; e += BS) sJ[e] = 0;
     if (threadIdx.x == 0) any = 0;
     __syncthreads();
-    const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
-    const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
     const real dv = g.dx * g.dy * g.dz;
     const long long nn = g.nn;
     double ke = 0;
@@ -346,8 +395,8 @@ k_absorb(GridP g, SpecP sp, PArr a, Bins bins, const uint8_t *__restrict__ sw,
         const long long ip = bin_slot(sp, t, p, nf, nbv);
         int cell = a.cell[ip];
         if (cell < 0) continue;
-        const int ci = cell % g.nx, rr = cell / g.nx;
-        const int cj = rr % g.ny, ck = rr / g.ny;
+        int ci, cj, ck;
+        cell_ijk(g, cell, ci, cj, ck);
         const real rx = a.rx[ip], ry = a.ry[ip], rz = a.rz[ip];
         int di, dj, dk;
         long long node = nearest_node(g, ci, cj, ck, rx, ry, rz, di, dj, dk);
@@ -369,7 +418,6 @@ k_absorb(GridP g, SpecP sp, PArr a, Bins bins, const uint8_t *__restrict__ sw,
     }
     block_add_d(ke, ledger);
     if (!any) return;
-    const int per = g.bcx == HK_BC_PERIODIC;
     for (int e = threadIdx.x; e < JT3; e += BS) {
         int aa = e % JT, b = (e / JT) % JT, c = e / (JT * JT);
         int gi = ox - 1 + aa;
@@ -414,7 +462,7 @@ k_spawn(GridP g, SpecP sp, const uint8_t *__restrict__ sw, real *__restrict__ n,
         real *__restrict__ uy, real *__restrict__ uz, real *__restrict__ Jx, real *__restrict__ Jy,
         real *__restrict__ Jz, real wmin, int m, uint64_t seed, int step, PArr inbox,
         int *__restrict__ inbox_n, int inbox_cap, int *__restrict__ deferred,
-        unsigned *__restrict__ wmax_bits) {
+        unsigned *__restrict__ wmax_bits, unsigned *__restrict__ umax2) {
     long long c = (long long)blockIdx.x * BS + threadIdx.x;
     if (c >= g.nn) return;
     int i, j, k;
@@ -437,6 +485,13 @@ k_spawn(GridP g, SpecP sp, const uint8_t *__restrict__ sw, real *__restrict__ n,
     const real w = mass / (real)m;
     if (__float_as_uint(fabsf((float)w)) > *wmax_bits) atomicMax(wmax_bits, __float_as_uint(fabsf((float)w)));
     const real u[3] = {ux[c], uy[c], uz[c]};
+    {
+        // the new particles sit in cells next to the node: raise the bound of
+        // the node's tile (the moments read the bounds of neighbouring tiles too)
+        const int ti = min(i, g.nx - 1) >> TLOG, tj = j >> TLOG, tk = k >> TLOG;
+        const float u2 = (float)(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        if (u2 > 0.f) atomicMax(&umax2[ti + g.ntx * (tj + g.nty * tk)], __float_as_uint(u2));
+    }
     const uint64_t node = (uint64_t)i + (uint64_t)nxn * ((uint64_t)j + (uint64_t)g.ny * k);
     const real qw = sp.q * w / dv;
     for (int q = 0; q < m; ++q) {
@@ -471,12 +526,13 @@ inline unsigned blocks(long long n) { return (unsigned)((n + BS - 1) / BS); }
 }  // namespace
 
 void launch_moments_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, int ion_only,
-                          int zmax, real *mom, hipStream_t s) {
-    k_moments<<<g.ntiles, BS, 0, s>>>(g, sp, a, b, ion_only, zmax, mom);
+                          int zmax, real *mom, const unsigned *wmax_bits, const unsigned *umax2,
+                          const int *active, hipStream_t s) {
+    k_moments<<<g.ntiles, BS, 0, s>>>(g, sp, a, b, ion_only, zmax, mom, wmax_bits, umax2, active);
 }
 void launch_fluid_moments_nodes(const GridP &g, real inv_ppc, const real *n, const real *ux,
-                                const real *uy, const real *uz, real *mom, hipStream_t s) {
-    k_fluid_moments<<<blocks(g.nn), BS, 0, s>>>(g, inv_ppc, n, ux, uy, uz, mom);
+                                const real *uy, const real *uz, real *mom, int first, hipStream_t s) {
+    k_fluid_moments<<<blocks(g.nn), BS, 0, s>>>(g, inv_ppc, n, ux, uy, uz, mom, first);
 }
 void launch_indicators_nodes(const GridP &g, const SwitchP &P, const real *mom, real *const f[9],
                              const IonP *const *ions, int nion, uint8_t *hot, uint8_t *notcold,
@@ -501,7 +557,7 @@ void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n
 void launch_spawn_nodes(const GridP &g, const SpecP &sp, const uint8_t *sw, real *n, real *ux,
                         real *uy, real *uz, real *const f[9], real wmin, int m, uint64_t seed,
                         int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
-                        unsigned *wmax_bits, hipStream_t s) {
+                        unsigned *wmax_bits, unsigned *umax2, hipStream_t s) {
     k_spawn<<<blocks(g.nn), BS, 0, s>>>(g, sp, sw, n, ux, uy, uz, f[HK_JX], f[HK_JY], f[HK_JZ], wmin,
-                                        m, seed, step, inbox, inbox_n, inbox_cap, deferred, wmax_bits);
+                                        m, seed, step, inbox, inbox_n, inbox_cap, deferred, wmax_bits, umax2);
 }
