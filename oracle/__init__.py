@@ -127,6 +127,17 @@ def lib():
         L.or_ionization_rate.argtypes = [C.c_double] * 4
         L.or_esirkepov.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p,
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_airy.argtypes = [C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
+        for f in ("or_qed_emission_spectrum", "or_qed_pair_spectrum"):
+            getattr(L, f).restype = C.c_double
+            getattr(L, f).argtypes = [C.c_double, C.c_double]
+        L.or_qed_total.restype = C.c_double
+        L.or_qed_total.argtypes = [C.c_int, C.c_double]
+        L.or_qed_build_tables.argtypes = [C.c_void_p] * 4
+        L.or_qed_chi.restype = C.c_double
+        L.or_qed_chi.argtypes = [C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        L.or_schwinger_field.restype = C.c_double
+        L.or_schwinger_field.argtypes = [C.c_double]
         _lib = L
     return _lib
 
@@ -186,8 +197,6 @@ class Oracle:
         self.cfg = cfg
         self._structs = structs(cfg)
         grid, sps, ns, laser, run = self._structs
-        if run.enable_qed:
-            raise NotImplementedError("QED is not part of the oracle yet")
         self.h = lib().or_create(C.byref(grid), sps, ns, C.byref(laser), C.byref(run))
         if not self.h:
             raise RuntimeError("or_create failed")
@@ -323,3 +332,47 @@ def esirkepov(x0, x1, qw_dv, dt, dx):
     # index n = a + 3 (b + 3 c): reshape to [c][b][a] then transpose to [a][b][c]
     f = lambda j: j.reshape(3, 3, 3).transpose(2, 1, 0)
     return f(jx), f(jy), f(jz), base
+
+
+# ---- QED building blocks ------------------------------------------------------------------
+
+QED_NCHI, QED_NU = 256, 128
+
+
+def airy(z: float):
+    """(Ai, Ai', Int_z^inf Ai) at z > 0."""
+    a = C.c_double(); b = C.c_double(); c = C.c_double()
+    lib().or_airy(float(z), C.byref(a), C.byref(b), C.byref(c))
+    return a.value, b.value, c.value
+
+
+def emission_spectrum(chi, delta) -> float:
+    return lib().or_qed_emission_spectrum(float(chi), float(delta))
+
+
+def pair_spectrum(chi, delta) -> float:
+    return lib().or_qed_pair_spectrum(float(chi), float(delta))
+
+
+def qed_total(kind: str, chi: float) -> float:
+    """Integral over delta of the emission spectrum ("emission"), the pair
+    spectrum ("pair") or delta times the emission spectrum ("power")."""
+    return lib().or_qed_total({"emission": 0, "pair": 1, "power": 2}[kind], float(chi))
+
+
+def qed_tables():
+    """(W_e[256], W_b[256], X_e[256, 128], X_b[256, 128]) as built by the oracle."""
+    We = np.empty(QED_NCHI); Wb = np.empty(QED_NCHI)
+    Xe = np.empty((QED_NCHI, QED_NU)); Xb = np.empty((QED_NCHI, QED_NU))
+    lib().or_qed_build_tables(_ptr(We), _ptr(Wb), _ptr(Xe), _ptr(Xb))
+    return We, Wb, Xe, Xb
+
+
+def qed_chi(a_s, e, b, u, photon=False) -> float:
+    e = np.ascontiguousarray(e, np.float64); b = np.ascontiguousarray(b, np.float64)
+    u = np.ascontiguousarray(u, np.float64)
+    return lib().or_qed_chi(float(a_s), _ptr(e), _ptr(b), _ptr(u), int(photon))
+
+
+def schwinger_field(lambda_um: float) -> float:
+    return lib().or_schwinger_field(float(lambda_um))

@@ -75,8 +75,8 @@ void or_ionize_particle(or_sim *s, int isp, size_t i, double emag) {
         e.ox = p->ox[i]; e.oy = p->oy[i]; e.oz = p->oz[i];
         e.ux = p->ux[i]; e.uy = p->uy[i]; e.uz = p->uz[i];
         e.w = p->w[i];
-        e.tau = 0.0;
         e.id = (1ull << 62) | ((uint64_t)lev << 56) | p->id[i];
+        e.tau = s->sp[sp->target].qed ? or_qed_tau0(s, e.id) : 0.0;
         e.zc = -1;
         or_spawn_add(s, &e);
         s->ion_energy += p->w[i] * sp->ip_ev[lev] / 510998.95;   /* m_e c^2 units */

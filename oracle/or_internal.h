@@ -109,6 +109,8 @@ void or_qed_init(or_sim *s);
 void or_qed_free(or_sim *s);
 void or_qed_emit(or_sim *s, int sp, size_t i, const double e[3], const double b[3]);
 void or_photon_phase(or_sim *s);
+double or_qed_tau0(const or_sim *s, uint64_t id);
+uint64_t or_child_id(uint64_t parent, uint32_t step, uint32_t k);
 /* cnn.c */
 void or_cnn_free(or_sim *s);
 #endif

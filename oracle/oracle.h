@@ -81,7 +81,8 @@ typedef struct {
     double gauss_max, gauss_l2;            /* max / rms of (div E - rho) - initial */
     double conv_loss;                      /* kinetic energy lost at absorption */
     double ion_energy;                     /* ionization potential energy spent */
-    double photon_energy;                  /* photon energy (particles + ledger) */
+    double photon_energy;                  /* photon ledger: radiated energy not held by photon
+                                              particles, escaped photons, pair rest energy */
     double kinetic_fraction;               /* fraction of kinetic nodes */
     double fallback_fraction;
 } or_diag;
@@ -130,4 +131,14 @@ double or_ionization_rate(double field_au, double ip_au, double zres, double ome
 void or_esirkepov(const double x0[3], const double x1[3], double qw_dv, double dt,
                   const double dx[3], double jx[27], double jy[27], double jz[27],
                   int base[3]);
+/* QED building blocks: Airy functions (z > 0), spectra, totals over delta
+ * (kind 0 emission, 1 pairs, 2 emitted energy fraction), the tables
+ * (256 chi values; 256 x 128 inverse spectra in the x variable), chi. */
+void or_airy(double z, double *ai, double *aip, double *iai);
+double or_qed_emission_spectrum(double chi, double delta);
+double or_qed_pair_spectrum(double chi, double delta);
+double or_qed_total(int kind, double chi);
+void or_qed_build_tables(double *We, double *Wb, double *Xe, double *Xb);
+double or_qed_chi(double a_s, const double e[3], const double b[3], const double u[3], int photon);
+double or_schwinger_field(double lambda_um);
 #endif

@@ -86,7 +86,8 @@ void or_init_species(or_sim *s, int isp) {
                     double uy = sp->u_th * m0 * sin(2.0 * OR_PI * r1);
                     double uz = sp->u_th * m1 * cos(2.0 * OR_PI * r3);
                     or_parts_push_back(p, i, j, k, or_uniform(rp[0]), or_uniform(rp[1]),
-                                       or_uniform(rp[2]), ux, uy, uz, n * dv / sp->ppc, 0.0, id,
+                                       or_uniform(rp[2]), ux, uy, uz, n * dv / sp->ppc,
+                                       sp->qed ? or_qed_tau0(s, id) : 0.0, id,
                                        (int32_t)llround(sp->charge));
                 }
             }

@@ -12,8 +12,8 @@
  *   1. switch evaluation every `switch_every` steps (threshold / CNN modes);
  *   2. J = 0; laser antenna current at t^{n+1/2};
  *   3. particles: gather, ionization, photon emission, Boris, move, deposit;
- *      newborn particles join their species;
- *   4. photons: ballistic push and pair creation;
+ *   4. photons: pair creation, ballistic push; the particles born in 3 and 4
+ *      then join their species (they move from the next step on);
  *   5. cold fluid update (adds its face current to J);
  *   6. conversion between fluid and particles (adds its current to J);
  *   7. B^{n+1/2} = B^n - dt/2 curl E^n; E^{n+1} = E^n + dt (curl B - J)
@@ -85,8 +85,8 @@ int or_step(or_sim *s, int nsteps) {
         for (int c = OR_JX; c <= OR_JZ; ++c) memset(s->f[c], 0, sizeof(double) * s->nn);
         or_antenna(s, s->t + 0.5 * g->dt);
         or_particle_phase(s);
-        or_spawn_flush(s);
-        if (s->run.enable_qed) { or_photon_phase(s); or_spawn_flush(s); }
+        if (s->run.enable_qed) or_photon_phase(s);
+        or_spawn_flush(s);   /* particles born this step move from the next one */
         if (mode != OR_SW_ALL_PIC) {
             or_fluid_phase(s);
             or_reconcile(s);
@@ -154,8 +154,11 @@ int or_set_particles(or_sim *s, int sp, size_t n, const double *x, const double 
             c[d] = (int)floor(X);
             o[d] = X - c[d];
         }
+        uint64_t pid = id ? id[q] : q;
+        /* without given optical depths a QED particle draws its own, as a new one does */
+        double t0 = tau ? tau[q] : (s->sp[sp].qed ? or_qed_tau0(s, pid) : 0.0);
         or_parts_push_back(p, c[0], c[1], c[2], o[0], o[1], o[2], u[3 * q], u[3 * q + 1],
-                           u[3 * q + 2], w[q], tau ? tau[q] : 0.0, id ? id[q] : q,
+                           u[3 * q + 2], w[q], t0, pid,
                            z ? z[q] : (int32_t)llround(s->sp[sp].charge));
     }
     s->have_gauss0 = 0;

@@ -253,7 +253,7 @@ void or_reconcile(or_sim *s) {
                         or_carry(s, cell, X1);
                         uint64_t id = (1ull << 63) | ((uint64_t)s->step << 40) | (node << 6) | (uint64_t)q;
                         or_parts_push_back(p, cell[0], cell[1], cell[2], X1[0], X1[1], X1[2],
-                                           u[0], u[1], u[2], w, 0.0, id,
+                                           u[0], u[1], u[2], w, sp->qed ? or_qed_tau0(s, id) : 0.0, id,
                                            (int32_t)llround(sp->charge));
                     }
                     n[c] = 0.0;
