@@ -137,6 +137,15 @@ typedef struct {
     void *alloc_ctx;
 } hk_run_desc;
 
+/* QED (run.enable_qed).  Species with `qed` set carry an optical depth.
+ * Electrons and positrons with `qed` emit photons (quantum-synchrotron
+ * spectrum, Airy form) into the first HK_PHOTON species; photons convert into
+ * pairs (Breit-Wheeler) in the first HK_ELECTRON and HK_POSITRON species and
+ * otherwise fly at c, leaving through open x walls.  Soft photons (|k| <= 2),
+ * escaped photons and the pairs' rest energy go to the photon ledger
+ * (hk_diag.photon_energy).  Paper: abstract and Methodology, plasma-model
+ * paragraph (QED effects with Airy-function approximations). */
+
 /* FP64 diagnostics (energies in m_e c^2 n_c (c/omega0)^3). */
 typedef struct {
     double t;
@@ -150,7 +159,8 @@ typedef struct {
     double gauss_max, gauss_l2;            /* change of div E - rho since step 0 */
     double conv_loss;                      /* kinetic energy lost by absorption */
     double ion_energy;                     /* ionization potential energy spent */
-    double photon_energy;                  /* photon energy (particles + ledger) */
+    double photon_energy;                  /* photon ledger: radiated energy not held by photon
+                                              particles, escaped photons, pair rest energy */
     double kinetic_fraction;               /* kinetic nodes / all nodes */
     double fallback_fraction;              /* CNN nodes that fell back to threshold */
 } hk_diag;
@@ -213,6 +223,14 @@ int hk_set_fluid(hk_sim *sim, int species, const double *n, const double *u, siz
 #define HK_NTIMERS 12
 int hk_enable_timing(hk_sim *sim, int on);
 int hk_timers(hk_sim *sim, double *ms, int n);
+
+/* The QED tables the library built (host FP64, independent of any context):
+ * We[256] and Wb[256] are the emission and pair spectra integrated over the
+ * energy fraction at chi_i = 10^(-3 + 6 i / 255); Xe and Xb [256 * 128], row
+ * i, hold the inverse cumulative spectra at u_j = (j + 1/2) / 128 in the
+ * variable x of delta = x^3 / (x^3 + (1 - x)^3).  The caller owns the arrays.
+ * Paper: Methodology, plasma-model paragraph (Airy-function QED rates). */
+int hk_qed_tables(double *We, double *Wb, double *Xe, double *Xb);
 
 int hk_real_size(void);
 const char *hk_strerror(int code);

@@ -55,6 +55,9 @@ struct DevSpecies {
 
 struct hk_sim {
     GridP g{};
+    double *qed_tab = nullptr;   // device copy of the QED tables (enable_qed)
+    double a_s = 0.0;            // Schwinger field in normalized units
+    int photon_sp = -1, electron_sp = -1, positron_sp = -1;   // QED sinks (first of each kind)
     hk_grid_desc gd{};
     hk_laser_desc las{};
     hk_run_desc run{};
@@ -188,6 +191,15 @@ double profile(const hk_species_desc &d, double x) {
     case HK_PROF_FOIL: return (x >= d.x0 && x < d.x0 + d.length) ? d.n0 : 0.0;
     default: return 0.0;
     }
+}
+
+// Particles a species starts with: ppc in every cell whose centre has n > 0.
+long long initial_count(const hk_grid_desc &g, const hk_species_desc &d) {
+    if (d.ppc <= 0 || d.profile == HK_PROF_NONE) return 0;
+    long long cols = 0;
+    for (int x = 0; x < g.nx; ++x)
+        if (profile(d, (x + 0.5) * g.dx) > 0) cols++;
+    return cols * (long long)g.ny * g.nz * d.ppc;
 }
 
 // Re-bin a species from its current bins plus unbinned lists into a fresh
@@ -467,6 +479,15 @@ int status_error(hk_sim *S) {
 
 int gauss_snapshot(hk_sim *S);
 
+// Kernel variant of a species' push: 0 charged particles, 1 QED leptons,
+// 2 photons; -1 for photons without QED (they are not advanced).
+int push_mode(const hk_sim *S, int isp) {
+    const hk_species_desc &d = S->sp[isp].d;
+    if (d.kind == HK_PHOTON) return S->run.enable_qed ? 2 : -1;
+    if (S->run.enable_qed && d.qed && (d.kind == HK_ELECTRON || d.kind == HK_POSITRON)) return 1;
+    return 0;
+}
+
 // Inbox size of a species: the particles one step can send past full bins
 // (a quarter of the capacity; bins keep 25% headroom) plus every electron the
 // ions targeting it can free in one step.
@@ -478,6 +499,14 @@ long long inbox_need(hk_sim *S, int isp) {
     for (int j = 0; j < S->nsp; ++j)
         if (S->sp[j].d.ionizable && S->sp[j].d.target == isp && S->run.enable_ionization)
             need += S->sp[j].capacity * std::max(1, S->sp[j].d.z_max);
+    if (S->run.enable_qed) {
+        // one photon per QED lepton per step; one pair member per photon
+        if (isp == S->photon_sp)
+            for (int j = 0; j < S->nsp; ++j)
+                if (push_mode(S, j) == 1) need += std::max<long long>(S->sp[j].capacity, S->sp[j].reserve_hint);
+        if ((isp == S->electron_sp || isp == S->positron_sp) && S->photon_sp >= 0)
+            need += std::max<long long>(S->sp[S->photon_sp].capacity, S->sp[S->photon_sp].reserve_hint);
+    }
     return need;
 }
 
@@ -609,6 +638,45 @@ void reconcile(hk_sim *S) {
     }
 }
 
+// Sinks and tables of the QED events: photons go to the first photon species,
+// pairs to the first electron and positron species.
+QedP qed_params(hk_sim *S, int mode) {
+    QedP Q{};
+    if (mode == 0) return Q;
+    Q.We = S->qed_tab;
+    Q.Wb = S->qed_tab + QED_NCHI;
+    Q.Xe = S->qed_tab + 2 * QED_NCHI;
+    Q.Xb = S->qed_tab + 2 * QED_NCHI + QED_NCHI * QED_NU;
+    Q.a_s = S->a_s;
+    Q.alpha_as = 7.2973525693e-3 * S->a_s;
+    Q.ledger = S->ledger + 2;
+    Q.sw = S->sw;
+    Q.hybrid = S->run.switch_mode != HK_SW_ALL_PIC;
+    Q.seed = S->run.seed;
+    Q.step = (int)S->step;
+    auto sink = [&](int sp, PArr &o, int *&n, int &cap, int &tau, int &have, unsigned *&wm) {
+        if (sp < 0) return;
+        DevSpecies &T = S->sp[sp];
+        o = T.inbox;
+        n = S->status + 1 + 2 * sp;
+        cap = T.inbox_cap;
+        tau = T.has_tau;
+        have = T.inbox_cap > 0;
+        wm = S->wmax + sp;
+    };
+    if (mode == 1) {
+        sink(S->photon_sp, Q.out1, Q.out1_n, Q.out1_cap, Q.out1_tau, Q.have1, Q.wmax1);
+    } else {
+        sink(S->electron_sp, Q.out1, Q.out1_n, Q.out1_cap, Q.out1_tau, Q.have1, Q.wmax1);
+        sink(S->positron_sp, Q.out2, Q.out2_n, Q.out2_cap, Q.out2_tau, Q.have2, Q.wmax2);
+    }
+    if (!Q.out1_n) Q.out1_n = S->status + 15;   // a dummy counter: nothing requests it
+    if (!Q.out2_n) Q.out2_n = S->status + 15;
+    if (!Q.wmax1) Q.wmax1 = S->wmax + HK_MAX_SPECIES;
+    if (!Q.wmax2) Q.wmax2 = S->wmax + HK_MAX_SPECIES;
+    return Q;
+}
+
 int one_step(hk_sim *S) {
     hipStream_t s = S->s;
     const GridP &g = S->g;
@@ -623,19 +691,22 @@ int one_step(hk_sim *S) {
     // 2. J = 0, antenna current at t^{n+1/2}
     launch_zero(S->f[HK_JX], sizeof(real) * 3 * (size_t)g.nn, s);
     launch_antenna(g, S->las, S->t + 0.5 * g.ddt, S->f[HK_JY], S->f[HK_JZ], s);
-    // 3. particles (mobile species push into the next bins; immobile ions ionize in place)
+    // 3. particles (mobile species push into the next bins; immobile ions ionize in
+    // place; QED leptons emit photons; photons create pairs and fly straight)
     for (int isp = 0; isp < S->nsp; ++isp) {
         DevSpecies &D = S->sp[isp];
         if (D.capacity == 0) continue;
         SpecP P = specp(D);
-        if (D.d.kind == HK_PHOTON) continue;
+        const int mode = push_mode(S, isp);
+        if (mode < 0) continue;
         if (D.d.mobile) {
             int nxt = 1 - D.cur;
             launch_zero(D.nb[nxt], sizeof(int) * g.ntiles, s);
+            QedP Q = qed_params(S, mode);
             hipEvent_t pa = S->timing ? ev_get(S) : nullptr;
             launch_push_tiles(g, P, D.buf[D.cur], cur_bins(D), D.buf[nxt], D.nf[nxt], D.mig, D.moff,
                               D.mcap, D.mcnt, D.inbox, S->status + 1 + 2 * isp, D.inbox_cap, S->f,
-                              S->status, S->dstat, S->wmax + isp, D.umax2, s);
+                              S->status, S->dstat, S->wmax + isp, D.umax2, mode, Q, s);
             if (S->timing) {
                 S->spans.push_back({pa, ev_get(S), 6});
                 S->timers[8] += 1;
@@ -646,12 +717,13 @@ int one_step(hk_sim *S) {
             DevSpecies &T = S->sp[D.d.target];
             launch_ionize_static(g, P, D.buf[D.cur], cur_bins(D), D.active, S->f, S->sw, hybrid,
                                  D.ion, T.inbox, S->status + 1 + 2 * D.d.target, T.inbox_cap,
-                                 S->run.seed, (int)S->step, S->ledger + 1, S->status, T.umax2, s);
+                                 S->run.seed, (int)S->step, S->ledger + 1, S->status, T.umax2,
+                                 T.has_tau, s);
         }
     }
     for (int isp = 0; isp < S->nsp; ++isp) {
         DevSpecies &D = S->sp[isp];
-        if (D.capacity && D.d.mobile && D.d.kind != HK_PHOTON) D.cur = 1 - D.cur;
+        if (D.capacity && D.d.mobile && push_mode(S, isp) >= 0) D.cur = 1 - D.cur;
     }
     time_mark(S, 1);
     // 4. newborn and overflow particles join their bins; 5. cold fluid (it
@@ -743,6 +815,16 @@ bool check_grid(const hk_grid_desc *g) {
 
 extern "C" {
 
+int hk_qed_tables(double *We, double *Wb, double *Xe, double *Xb) {
+    if (!We || !Wb || !Xe || !Xb) return HK_EINVAL;
+    const double *t = hk_qed_host_tables();
+    std::memcpy(We, t, sizeof(double) * QED_NCHI);
+    std::memcpy(Wb, t + QED_NCHI, sizeof(double) * QED_NCHI);
+    std::memcpy(Xe, t + 2 * QED_NCHI, sizeof(double) * QED_NCHI * QED_NU);
+    std::memcpy(Xb, t + 2 * QED_NCHI + QED_NCHI * QED_NU, sizeof(double) * QED_NCHI * QED_NU);
+    return HK_OK;
+}
+
 int hk_real_size(void) { return HK_REAL_BYTES; }
 
 const char *hk_strerror(int code) {
@@ -781,7 +863,6 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
                             d.target < 0 || d.target >= nspecies || d.mobile))
             return HK_EINVAL;
     }
-    if (run->enable_qed) return HK_ENOTSUP;
     if (run->switch_mode == HK_SW_CNN) return HK_ENOTSUP;
     if (run->switch_every < 0 || run->dilation < 0 || run->dilation > 4 || run->hysteresis < 1 ||
         run->hysteresis > 255)
@@ -812,7 +893,9 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
     S->ledger = (double *)dalloc(S, sizeof(double) * 8);
     S->status = (int *)dalloc(S, sizeof(int) * 16);
     S->dstat = (unsigned long long *)dalloc(S, sizeof(unsigned long long) * 4);
-    S->wmax = (unsigned *)dalloc(S, sizeof(unsigned) * HK_MAX_SPECIES);
+    // species weight bounds, plus one spare slot that QED kernels may raise
+    // when a sink species does not exist
+    S->wmax = (unsigned *)dalloc(S, sizeof(unsigned) * (HK_MAX_SPECIES + 1));
     if (hipHostMalloc((void **)&S->h_status, sizeof(int) * 16, 0) != hipSuccess)
         S->h_status = nullptr;
     if (hipEventCreateWithFlags(&S->status_ev, hipEventDisableTiming) != hipSuccess)
@@ -829,17 +912,35 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
         DevSpecies &D = S->sp[i];
         D.d = species[i];
         D.has_z = D.d.kind == HK_ION;
-        D.has_tau = 0;
+        D.has_tau = D.d.qed != 0;
+    }
+    if (run->enable_qed) {
+        for (int i = nspecies - 1; i >= 0; --i) {
+            if (species[i].kind == HK_PHOTON) S->photon_sp = i;
+            if (species[i].kind == HK_ELECTRON) S->electron_sp = i;
+            if (species[i].kind == HK_POSITRON) S->positron_sp = i;
+        }
+        // bins for the particles QED creates: photons up to the QED leptons'
+        // count, pairs a quarter of that (re-binning grows them when needed)
+        long long leptons = 0;
+        for (int i = 0; i < nspecies; ++i)
+            if (species[i].qed && (species[i].kind == HK_ELECTRON || species[i].kind == HK_POSITRON))
+                leptons += initial_count(*grid, species[i]);
+        if (S->photon_sp >= 0) S->sp[S->photon_sp].reserve_hint += leptons;
+        if (S->electron_sp >= 0) S->sp[S->electron_sp].reserve_hint += leptons / 4;
+        if (S->positron_sp >= 0) S->sp[S->positron_sp].reserve_hint += leptons / 4;
+        double omega0 = 2.0 * PI * PHYS_C / (laser->lambda_um * 1e-6);
+        S->a_s = PHYS_ME * PHYS_C * PHYS_C / (PHYS_HBAR * omega0);
+        const size_t nt = 2 * QED_NCHI + 2 * (size_t)QED_NCHI * QED_NU;
+        S->qed_tab = (double *)dalloc(S, sizeof(double) * nt);
+        if (!S->qed_tab) rc = HK_ENOMEM;
+        else if (hipMemcpyAsync(S->qed_tab, hk_qed_host_tables(), sizeof(double) * nt,
+                                hipMemcpyHostToDevice, S->s) != hipSuccess) rc = HK_EDEVICE;
     }
     // ionization targets: reserve bins for the electrons the ions can free
     for (int i = 0; i < nspecies; ++i)
         if (species[i].ionizable && run->enable_ionization) {
-            double dv = grid->dx * grid->dy * grid->dz;
-            long long ions = 0;
-            for (int x = 0; x < grid->nx; ++x)
-                if (profile(species[i], (x + 0.5) * grid->dx) > 0) ions += (long long)grid->ny * grid->nz * species[i].ppc;
-            (void)dv;
-            S->sp[species[i].target].reserve_hint += ions * species[i].z_max;
+            S->sp[species[i].target].reserve_hint += initial_count(*grid, species[i]) * species[i].z_max;
         }
     for (int i = 0; i < nspecies && rc == HK_OK; ++i) rc = init_species(S, i);
     for (int i = 0; i < nspecies && rc == HK_OK; ++i)
@@ -851,6 +952,21 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
             std::memcpy(&f, &b, 4);
             if (rc == HK_OK) rc = raise_wmax(S, species[i].target, f);
         }
+    if (rc == HK_OK && run->enable_qed) {
+        // photons carry their parent's weight and pairs their photon's: one bound
+        // covers the leptons and photons of QED (spawns raise it further)
+        float wq = 0.f;
+        for (int i = 0; i < nspecies && rc == HK_OK; ++i) {
+            if (species[i].kind == HK_ION) continue;
+            unsigned b = 0;
+            if (hipMemcpy(&b, S->wmax + i, 4, hipMemcpyDeviceToHost) != hipSuccess) rc = HK_EDEVICE;
+            float f;
+            std::memcpy(&f, &b, 4);
+            wq = std::max(wq, f);
+        }
+        for (int i = 0; i < nspecies && rc == HK_OK; ++i)
+            if (species[i].kind != HK_ION) rc = raise_wmax(S, i, wq);
+    }
     for (int i = 0; i < nspecies && rc == HK_OK; ++i) rc = ensure_inbox(S, i, inbox_need(S, i));
     if (rc == HK_OK && run->switch_mode != HK_SW_ALL_PIC) rc = ensure_fluid(S);
     if (rc == HK_OK && hipStreamSynchronize(S->s) != hipSuccess) rc = HK_EDEVICE;
@@ -1076,6 +1192,7 @@ int hk_set_particles(hk_sim *S, int isp, const hk_particles *in) {
         id[q] = in->id ? in->id[q] : q;
         zc[q] = in->z ? in->z[q] : (int)std::llround(D.d.charge);
         if (in->tau) tau[q] = in->tau[q];
+        else if (D.has_tau) tau[q] = tau0(S->run.seed, id[q]);   // as a new particle draws it
     }
     int rc = ensure_inbox(S, isp, (long long)n + 1024);
     if (rc) return rc;

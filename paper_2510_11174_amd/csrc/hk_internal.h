@@ -72,8 +72,27 @@ __host__ __device__ inline double u01d(uint32_t x) {
 }
 
 // Philox tags (one stream per purpose).
-enum { TAG_POS = 1, TAG_MOM = 2, TAG_ION = 3, TAG_CONV = 12, TAG_EMIT = 16, TAG_EMIT_TAU = 17,
-       TAG_PAIR = 18, TAG_PAIR_TAU = 19, TAG_DROP = 24 };
+enum { TAG_POS = 1, TAG_MOM = 2, TAG_ION = 3, TAG_CONV = 12, TAG_EMIT = 16, TAG_TAU = 17,
+       TAG_PAIR = 18, TAG_DROP = 24 };
+
+// Ids of particles born in QED events: splitmix64 (S. Vigna's finaliser)
+// of the parent id mixed with the step and the kind k (1 photon, 2 electron,
+// 3 positron); collisions are as unlikely as for any 64-bit hash.
+__host__ __device__ inline uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+__host__ __device__ inline uint64_t child_id(uint64_t parent, uint32_t step, uint32_t k) {
+    return splitmix64(parent ^ splitmix64(((uint64_t)step << 8) | k));
+}
+// Optical depth of a new QED particle: -ln(1 - r), r drawn from its id alone.
+__host__ __device__ inline double tau0(uint64_t seed, uint64_t id) {
+    uint32_t r[4];
+    draw4(seed, id, 0xffffffffu, TAG_TAU, 0, r);
+    return -log(1.0 - u01d(r[0]));
+}
 
 // ---------------------------------------------------------------------------------------
 // Particle storage: structure of arrays, binned per tile.  Tile t owns slots
@@ -112,6 +131,30 @@ __device__ inline int bin_count(const SpecP &sp, const Bins &b, int t, int &nf, 
 __device__ inline long long bin_slot(const SpecP &sp, int t, int p, int nf, int nbv) {
     return sp.off[t] + (p < nf ? p : sp.cap[t] - nbv + (p - nf));
 }
+
+// QED Monte Carlo: device tables and the particle sinks of the events.
+// Tables: We/Wb[256] spectrum totals over chi_i = 10^(-3 + 6 i / 255);
+// Xe/Xb[256][128] inverse cumulative spectra at u_j = (j + 1/2) / 128 in the
+// variable x of delta = x^3 / (x^3 + (1 - x)^3).
+#define QED_NCHI 256
+#define QED_NU 128
+struct QedP {
+    const double *We, *Wb, *Xe, *Xb;
+    double a_s, alpha_as;         // Schwinger field and alpha * a_s (normalized units)
+    PArr out1;                    // emitted photons (leptons) / pair electrons (photons)
+    int *out1_n;
+    int out1_cap, out1_tau;       // capacity; the sink species keeps optical depths
+    PArr out2;                    // pair positrons
+    int *out2_n;
+    int out2_cap, out2_tau;
+    int have1, have2;             // the sink species exist
+    unsigned *wmax1, *wmax2;      // weight bounds of the pair species (float bits)
+    double *ledger;               // photon ledger
+    const uint8_t *sw;            // switch map (emission only in kinetic nodes)
+    int hybrid;
+    uint64_t seed;
+    int step;
+};
 
 // Error flags raised by kernels (bitmask in a device int).
 enum { ERR_NONFINITE = 1, ERR_CFL = 2, ERR_INBOX = 4, ERR_TILE = 8 };
@@ -187,11 +230,11 @@ void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PA
                        int *nf_out, PArr mig, const long long *moff, const int *mcap, int *mcnt,
                        PArr inbox, int *inbox_n, int inbox_cap, real *const f[9], int *err,
                        unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
-                       hipStream_t s);
+                       int mode, const QedP &Q, hipStream_t s);
 void launch_ionize_static(const GridP &g, const SpecP &sp, PArr a, Bins b, int *active,
                           real *const f[9], const uint8_t *sw, int hybrid, const IonP *ion,
                           PArr eout, int *eout_n, int eout_cap, uint64_t seed, int step,
-                          double *ledger, int *err, unsigned *umax2, hipStream_t s);
+                          double *ledger, int *err, unsigned *umax2, int eout_tau, hipStream_t s);
 void launch_count_active(const GridP &g, const SpecP &sp, PArr a, Bins b, int zmax, int *active,
                          hipStream_t s);
 void launch_rho_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, double *rho, hipStream_t s);
@@ -214,3 +257,6 @@ void launch_spawn_nodes(const GridP &g, const SpecP &sp, const uint8_t *sw, real
                         real *uy, real *uz, real *const f[9], real wmin, int m, uint64_t seed,
                         int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
                         unsigned *wmax_bits, unsigned *umax2, hipStream_t s);
+
+// QED tables built on the host (hk_qed.cpp): We[256], Wb[256], Xe[256*128], Xb[256*128]
+const double *hk_qed_host_tables();

@@ -221,4 +221,59 @@ __device__ inline real below_one() {
 }
 
 
+// ------------------------------------------------------------------ QED lookups
+// Table position of chi: the tables cover log10 chi in [-3, 3] in 255 steps;
+// chi is clamped to that range.
+__device__ inline void qed_chi_pos(double chi, int &i, double &f) {
+    double x = (log10(chi) + 3.0) * (double)(QED_NCHI - 1) / 6.0;
+    x = fmin(fmax(x, 0.0), (double)(QED_NCHI - 1));
+    i = min((int)x, QED_NCHI - 2);
+    f = x - i;
+}
+// Spectrum total W(chi), linear in log10 chi.
+__device__ inline double qed_total(const double *W, double chi) {
+    int i; double f;
+    qed_chi_pos(chi, i, f);
+    return (1.0 - f) * W[i] + f * W[i + 1];
+}
+// Energy fraction delta for the uniform draw r: bilinear in (log10 chi, u) on
+// the table of x, then delta = x^3 / (x^3 + (1 - x)^3).
+__device__ inline double qed_fraction(const double *X, double chi, double r) {
+    int i; double f;
+    qed_chi_pos(chi, i, f);
+    double y = fmin(fmax(r * QED_NU - 0.5, 0.0), (double)(QED_NU - 1));
+    const int j = min((int)y, QED_NU - 2);
+    const double g = y - j;
+    const double *a = X + (size_t)i * QED_NU, *b = a + QED_NU;
+    const double x = (1.0 - f) * ((1.0 - g) * a[j] + g * a[j + 1]) + f * ((1.0 - g) * b[j] + g * b[j + 1]);
+    const double x3 = x * x * x, y3 = (1.0 - x) * (1.0 - x) * (1.0 - x);
+    return x3 / (x3 + y3);
+}
+// Quantum parameter of a lepton (momentum u) or photon (momentum k, photon = 1):
+// (energy / a_s) sqrt(|E + v x B|^2 - (v.E)^2), v the velocity.
+__device__ inline double qed_chi(double a_s, double ex, double ey, double ez, double bx, double by,
+                                 double bz, double ux, double uy, double uz, bool photon) {
+    const double p = sqrt(ux * ux + uy * uy + uz * uz);
+    if (!(p > 0.0)) return 0.0;
+    const double en = photon ? p : sqrt(1.0 + p * p);
+    const double vx = ux / en, vy = uy / en, vz = uz / en;
+    const double fx = ex + vy * bz - vz * by, fy = ey + vz * bx - vx * bz, fz = ez + vx * by - vy * bx;
+    const double ve = vx * ex + vy * ey + vz * ez;
+    const double q2 = fx * fx + fy * fy + fz * fz - ve * ve;
+    return en / a_s * sqrt(fmax(q2, 0.0));
+}
+
+// One slot per requesting lane in ctr, one atomic per wave.  Every lane of
+// the wave calls it.
+__device__ inline int wave_slot(int *ctr, bool want) {
+    const uint64_t m = __ballot(want);
+    if (!m) return -1;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(ctr, __popcll(m));
+    base = __shfl(base, leader);
+    return want ? base + __popcll(m & ((1ull << lane) - 1ull)) : -1;
+}
+
 }  // namespace hkdev

@@ -69,7 +69,7 @@ k_init(GridP g, int ppc, double u_th, double charge, uint64_t seed, const int *_
     out.w[tid] = (real)wcol[col];
     out.id[tid] = id;
     if (has_z) out.zc[tid] = (int)llround(charge);
-    if (has_tau) out.tau[tid] = 0.0;
+    if (has_tau) out.tau[tid] = tau0(seed, id);
 }
 
 // --------------------------------------------------------- wave helpers ------------------
@@ -200,6 +200,10 @@ k_migrate(GridP g, SpecP sp, PArr mig, const long long *__restrict__ moff,
 // ------------------------------------------------------------- the push -----------------
 constexpr int PBS = 512;   // push workgroup: 8 waves share one tile
 
+// MODE 0: charged particles; MODE 1: QED leptons (photon emission from the
+// fields at x^n and u^{n-1/2}, before the Boris push); MODE 2: photons
+// (Breit-Wheeler pair creation, then a ballistic move at c; no current).
+template <int MODE>
 __global__ void __launch_bounds__(PBS)
 k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_out, PArr mig,
        const long long *__restrict__ moff, const int *__restrict__ mcap, int *__restrict__ mcnt,
@@ -208,7 +212,7 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
        const real *__restrict__ By, const real *__restrict__ Bz, real *__restrict__ Jx,
        real *__restrict__ Jy, real *__restrict__ Jz, int *__restrict__ err,
        unsigned long long *__restrict__ stats, const unsigned *__restrict__ wmax_bits,
-       unsigned *__restrict__ umax2) {
+       unsigned *__restrict__ umax2, QedP Q) {
     __shared__ real sF[6 * FT3];
     __shared__ jacc_t sJ[3 * JT3];
     __shared__ int s_stay, s_move;
@@ -242,13 +246,15 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
         sF[4 * FT3 + e] = By[ch];
         sF[5 * FT3 + e] = Bz[ch];
     }
-    for (int e = threadIdx.x; e < 3 * JT3; e += PBS) sJ[e] = 0;
+    if (MODE != 2)
+        for (int e = threadIdx.x; e < 3 * JT3; e += PBS) sJ[e] = 0;
     if (threadIdx.x == 0) { s_stay = 0; s_move = 0; s_u2 = 0; }
     __syncthreads();
 
     const real dv = g.dx * g.dy * g.dz;
     const real hq = (real)0.5 * sp.qm * g.dt;
     float u2max = 0.f;   // largest |u|^2 pushed by this thread
+    double led = 0.0;    // photon ledger contributions of this thread
     const int lane = __lane_id();
     const uint64_t lt = (1ull << lane) - 1ull;
     const long long obase = sp.off[t];
@@ -273,10 +279,14 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
         }
         bool valid = cell >= 0;
         int ncell = -1, ntile = -1;
+        real rx = 0, ry = 0, rz = 0;
         real nrx = 0, nry = 0, nrz = 0, ux = 0, uy = 0, uz = 0, w = 0;
         uint64_t id = 0;
         int zc = 0;
         double tau = 0;
+        // QED event products: a photon (MODE 1) or a pair (MODE 2)
+        bool want1 = false, want2 = false;
+        double kx = 0, ky = 0, kz = 0, m1 = 0, m2 = 0;
         int ci = 0, cj = 0, ck = 0, lx = 0, ly = 0, lz = 0;
         if (valid) {
             cell_ijk(g, cell, ci, cj, ck);
@@ -287,7 +297,7 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
             }
         }
         if (valid) {
-            const real rx = in.rx[ip], ry = in.ry[ip], rz = in.rz[ip];
+            rx = in.rx[ip]; ry = in.ry[ip]; rz = in.rz[ip];
             ux = in.ux[ip]; uy = in.uy[ip]; uz = in.uz[ip];
             w = in.w[ip];
             id = in.id[ip];
@@ -301,42 +311,104 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
             real bx = tri(sF + 3 * FT3, X.in_, Y.ih, Z.ih, X.fn, Y.fh, Z.fh);
             real by = tri(sF + 4 * FT3, X.ih, Y.in_, Z.ih, X.fh, Y.fn, Z.fh);
             real bz = tri(sF + 5 * FT3, X.ih, Y.ih, Z.in_, X.fh, Y.fh, Z.fn);
-            // Boris rotation
-            real umx = ux + hq * ex, umy = uy + hq * ey, umz = uz + hq * ez;
-            real gm = sqrt((real)1 + umx * umx + umy * umy + umz * umz);
-            const real igm = hq / gm;
-            real tx_ = bx * igm, ty_ = by * igm, tz_ = bz * igm;
-            real t2 = tx_ * tx_ + ty_ * ty_ + tz_ * tz_;
-            const real is = (real)2 / (1 + t2);
-            real sx = tx_ * is, sy = ty_ * is, sz = tz_ * is;
-            real upx = umx + (umy * tz_ - umz * ty_);
-            real upy = umy + (umz * tx_ - umx * tz_);
-            real upz = umz + (umx * ty_ - umy * tx_);
-            real uqx = umx + (upy * sz - upz * sy);
-            real uqy = umy + (upz * sx - upx * sz);
-            real uqz = umz + (upx * sy - upy * sx);
-            ux = uqx + hq * ex; uy = uqy + hq * ey; uz = uqz + hq * ez;
-            real gam = sqrt((real)1 + ux * ux + uy * uy + uz * uz);
-            const real igam = (real)1 / gam;
-            real X1 = rx + dtdx * ux * igam;
-            real Y1 = ry + dtdy * uy * igam;
-            real Z1 = rz + dtdz * uz * igam;
-            // specular reflection at the open x walls
-            if (!per) {
-                if (ci == 0 && X1 < (real)0) { X1 = -X1; ux = -ux; }
-                else if (ci == g.nx - 1 && X1 >= (real)1) {
-                    X1 = (real)2 - X1; ux = -ux;
-                    if (X1 >= (real)1) X1 = below_one();
+            real X1, Y1, Z1;
+            bool gone = false;   // MODE 2: converted, or left through an open wall
+            if (MODE == 2) {
+                const double eps = sqrt((double)ux * ux + (double)uy * uy + (double)uz * uz);
+                const double chi = qed_chi(Q.a_s, ex, ey, ez, bx, by, bz, ux, uy, uz, true);
+                if (sp.qed && chi > 1e-3) {
+                    tau -= Q.alpha_as / eps * qed_total(Q.Wb, chi) * g.ddt;
+                    if (tau <= 0.0) {
+                        uint32_t r[4];
+                        draw4(Q.seed, id, (uint32_t)Q.step, TAG_PAIR, 0, r);
+                        const double d = qed_fraction(Q.Xb, chi, u01d(r[0]));
+                        const double ge = fmax(d * eps, 1.0), gp = fmax((1.0 - d) * eps, 1.0);
+                        m1 = sqrt(ge * ge - 1.0) / eps;
+                        m2 = sqrt(gp * gp - 1.0) / eps;
+                        kx = ux; ky = uy; kz = uz;
+                        want1 = Q.have1 && Q.have2;
+                        want2 = want1;
+                        led += want1 ? (double)w * (eps - ge - gp + 2.0) : (double)w * eps;
+                        gone = true;
+                    }
+                }
+                if (!gone) {
+                    const real ie = (real)(1.0 / eps);
+                    X1 = rx + dtdx * ux * ie;
+                    Y1 = ry + dtdy * uy * ie;
+                    Z1 = rz + dtdz * uz * ie;
+                    if (!per && ((ci == 0 && X1 < (real)0) || (ci == g.nx - 1 && X1 >= (real)1))) {
+                        led += (double)w * eps;
+                        gone = true;
+                    }
+                }
+            } else {
+                if (MODE == 1) {
+                    bool kin = true;
+                    if (Q.hybrid) {
+                        int ni = ci + (rx >= (real)0.5), nj = cj + (ry >= (real)0.5), nk = ck + (rz >= (real)0.5);
+                        if (per) ni = wrapi(ni, g.nx);
+                        if (nj >= g.ny) nj -= g.ny;
+                        if (nk >= g.nz) nk -= g.nz;
+                        kin = Q.sw[gidx(g, ni, nj, nk)] != 0;
+                    }
+                    const double chi = kin ? qed_chi(Q.a_s, ex, ey, ez, bx, by, bz, ux, uy, uz, false) : 0.0;
+                    if (chi > 1e-3) {
+                        const double gam = sqrt(1.0 + (double)ux * ux + (double)uy * uy + (double)uz * uz);
+                        tau -= Q.alpha_as / gam * qed_total(Q.We, chi) * g.ddt;
+                        if (tau <= 0.0) {
+                            uint32_t r[4];
+                            draw4(Q.seed, id, (uint32_t)Q.step, TAG_EMIT, 0, r);
+                            const double d = qed_fraction(Q.Xe, chi, u01d(r[0]));
+                            kx = d * ux; ky = d * uy; kz = d * uz;
+                            ux = (real)(ux - kx); uy = (real)(uy - ky); uz = (real)(uz - kz);
+                            draw4(Q.seed, id, (uint32_t)Q.step, TAG_TAU, 0, r);
+                            tau = -log(1.0 - u01d(r[0]));
+                            const double kk = sqrt(kx * kx + ky * ky + kz * kz);
+                            want1 = kk > 2.0 && Q.have1;
+                            if (!want1) led += (double)w * kk;
+                        }
+                    }
+                }
+                // Boris rotation
+                real umx = ux + hq * ex, umy = uy + hq * ey, umz = uz + hq * ez;
+                real gm = sqrt((real)1 + umx * umx + umy * umy + umz * umz);
+                const real igm = hq / gm;
+                real tx_ = bx * igm, ty_ = by * igm, tz_ = bz * igm;
+                real t2 = tx_ * tx_ + ty_ * ty_ + tz_ * tz_;
+                const real is = (real)2 / (1 + t2);
+                real sx = tx_ * is, sy = ty_ * is, sz = tz_ * is;
+                real upx = umx + (umy * tz_ - umz * ty_);
+                real upy = umy + (umz * tx_ - umx * tz_);
+                real upz = umz + (umx * ty_ - umy * tx_);
+                real uqx = umx + (upy * sz - upz * sy);
+                real uqy = umy + (upz * sx - upx * sz);
+                real uqz = umz + (upx * sy - upy * sx);
+                ux = uqx + hq * ex; uy = uqy + hq * ey; uz = uqz + hq * ez;
+                real gam = sqrt((real)1 + ux * ux + uy * uy + uz * uz);
+                const real igam = (real)1 / gam;
+                X1 = rx + dtdx * ux * igam;
+                Y1 = ry + dtdy * uy * igam;
+                Z1 = rz + dtdz * uz * igam;
+                // specular reflection at the open x walls
+                if (!per) {
+                    if (ci == 0 && X1 < (real)0) { X1 = -X1; ux = -ux; }
+                    else if (ci == g.nx - 1 && X1 >= (real)1) {
+                        X1 = (real)2 - X1; ux = -ux;
+                        if (X1 >= (real)1) X1 = below_one();
+                    }
                 }
             }
-            if (!(isfinite(ux) && isfinite(uy) && isfinite(uz) && fabs(X1 - rx) < 1 &&
-                  fabs(Y1 - ry) < 1 && fabs(Z1 - rz) < 1)) {
+            if (gone) {
+                valid = false;
+            } else if (!(isfinite(ux) && isfinite(uy) && isfinite(uz) && fabs(X1 - rx) < 1 &&
+                         fabs(Y1 - ry) < 1 && fabs(Z1 - rz) < 1)) {
                 atomicOr(err, isfinite(ux + uy + uz) ? ERR_CFL : ERR_NONFINITE);
                 valid = false;
             } else {
                 u2max = fmaxf(u2max, (float)(ux * ux + uy * uy + uz * uz));
                 // Esirkepov deposit of J^{n+1/2}
-                if (sp.q != (real)0) {
+                if (MODE != 2 && sp.q != (real)0) {
                     AxisS SX = axis_shapes(rx, X1), SY = axis_shapes(ry, Y1), SZ = axis_shapes(rz, Z1);
                     const real qw = sp.q * w / dv;
                     esirkepov_acc(sJ, lx, ly, lz, SX, SY, SZ, qw * cdx, qw * cdy, qw * cdz, inv_scale);
@@ -370,26 +442,67 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
         bm = __shfl(bm, 0);
         if (valid) {
             PArr dst = out;
-            long long j;
+            long long j = -1;
             if (stay) j = obase + bs + __popcll(ms & lt);
             else {
                 const int k = bm + __popcll(mm & lt);
                 if (k < mlim) { dst = mig; j = mbase + k; }
                 else {
                     const int q = atomicAdd(inbox_n, 1);
-                    if (q >= inbox_cap) { atomicOr(err, ERR_INBOX); continue; }
-                    dst = inbox;
-                    j = q;
+                    if (q >= inbox_cap) atomicOr(err, ERR_INBOX);
+                    else { dst = inbox; j = q; }
                 }
             }
-            dst.cell[j] = ncell;
-            dst.rx[j] = nrx; dst.ry[j] = nry; dst.rz[j] = nrz;
-            dst.ux[j] = ux; dst.uy[j] = uy; dst.uz[j] = uz;
-            dst.w[j] = w;
-            dst.id[j] = id;
-            if (sp.has_z) dst.zc[j] = zc;
-            if (sp.has_tau) dst.tau[j] = tau;
+            if (j >= 0) {
+                dst.cell[j] = ncell;
+                dst.rx[j] = nrx; dst.ry[j] = nry; dst.rz[j] = nrz;
+                dst.ux[j] = ux; dst.uy[j] = uy; dst.uz[j] = uz;
+                dst.w[j] = w;
+                dst.id[j] = id;
+                if (sp.has_z) dst.zc[j] = zc;
+                if (sp.has_tau) dst.tau[j] = tau;
+            }
         }
+        if (MODE != 0) {
+            // new particles sit where their parent was at the start of the step
+            const int k1 = wave_slot(Q.out1_n, want1);
+            const int k2 = MODE == 2 ? wave_slot(Q.out2_n, want2) : -1;
+            if (want1) {
+                if (k1 >= Q.out1_cap) atomicOr(err, ERR_INBOX);
+                else {
+                    PArr o = Q.out1;
+                    o.cell[k1] = cell;
+                    o.rx[k1] = rx; o.ry[k1] = ry; o.rz[k1] = rz;
+                    const double f = MODE == 2 ? m1 : 1.0;
+                    o.ux[k1] = (real)(f * kx); o.uy[k1] = (real)(f * ky); o.uz[k1] = (real)(f * kz);
+                    o.w[k1] = w;
+                    const uint64_t cid = child_id(id, (uint32_t)Q.step, MODE == 2 ? 2u : 1u);
+                    o.id[k1] = cid;
+                    if (Q.out1_tau) o.tau[k1] = tau0(Q.seed, cid);
+                    if (MODE == 2 && __float_as_uint(fabsf((float)w)) > *Q.wmax1)
+                        atomicMax(Q.wmax1, __float_as_uint(fabsf((float)w)));
+                }
+            }
+            if (MODE == 2 && want2) {
+                if (k2 >= Q.out2_cap) atomicOr(err, ERR_INBOX);
+                else {
+                    PArr o = Q.out2;
+                    o.cell[k2] = cell;
+                    o.rx[k2] = rx; o.ry[k2] = ry; o.rz[k2] = rz;
+                    o.ux[k2] = (real)(m2 * kx); o.uy[k2] = (real)(m2 * ky); o.uz[k2] = (real)(m2 * kz);
+                    o.w[k2] = w;
+                    const uint64_t cid = child_id(id, (uint32_t)Q.step, 3u);
+                    o.id[k2] = cid;
+                    if (Q.out2_tau) o.tau[k2] = tau0(Q.seed, cid);
+                    if (__float_as_uint(fabsf((float)w)) > *Q.wmax2)
+                        atomicMax(Q.wmax2, __float_as_uint(fabsf((float)w)));
+                }
+            }
+        }
+    }
+    if (MODE != 0) {
+        for (int o = 32; o > 0; o >>= 1) led += __shfl_xor(led, o);
+        if (lane == 0 && led != 0.0) atomicAdd(Q.ledger, led);
     }
     // per-tile bound on |u|^2 of the pushed particles (non-negative float bits
     // order like unsigned integers); read by the next switch evaluation
@@ -403,6 +516,7 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
         atomicAdd(&stats[0], (unsigned long long)(s_stay + s_move));   // particles pushed
         atomicAdd(&stats[1], 1ull);                                    // tiles with particles
     }
+    if (MODE == 2) return;
     // flush the LDS current tile (nodes ox-1 .. ox+TILE+1) to HBM
     for (int e = threadIdx.x; e < JT3; e += PBS) {
         int a = e % JT, b = (e / JT) % JT, c = e / (JT * JT);
@@ -440,7 +554,8 @@ k_ionize_static(GridP g, SpecP sp, PArr a, Bins bins, int *__restrict__ active,
                 const real *__restrict__ Ex, const real *__restrict__ Ey, const real *__restrict__ Ez,
                 const uint8_t *__restrict__ sw, int hybrid, const IonP *__restrict__ ion, PArr eout,
                 int *__restrict__ eout_n, int eout_cap, uint64_t seed, int step,
-                double *__restrict__ ledger, int *__restrict__ err, unsigned *__restrict__ umax2) {
+                double *__restrict__ ledger, int *__restrict__ err, unsigned *__restrict__ umax2,
+                int eout_tau) {
     __shared__ real sF[3 * FT3];
     const int t = blockIdx.x;
     int nf, nbv;
@@ -543,6 +658,7 @@ k_ionize_static(GridP g, SpecP sp, PArr a, Bins bins, int *__restrict__ active,
                 eout.ux[k] = ux; eout.uy[k] = uy; eout.uz[k] = uz;
                 eout.w[k] = w;
                 eout.id[k] = (1ull << 62) | ((uint64_t)lev << 56) | pid;
+                if (eout_tau) eout.tau[k] = tau0(seed, eout.id[k]);
                 led += (double)w * ion->lev[lev].ip_au * 27.211386245988 / 510998.95;
             }
             a.zc[ip] = z0 + nev;
@@ -651,20 +767,23 @@ void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PA
                        int *nf_out, PArr mig, const long long *moff, const int *mcap, int *mcnt,
                        PArr inbox, int *inbox_n, int inbox_cap, real *const f[9], int *err,
                        unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
-                       hipStream_t s) {
-    k_push<<<g.ntiles, PBS, 0, s>>>(g, sp, in, bin_in, out, nf_out, mig, moff, mcap, mcnt, inbox,
-                                    inbox_n, inbox_cap, f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX],
-                                    f[HK_BY], f[HK_BZ], f[HK_JX], f[HK_JY], f[HK_JZ], err, stats,
-                                    wmax_bits, umax2);
+                       int mode, const QedP &Q, hipStream_t s) {
+#define HK_PUSH_ARGS g, sp, in, bin_in, out, nf_out, mig, moff, mcap, mcnt, inbox, inbox_n, inbox_cap, \
+        f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], f[HK_JX], f[HK_JY], f[HK_JZ], err, \
+        stats, wmax_bits, umax2, Q
+    if (mode == 1) k_push<1><<<g.ntiles, PBS, 0, s>>>(HK_PUSH_ARGS);
+    else if (mode == 2) k_push<2><<<g.ntiles, PBS, 0, s>>>(HK_PUSH_ARGS);
+    else k_push<0><<<g.ntiles, PBS, 0, s>>>(HK_PUSH_ARGS);
+#undef HK_PUSH_ARGS
 }
 
 void launch_ionize_static(const GridP &g, const SpecP &sp, PArr a, Bins b, int *active,
                           real *const f[9], const uint8_t *sw, int hybrid, const IonP *ion,
                           PArr eout, int *eout_n, int eout_cap, uint64_t seed, int step,
-                          double *ledger, int *err, unsigned *umax2, hipStream_t s) {
+                          double *ledger, int *err, unsigned *umax2, int eout_tau, hipStream_t s) {
     k_ionize_static<<<g.ntiles, BS, 0, s>>>(g, sp, a, b, active, f[HK_EX], f[HK_EY], f[HK_EZ], sw,
                                             hybrid, ion, eout, eout_n, eout_cap, seed, step, ledger,
-                                            err, umax2);
+                                            err, umax2, eout_tau);
 }
 
 void launch_count_active(const GridP &g, const SpecP &sp, PArr a, Bins b, int zmax, int *active,

@@ -516,7 +516,7 @@ k_spawn(GridP g, SpecP sp, const uint8_t *__restrict__ sw, real *__restrict__ n,
         inbox.w[s] = w;
         inbox.id[s] = (1ull << 63) | ((uint64_t)step << 40) | (node << 6) | (uint64_t)q;
         if (sp.has_z) inbox.zc[s] = (int)sp.q;
-        if (sp.has_tau) inbox.tau[s] = 0.0;
+        if (sp.has_tau) inbox.tau[s] = tau0(seed, inbox.id[s]);
     }
     n[c] = 0; ux[c] = 0; uy[c] = 0; uz[c] = 0;
 }

@@ -89,7 +89,7 @@ ABI_SYMBOLS = ["hk_create", "hk_destroy", "hk_step", "hk_switch_map", "hk_set_sw
                "hk_set_switch_mode", "hk_diagnostics", "hk_get_field", "hk_set_field",
                "hk_get_rho", "hk_get_divE", "hk_particle_count", "hk_get_particles",
                "hk_set_particles", "hk_get_fluid", "hk_set_fluid", "hk_enable_timing",
-               "hk_timers", "hk_real_size", "hk_strerror", "hk_last_error"]
+               "hk_timers", "hk_qed_tables", "hk_real_size", "hk_strerror", "hk_last_error"]
 
 _libs: dict = {}
 
@@ -123,6 +123,7 @@ def load(prec: str = "f32"):
     L.hk_set_fluid.argtypes = [vp, C.c_int, vp, vp, C.c_size_t]
     L.hk_enable_timing.argtypes = [vp, C.c_int]
     L.hk_timers.argtypes = [vp, vp, C.c_int]
+    L.hk_qed_tables.argtypes = [vp, vp, vp, vp]
     L.hk_real_size.restype = C.c_int
     L.hk_strerror.restype = C.c_char_p
     L.hk_strerror.argtypes = [C.c_int]
@@ -335,3 +336,14 @@ class Sim:
         out = np.zeros(NTIMERS)
         self._check(self.lib.hk_timers(self.h, _ptr(out), NTIMERS))
         return dict(zip(TIMER_NAMES, out.tolist()))
+
+
+def qed_tables(precision: str = "f32"):
+    """(W_e[256], W_b[256], X_e[256, 128], X_b[256, 128]) as the library built them."""
+    L = load(precision)
+    We = np.empty(256); Wb = np.empty(256)
+    Xe = np.empty((256, 128)); Xb = np.empty((256, 128))
+    rc = L.hk_qed_tables(_ptr(We), _ptr(Wb), _ptr(Xe), _ptr(Xb))
+    if rc:
+        raise HKError(rc, "hk_qed_tables failed")
+    return We, Wb, Xe, Xb

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2510_11174_amd import build, hk
@@ -60,3 +61,19 @@ def test_config_marshalling_matches_header_layout():
     assert ctypes.sizeof(hk.SpeciesDesc) == 10 * 4 + 6 * 8 + 8 * 8
     assert ctypes.sizeof(hk.LaserDesc) == 4 * 4 + 5 * 8
     assert ctypes.sizeof(hk.Diag) == 8 + 8 + 2 * 8 + 4 * 6 * 8 + 8 * 8
+
+
+def test_qed_tables_match_oracle(oracle_mod):
+    # the library builds its tables with its own Airy functions (backward ODE
+    # integration) and quadrature; the oracle with Bessel integrals and Simpson
+    from paper_2510_11174_amd import hk
+    We, Wb, Xe, Xb = hk.qed_tables("f32")
+    oWe, oWb, oXe, oXb = oracle_mod.qed_tables()
+    np.testing.assert_allclose(We, oWe, rtol=1e-10, atol=0)
+    live = (oWb > 1e-200) & (Wb > 1e-200)      # rows where the pair rate does not underflow
+    np.testing.assert_allclose(Wb[live], oWb[live], rtol=1e-10, atol=0)
+    assert np.all(Wb[~live] < 1e-200) and np.all(oWb[~live] < 1e-200)
+    np.testing.assert_allclose(Xe, oXe, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(Xb[live], oXb[live], rtol=0, atol=1e-7)
+    f64 = hk.qed_tables("f64")
+    np.testing.assert_array_equal(f64[0], We)
