@@ -138,6 +138,17 @@ def lib():
         L.or_qed_chi.argtypes = [C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         L.or_schwinger_field.restype = C.c_double
         L.or_schwinger_field.argtypes = [C.c_double]
+        L.or_cnn_nparam.restype = C.c_int
+        L.or_cnn_set_rounding.argtypes = [C.c_int]
+        L.or_bf16.restype = C.c_double
+        L.or_bf16.argtypes = [C.c_double]
+        L.or_cnn_forward.argtypes = [C.c_void_p, C.c_void_p] + [C.c_int] * 4 + [C.c_void_p, C.c_void_p]
+        L.or_cnn_loss_grad.restype = C.c_double
+        L.or_cnn_loss_grad.argtypes = [C.c_void_p] * 4 + [C.c_int] * 4 + [C.c_double, C.c_void_p, C.c_void_p]
+        L.or_cnn_adamw.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int] + \
+            [C.c_double] * 5 + [C.c_int]
+        L.or_cnn_mask.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_int, C.c_void_p]
+        L.or_set_cnn.argtypes = [C.c_void_p] * 4
         _lib = L
     return _lib
 
@@ -276,6 +287,13 @@ class Oracle:
     def set_switch_mode(self, mode: str):
         lib().or_set_switch_mode(self.h, SWITCH[mode])
 
+    def set_cnn(self, params, mean, std):
+        """Install the switch network (FP64 parameter vector) and input statistics."""
+        p = np.ascontiguousarray(params, np.float64)
+        assert p.size == cnn_nparam()
+        m = np.ascontiguousarray(mean, np.float64); s = np.ascontiguousarray(std, np.float64)
+        lib().or_set_cnn(self.h, _ptr(p), _ptr(m), _ptr(s))
+
     def diagnostics(self) -> dict:
         d = Diag()
         lib().or_diagnostics(self.h, C.byref(d))
@@ -376,3 +394,52 @@ def qed_chi(a_s, e, b, u, photon=False) -> float:
 
 def schwinger_field(lambda_um: float) -> float:
     return lib().or_schwinger_field(float(lambda_um))
+
+
+# ---- CNN switch building blocks ------------------------------------------------------------
+
+def cnn_nparam() -> int:
+    return lib().or_cnn_nparam()
+
+
+def cnn_set_rounding(on: bool):
+    lib().or_cnn_set_rounding(int(on))
+
+
+def bf16(x: float) -> float:
+    return lib().or_bf16(float(x))
+
+
+def cnn_forward(params, x, mask=None) -> np.ndarray:
+    """Logits of crops x[B, D, H, W, 8] (normalized inputs) over the valid outputs."""
+    p = np.ascontiguousarray(params, np.float64); x = np.ascontiguousarray(x, np.float64)
+    B, D, H, W, _ = x.shape
+    out = np.empty((B, D - 8, H - 8, W - 8))
+    m = None if mask is None else np.ascontiguousarray(mask, np.float64)
+    lib().or_cnn_forward(_ptr(p), _ptr(x), B, D, H, W, None if m is None else _ptr(m), _ptr(out))
+    return out
+
+
+def cnn_loss_grad(params, x, y, e, lam=0.1, mask=None):
+    p = np.ascontiguousarray(params, np.float64); x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64); e = np.ascontiguousarray(e, np.float64)
+    B, D, H, W, _ = x.shape
+    g = np.empty(cnn_nparam())
+    m = None if mask is None else np.ascontiguousarray(mask, np.float64)
+    loss = lib().or_cnn_loss_grad(_ptr(p), _ptr(x), _ptr(y), _ptr(e), B, D, H, W, float(lam),
+                                  None if m is None else _ptr(m), _ptr(g))
+    return loss, g
+
+
+def cnn_adamw(params, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, wd=0.01):
+    """One AdamW step in place on params, m, v (FP64 arrays)."""
+    for a in (params, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = np.ascontiguousarray(grad, np.float64)
+    lib().or_cnn_adamw(_ptr(params), _ptr(g), _ptr(m), _ptr(v), int(t), lr, b1, b2, eps, wd, params.size)
+
+
+def cnn_mask(seed: int, node: int, step: int, sample: int) -> np.ndarray:
+    out = np.empty(32)
+    lib().or_cnn_mask(int(seed), int(node), int(step), int(sample), _ptr(out))
+    return out

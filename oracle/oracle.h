@@ -141,4 +141,18 @@ double or_qed_total(int kind, double chi);
 void or_qed_build_tables(double *We, double *Wb, double *Xe, double *Xb);
 double or_qed_chi(double a_s, const double e[3], const double b[3], const double u[3], int photon);
 double or_schwinger_field(double lambda_um);
+/* CNN switch: parameter count, BF16 rounding, forward over crops, loss and
+ * gradient, AdamW, dropout masks, node inputs; or_set_cnn installs the
+ * network and its input statistics for switch mode CNN. */
+int or_cnn_nparam(void);
+void or_cnn_set_rounding(int on);
+double or_bf16(double x);
+void or_cnn_forward(const double *par, const double *x, int B, int D, int H, int W,
+                    const double *mask, double *logit);
+double or_cnn_loss_grad(const double *par, const double *x, const double *y, const double *e,
+                        int B, int D, int H, int W, double lambda, const double *mask, double *grad);
+void or_cnn_adamw(double *par, const double *grad, double *m, double *v, int t, double lr,
+                  double b1, double b2, double eps, double wd, int n);
+void or_cnn_mask(uint64_t seed, uint64_t id, uint32_t step, int sample, double out[32]);
+int or_set_cnn(or_sim *s, const double *par, const double mean[8], const double stdv[8]);
 #endif
