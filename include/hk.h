@@ -232,6 +232,64 @@ int hk_timers(hk_sim *sim, double *ms, int n);
  * Paper: Methodology, plasma-model paragraph (Airy-function QED rates). */
 int hk_qed_tables(double *We, double *Wb, double *Xe, double *Xb);
 
+/* ------------------------------------------------------------------------
+ * The learned switch (Methodology: a neural network selects fluid or kinetic
+ * treatment per region, Monte Carlo dropout measures its uncertainty, the
+ * physics thresholds are the fallback; it is trained on the simulation's own
+ * data with an energy penalty).
+ *
+ * Network: 8 input channels per node (E, B at the node, electron density,
+ * rms momentum), normalized with frozen statistics (hk_cnn_set_norm); four
+ * valid 3^3 convolutions of 32 channels with exact GELU; a 1x1x1 head to one
+ * logit.  BF16 inputs, weights and activations, FP32 accumulation (matrix
+ * cores).  90017 parameters (hk_cnn_nparams), FP32 masters, laid out as
+ * W1[27][8][32], b1[32], then W[27][32][32], b[32] for layers 2..4, then the
+ * head w[32], b (tap = kx + 3 ky + 9 kz).
+ *
+ * Crops: x[B][D][H][W][8] FP32 normalized inputs, channels last (device
+ * pointers); outputs cover the valid (D-8)(H-8)(W-8) nodes, x fastest.
+ * Loss per output node: BCE(p, y) + lambda_e (1 - p) e, averaged; y the
+ * kinetic label (0/1), e the energy a cold-fluid conversion would destroy.
+ * Training dropout (p = 26/256 on the head input) uses Philox (seed, output
+ * node index, AdamW step); the switch uses 16 samples per node with counter
+ * (node, evaluation number), mean p > 0.5 = kinetic unless the samples' std
+ * exceeds 0.2 (then the threshold decision stays). */
+typedef struct hk_cnn hk_cnn;
+typedef struct {
+    uint64_t seed;          /* dropout streams */
+    void *stream;           /* hipStream_t or NULL */
+    hk_alloc_fn alloc;      /* optional device allocator */
+    hk_free_fn free;
+    void *alloc_ctx;
+} hk_cnn_desc;
+typedef struct {
+    double lr, beta1, beta2, eps, weight_decay;   /* AdamW */
+    double lambda_e;                               /* energy penalty weight */
+    int32_t dropout, pad;                          /* train with head-input dropout */
+} hk_cnn_train_desc;
+
+int hk_cnn_nparams(void);
+int hk_cnn_create(const hk_cnn_desc *desc, hk_cnn **out);
+void hk_cnn_destroy(hk_cnn *cnn);
+/* host FP32 parameters in and out (n = hk_cnn_nparams()); setting resets AdamW */
+int hk_cnn_set_params(hk_cnn *cnn, const float *params, size_t n);
+int hk_cnn_get_params(hk_cnn *cnn, float *params, size_t n);
+/* input statistics: 8 means and 8 standard deviations (host) */
+int hk_cnn_set_norm(hk_cnn *cnn, const float *mean, const float *stdv);
+/* logits (device FP32, B (D-8)(H-8)(W-8)) of crops x (device), no dropout */
+int hk_cnn_forward(hk_cnn *cnn, const float *x, int B, int D, int H, int W, float *logit);
+/* loss and gradient (host FP32, n = hk_cnn_nparams(), may be NULL); y and e
+ * device FP32 per output node; mask_step < 0: no dropout */
+int hk_cnn_loss_grad(hk_cnn *cnn, const float *x, const float *y, const float *e, int B, int D, int H,
+                     int W, float lambda_e, int mask_step, float *grad_host, double *loss);
+/* one AdamW step on a batch (dropout masks keyed by the step count) */
+int hk_cnn_train_step(hk_cnn *cnn, const float *x, const float *y, const float *e, int B, int D, int H,
+                      int W, const hk_cnn_train_desc *train, double *loss);
+const char *hk_cnn_last_error(const hk_cnn *cnn);
+/* the network the simulation's HK_SW_CNN mode uses (borrowed; NULL detaches;
+ * without one the mode decides by the thresholds alone) */
+int hk_set_cnn(hk_sim *sim, hk_cnn *cnn);
+
 int hk_real_size(void);
 const char *hk_strerror(int code);
 const char *hk_last_error(const hk_sim *sim);

@@ -14,6 +14,13 @@
 #include <vector>
 
 #include "hk_internal.h"
+#include "hk_cnn_internal.h"
+
+void cnn_launch_inputs(const GridP &g, real *const f[9], const real *mom, const float mean[8],
+                       const float inv_std[8], unsigned short *x, hipStream_t s);
+void cnn_launch_decide(const GridP &g, const unsigned short *a4, const unsigned short *wh, const float *bh,
+                       uint64_t seed, uint32_t eval, uint8_t *hot, uint8_t *notcold, int *nfall,
+                       float *pmean, hipStream_t s);
 
 namespace {
 
@@ -56,6 +63,10 @@ struct DevSpecies {
 struct hk_sim {
     GridP g{};
     double *qed_tab = nullptr;   // device copy of the QED tables (enable_qed)
+    hk_cnn *cnn = nullptr;       // learned switch (borrowed)
+    uint32_t cnn_evals = 0;      // evaluations so far (dropout counter)
+    unsigned short *cnn_x = nullptr;   // padded BF16 node inputs of the grid
+    int *cnn_nfall = nullptr;    // nodes that kept the threshold decision, last evaluation
     double a_s = 0.0;            // Schwinger field in normalized units
     int photon_sp = -1, electron_sp = -1, positron_sp = -1;   // QED sinks (first of each kind)
     hk_grid_desc gd{};
@@ -577,6 +588,30 @@ SwitchP switch_params(const hk_sim *S) {
     return P;
 }
 
+// Learned switch on the whole node grid: inputs with a 4-node halo, the four
+// convolutions, then 16 dropout samples of the head decide where the network
+// is confident; elsewhere the threshold flags stay.
+void cnn_switch(hk_sim *S) {
+    const GridP &g = S->g;
+    hk_cnn *c = S->cnn;
+    const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
+    const int D = g.nz + 8, H = g.ny + 8, W = NX + 8;
+    if (!S->cnn_x) S->cnn_x = (unsigned short *)dalloc(S, sizeof(unsigned short) * 8 * (size_t)D * H * W);
+    if (!S->cnn_nfall) S->cnn_nfall = (int *)dalloc(S, sizeof(int));
+    if (!S->cnn_x || !S->cnn_nfall) { fail(S, HK_ENOMEM, "CNN switch inputs"); return; }
+    cnn_launch_inputs(g, S->f, S->mom, c->mean, c->inv_std, S->cnn_x, S->s);
+    const unsigned short *a4;
+    if (cnn_forward_bf16(c, S->cnn_x, 1, D, H, W, false, S->s, &a4) != HK_OK) {
+        fail(S, HK_ENOMEM, "CNN switch: %s", c->err.c_str());
+        return;
+    }
+    launch_zero(S->cnn_nfall, sizeof(int), S->s);
+    const long long head = 27LL * 8 * 32 + 32 + 3 * (27LL * 32 * 32 + 32);
+    cnn_launch_decide(g, a4, c->wh, c->p + head + 32, S->run.seed, S->cnn_evals, S->hot, S->notcold,
+                      S->cnn_nfall, nullptr, S->s);
+    S->cnn_evals++;
+}
+
 // Threshold criterion: nearest-node moments, indicators, dilation, hysteresis.
 void switch_eval(hk_sim *S) {
     hipStream_t s = S->s;
@@ -614,6 +649,7 @@ void switch_eval(hk_sim *S) {
     }
     SwitchP P = switch_params(S);
     launch_indicators_nodes(g, P, S->mom, S->f, ions, nion, S->hot, S->notcold, s);
+    if (S->run.switch_mode == HK_SW_CNN && S->cnn) cnn_switch(S);
     launch_dilate_nodes(g, P, S->hot, S->notcold, S->sw, S->calm, s);
 }
 
@@ -815,6 +851,13 @@ bool check_grid(const hk_grid_desc *g) {
 
 extern "C" {
 
+int hk_set_cnn(hk_sim *S, hk_cnn *cnn) {
+    if (!S) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    S->cnn = cnn;
+    return HK_OK;
+}
+
 int hk_qed_tables(double *We, double *Wb, double *Xe, double *Xb) {
     if (!We || !Wb || !Xe || !Xb) return HK_EINVAL;
     const double *t = hk_qed_host_tables();
@@ -863,7 +906,6 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
                             d.target < 0 || d.target >= nspecies || d.mobile))
             return HK_EINVAL;
     }
-    if (run->switch_mode == HK_SW_CNN) return HK_ENOTSUP;
     if (run->switch_every < 0 || run->dilation < 0 || run->dilation > 4 || run->hysteresis < 1 ||
         run->hysteresis > 255)
         return HK_EINVAL;
@@ -1010,7 +1052,6 @@ int hk_step(hk_sim *S, int nsteps) {
 int hk_set_switch_mode(hk_sim *S, int mode) {
     if (!S || mode < HK_SW_ALL_PIC || mode > HK_SW_FIXED) return HK_EINVAL;
     if (S->poisoned) return HK_ESTATE;
-    if (mode == HK_SW_CNN) return fail(S, HK_ENOTSUP, "learned switch not built");
     if (mode == HK_SW_ALL_PIC) {
         for (int i = 0; i < S->nsp; ++i)
             if (S->sp[i].fn) return fail(S, HK_ESTATE, "fluid present: cannot return to all-PIC");
@@ -1335,7 +1376,20 @@ int hk_diagnostics(hk_sim *S, hk_diag *d) {
     d->conv_loss = led[0];
     d->ion_energy = led[1];
     d->photon_energy = led[2];
-    d->fallback_fraction = S->fallback_fraction;
+    d->fallback_fraction = 0.0;
+    if (S->run.switch_mode == HK_SW_CNN) {
+        int nf = 0;
+        if (S->cnn && !S->cnn_nfall) {
+            d->fallback_fraction = 0.0;   // not evaluated yet
+        } else if (S->cnn) {
+            HIPCHK(S, hipMemcpyAsync(&nf, S->cnn_nfall, sizeof(int), hipMemcpyDeviceToHost, S->s));
+            HIPCHK(S, hipStreamSynchronize(S->s));
+            const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
+            d->fallback_fraction = (double)nf / ((double)NX * g.ny * g.nz);
+        } else {
+            d->fallback_fraction = 1.0;   // no network: every node decided by the thresholds
+        }
+    }
     return HK_OK;
 }
 

@@ -1,0 +1,501 @@
+// The learned regime switch on gfx950: a 4-layer 3D CNN (valid 3^3
+// convolutions, 32 channels, exact GELU) with a 1x1x1 head, in BF16 with FP32
+// accumulation on the matrix cores, its backward pass and AdamW.
+//
+// Paper: abstract and Methodology (a neural network picks fluid or kinetic
+// treatment per region; Monte Carlo dropout gives its uncertainty; physics
+// thresholds are the fallback; it is trained on data the simulation makes,
+// with an energy penalty).
+//
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16: rows are 16
+// consecutive output voxels along x, columns the 32 output channels (two
+// 16-wide halves), and K runs over (tap, input channel), k = tap * CIN + ci,
+// tap = kx + 3 ky + 9 kz, padded to a multiple of 32.  Lane l holds A[l%16]
+// [8 (l/16) .. +8] (8 channels of one tap: one 16-byte load, channels last),
+// B[8 (l/16) .. +8][l%16] (16 bytes of the weight matrix stored co-major), and
+// D[4 (l/16) + i][l%16], i < 4.  The weight matrix of a layer sits in LDS.
+// The data gradient is the same GEMM over input voxels with K = (tap, co) and
+// the transposed weights; the weight gradient is a GEMM with K over voxels on
+// v_mfma_f32_32x32x16_bf16 (rows (tap, ci), columns co).
+//
+// Activations are stored channels last in BF16 (round to nearest even from
+// FP32); pre-activations in FP32 when the backward pass needs them.
+#include "hk_internal.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int NC = 32;
+constexpr int CBS = 256;                  // 4 waves
+
+__device__ inline unsigned short bf16_bits(float x) {
+    // round to nearest even (finite inputs)
+    const unsigned u = __float_as_uint(x);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf16_val(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
+
+__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ inline float gelu_d(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * __expf(-0.5f * z * z) * 0.3989422804014327f;
+}
+
+struct Dims { int B, D, H, W; };   // voxel grid of an activation
+
+__device__ inline long long vidx(const Dims &d, int b, int z, int y, int x) {
+    return (((long long)b * d.D + z) * d.H + y) * d.W + x;
+}
+
+// ------------------------------------------------------------------ forward
+// out dims = in dims - 2.  Wf: [NC][kpad] BF16 (co-major), kpad = 27 CIN
+// rounded up to 32 with zeros.  Each wave computes 16 x-voxels of one output
+// row; a workgroup loops over rows.
+template <int CIN>
+__global__ void __launch_bounds__(CBS)
+k_conv_fwd(Dims in, const unsigned short *__restrict__ act, const unsigned short *__restrict__ Wf,
+           const float *__restrict__ bias, float *__restrict__ zout, unsigned short *__restrict__ aout) {
+    constexpr int K = 27 * CIN, KPAD = (K + 31) / 32 * 32;
+    __shared__ __attribute__((aligned(16))) unsigned short sW[NC * KPAD];
+    for (int e = threadIdx.x; e < NC * KPAD / 8; e += CBS)
+        reinterpret_cast<uint4 *>(sW)[e] = reinterpret_cast<const uint4 *>(Wf)[e];
+    __syncthreads();
+    const Dims out{in.B, in.D - 2, in.H - 2, in.W - 2};
+    const int segs = (out.W + 15) / 16;
+    const long long nrows = (long long)out.B * out.D * out.H * segs;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    for (long long row = (long long)blockIdx.x * 4 + wave; row < nrows; row += (long long)gridDim.x * 4) {
+        const int seg = (int)(row % segs);
+        long long q = row / segs;
+        const int y = (int)(q % out.H); q /= out.H;
+        const int z = (int)(q % out.D);
+        const int b = (int)(q / out.D);
+        const int x0 = seg * 16;
+        const bool xin = x0 + r < out.W;
+        f32x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+        for (int kb = 0; kb < KPAD; kb += 32) {
+            const int k = kb + 8 * g;
+            bf16x8 a;
+            uint4 raw = make_uint4(0, 0, 0, 0);
+            if (xin && k < K) {
+                const int t = k / CIN, ci = k % CIN;
+                const int kx = t % 3, ky = (t / 3) % 3, kz = t / 9;
+                const long long v = vidx(in, b, z + kz, y + ky, x0 + r + kx);
+                raw = *reinterpret_cast<const uint4 *>(act + v * CIN + ci);
+            }
+            a = __builtin_bit_cast(bf16x8, raw);
+            const bf16x8 w0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + r * KPAD + k));
+            const bf16x8 w1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + (16 + r) * KPAD + k));
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w1, acc1, 0, 0, 0);
+        }
+        for (int i = 0; i < 4; ++i) {
+            const int x = x0 + 4 * g + i;
+            if (x >= out.W) continue;
+            const long long v = vidx(out, b, z, y, x);
+            const float z0 = acc0[i] + bias[r], z1 = acc1[i] + bias[16 + r];
+            if (zout) { zout[v * NC + r] = z0; zout[v * NC + 16 + r] = z1; }
+            aout[v * NC + r] = bf16_bits(gelu(z0));
+            aout[v * NC + 16 + r] = bf16_bits(gelu(z1));
+        }
+    }
+}
+
+// ---------------------------------------------------------- data gradient
+// din[u][ci] = sum_{t, co} dz[u - off(t)][co] W[t][ci][co] over the input
+// voxels u (dims `in`; dz lives on in - 2), then times GELU'(z_in[u][ci]) and
+// stored in BF16: the pre-activation gradient of the layer below.  Wb:
+// [CIN][864] BF16 with k = t * 32 + co.  CIN = 32 here (layer 1's input needs
+// no gradient).
+__global__ void __launch_bounds__(CBS)
+k_conv_bwd_data(Dims in, const unsigned short *__restrict__ dz, const unsigned short *__restrict__ Wb,
+                const float *__restrict__ zin, unsigned short *__restrict__ dzin) {
+    constexpr int KPAD = 27 * NC;
+    __shared__ __attribute__((aligned(16))) unsigned short sW[NC * KPAD];
+    for (int e = threadIdx.x; e < NC * KPAD / 8; e += CBS)
+        reinterpret_cast<uint4 *>(sW)[e] = reinterpret_cast<const uint4 *>(Wb)[e];
+    __syncthreads();
+    const Dims out{in.B, in.D - 2, in.H - 2, in.W - 2};
+    const int segs = (in.W + 15) / 16;
+    const long long nrows = (long long)in.B * in.D * in.H * segs;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    for (long long row = (long long)blockIdx.x * 4 + wave; row < nrows; row += (long long)gridDim.x * 4) {
+        const int seg = (int)(row % segs);
+        long long q = row / segs;
+        const int y = (int)(q % in.H); q /= in.H;
+        const int z = (int)(q % in.D);
+        const int b = (int)(q / in.D);
+        const int x0 = seg * 16;
+        const int u = x0 + r;
+        f32x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+        for (int kb = 0; kb < KPAD; kb += 32) {
+            const int k = kb + 8 * g;
+            const int t = k / NC, co = k % NC;
+            const int kx = t % 3, ky = (t / 3) % 3, kz = t / 9;
+            const int ox = u - kx, oy = y - ky, oz = z - kz;
+            uint4 raw = make_uint4(0, 0, 0, 0);
+            if (u < in.W && ox >= 0 && ox < out.W && oy >= 0 && oy < out.H && oz >= 0 && oz < out.D)
+                raw = *reinterpret_cast<const uint4 *>(dz + vidx(out, b, oz, oy, ox) * NC + co);
+            const bf16x8 a = __builtin_bit_cast(bf16x8, raw);
+            const bf16x8 w0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + r * KPAD + k));
+            const bf16x8 w1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + (16 + r) * KPAD + k));
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w1, acc1, 0, 0, 0);
+        }
+        for (int i = 0; i < 4; ++i) {
+            const int x = x0 + 4 * g + i;
+            if (x >= in.W) continue;
+            const long long v = vidx(in, b, z, y, x);
+            dzin[v * NC + r] = bf16_bits(acc0[i] * gelu_d(zin[v * NC + r]));
+            dzin[v * NC + 16 + r] = bf16_bits(acc1[i] * gelu_d(zin[v * NC + 16 + r]));
+        }
+    }
+}
+
+// -------------------------------------------------------- weight gradient
+// gW[t][ci][co] += sum_v act[v + off(t)][ci] dz[v][co], over the output
+// voxels v (dims in - 2).  One wave per (tap, chunk of 16-voxel x-segments);
+// MFMA 32x32x16: A[m = ci][k = voxel], B[k = voxel][n = co]; lane l holds
+// A[l%32][8 (l/32) .. +8], B[8 (l/32) .. +8][l%32], D[8 (i/4) + 4 (l/32) + i%4][l%32].
+template <int CIN>
+__global__ void __launch_bounds__(CBS)
+k_conv_bwd_weight(Dims in, const unsigned short *__restrict__ act, const unsigned short *__restrict__ dz,
+                  float *__restrict__ gW, int seg_per_wave) {
+    const Dims out{in.B, in.D - 2, in.H - 2, in.W - 2};
+    const int segs = (out.W + 15) / 16;
+    const long long nrows = (long long)out.B * out.D * out.H * segs;
+    const int lane = threadIdx.x & 63;
+    const long long wid = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int t = (int)(wid % 27);
+    const long long chunk = wid / 27;
+    const int kx = t % 3, ky = (t / 3) % 3, kz = t / 9;
+    const int m = lane & 31, h = lane >> 5;
+    f32x16 acc = {};
+    const long long r0 = chunk * seg_per_wave;
+    for (long long row = r0; row < r0 + seg_per_wave && row < nrows; ++row) {
+        const int seg = (int)(row % segs);
+        long long q = row / segs;
+        const int y = (int)(q % out.H); q /= out.H;
+        const int z = (int)(q % out.D);
+        const int b = (int)(q / out.D);
+        bf16x8 a, bb;
+        for (int i = 0; i < 8; ++i) {
+            const int x = seg * 16 + 8 * h + i;
+            unsigned short av = 0, dv = 0;
+            if (x < out.W) {
+                if (m < CIN) av = act[vidx(in, b, z + kz, y + ky, x + kx) * CIN + m];
+                dv = dz[vidx(out, b, z, y, x) * NC + m];
+            }
+            a[i] = __builtin_bit_cast(__bf16, av);
+            bb[i] = __builtin_bit_cast(__bf16, dv);
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
+    }
+    if (r0 >= nrows) return;
+    for (int i = 0; i < 16; ++i) {
+        const int ci = 8 * (i / 4) + 4 * h + (i % 4), co = m;
+        if (ci < CIN && acc[i] != 0.f) atomicAdd(&gW[((long long)t * CIN + ci) * NC + co], acc[i]);
+    }
+}
+
+// bias gradient: gb[co] += sum_v dz[v][co]
+__global__ void __launch_bounds__(CBS)
+k_bias_grad(long long n, const unsigned short *__restrict__ dz, float *__restrict__ gb) {
+    __shared__ float s[NC];
+    if (threadIdx.x < NC) s[threadIdx.x] = 0.f;
+    __syncthreads();
+    const int co = threadIdx.x & 31;
+    float acc = 0.f;
+    for (long long v = (long long)blockIdx.x * (CBS / 32) + threadIdx.x / 32; v < n;
+         v += (long long)gridDim.x * (CBS / 32))
+        acc += bf16_val(dz[v * NC + co]);
+    atomicAdd(&s[co], acc);
+    __syncthreads();
+    if (threadIdx.x < NC && s[threadIdx.x] != 0.f) atomicAdd(&gb[threadIdx.x], s[threadIdx.x]);
+}
+
+// ------------------------------------------------------------------- head
+// dropout keep factors of channel c: byte c of Philox draws (tag TAG_DROP,
+// draws 2s and 2s + 1) >= 26 keeps it, scaled by 256/230
+__device__ inline void drop_mask(uint64_t seed, uint64_t id, uint32_t step, int sample, float m[NC]) {
+    for (int hh = 0; hh < 2; ++hh) {
+        uint32_t r[4];
+        draw4(seed, id, step, TAG_DROP, (uint32_t)(2 * sample + hh), r);
+        for (int c = 0; c < 16; ++c) {
+            const uint32_t byte = (r[c / 4] >> (8 * (c % 4))) & 0xffu;
+            m[16 * hh + c] = byte >= 26u ? 256.0f / 230.0f : 0.0f;
+        }
+    }
+}
+
+// logits (optionally with the training dropout mask of (id = v, step))
+__global__ void __launch_bounds__(CBS)
+k_head(long long n, const unsigned short *__restrict__ a4, const unsigned short *__restrict__ wh,
+       const float *__restrict__ bh, int use_mask, uint64_t seed, uint32_t step, float *__restrict__ logit) {
+    const long long v = (long long)blockIdx.x * CBS + threadIdx.x;
+    if (v >= n) return;
+    float m[NC];
+    if (use_mask) drop_mask(seed, (uint64_t)v, step, 0, m);
+    float s = bh[0];
+    for (int c = 0; c < NC; ++c) s += bf16_val(wh[c]) * bf16_val(a4[v * NC + c]) * (use_mask ? m[c] : 1.0f);
+    logit[v] = s;
+}
+
+// loss, head gradient and the pre-activation gradient of layer 4 (BF16)
+__global__ void __launch_bounds__(CBS)
+k_head_bwd(long long n, const unsigned short *__restrict__ a4, const float *__restrict__ z4,
+           const unsigned short *__restrict__ wh, const float *__restrict__ bh, int use_mask, uint64_t seed,
+           uint32_t step, const float *__restrict__ y, const float *__restrict__ e, float lambda,
+           unsigned short *__restrict__ dz4, float *__restrict__ gwh, double *__restrict__ loss) {
+    __shared__ float sg[NC + 1];
+    __shared__ double sl;
+    if (threadIdx.x <= NC) sg[threadIdx.x] = 0.f;
+    if (threadIdx.x == 0) sl = 0.0;
+    __syncthreads();
+    const long long v = (long long)blockIdx.x * CBS + threadIdx.x;
+    if (v < n) {
+        float m[NC];
+        if (use_mask) drop_mask(seed, (uint64_t)v, step, 0, m);
+        float s = bh[0];
+        for (int c = 0; c < NC; ++c) s += bf16_val(wh[c]) * bf16_val(a4[v * NC + c]) * (use_mask ? m[c] : 1.0f);
+        const float p = 1.0f / (1.0f + __expf(-s));
+        const float sp = s > 0.f ? s + log1pf(__expf(-s)) : log1pf(__expf(s));
+        atomicAdd(&sl, (double)(sp - y[v] * s + lambda * (1.0f - p) * e[v]) / (double)n);
+        const float dl = (p - y[v] - lambda * p * (1.0f - p) * e[v]) / (float)n;
+        for (int c = 0; c < NC; ++c) {
+            const float mc = use_mask ? m[c] : 1.0f;
+            atomicAdd(&sg[c], dl * bf16_val(a4[v * NC + c]) * mc);
+            dz4[v * NC + c] = bf16_bits(dl * bf16_val(wh[c]) * mc * gelu_d(z4[v * NC + c]));
+        }
+        atomicAdd(&sg[NC], dl);
+    }
+    __syncthreads();
+    if (threadIdx.x <= NC && sg[threadIdx.x] != 0.f) atomicAdd(&gwh[threadIdx.x], sg[threadIdx.x]);
+    if (threadIdx.x == 0 && sl != 0.0) atomicAdd(loss, sl);
+}
+
+// AdamW on the FP32 master parameters (decoupled weight decay)
+__global__ void __launch_bounds__(CBS)
+k_adamw(int n, float *__restrict__ p, const float *__restrict__ gr, float *__restrict__ m,
+        float *__restrict__ v, float lr, float b1, float b2, float eps, float wd, float c1, float c2) {
+    const int i = blockIdx.x * CBS + threadIdx.x;
+    if (i >= n) return;
+    const float g = gr[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * g, vi = b2 * v[i] + (1.0f - b2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1 / (sqrtf(vi / c2) + eps) + wd * p[i]);
+}
+
+// BF16 copies of the weights: forward (co-major, k = t CIN + ci, padded) and
+// data-gradient (ci-major, k = t 32 + co) layouts, and the head
+__global__ void __launch_bounds__(CBS)
+k_pack(const float *__restrict__ p, int cin, long long woff, int kpad, unsigned short *__restrict__ Wf,
+       unsigned short *__restrict__ Wb) {
+    const int i = blockIdx.x * CBS + threadIdx.x;
+    if (i >= NC * kpad) return;
+    const int co = i / kpad, k = i % kpad;
+    const int K = 27 * cin;
+    Wf[i] = k < K ? bf16_bits(p[woff + (long long)k * NC + co]) : (unsigned short)0;
+    if (Wb && i < cin * 27 * NC) {
+        const int ci = i / (27 * NC), kk = i % (27 * NC);
+        const int t = kk / NC, c2 = kk % NC;
+        Wb[i] = bf16_bits(p[woff + ((long long)t * cin + ci) * NC + c2]);
+    }
+}
+
+__global__ void k_pack_head(const float *__restrict__ p, long long off, unsigned short *__restrict__ wh) {
+    if (threadIdx.x < NC) wh[threadIdx.x] = bf16_bits(p[off + threadIdx.x]);
+}
+
+// FP32 (normalized) inputs -> BF16
+__global__ void __launch_bounds__(CBS)
+k_to_bf16(long long n, const float *__restrict__ x, unsigned short *__restrict__ o) {
+    const long long i = (long long)blockIdx.x * CBS + threadIdx.x;
+    if (i < n) o[i] = bf16_bits(x[i]);
+}
+
+// ------------------------------------------------------------- the switch
+// Node inputs of the canonical node grid into the padded BF16 grid
+// [nz + 8][ny + 8][NX + 8][8] (halo 4: wrap in y, z and periodic x; the wall
+// node repeated in open x), normalized with the frozen statistics.
+__device__ inline real node_field(const GridP &g, const real *F, int i, int j, int k, int hx, int hy,
+                                  int hz) {
+    const int per = g.bcx == HK_BC_PERIODIC;
+    int i0 = hx ? i - 1 : i, j0 = hy ? j - 1 : j, k0 = hz ? k - 1 : k;
+    real acc = 0;
+    for (int c = 0; c < (hz ? 2 : 1); ++c)
+        for (int b = 0; b < (hy ? 2 : 1); ++b)
+            for (int a = 0; a < (hx ? 2 : 1); ++a) {
+                int ii = i0 + a;
+                if (per) ii = wrapi(ii, g.nx);
+                else if (hx) ii = ii < 0 ? 0 : (ii > g.nx - 1 ? g.nx - 1 : ii);
+                real wgt = (hx ? (real)0.5 : (real)1) * (hy ? (real)0.5 : (real)1) * (hz ? (real)0.5 : (real)1);
+                acc += wgt * F[gidx(g, ii, wrapi(j0 + b, g.ny), wrapi(k0 + c, g.nz))];
+            }
+    return acc;
+}
+
+struct Norm { float mean[8], inv_std[8]; };
+
+__global__ void __launch_bounds__(CBS)
+k_cnn_inputs(GridP g, const real *__restrict__ Ex, const real *__restrict__ Ey, const real *__restrict__ Ez,
+             const real *__restrict__ Bx, const real *__restrict__ By, const real *__restrict__ Bz,
+             const real *__restrict__ mom, Norm nm, unsigned short *__restrict__ x) {
+    const int per = g.bcx == HK_BC_PERIODIC;
+    const int NX = per ? g.nx : g.nx + 1;
+    const int W = NX + 8, H = g.ny + 8, D = g.nz + 8;
+    const long long n = (long long)W * H * D;
+    const long long v = (long long)blockIdx.x * CBS + threadIdx.x;
+    if (v >= n) return;
+    const int i = (int)(v % W), j = (int)((v / W) % H), k = (int)(v / ((long long)W * H));
+    int ii = i - 4;
+    if (per) ii = wrapi(ii, g.nx);
+    else ii = ii < 0 ? 0 : (ii > NX - 1 ? NX - 1 : ii);
+    const int jj = wrapi(j - 4, g.ny), kk = wrapi(k - 4, g.nz);
+    const long long c = gidx(g, ii, jj, kk);
+    const double dv = (double)g.dx * g.dy * g.dz;
+    float f[8];
+    f[0] = node_field(g, Ex, ii, jj, kk, 1, 0, 0);
+    f[1] = node_field(g, Ey, ii, jj, kk, 0, 1, 0);
+    f[2] = node_field(g, Ez, ii, jj, kk, 0, 0, 1);
+    f[3] = node_field(g, Bx, ii, jj, kk, 0, 1, 1);
+    f[4] = node_field(g, By, ii, jj, kk, 1, 0, 1);
+    f[5] = node_field(g, Bz, ii, jj, kk, 1, 1, 0);
+    const float N = mom[c], U2 = mom[5 * g.nn + c];
+    f[6] = (float)(N / dv);
+    f[7] = N > 0.f ? sqrtf(U2 / N) : 0.f;
+    for (int q = 0; q < 8; ++q) x[v * 8 + q] = bf16_bits((f[q] - nm.mean[q]) * nm.inv_std[q]);
+}
+
+// 16 dropout samples of the head per node: mean p > 0.5 is kinetic unless the
+// samples' standard deviation exceeds 0.2 (then the threshold flags stay)
+__global__ void __launch_bounds__(CBS)
+k_cnn_decide(GridP g, const unsigned short *__restrict__ a4, const unsigned short *__restrict__ wh,
+             const float *__restrict__ bh, uint64_t seed, uint32_t eval, uint8_t *__restrict__ hot,
+             uint8_t *__restrict__ notcold, int *__restrict__ nfall, float *__restrict__ pmean) {
+    const int per = g.bcx == HK_BC_PERIODIC;
+    const int NX = per ? g.nx : g.nx + 1;
+    const long long n = (long long)NX * g.ny * g.nz;
+    const long long v = (long long)blockIdx.x * CBS + threadIdx.x;
+    bool fall = false;
+    if (v < n) {
+        const int i = (int)(v % NX), j = (int)((v / NX) % g.ny), k = (int)(v / ((long long)NX * g.ny));
+        const long long c = gidx(g, i, j, k);
+        float h[NC], w[NC];
+        for (int q = 0; q < NC; ++q) { h[q] = bf16_val(a4[v * NC + q]); w[q] = bf16_val(wh[q]); }
+        float ps[16], mean = 0.f;
+        for (int s = 0; s < 16; ++s) {
+            float m[NC];
+            drop_mask(seed, (uint64_t)c, eval, s, m);
+            float z = bh[0];
+            for (int q = 0; q < NC; ++q) z += w[q] * h[q] * m[q];
+            ps[s] = 1.0f / (1.0f + __expf(-z));
+            mean += ps[s];
+        }
+        mean *= 1.0f / 16.0f;
+        float var = 0.f;
+        for (int s = 0; s < 16; ++s) var += (ps[s] - mean) * (ps[s] - mean);
+        const float sd = sqrtf(var * (1.0f / 16.0f));
+        if (pmean) pmean[v] = mean;
+        if (sd > 0.2f) fall = true;
+        else {
+            hot[c] = mean > 0.5f;
+            notcold[c] = hot[c];
+        }
+    }
+    const uint64_t bal = __ballot(fall);
+    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(nfall, __popcll(bal));
+}
+
+inline unsigned nblk(long long n) { return (unsigned)((n + CBS - 1) / CBS); }
+inline unsigned rows_grid(long long rows) {
+    long long b = (rows + 3) / 4;
+    return (unsigned)(b < 4096 ? b : 4096);
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- launchers
+void cnn_launch_to_bf16(long long n, const float *x, unsigned short *o, hipStream_t s) {
+    k_to_bf16<<<nblk(n), CBS, 0, s>>>(n, x, o);
+}
+
+void cnn_launch_conv_fwd(int cin, int B, int D, int H, int W, const unsigned short *act,
+                         const unsigned short *Wf, const float *bias, float *zout, unsigned short *aout,
+                         hipStream_t s) {
+    Dims in{B, D, H, W};
+    const long long rows = (long long)B * (D - 2) * (H - 2) * ((W - 2 + 15) / 16);
+    if (cin == 8) k_conv_fwd<8><<<rows_grid(rows), CBS, 0, s>>>(in, act, Wf, bias, zout, aout);
+    else k_conv_fwd<32><<<rows_grid(rows), CBS, 0, s>>>(in, act, Wf, bias, zout, aout);
+}
+
+void cnn_launch_conv_bwd_data(int B, int D, int H, int W, const unsigned short *dz,
+                              const unsigned short *Wb, const float *zin, unsigned short *dzin,
+                              hipStream_t s) {
+    Dims in{B, D, H, W};
+    const long long rows = (long long)B * D * H * ((W + 15) / 16);
+    k_conv_bwd_data<<<rows_grid(rows), CBS, 0, s>>>(in, dz, Wb, zin, dzin);
+}
+
+void cnn_launch_conv_bwd_weight(int cin, int B, int D, int H, int W, const unsigned short *act,
+                                const unsigned short *dz, float *gW, float *gb, hipStream_t s) {
+    Dims in{B, D, H, W};
+    const long long rows = (long long)B * (D - 2) * (H - 2) * ((W - 2 + 15) / 16);
+    const int spw = 32;
+    const long long waves = 27 * ((rows + spw - 1) / spw);
+    const unsigned grid = (unsigned)((waves + 3) / 4);
+    if (cin == 8) k_conv_bwd_weight<8><<<grid, CBS, 0, s>>>(in, act, dz, gW, spw);
+    else k_conv_bwd_weight<32><<<grid, CBS, 0, s>>>(in, act, dz, gW, spw);
+    const long long n = (long long)B * (D - 2) * (H - 2) * (W - 2);
+    k_bias_grad<<<1024, CBS, 0, s>>>(n, dz, gb);
+}
+
+void cnn_launch_head(long long n, const unsigned short *a4, const unsigned short *wh, const float *bh,
+                     int use_mask, uint64_t seed, uint32_t step, float *logit, hipStream_t s) {
+    k_head<<<nblk(n), CBS, 0, s>>>(n, a4, wh, bh, use_mask, seed, step, logit);
+}
+
+void cnn_launch_head_bwd(long long n, const unsigned short *a4, const float *z4, const unsigned short *wh,
+                         const float *bh, int use_mask, uint64_t seed, uint32_t step, const float *y,
+                         const float *e, float lambda, unsigned short *dz4, float *gwh, double *loss,
+                         hipStream_t s) {
+    k_head_bwd<<<nblk(n), CBS, 0, s>>>(n, a4, z4, wh, bh, use_mask, seed, step, y, e, lambda, dz4, gwh, loss);
+}
+
+void cnn_launch_adamw(int n, float *p, const float *g, float *m, float *v, float lr, float b1, float b2,
+                      float eps, float wd, int t, hipStream_t s) {
+    const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
+    k_adamw<<<nblk(n), CBS, 0, s>>>(n, p, g, m, v, lr, b1, b2, eps, wd, c1, c2);
+}
+
+void cnn_launch_pack(const float *p, int layer_cin, long long woff, int kpad, unsigned short *Wf,
+                     unsigned short *Wb, hipStream_t s) {
+    k_pack<<<nblk((long long)NC * kpad), CBS, 0, s>>>(p, layer_cin, woff, kpad, Wf, Wb);
+}
+
+void cnn_launch_pack_head(const float *p, long long off, unsigned short *wh, hipStream_t s) {
+    k_pack_head<<<1, 64, 0, s>>>(p, off, wh);
+}
+
+void cnn_launch_inputs(const GridP &g, real *const f[9], const real *mom, const float mean[8],
+                       const float inv_std[8], unsigned short *x, hipStream_t s) {
+    Norm nm;
+    for (int q = 0; q < 8; ++q) { nm.mean[q] = mean[q]; nm.inv_std[q] = inv_std[q]; }
+    const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
+    const long long n = (long long)(NX + 8) * (g.ny + 8) * (g.nz + 8);
+    k_cnn_inputs<<<nblk(n), CBS, 0, s>>>(g, f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], mom,
+                                         nm, x);
+}
+
+void cnn_launch_decide(const GridP &g, const unsigned short *a4, const unsigned short *wh, const float *bh,
+                       uint64_t seed, uint32_t eval, uint8_t *hot, uint8_t *notcold, int *nfall,
+                       float *pmean, hipStream_t s) {
+    const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
+    const long long n = (long long)NX * g.ny * g.nz;
+    k_cnn_decide<<<nblk(n), CBS, 0, s>>>(g, a4, wh, bh, seed, eval, hot, notcold, nfall, pmean);
+}

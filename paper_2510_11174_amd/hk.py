@@ -85,11 +85,25 @@ class Particles(C.Structure):
                 ("id", C.c_void_p), ("z", C.c_void_p), ("tau", C.c_void_p)]
 
 
+class CnnDesc(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_ctx", C.c_void_p)]
+
+
+class CnnTrainDesc(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("weight_decay", C.c_double), ("lambda_e", C.c_double), ("dropout", C.c_int32),
+                ("pad", C.c_int32)]
+
+
 ABI_SYMBOLS = ["hk_create", "hk_destroy", "hk_step", "hk_switch_map", "hk_set_switch_map",
                "hk_set_switch_mode", "hk_diagnostics", "hk_get_field", "hk_set_field",
                "hk_get_rho", "hk_get_divE", "hk_particle_count", "hk_get_particles",
                "hk_set_particles", "hk_get_fluid", "hk_set_fluid", "hk_enable_timing",
-               "hk_timers", "hk_qed_tables", "hk_real_size", "hk_strerror", "hk_last_error"]
+               "hk_timers", "hk_qed_tables", "hk_cnn_nparams", "hk_cnn_create", "hk_cnn_destroy",
+               "hk_cnn_set_params", "hk_cnn_get_params", "hk_cnn_set_norm", "hk_cnn_forward",
+               "hk_cnn_loss_grad", "hk_cnn_train_step", "hk_cnn_last_error", "hk_set_cnn",
+               "hk_real_size", "hk_strerror", "hk_last_error"]
 
 _libs: dict = {}
 
@@ -124,6 +138,19 @@ def load(prec: str = "f32"):
     L.hk_enable_timing.argtypes = [vp, C.c_int]
     L.hk_timers.argtypes = [vp, vp, C.c_int]
     L.hk_qed_tables.argtypes = [vp, vp, vp, vp]
+    L.hk_cnn_nparams.restype = C.c_int
+    L.hk_cnn_create.argtypes = [P(CnnDesc), P(vp)]
+    L.hk_cnn_destroy.argtypes = [vp]
+    L.hk_cnn_set_params.argtypes = [vp, vp, C.c_size_t]
+    L.hk_cnn_get_params.argtypes = [vp, vp, C.c_size_t]
+    L.hk_cnn_set_norm.argtypes = [vp, vp, vp]
+    L.hk_cnn_forward.argtypes = [vp, vp] + [C.c_int] * 4 + [vp]
+    L.hk_cnn_loss_grad.argtypes = [vp, vp, vp, vp] + [C.c_int] * 4 + [C.c_float, C.c_int, vp,
+                                                                      P(C.c_double)]
+    L.hk_cnn_train_step.argtypes = [vp, vp, vp, vp] + [C.c_int] * 4 + [P(CnnTrainDesc), P(C.c_double)]
+    L.hk_cnn_last_error.restype = C.c_char_p
+    L.hk_cnn_last_error.argtypes = [vp]
+    L.hk_set_cnn.argtypes = [vp, vp]
     L.hk_real_size.restype = C.c_int
     L.hk_strerror.restype = C.c_char_p
     L.hk_strerror.argtypes = [C.c_int]
@@ -329,6 +356,11 @@ class Sim:
         self._check(self.lib.hk_get_divE(self.h, _ptr(out), out.size))
         return out
 
+    def set_cnn(self, cnn):
+        """Use `cnn` (a CNN, kept alive by this object) in switch mode "cnn"; None detaches."""
+        self._cnn = cnn
+        self._check(self.lib.hk_set_cnn(self.h, cnn.h if cnn is not None else None))
+
     def enable_timing(self, on=True):
         self._check(self.lib.hk_enable_timing(self.h, int(on)))
 
@@ -347,3 +379,78 @@ def qed_tables(precision: str = "f32"):
     if rc:
         raise HKError(rc, "hk_qed_tables failed")
     return We, Wb, Xe, Xb
+
+
+class CNN:
+    """The switch network on the GPU (device memory from torch's allocator).
+    Crops are torch tensors on cuda:0: x [B, D, H, W, 8] float32 (normalized),
+    y and e [B, D-8, H-8, W-8] float32."""
+
+    def __init__(self, seed: int = 0, precision: str = "f32"):
+        import torch
+        self.lib = load(precision)
+        self._mem = _TorchMemory()
+        d = CnnDesc(seed=seed, stream=self._mem.stream.cuda_stream, alloc=self._mem.alloc,
+                    free=self._mem.free, alloc_ctx=None)
+        h = C.c_void_p()
+        rc = self.lib.hk_cnn_create(C.byref(d), C.byref(h))
+        if rc:
+            raise HKError(rc, "hk_cnn_create failed")
+        self.h = h
+        self.nparams = self.lib.hk_cnn_nparams()
+
+    def _check(self, rc):
+        if rc:
+            raise HKError(rc, self.lib.hk_cnn_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hk_cnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, np.float32)
+        assert a.size == self.nparams
+        self._check(self.lib.hk_cnn_set_params(self.h, _ptr(a), a.size))
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(self.nparams, np.float32)
+        self._check(self.lib.hk_cnn_get_params(self.h, _ptr(a), a.size))
+        return a
+
+    def set_norm(self, mean, std):
+        m = np.ascontiguousarray(mean, np.float32); s = np.ascontiguousarray(std, np.float32)
+        self._check(self.lib.hk_cnn_set_norm(self.h, _ptr(m), _ptr(s)))
+
+    def forward(self, x):
+        import torch
+        x = x.contiguous()
+        B, D, H, W, _ = x.shape
+        out = torch.empty((B, D - 8, H - 8, W - 8), device=x.device, dtype=torch.float32)
+        self._check(self.lib.hk_cnn_forward(self.h, x.data_ptr(), B, D, H, W, out.data_ptr()))
+        return out
+
+    def loss_grad(self, x, y, e, lam=0.1, mask_step=-1):
+        x = x.contiguous(); y = y.contiguous(); e = e.contiguous()
+        B, D, H, W, _ = x.shape
+        g = np.empty(self.nparams, np.float32)
+        loss = C.c_double()
+        self._check(self.lib.hk_cnn_loss_grad(self.h, x.data_ptr(), y.data_ptr(), e.data_ptr(), B, D, H, W,
+                                              float(lam), int(mask_step), _ptr(g), C.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, x, y, e, lr=1e-3, lam=0.1, dropout=True, weight_decay=0.01):
+        x = x.contiguous(); y = y.contiguous(); e = e.contiguous()
+        B, D, H, W, _ = x.shape
+        t = CnnTrainDesc(lr=lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=weight_decay,
+                         lambda_e=lam, dropout=int(dropout))
+        loss = C.c_double()
+        self._check(self.lib.hk_cnn_train_step(self.h, x.data_ptr(), y.data_ptr(), e.data_ptr(), B, D, H,
+                                               W, C.byref(t), C.byref(loss)))
+        return loss.value
