@@ -147,6 +147,43 @@ def cpu_baseline(warm=60, timed=50):
             "pushes_per_s": n * timed / dt}
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16
+
+
+def cnn_inference(reps=20):
+    """One learned-switch evaluation's network pass on the ionizing-helium node
+    grid (129 x 64 x 64 nodes with the 4-node halo), timed with HIP events on
+    the library stream; flops are those of the four valid convolutions and the head."""
+    import numpy as np
+    import torch
+
+    from paper_2510_11174_amd import hk
+    from paper_2510_11174_amd import train as T
+    D, H, W = 64 + 8, 64 + 8, 129 + 8
+    cnn = hk.CNN(seed=1)
+    cnn.set_params(T.init_params(1))
+    x = torch.randn((1, D, H, W, 8), device="cuda", dtype=torch.float32)
+    flops = 0
+    for l, cin in enumerate((8, 32, 32, 32)):
+        flops += 2 * 27 * cin * 32 * (D - 2 * l - 2) * (H - 2 * l - 2) * (W - 2 * l - 2)
+    flops += 2 * 32 * (D - 8) * (H - 8) * (W - 8)
+    cnn.forward(x)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        cnn.forward(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    cnn.close()
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"bound": "mfma", "achieved": round(tf, 1), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4), "kernel": "k_conv_fwd (4 layers) + k_head",
+            "ms_per_eval": round(ms, 3), "flop_per_eval": flops,
+            "grid": "129 x 64 x 64 nodes + halo 4"}
+
+
 def field_l2(x, y):
     import numpy as np
     num = math.sqrt(sum(float(np.sum((x[c] - y[c]) ** 2)) for c in x))
@@ -253,6 +290,7 @@ def main():
         "timers_allpic_ms_per_step": {k: round(v / K, 4) for k, v in p["timers"].items() if k.endswith("_ms")},
         "rebins": {"hybrid": h["timers"]["rebins"], "all_pic": p["timers"]["rebins"]},
     }
+    out["roofline_cnn_switch"] = cnn_inference()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

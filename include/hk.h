@@ -286,6 +286,13 @@ int hk_cnn_loss_grad(hk_cnn *cnn, const float *x, const float *y, const float *e
 int hk_cnn_train_step(hk_cnn *cnn, const float *x, const float *y, const float *e, int B, int D, int H,
                       int W, const hk_cnn_train_desc *train, double *loss);
 const char *hk_cnn_last_error(const hk_cnn *cnn);
+/* Training data from a simulation, per node of the grid [nz][ny][NX] (NX = nx
+ * for periodic x, nx + 1 for open x), x fastest, all host arrays (NULL skips
+ * one): raw[8 n] the network's 8 inputs before normalization; ehat[n] the
+ * thermal energy (m_e c^2 n_c (c/omega0)^3, small-u limit) a cold-fluid
+ * conversion would destroy; hot[n] the threshold criterion's undilated flags
+ * now.  The switch map is left unchanged.  n must equal NX ny nz. */
+int hk_node_inputs(hk_sim *sim, double *raw, double *ehat, uint8_t *hot, size_t n);
 /* the network the simulation's HK_SW_CNN mode uses (borrowed; NULL detaches;
  * without one the mode decides by the thresholds alone) */
 int hk_set_cnn(hk_sim *sim, hk_cnn *cnn);

@@ -18,6 +18,7 @@
 
 void cnn_launch_inputs(const GridP &g, real *const f[9], const real *mom, const float mean[8],
                        const float inv_std[8], unsigned short *x, hipStream_t s);
+void cnn_launch_node_raw(const GridP &g, real *const f[9], const real *mom, float *out, hipStream_t s);
 void cnn_launch_decide(const GridP &g, const unsigned short *a4, const unsigned short *wh, const float *bh,
                        uint64_t seed, uint32_t eval, uint8_t *hot, uint8_t *notcold, int *nfall,
                        float *pmean, hipStream_t s);
@@ -67,6 +68,7 @@ struct hk_sim {
     uint32_t cnn_evals = 0;      // evaluations so far (dropout counter)
     unsigned short *cnn_x = nullptr;   // padded BF16 node inputs of the grid
     int *cnn_nfall = nullptr;    // nodes that kept the threshold decision, last evaluation
+    float *cnn_raw = nullptr;    // node inputs and conversion energy (hk_node_inputs)
     double a_s = 0.0;            // Schwinger field in normalized units
     int photon_sp = -1, electron_sp = -1, positron_sp = -1;   // QED sinks (first of each kind)
     hk_grid_desc gd{};
@@ -613,7 +615,11 @@ void cnn_switch(hk_sim *S) {
 }
 
 // Threshold criterion: nearest-node moments, indicators, dilation, hysteresis.
-void switch_eval(hk_sim *S) {
+// Switch moments of every fluid species (particles and fluid) and of the
+// ionizable ions.  use_bounds: particle moments take their fixed-point scale
+// from the per-tile |u|^2 bounds (the switch evaluation, which then restarts
+// them); otherwise they scan the tiles for it.
+int switch_moments(hk_sim *S, bool use_bounds, const IonP **ions) {
     hipStream_t s = S->s;
     const GridP &g = S->g;
     // fluid moments first: the first fluid species overwrites the arrays
@@ -626,20 +632,27 @@ void switch_eval(hk_sim *S) {
         first = 0;
     }
     if (first) launch_zero(S->mom, sizeof(real) * 7 * (size_t)g.nn, s);
-    const IonP *ions[4];
     int nion = 0;
     for (int isp = 0; isp < S->nsp; ++isp) {
         DevSpecies &D = S->sp[isp];
         SpecP P = specp(D);
         if (D.d.fluid && D.capacity)
             launch_moments_tiles(g, P, D.buf[D.cur], cur_bins(D), 0, 0, S->mom, S->wmax + isp,
-                                 D.d.mobile && D.umax_ok ? D.umax2 : nullptr, nullptr, s);
+                                 use_bounds && D.d.mobile && D.umax_ok ? D.umax2 : nullptr, nullptr, s);
         if (D.d.ionizable && S->run.enable_ionization && D.capacity) {
             launch_moments_tiles(g, P, D.buf[D.cur], cur_bins(D), 1, D.d.z_max, S->mom, S->wmax + isp,
                                  nullptr, D.d.mobile ? nullptr : D.active, s);
             if (nion < 4) ions[nion++] = D.ion;
         }
     }
+    return nion;
+}
+
+void switch_eval(hk_sim *S) {
+    hipStream_t s = S->s;
+    const GridP &g = S->g;
+    const IonP *ions[4];
+    const int nion = switch_moments(S, true, ions);
     // the |u|^2 bounds start again from here
     for (int isp = 0; isp < S->nsp; ++isp) {
         DevSpecies &D = S->sp[isp];
@@ -850,6 +863,41 @@ bool check_grid(const hk_grid_desc *g) {
 // ====================================================================== ABI ===============
 
 extern "C" {
+
+int hk_node_inputs(hk_sim *S, double *raw, double *ehat, uint8_t *hot, size_t nodes) {
+    if (!S) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    const GridP &g = S->g;
+    const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
+    const size_t n = (size_t)NX * g.ny * g.nz;
+    if (nodes != n) return fail(S, HK_EINVAL, "node count %zu, expected %zu", nodes, n);
+    int rc = ensure_fluid(S);
+    if (rc) return rc;
+    if (!S->cnn_raw) {
+        S->cnn_raw = (float *)dalloc(S, sizeof(float) * 9 * n);
+        if (!S->cnn_raw) return fail(S, HK_ENOMEM, "node inputs");
+    }
+    const IonP *ions[4];
+    const int nion = switch_moments(S, false, ions);
+    SwitchP P = switch_params(S);
+    // indicators into scratch flags; the switch map and its hysteresis state stay
+    launch_indicators_nodes(g, P, S->mom, S->f, ions, nion, S->hot, S->notcold, S->s);
+    cnn_launch_node_raw(g, S->f, S->mom, S->cnn_raw, S->s);
+    std::vector<float> h(9 * n);
+    std::vector<uint8_t> hh(g.nn);
+    HIPCHK(S, hipMemcpyAsync(h.data(), S->cnn_raw, sizeof(float) * 9 * n, hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipMemcpyAsync(hh.data(), S->hot, g.nn, hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    for (size_t v = 0; v < n; ++v) {
+        if (raw) for (int q = 0; q < 8; ++q) raw[8 * v + q] = h[9 * v + q];
+        if (ehat) ehat[v] = h[9 * v + 8];
+        if (hot) {
+            const int i = (int)(v % NX), j = (int)((v / NX) % g.ny), k = (int)(v / ((size_t)NX * g.ny));
+            hot[v] = hh[(size_t)i + (size_t)g.sx * ((size_t)j + (size_t)g.ny * k)];
+        }
+    }
+    return HK_OK;
+}
 
 int hk_set_cnn(hk_sim *S, hk_cnn *cnn) {
     if (!S) return HK_EINVAL;

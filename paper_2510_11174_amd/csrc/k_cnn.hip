@@ -372,6 +372,34 @@ k_cnn_inputs(GridP g, const real *__restrict__ Ex, const real *__restrict__ Ey, 
     for (int q = 0; q < 8; ++q) x[v * 8 + q] = bf16_bits((f[q] - nm.mean[q]) * nm.inv_std[q]);
 }
 
+// Raw node inputs (8 channels) and the conversion energy per node of the
+// canonical node grid [nz][ny][NX]: e = (sum w |u|^2 - |sum w u|^2 / sum w) / 2,
+// the thermal energy (m_e c^2, small-u limit) a cold fluid would not carry.
+__global__ void __launch_bounds__(CBS)
+k_node_raw(GridP g, const real *__restrict__ Ex, const real *__restrict__ Ey, const real *__restrict__ Ez,
+           const real *__restrict__ Bx, const real *__restrict__ By, const real *__restrict__ Bz,
+           const real *__restrict__ mom, float *__restrict__ out) {
+    const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
+    const long long n = (long long)NX * g.ny * g.nz;
+    const long long v = (long long)blockIdx.x * CBS + threadIdx.x;
+    if (v >= n) return;
+    const int i = (int)(v % NX), j = (int)((v / NX) % g.ny), k = (int)(v / ((long long)NX * g.ny));
+    const long long c = gidx(g, i, j, k);
+    const double dv = (double)g.dx * g.dy * g.dz;
+    float *o = out + 9 * v;
+    o[0] = node_field(g, Ex, i, j, k, 1, 0, 0);
+    o[1] = node_field(g, Ey, i, j, k, 0, 1, 0);
+    o[2] = node_field(g, Ez, i, j, k, 0, 0, 1);
+    o[3] = node_field(g, Bx, i, j, k, 0, 1, 1);
+    o[4] = node_field(g, By, i, j, k, 1, 0, 1);
+    o[5] = node_field(g, Bz, i, j, k, 1, 1, 0);
+    const double N = mom[c], U2 = mom[5 * g.nn + c];
+    const double px = mom[2 * g.nn + c], py = mom[3 * g.nn + c], pz = mom[4 * g.nn + c];
+    o[6] = (float)(N / dv);
+    o[7] = N > 0.0 ? (float)sqrt(U2 / N) : 0.f;
+    o[8] = N > 0.0 ? (float)fmax(0.0, 0.5 * (U2 - (px * px + py * py + pz * pz) / N)) : 0.f;
+}
+
 // 16 dropout samples of the head per node: mean p > 0.5 is kinetic unless the
 // samples' standard deviation exceeds 0.2 (then the threshold flags stay)
 __global__ void __launch_bounds__(CBS)
@@ -490,6 +518,12 @@ void cnn_launch_inputs(const GridP &g, real *const f[9], const real *mom, const 
     const long long n = (long long)(NX + 8) * (g.ny + 8) * (g.nz + 8);
     k_cnn_inputs<<<nblk(n), CBS, 0, s>>>(g, f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], mom,
                                          nm, x);
+}
+
+void cnn_launch_node_raw(const GridP &g, real *const f[9], const real *mom, float *out, hipStream_t s) {
+    const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
+    const long long n = (long long)NX * g.ny * g.nz;
+    k_node_raw<<<nblk(n), CBS, 0, s>>>(g, f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], mom, out);
 }
 
 void cnn_launch_decide(const GridP &g, const unsigned short *a4, const unsigned short *wh, const float *bh,

@@ -102,7 +102,7 @@ ABI_SYMBOLS = ["hk_create", "hk_destroy", "hk_step", "hk_switch_map", "hk_set_sw
                "hk_set_particles", "hk_get_fluid", "hk_set_fluid", "hk_enable_timing",
                "hk_timers", "hk_qed_tables", "hk_cnn_nparams", "hk_cnn_create", "hk_cnn_destroy",
                "hk_cnn_set_params", "hk_cnn_get_params", "hk_cnn_set_norm", "hk_cnn_forward",
-               "hk_cnn_loss_grad", "hk_cnn_train_step", "hk_cnn_last_error", "hk_set_cnn",
+               "hk_cnn_loss_grad", "hk_cnn_train_step", "hk_cnn_last_error", "hk_set_cnn", "hk_node_inputs",
                "hk_real_size", "hk_strerror", "hk_last_error"]
 
 _libs: dict = {}
@@ -151,6 +151,7 @@ def load(prec: str = "f32"):
     L.hk_cnn_last_error.restype = C.c_char_p
     L.hk_cnn_last_error.argtypes = [vp]
     L.hk_set_cnn.argtypes = [vp, vp]
+    L.hk_node_inputs.argtypes = [vp, vp, vp, vp, C.c_size_t]
     L.hk_real_size.restype = C.c_int
     L.hk_strerror.restype = C.c_char_p
     L.hk_strerror.argtypes = [C.c_int]
@@ -355,6 +356,15 @@ class Sim:
         out = np.empty(self.shape)
         self._check(self.lib.hk_get_divE(self.h, _ptr(out), out.size))
         return out
+
+    def node_inputs(self):
+        """(raw[n, 8], e[n], hot[n]) over the node grid [nz][ny][NX] (x fastest)."""
+        g = self.cfg["grid"]
+        nx = g["nx"] if g.get("bc_x", "open") == "periodic" else g["nx"] + 1
+        n = nx * self.ny * self.nz
+        raw = np.empty((n, 8)); e = np.empty(n); hot = np.empty(n, np.uint8)
+        self._check(self.lib.hk_node_inputs(self.h, _ptr(raw), _ptr(e), _ptr(hot), n))
+        return raw, e, hot
 
     def set_cnn(self, cnn):
         """Use `cnn` (a CNN, kept alive by this object) in switch mode "cnn"; None detaches."""

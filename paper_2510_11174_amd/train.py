@@ -1,0 +1,147 @@
+"""Training data and training loop of the learned switch, on the GPU.
+
+Paper: Methodology (the regime classifier is trained on data the simulations
+generate, with uncertainty from Monte Carlo dropout and a physics penalty on
+energy violation).  Everything numeric runs in the library: the simulation
+makes the data (hk_node_inputs), and the network is trained by its own BF16
+matrix-core forward and backward kernels and AdamW (hk_cnn_train_step).  This
+module only picks snapshots, labels and crops.
+
+Labels: a node is kinetic (y = 1) at step s when the physics criterion fires
+there at any step in s .. s + window of the all-PIC run: the network learns
+where the plasma is about to need particles, which the threshold switch,
+evaluated every `window` steps, cannot see.  Energy weight e: the thermal
+energy a cold-fluid conversion would destroy, over the crop's kinetic energy.
+"""
+from __future__ import annotations
+
+import copy
+
+import numpy as np
+
+HALO = 4
+CROP = 24
+
+
+def node_dims(cfg):
+    g = cfg["grid"]
+    nx = g["nx"] if g.get("bc_x", "open") == "periodic" else g["nx"] + 1
+    return g["nz"], g["ny"], nx
+
+
+def generate(hk, cfg, steps, every, start=0, window=10, precision="f32"):
+    """Run `cfg` all-PIC for steps + window steps; snapshots every `every`
+    steps from `start`.  Returns a list of (raw[nz, ny, NX, 8], y, e, hot_now)."""
+    c = copy.deepcopy(cfg)
+    c["run"]["switch_mode"] = "all_pic"
+    sim = hk.Sim(c, precision=precision)
+    dims = node_dims(c)
+    n = int(np.prod(dims))
+    hots, snaps = [], {}
+    for s in range(steps + window + 1):
+        raw, e, hot = sim.node_inputs()
+        hots.append(hot.reshape(dims))
+        if s >= start and (s - start) % every == 0 and s <= steps:
+            snaps[s] = (raw, e)
+        sim.step(1)
+    sim.close()
+    out = []
+    for s, (raw, e) in sorted(snaps.items()):
+        y = np.zeros(dims, np.float32)
+        for h in hots[s:s + window + 1]:
+            y = np.maximum(y, h.astype(np.float32))
+        out.append((raw.reshape(dims + (8,)), y, e.reshape(dims), hots[s].astype(np.float32)))
+    return out
+
+
+def init_params(seed=0):
+    """He-normal convolution weights, zero biases, small head (FP32 vector in the
+    library's parameter layout)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for cin in (8, 32, 32, 32):
+        parts.append(rng.normal(0, np.sqrt(2.0 / (27 * cin)), 27 * cin * 32))
+        parts.append(np.zeros(32))
+    parts.append(rng.normal(0, np.sqrt(1.0 / 32), 32))
+    parts.append(np.zeros(1))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def stats(data):
+    x = np.concatenate([d[0].reshape(-1, 8) for d in data])
+    mean = x.mean(0)
+    std = x.std(0)
+    std[std <= 0] = 1.0
+    return mean.astype(np.float32), std.astype(np.float32)
+
+
+def pad(a, periodic_x):
+    """4-node halo: wrap in y and z (and periodic x), repeat the wall node in open x."""
+    a = np.pad(a, [(HALO, HALO), (HALO, HALO), (0, 0)] + [(0, 0)] * (a.ndim - 3), mode="wrap")
+    mode = "wrap" if periodic_x else "edge"
+    return np.pad(a, [(0, 0), (0, 0), (HALO, HALO)] + [(0, 0)] * (a.ndim - 3), mode=mode)
+
+
+def crops(data, mean, std, B, rng, periodic_x=False, dv=1.0):
+    """B random crops: x [B, 24, 24, 24, 8] normalized, y and e [B, 16, 16, 16]."""
+    xs, ys, es = [], [], []
+    for _ in range(B):
+        raw, y, e = data[rng.integers(len(data))][:3]
+        P = pad(raw, periodic_x)
+        D, H, W = y.shape
+        z0 = rng.integers(0, max(1, D - 16 + 1)); y0 = rng.integers(0, max(1, H - 16 + 1))
+        x0 = rng.integers(0, max(1, W - 16 + 1))
+        xc = P[z0:z0 + CROP, y0:y0 + CROP, x0:x0 + CROP]
+        yc = np.pad(y, [(0, 16), (0, 16), (0, 16)])[z0:z0 + 16, y0:y0 + 16, x0:x0 + 16]
+        ec = np.pad(e, [(0, 16), (0, 16), (0, 16)])[z0:z0 + 16, y0:y0 + 16, x0:x0 + 16]
+        if xc.shape[:3] != (CROP, CROP, CROP):
+            xc = np.pad(xc, [(0, CROP - xc.shape[0]), (0, CROP - xc.shape[1]), (0, CROP - xc.shape[2]), (0, 0)],
+                        mode="edge")
+        # kinetic energy of the crop from the inputs: (1/2) n dV |p|_rms^2 per node
+        ke = 0.5 * (raw[..., 6] * dv * raw[..., 7] ** 2).sum() + 1e-30
+        xs.append((xc - mean) / std); ys.append(yc); es.append(ec / ke * yc.size)
+    return (np.stack(xs).astype(np.float32), np.stack(ys).astype(np.float32),
+            np.stack(es).astype(np.float32))
+
+
+def train(cnn, data, mean, std, iters, B=8, lr=1e-3, lam=0.1, seed=0, periodic_x=False, dv=1.0, log=None):
+    import torch
+    rng = np.random.default_rng(seed)
+    cnn.set_norm(mean, std)
+    losses = []
+    for it in range(iters):
+        x, y, e = crops(data, mean, std, B, rng, periodic_x, dv)
+        xd, yd, ed = (torch.tensor(a, device="cuda") for a in (x, y, e))
+        losses.append(cnn.train_step(xd, yd, ed, lr=lr, lam=lam, dropout=True))
+        if log and (it % 50 == 0 or it == iters - 1):
+            log("iter %d loss %.4f" % (it, losses[-1]))
+    return losses
+
+
+def predict(cnn, raw, mean, std, periodic_x=False):
+    """p over the node grid of one snapshot (no dropout)."""
+    import torch
+    x = (pad(raw, periodic_x) - mean) / std
+    xd = torch.tensor(x[None].astype(np.float32), device="cuda")
+    return torch.sigmoid(cnn.forward(xd))[0].cpu().numpy()
+
+
+def auc(score, label):
+    """Area under the ROC curve (ties count half)."""
+    s = np.asarray(score, float).ravel(); y = np.asarray(label).ravel() > 0.5
+    npos, nneg = y.sum(), (~y).sum()
+    if npos == 0 or nneg == 0:
+        return float("nan")
+    order = np.argsort(s, kind="mergesort")
+    ranks = np.empty(len(s)); ranks[order] = np.arange(1, len(s) + 1)
+    # average ranks over ties
+    ss = s[order]
+    i = 0
+    while i < len(ss):
+        j = i
+        while j + 1 < len(ss) and ss[j + 1] == ss[i]:
+            j += 1
+        if j > i:
+            ranks[order[i:j + 1]] = 0.5 * (i + j) + 1
+        i = j + 1
+    return float((ranks[y].sum() - npos * (npos + 1) / 2) / (npos * nneg))
