@@ -45,7 +45,7 @@ struct DevSpecies {
     int max_cap = 0;
     PArr mig{};                // per-tile mover regions
     long long *moff = nullptr;
-    int *mcap = nullptr, *mcnt = nullptr;
+    int *mcap = nullptr;
     int *active = nullptr;     // immobile ionizable ions: ions below z_max per tile
     PArr inbox{}, fail{};
     int inbox_cap = 0;
@@ -106,6 +106,8 @@ struct hk_sim {
     hipEvent_t last_mark = nullptr;
     unsigned long long *dstat = nullptr;   // [0] particles pushed, [1] tiles pushed
     unsigned *wmax = nullptr;       // per species: bound on |w| (FP32 bits), never lowered
+    int2 *plan = nullptr;           // push work items (tile, chunk), rebuilt before every push
+    int *plan_ctl = nullptr;        // [0] items, [1] ticket
     unsigned long long stat0[2]{};  // device counters when timing was enabled
     double fallback_fraction = 0;
 };
@@ -270,11 +272,11 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     long long *dmoff = (long long *)dalloc(S, sizeof(long long) * nt);
     int *dcap = (int *)dalloc(S, sizeof(int) * nt);
     int *dmcap = (int *)dalloc(S, sizeof(int) * nt);
-    int *dmcnt = (int *)dalloc(S, sizeof(int) * nt);
-    int *dfill = (int *)dalloc(S, sizeof(int) * nt);
-    int *f1 = (int *)dalloc(S, sizeof(int) * nt), *b0 = (int *)dalloc(S, sizeof(int) * nt),
-        *b1 = (int *)dalloc(S, sizeof(int) * nt);
-    if (!doff || !dmoff || !dcap || !dmcap || !dmcnt || !dfill || !f1 || !b0 || !b1)
+    // per buffer one block of 3 nt counters: front fills, back fills, mover
+    // ranks (cleared together before a push into that buffer)
+    int *dfill = (int *)dalloc(S, sizeof(int) * 3 * nt);
+    int *f1 = (int *)dalloc(S, sizeof(int) * 3 * nt);
+    if (!doff || !dmoff || !dcap || !dmcap || !dfill || !f1)
         return fail(S, HK_ENOMEM, "rebuild: tables");
     HIPCHK(S, hipMemcpyAsync(doff, off.data(), sizeof(long long) * nt, hipMemcpyHostToDevice, S->s));
     HIPCHK(S, hipMemcpyAsync(dmoff, moff.data(), sizeof(long long) * nt, hipMemcpyHostToDevice, S->s));
@@ -290,7 +292,7 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     free_parr(S, D.buf[0]);
     free_parr(S, D.buf[1]);
     free_parr(S, D.mig);
-    int *olds[] = {D.nf[0], D.nf[1], D.nb[0], D.nb[1], D.cap, D.mcap, D.mcnt};
+    int *olds[] = {D.nf[0], D.nf[1], D.cap, D.mcap};
     for (int *q : olds) dfree(S, q);
     dfree(S, D.off); dfree(S, D.moff);
     dfree(S, newcnt);
@@ -302,11 +304,10 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     D.cap = dcap;
     D.moff = dmoff;
     D.mcap = dmcap;
-    D.mcnt = dmcnt;
     D.nf[0] = dfill;   // the scatter fill counts are the new front counts
     D.nf[1] = f1;
-    D.nb[0] = b0;
-    D.nb[1] = b1;
+    D.nb[0] = dfill + nt;
+    D.nb[1] = f1 + nt;
     D.capacity = total;
     D.max_cap = maxc;
     D.h_off = off;
@@ -750,17 +751,21 @@ int one_step(hk_sim *S) {
         if (mode < 0) continue;
         if (D.d.mobile) {
             int nxt = 1 - D.cur;
-            launch_zero(D.nb[nxt], sizeof(int) * g.ntiles, s);
+            // front and back fills of the next buffer and the mover ranks start
+            // at zero: several push workgroups share a dense tile
+            int *mcnt = D.nf[nxt] + 2 * g.ntiles;
+            launch_zero(D.nf[nxt], sizeof(int) * 3 * g.ntiles, s);
             QedP Q = qed_params(S, mode);
             hipEvent_t pa = S->timing ? ev_get(S) : nullptr;
             launch_push_tiles(g, P, D.buf[D.cur], cur_bins(D), D.buf[nxt], D.nf[nxt], D.mig, D.moff,
-                              D.mcap, D.mcnt, D.inbox, S->status + 1 + 2 * isp, D.inbox_cap, S->f,
-                              S->status, S->dstat, S->wmax + isp, D.umax2, mode, Q, s);
+                              D.mcap, mcnt, D.inbox, S->status + 1 + 2 * isp, D.inbox_cap, S->f,
+                              S->status, S->dstat, S->wmax + isp, D.umax2, mode, Q, S->plan,
+                              S->plan_ctl, D.capacity, s);
             if (S->timing) {
                 S->spans.push_back({pa, ev_get(S), 6});
                 S->timers[8] += 1;
             }
-            launch_migrate(g, P, D.mig, D.moff, D.mcnt, D.buf[nxt], D.nf[nxt], D.nb[nxt],
+            launch_migrate(g, P, D.mig, D.moff, mcnt, D.mcap, D.buf[nxt], D.nf[nxt], D.nb[nxt],
                            S->status + 2 + 2 * isp, D.fail, D.inbox_cap, S->status, s);
         } else if (D.d.ionizable && S->run.enable_ionization) {
             DevSpecies &T = S->sp[D.d.target];
@@ -986,13 +991,15 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
     // species weight bounds, plus one spare slot that QED kernels may raise
     // when a sink species does not exist
     S->wmax = (unsigned *)dalloc(S, sizeof(unsigned) * (HK_MAX_SPECIES + 1));
+    S->plan = (int2 *)dalloc(S, sizeof(int2) * (size_t)push_plan_items(g));
+    S->plan_ctl = (int *)dalloc(S, sizeof(int) * 2);
     if (hipHostMalloc((void **)&S->h_status, sizeof(int) * 16, 0) != hipSuccess)
         S->h_status = nullptr;
     if (hipEventCreateWithFlags(&S->status_ev, hipEventDisableTiming) != hipSuccess)
         S->status_ev = nullptr;
     if (!S->fblock || !S->mur_old || !S->sw || !S->calm || !S->gauss0 || !S->tmp_a || !S->tmp_b ||
         !S->dsum || !S->ledger || !S->status || !S->h_status || !S->dstat || !S->wmax ||
-        !S->status_ev) {
+        !S->plan || !S->plan_ctl || !S->status_ev) {
         hk_destroy(S);
         return HK_ENOMEM;
     }

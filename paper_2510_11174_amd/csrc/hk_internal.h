@@ -224,13 +224,16 @@ void launch_merge_inbox(const GridP &g, const SpecP &sp, PArr inbox, const int *
                         long long max_n, PArr dst, const int *nf, int *nb, int *fail_n, PArr fail,
                         int *err, hipStream_t s);
 void launch_migrate(const GridP &g, const SpecP &sp, PArr mig, const long long *moff,
-                    const int *mcnt, PArr dst, const int *nf, int *nb, int *fail_n, PArr fail,
-                    int fail_cap, int *err, hipStream_t s);
+                    const int *mcnt, const int *mcap, PArr dst, const int *nf, int *nb, int *fail_n,
+                    PArr fail, int fail_cap, int *err, hipStream_t s);
 void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
                        int *nf_out, PArr mig, const long long *moff, const int *mcap, int *mcnt,
                        PArr inbox, int *inbox_n, int inbox_cap, real *const f[9], int *err,
                        unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
-                       int mode, const QedP &Q, hipStream_t s);
+                       int mode, const QedP &Q, int2 *items, int *ctl, long long capacity,
+                       hipStream_t s);
+// Size of the push work plan (items) for grid g; ctl holds 2 ints.
+long long push_plan_items(const GridP &g);
 void launch_ionize_static(const GridP &g, const SpecP &sp, PArr a, Bins b, int *active,
                           real *const f[9], const uint8_t *sw, int hybrid, const IonP *ion,
                           PArr eout, int *eout_n, int eout_cap, uint64_t seed, int step,

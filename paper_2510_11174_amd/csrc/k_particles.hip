@@ -175,14 +175,17 @@ k_merge(GridP g, SpecP sp, PArr inbox, const int *__restrict__ inbox_n, int inbo
 // destination bins in the next buffer.
 __global__ void __launch_bounds__(BS)
 k_migrate(GridP g, SpecP sp, PArr mig, const long long *__restrict__ moff,
-          const int *__restrict__ mcnt, PArr dst, const int *__restrict__ nf, int *__restrict__ nb,
-          int *__restrict__ fail_n, PArr fail, int fail_cap, int *__restrict__ err) {
+          const int *__restrict__ mcnt, const int *__restrict__ mcap, PArr dst, const int *__restrict__ nf,
+          int *__restrict__ nb, int *__restrict__ fail_n, PArr fail, int fail_cap, int *__restrict__ err) {
     const int t = blockIdx.x;
-    const int n = mcnt[t];
+    // movers beyond the region went to the inbox; blocks along y share the rest
+    const int n = min(mcnt[t], mcap[t]);
+    const int per = ((n + gridDim.y - 1) / gridDim.y + BS - 1) / BS * BS;
+    const int beg = blockIdx.y * per, end = min(n, beg + per);
     const long long b0 = moff[t];
-    for (int p0 = 0; p0 < n; p0 += BS) {
+    for (int p0 = beg; p0 < end; p0 += BS) {
         const int p = p0 + threadIdx.x;
-        const int cell = p < n ? mig.cell[b0 + p] : -1;
+        const int cell = p < end ? mig.cell[b0 + p] : -1;
         const bool ok = cell >= 0;
         const int d = ok ? tile_of(g, cell) : 0;
         const int slot = wave_reserve(nb, d, ok);
@@ -199,6 +202,79 @@ k_migrate(GridP g, SpecP sp, PArr mig, const long long *__restrict__ moff,
 
 // ------------------------------------------------------------- the push -----------------
 constexpr int PBS = 512;   // push workgroup: 8 waves share one tile
+constexpr int PUSH_SPLIT = 16;      // most workgroups per tile
+constexpr int PUSH_CHUNK = 16 * PBS; // tiles up to this many particles take one workgroup
+
+// ------------------------------------------------------------ push work plan ----------
+// A tile with n particles forms ceil(n / chunk) work items of `chunk`
+// consecutive bin slots (the last one shorter).  Workgroups take the items in
+// order from a global ticket, and the plan lists them by decreasing chunk size:
+// the dense tiles start first and every compute unit, whichever XCD it sits
+// on, pulls the next item when it frees a slot.  (Launch order alone sends
+// block i to XCD i mod 8, and a dense sheet of tiles at one x index then lands
+// on a single XCD.)
+__device__ inline int push_chunk(int n) {
+    return max(PUSH_CHUNK, ((n + PUSH_SPLIT - 1) / PUSH_SPLIT + PBS - 1) / PBS * PBS);
+}
+constexpr int PLAN_BS = 1024;
+
+__global__ void __launch_bounds__(PLAN_BS)
+k_push_plan(int ntiles, SpecP sp, Bins bins, int2 *__restrict__ items, int *__restrict__ ctl) {
+    __shared__ int cnt[32], cur[32];
+    if (threadIdx.x < 32) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < ntiles; t += PLAN_BS) {
+        int nfi, nbi;
+        const int n = bin_count(sp, bins, t, nfi, nbi);
+        if (n > 0) {
+            const int c = push_chunk(n);
+            atomicAdd(&cnt[31 - __clz(min(n, c))], (n + c - 1) / c);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int total = 0;
+        for (int b = 31; b >= 0; --b) { cur[b] = total; total += cnt[b]; }
+        ctl[0] = total;   // items
+        ctl[1] = 0;       // ticket
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ntiles; t += PLAN_BS) {
+        int nfi, nbi;
+        const int n = bin_count(sp, bins, t, nfi, nbi);
+        if (n > 0) {
+            const int c = push_chunk(n), k = (n + c - 1) / c;
+            const int at = atomicAdd(&cur[31 - __clz(min(n, c))], k);
+            for (int j = 0; j < k; ++j) items[at + j] = make_int2(t, j);
+        }
+    }
+}
+
+// One particle's state as the push reads it.  Every field is loaded at once
+// (no load waits on another) and one loop iteration ahead of its use.
+struct PLoad {
+    int cell;
+    real rx, ry, rz, ux, uy, uz, w;
+    uint64_t id;
+    int zc;
+    double tau;
+};
+__device__ inline PLoad pload(const PArr &in, const SpecP &sp, long long ip, bool ok) {
+    PLoad L;
+    L.cell = -1;
+    L.rx = L.ry = L.rz = L.ux = L.uy = L.uz = L.w = 0;
+    L.id = 0; L.zc = 0; L.tau = 0.0;
+    if (ok) {
+        L.cell = in.cell[ip];
+        L.rx = in.rx[ip]; L.ry = in.ry[ip]; L.rz = in.rz[ip];
+        L.ux = in.ux[ip]; L.uy = in.uy[ip]; L.uz = in.uz[ip];
+        L.w = in.w[ip];
+        L.id = in.id[ip];
+        if (sp.has_z) L.zc = in.zc[ip];
+        if (sp.has_tau) L.tau = in.tau[ip];
+    }
+    return L;
+}
 
 // MODE 0: charged particles; MODE 1: QED leptons (photon emission from the
 // fields at x^n and u^{n-1/2}, before the Boris push); MODE 2: photons
@@ -212,18 +288,27 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
        const real *__restrict__ By, const real *__restrict__ Bz, real *__restrict__ Jx,
        real *__restrict__ Jy, real *__restrict__ Jz, int *__restrict__ err,
        unsigned long long *__restrict__ stats, const unsigned *__restrict__ wmax_bits,
-       unsigned *__restrict__ umax2, QedP Q) {
+       unsigned *__restrict__ umax2, const int2 *__restrict__ items, int *__restrict__ ctl, QedP Q) {
     __shared__ real sF[6 * FT3];
     __shared__ jacc_t sJ[3 * JT3];
-    __shared__ int s_stay, s_move;
+    __shared__ int s_stay, s_move, s_t, s_j;
     __shared__ unsigned s_u2;
-    const int t = blockIdx.x;
+    if (threadIdx.x == 0) {
+        const int k = atomicAdd(&ctl[1], 1);
+        const int2 it = k < ctl[0] ? items[k] : make_int2(-1, 0);
+        s_t = it.x; s_j = it.y;
+    }
+    __syncthreads();
+    const int t = s_t, item = s_j;
+    if (t < 0) return;
     int nfi, nbi;
     const int n = bin_count(sp, bin_in, t, nfi, nbi);
-    if (n <= 0) {
-        if (threadIdx.x == 0) { nf_out[t] = 0; mcnt[t] = 0; }
-        return;
-    }
+    // a dense tile's items go to several workgroups: they take the stayer and
+    // mover ranks from the tile's global counters, a tile of one item from LDS
+    const int chunk = push_chunk(n);
+    const int pbeg = item * chunk, pend = min(n, pbeg + chunk);
+    if (pbeg >= pend) return;
+    const bool shared = n > chunk;
     const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
     const int per = g.bcx == HK_BC_PERIODIC;
@@ -254,6 +339,7 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
     const real dv = g.dx * g.dy * g.dz;
     const real hq = (real)0.5 * sp.qm * g.dt;
     float u2max = 0.f;   // largest |u|^2 pushed by this thread
+    int pushed = 0;      // particles this wave ranked (shared tiles)
     double led = 0.0;    // photon ledger contributions of this thread
     const int lane = __lane_id();
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -269,21 +355,23 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
                         (double)fmaxf(fmaxf((float)cdx, (float)cdy), (float)cdz);
     const double jscale = jmax > 0.0 ? jmax / (double)JFIX_UNITS : 1.0;
     const real inv_scale = (real)(1.0 / jscale);
-    for (int p0 = 0; p0 < n; p0 += PBS) {
-        const int p = p0 + threadIdx.x;
-        long long ip = 0;
-        int cell = -1;
-        if (p < n) {
-            ip = bin_slot(sp, t, p, nfi, nbi);
-            cell = in.cell[ip];
+    PLoad nx_ = pload(in, sp, bin_slot(sp, t, min(pbeg + (int)threadIdx.x, pend - 1), nfi, nbi),
+                      pbeg + (int)threadIdx.x < pend);
+    for (int p0 = pbeg; p0 < pend; p0 += PBS) {
+        const PLoad cur = nx_;
+        if (p0 + PBS < pend) {
+            const int pn = p0 + PBS + threadIdx.x;
+            nx_ = pload(in, sp, bin_slot(sp, t, min(pn, pend - 1), nfi, nbi), pn < pend);
         }
+        const int cell = cur.cell;
         bool valid = cell >= 0;
         int ncell = -1, ntile = -1;
-        real rx = 0, ry = 0, rz = 0;
-        real nrx = 0, nry = 0, nrz = 0, ux = 0, uy = 0, uz = 0, w = 0;
-        uint64_t id = 0;
-        int zc = 0;
-        double tau = 0;
+        const real rx = cur.rx, ry = cur.ry, rz = cur.rz;
+        real nrx = 0, nry = 0, nrz = 0, ux = cur.ux, uy = cur.uy, uz = cur.uz;
+        const real w = cur.w;
+        const uint64_t id = cur.id;
+        const int zc = cur.zc;
+        double tau = cur.tau;
         // QED event products: a photon (MODE 1) or a pair (MODE 2)
         bool want1 = false, want2 = false;
         double kx = 0, ky = 0, kz = 0, m1 = 0, m2 = 0;
@@ -297,12 +385,6 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
             }
         }
         if (valid) {
-            rx = in.rx[ip]; ry = in.ry[ip]; rz = in.rz[ip];
-            ux = in.ux[ip]; uy = in.uy[ip]; uz = in.uz[ip];
-            w = in.w[ip];
-            id = in.id[ip];
-            if (sp.has_z) zc = in.zc[ip];
-            if (sp.has_tau) tau = in.tau[ip];
             // gather E^n, B^n (CIC on the Yee stagger)
             AxisW X = axis_weights(lx, rx), Y = axis_weights(ly, ry), Z = axis_weights(lz, rz);
             real ex = tri(sF + 0 * FT3, X.ih, Y.in_, Z.in_, X.fh, Y.fn, Z.fn);
@@ -429,14 +511,16 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
                 ntile = (ni >> TLOG) + g.ntx * ((nj >> TLOG) + g.nty * (nk >> TLOG));
             }
         }
-        // ranks from LDS counters: one LDS atomic per wave for each class
+        // ranks from the tile's counters (zeroed before the launch): one atomic
+        // per wave and class, shared by the workgroups of the tile
         const bool stay = valid && ntile == t;
         const bool move = valid && ntile != t;
         const uint64_t ms = __ballot(stay), mm = __ballot(move);
         int bs = 0, bm = 0;
         if (lane == 0) {
-            if (ms) bs = atomicAdd(&s_stay, __popcll(ms));
-            if (mm) bm = atomicAdd(&s_move, __popcll(mm));
+            if (ms) bs = atomicAdd(shared ? &nf_out[t] : &s_stay, __popcll(ms));
+            if (mm) bm = atomicAdd(shared ? &mcnt[t] : &s_move, __popcll(mm));
+            if (shared) pushed += __popcll(ms) + __popcll(mm);
         }
         bs = __shfl(bs, 0);
         bm = __shfl(bm, 0);
@@ -508,13 +592,16 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
     // order like unsigned integers); read by the next switch evaluation
     for (int o = 32; o > 0; o >>= 1) u2max = fmaxf(u2max, __shfl_xor(u2max, o));
     if (lane == 0 && u2max > 0.f) atomicMax(&s_u2, __float_as_uint(u2max));
+    if (shared && lane == 0 && pushed) atomicAdd(&s_stay, pushed);
     __syncthreads();
     if (threadIdx.x == 0) {
         if (s_u2) atomicMax(&umax2[t], s_u2);
-        nf_out[t] = s_stay;          // stayers never exceed the bin: they were in it
-        mcnt[t] = min(s_move, mlim);
+        if (!shared) {
+            nf_out[t] = s_stay;   // stayers never exceed the bin: they were in it
+            mcnt[t] = s_move;     // the migration reads at most the region's capacity
+        }
         atomicAdd(&stats[0], (unsigned long long)(s_stay + s_move));   // particles pushed
-        atomicAdd(&stats[1], 1ull);                                    // tiles with particles
+        if (item == 0) atomicAdd(&stats[1], 1ull);                     // tiles with particles
     }
     if (MODE == 2) return;
     // flush the LDS current tile (nodes ox-1 .. ox+TILE+1) to HBM
@@ -758,22 +845,32 @@ void launch_merge_inbox(const GridP &g, const SpecP &sp, PArr inbox, const int *
 }
 
 void launch_migrate(const GridP &g, const SpecP &sp, PArr mig, const long long *moff,
-                    const int *mcnt, PArr dst, const int *nf, int *nb, int *fail_n, PArr fail,
-                    int fail_cap, int *err, hipStream_t s) {
-    k_migrate<<<g.ntiles, BS, 0, s>>>(g, sp, mig, moff, mcnt, dst, nf, nb, fail_n, fail, fail_cap, err);
+                    const int *mcnt, const int *mcap, PArr dst, const int *nf, int *nb, int *fail_n,
+                    PArr fail, int fail_cap, int *err, hipStream_t s) {
+    k_migrate<<<dim3(g.ntiles, 4), BS, 0, s>>>(g, sp, mig, moff, mcnt, mcap, dst, nf, nb, fail_n, fail,
+                                                 fail_cap, err);
 }
+
+long long push_plan_items(const GridP &g) { return (long long)g.ntiles * PUSH_SPLIT; }
 
 void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
                        int *nf_out, PArr mig, const long long *moff, const int *mcap, int *mcnt,
                        PArr inbox, int *inbox_n, int inbox_cap, real *const f[9], int *err,
                        unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
-                       int mode, const QedP &Q, hipStream_t s) {
+                       int mode, const QedP &Q, int2 *items, int *ctl, long long capacity,
+                       hipStream_t s) {
 #define HK_PUSH_ARGS g, sp, in, bin_in, out, nf_out, mig, moff, mcap, mcnt, inbox, inbox_n, inbox_cap, \
         f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], f[HK_JX], f[HK_JY], f[HK_JZ], err, \
-        stats, wmax_bits, umax2, Q
-    if (mode == 1) k_push<1><<<g.ntiles, PBS, 0, s>>>(HK_PUSH_ARGS);
-    else if (mode == 2) k_push<2><<<g.ntiles, PBS, 0, s>>>(HK_PUSH_ARGS);
-    else k_push<0><<<g.ntiles, PBS, 0, s>>>(HK_PUSH_ARGS);
+        stats, wmax_bits, umax2, items, ctl, Q
+    // items: at most PUSH_SPLIT per tile, and at most one per tile plus one per
+    // PUSH_CHUNK particles; surplus workgroups find the ticket past the end
+    k_push_plan<<<1, PLAN_BS, 0, s>>>(g.ntiles, sp, bin_in, items, ctl);
+    const long long nmax = std::min<long long>((long long)g.ntiles * PUSH_SPLIT,
+                                               g.ntiles + capacity / PUSH_CHUNK + 1);
+    const unsigned grid = (unsigned)nmax;
+    if (mode == 1) k_push<1><<<grid, PBS, 0, s>>>(HK_PUSH_ARGS);
+    else if (mode == 2) k_push<2><<<grid, PBS, 0, s>>>(HK_PUSH_ARGS);
+    else k_push<0><<<grid, PBS, 0, s>>>(HK_PUSH_ARGS);
 #undef HK_PUSH_ARGS
 }
 
