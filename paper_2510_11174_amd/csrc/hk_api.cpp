@@ -107,7 +107,7 @@ struct hk_sim {
     unsigned long long *dstat = nullptr;   // [0] particles pushed, [1] tiles pushed
     unsigned *wmax = nullptr;       // per species: bound on |w| (FP32 bits), never lowered
     int2 *plan = nullptr;           // push work items (tile, chunk), rebuilt before every push
-    int *plan_ctl = nullptr;        // [0] items, [1] ticket
+    int *plan_ctl = nullptr;        // [0] items, [1..3] tickets (push, migration, moments)
     unsigned long long stat0[2]{};  // device counters when timing was enabled
     double fallback_fraction = 0;
 };
@@ -639,10 +639,12 @@ int switch_moments(hk_sim *S, bool use_bounds, const IonP **ions) {
         SpecP P = specp(D);
         if (D.d.fluid && D.capacity)
             launch_moments_tiles(g, P, D.buf[D.cur], cur_bins(D), 0, 0, S->mom, S->wmax + isp,
-                                 use_bounds && D.d.mobile && D.umax_ok ? D.umax2 : nullptr, nullptr, s);
+                                 use_bounds && D.d.mobile && D.umax_ok ? D.umax2 : nullptr, nullptr,
+                                 S->plan, S->plan_ctl, D.capacity, s);
         if (D.d.ionizable && S->run.enable_ionization && D.capacity) {
             launch_moments_tiles(g, P, D.buf[D.cur], cur_bins(D), 1, D.d.z_max, S->mom, S->wmax + isp,
-                                 nullptr, D.d.mobile ? nullptr : D.active, s);
+                                 nullptr, D.d.mobile ? nullptr : D.active, S->plan, S->plan_ctl,
+                                 D.capacity, s);
             if (nion < 4) ions[nion++] = D.ion;
         }
     }
@@ -766,7 +768,7 @@ int one_step(hk_sim *S) {
                 S->timers[8] += 1;
             }
             launch_migrate(g, P, D.mig, D.moff, mcnt, D.mcap, D.buf[nxt], D.nf[nxt], D.nb[nxt],
-                           S->status + 2 + 2 * isp, D.fail, D.inbox_cap, S->status, s);
+                           S->status + 2 + 2 * isp, D.fail, D.inbox_cap, S->status, S->plan_ctl + 2, s);
         } else if (D.d.ionizable && S->run.enable_ionization) {
             DevSpecies &T = S->sp[D.d.target];
             launch_ionize_static(g, P, D.buf[D.cur], cur_bins(D), D.active, S->f, S->sw, hybrid,
@@ -991,8 +993,8 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
     // species weight bounds, plus one spare slot that QED kernels may raise
     // when a sink species does not exist
     S->wmax = (unsigned *)dalloc(S, sizeof(unsigned) * (HK_MAX_SPECIES + 1));
-    S->plan = (int2 *)dalloc(S, sizeof(int2) * (size_t)push_plan_items(g));
-    S->plan_ctl = (int *)dalloc(S, sizeof(int) * 2);
+    S->plan = (int2 *)dalloc(S, sizeof(int2) * (size_t)tile_plan_items(g));
+    S->plan_ctl = (int *)dalloc(S, sizeof(int) * 4);
     if (hipHostMalloc((void **)&S->h_status, sizeof(int) * 16, 0) != hipSuccess)
         S->h_status = nullptr;
     if (hipEventCreateWithFlags(&S->status_ev, hipEventDisableTiming) != hipSuccess)

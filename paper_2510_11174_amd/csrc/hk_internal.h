@@ -225,15 +225,22 @@ void launch_merge_inbox(const GridP &g, const SpecP &sp, PArr inbox, const int *
                         int *err, hipStream_t s);
 void launch_migrate(const GridP &g, const SpecP &sp, PArr mig, const long long *moff,
                     const int *mcnt, const int *mcap, PArr dst, const int *nf, int *nb, int *fail_n,
-                    PArr fail, int fail_cap, int *err, hipStream_t s);
+                    PArr fail, int fail_cap, int *err, int *ticket, hipStream_t s);
 void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
                        int *nf_out, PArr mig, const long long *moff, const int *mcap, int *mcnt,
                        PArr inbox, int *inbox_n, int inbox_cap, real *const f[9], int *err,
                        unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
                        int mode, const QedP &Q, int2 *items, int *ctl, long long capacity,
                        hipStream_t s);
-// Size of the push work plan (items) for grid g; ctl holds 2 ints.
-long long push_plan_items(const GridP &g);
+// Work plans of the per-tile particle kernels: items (tile, chunk) for grid g
+// (tile_plan_items entries) and ctl[4] (item count and three tickets: [1] the
+// push, [2] the migration, [3] the moments).  The plan lists the chunks of
+// at least cmin particles of bins b by decreasing size; tile_plan_grid is the
+// launch size that covers every item of a species of this capacity.
+long long tile_plan_items(const GridP &g);
+unsigned tile_plan_grid(const GridP &g, long long capacity, int cmin);
+void launch_tile_plan(const GridP &g, const SpecP &sp, Bins b, int cmin, int2 *items, int *ctl,
+                      hipStream_t s);
 void launch_ionize_static(const GridP &g, const SpecP &sp, PArr a, Bins b, int *active,
                           real *const f[9], const uint8_t *sw, int hybrid, const IonP *ion,
                           PArr eout, int *eout_n, int eout_cap, uint64_t seed, int step,
@@ -243,7 +250,7 @@ void launch_count_active(const GridP &g, const SpecP &sp, PArr a, Bins b, int zm
 void launch_rho_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, double *rho, hipStream_t s);
 void launch_moments_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, int ion_only,
                           int zmax, real *mom, const unsigned *wmax_bits, const unsigned *umax2,
-                          const int *active, hipStream_t s);
+                          const int *active, int2 *items, int *ctl, long long capacity, hipStream_t s);
 void launch_fluid_moments_nodes(const GridP &g, real inv_ppc, const real *n, const real *ux,
                                 const real *uy, const real *uz, real *mom, int first,
                                 hipStream_t s);

@@ -276,4 +276,22 @@ __device__ inline int wave_slot(int *ctr, bool want) {
     return want ? base + __popcll(m & ((1ull << lane) - 1ull)) : -1;
 }
 
+// Work items of the per-tile particle kernels.  A tile of n particles forms
+// ceil(n / c) items of c = tile_chunk(n, cmin) consecutive bin slots (the last
+// one shorter), at most TILE_SPLIT of them.  A planner lists the items by
+// decreasing size, and workgroups take them in order from a global ticket, so
+// dense tiles start first and every compute unit, whichever XCD it sits on,
+// pulls the next item when it frees a slot.  (Block i of a launch goes to XCD
+// i mod 8: a dense sheet of tiles at one x index would land on one XCD.)
+constexpr int TILE_SPLIT = 16;
+__device__ inline int tile_chunk(int n, int cmin) {
+    return max(cmin, ((n + TILE_SPLIT - 1) / TILE_SPLIT + 511) / 512 * 512);
+}
+// Thread 0 takes the workgroup's item from ticket ctl[ticket]; (-1, 0) when
+// the list (ctl[0] items) is exhausted.
+__device__ inline int2 take_item(const int2 *items, int *ctl, int ticket) {
+    const int k = atomicAdd(&ctl[ticket], 1);
+    return k < ctl[0] ? items[k] : make_int2(-1, 0);
+}
+
 }  // namespace hkdev

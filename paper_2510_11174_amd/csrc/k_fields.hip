@@ -17,6 +17,11 @@ __global__ void __launch_bounds__(BS) k_zero(uint32_t *p, size_t n) {
     size_t i = (size_t)blockIdx.x * BS + threadIdx.x;
     if (i < n) p[i] = 0u;
 }
+// 16-byte stores for 16-byte aligned buffers (n counts uint4)
+__global__ void __launch_bounds__(BS) k_zero16(uint4 *p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
 
 __device__ inline void decompose(const GridP &g, long long c, int &i, int &j, int &k) {
     i = (int)(c % g.sx);
@@ -165,6 +170,14 @@ inline unsigned blocks(long long n) { return (unsigned)((n + BS - 1) / BS); }
 void launch_zero(void *p, size_t bytes, hipStream_t s) {
     size_t n = bytes / 4;
     if (n == 0) return;
+    const size_t n16 = ((uintptr_t)p & 15) ? 0 : bytes / 16;
+    if (n16 >= 1024) {
+        const long long nb = std::min<long long>(blocks((long long)n16), 4096);
+        k_zero16<<<(unsigned)nb, BS, 0, s>>>((uint4 *)p, n16);
+        n -= 4 * n16;
+        if (n == 0) return;
+        p = (uint32_t *)p + 4 * n16;
+    }
     k_zero<<<blocks((long long)n), BS, 0, s>>>((uint32_t *)p, n);
 }
 

@@ -173,15 +173,23 @@ k_merge(GridP g, SpecP sp, PArr inbox, const int *__restrict__ inbox_n, int inbo
 
 // Movers of tile t (its region of the mover buffer) join the back of their
 // destination bins in the next buffer.
+constexpr int MIGRATE_PARTS = 4;
 __global__ void __launch_bounds__(BS)
 k_migrate(GridP g, SpecP sp, PArr mig, const long long *__restrict__ moff,
           const int *__restrict__ mcnt, const int *__restrict__ mcap, PArr dst, const int *__restrict__ nf,
-          int *__restrict__ nb, int *__restrict__ fail_n, PArr fail, int fail_cap, int *__restrict__ err) {
-    const int t = blockIdx.x;
-    // movers beyond the region went to the inbox; blocks along y share the rest
+          int *__restrict__ nb, int *__restrict__ fail_n, PArr fail, int fail_cap, int *__restrict__ err,
+          int *__restrict__ ticket) {
+    // tile t, part y of MIGRATE_PARTS from a global ticket: launch order would
+    // put the dense tiles of one x index on one XCD
+    __shared__ int s_k;
+    if (threadIdx.x == 0) s_k = atomicAdd(ticket, 1);
+    __syncthreads();
+    const int t = s_k % g.ntiles, y = s_k / g.ntiles;
+    if (y >= MIGRATE_PARTS) return;
+    // movers beyond the region went to the inbox; the parts share the rest
     const int n = min(mcnt[t], mcap[t]);
-    const int per = ((n + gridDim.y - 1) / gridDim.y + BS - 1) / BS * BS;
-    const int beg = blockIdx.y * per, end = min(n, beg + per);
+    const int per = ((n + MIGRATE_PARTS - 1) / MIGRATE_PARTS + BS - 1) / BS * BS;
+    const int beg = y * per, end = min(n, beg + per);
     const long long b0 = moff[t];
     for (int p0 = beg; p0 < end; p0 += BS) {
         const int p = p0 + threadIdx.x;
@@ -202,24 +210,15 @@ k_migrate(GridP g, SpecP sp, PArr mig, const long long *__restrict__ moff,
 
 // ------------------------------------------------------------- the push -----------------
 constexpr int PBS = 512;   // push workgroup: 8 waves share one tile
-constexpr int PUSH_SPLIT = 16;      // most workgroups per tile
 constexpr int PUSH_CHUNK = 16 * PBS; // tiles up to this many particles take one workgroup
 
-// ------------------------------------------------------------ push work plan ----------
-// A tile with n particles forms ceil(n / chunk) work items of `chunk`
-// consecutive bin slots (the last one shorter).  Workgroups take the items in
-// order from a global ticket, and the plan lists them by decreasing chunk size:
-// the dense tiles start first and every compute unit, whichever XCD it sits
-// on, pulls the next item when it frees a slot.  (Launch order alone sends
-// block i to XCD i mod 8, and a dense sheet of tiles at one x index then lands
-// on a single XCD.)
-__device__ inline int push_chunk(int n) {
-    return max(PUSH_CHUNK, ((n + PUSH_SPLIT - 1) / PUSH_SPLIT + PBS - 1) / PBS * PBS);
-}
+// ------------------------------------------------------ work plan of tile kernels -----
 constexpr int PLAN_BS = 1024;
 
+// ctl[0] = number of items, ctl[1..3] = tickets (zeroed here); items sorted
+// by decreasing chunk size through 32 power-of-two buckets.
 __global__ void __launch_bounds__(PLAN_BS)
-k_push_plan(int ntiles, SpecP sp, Bins bins, int2 *__restrict__ items, int *__restrict__ ctl) {
+k_tile_plan(int ntiles, SpecP sp, Bins bins, int cmin, int2 *__restrict__ items, int *__restrict__ ctl) {
     __shared__ int cnt[32], cur[32];
     if (threadIdx.x < 32) cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -227,7 +226,7 @@ k_push_plan(int ntiles, SpecP sp, Bins bins, int2 *__restrict__ items, int *__re
         int nfi, nbi;
         const int n = bin_count(sp, bins, t, nfi, nbi);
         if (n > 0) {
-            const int c = push_chunk(n);
+            const int c = tile_chunk(n, cmin);
             atomicAdd(&cnt[31 - __clz(min(n, c))], (n + c - 1) / c);
         }
     }
@@ -235,15 +234,15 @@ k_push_plan(int ntiles, SpecP sp, Bins bins, int2 *__restrict__ items, int *__re
     if (threadIdx.x == 0) {
         int total = 0;
         for (int b = 31; b >= 0; --b) { cur[b] = total; total += cnt[b]; }
-        ctl[0] = total;   // items
-        ctl[1] = 0;       // ticket
+        ctl[0] = total;
+        ctl[1] = 0; ctl[2] = 0; ctl[3] = 0;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < ntiles; t += PLAN_BS) {
         int nfi, nbi;
         const int n = bin_count(sp, bins, t, nfi, nbi);
         if (n > 0) {
-            const int c = push_chunk(n), k = (n + c - 1) / c;
+            const int c = tile_chunk(n, cmin), k = (n + c - 1) / c;
             const int at = atomicAdd(&cur[31 - __clz(min(n, c))], k);
             for (int j = 0; j < k; ++j) items[at + j] = make_int2(t, j);
         }
@@ -294,8 +293,7 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
     __shared__ int s_stay, s_move, s_t, s_j;
     __shared__ unsigned s_u2;
     if (threadIdx.x == 0) {
-        const int k = atomicAdd(&ctl[1], 1);
-        const int2 it = k < ctl[0] ? items[k] : make_int2(-1, 0);
+        const int2 it = take_item(items, ctl, 1);
         s_t = it.x; s_j = it.y;
     }
     __syncthreads();
@@ -305,7 +303,7 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
     const int n = bin_count(sp, bin_in, t, nfi, nbi);
     // a dense tile's items go to several workgroups: they take the stayer and
     // mover ranks from the tile's global counters, a tile of one item from LDS
-    const int chunk = push_chunk(n);
+    const int chunk = tile_chunk(n, PUSH_CHUNK);
     const int pbeg = item * chunk, pend = min(n, pbeg + chunk);
     if (pbeg >= pend) return;
     const bool shared = n > chunk;
@@ -846,12 +844,24 @@ void launch_merge_inbox(const GridP &g, const SpecP &sp, PArr inbox, const int *
 
 void launch_migrate(const GridP &g, const SpecP &sp, PArr mig, const long long *moff,
                     const int *mcnt, const int *mcap, PArr dst, const int *nf, int *nb, int *fail_n,
-                    PArr fail, int fail_cap, int *err, hipStream_t s) {
-    k_migrate<<<dim3(g.ntiles, 4), BS, 0, s>>>(g, sp, mig, moff, mcnt, mcap, dst, nf, nb, fail_n, fail,
-                                                 fail_cap, err);
+                    PArr fail, int fail_cap, int *err, int *ticket, hipStream_t s) {
+    k_migrate<<<g.ntiles * MIGRATE_PARTS, BS, 0, s>>>(g, sp, mig, moff, mcnt, mcap, dst, nf, nb, fail_n,
+                                                        fail, fail_cap, err, ticket);
 }
 
-long long push_plan_items(const GridP &g) { return (long long)g.ntiles * PUSH_SPLIT; }
+long long tile_plan_items(const GridP &g) { return (long long)g.ntiles * TILE_SPLIT; }
+
+// Items: at most TILE_SPLIT per tile, and at most one per tile plus one per
+// cmin particles (chunks are never shorter than cmin but the last); surplus
+// workgroups find the ticket past the end.
+unsigned tile_plan_grid(const GridP &g, long long capacity, int cmin) {
+    return (unsigned)std::min<long long>((long long)g.ntiles * TILE_SPLIT, g.ntiles + capacity / cmin + 1);
+}
+
+void launch_tile_plan(const GridP &g, const SpecP &sp, Bins b, int cmin, int2 *items, int *ctl,
+                      hipStream_t s) {
+    k_tile_plan<<<1, PLAN_BS, 0, s>>>(g.ntiles, sp, b, cmin, items, ctl);
+}
 
 void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
                        int *nf_out, PArr mig, const long long *moff, const int *mcap, int *mcnt,
@@ -862,12 +872,8 @@ void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PA
 #define HK_PUSH_ARGS g, sp, in, bin_in, out, nf_out, mig, moff, mcap, mcnt, inbox, inbox_n, inbox_cap, \
         f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], f[HK_JX], f[HK_JY], f[HK_JZ], err, \
         stats, wmax_bits, umax2, items, ctl, Q
-    // items: at most PUSH_SPLIT per tile, and at most one per tile plus one per
-    // PUSH_CHUNK particles; surplus workgroups find the ticket past the end
-    k_push_plan<<<1, PLAN_BS, 0, s>>>(g.ntiles, sp, bin_in, items, ctl);
-    const long long nmax = std::min<long long>((long long)g.ntiles * PUSH_SPLIT,
-                                               g.ntiles + capacity / PUSH_CHUNK + 1);
-    const unsigned grid = (unsigned)nmax;
+    k_tile_plan<<<1, PLAN_BS, 0, s>>>(g.ntiles, sp, bin_in, PUSH_CHUNK, items, ctl);
+    const unsigned grid = tile_plan_grid(g, capacity, PUSH_CHUNK);
     if (mode == 1) k_push<1><<<grid, PBS, 0, s>>>(HK_PUSH_ARGS);
     else if (mode == 2) k_push<2><<<grid, PBS, 0, s>>>(HK_PUSH_ARGS);
     else k_push<0><<<grid, PBS, 0, s>>>(HK_PUSH_ARGS);

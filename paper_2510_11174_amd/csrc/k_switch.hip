@@ -78,16 +78,28 @@ __device__ inline void madd(jacc_t *p, real v, real inv) {
 #endif
 }
 
+constexpr int MOM_CHUNK = 8192;   // particles per workgroup of the tile moments
+
 __global__ void __launch_bounds__(BS)
 k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__restrict__ mom,
           const unsigned *__restrict__ wmax_bits, const unsigned *__restrict__ umax2,
-          const int *__restrict__ active) {
+          const int *__restrict__ active, const int2 *__restrict__ items, int *__restrict__ ctl) {
     __shared__ jacc_t sm[6 * NT3];
     __shared__ unsigned s_u2;
-    const int t = blockIdx.x;
+    __shared__ int s_t, s_j;
+    if (threadIdx.x == 0) {
+        const int2 it = take_item(items, ctl, 3);
+        s_t = it.x; s_j = it.y;
+    }
+    __syncthreads();
+    const int t = s_t;
+    if (t < 0) return;
     int nf, nbv;
-    const int n = bin_count(sp, bins, t, nf, nbv);
-    if (n <= 0) return;
+    const int nt_ = bin_count(sp, bins, t, nf, nbv);
+    // this workgroup's chunk [p0, n) of the tile's bin slots
+    const int chunk = tile_chunk(nt_, MOM_CHUNK);
+    const int p0 = s_j * chunk, n = min(nt_, p0 + chunk);
+    if (p0 >= n) return;
     if (ion_only && active && active[t] <= 0) return;   // every ion of the tile at z_max
     const int nq = ion_only ? 1 : 6;
     for (int e = threadIdx.x; e < nq * NT3; e += BS) sm[e] = 0;
@@ -105,7 +117,7 @@ k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__
             }
         } else {
             float l = 0.f;
-            for (int p = threadIdx.x; p < n; p += BS) {
+            for (int p = p0 + threadIdx.x; p < n; p += BS) {
                 const long long ip = bin_slot(sp, t, p, nf, nbv);
                 if (a.cell[ip] < 0) continue;
                 const real ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip];
@@ -126,7 +138,7 @@ k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__
         scl[q] = (real)(bound[q] / (double)JFIX_UNITS);
     }
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
-    for (int p = threadIdx.x; p < n; p += BS) {
+    for (int p = p0 + threadIdx.x; p < n; p += BS) {
         const long long ip = bin_slot(sp, t, p, nf, nbv);
         int cell = a.cell[ip];
         if (cell < 0) continue;
@@ -527,8 +539,10 @@ inline unsigned blocks(long long n) { return (unsigned)((n + BS - 1) / BS); }
 
 void launch_moments_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, int ion_only,
                           int zmax, real *mom, const unsigned *wmax_bits, const unsigned *umax2,
-                          const int *active, hipStream_t s) {
-    k_moments<<<g.ntiles, BS, 0, s>>>(g, sp, a, b, ion_only, zmax, mom, wmax_bits, umax2, active);
+                          const int *active, int2 *items, int *ctl, long long capacity, hipStream_t s) {
+    launch_tile_plan(g, sp, b, MOM_CHUNK, items, ctl, s);
+    k_moments<<<tile_plan_grid(g, capacity, MOM_CHUNK), BS, 0, s>>>(g, sp, a, b, ion_only, zmax, mom,
+                                                                  wmax_bits, umax2, active, items, ctl);
 }
 void launch_fluid_moments_nodes(const GridP &g, real inv_ppc, const real *n, const real *ux,
                                 const real *uy, const real *uz, real *mom, int first, hipStream_t s) {
