@@ -178,8 +178,9 @@ typedef struct {
 
 typedef struct hk_sim hk_sim;
 
-/* Build the context: validates the descriptors (HK_EINVAL), allocates device
- * state, initialises species on the device and zeroes the fields. */
+/* Build the context: validates the descriptors (HK_EINVAL; among others the
+ * node count (nx+1)*ny*nz must stay below 2^31), allocates device state,
+ * initialises species on the device and zeroes the fields. */
 int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspecies,
               const hk_laser_desc *laser, const hk_run_desc *run, hk_sim **out);
 void hk_destroy(hk_sim *sim);

@@ -107,7 +107,7 @@ struct hk_sim {
     unsigned long long *dstat = nullptr;   // [0] particles pushed, [1] tiles pushed
     unsigned *wmax = nullptr;       // per species: bound on |w| (FP32 bits), never lowered
     int2 *plan = nullptr;           // push work items (tile, chunk), rebuilt before every push
-    int *plan_ctl = nullptr;        // [0] items, [1..3] tickets (push, migration, moments)
+    int *plan_ctl = nullptr;        // [0] items of the current plan
     unsigned long long stat0[2]{};  // device counters when timing was enabled
     double fallback_fraction = 0;
 };
@@ -133,7 +133,7 @@ int fail(hk_sim *S, int code, const char *fmt, ...) {
         if (e_ != hipSuccess) return fail(S, HK_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
     } while (0)
 
-void *dalloc(hk_sim *S, size_t bytes) {
+void *dalloc(hk_sim *S, size_t bytes, bool zero = true) {
     bytes = (bytes + 255) & ~(size_t)255;
     if (bytes == 0) bytes = 256;
     void *p = nullptr;
@@ -141,7 +141,7 @@ void *dalloc(hk_sim *S, size_t bytes) {
     else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
     if (p) {
         S->allocs.push_back(p);
-        launch_zero(p, bytes, S->s);
+        if (zero) launch_zero(p, bytes, S->s);
     }
     return p;
 }
@@ -154,27 +154,30 @@ void dfree(hk_sim *S, void *p) {
     else (void)hipFree(p);
 }
 
+// One allocation per particle array set, fields on 256-byte boundaries.  Slots
+// are written before they are read (bins count only filled slots); cells start
+// at -1, the mark of an empty slot, and nothing else is cleared.
 bool alloc_parr(hk_sim *S, PArr &a, long long n, int has_z, int has_tau) {
     a = PArr{};
     if (n <= 0) n = 1;
-    a.cell = (int *)dalloc(S, sizeof(int) * n);
-    a.rx = (real *)dalloc(S, sizeof(real) * n);
-    a.ry = (real *)dalloc(S, sizeof(real) * n);
-    a.rz = (real *)dalloc(S, sizeof(real) * n);
-    a.ux = (real *)dalloc(S, sizeof(real) * n);
-    a.uy = (real *)dalloc(S, sizeof(real) * n);
-    a.uz = (real *)dalloc(S, sizeof(real) * n);
-    a.w = (real *)dalloc(S, sizeof(real) * n);
-    a.id = (uint64_t *)dalloc(S, sizeof(uint64_t) * n);
-    if (has_z) a.zc = (int *)dalloc(S, sizeof(int) * n);
-    if (has_tau) a.tau = (double *)dalloc(S, sizeof(double) * n);
-    return a.cell && a.rx && a.ry && a.rz && a.ux && a.uy && a.uz && a.w && a.id &&
-           (!has_z || a.zc) && (!has_tau || a.tau);
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t s4 = al(4 * (size_t)n), s8 = al(8 * (size_t)n), sr = al(sizeof(real) * (size_t)n);
+    const size_t total = s4 + 7 * sr + s8 + (has_z ? s4 : 0) + (has_tau ? s8 : 0);
+    char *base = (char *)dalloc(S, total, false);
+    if (!base) return false;
+    size_t o = 0;
+    a.cell = (int *)(base + o); o += s4;
+    real **rs[] = {&a.rx, &a.ry, &a.rz, &a.ux, &a.uy, &a.uz, &a.w};
+    for (real **r : rs) { *r = (real *)(base + o); o += sr; }
+    a.id = (uint64_t *)(base + o); o += s8;
+    if (has_z) { a.zc = (int *)(base + o); o += s4; }
+    if (has_tau) { a.tau = (double *)(base + o); o += s8; }
+    launch_fill32(a.cell, (size_t)n, 0xFFFFFFFFu, S->s);
+    return true;
 }
 
 void free_parr(hk_sim *S, PArr &a) {
-    void *ps[] = {a.cell, a.rx, a.ry, a.rz, a.ux, a.uy, a.uz, a.w, a.id, a.zc, a.tau};
-    for (void *p : ps) dfree(S, p);
+    dfree(S, a.cell);   // the base of the set's one allocation
     a = PArr{};
 }
 
@@ -237,10 +240,10 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     std::vector<int> h(nt);
     HIPCHK(S, hipMemcpyAsync(h.data(), newcnt, sizeof(int) * nt, hipMemcpyDeviceToHost, S->s));
     HIPCHK(S, hipStreamSynchronize(S->s));
-    // capacity: twice the larger of the tile's count and the species' mean
-    // count per tile, plus 256 slots, at least the reserve hint share.  Local
-    // density spikes (a laser snow-plough) then rarely overflow a bin; spare
-    // slots cost memory only, never traffic (kernels touch occupied slots).
+    // capacity: three times the larger of the tile's count and the species'
+    // mean count per tile, plus 256 slots, at least the reserve hint share.
+    // Local density spikes (a laser snow-plough) then rarely overflow a bin;
+    // spare slots cost memory only, never traffic (kernels touch occupied slots).
     long long hint_per_tile = D.reserve_hint > 0 ? (D.reserve_hint + nt - 1) / nt : 0;
     long long hsum = 0;
     for (int t = 0; t < nt; ++t) hsum += h[t];
@@ -250,7 +253,7 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     long long total = 0, mtotal = 0;
     int maxc = 0;
     for (int t = 0; t < nt; ++t) {
-        long long c = 2 * std::max<long long>(h[t], mean) + 256;
+        long long c = 3 * std::max<long long>(h[t], mean) + 256;
         long long hc = hint_per_tile + hint_per_tile / 4 + 128;
         c = std::max(c, std::min<long long>(hc, INT_MAX / 4));
         c = (c + 63) & ~63LL;
@@ -389,6 +392,35 @@ int build_ion_table(hk_sim *S, int isp) {
                 if (bound(mid) < 1e-9) lo = mid; else hi = mid;
             }
             L.fskip = lo;
+        }
+        // probability bounds over field bins: the blend is a convex combination
+        // of w_MPI (rising in F) and w_ADK (rising up to F* = 2 k3 / (3 expo),
+        // falling after), so over [Fa, Fb] it stays under max(w_MPI(Fb),
+        // w_ADK at F* clamped to the bin); and 1 - exp(-w dt) <= w dt
+        const double f0 = L.fskip > 0.0 ? L.fskip : 1e-9;
+        const double octaves = 24.0;
+        L.lf0 = (float)std::log2(f0);
+        L.ilr = (float)(ION_NBND / octaves);
+        const double fstar = L.expo > 0.0 ? 2.0 * L.k3 / (3.0 * L.expo) : 1e300;
+        std::vector<double> b1(ION_NBND);
+        for (int b = 0; b < ION_NBND; ++b) {
+            // bins widened by 1e-3 of a bin on both sides against FP32 edge rounding
+            const double fa = std::exp2((double)L.lf0 + (b - 1e-3) / (double)L.ilr);
+            const double fb = std::exp2((double)L.lf0 + (b + 1 + 1e-3) / (double)L.ilr);
+            const double wm = L.wfc * std::pow(std::fmin(fb, L.fc) / L.fc, L.K2);
+            const double fm = std::fmin(std::fmax(fstar, fa), fb);
+            const double wa = L.c2 * L.ip_au * std::pow(2.0 * L.k3 / fm, L.expo) *
+                              std::exp(-2.0 * L.k3 / (3.0 * fm));
+            const double x = std::fmax(wm, wa) * P.rate_norm * S->gd.dt * (1.0 + 1e-6);
+            b1[b] = std::isfinite(x) ? x : 2.0;
+        }
+        for (int b = 0; b < ION_NBND; ++b) {
+            double m = b1[b];
+            if (b > 0) m = std::fmax(m, b1[b - 1]);
+            if (b + 1 < ION_NBND) m = std::fmax(m, b1[b + 1]);
+            // the top bin also stands for every larger field: no bound there
+            if (b >= ION_NBND - 2) m = 2.0;
+            L.bnd[b] = m >= 1.0 ? 2.0f : std::nextafter((float)m, 2.0f);
         }
     }
     D.ion = (IonP *)dalloc(S, sizeof(IonP));
@@ -768,7 +800,7 @@ int one_step(hk_sim *S) {
                 S->timers[8] += 1;
             }
             launch_migrate(g, P, D.mig, D.moff, mcnt, D.mcap, D.buf[nxt], D.nf[nxt], D.nb[nxt],
-                           S->status + 2 + 2 * isp, D.fail, D.inbox_cap, S->status, S->plan_ctl + 2, s);
+                           S->status + 2 + 2 * isp, D.fail, D.inbox_cap, S->status, s);
         } else if (D.d.ionizable && S->run.enable_ionization) {
             DevSpecies &T = S->sp[D.d.target];
             launch_ionize_static(g, P, D.buf[D.cur], cur_bins(D), D.active, S->f, S->sw, hybrid,
@@ -861,7 +893,7 @@ int gauss_snapshot(hk_sim *S) {
 bool check_grid(const hk_grid_desc *g) {
     return g && g->nx >= 4 && g->ny >= 2 && g->nz >= 2 && g->dx > 0 && g->dy > 0 && g->dz > 0 &&
            g->dt > 0 && (g->bc_x == HK_BC_OPEN || g->bc_x == HK_BC_PERIODIC) &&
-           (long long)g->nx * g->ny * g->nz < (1LL << 31) &&
+           (long long)(g->nx + 1) * g->ny * g->nz < (1LL << 31) &&   // nodes: 32-bit indices
            g->dt < 1.0 / std::sqrt(1.0 / (g->dx * g->dx) + 1.0 / (g->dy * g->dy) + 1.0 / (g->dz * g->dz));
 }
 

@@ -30,6 +30,15 @@ struct GridP {
 __host__ __device__ inline long long gidx(const GridP &g, int i, int j, int k) {
     return (long long)i + (long long)g.sx * ((long long)j + (long long)g.ny * (long long)k);
 }
+// (i, j, k) of canonical node c; node counts stay below 2^31 (checked when a
+// simulation is created), so 32-bit unsigned division is exact
+__device__ inline void node_ijk(const GridP &g, long long c, int &i, int &j, int &k) {
+    const unsigned u = (unsigned)c, sx = (unsigned)g.sx, ny = (unsigned)g.ny;
+    const unsigned r = u / sx;
+    i = (int)(u - r * sx);
+    j = (int)(r % ny);
+    k = (int)(r / ny);
+}
 __host__ __device__ inline int wrapi(int i, int n) {
     int r = i % n;
     return r < 0 ? r + n : r;
@@ -160,9 +169,17 @@ struct QedP {
 enum { ERR_NONFINITE = 1, ERR_CFL = 2, ERR_INBOX = 4, ERR_TILE = 8 };
 
 // Device-side rate tables for ionization (per species, per level).
+// Bounds of the step probability over bins of the field: bin b holds fields
+// F with log2(F) in [lf0 + b / ilr, lf0 + (b + 1) / ilr); bnd[b] bounds the
+// probability over bins b - 1 .. b + 1 (so an index off by one from rounding
+// still finds a bound), rounded up.  A draw at or above the bound decides "no
+// event" without the rate.
+#define ION_NBND 512
 struct IonLevel {
     double ip_au, zres, c2, k3, expo, fc, wfc, K2;  // constants of the ADK/MPI blend
     double fskip;  // fields below this give a step probability under the smallest draw
+    float lf0, ilr;
+    float bnd[ION_NBND];
 };
 struct IonP {
     double field_au;   // atomic field units per normalized field unit
@@ -177,6 +194,7 @@ struct IonP {
 // ----------------------------------------------------------------- launchers ------------
 // fields (k_fields.hip)
 void launch_zero(void *p, size_t bytes, hipStream_t s);
+void launch_fill32(void *p, size_t n, uint32_t v, hipStream_t s);   // n 32-bit words
 void launch_yee_b_half(const GridP &g, real *const f[9], hipStream_t s);
 void launch_yee_e_full(const GridP &g, real *const f[9], real *mur_old, hipStream_t s);
 void launch_antenna(const GridP &g, const hk_laser_desc &L, double t, real *jy, real *jz,
@@ -225,7 +243,7 @@ void launch_merge_inbox(const GridP &g, const SpecP &sp, PArr inbox, const int *
                         int *err, hipStream_t s);
 void launch_migrate(const GridP &g, const SpecP &sp, PArr mig, const long long *moff,
                     const int *mcnt, const int *mcap, PArr dst, const int *nf, int *nb, int *fail_n,
-                    PArr fail, int fail_cap, int *err, int *ticket, hipStream_t s);
+                    PArr fail, int fail_cap, int *err, hipStream_t s);
 void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
                        int *nf_out, PArr mig, const long long *moff, const int *mcap, int *mcnt,
                        PArr inbox, int *inbox_n, int inbox_cap, real *const f[9], int *err,
@@ -233,8 +251,7 @@ void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PA
                        int mode, const QedP &Q, int2 *items, int *ctl, long long capacity,
                        hipStream_t s);
 // Work plans of the per-tile particle kernels: items (tile, chunk) for grid g
-// (tile_plan_items entries) and ctl[4] (item count and three tickets: [1] the
-// push, [2] the migration, [3] the moments).  The plan lists the chunks of
+// (tile_plan_items entries) and ctl[0] (the item count).  The plan lists the chunks of
 // at least cmin particles of bins b by decreasing size; tile_plan_grid is the
 // launch size that covers every item of a species of this capacity.
 long long tile_plan_items(const GridP &g);

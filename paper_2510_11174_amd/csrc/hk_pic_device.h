@@ -40,19 +40,19 @@ __device__ inline AxisW axis_weights(int l, real o) {
     return a;
 }
 
+// Reciprocal: the hardware's (1 ulp) in FP32, a division in FP64.
+__device__ inline float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double rcp_(double x) { return 1.0 / x; }
+
+// Trilinear interpolation as three rounds of linear interpolation (x, y, z).
 __device__ inline real tri(const real *F, int i, int j, int k, real fx, real fy, real fz) {
-    const int b = i + FT * (j + FT * k);
-    real acc = 0;
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                real wgt = (a ? fx : 1 - fx) * (bb ? fy : 1 - fy) * (c ? fz : 1 - fz);
-                acc += wgt * F[b + a + FT * (bb + FT * c)];
-            }
-    return acc;
+    const real *p = F + i + FT * (j + FT * k);
+    const real c00 = p[0] + fx * (p[1] - p[0]);
+    const real c10 = p[FT] + fx * (p[FT + 1] - p[FT]);
+    const real c01 = p[FT * FT] + fx * (p[FT * FT + 1] - p[FT * FT]);
+    const real c11 = p[FT * FT + FT] + fx * (p[FT * FT + FT + 1] - p[FT * FT + FT]);
+    const real c0 = c00 + fy * (c10 - c00), c1 = c01 + fy * (c11 - c01);
+    return c0 + fz * (c1 - c0);
 }
 
 // Esirkepov shape factors along one axis for a move from offset o to X1 = o +
@@ -160,55 +160,69 @@ __device__ inline void jadd(jacc_t *p, real v, real inv_scale) {
 }
 __device__ inline double jval(jacc_t v, double scale) { return (double)(long long)v * scale; }
 #endif
-constexpr float JFIX_UNITS = 1099511627776.0f;   // 2^40
+constexpr float JFIX_UNITS = 1099511627776.0f;   // 2^40 (moment sums)
 
-// Esirkepov current of one particle added to an LDS tile of accumulators.
+// The push deposits in 32-bit units: one particle's largest current
+// contribution is 2^30 units, so every contribution converts with one FP32 ->
+// int32 rounding and is added to the 64-bit LDS sum (no overflow for any
+// count of particles a tile can hold).
+constexpr float JDEP_UNITS = 1073741824.0f;   // 2^30
+#ifdef HK_DOUBLE
+__device__ inline void jput(jacc_t *p, real v) {
+    if (v != (real)0) atomicAdd(p, v);
+}
+#else
+__device__ inline void jput(jacc_t *p, real v) {   // v in units
+    const int q = __float2int_rn(v);
+    if (q) atomicAdd(p, (unsigned long long)(long long)q);
+}
+#endif
+
+// Esirkepov current of one particle (linear shapes, a 3-node window per
+// axis) added to the LDS accumulators.  With A = S0 + DS / 2 and B = S0 / 2 +
+// DS / 3 per axis, the transverse weight of an x face (b, c) is
+// S0z_c Ay_b + DSz_c By_b (likewise for y and z faces), and the face current
+// is minus the running sum of the longitudinal shape change, times q w / dV
+// * dx / dt (cx, cy, cz: in units in the FP32 build).  The running sum over
+// the last node of the window is zero, so two faces per line carry current.
 __device__ inline void esirkepov_acc(jacc_t *sJ, int lx, int ly, int lz, const AxisS &X,
-                                     const AxisS &Y, const AxisS &Z, real cx, real cy, real cz,
-                                     real inv_scale) {
+                                     const AxisS &Y, const AxisS &Z, real cx, real cy, real cz) {
     const real third = (real)(1.0 / 3.0), half = (real)0.5;
-    const int ox = lx + X.base + 1, oy = ly + Y.base + 1, oz = lz + Z.base + 1;
+    real Ax[3], Bx[3], Ay[3], By[3], Az[3], Bz[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        Ax[k] = X.S0[k] + half * X.DS[k]; Bx[k] = half * X.S0[k] + third * X.DS[k];
+        Ay[k] = Y.S0[k] + half * Y.DS[k]; By[k] = half * Y.S0[k] + third * Y.DS[k];
+        Az[k] = Z.S0[k] + half * Z.DS[k]; Bz[k] = half * Z.S0[k] + third * Z.DS[k];
+    }
+    // window origin in the tile: constant offsets from here on
+    jacc_t *o = sJ + (lx + X.base + 1) + JT * ((ly + Y.base + 1) + JT * (lz + Z.base + 1));
+    const real kx0 = -cx * X.DS[0], kx1 = -cx * (X.DS[0] + X.DS[1]);
+    const real ky0 = -cy * Y.DS[0], ky1 = -cy * (Y.DS[0] + Y.DS[1]);
+    const real kz0 = -cz * Z.DS[0], kz1 = -cz * (Z.DS[0] + Z.DS[1]);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            real fyz = Y.S0[b] * Z.S0[c] + half * Y.DS[b] * Z.S0[c] + half * Y.S0[b] * Z.DS[c] +
-                       third * Y.DS[b] * Z.DS[c];
-            real acc = 0;
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                acc -= cx * (X.DS[a] * fyz);
-                if (acc != (real)0)
-                    jadd(&sJ[0 * JT3 + (ox + a) + JT * ((oy + b) + JT * (oz + c))], acc, inv_scale);
-            }
+            const real f = Z.S0[c] * Ay[b] + Z.DS[c] * By[b];
+            jput(o + 0 * JT3 + 0 + JT * (b + JT * c), kx0 * f);
+            jput(o + 0 * JT3 + 1 + JT * (b + JT * c), kx1 * f);
         }
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            real fxz = X.S0[a] * Z.S0[c] + half * X.DS[a] * Z.S0[c] + half * X.S0[a] * Z.DS[c] +
-                       third * X.DS[a] * Z.DS[c];
-            real acc = 0;
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                acc -= cy * (Y.DS[b] * fxz);
-                if (acc != (real)0)
-                    jadd(&sJ[1 * JT3 + (ox + a) + JT * ((oy + b) + JT * (oz + c))], acc, inv_scale);
-            }
+            const real f = Z.S0[c] * Ax[a] + Z.DS[c] * Bx[a];
+            jput(o + 1 * JT3 + a + JT * (0 + JT * c), ky0 * f);
+            jput(o + 1 * JT3 + a + JT * (1 + JT * c), ky1 * f);
         }
 #pragma unroll
     for (int b = 0; b < 3; ++b)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            real fxy = X.S0[a] * Y.S0[b] + half * X.DS[a] * Y.S0[b] + half * X.S0[a] * Y.DS[b] +
-                       third * X.DS[a] * Y.DS[b];
-            real acc = 0;
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                acc -= cz * (Z.DS[c] * fxy);
-                if (acc != (real)0)
-                    jadd(&sJ[2 * JT3 + (ox + a) + JT * ((oy + b) + JT * (oz + c))], acc, inv_scale);
-            }
+            const real f = Y.S0[b] * Ax[a] + Y.DS[b] * Bx[a];
+            jput(o + 2 * JT3 + a + JT * (b + JT * 0), kz0 * f);
+            jput(o + 2 * JT3 + a + JT * (b + JT * 1), kz1 * f);
         }
 }
 
@@ -279,19 +293,26 @@ __device__ inline int wave_slot(int *ctr, bool want) {
 // Work items of the per-tile particle kernels.  A tile of n particles forms
 // ceil(n / c) items of c = tile_chunk(n, cmin) consecutive bin slots (the last
 // one shorter), at most TILE_SPLIT of them.  A planner lists the items by
-// decreasing size, and workgroups take them in order from a global ticket, so
-// dense tiles start first and every compute unit, whichever XCD it sits on,
-// pulls the next item when it frees a slot.  (Block i of a launch goes to XCD
-// i mod 8: a dense sheet of tiles at one x index would land on one XCD.)
+// decreasing size and block b of the launch takes item b: blocks go to the 8
+// XCDs in turn and each XCD starts its blocks in order, so every XCD gets an
+// even share of the dense tiles and starts with them.  (One block per tile in
+// tile order would put a dense sheet of tiles at one x index, whose indices
+// agree mod 8, on one XCD.)  No global ticket: a counter that every block
+// bumps serializes at one L2 address, about 10 ns per block.
 constexpr int TILE_SPLIT = 16;
 __device__ inline int tile_chunk(int n, int cmin) {
     return max(cmin, ((n + TILE_SPLIT - 1) / TILE_SPLIT + 511) / 512 * 512);
 }
-// Thread 0 takes the workgroup's item from ticket ctl[ticket]; (-1, 0) when
-// the list (ctl[0] items) is exhausted.
-__device__ inline int2 take_item(const int2 *items, int *ctl, int ticket) {
-    const int k = atomicAdd(&ctl[ticket], 1);
-    return k < ctl[0] ? items[k] : make_int2(-1, 0);
+// Item b of a plan with ctl[0] items; (-1, 0) past the end.
+__device__ inline int2 plan_item(const int2 *items, const int *ctl, int b) {
+    return b < ctl[0] ? items[b] : make_int2(-1, 0);
+}
+// Kernels without a plan (tile, part items in tile order): block b of a grid
+// of 8 q blocks takes item (b mod 8) q + b / 8, so XCD x handles the
+// contiguous item range [x q, (x + 1) q), a slab of whole tile rows in z.
+__device__ inline int xcd_item(int b, int nblocks) {
+    const int q = nblocks >> 3;
+    return (b & 7) * q + (b >> 3);
 }
 
 }  // namespace hkdev

@@ -26,12 +26,6 @@ __device__ inline void block_add(double v, double *out) {
     __syncthreads();
 }
 
-__device__ inline void decompose(const GridP &g, long long c, int &i, int &j, int &k) {
-    i = (int)(c % g.sx);
-    long long r = c / g.sx;
-    j = (int)(r % g.ny);
-    k = (int)(r / g.ny);
-}
 
 __global__ void __launch_bounds__(BS)
 k_field_energy(GridP g, const real *Ex, const real *Ey, const real *Ez, const real *Bx,
@@ -40,7 +34,7 @@ k_field_energy(GridP g, const real *Ex, const real *Ey, const real *Ez, const re
     double ee = 0, bb = 0;
     if (c < g.nn) {
         int i, j, k;
-        decompose(g, c, i, j, k);
+        node_ijk(g, c, i, j, k);
         const int per = g.bcx == HK_BC_PERIODIC;
         bool half_ok = i < g.nx, node_ok = per ? i < g.nx : true;
         if (half_ok) {
@@ -109,7 +103,7 @@ k_gauss(GridP g, const double *dive, const double *rho, const double *g0, int sk
     double r2 = 0, num = 0, mx = 0;
     if (c < g.nn) {
         int i, j, k;
-        decompose(g, c, i, j, k);
+        node_ijk(g, c, i, j, k);
         const int per = g.bcx == HK_BC_PERIODIC;
         bool ok = i < g.nx && (per || (i != 0 && i != skip_plane));
         if (ok) {

@@ -13,22 +13,16 @@ namespace {
 
 constexpr int BS = 256;
 
-__global__ void __launch_bounds__(BS) k_zero(uint32_t *p, size_t n) {
+__global__ void __launch_bounds__(BS) k_fill(uint32_t *p, size_t n, uint32_t v) {
     size_t i = (size_t)blockIdx.x * BS + threadIdx.x;
-    if (i < n) p[i] = 0u;
+    if (i < n) p[i] = v;
 }
 // 16-byte stores for 16-byte aligned buffers (n counts uint4)
-__global__ void __launch_bounds__(BS) k_zero16(uint4 *p, size_t n) {
+__global__ void __launch_bounds__(BS) k_fill16(uint4 *p, size_t n, uint32_t v) {
     for (size_t i = (size_t)blockIdx.x * BS + threadIdx.x; i < n; i += (size_t)gridDim.x * BS)
-        p[i] = make_uint4(0u, 0u, 0u, 0u);
+        p[i] = make_uint4(v, v, v, v);
 }
 
-__device__ inline void decompose(const GridP &g, long long c, int &i, int &j, int &k) {
-    i = (int)(c % g.sx);
-    long long r = c / g.sx;
-    j = (int)(r % g.ny);
-    k = (int)(r / g.ny);
-}
 
 // B <- B - dt/2 curl E.  Node-type Bx on x planes 0..nx (open) or 0..nx-1
 // (periodic); half-type By, Bz on 0..nx-1.
@@ -39,7 +33,7 @@ k_b_half(GridP g, const real *__restrict__ Ex, const real *__restrict__ Ey,
     long long c = (long long)blockIdx.x * BS + threadIdx.x;
     if (c >= g.nn) return;
     int i, j, k;
-    decompose(g, c, i, j, k);
+    node_ijk(g, c, i, j, k);
     const real h = (real)0.5 * g.dt;
     const int per = g.bcx == HK_BC_PERIODIC;
     const int jp = j + 1 == g.ny ? 0 : j + 1, kp = k + 1 == g.nz ? 0 : k + 1;
@@ -68,7 +62,7 @@ k_e_full(GridP g, real *__restrict__ Ex, real *__restrict__ Ey, real *__restrict
     long long c = (long long)blockIdx.x * BS + threadIdx.x;
     if (c >= g.nn) return;
     int i, j, k;
-    decompose(g, c, i, j, k);
+    node_ijk(g, c, i, j, k);
     const real dt = g.dt;
     const int per = g.bcx == HK_BC_PERIODIC;
     const int jm = j == 0 ? g.ny - 1 : j - 1, km = k == 0 ? g.nz - 1 : k - 1;
@@ -151,7 +145,7 @@ k_divE(GridP g, const real *__restrict__ Ex, const real *__restrict__ Ey,
     long long c = (long long)blockIdx.x * BS + threadIdx.x;
     if (c >= g.nn) return;
     int i, j, k;
-    decompose(g, c, i, j, k);
+    node_ijk(g, c, i, j, k);
     const int per = g.bcx == HK_BC_PERIODIC;
     double v = 0.0;
     if ((per && i < g.nx) || (!per && i >= 1 && i <= g.nx - 1)) {
@@ -167,19 +161,20 @@ inline unsigned blocks(long long n) { return (unsigned)((n + BS - 1) / BS); }
 
 }  // namespace
 
-void launch_zero(void *p, size_t bytes, hipStream_t s) {
-    size_t n = bytes / 4;
+void launch_fill32(void *p, size_t n, uint32_t v, hipStream_t s) {
     if (n == 0) return;
-    const size_t n16 = ((uintptr_t)p & 15) ? 0 : bytes / 16;
+    const size_t n16 = ((uintptr_t)p & 15) ? 0 : n / 4;
     if (n16 >= 1024) {
         const long long nb = std::min<long long>(blocks((long long)n16), 4096);
-        k_zero16<<<(unsigned)nb, BS, 0, s>>>((uint4 *)p, n16);
+        k_fill16<<<(unsigned)nb, BS, 0, s>>>((uint4 *)p, n16, v);
         n -= 4 * n16;
         if (n == 0) return;
         p = (uint32_t *)p + 4 * n16;
     }
-    k_zero<<<blocks((long long)n), BS, 0, s>>>((uint32_t *)p, n);
+    k_fill<<<blocks((long long)n), BS, 0, s>>>((uint32_t *)p, n, v);
 }
+
+void launch_zero(void *p, size_t bytes, hipStream_t s) { launch_fill32(p, bytes / 4, 0u, s); }
 
 void launch_yee_b_half(const GridP &g, real *const f[9], hipStream_t s) {
     k_b_half<<<blocks(g.nn), BS, 0, s>>>(g, f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY],

@@ -22,12 +22,6 @@ namespace {
 
 constexpr int BS = 256;
 
-__device__ inline void decompose(const GridP &g, long long c, int &i, int &j, int &k) {
-    i = (int)(c % g.sx);
-    long long r = c / g.sx;
-    j = (int)(r % g.ny);
-    k = (int)(r / g.ny);
-}
 
 // field component at node (i, j, k): trilinear at offset 0, i.e. the node
 // value for node-type axes and the mean of the two neighbours for half axes
@@ -57,7 +51,7 @@ k_fluid_lorentz(GridP g, real qm, const real *__restrict__ n, const real *__rest
     long long c = (long long)blockIdx.x * BS + threadIdx.x;
     if (c >= g.nn) return;
     int i, j, k;
-    decompose(g, c, i, j, k);
+    node_ijk(g, c, i, j, k);
     const int nxn = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
     if (i >= nxn || !(n[c] > (real)0)) return;
     real ex = node_val(g, Ex, i, j, k, 1, 0, 0), ey = node_val(g, Ey, i, j, k, 0, 1, 0);
@@ -121,7 +115,7 @@ k_fluid_update(GridP g, real q, real n_floor, real *__restrict__ n, real *__rest
     long long c = (long long)blockIdx.x * BS + threadIdx.x;
     if (c >= g.nn) return;
     int i, j, k;
-    decompose(g, c, i, j, k);
+    node_ijk(g, c, i, j, k);
     const int per = g.bcx == HK_BC_PERIODIC;
     const int nxn = per ? g.nx : g.nx + 1;
     const real n0 = n[c];

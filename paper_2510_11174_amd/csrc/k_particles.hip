@@ -178,33 +178,81 @@ __global__ void __launch_bounds__(BS)
 k_migrate(GridP g, SpecP sp, PArr mig, const long long *__restrict__ moff,
           const int *__restrict__ mcnt, const int *__restrict__ mcap, PArr dst, const int *__restrict__ nf,
           int *__restrict__ nb, int *__restrict__ fail_n, PArr fail, int fail_cap, int *__restrict__ err,
-          int *__restrict__ ticket) {
-    // tile t, part y of MIGRATE_PARTS from a global ticket: launch order would
-    // put the dense tiles of one x index on one XCD
-    __shared__ int s_k;
-    if (threadIdx.x == 0) s_k = atomicAdd(ticket, 1);
-    __syncthreads();
-    const int t = s_k % g.ntiles, y = s_k / g.ntiles;
-    if (y >= MIGRATE_PARTS) return;
+          int nitems) {
+    // (tile, part) items spread over the XCDs by slabs of tiles
+    __shared__ int s_cnt[27], s_base[27];
+    const int k = xcd_item(blockIdx.x, gridDim.x);
+    if (k >= nitems) return;
+    const int t = k / MIGRATE_PARTS, y = k % MIGRATE_PARTS;
     // movers beyond the region went to the inbox; the parts share the rest
     const int n = min(mcnt[t], mcap[t]);
     const int per = ((n + MIGRATE_PARTS - 1) / MIGRATE_PARTS + BS - 1) / BS * BS;
     const int beg = y * per, end = min(n, beg + per);
     const long long b0 = moff[t];
+    const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
+    const int per_x = g.bcx == HK_BC_PERIODIC;
     for (int p0 = beg; p0 < end; p0 += BS) {
+        if (threadIdx.x < 27) s_cnt[threadIdx.x] = 0;
+        __syncthreads();
+        // the whole particle at once, then one global atomic per destination
+        // tile and workgroup (ranks from LDS counters by direction)
         const int p = p0 + threadIdx.x;
-        const int cell = p < end ? mig.cell[b0 + p] : -1;
-        const bool ok = cell >= 0;
-        const int d = ok ? tile_of(g, cell) : 0;
-        const int slot = wave_reserve(nb, d, ok);
-        if (!ok) continue;
-        if (nf[d] + slot < sp.cap[d]) {
-            copy_particle(mig, b0 + p, dst, sp.off[d] + sp.cap[d] - 1 - slot, sp.has_z, sp.has_tau);
-        } else {
-            int k = atomicAdd(fail_n, 1);
-            if (k < fail_cap) copy_particle(mig, b0 + p, fail, k, sp.has_z, sp.has_tau);
-            else atomicOr(err, ERR_INBOX);
+        const long long i = b0 + p;
+        int cell = -1, zc = 0;
+        real rx = 0, ry = 0, rz = 0, ux = 0, uy = 0, uz = 0, w = 0;
+        uint64_t id = 0;
+        double tau = 0.0;
+        if (p < end) {
+            cell = mig.cell[i];
+            rx = mig.rx[i]; ry = mig.ry[i]; rz = mig.rz[i];
+            ux = mig.ux[i]; uy = mig.uy[i]; uz = mig.uz[i];
+            w = mig.w[i]; id = mig.id[i];
+            if (sp.has_z) zc = mig.zc[i];
+            if (sp.has_tau) tau = mig.tau[i];
         }
+        const bool ok = cell >= 0;
+        int d = 0, dir = -1, rank = 0;
+        if (ok) {
+            int ci, cj, ck;
+            cell_ijk(g, cell, ci, cj, ck);
+            const int dtx_ = ci >> TLOG, dty_ = cj >> TLOG, dtz_ = ck >> TLOG;
+            d = dtx_ + g.ntx * (dty_ + g.nty * dtz_);
+            int ex = dtx_ - tx, ey = dty_ - ty, ez = dtz_ - tz;
+            if (ex > 1) ex -= g.ntx; else if (ex < -1) ex += g.ntx;
+            if (ey > 1) ey -= g.nty; else if (ey < -1) ey += g.nty;
+            if (ez > 1) ez -= g.ntz; else if (ez < -1) ez += g.ntz;
+            if (ex >= -1 && ex <= 1 && ey >= -1 && ey <= 1 && ez >= -1 && ez <= 1) {
+                dir = (ex + 1) + 3 * ((ey + 1) + 3 * (ez + 1));
+                rank = atomicAdd(&s_cnt[dir], 1);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 27 && s_cnt[threadIdx.x] > 0) {
+            const int q = threadIdx.x;
+            int nx_ = tx + q % 3 - 1;
+            if (per_x) nx_ = wrapi(nx_, g.ntx);
+            const int ny_ = wrapi(ty + (q / 3) % 3 - 1, g.nty), nz_ = wrapi(tz + q / 9 - 1, g.ntz);
+            s_base[q] = atomicAdd(&nb[nx_ + g.ntx * (ny_ + g.nty * nz_)], s_cnt[q]);
+        }
+        __syncthreads();
+        if (!ok) continue;
+        // a destination beyond the neighbouring tiles (not reachable in one
+        // step) takes a slot of its own
+        const int slot = dir >= 0 ? s_base[dir] + rank : atomicAdd(&nb[d], 1);
+        PArr to = dst;
+        long long j;
+        if (nf[d] + slot < sp.cap[d]) j = sp.off[d] + sp.cap[d] - 1 - slot;
+        else {
+            const int k = atomicAdd(fail_n, 1);
+            if (k >= fail_cap) { atomicOr(err, ERR_INBOX); continue; }
+            to = fail; j = k;
+        }
+        to.cell[j] = cell;
+        to.rx[j] = rx; to.ry[j] = ry; to.rz[j] = rz;
+        to.ux[j] = ux; to.uy[j] = uy; to.uz[j] = uz;
+        to.w[j] = w; to.id[j] = id;
+        if (sp.has_z) to.zc[j] = zc;
+        if (sp.has_tau) to.tau[j] = tau;
     }
 }
 
@@ -215,8 +263,8 @@ constexpr int PUSH_CHUNK = 16 * PBS; // tiles up to this many particles take one
 // ------------------------------------------------------ work plan of tile kernels -----
 constexpr int PLAN_BS = 1024;
 
-// ctl[0] = number of items, ctl[1..3] = tickets (zeroed here); items sorted
-// by decreasing chunk size through 32 power-of-two buckets.
+// ctl[0] = number of items; items sorted by decreasing chunk size through 32
+// power-of-two buckets.
 __global__ void __launch_bounds__(PLAN_BS)
 k_tile_plan(int ntiles, SpecP sp, Bins bins, int cmin, int2 *__restrict__ items, int *__restrict__ ctl) {
     __shared__ int cnt[32], cur[32];
@@ -235,7 +283,6 @@ k_tile_plan(int ntiles, SpecP sp, Bins bins, int cmin, int2 *__restrict__ items,
         int total = 0;
         for (int b = 31; b >= 0; --b) { cur[b] = total; total += cnt[b]; }
         ctl[0] = total;
-        ctl[1] = 0; ctl[2] = 0; ctl[3] = 0;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < ntiles; t += PLAN_BS) {
@@ -287,17 +334,13 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
        const real *__restrict__ By, const real *__restrict__ Bz, real *__restrict__ Jx,
        real *__restrict__ Jy, real *__restrict__ Jz, int *__restrict__ err,
        unsigned long long *__restrict__ stats, const unsigned *__restrict__ wmax_bits,
-       unsigned *__restrict__ umax2, const int2 *__restrict__ items, int *__restrict__ ctl, QedP Q) {
+       unsigned *__restrict__ umax2, const int2 *__restrict__ items, const int *__restrict__ ctl, QedP Q) {
     __shared__ real sF[6 * FT3];
     __shared__ jacc_t sJ[3 * JT3];
-    __shared__ int s_stay, s_move, s_t, s_j;
+    __shared__ int s_stay, s_move;
     __shared__ unsigned s_u2;
-    if (threadIdx.x == 0) {
-        const int2 it = take_item(items, ctl, 1);
-        s_t = it.x; s_j = it.y;
-    }
-    __syncthreads();
-    const int t = s_t, item = s_j;
+    const int2 it = plan_item(items, ctl, blockIdx.x);
+    const int t = it.x, item = it.y;
     if (t < 0) return;
     int nfi, nbi;
     const int n = bin_count(sp, bin_in, t, nfi, nbi);
@@ -351,8 +394,12 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
     // bound (never lowered; raised by every kernel that creates particles)
     const double jmax = (double)fabsf((float)sp.q) * (double)__uint_as_float(*wmax_bits) / (double)dv *
                         (double)fmaxf(fmaxf((float)cdx, (float)cdy), (float)cdz);
-    const double jscale = jmax > 0.0 ? jmax / (double)JFIX_UNITS : 1.0;
-    const real inv_scale = (real)(1.0 / jscale);
+#ifdef HK_DOUBLE
+    const double jscale = 1.0;   // FP64 sums, no scale
+#else
+    const double jscale = jmax > 0.0 ? jmax / (double)JDEP_UNITS : 1.0;
+#endif
+    const real qsc = (real)((double)sp.q / (double)dv / jscale);   // q / dV in units
     PLoad nx_ = pload(in, sp, bin_slot(sp, t, min(pbeg + (int)threadIdx.x, pend - 1), nfi, nbi),
                       pbeg + (int)threadIdx.x < pend);
     for (int p0 = pbeg; p0 < pend; p0 += PBS) {
@@ -453,10 +500,10 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
                 // Boris rotation
                 real umx = ux + hq * ex, umy = uy + hq * ey, umz = uz + hq * ez;
                 real gm = sqrt((real)1 + umx * umx + umy * umy + umz * umz);
-                const real igm = hq / gm;
+                const real igm = hq * rcp_(gm);
                 real tx_ = bx * igm, ty_ = by * igm, tz_ = bz * igm;
                 real t2 = tx_ * tx_ + ty_ * ty_ + tz_ * tz_;
-                const real is = (real)2 / (1 + t2);
+                const real is = (real)2 * rcp_(1 + t2);
                 real sx = tx_ * is, sy = ty_ * is, sz = tz_ * is;
                 real upx = umx + (umy * tz_ - umz * ty_);
                 real upy = umy + (umz * tx_ - umx * tz_);
@@ -466,7 +513,7 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
                 real uqz = umz + (upx * sy - upy * sx);
                 ux = uqx + hq * ex; uy = uqy + hq * ey; uz = uqz + hq * ez;
                 real gam = sqrt((real)1 + ux * ux + uy * uy + uz * uz);
-                const real igam = (real)1 / gam;
+                const real igam = rcp_(gam);
                 X1 = rx + dtdx * ux * igam;
                 Y1 = ry + dtdy * uy * igam;
                 Z1 = rz + dtdz * uz * igam;
@@ -490,8 +537,8 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
                 // Esirkepov deposit of J^{n+1/2}
                 if (MODE != 2 && sp.q != (real)0) {
                     AxisS SX = axis_shapes(rx, X1), SY = axis_shapes(ry, Y1), SZ = axis_shapes(rz, Z1);
-                    const real qw = sp.q * w / dv;
-                    esirkepov_acc(sJ, lx, ly, lz, SX, SY, SZ, qw * cdx, qw * cdy, qw * cdz, inv_scale);
+                    const real qws = qsc * w;
+                    esirkepov_acc(sJ, lx, ly, lz, SX, SY, SZ, qws * cdx, qws * cdy, qws * cdz);
                 }
                 // new cell and offsets
                 int fx = X1 >= (real)1 ? 1 : (X1 < (real)0 ? -1 : 0);
@@ -523,26 +570,23 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
         bs = __shfl(bs, 0);
         bm = __shfl(bm, 0);
         if (valid) {
-            PArr dst = out;
-            long long j = -1;
-            if (stay) j = obase + bs + __popcll(ms & lt);
+            // three store groups with uniform bases (no per-lane pointer choice)
+            auto put = [&](const PArr &d, long long j) {
+                d.cell[j] = ncell;
+                d.rx[j] = nrx; d.ry[j] = nry; d.rz[j] = nrz;
+                d.ux[j] = ux; d.uy[j] = uy; d.uz[j] = uz;
+                d.w[j] = w;
+                d.id[j] = id;
+                if (sp.has_z) d.zc[j] = zc;
+                if (sp.has_tau) d.tau[j] = tau;
+            };
+            const int k = bm + __popcll(mm & lt);
+            if (stay) put(out, obase + bs + __popcll(ms & lt));
+            else if (k < mlim) put(mig, mbase + k);
             else {
-                const int k = bm + __popcll(mm & lt);
-                if (k < mlim) { dst = mig; j = mbase + k; }
-                else {
-                    const int q = atomicAdd(inbox_n, 1);
-                    if (q >= inbox_cap) atomicOr(err, ERR_INBOX);
-                    else { dst = inbox; j = q; }
-                }
-            }
-            if (j >= 0) {
-                dst.cell[j] = ncell;
-                dst.rx[j] = nrx; dst.ry[j] = nry; dst.rz[j] = nrz;
-                dst.ux[j] = ux; dst.uy[j] = uy; dst.uz[j] = uz;
-                dst.w[j] = w;
-                dst.id[j] = id;
-                if (sp.has_z) dst.zc[j] = zc;
-                if (sp.has_tau) dst.tau[j] = tau;
+                const int q = atomicAdd(inbox_n, 1);
+                if (q >= inbox_cap) atomicOr(err, ERR_INBOX);
+                else put(inbox, q);
             }
         }
         if (MODE != 0) {
@@ -634,125 +678,155 @@ __device__ inline double blended_rate(const IonLevel &L, double F, double omega)
     return sig * wm + (1.0 - sig) * adk(L, F);
 }
 
+// Immobile ions of tile t are shared by ION_PARTS workgroups (tile, part
+// items spread over the XCDs by slabs of tiles).
+constexpr int ION_PARTS = 4;
+constexpr int INT_ = TILE + 1;   // nearest-node tile edge
+constexpr int INT3 = INT_ * INT_ * INT_;
+
 __global__ void __launch_bounds__(BS)
 k_ionize_static(GridP g, SpecP sp, PArr a, Bins bins, int *__restrict__ active,
                 const real *__restrict__ Ex, const real *__restrict__ Ey, const real *__restrict__ Ez,
                 const uint8_t *__restrict__ sw, int hybrid, const IonP *__restrict__ ion, PArr eout,
                 int *__restrict__ eout_n, int eout_cap, uint64_t seed, int step,
                 double *__restrict__ ledger, int *__restrict__ err, unsigned *__restrict__ umax2,
-                int eout_tau) {
+                int eout_tau, int nitems) {
     __shared__ real sF[3 * FT3];
-    const int t = blockIdx.x;
-    int nf, nbv;
+    __shared__ uint8_t sS[INT3];
+    const int kk = xcd_item(blockIdx.x, gridDim.x);
+    if (kk >= nitems) return;
+    const int t = kk / ION_PARTS, part = kk % ION_PARTS;
+    if (active[t] <= 0) return;   // every ion of the tile at z_max
+    int nf = 0, nbv = 0;
     const int n = bin_count(sp, bins, t, nf, nbv);
-    if (n <= 0 || active[t] <= 0) return;
-    const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
-    const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
-    const int per = g.bcx == HK_BC_PERIODIC;
-    for (int e = threadIdx.x; e < FT3; e += BS) {
-        int aa = e % FT, b = (e / FT) % FT, c = e / (FT * FT);
-        int gi = ox - 1 + aa;
-        int gj = wrapi(oy - 1 + b, g.ny), gk = wrapi(oz - 1 + c, g.nz);
-        int ih, in_;
-        if (per) { ih = in_ = wrapi(gi, g.nx); }
-        else {
-            ih = gi < 0 ? 0 : (gi > g.nx - 1 ? g.nx - 1 : gi);
-            in_ = gi < 0 ? 0 : (gi > g.nx ? g.nx : gi);
+    if (n > 0) {
+        const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
+        const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
+        const int per = g.bcx == HK_BC_PERIODIC;
+        for (int e = threadIdx.x; e < FT3; e += BS) {
+            int aa = e % FT, b = (e / FT) % FT, c = e / (FT * FT);
+            int gi = ox - 1 + aa;
+            int gj = wrapi(oy - 1 + b, g.ny), gk = wrapi(oz - 1 + c, g.nz);
+            int ih, in_;
+            if (per) { ih = in_ = wrapi(gi, g.nx); }
+            else {
+                ih = gi < 0 ? 0 : (gi > g.nx - 1 ? g.nx - 1 : gi);
+                in_ = gi < 0 ? 0 : (gi > g.nx ? g.nx : gi);
+            }
+            sF[0 * FT3 + e] = Ex[gidx(g, ih, gj, gk)];
+            sF[1 * FT3 + e] = Ey[gidx(g, in_, gj, gk)];
+            sF[2 * FT3 + e] = Ez[gidx(g, in_, gj, gk)];
         }
-        sF[0 * FT3 + e] = Ex[gidx(g, ih, gj, gk)];
-        sF[1 * FT3 + e] = Ey[gidx(g, in_, gj, gk)];
-        sF[2 * FT3 + e] = Ez[gidx(g, in_, gj, gk)];
+        // switch map of the tile's nearest nodes ox .. ox + TILE (node nx exists
+        // in open x; periodic directions wrap)
+        if (hybrid)
+            for (int e = threadIdx.x; e < INT3; e += BS) {
+                int aa = e % INT_, b = (e / INT_) % INT_, c = e / (INT_ * INT_);
+                int gi = ox + aa;
+                if (per) gi = wrapi(gi, g.nx);
+                sS[e] = sw[gidx(g, gi, wrapi(oy + b, g.ny), wrapi(oz + c, g.nz))];
+            }
+        __syncthreads();
+        const double omega = ion->omega_au;
+        const int zmax = ion->z_max;
+        const int lane = __lane_id();
+        int done = 0;
+        const int span = ((n + ION_PARTS - 1) / ION_PARTS + BS - 1) / BS * BS;
+        const int pbeg = part * span, pend = min(n, pbeg + span);
+        // next iteration's slot, loaded one iteration ahead
+        auto ld = [&](int p, int &cell, int &z, real &x, real &y, real &zz, uint64_t &id, long long &ip) {
+            cell = -1; z = 0; x = y = zz = 0; id = 0; ip = 0;
+            if (p < pend) {
+                ip = bin_slot(sp, t, p, nf, nbv);
+                cell = a.cell[ip]; z = a.zc[ip];
+                x = a.rx[ip]; y = a.ry[ip]; zz = a.rz[ip];
+                id = a.id[ip];
+            }
+        };
+        int ncell, nz0; real nrx, nry, nrz; uint64_t nid; long long nip;
+        ld(pbeg + threadIdx.x, ncell, nz0, nrx, nry, nrz, nid, nip);
+        // uniform trip count so that every lane of a wave takes part in the
+        // event-slot scan below
+        for (int p0 = pbeg; p0 < pend; p0 += BS) {
+            const int cell = ncell, z0 = ncell >= 0 ? nz0 : 0;
+            const real rx = nrx, ry = nry, rz = nrz;
+            const uint64_t pid = nid;
+            const long long ip = nip;
+            if (p0 + BS < pend) ld(p0 + BS + threadIdx.x, ncell, nz0, nrx, nry, nrz, nid, nip);
+            int nev = 0;
+            bool live = cell >= 0 && z0 < zmax;
+            int ci = 0, cj = 0, ck = 0;
+            if (live) cell_ijk(g, cell, ci, cj, ck);
+            const int lx = ci - ox, ly = cj - oy, lz = ck - oz;
+            if (live && ((unsigned)lx >= TILE || (unsigned)ly >= TILE || (unsigned)lz >= TILE)) {
+                atomicOr(err, ERR_TILE);
+                live = false;
+            }
+            if (live && hybrid) {
+                const int e = (lx + (rx >= (real)0.5)) + INT_ * ((ly + (ry >= (real)0.5)) + INT_ * (lz + (rz >= (real)0.5)));
+                if (!sS[e]) live = false;
+            }
+            if (live) {
+                AxisW X = axis_weights(lx, rx), Y = axis_weights(ly, ry), Z = axis_weights(lz, rz);
+                double ex = tri(sF + 0 * FT3, X.ih, Y.in_, Z.in_, X.fh, Y.fn, Z.fn);
+                double ey = tri(sF + 1 * FT3, X.in_, Y.ih, Z.in_, X.fn, Y.fh, Z.fn);
+                double ez = tri(sF + 2 * FT3, X.in_, Y.in_, Z.ih, X.fn, Y.fn, Z.fh);
+                double F = sqrt(ex * ex + ey * ey + ez * ez) * ion->field_au;
+                // levels ionize in sequence; below fskip the probability is under
+                // the smallest uniform draw, so no event is possible; a draw at or
+                // above the level's probability bound for this field decides
+                // "no event" without evaluating the rate
+                const float lf = __log2f((float)F);
+                for (int lev = z0; lev < zmax; ++lev) {
+                    const IonLevel &L = ion->lev[lev];
+                    if (F < L.fskip) break;
+                    uint32_t r[4];
+                    draw4(seed, pid, (uint32_t)step, TAG_ION + (uint32_t)lev, 0, r);
+                    const double u = u01d(r[0]);
+                    const int b = min(max((int)((lf - L.lf0) * L.ilr), 0), ION_NBND - 1);
+                    if (u >= (double)L.bnd[b]) break;
+                    const double wr = blended_rate(L, F, omega) * ion->rate_norm;
+                    const double P = -expm1(-wr * g.ddt);
+                    if (!(u < P)) break;
+                    nev++;
+                }
+            }
+            // one slot reservation per wave: inclusive scan of the event counts
+            int incl = nev;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_up(incl, o);
+                if (lane >= o) incl += v;
+            }
+            const int tot = __shfl(incl, 63);
+            if (tot == 0) continue;
+            int base = 0;
+            if (lane == 63) base = atomicAdd(eout_n, tot);
+            base = __shfl(base, 63);
+            double led = 0.0;
+            if (nev) {
+                const real ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip], w = a.w[ip];
+                const float u2 = (float)(ux * ux + uy * uy + uz * uz);
+                if (u2 > 0.f) atomicMax(&umax2[t], __float_as_uint(u2));   // newborns keep the ion's u
+                for (int e = 0; e < nev; ++e) {
+                    const int k = base + incl - nev + e;
+                    const int lev = z0 + e;
+                    if (k >= eout_cap) { atomicOr(err, ERR_INBOX); break; }
+                    eout.cell[k] = cell;
+                    eout.rx[k] = rx; eout.ry[k] = ry; eout.rz[k] = rz;
+                    eout.ux[k] = ux; eout.uy[k] = uy; eout.uz[k] = uz;
+                    eout.w[k] = w;
+                    eout.id[k] = (1ull << 62) | ((uint64_t)lev << 56) | pid;
+                    if (eout_tau) eout.tau[k] = tau0(seed, eout.id[k]);
+                    led += (double)w * ion->lev[lev].ip_au * 27.211386245988 / 510998.95;
+                }
+                a.zc[ip] = z0 + nev;
+                if (z0 + nev >= zmax) done++;
+            }
+            for (int o = 32; o > 0; o >>= 1) led += __shfl_xor(led, o);
+            if (lane == 0 && led != 0.0) atomicAdd(ledger, led);
+        }
+        if (done) atomicSub(&active[t], done);
     }
-    __syncthreads();
-    const double omega = ion->omega_au;
-    const int zmax = ion->z_max;
-    const int lane = __lane_id();
-    int done = 0;
-    // uniform trip count so that every lane of a wave takes part in the
-    // event-slot scan below
-    for (int p0 = 0; p0 < n; p0 += BS) {
-        const int p = p0 + threadIdx.x;
-        long long ip = 0;
-        int z0 = 0, nev = 0, cell = -1;
-        real rx = 0, ry = 0, rz = 0;
-        if (p < n) {
-            ip = bin_slot(sp, t, p, nf, nbv);
-            cell = a.cell[ip];
-            if (cell >= 0) z0 = a.zc[ip];
-        }
-        bool live = cell >= 0 && z0 < zmax;
-        int ci = 0, cj = 0, ck = 0;
-        if (live) {
-            cell_ijk(g, cell, ci, cj, ck);
-            rx = a.rx[ip]; ry = a.ry[ip]; rz = a.rz[ip];
-            if (hybrid) {
-                int ni = ci + (rx >= (real)0.5), nj = cj + (ry >= (real)0.5), nk = ck + (rz >= (real)0.5);
-                if (per) ni = wrapi(ni, g.nx);
-                if (nj >= g.ny) nj -= g.ny;
-                if (nk >= g.nz) nk -= g.nz;
-                if (!sw[gidx(g, ni, nj, nk)]) live = false;
-            }
-        }
-        const int lx = ci - ox, ly = cj - oy, lz = ck - oz;
-        if (live && ((unsigned)lx >= TILE || (unsigned)ly >= TILE || (unsigned)lz >= TILE)) {
-            atomicOr(err, ERR_TILE);
-            live = false;
-        }
-        uint64_t pid = 0;
-        if (live) {
-            AxisW X = axis_weights(lx, rx), Y = axis_weights(ly, ry), Z = axis_weights(lz, rz);
-            double ex = tri(sF + 0 * FT3, X.ih, Y.in_, Z.in_, X.fh, Y.fn, Z.fn);
-            double ey = tri(sF + 1 * FT3, X.in_, Y.ih, Z.in_, X.fn, Y.fh, Z.fn);
-            double ez = tri(sF + 2 * FT3, X.in_, Y.in_, Z.ih, X.fn, Y.fn, Z.fh);
-            double F = sqrt(ex * ex + ey * ey + ez * ez) * ion->field_au;
-            pid = a.id[ip];
-            // levels ionize in sequence; below fskip the probability is under
-            // the smallest uniform draw, so no event is possible
-            for (int lev = z0; lev < zmax; ++lev) {
-                if (F < ion->lev[lev].fskip) break;
-                double wr = blended_rate(ion->lev[lev], F, omega) * ion->rate_norm;
-                double P = -expm1(-wr * g.ddt);
-                uint32_t r[4];
-                draw4(seed, pid, (uint32_t)step, TAG_ION + (uint32_t)lev, 0, r);
-                if (!(u01d(r[0]) < P)) break;
-                nev++;
-            }
-        }
-        // one slot reservation per wave: inclusive scan of the event counts
-        int incl = nev;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int v = __shfl_up(incl, o);
-            if (lane >= o) incl += v;
-        }
-        const int tot = __shfl(incl, 63);
-        if (tot == 0) continue;
-        int base = 0;
-        if (lane == 63) base = atomicAdd(eout_n, tot);
-        base = __shfl(base, 63);
-        double led = 0.0;
-        if (nev) {
-            const real ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip], w = a.w[ip];
-            const float u2 = (float)(ux * ux + uy * uy + uz * uz);
-            if (u2 > 0.f) atomicMax(&umax2[t], __float_as_uint(u2));   // newborns keep the ion's u
-            for (int e = 0; e < nev; ++e) {
-                const int k = base + incl - nev + e;
-                const int lev = z0 + e;
-                if (k >= eout_cap) { atomicOr(err, ERR_INBOX); break; }
-                eout.cell[k] = cell;
-                eout.rx[k] = rx; eout.ry[k] = ry; eout.rz[k] = rz;
-                eout.ux[k] = ux; eout.uy[k] = uy; eout.uz[k] = uz;
-                eout.w[k] = w;
-                eout.id[k] = (1ull << 62) | ((uint64_t)lev << 56) | pid;
-                if (eout_tau) eout.tau[k] = tau0(seed, eout.id[k]);
-                led += (double)w * ion->lev[lev].ip_au * 27.211386245988 / 510998.95;
-            }
-            a.zc[ip] = z0 + nev;
-            if (z0 + nev >= zmax) done++;
-        }
-        for (int o = 32; o > 0; o >>= 1) led += __shfl_xor(led, o);
-        if (lane == 0) atomicAdd(ledger, led);
-    }
-    if (done) atomicSub(&active[t], done);
 }
 
 // Ions below full ionization per tile.
@@ -844,9 +918,10 @@ void launch_merge_inbox(const GridP &g, const SpecP &sp, PArr inbox, const int *
 
 void launch_migrate(const GridP &g, const SpecP &sp, PArr mig, const long long *moff,
                     const int *mcnt, const int *mcap, PArr dst, const int *nf, int *nb, int *fail_n,
-                    PArr fail, int fail_cap, int *err, int *ticket, hipStream_t s) {
-    k_migrate<<<g.ntiles * MIGRATE_PARTS, BS, 0, s>>>(g, sp, mig, moff, mcnt, mcap, dst, nf, nb, fail_n,
-                                                        fail, fail_cap, err, ticket);
+                    PArr fail, int fail_cap, int *err, hipStream_t s) {
+    const int n = g.ntiles * MIGRATE_PARTS;
+    k_migrate<<<(n + 7) / 8 * 8, BS, 0, s>>>(g, sp, mig, moff, mcnt, mcap, dst, nf, nb, fail_n, fail,
+                                              fail_cap, err, n);
 }
 
 long long tile_plan_items(const GridP &g) { return (long long)g.ntiles * TILE_SPLIT; }
@@ -884,9 +959,10 @@ void launch_ionize_static(const GridP &g, const SpecP &sp, PArr a, Bins b, int *
                           real *const f[9], const uint8_t *sw, int hybrid, const IonP *ion,
                           PArr eout, int *eout_n, int eout_cap, uint64_t seed, int step,
                           double *ledger, int *err, unsigned *umax2, int eout_tau, hipStream_t s) {
-    k_ionize_static<<<g.ntiles, BS, 0, s>>>(g, sp, a, b, active, f[HK_EX], f[HK_EY], f[HK_EZ], sw,
-                                            hybrid, ion, eout, eout_n, eout_cap, seed, step, ledger,
-                                            err, umax2, eout_tau);
+    const int n = g.ntiles * ION_PARTS;
+    k_ionize_static<<<(n + 7) / 8 * 8, BS, 0, s>>>(g, sp, a, b, active, f[HK_EX], f[HK_EY], f[HK_EZ],
+                                                   sw, hybrid, ion, eout, eout_n, eout_cap, seed, step,
+                                                   ledger, err, umax2, eout_tau, n);
 }
 
 void launch_count_active(const GridP &g, const SpecP &sp, PArr a, Bins b, int zmax, int *active,

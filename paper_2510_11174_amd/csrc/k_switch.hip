@@ -27,12 +27,6 @@ constexpr int BS = 256;
 constexpr int NT = TILE + 1;          // node tile edge: nearest nodes 0 .. TILE
 constexpr int NT3 = NT * NT * NT;
 
-__device__ inline void decompose(const GridP &g, long long c, int &i, int &j, int &k) {
-    i = (int)(c % g.sx);
-    long long r = c / g.sx;
-    j = (int)(r % g.ny);
-    k = (int)(r / g.ny);
-}
 
 // Nearest node of a particle (cell + offset), wrapped in periodic directions.
 __device__ inline long long nearest_node(const GridP &g, int ci, int cj, int ck, real rx, real ry,
@@ -79,30 +73,26 @@ __device__ inline void madd(jacc_t *p, real v, real inv) {
 }
 
 constexpr int MOM_CHUNK = 8192;   // particles per workgroup of the tile moments
+constexpr int MBS = 512;          // moments workgroup: LDS allows four per CU, 8 waves per SIMD
 
-__global__ void __launch_bounds__(BS)
+__global__ void __launch_bounds__(MBS)
 k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__restrict__ mom,
           const unsigned *__restrict__ wmax_bits, const unsigned *__restrict__ umax2,
-          const int *__restrict__ active, const int2 *__restrict__ items, int *__restrict__ ctl) {
+          const int *__restrict__ active, const int2 *__restrict__ items, const int *__restrict__ ctl) {
     __shared__ jacc_t sm[6 * NT3];
     __shared__ unsigned s_u2;
-    __shared__ int s_t, s_j;
-    if (threadIdx.x == 0) {
-        const int2 it = take_item(items, ctl, 3);
-        s_t = it.x; s_j = it.y;
-    }
-    __syncthreads();
-    const int t = s_t;
+    const int2 it = plan_item(items, ctl, blockIdx.x);
+    const int t = it.x;
     if (t < 0) return;
     int nf, nbv;
     const int nt_ = bin_count(sp, bins, t, nf, nbv);
     // this workgroup's chunk [p0, n) of the tile's bin slots
     const int chunk = tile_chunk(nt_, MOM_CHUNK);
-    const int p0 = s_j * chunk, n = min(nt_, p0 + chunk);
+    const int p0 = it.y * chunk, n = min(nt_, p0 + chunk);
     if (p0 >= n) return;
     if (ion_only && active && active[t] <= 0) return;   // every ion of the tile at z_max
     const int nq = ion_only ? 1 : 6;
-    for (int e = threadIdx.x; e < nq * NT3; e += BS) sm[e] = 0;
+    for (int e = threadIdx.x; e < nq * NT3; e += MBS) sm[e] = 0;
     if (threadIdx.x == 0) s_u2 = 0;
     __syncthreads();
     const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
@@ -117,7 +107,7 @@ k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__
             }
         } else {
             float l = 0.f;
-            for (int p = p0 + threadIdx.x; p < n; p += BS) {
+            for (int p = p0 + threadIdx.x; p < n; p += MBS) {
                 const long long ip = bin_slot(sp, t, p, nf, nbv);
                 if (a.cell[ip] < 0) continue;
                 const real ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip];
@@ -138,27 +128,31 @@ k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__
         scl[q] = (real)(bound[q] / (double)JFIX_UNITS);
     }
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
-    for (int p = p0 + threadIdx.x; p < n; p += BS) {
+    for (int p = p0 + threadIdx.x; p < n; p += MBS) {
+        // every field of the slot at once: no load waits on another
         const long long ip = bin_slot(sp, t, p, nf, nbv);
-        int cell = a.cell[ip];
+        const int cell = a.cell[ip];
+        const real rx = a.rx[ip], ry = a.ry[ip], rz = a.rz[ip], w = a.w[ip];
+        real ux = 0, uy = 0, uz = 0;
+        int zc = 0;
+        if (ion_only) zc = a.zc[ip];
+        else { ux = a.ux[ip]; uy = a.uy[ip]; uz = a.uz[ip]; }
         if (cell < 0) continue;
         int ci, cj, ck;
         cell_ijk(g, cell, ci, cj, ck);
-        const int lx = ci - ox + (a.rx[ip] >= (real)0.5), ly = cj - oy + (a.ry[ip] >= (real)0.5),
-                  lz = ck - oz + (a.rz[ip] >= (real)0.5);
+        const int lx = ci - ox + (rx >= (real)0.5), ly = cj - oy + (ry >= (real)0.5),
+                  lz = ck - oz + (rz >= (real)0.5);
         if ((unsigned)lx > TILE || (unsigned)ly > TILE || (unsigned)lz > TILE) continue;
         const int e = lx + NT * (ly + NT * lz);
-        const real w = a.w[ip];
         if (ion_only) {
-            if (a.zc[ip] < zmax) madd(&sm[e], w, inv[0]);
+            if (zc < zmax) madd(&sm[e], w, inv[0]);
             continue;
         }
-        const real ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip];
         for (int q = 0; q < 6; ++q) madd(&sm[q * NT3 + e], tile_moment_term(q, w, ux, uy, uz), inv[q]);
     }
     __syncthreads();
     const int per = g.bcx == HK_BC_PERIODIC;
-    for (int e = threadIdx.x; e < NT3; e += BS) {
+    for (int e = threadIdx.x; e < NT3; e += MBS) {
         int aa = e % NT, b = (e / NT) % NT, c = e / (NT * NT);
         int gi = ox + aa, gj = wrapi(oy + b, g.ny), gk = wrapi(oz + c, g.nz);
         if (per) gi = wrapi(gi, g.nx);
@@ -246,7 +240,7 @@ k_indicators(GridP g, SwitchP P, const real *__restrict__ mom, const real *__res
     long long c = (long long)blockIdx.x * BS + threadIdx.x;
     if (c >= g.nn) return;
     int i, j, k;
-    decompose(g, c, i, j, k);
+    node_ijk(g, c, i, j, k);
     const int per = g.bcx == HK_BC_PERIODIC;
     const int nxn = per ? g.nx : g.nx + 1;
     if (i >= nxn) { hot[c] = 0; notcold[c] = 0; return; }
@@ -294,22 +288,23 @@ k_dilate(GridP g, SwitchP P, const uint8_t *__restrict__ hot, const uint8_t *__r
     long long c = (long long)blockIdx.x * BS + threadIdx.x;
     if (c >= g.nn) return;
     int i, j, k;
-    decompose(g, c, i, j, k);
+    node_ijk(g, c, i, j, k);
     const int per = g.bcx == HK_BC_PERIODIC;
     const int nxn = per ? g.nx : g.nx + 1;
     if (i >= nxn) return;
     const int D = P.dilation;
     int kin = 0, warm = 0;
-    for (int dk = -D; dk <= D; ++dk)
-        for (int dj = -D; dj <= D; ++dj)
+    for (int dk = -D; dk <= D && !kin; ++dk)
+        for (int dj = -D; dj <= D; ++dj) {
+            const long long row = gidx(g, 0, wrapi(j + dj, g.ny), wrapi(k + dk, g.nz));
             for (int di = -D; di <= D; ++di) {
                 int ii = i + di;
                 if (!per && (ii < 0 || ii > g.nx)) continue;
                 if (per) ii = wrapi(ii, g.nx);
-                long long q = gidx(g, ii, wrapi(j + dj, g.ny), wrapi(k + dk, g.nz));
-                kin |= hot[q];
-                warm |= notcold[q];
+                kin |= hot[row + ii];
+                warm |= notcold[row + ii];
             }
+        }
     if (kin) { sw[c] = 1; calm[c] = 0; }
     else if (sw[c]) {
         if (warm) calm[c] = 0;
@@ -478,7 +473,7 @@ k_spawn(GridP g, SpecP sp, const uint8_t *__restrict__ sw, real *__restrict__ n,
     long long c = (long long)blockIdx.x * BS + threadIdx.x;
     if (c >= g.nn) return;
     int i, j, k;
-    decompose(g, c, i, j, k);
+    node_ijk(g, c, i, j, k);
     const int per = g.bcx == HK_BC_PERIODIC;
     const int nxn = per ? g.nx : g.nx + 1;
     if (i >= nxn || !sw[c]) return;
@@ -541,7 +536,7 @@ void launch_moments_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, int i
                           int zmax, real *mom, const unsigned *wmax_bits, const unsigned *umax2,
                           const int *active, int2 *items, int *ctl, long long capacity, hipStream_t s) {
     launch_tile_plan(g, sp, b, MOM_CHUNK, items, ctl, s);
-    k_moments<<<tile_plan_grid(g, capacity, MOM_CHUNK), BS, 0, s>>>(g, sp, a, b, ion_only, zmax, mom,
+    k_moments<<<tile_plan_grid(g, capacity, MOM_CHUNK), MBS, 0, s>>>(g, sp, a, b, ion_only, zmax, mom,
                                                                   wmax_bits, umax2, active, items, ctl);
 }
 void launch_fluid_moments_nodes(const GridP &g, real inv_ppc, const real *n, const real *ux,
