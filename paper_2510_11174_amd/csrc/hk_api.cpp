@@ -43,11 +43,13 @@ struct DevSpecies {
     std::vector<long long> h_off;
     std::vector<int> h_cap;
     int max_cap = 0;
-    PArr mig{};                // per-tile mover regions
+    long long mig0 = 0;        // slot of the first per-tile mover region in each bin buffer
     long long *moff = nullptr;
     int *mcap = nullptr;
     int *active = nullptr;     // immobile ionizable ions: ions below z_max per tile
     PArr inbox{}, fail{};
+    PArr *inbox_dev = nullptr;    // device copy of the inbox descriptor (the push reads it
+                                  // only when a mover region overflows)
     int inbox_cap = 0;
     long long *g_off0 = nullptr;  // device {0}
     int *g_capmax = nullptr;      // device {INT_MAX}
@@ -176,6 +178,16 @@ bool alloc_parr(hk_sim *S, PArr &a, long long n, int has_z, int has_tau) {
     return true;
 }
 
+// The same arrays from slot k on.
+PArr shifted(const PArr &a, long long k) {
+    PArr v = a;
+    v.cell += k; v.rx += k; v.ry += k; v.rz += k; v.ux += k; v.uy += k; v.uz += k; v.w += k;
+    v.id += k;
+    if (v.zc) v.zc += k;
+    if (v.tau) v.tau += k;
+    return v;
+}
+
 void free_parr(hk_sim *S, PArr &a) {
     dfree(S, a.cell);   // the base of the set's one allocation
     a = PArr{};
@@ -266,11 +278,12 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
         mcap[t] = (int)m;
         mtotal += m;
     }
-    PArr nbuf[2], nmig;
-    if (!alloc_parr(S, nbuf[0], total, D.has_z, D.has_tau) ||
-        !alloc_parr(S, nbuf[1], total, D.has_z, D.has_tau) ||
-        !alloc_parr(S, nmig, D.d.mobile ? mtotal : 1, D.has_z, D.has_tau))
-        return fail(S, HK_ENOMEM, "rebuild: %lld particle slots", total);
+    // each bin buffer carries the per-tile mover regions after its bins
+    PArr nbuf[2];
+    const long long slots = total + (D.d.mobile ? mtotal : 0);
+    if (!alloc_parr(S, nbuf[0], slots, D.has_z, D.has_tau) ||
+        !alloc_parr(S, nbuf[1], slots, D.has_z, D.has_tau))
+        return fail(S, HK_ENOMEM, "rebuild: %lld particle slots", slots);
     long long *doff = (long long *)dalloc(S, sizeof(long long) * nt);
     long long *dmoff = (long long *)dalloc(S, sizeof(long long) * nt);
     int *dcap = (int *)dalloc(S, sizeof(int) * nt);
@@ -294,14 +307,13 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     HIPCHK(S, hipStreamSynchronize(S->s));
     free_parr(S, D.buf[0]);
     free_parr(S, D.buf[1]);
-    free_parr(S, D.mig);
     int *olds[] = {D.nf[0], D.nf[1], D.cap, D.mcap};
     for (int *q : olds) dfree(S, q);
     dfree(S, D.off); dfree(S, D.moff);
     dfree(S, newcnt);
     D.buf[0] = nbuf[0];
     D.buf[1] = nbuf[1];
-    D.mig = nmig;
+    D.mig0 = total;
     D.cur = 0;
     D.off = doff;
     D.cap = dcap;
@@ -347,6 +359,9 @@ int ensure_inbox(hk_sim *S, int isp, long long need) {
     if (!alloc_parr(S, D.inbox, c, D.has_z, D.has_tau) || !alloc_parr(S, D.fail, c, D.has_z, D.has_tau))
         return fail(S, HK_ENOMEM, "inbox of %lld", c);
     D.inbox_cap = (int)c;
+    if (!D.inbox_dev) D.inbox_dev = (PArr *)dalloc(S, sizeof(PArr));
+    if (!D.inbox_dev) return fail(S, HK_ENOMEM, "inbox descriptor");
+    HIPCHK(S, hipMemcpyAsync(D.inbox_dev, &D.inbox, sizeof(PArr), hipMemcpyHostToDevice, S->s));
     int capv[1] = {(int)INT_MAX};
     HIPCHK(S, hipMemcpyAsync(D.g_capmax, capv, sizeof(int), hipMemcpyHostToDevice, S->s));
     return HK_OK;
@@ -791,15 +806,15 @@ int one_step(hk_sim *S) {
             launch_zero(D.nf[nxt], sizeof(int) * 3 * g.ntiles, s);
             QedP Q = qed_params(S, mode);
             hipEvent_t pa = S->timing ? ev_get(S) : nullptr;
-            launch_push_tiles(g, P, D.buf[D.cur], cur_bins(D), D.buf[nxt], D.nf[nxt], D.mig, D.moff,
-                              D.mcap, mcnt, D.inbox, S->status + 1 + 2 * isp, D.inbox_cap, S->f,
+            launch_push_tiles(g, P, D.buf[D.cur], cur_bins(D), D.buf[nxt], D.nf[nxt], D.mig0, D.moff,
+                              D.mcap, mcnt, D.inbox_dev, S->status + 1 + 2 * isp, D.inbox_cap, S->f,
                               S->status, S->dstat, S->wmax + isp, D.umax2, mode, Q, S->plan,
                               S->plan_ctl, D.capacity, s);
             if (S->timing) {
                 S->spans.push_back({pa, ev_get(S), 6});
                 S->timers[8] += 1;
             }
-            launch_migrate(g, P, D.mig, D.moff, mcnt, D.mcap, D.buf[nxt], D.nf[nxt], D.nb[nxt],
+            launch_migrate(g, P, shifted(D.buf[nxt], D.mig0), D.moff, mcnt, D.mcap, D.buf[nxt], D.nf[nxt], D.nb[nxt],
                            S->status + 2 + 2 * isp, D.fail, D.inbox_cap, S->status, s);
         } else if (D.d.ionizable && S->run.enable_ionization) {
             DevSpecies &T = S->sp[D.d.target];

@@ -245,8 +245,8 @@ void launch_migrate(const GridP &g, const SpecP &sp, PArr mig, const long long *
                     const int *mcnt, const int *mcap, PArr dst, const int *nf, int *nb, int *fail_n,
                     PArr fail, int fail_cap, int *err, hipStream_t s);
 void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
-                       int *nf_out, PArr mig, const long long *moff, const int *mcap, int *mcnt,
-                       PArr inbox, int *inbox_n, int inbox_cap, real *const f[9], int *err,
+                       int *nf_out, long long mig0, const long long *moff, const int *mcap, int *mcnt,
+                       const PArr *inbox_p, int *inbox_n, int inbox_cap, real *const f[9], int *err,
                        unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
                        int mode, const QedP &Q, int2 *items, int *ctl, long long capacity,
                        hipStream_t s);

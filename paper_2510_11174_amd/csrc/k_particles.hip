@@ -327,9 +327,9 @@ __device__ inline PLoad pload(const PArr &in, const SpecP &sp, long long ip, boo
 // (Breit-Wheeler pair creation, then a ballistic move at c; no current).
 template <int MODE>
 __global__ void __launch_bounds__(PBS)
-k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_out, PArr mig,
+k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_out, long long mig0,
        const long long *__restrict__ moff, const int *__restrict__ mcap, int *__restrict__ mcnt,
-       PArr inbox, int *__restrict__ inbox_n, int inbox_cap, const real *__restrict__ Ex,
+       const PArr *__restrict__ inbox_p, int *__restrict__ inbox_n, int inbox_cap, const real *__restrict__ Ex,
        const real *__restrict__ Ey, const real *__restrict__ Ez, const real *__restrict__ Bx,
        const real *__restrict__ By, const real *__restrict__ Bz, real *__restrict__ Jx,
        real *__restrict__ Jy, real *__restrict__ Jz, int *__restrict__ err,
@@ -581,12 +581,14 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
                 if (sp.has_tau) d.tau[j] = tau;
             };
             const int k = bm + __popcll(mm & lt);
+            // the mover regions follow the bins in the output buffer; the inbox
+            // descriptor is read only when a region overflows
             if (stay) put(out, obase + bs + __popcll(ms & lt));
-            else if (k < mlim) put(mig, mbase + k);
+            else if (k < mlim) put(out, mig0 + mbase + k);
             else {
                 const int q = atomicAdd(inbox_n, 1);
                 if (q >= inbox_cap) atomicOr(err, ERR_INBOX);
-                else put(inbox, q);
+                else put(*inbox_p, q);
             }
         }
         if (MODE != 0) {
@@ -939,12 +941,12 @@ void launch_tile_plan(const GridP &g, const SpecP &sp, Bins b, int cmin, int2 *i
 }
 
 void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
-                       int *nf_out, PArr mig, const long long *moff, const int *mcap, int *mcnt,
-                       PArr inbox, int *inbox_n, int inbox_cap, real *const f[9], int *err,
+                       int *nf_out, long long mig0, const long long *moff, const int *mcap, int *mcnt,
+                       const PArr *inbox_p, int *inbox_n, int inbox_cap, real *const f[9], int *err,
                        unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
                        int mode, const QedP &Q, int2 *items, int *ctl, long long capacity,
                        hipStream_t s) {
-#define HK_PUSH_ARGS g, sp, in, bin_in, out, nf_out, mig, moff, mcap, mcnt, inbox, inbox_n, inbox_cap, \
+#define HK_PUSH_ARGS g, sp, in, bin_in, out, nf_out, mig0, moff, mcap, mcnt, inbox_p, inbox_n, inbox_cap, \
         f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], f[HK_JX], f[HK_JY], f[HK_JZ], err, \
         stats, wmax_bits, umax2, items, ctl, Q
     k_tile_plan<<<1, PLAN_BS, 0, s>>>(g.ntiles, sp, bin_in, PUSH_CHUNK, items, ctl);

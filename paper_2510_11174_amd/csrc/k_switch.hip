@@ -152,18 +152,32 @@ k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__
     }
     __syncthreads();
     const int per = g.bcx == HK_BC_PERIODIC;
+    // nodes 1 .. TILE-1 of a tile that one workgroup covers belong to no other
+    // tile's node block, a plain add (no atomic) suffices, when the tiles
+    // divide every periodic direction into two or more: a partial last tile
+    // would wrap its local nodes onto the first tile's
+    const bool own = nt_ <= chunk && g.ny % TILE == 0 && g.ny > TILE && g.nz % TILE == 0 &&
+                     g.nz > TILE && (!per || (g.nx % TILE == 0 && g.nx > TILE));
     for (int e = threadIdx.x; e < NT3; e += MBS) {
         int aa = e % NT, b = (e / NT) % NT, c = e / (NT * NT);
         int gi = ox + aa, gj = wrapi(oy + b, g.ny), gk = wrapi(oz + c, g.nz);
         if (per) gi = wrapi(gi, g.nx);
         else if (gi > g.nx) continue;
+        const bool inner = own && aa > 0 && aa < TILE && b > 0 && b < TILE && c > 0 && c < TILE;
         long long node = gidx(g, gi, gj, gk);
         if (ion_only) {
-            if (sm[e] != 0) atomicAdd(&mom[6 * g.nn + node], (real)jval(sm[e], scl[0]));
+            if (sm[e] == 0) continue;
+            const real v = (real)jval(sm[e], scl[0]);
+            if (inner) mom[6 * g.nn + node] += v;
+            else atomicAdd(&mom[6 * g.nn + node], v);
             continue;
         }
-        for (int q = 0; q < 6; ++q)
-            if (sm[q * NT3 + e] != 0) atomicAdd(&mom[q * g.nn + node], (real)jval(sm[q * NT3 + e], scl[q]));
+        for (int q = 0; q < 6; ++q) {
+            if (sm[q * NT3 + e] == 0) continue;
+            const real v = (real)jval(sm[q * NT3 + e], scl[q]);
+            if (inner) mom[q * g.nn + node] += v;
+            else atomicAdd(&mom[q * g.nn + node], v);
+        }
     }
 }
 
