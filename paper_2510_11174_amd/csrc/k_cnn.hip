@@ -52,14 +52,17 @@ __device__ inline long long vidx(const Dims &d, int b, int z, int y, int x) {
 // ------------------------------------------------------------------ forward
 // out dims = in dims - 2.  Wf: [NC][kpad] BF16 (co-major), kpad = 27 CIN
 // rounded up to 32 with zeros.  Each wave computes 16 x-voxels of one output
-// row; a workgroup loops over rows.
+// row at a time; a workgroup of 8 waves shares the weight matrix in LDS and
+// loops over rows.  All of a row's A fragments (one 16-byte load per lane and
+// K step) are issued before the first MFMA, so the row's loads overlap.
+constexpr int FBS = 512;
 template <int CIN>
-__global__ void __launch_bounds__(CBS)
+__global__ void __launch_bounds__(FBS)
 k_conv_fwd(Dims in, const unsigned short *__restrict__ act, const unsigned short *__restrict__ Wf,
            const float *__restrict__ bias, float *__restrict__ zout, unsigned short *__restrict__ aout) {
-    constexpr int K = 27 * CIN, KPAD = (K + 31) / 32 * 32;
+    constexpr int K = 27 * CIN, KPAD = (K + 31) / 32 * 32, NK = KPAD / 32;
     __shared__ __attribute__((aligned(16))) unsigned short sW[NC * KPAD];
-    for (int e = threadIdx.x; e < NC * KPAD / 8; e += CBS)
+    for (int e = threadIdx.x; e < NC * KPAD / 8; e += FBS)
         reinterpret_cast<uint4 *>(sW)[e] = reinterpret_cast<const uint4 *>(Wf)[e];
     __syncthreads();
     const Dims out{in.B, in.D - 2, in.H - 2, in.W - 2};
@@ -67,7 +70,9 @@ k_conv_fwd(Dims in, const unsigned short *__restrict__ act, const unsigned short
     const long long nrows = (long long)out.B * out.D * out.H * segs;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
-    for (long long row = (long long)blockIdx.x * 4 + wave; row < nrows; row += (long long)gridDim.x * 4) {
+    const float b0 = bias[r], b1 = bias[16 + r];
+    for (long long row = (long long)blockIdx.x * (FBS / 64) + wave; row < nrows;
+         row += (long long)gridDim.x * (FBS / 64)) {
         const int seg = (int)(row % segs);
         long long q = row / segs;
         const int y = (int)(q % out.H); q /= out.H;
@@ -75,28 +80,38 @@ k_conv_fwd(Dims in, const unsigned short *__restrict__ act, const unsigned short
         const int b = (int)(q / out.D);
         const int x0 = seg * 16;
         const bool xin = x0 + r < out.W;
+        const unsigned short *src = act + vidx(in, b, z, y, x0 + r) * CIN;
         f32x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-        for (int kb = 0; kb < KPAD; kb += 32) {
-            const int k = kb + 8 * g;
-            bf16x8 a;
-            uint4 raw = make_uint4(0, 0, 0, 0);
-            if (xin && k < K) {
-                const int t = k / CIN, ci = k % CIN;
-                const int kx = t % 3, ky = (t / 3) % 3, kz = t / 9;
-                const long long v = vidx(in, b, z + kz, y + ky, x0 + r + kx);
-                raw = *reinterpret_cast<const uint4 *>(act + v * CIN + ci);
+        // K steps in batches of NB: a batch's loads are all in flight at once
+        constexpr int NB = NK % 9 == 0 ? 9 : NK;
+#pragma unroll 1
+        for (int s0 = 0; s0 < NK; s0 += NB) {
+            uint4 av[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int k = (s0 + j) * 32 + 8 * g;
+                av[j] = make_uint4(0, 0, 0, 0);
+                if (xin && k < K) {
+                    const int t = k / CIN, ci = k % CIN;
+                    const int kx = t % 3, ky = (t / 3) % 3, kz = t / 9;
+                    av[j] = *reinterpret_cast<const uint4 *>(src + ((kz * in.H + ky) * in.W + kx) * CIN + ci);
+                }
             }
-            a = __builtin_bit_cast(bf16x8, raw);
-            const bf16x8 w0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + r * KPAD + k));
-            const bf16x8 w1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + (16 + r) * KPAD + k));
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w1, acc1, 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int k = (s0 + j) * 32 + 8 * g;
+                const bf16x8 a = __builtin_bit_cast(bf16x8, av[j]);
+                const bf16x8 w0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + r * KPAD + k));
+                const bf16x8 w1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + (16 + r) * KPAD + k));
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w0, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w1, acc1, 0, 0, 0);
+            }
         }
         for (int i = 0; i < 4; ++i) {
             const int x = x0 + 4 * g + i;
             if (x >= out.W) continue;
             const long long v = vidx(out, b, z, y, x);
-            const float z0 = acc0[i] + bias[r], z1 = acc1[i] + bias[16 + r];
+            const float z0 = acc0[i] + b0, z1 = acc1[i] + b1;
             if (zout) { zout[v * NC + r] = z0; zout[v * NC + 16 + r] = z1; }
             aout[v * NC + r] = bf16_bits(gelu(z0));
             aout[v * NC + 16 + r] = bf16_bits(gelu(z1));
@@ -458,8 +473,12 @@ void cnn_launch_conv_fwd(int cin, int B, int D, int H, int W, const unsigned sho
                          hipStream_t s) {
     Dims in{B, D, H, W};
     const long long rows = (long long)B * (D - 2) * (H - 2) * ((W - 2 + 15) / 16);
-    if (cin == 8) k_conv_fwd<8><<<rows_grid(rows), CBS, 0, s>>>(in, act, Wf, bias, zout, aout);
-    else k_conv_fwd<32><<<rows_grid(rows), CBS, 0, s>>>(in, act, Wf, bias, zout, aout);
+    // two workgroups per CU (the weights fill a third of LDS each), every one
+    // looping over rows: the weight matrix is read once per workgroup
+    long long nb = (rows + FBS / 64 - 1) / (FBS / 64);
+    const unsigned grid = (unsigned)(nb < 512 ? nb : 512);
+    if (cin == 8) k_conv_fwd<8><<<grid, FBS, 0, s>>>(in, act, Wf, bias, zout, aout);
+    else k_conv_fwd<32><<<grid, FBS, 0, s>>>(in, act, Wf, bias, zout, aout);
 }
 
 void cnn_launch_conv_bwd_data(int B, int D, int H, int W, const unsigned short *dz,

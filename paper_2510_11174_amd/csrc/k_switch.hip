@@ -128,15 +128,24 @@ k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__
         scl[q] = (real)(bound[q] / (double)JFIX_UNITS);
     }
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
-    for (int p = p0 + threadIdx.x; p < n; p += MBS) {
-        // every field of the slot at once: no load waits on another
+    // every field of a slot at once (no load waits on another), one iteration
+    // ahead of its use
+    int n_cell = -1, n_zc = 0;
+    real n_rx = 0, n_ry = 0, n_rz = 0, n_w = 0, n_ux = 0, n_uy = 0, n_uz = 0;
+    auto ld = [&](int p) {
+        n_cell = -1;
+        if (p >= n) return;
         const long long ip = bin_slot(sp, t, p, nf, nbv);
-        const int cell = a.cell[ip];
-        const real rx = a.rx[ip], ry = a.ry[ip], rz = a.rz[ip], w = a.w[ip];
-        real ux = 0, uy = 0, uz = 0;
-        int zc = 0;
-        if (ion_only) zc = a.zc[ip];
-        else { ux = a.ux[ip]; uy = a.uy[ip]; uz = a.uz[ip]; }
+        n_cell = a.cell[ip];
+        n_rx = a.rx[ip]; n_ry = a.ry[ip]; n_rz = a.rz[ip]; n_w = a.w[ip];
+        if (ion_only) n_zc = a.zc[ip];
+        else { n_ux = a.ux[ip]; n_uy = a.uy[ip]; n_uz = a.uz[ip]; }
+    };
+    ld(p0 + threadIdx.x);
+    for (int p = p0 + threadIdx.x; p < n; p += MBS) {
+        const int cell = n_cell, zc = n_zc;
+        const real rx = n_rx, ry = n_ry, rz = n_rz, w = n_w, ux = n_ux, uy = n_uy, uz = n_uz;
+        ld(p + MBS);
         if (cell < 0) continue;
         int ci, cj, ck;
         cell_ijk(g, cell, ci, cj, ck);
