@@ -178,6 +178,20 @@ bool alloc_parr(hk_sim *S, PArr &a, long long n, int has_z, int has_tau) {
     return true;
 }
 
+// Every field of b at the same byte distance from that of a.
+bool same_layout(const PArr &a, const PArr &b) {
+    const char *pa[] = {(const char *)a.rx, (const char *)a.ry, (const char *)a.rz, (const char *)a.ux,
+                        (const char *)a.uy, (const char *)a.uz, (const char *)a.w, (const char *)a.id,
+                        (const char *)a.zc, (const char *)a.tau};
+    const char *pb[] = {(const char *)b.rx, (const char *)b.ry, (const char *)b.rz, (const char *)b.ux,
+                        (const char *)b.uy, (const char *)b.uz, (const char *)b.w, (const char *)b.id,
+                        (const char *)b.zc, (const char *)b.tau};
+    const long long d = (const char *)b.cell - (const char *)a.cell;
+    for (int k = 0; k < 10; ++k)
+        if ((pa[k] == nullptr) != (pb[k] == nullptr) || (pa[k] && pb[k] - pa[k] != d)) return false;
+    return true;
+}
+
 // The same arrays from slot k on.
 PArr shifted(const PArr &a, long long k) {
     PArr v = a;
@@ -284,6 +298,9 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     if (!alloc_parr(S, nbuf[0], slots, D.has_z, D.has_tau) ||
         !alloc_parr(S, nbuf[1], slots, D.has_z, D.has_tau))
         return fail(S, HK_ENOMEM, "rebuild: %lld particle slots", slots);
+    // the push addresses its output through the input's field pointers plus
+    // one byte distance: both buffers must have the same layout
+    if (!same_layout(nbuf[0], nbuf[1])) return fail(S, HK_ENOMEM, "rebuild: buffer layouts differ");
     long long *doff = (long long *)dalloc(S, sizeof(long long) * nt);
     long long *dmoff = (long long *)dalloc(S, sizeof(long long) * nt);
     int *dcap = (int *)dalloc(S, sizeof(int) * nt);
@@ -801,9 +818,9 @@ int one_step(hk_sim *S) {
         if (D.d.mobile) {
             int nxt = 1 - D.cur;
             // front and back fills of the next buffer and the mover ranks start
-            // at zero: several push workgroups share a dense tile
+            // at zero (cleared by the push's planner): several push workgroups
+            // share a dense tile
             int *mcnt = D.nf[nxt] + 2 * g.ntiles;
-            launch_zero(D.nf[nxt], sizeof(int) * 3 * g.ntiles, s);
             QedP Q = qed_params(S, mode);
             hipEvent_t pa = S->timing ? ev_get(S) : nullptr;
             launch_push_tiles(g, P, D.buf[D.cur], cur_bins(D), D.buf[nxt], D.nf[nxt], D.mig0, D.moff,

@@ -266,9 +266,13 @@ constexpr int PLAN_BS = 1024;
 // ctl[0] = number of items; items sorted by decreasing chunk size through 32
 // power-of-two buckets.
 __global__ void __launch_bounds__(PLAN_BS)
-k_tile_plan(int ntiles, SpecP sp, Bins bins, int cmin, int2 *__restrict__ items, int *__restrict__ ctl) {
+k_tile_plan(int ntiles, SpecP sp, Bins bins, int cmin, int2 *__restrict__ items, int *__restrict__ ctl,
+            int *__restrict__ zero3) {
     __shared__ int cnt[32], cur[32];
     if (threadIdx.x < 32) cnt[threadIdx.x] = 0;
+    // the push's output counters (3 ntiles ints), cleared here to save a launch
+    if (zero3)
+        for (int t = threadIdx.x; t < 3 * ntiles; t += PLAN_BS) zero3[t] = 0;
     __syncthreads();
     for (int t = threadIdx.x; t < ntiles; t += PLAN_BS) {
         int nfi, nbi;
@@ -327,7 +331,7 @@ __device__ inline PLoad pload(const PArr &in, const SpecP &sp, long long ip, boo
 // (Breit-Wheeler pair creation, then a ballistic move at c; no current).
 template <int MODE>
 __global__ void __launch_bounds__(PBS)
-k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_out, long long mig0,
+k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict__ nf_out, long long mig0,
        const long long *__restrict__ moff, const int *__restrict__ mcap, int *__restrict__ mcnt,
        const PArr *__restrict__ inbox_p, int *__restrict__ inbox_n, int inbox_cap, const real *__restrict__ Ex,
        const real *__restrict__ Ey, const real *__restrict__ Ez, const real *__restrict__ Bx,
@@ -580,11 +584,25 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, PArr out, int *__restrict__ nf_o
                 if (sp.has_z) d.zc[j] = zc;
                 if (sp.has_tau) d.tau[j] = tau;
             };
+            // the output buffer has the input's layout, dout bytes further:
+            // its stores reuse the input's field pointers (fewer live SGPRs)
+            auto put_out = [&](long long j) {
+                const long long o4 = j * 4 + dout, or_ = j * (long long)sizeof(real) + dout, o8 = j * 8 + dout;
+                *(int *)((char *)in.cell + o4) = ncell;
+                *(real *)((char *)in.rx + or_) = nrx; *(real *)((char *)in.ry + or_) = nry;
+                *(real *)((char *)in.rz + or_) = nrz;
+                *(real *)((char *)in.ux + or_) = ux; *(real *)((char *)in.uy + or_) = uy;
+                *(real *)((char *)in.uz + or_) = uz;
+                *(real *)((char *)in.w + or_) = w;
+                *(uint64_t *)((char *)in.id + o8) = id;
+                if (sp.has_z) *(int *)((char *)in.zc + o4) = zc;
+                if (sp.has_tau) *(double *)((char *)in.tau + o8) = tau;
+            };
             const int k = bm + __popcll(mm & lt);
             // the mover regions follow the bins in the output buffer; the inbox
             // descriptor is read only when a region overflows
-            if (stay) put(out, obase + bs + __popcll(ms & lt));
-            else if (k < mlim) put(out, mig0 + mbase + k);
+            if (stay) put_out(obase + bs + __popcll(ms & lt));
+            else if (k < mlim) put_out(mig0 + mbase + k);
             else {
                 const int q = atomicAdd(inbox_n, 1);
                 if (q >= inbox_cap) atomicOr(err, ERR_INBOX);
@@ -937,7 +955,7 @@ unsigned tile_plan_grid(const GridP &g, long long capacity, int cmin) {
 
 void launch_tile_plan(const GridP &g, const SpecP &sp, Bins b, int cmin, int2 *items, int *ctl,
                       hipStream_t s) {
-    k_tile_plan<<<1, PLAN_BS, 0, s>>>(g.ntiles, sp, b, cmin, items, ctl);
+    k_tile_plan<<<1, PLAN_BS, 0, s>>>(g.ntiles, sp, b, cmin, items, ctl, nullptr);
 }
 
 void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
@@ -946,10 +964,15 @@ void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PA
                        unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
                        int mode, const QedP &Q, int2 *items, int *ctl, long long capacity,
                        hipStream_t s) {
-#define HK_PUSH_ARGS g, sp, in, bin_in, out, nf_out, mig0, moff, mcap, mcnt, inbox_p, inbox_n, inbox_cap, \
+#define HK_PUSH_ARGS g, sp, in, bin_in, dout, nf_out, mig0, moff, mcap, mcnt, inbox_p, inbox_n, inbox_cap, \
         f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], f[HK_JX], f[HK_JY], f[HK_JZ], err, \
         stats, wmax_bits, umax2, items, ctl, Q
-    k_tile_plan<<<1, PLAN_BS, 0, s>>>(g.ntiles, sp, bin_in, PUSH_CHUNK, items, ctl);
+    // nf_out is the first of the next buffer's three counter arrays (front
+    // fills, back fills, mover ranks), cleared by the planner
+    k_tile_plan<<<1, PLAN_BS, 0, s>>>(g.ntiles, sp, bin_in, PUSH_CHUNK, items, ctl, nf_out);
+    // the two bin buffers share one layout (checked when they are allocated):
+    // every field of `out` sits the same byte distance from that of `in`
+    const long long dout = (const char *)out.cell - (const char *)in.cell;
     const unsigned grid = tile_plan_grid(g, capacity, PUSH_CHUNK);
     if (mode == 1) k_push<1><<<grid, PBS, 0, s>>>(HK_PUSH_ARGS);
     else if (mode == 2) k_push<2><<<grid, PBS, 0, s>>>(HK_PUSH_ARGS);
