@@ -267,19 +267,22 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     HIPCHK(S, hipMemcpyAsync(h.data(), newcnt, sizeof(int) * nt, hipMemcpyDeviceToHost, S->s));
     HIPCHK(S, hipStreamSynchronize(S->s));
     // capacity: three times the larger of the tile's count and the species'
-    // mean count per tile, plus 256 slots, at least the reserve hint share.
-    // Local density spikes (a laser snow-plough) then rarely overflow a bin;
-    // spare slots cost memory only, never traffic (kernels touch occupied slots).
+    // mean count per tile, plus 256 slots, at least the reserve hint share;
+    // twice when the species is large (two buffers of three times 2^28
+    // particles take about a quarter of the 288 GB HBM).  Local density spikes (a laser
+    // snow-plough) then rarely overflow a bin; spare slots cost memory only,
+    // never traffic (kernels touch occupied slots).
     long long hint_per_tile = D.reserve_hint > 0 ? (D.reserve_hint + nt - 1) / nt : 0;
     long long hsum = 0;
     for (int t = 0; t < nt; ++t) hsum += h[t];
     const long long mean = (hsum + nt - 1) / nt;
+    const long long factor = std::max(hsum, D.reserve_hint) > (1LL << 28) ? 2 : 3;
     std::vector<long long> off(nt), moff(nt);
     std::vector<int> cap(nt), mcap(nt);
     long long total = 0, mtotal = 0;
     int maxc = 0;
     for (int t = 0; t < nt; ++t) {
-        long long c = 3 * std::max<long long>(h[t], mean) + 256;
+        long long c = factor * std::max<long long>(h[t], mean) + 256;
         long long hc = hint_per_tile + hint_per_tile / 4 + 128;
         c = std::max(c, std::min<long long>(hc, INT_MAX / 4));
         c = (c + 63) & ~63LL;
@@ -588,6 +591,18 @@ long long inbox_need(hk_sim *S, int isp) {
     return need;
 }
 
+// Whether kernels of a step can send particles to species isp's inbox: its own
+// push (overflowing mover regions), ionization of ions that target it, QED
+// products, or fluid-to-particle spawning.
+bool receives(const hk_sim *S, int isp) {
+    const DevSpecies &D = S->sp[isp];
+    if (D.d.mobile) return true;
+    if (D.d.fluid && S->run.switch_mode != HK_SW_ALL_PIC) return true;
+    for (int j = 0; j < S->nsp; ++j)
+        if (S->sp[j].d.ionizable && S->sp[j].d.target == isp && S->run.enable_ionization) return true;
+    return S->run.enable_qed && (isp == S->photon_sp || isp == S->electron_sp || isp == S->positron_sp);
+}
+
 // Append every species' inbox to the back of its current bins and start the
 // copy of the device status to the host (merge_launch); work that does not
 // touch the particle bins may be enqueued before merge_finish waits for the
@@ -595,7 +610,7 @@ long long inbox_need(hk_sim *S, int isp) {
 int merge_launch(hk_sim *S) {
     for (int isp = 0; isp < S->nsp; ++isp) {
         DevSpecies &D = S->sp[isp];
-        if (D.capacity == 0) continue;
+        if (D.capacity == 0 || !receives(S, isp)) continue;
         SpecP P = specp(D);
         int *inbox_n = S->status + 1 + 2 * isp, *fail_n = S->status + 2 + 2 * isp;
         launch_merge_inbox(S->g, P, D.inbox, inbox_n, D.inbox_cap, D.buf[D.cur], D.nf[D.cur],

@@ -110,6 +110,31 @@ def test_threshold_hybrid_plain(hk, oracle_mod, prec):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_threshold_dense_tiles(hk, oracle_mod, prec):
+    # 40 particles per cell (20480 per tile): the first evaluation sums the
+    # tile moments with several workgroups per tile (the tiles divide y and z
+    # exactly, so tile-interior nodes take plain adds) and the first push
+    # splits every tile; u_th 0.005 leaves about a fifth of the nodes kinetic
+    cfg = configs.plain_hybrid(16, 16, 16, mode="threshold")
+    cfg["species"][0]["ppc"] = 40
+    cfg["species"][0]["u_th"] = 0.005
+    cfg["laser"]["enabled"] = False
+    g, o = _pair(hk, oracle_mod, cfg, prec)
+    for n in range(3):
+        g.step(5); o.step(5)
+        mg, mo = g.get_switch(), o.get_switch()
+        frac = (mg != mo).mean()
+        print("step %d kinetic %.3f / %.3f mismatch %.2e" % (5 * n + 5, mg.mean(), mo.mean(), frac))
+        assert frac <= (1e-3 if prec == "f32" else 0.0)
+        if n == 0:
+            assert 0.05 < mo.mean() < 0.95
+    vec = {f: rel_l2(np.stack([g.get_field(f + c) for c in "xyz"]),
+                     np.stack([o.get_field(f + c) for c in "xyz"])) for f in "eb"}
+    print(vec)
+    assert max(vec.values()) <= (1e-3 if prec == "f32" else 1e-10)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("mode", ["all_pic", "threshold"])
 def test_ionization_events(hk, oracle_mod, prec, mode):
     # ionizing helium (a0 = 10): which atoms ionize, and to which level, is

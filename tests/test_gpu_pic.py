@@ -102,6 +102,27 @@ def test_gauss_law_preserved(hk, oracle_mod, prec):
     assert abs(d["charge_total"] + 0.01 * 16 * 8 * 8 * 0.2 ** 3) <= 1e-6 * 0.01
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_dense_tiles_split_over_workgroups(hk, oracle_mod, prec):
+    # 40 particles per cell make 20480 per 8^3 tile: the push splits every tile
+    # into three work items whose workgroups rank stayers and movers through
+    # the tile's global counters; hot electrons cross cells and tiles
+    cfg = _c1(bc="periodic", laser=True, u_th=0.2, nx=16, ny=16, nz=16)
+    cfg["species"][0]["ppc"] = 40
+    g, o = _pair(hk, oracle_mod, cfg, prec)
+    rng = np.random.default_rng(11)
+    for c in ["ex", "ey", "ez", "bx", "by", "bz"]:
+        a = rng.normal(0, 0.05, o.shape)
+        g.set_field(c, a.astype(g.real)); o.set_field(c, a.astype(g.real).astype(np.float64))
+    g.step(2); o.step(2)
+    assert g.count(0) == o.count(0) == 40 * 16 ** 3
+    pos, mom, w = particle_errors(g.get_particles(0), o.get_particles(0), _dx(cfg), _box(cfg))
+    errs = field_errors(g, o)
+    print("pos %.2e mom %.2e" % (pos, mom), {k: "%.1e" % v for k, v in errs.items()})
+    tol = 2e-5 if prec == "f32" else 1e-12
+    assert pos <= tol and mom <= tol and max(errs.values()) <= tol
+
+
 def test_ragged_tiles_and_tiny_box(hk, oracle_mod):
     # nx, ny, nz not multiples of the 8-cell tile; ny = 4 wraps inside one tile
     cfg = _c1(bc="open", laser=True, u_th=0.3, nx=20, ny=4, nz=12)
