@@ -225,6 +225,24 @@ int hk_set_fluid(hk_sim *sim, int species, const double *n, const double *u, siz
 int hk_enable_timing(hk_sim *sim, int on);
 int hk_timers(hk_sim *sim, double *ms, int n);
 
+/* Checkpoint and resume.  hk_save writes the whole state a step depends on:
+ * fields (E, B, J), the Mur boundary planes, the switch map and its calm
+ * counters, the energy ledgers, the species weight bounds, the Gauss
+ * baseline, the CNN evaluation count, every species' particles in the
+ * library's own representation (cell, cell-relative offsets, u, w, id, z,
+ * tau) and fluid arrays, the step counter and the time.  hk_load restores it
+ * into a context created with the same descriptors (grid, species kinds,
+ * precision: HK_EINVAL otherwise, nothing changed); particles are re-binned,
+ * so a resumed run draws the same Philox numbers (counters are id, step and
+ * tag) and takes the same decisions as an uninterrupted one.  An attached
+ * CNN is not part of the file: save it with hk_cnn_get_params.  The path is
+ * borrowed for the call; file errors return HK_EIO.  A failed hk_load may
+ * leave a partly restored state.
+ * Paper: Methodology (keeping code, parameters and outputs together for
+ * reproducible runs). */
+int hk_save(hk_sim *sim, const char *path);
+int hk_load(hk_sim *sim, const char *path);
+
 /* The QED tables the library built (host FP64, independent of any context):
  * We[256] and Wb[256] are the emission and pair spectra integrated over the
  * energy fraction at chi_i = 10^(-3 + 6 i / 255); Xe and Xb [256 * 128], row

@@ -944,6 +944,92 @@ bool check_grid(const hk_grid_desc *g) {
            g->dt < 1.0 / std::sqrt(1.0 / (g->dx * g->dx) + 1.0 / (g->dy * g->dy) + 1.0 / (g->dz * g->dz));
 }
 
+// Host copy of the valid slots of a species' current bins, in storage order.
+int valid_slots(hk_sim *S, DevSpecies &D, std::vector<long long> &slots) {
+    slots.clear();
+    if (D.capacity == 0) return HK_OK;
+    const int nt = S->g.ntiles;
+    std::vector<int> nf(nt), nb(nt), cells((size_t)D.capacity);
+    HIPCHK(S, hipMemcpyAsync(nf.data(), D.nf[D.cur], sizeof(int) * nt, hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipMemcpyAsync(nb.data(), D.nb[D.cur], sizeof(int) * nt, hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipMemcpyAsync(cells.data(), D.buf[D.cur].cell, sizeof(int) * D.capacity,
+                             hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    for (int t = 0; t < nt; ++t) {
+        int c = D.h_cap[t];
+        int f = std::min(nf[t], c), b = std::min(nb[t], c - f);
+        for (int p = 0; p < f + b; ++p) {
+            long long i = D.h_off[t] + (p < f ? p : c - b + (p - f));
+            if (cells[i] >= 0) slots.push_back(i);
+        }
+    }
+    return HK_OK;
+}
+
+// Replace species isp's particles by n particles in the library's own
+// representation (cell, offsets, u, w, id, z, tau) and re-bin them.
+int upload_particles(hk_sim *S, int isp, size_t n, const std::vector<int> &cell, const std::vector<real> r[7],
+                     const std::vector<uint64_t> &id, const std::vector<int> &zc, const std::vector<double> &tau,
+                     double wm) {
+    DevSpecies &D = S->sp[isp];
+    D.umax_ok = false;
+    int rc = ensure_inbox(S, isp, (long long)n + 1024);
+    if (rc) return rc;
+    rc = raise_wmax(S, isp, wm);
+    if (rc) return rc;
+    const PArr &a = D.inbox;
+    hipStream_t s = S->s;
+    if (n) {
+        HIPCHK(S, hipMemcpyAsync(a.cell, cell.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+        real *dst[7] = {a.rx, a.ry, a.rz, a.ux, a.uy, a.uz, a.w};
+        for (int k = 0; k < 7; ++k)
+            HIPCHK(S, hipMemcpyAsync(dst[k], r[k].data(), sizeof(real) * n, hipMemcpyHostToDevice, s));
+        HIPCHK(S, hipMemcpyAsync(a.id, id.data(), sizeof(uint64_t) * n, hipMemcpyHostToDevice, s));
+        if (D.has_z) HIPCHK(S, hipMemcpyAsync(a.zc, zc.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+        if (D.has_tau) HIPCHK(S, hipMemcpyAsync(a.tau, tau.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+    }
+    int n32 = (int)n;
+    HIPCHK(S, hipMemcpyAsync(S->status + 1 + 2 * isp, &n32, sizeof(int), hipMemcpyHostToDevice, s));
+    int *ln = S->status + 1 + 2 * isp;
+    PArr lists[1] = {D.inbox};
+    long long lmax[1] = {(long long)n};
+    rc = rebuild(S, isp, false, lists, &ln, lmax, 1);
+    if (rc) return rc;
+    HIPCHK(S, hipMemsetAsync(S->status + 1 + 2 * isp, 0, sizeof(int), s));
+    HIPCHK(S, hipStreamSynchronize(s));
+    return ensure_inbox(S, isp, inbox_need(S, isp));
+}
+
+constexpr uint32_t CK_MAGIC = 0x4b434b48u;   // "HKCK"
+constexpr uint32_t CK_VERSION = 1;
+
+struct CkFile {
+    FILE *f = nullptr;
+    bool ok = true;
+    ~CkFile() { if (f) fclose(f); }
+    void put(const void *p, size_t n) { if (ok && n && fwrite(p, 1, n, f) != n) ok = false; }
+    void get(void *p, size_t n) { if (ok && n && fread(p, 1, n, f) != n) ok = false; }
+    template <class T> void put(const T &v) { put(&v, sizeof(T)); }
+    template <class T> void get(T &v) { get(&v, sizeof(T)); }
+};
+
+// device -> file and file -> device through a host buffer
+int ck_dev_out(hk_sim *S, CkFile &F, const void *dev, size_t bytes) {
+    std::vector<char> h(bytes);
+    if (bytes) HIPCHK(S, hipMemcpyAsync(h.data(), dev, bytes, hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    F.put(h.data(), bytes);
+    return HK_OK;
+}
+int ck_dev_in(hk_sim *S, CkFile &F, void *dev, size_t bytes) {
+    std::vector<char> h(bytes);
+    F.get(h.data(), bytes);
+    if (!F.ok) return fail(S, HK_EIO, "checkpoint: file ends early");
+    if (bytes) HIPCHK(S, hipMemcpyAsync(dev, h.data(), bytes, hipMemcpyHostToDevice, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    return HK_OK;
+}
+
 }  // namespace
 
 // ====================================================================== ABI ===============
@@ -1260,27 +1346,6 @@ int hk_get_divE(hk_sim *S, double *host_out, size_t n) {
     return HK_OK;
 }
 
-// Host copy of the valid slots of a species' current bins, in storage order.
-int valid_slots(hk_sim *S, DevSpecies &D, std::vector<long long> &slots) {
-    slots.clear();
-    if (D.capacity == 0) return HK_OK;
-    const int nt = S->g.ntiles;
-    std::vector<int> nf(nt), nb(nt), cells((size_t)D.capacity);
-    HIPCHK(S, hipMemcpyAsync(nf.data(), D.nf[D.cur], sizeof(int) * nt, hipMemcpyDeviceToHost, S->s));
-    HIPCHK(S, hipMemcpyAsync(nb.data(), D.nb[D.cur], sizeof(int) * nt, hipMemcpyDeviceToHost, S->s));
-    HIPCHK(S, hipMemcpyAsync(cells.data(), D.buf[D.cur].cell, sizeof(int) * D.capacity,
-                             hipMemcpyDeviceToHost, S->s));
-    HIPCHK(S, hipStreamSynchronize(S->s));
-    for (int t = 0; t < nt; ++t) {
-        int c = D.h_cap[t];
-        int f = std::min(nf[t], c), b = std::min(nb[t], c - f);
-        for (int p = 0; p < f + b; ++p) {
-            long long i = D.h_off[t] + (p < f ? p : c - b + (p - f));
-            if (cells[i] >= 0) slots.push_back(i);
-        }
-    }
-    return HK_OK;
-}
 
 int hk_particle_count(hk_sim *S, int isp, size_t *n) {
     if (!S || !n || isp < 0 || isp >= S->nsp) return HK_EINVAL;
@@ -1371,36 +1436,13 @@ int hk_set_particles(hk_sim *S, int isp, const hk_particles *in) {
         if (in->tau) tau[q] = in->tau[q];
         else if (D.has_tau) tau[q] = tau0(S->run.seed, id[q]);   // as a new particle draws it
     }
-    int rc = ensure_inbox(S, isp, (long long)n + 1024);
-    if (rc) return rc;
     double wm = 0;
     for (size_t q = 0; q < n; ++q) wm = std::max(wm, std::fabs(in->w[q]));
-    rc = raise_wmax(S, isp, wm);
-    if (rc) return rc;
-    const PArr &a = D.inbox;
-    hipStream_t s = S->s;
-    if (n) {
-        HIPCHK(S, hipMemcpyAsync(a.cell, cell.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
-        real *dst[7] = {a.rx, a.ry, a.rz, a.ux, a.uy, a.uz, a.w};
-        for (int k = 0; k < 7; ++k)
-            HIPCHK(S, hipMemcpyAsync(dst[k], r[k].data(), sizeof(real) * n, hipMemcpyHostToDevice, s));
-        HIPCHK(S, hipMemcpyAsync(a.id, id.data(), sizeof(uint64_t) * n, hipMemcpyHostToDevice, s));
-        if (D.has_z) HIPCHK(S, hipMemcpyAsync(a.zc, zc.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
-        if (D.has_tau) HIPCHK(S, hipMemcpyAsync(a.tau, tau.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
-    }
-    int n32 = (int)n;
-    HIPCHK(S, hipMemcpyAsync(S->status + 1 + 2 * isp, &n32, sizeof(int), hipMemcpyHostToDevice, s));
-    int *ln = S->status + 1 + 2 * isp;
-    PArr lists[1] = {D.inbox};
-    long long lmax[1] = {(long long)n};
-    rc = rebuild(S, isp, false, lists, &ln, lmax, 1);
-    if (rc) return rc;
-    HIPCHK(S, hipMemsetAsync(S->status + 1 + 2 * isp, 0, sizeof(int), s));
-    HIPCHK(S, hipStreamSynchronize(s));
-    rc = ensure_inbox(S, isp, inbox_need(S, isp));
+    int rc = upload_particles(S, isp, n, cell, r, id, zc, tau, wm);
     S->have_gauss0 = 0;
     return rc;
 }
+
 
 int hk_get_fluid(hk_sim *S, int isp, double *n, double *u, size_t nodes) {
     if (!S || !n || !u || isp < 0 || isp >= S->nsp || nodes != (size_t)S->g.nn) return HK_EINVAL;
@@ -1526,6 +1568,149 @@ int hk_diagnostics(hk_sim *S, hk_diag *d) {
             d->fallback_fraction = 1.0;   // no network: every node decided by the thresholds
         }
     }
+    return HK_OK;
+}
+
+
+// ------------------------------------------------------------------ checkpoint ----------
+// File: "HKCK", version, real size, grid and species kinds (checked on load),
+// step and time, then fixed sections in order: the 9 field components, the
+// Mur planes, switch map and calm counters, ledgers, species weight bounds,
+// the Gauss baseline, CNN evaluation count, then per species the particles
+// (count, then cell, offsets, u, w, id, z, tau in the library's own layout)
+// and the fluid (n, u) when the species has one.  Little endian, as written.
+
+int hk_save(hk_sim *S, const char *path) {
+    if (!S || !path) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    ev_resolve(S);
+    CkFile F;
+    F.f = fopen(path, "wb");
+    if (!F.f) return fail(S, HK_EIO, "checkpoint: cannot open %s for writing", path);
+    const GridP &g = S->g;
+    F.put(CK_MAGIC); F.put(CK_VERSION); F.put((uint32_t)sizeof(real));
+    F.put(g.nx); F.put(g.ny); F.put(g.nz); F.put(S->nsp);
+    for (int i = 0; i < S->nsp; ++i) F.put(S->sp[i].d.kind);
+    F.put(S->step); F.put(S->t); F.put(S->have_gauss0);
+    int rc;
+    if ((rc = ck_dev_out(S, F, S->fblock, sizeof(real) * 9 * (size_t)g.nn))) return rc;
+    if ((rc = ck_dev_out(S, F, S->mur_old, sizeof(real) * 8 * (size_t)g.ny * g.nz))) return rc;
+    if ((rc = ck_dev_out(S, F, S->sw, (size_t)g.nn))) return rc;
+    if ((rc = ck_dev_out(S, F, S->calm, (size_t)g.nn))) return rc;
+    if ((rc = ck_dev_out(S, F, S->ledger, sizeof(double) * 8))) return rc;
+    if ((rc = ck_dev_out(S, F, S->wmax, sizeof(unsigned) * (HK_MAX_SPECIES + 1)))) return rc;
+    if ((rc = ck_dev_out(S, F, S->gauss0, S->have_gauss0 ? sizeof(double) * (size_t)g.nn : 0))) return rc;
+    F.put(S->cnn_evals);
+    for (int isp = 0; isp < S->nsp; ++isp) {
+        DevSpecies &D = S->sp[isp];
+        std::vector<long long> slots;
+        if ((rc = valid_slots(S, D, slots))) return rc;
+        const uint64_t n = slots.size();
+        F.put(n);
+        const long long C = D.capacity;
+        const PArr &a = D.buf[D.cur];
+        // one field at a time: copy the whole buffer, keep the valid slots
+        auto field = [&](const void *dev, size_t esz) -> int {
+            std::vector<char> h((size_t)C * esz), o((size_t)n * esz);
+            if (C) HIPCHK(S, hipMemcpyAsync(h.data(), dev, (size_t)C * esz, hipMemcpyDeviceToHost, S->s));
+            HIPCHK(S, hipStreamSynchronize(S->s));
+            for (uint64_t q = 0; q < n; ++q) memcpy(&o[q * esz], &h[(size_t)slots[q] * esz], esz);
+            F.put(o.data(), o.size());
+            return HK_OK;
+        };
+        if ((rc = field(a.cell, sizeof(int)))) return rc;
+        const real *rs[7] = {a.rx, a.ry, a.rz, a.ux, a.uy, a.uz, a.w};
+        for (const real *r : rs)
+            if ((rc = field(r, sizeof(real)))) return rc;
+        if ((rc = field(a.id, sizeof(uint64_t)))) return rc;
+        if (D.has_z && (rc = field(a.zc, sizeof(int)))) return rc;
+        if (D.has_tau && (rc = field(a.tau, sizeof(double)))) return rc;
+        const int has_fluid = D.fn != nullptr;
+        F.put(has_fluid);
+        if (has_fluid) {
+            real *fl[4] = {D.fn, D.fu[0], D.fu[1], D.fu[2]};
+            for (real *q : fl)
+                if ((rc = ck_dev_out(S, F, q, sizeof(real) * (size_t)g.nn))) return rc;
+        }
+    }
+    if (!F.ok) return fail(S, HK_EIO, "checkpoint: write to %s failed", path);
+    return HK_OK;
+}
+
+int hk_load(hk_sim *S, const char *path) {
+    if (!S || !path) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    ev_resolve(S);
+    CkFile F;
+    F.f = fopen(path, "rb");
+    if (!F.f) return fail(S, HK_EIO, "checkpoint: cannot open %s", path);
+    const GridP &g = S->g;
+    uint32_t magic = 0, version = 0, rsz = 0;
+    int nx = 0, ny = 0, nz = 0, nsp = 0;
+    F.get(magic); F.get(version); F.get(rsz);
+    F.get(nx); F.get(ny); F.get(nz); F.get(nsp);
+    if (!F.ok || magic != CK_MAGIC || version != CK_VERSION)
+        return fail(S, HK_EIO, "checkpoint: %s is not a checkpoint of this version", path);
+    if (rsz != sizeof(real) || nx != g.nx || ny != g.ny || nz != g.nz || nsp != S->nsp)
+        return fail(S, HK_EINVAL, "checkpoint: precision, grid or species count differ from this context");
+    for (int i = 0; i < nsp; ++i) {
+        int kind = -1;
+        F.get(kind);
+        if (kind != S->sp[i].d.kind) return fail(S, HK_EINVAL, "checkpoint: species %d has another kind", i);
+    }
+    int64_t step = 0;
+    double t = 0;
+    int have_g0 = 0;
+    F.get(step); F.get(t); F.get(have_g0);
+    int rc;
+    if ((rc = ck_dev_in(S, F, S->fblock, sizeof(real) * 9 * (size_t)g.nn))) return rc;
+    if ((rc = ck_dev_in(S, F, S->mur_old, sizeof(real) * 8 * (size_t)g.ny * g.nz))) return rc;
+    if ((rc = ck_dev_in(S, F, S->sw, (size_t)g.nn))) return rc;
+    if ((rc = ck_dev_in(S, F, S->calm, (size_t)g.nn))) return rc;
+    if ((rc = ck_dev_in(S, F, S->ledger, sizeof(double) * 8))) return rc;
+    std::vector<unsigned> wmax(HK_MAX_SPECIES + 1);
+    F.get(wmax.data(), sizeof(unsigned) * wmax.size());
+    if ((rc = ck_dev_in(S, F, S->gauss0, have_g0 ? sizeof(double) * (size_t)g.nn : 0))) return rc;
+    uint32_t evals = 0;
+    F.get(evals);
+    for (int isp = 0; isp < nsp; ++isp) {
+        DevSpecies &D = S->sp[isp];
+        uint64_t n = 0;
+        F.get(n);
+        if (!F.ok || n > (uint64_t)INT_MAX) return fail(S, HK_EIO, "checkpoint: bad particle count");
+        std::vector<int> cell(n), zc(n);
+        std::vector<real> r[7];
+        std::vector<uint64_t> id(n);
+        std::vector<double> tau(n, 0.0);
+        F.get(cell.data(), sizeof(int) * n);
+        for (auto &v : r) { v.resize(n); F.get(v.data(), sizeof(real) * n); }
+        F.get(id.data(), sizeof(uint64_t) * n);
+        if (D.has_z) F.get(zc.data(), sizeof(int) * n);
+        if (D.has_tau) F.get(tau.data(), sizeof(double) * n);
+        if (!F.ok) return fail(S, HK_EIO, "checkpoint: file ends early");
+        for (uint64_t q = 0; q < n; ++q)
+            if (cell[q] < 0 || cell[q] >= g.nx * g.ny * g.nz) return fail(S, HK_EIO, "checkpoint: bad cell");
+        double wm = 0;
+        for (uint64_t q = 0; q < n; ++q) wm = std::max(wm, std::fabs((double)r[6][q]));
+        if ((rc = upload_particles(S, isp, n, cell, r, id, zc, tau, wm))) return rc;
+        int has_fluid = 0;
+        F.get(has_fluid);
+        if (has_fluid) {
+            if ((rc = ensure_fluid(S))) return rc;
+            if (!D.fn) return fail(S, HK_EINVAL, "checkpoint: species %d has a fluid here only in the file", isp);
+            real *fl[4] = {D.fn, D.fu[0], D.fu[1], D.fu[2]};
+            for (real *q : fl)
+                if ((rc = ck_dev_in(S, F, q, sizeof(real) * (size_t)g.nn))) return rc;
+        }
+    }
+    if (!F.ok) return fail(S, HK_EIO, "checkpoint: file ends early");
+    // weight bounds exactly as saved (they set the fixed-point scales)
+    HIPCHK(S, hipMemcpyAsync(S->wmax, wmax.data(), sizeof(unsigned) * wmax.size(), hipMemcpyHostToDevice, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    S->step = step;
+    S->t = t;
+    S->have_gauss0 = have_g0;
+    S->cnn_evals = evals;
     return HK_OK;
 }
 

@@ -103,7 +103,7 @@ ABI_SYMBOLS = ["hk_create", "hk_destroy", "hk_step", "hk_switch_map", "hk_set_sw
                "hk_timers", "hk_qed_tables", "hk_cnn_nparams", "hk_cnn_create", "hk_cnn_destroy",
                "hk_cnn_set_params", "hk_cnn_get_params", "hk_cnn_set_norm", "hk_cnn_forward",
                "hk_cnn_loss_grad", "hk_cnn_train_step", "hk_cnn_last_error", "hk_set_cnn", "hk_node_inputs",
-               "hk_real_size", "hk_strerror", "hk_last_error"]
+               "hk_real_size", "hk_strerror", "hk_last_error", "hk_save", "hk_load"]
 
 _libs: dict = {}
 
@@ -122,6 +122,8 @@ def load(prec: str = "f32"):
     L.hk_destroy.argtypes = [vp]
     L.hk_destroy.restype = None
     L.hk_step.argtypes = [vp, C.c_int]
+    L.hk_save.argtypes = [vp, C.c_char_p]
+    L.hk_load.argtypes = [vp, C.c_char_p]
     L.hk_switch_map.argtypes = [vp, vp, C.c_size_t]
     L.hk_set_switch_map.argtypes = [vp, vp, C.c_size_t]
     L.hk_set_switch_mode.argtypes = [vp, C.c_int]
@@ -315,6 +317,12 @@ class Sim:
         tau = None if tau is None else np.ascontiguousarray(tau, np.float64)
         p = Particles(n=n, x=_ptr(x), u=_ptr(u), w=_ptr(w), id=_ptr(ids), z=_ptr(z), tau=_ptr(tau))
         self._check(self.lib.hk_set_particles(self.h, sp, C.byref(p)))
+
+    def save(self, path: str):
+        self._check(self.lib.hk_save(self.h, str(path).encode()))
+
+    def load(self, path: str):
+        self._check(self.lib.hk_load(self.h, str(path).encode()))
 
     def get_fluid(self, sp: int):
         n = np.empty(self.shape); u = np.empty(self.shape + (3,))
