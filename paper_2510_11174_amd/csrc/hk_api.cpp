@@ -44,6 +44,7 @@ struct DevSpecies {
     std::vector<int> h_cap;
     int max_cap = 0;
     long long mig0 = 0;        // slot of the first per-tile mover region in each bin buffer
+    long long alloc_slots = 0; // slots allocated per bin buffer (both alike)
     long long *moff = nullptr;
     int *mcap = nullptr;
     int *active = nullptr;     // immobile ionizable ions: ions below z_max per tile
@@ -295,15 +296,25 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
         mcap[t] = (int)m;
         mtotal += m;
     }
-    // each bin buffer carries the per-tile mover regions after its bins
-    PArr nbuf[2];
+    // each bin buffer carries the per-tile mover regions after its bins.  The
+    // spare buffer (the push's output, idle now) takes the scatter when it is
+    // large enough; otherwise both are allocated anew with a quarter of
+    // slack, so that re-binning a large species rarely allocates
     const long long slots = total + (D.d.mobile ? mtotal : 0);
-    if (!alloc_parr(S, nbuf[0], slots, D.has_z, D.has_tau) ||
-        !alloc_parr(S, nbuf[1], slots, D.has_z, D.has_tau))
-        return fail(S, HK_ENOMEM, "rebuild: %lld particle slots", slots);
-    // the push addresses its output through the input's field pointers plus
-    // one byte distance: both buffers must have the same layout
-    if (!same_layout(nbuf[0], nbuf[1])) return fail(S, HK_ENOMEM, "rebuild: buffer layouts differ");
+    const bool reuse = D.alloc_slots >= slots && D.buf[1 - D.cur].cell != nullptr;
+    PArr nbuf[2];
+    if (!reuse) {
+        const long long n_alloc = slots + slots / 4;
+        if (!alloc_parr(S, nbuf[0], n_alloc, D.has_z, D.has_tau) ||
+            !alloc_parr(S, nbuf[1], n_alloc, D.has_z, D.has_tau))
+            return fail(S, HK_ENOMEM, "rebuild: %lld particle slots", n_alloc);
+        // the push addresses its output through the input's field pointers plus
+        // one byte distance: both buffers must have the same layout
+        if (!same_layout(nbuf[0], nbuf[1])) return fail(S, HK_ENOMEM, "rebuild: buffer layouts differ");
+        D.alloc_slots = n_alloc;
+    }
+    const int dst_i = reuse ? 1 - D.cur : 0;
+    const PArr dst = reuse ? D.buf[dst_i] : nbuf[0];
     long long *doff = (long long *)dalloc(S, sizeof(long long) * nt);
     long long *dmoff = (long long *)dalloc(S, sizeof(long long) * nt);
     int *dcap = (int *)dalloc(S, sizeof(int) * nt);
@@ -319,30 +330,33 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     HIPCHK(S, hipMemcpyAsync(dcap, cap.data(), sizeof(int) * nt, hipMemcpyHostToDevice, S->s));
     HIPCHK(S, hipMemcpyAsync(dmcap, mcap.data(), sizeof(int) * nt, hipMemcpyHostToDevice, S->s));
     if (use_tiles && D.capacity > 0)
-        launch_scatter_groups(g, cur, D.off, D.nf[D.cur], D.nb[D.cur], D.cap, nt, D.max_cap, nbuf[0],
+        launch_scatter_groups(g, cur, D.off, D.nf[D.cur], D.nb[D.cur], D.cap, nt, D.max_cap, dst,
                               doff, dfill, D.has_z, D.has_tau, S->s);
     for (int l = 0; l < nlists; ++l)
         launch_scatter_groups(g, lists[l], D.g_off0, list_n[l], nullptr, D.g_capmax, 1, list_max[l],
-                              nbuf[0], doff, dfill, D.has_z, D.has_tau, S->s);
+                              dst, doff, dfill, D.has_z, D.has_tau, S->s);
     HIPCHK(S, hipStreamSynchronize(S->s));
-    free_parr(S, D.buf[0]);
-    free_parr(S, D.buf[1]);
+    if (!reuse) {
+        free_parr(S, D.buf[0]);
+        free_parr(S, D.buf[1]);
+        D.buf[0] = nbuf[0];
+        D.buf[1] = nbuf[1];
+    }
     int *olds[] = {D.nf[0], D.nf[1], D.cap, D.mcap};
     for (int *q : olds) dfree(S, q);
     dfree(S, D.off); dfree(S, D.moff);
     dfree(S, newcnt);
-    D.buf[0] = nbuf[0];
-    D.buf[1] = nbuf[1];
     D.mig0 = total;
-    D.cur = 0;
+    D.cur = dst_i;
     D.off = doff;
     D.cap = dcap;
     D.moff = dmoff;
     D.mcap = dmcap;
-    D.nf[0] = dfill;   // the scatter fill counts are the new front counts
-    D.nf[1] = f1;
-    D.nb[0] = dfill + nt;
-    D.nb[1] = f1 + nt;
+    // the scatter fill counts are the new front counts of the current buffer
+    D.nf[dst_i] = dfill;
+    D.nf[1 - dst_i] = f1;
+    D.nb[dst_i] = dfill + nt;
+    D.nb[1 - dst_i] = f1 + nt;
     D.capacity = total;
     D.max_cap = maxc;
     D.h_off = off;
@@ -351,7 +365,7 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
         dfree(S, D.active);
         D.active = (int *)dalloc(S, sizeof(int) * nt);
         if (!D.active) return fail(S, HK_ENOMEM, "rebuild: active counts");
-        launch_count_active(g, specp(D), D.buf[0], cur_bins(D), D.d.z_max, D.active, S->s);
+        launch_count_active(g, specp(D), D.buf[D.cur], cur_bins(D), D.d.z_max, D.active, S->s);
     }
     return HK_OK;
 }
