@@ -21,7 +21,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SOURCES = ["philox.c", "fields.c", "particles.c", "fluid.c", "switch.c", "ionize.c",
-            "qed.c", "cnn.c", "sim.c"]
+            "qed.c", "cnn.c", "sp.c", "sim.c"]
 
 MAX_SPECIES = 6
 MAX_LEVELS = 8
@@ -148,6 +148,12 @@ def lib():
         L.or_cnn_adamw.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int] + \
             [C.c_double] * 5 + [C.c_int]
         L.or_cnn_mask.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_int, C.c_void_p]
+        L.or_sp_nparam.restype = C.c_int
+        L.or_sp_forward.argtypes = [C.c_void_p, C.c_void_p] + [C.c_int] * 4 + [C.c_void_p, C.c_void_p]
+        L.or_sp_loss_grad.restype = C.c_double
+        L.or_sp_loss_grad.argtypes = [C.c_void_p] * 3 + [C.c_int] * 4 + [C.c_void_p, C.c_void_p] + \
+            [C.c_double, C.c_double, C.c_void_p, C.c_void_p]
+        L.or_sp_mask.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_int, C.c_void_p]
         L.or_set_cnn.argtypes = [C.c_void_p] * 4
         _lib = L
     return _lib
@@ -442,4 +448,38 @@ def cnn_adamw(params, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, wd=0.0
 def cnn_mask(seed: int, node: int, step: int, sample: int) -> np.ndarray:
     out = np.empty(32)
     lib().or_cnn_mask(int(seed), int(node), int(step), int(sample), _ptr(out))
+    return out
+
+
+# ---- next-state surrogate (StatePredictor) -------------------------------------------------
+
+def sp_nparam() -> int:
+    return lib().or_sp_nparam()
+
+
+def sp_forward(params, x, mask=None) -> np.ndarray:
+    """Normalized next states of patches x[B, D, H, W, 10] (same shape)."""
+    p = np.ascontiguousarray(params, np.float64); x = np.ascontiguousarray(x, np.float64)
+    B, D, H, W, _ = x.shape
+    out = np.empty((B, D, H, W, 10))
+    m = None if mask is None else np.ascontiguousarray(mask, np.float64)
+    lib().or_sp_forward(_ptr(p), _ptr(x), B, D, H, W, None if m is None else _ptr(m), _ptr(out))
+    return out
+
+
+def sp_loss_grad(params, x, y, mean, std, delta=0.01, lam=0.1, mask=None):
+    p = np.ascontiguousarray(params, np.float64); x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    mean = np.ascontiguousarray(mean, np.float64); std = np.ascontiguousarray(std, np.float64)
+    B, D, H, W, _ = x.shape
+    g = np.empty(sp_nparam())
+    m = None if mask is None else np.ascontiguousarray(mask, np.float64)
+    loss = lib().or_sp_loss_grad(_ptr(p), _ptr(x), _ptr(y), B, D, H, W, _ptr(mean), _ptr(std), float(delta),
+                                 float(lam), None if m is None else _ptr(m), _ptr(g))
+    return loss, g
+
+
+def sp_mask(seed: int, voxel: int, step: int, sample: int) -> np.ndarray:
+    out = np.empty(32)
+    lib().or_sp_mask(int(seed), int(voxel), int(step), int(sample), _ptr(out))
     return out

@@ -155,4 +155,16 @@ void or_cnn_adamw(double *par, const double *grad, double *m, double *v, int t, 
                   double b1, double b2, double eps, double wd, int n);
 void or_cnn_mask(uint64_t seed, uint64_t id, uint32_t step, int sample, double out[32]);
 int or_set_cnn(or_sim *s, const double *par, const double mean[8], const double stdv[8]);
+
+/* Next-state surrogate (sp.c): parameter count, forward over B patches of
+ * D x H x W x 10 normalized inputs (same-size output), loss (Huber + energy
+ * term) and gradient, dropout factors. */
+int or_sp_nparam(void);
+void or_sp_forward(const double *par, const double *x, int B, int D, int H, int W, const double *mask,
+                   double *out);
+double or_sp_loss_grad(const double *par, const double *x, const double *y, int B, int D, int H, int W,
+                       const double mean[10], const double stdv[10], double delta, double lambda,
+                       const double *mask, double *grad);
+void or_sp_mask(uint64_t seed, uint64_t id, uint32_t step, int sample, double out[32]);
+
 #endif
