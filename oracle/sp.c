@@ -17,7 +17,8 @@
  *   a residual across a change of width with no extra weights;
  *   dropout on block 2's output (32 channels): byte c of two Philox draws
  *   (tag 25, draws 2s and 2s + 1 for sample s, counter = voxel id and step)
- *   below 26 drops the channel, kept channels are scaled by 256/230;
+ *   below 26 drops the channel, kept channels are scaled by 256/230; the
+ *   activation is rounded to BF16 once, after the dropout factor;
  *   block 4 (the 128-32-10 row of Table 2): conv 64->128 + relu, conv
  *   128->32 + relu, conv 32->10, linear: the output is the normalized next
  *   state, signed, in FP32 (not rounded);
@@ -107,9 +108,8 @@ static void sp_forward(const double *par, const double *x, int B, int D, int H, 
                 double o = sp_relu[l] ? (zz > 0.0 ? zz : 0.0) : zz;
                 if (sp_res[l] && c < ci) o += f->a[l][v * ci + c];
                 if (l == SP_NL - 1) { f->a[l + 1][v * co + c] = o; continue; }   /* FP32 output */
-                o = or_bf16(o);
                 if (l == SP_DROP_LAYER && mask) o *= mask[v * 32 + c];
-                f->a[l + 1][v * co + c] = o;
+                f->a[l + 1][v * co + c] = or_bf16(o);
             }
     }
 }

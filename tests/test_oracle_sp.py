@@ -47,10 +47,9 @@ def _torch_forward(p, x, rnd, mask=None):
         if l == len(CIN) - 1:
             a = h
             break
-        h = bf(h)
         if l == 1 and mask is not None:
             h = h * mask.permute(0, 4, 1, 2, 3)
-        a = h
+        a = bf(h)
     return a.permute(0, 2, 3, 4, 1)
 
 
@@ -68,6 +67,18 @@ def test_forward_matches_torch(oracle_mod):
     ref = _torch_forward(torch.tensor(p), torch.tensor(x), True).numpy()
     assert got.shape == x.shape
     np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-10)
+
+
+def test_forward_with_dropout_rounds_once(oracle_mod):
+    """BF16 rounding with dropout: block 2's output is scaled, then rounded."""
+    p = sp_params(oracle_mod, 3)
+    shape = (1, 4, 5, 3)
+    x = np.random.default_rng(4).normal(0, 1, shape + (10,))
+    mask = np.stack([oracle_mod.sp_mask(11, v, 2, 0) for v in range(int(np.prod(shape)))]).reshape(shape + (32,))
+    got = oracle_mod.sp_forward(p, x, mask=mask)
+    ref = _torch_forward(torch.tensor(p), torch.tensor(x), True, torch.tensor(mask)).numpy()
+    np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-10)
+    assert not np.allclose(got, oracle_mod.sp_forward(p, x), atol=1e-6)
 
 
 @pytest.fixture
