@@ -316,6 +316,65 @@ int hk_node_inputs(hk_sim *sim, double *raw, double *ehat, uint8_t *hot, size_t 
  * without one the mode decides by the thresholds alone) */
 int hk_set_cnn(hk_sim *sim, hk_cnn *cnn);
 
+/* ------------------------------------------------------------------------
+ * Next-state surrogate (Results, Table 2 and the paragraph before it: a
+ * residual 3D CNN, the StatePredictor, trained with a Huber loss and a
+ * physics penalty on the field energy).
+ *
+ * Network: 10 channels per node in and out (Ex, Ey, Ez, Bx, By, Bz, Jx, Jy,
+ * Jz, rho, each normalized (x - mean) / std with frozen statistics); six
+ * "same" 3^3 convolutions with zero padding, widths 10->13->32->64->128->32->
+ * 10; ReLU after all but the last; the first three add their input to their
+ * first output channels (residual copy, no weights); dropout (p = 26/256,
+ * kept channels scaled by 256/230) on the 32-channel output of the second,
+ * keyed by Philox (seed, voxel index in the batch, mask step), tag 25.  BF16
+ * inputs, weights and activations (rounded to nearest even; the dropped-out
+ * activation is rounded once, after scaling), FP32 accumulation on the matrix
+ * cores, FP32 output.  410733 parameters (hk_sp_nparams), FP32 masters,
+ * per layer W[27][cin][cout] then b[cout] (tap = kx + 3 ky + 9 kz reads the
+ * offset (kx - 1, ky - 1, kz - 1)).
+ *
+ * Patches: x[B][D][H][W][10] FP32 normalized states, channels last, x
+ * fastest (device pointers); the output has the same shape.  Loss: the mean
+ * over voxels and channels of Huber_delta(pred - y) plus lambda_e times the
+ * mean over patches of ((U_pred - U_y) / U_y)^2, U = sum over the patch of
+ * sum_{c < 6} (x_c std_c + mean_c)^2 (hk_sp_set_norm; patches with U_y = 0
+ * add no energy term).  Training needs W % 8 == 0; errors: HK_EINVAL for a
+ * bad shape or argument, HK_ENOMEM when the workspace cannot grow,
+ * HK_EDEVICE for a failed HIP call (hk_sp_last_error has the text).  The
+ * workspace (about 3 KB per voxel when training) is kept between calls and
+ * freed by hk_sp_destroy; calls on one network are serialized on its stream. */
+typedef struct hk_sp hk_sp;
+typedef struct {
+    double lr, beta1, beta2, eps, weight_decay;   /* AdamW */
+    double delta;                                  /* Huber threshold */
+    double lambda_e;                               /* energy penalty weight */
+    int32_t dropout, pad;                          /* train with dropout (mask step = AdamW step) */
+} hk_sp_train_desc;
+
+int hk_sp_nparams(void);
+/* desc as for hk_cnn_create: dropout seed, stream, optional allocator */
+int hk_sp_create(const hk_cnn_desc *desc, hk_sp **out);
+void hk_sp_destroy(hk_sp *sp);
+/* host FP32 parameters in and out (n = hk_sp_nparams()); setting resets AdamW */
+int hk_sp_set_params(hk_sp *sp, const float *params, size_t n);
+int hk_sp_get_params(hk_sp *sp, float *params, size_t n);
+/* 10 means and 10 standard deviations (host) of the raw channels: only the
+ * energy term uses them (the inputs arrive normalized) */
+int hk_sp_set_norm(hk_sp *sp, const float *mean, const float *stdv);
+/* out (device FP32, same shape as x) = the predicted normalized next states;
+ * mask_step >= 0 applies that step's dropout masks (Monte Carlo samples),
+ * < 0 none */
+int hk_sp_forward(hk_sp *sp, const float *x, int B, int D, int H, int W, int mask_step, float *out);
+/* loss (host) and gradient (host FP32, n = hk_sp_nparams(), may be NULL) for
+ * targets y (device, same shape as x) */
+int hk_sp_loss_grad(hk_sp *sp, const float *x, const float *y, int B, int D, int H, int W, double delta,
+                    double lambda_e, int mask_step, float *grad_host, double *loss);
+/* one AdamW step on a batch */
+int hk_sp_train_step(hk_sp *sp, const float *x, const float *y, int B, int D, int H, int W,
+                     const hk_sp_train_desc *train, double *loss);
+const char *hk_sp_last_error(const hk_sp *sp);
+
 int hk_real_size(void);
 const char *hk_strerror(int code);
 const char *hk_last_error(const hk_sim *sim);

@@ -1,0 +1,57 @@
+// Kernel arguments and launchers of the next-state surrogate (k_sp.hip),
+// used by its host side (hk_sp.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+// One "same" 3^3 convolution as an implicit GEMM (forward or data gradient).
+struct SpConv {
+    int B, D, H, W;                 // voxel grid, shared by input and output
+    const unsigned short *in;       // [n][CPIN] BF16, channels last
+    const unsigned short *wp;       // [cols][KPAD] BF16 weight matrix
+    int cols, cout;                 // padded (output stride) and real output channels
+    // forward epilogue
+    const float *bias;              // [cout]
+    int relu, res;                  // res: leading channels of `in` added after the ReLU
+    float *fout;                    // last layer: FP32 [n][cout] (no BF16 output)
+    // both epilogues
+    int drop;                       // apply the dropout factors of (seed, voxel, step)
+    uint64_t seed;
+    uint32_t step;
+    unsigned short *zout;           // forward: BF16 pre-activations (for the backward pass), or null
+    unsigned short *aout, *aT;      // BF16 result, channels last and channel-major (or null)
+    // data-gradient epilogue
+    const float *gin;               // residual-path gradient of the layer above (or null)
+    int gin_ch, gin_stride;
+    float *gout;                    // gradient after dropout of the layer below (or null)
+    const unsigned short *zin;      // BF16 pre-activations of the layer below
+    int ntask, G;                   // wave tasks, column groups
+};
+
+// Weight gradient of one convolution from the channel-major copies.
+struct SpWgrad {
+    int B, D, H, W;
+    const unsigned short *aT;       // [B][cpi][D][H][W] layer input
+    const unsigned short *dT;       // [B][cpo][D][H][W] pre-activation gradient
+    int cpi, cpo, cin, cout;
+    float *gw;                      // [27][cin][cout], accumulated
+    int mtn, ngn, nitems;           // ci tiles, co groups, workgroups
+    long long nblk, nks, kpc;       // 8-voxel blocks, K steps (4 blocks), steps per chunk
+};
+
+struct SpNorm { float mean[10], stdv[10]; };
+
+int sp_conv_mt();
+int sp_launch_conv(int cpin, int nt, bool bwd, const SpConv &a, hipStream_t s);
+int sp_launch_wgrad(int nt, const SpWgrad &a, hipStream_t s);
+void sp_launch_bias_grad(long long n, int cols, int cout, const unsigned short *dz, float *gb, hipStream_t s);
+void sp_launch_energy(long long n, long long per, const float *p, const float *y, const SpNorm &nm, double *U,
+                      hipStream_t s);
+void sp_launch_loss(long long n, long long per, int B, const float *p, const float *y, const SpNorm &nm,
+                    const double *U, float delta, float lambda, unsigned short *dz, unsigned short *dzT,
+                    double *loss, hipStream_t s);
+void sp_launch_pack(const float *W, int cin, int cout, int cpi, int cpo, unsigned short *Wf, unsigned short *Wb,
+                    hipStream_t s);
+void sp_launch_input(long long n, long long per, const float *x, unsigned short *xb, unsigned short *xT,
+                     hipStream_t s);

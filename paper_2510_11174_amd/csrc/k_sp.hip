@@ -1,0 +1,506 @@
+// The next-state surrogate on gfx950: a residual 3D CNN (six "same" 3^3
+// convolutions, widths 10-13-32-64-128-32-10) that maps a normalized state
+// patch (E, B, J, rho at the nodes) to the state a few steps later, with its
+// loss (Huber plus an energy-violation term), backward pass and packing.
+//
+// Paper: Results, Table 2 (StatePredictor layers) and the paragraph before it
+// (residual blocks, dropout, Huber loss, physics term on the field energy).
+//
+// Storage: activations BF16, channels last, the channel count padded to a
+// multiple of 16 (CP) with zeros.  Convolutions are implicit GEMMs on
+// v_mfma_f32_16x16x32_bf16: rows are 16 consecutive voxels along x, columns
+// output channels, K = (tap, input channel), k = t CP + ci, tap
+// t = kx + 3 ky + 9 kz reading offset (kx - 1, ky - 1, kz - 1), zero outside
+// the patch.  Lane l supplies A[l%16][8 (l/16) .. +8] (one 16-byte load of 8
+// channels of one voxel), B[8 (l/16) .. +8][l%16] (16 bytes of the weight
+// matrix stored column-major, [column][K]) and gets D[4 (l/16) + i][l%16].
+// A wave owns MT row tiles x NT column tiles, so each fragment it loads feeds
+// NT (A) or MT (B) matrix instructions.
+//
+// The data gradient is the same GEMM over input voxels with the transposed,
+// tap-reversed weights (tap 26 - t): a "same" convolution of the output
+// gradient.  Its epilogue finishes the layer below in place: it adds the
+// residual path, applies the dropout factors and the ReLU derivative, and
+// writes that layer's pre-activation gradient in BF16.
+//
+// The weight gradient contracts over voxels, which lie along x in memory only
+// in a channel-major copy ([b][c][z][y][x]) that the forward and backward
+// epilogues write beside the channels-last tensors.  A lane then loads 8
+// consecutive x of one channel with one 16-byte load; the x shift of taps
+// kx = 0 and 2 is done in registers from the neighbouring 8-voxel blocks.
+#include "hk_internal.h"
+#include "hk_sp_internal.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16;
+
+constexpr int SBS = 256;                  // 4 waves
+constexpr uint32_t TAG_SP_DROP = 25;      // Philox stream of the surrogate's dropout
+
+__device__ inline u16 bf16_bits(float x) {
+    // round to nearest even (finite inputs)
+    const unsigned u = __float_as_uint(x);
+    return (u16)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf16_val(u16 b) { return __uint_as_float((unsigned)b << 16); }
+
+// dropout keep factor of channel c (< 32) at voxel v: byte c % 16 of Philox
+// draw c / 16 (counter: voxel, step; sample 0) >= 26 keeps, scaled by 256/230
+__device__ inline float keep(uint64_t seed, uint64_t v, uint32_t step, int c) {
+    uint32_t r[4];
+    draw4(seed, v, step, TAG_SP_DROP, (uint32_t)(c >> 4), r);
+    const int byte = c & 15;
+    return ((r[byte >> 2] >> (8 * (byte & 3))) & 0xffu) >= 26u ? 256.0f / 230.0f : 0.0f;
+}
+
+// blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous run
+// of work items so neighbouring rows share one L2 (nb is a multiple of 8)
+__device__ inline int xcd_block(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
+
+// ------------------------------------------------------------ convolution
+template <int CPIN, int MT, int NT, bool BWD>
+__global__ void __launch_bounds__(SBS) k_sp_conv(SpConv a) {
+    constexpr int K = 27 * CPIN, KPAD = (K + 31) / 32 * 32, NK = KPAD / 32;
+    const int task = xcd_block(blockIdx.x, gridDim.x) * (SBS / 64) + (threadIdx.x >> 6);
+    if (task >= a.ntask) return;
+    const int cg = task % a.G, rg = task / a.G;
+    const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+    const int segs = (a.W + 15) >> 4;
+    const long long nrows = (long long)a.B * a.D * a.H * segs;
+    const long long HW = (long long)a.H * a.W;
+
+    // per row tile: this lane's voxel and the taps that stay inside the patch
+    long long vb[MT];
+    unsigned tmask[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        const long long row = (long long)rg * MT + m;
+        vb[m] = 0;
+        tmask[m] = 0;
+        if (row >= nrows) continue;
+        const int seg = (int)(row % segs);
+        long long q = row / segs;
+        const int y = (int)(q % a.H);
+        q /= a.H;
+        const int z = (int)(q % a.D);
+        const int b = (int)(q / a.D);
+        const int x = seg * 16 + r;
+        if (x >= a.W) continue;
+        vb[m] = ((long long)b * a.D + z) * HW + (long long)y * a.W + x;
+        for (int t = 0; t < 27; ++t) {
+            const int xx = x + t % 3 - 1, yy = y + (t / 3) % 3 - 1, zz = z + t / 9 - 1;
+            if (xx >= 0 && xx < a.W && yy >= 0 && yy < a.H && zz >= 0 && zz < a.D) tmask[m] |= 1u << t;
+        }
+    }
+    const u16 *wrow[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) wrow[nt] = a.wp + (long long)((cg * NT + nt) * 16 + r) * KPAD + 8 * g;
+
+    auto loadA = [&](int ks, uint4 (&av)[MT]) {
+        const int k = ks * 32 + 8 * g;
+        const int t = k / CPIN, ci = k % CPIN;
+        const int kx = t % 3, ky = (t / 3) % 3, kz = t / 9;
+        const long long off = ((long long)(kz - 1) * a.H + (ky - 1)) * a.W + (kx - 1);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            av[m] = make_uint4(0, 0, 0, 0);
+            if (k < K && ((tmask[m] >> t) & 1u))
+                av[m] = *reinterpret_cast<const uint4 *>(a.in + (vb[m] + off) * CPIN + ci);
+        }
+    };
+    auto loadB = [&](int ks, uint4 (&bv)[NT]) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) bv[nt] = *reinterpret_cast<const uint4 *>(wrow[nt] + ks * 32);
+    };
+
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[m][nt] = f32x4{0, 0, 0, 0};
+    uint4 av[MT], bv[NT];
+    loadA(0, av);
+    loadB(0, bv);
+    for (int ks = 0; ks < NK; ++ks) {
+        uint4 an[MT], bn[NT];
+        if (ks + 1 < NK) {
+            loadA(ks + 1, an);
+            loadB(ks + 1, bn);
+        } else {
+#pragma unroll
+            for (int m = 0; m < MT; ++m) an[m] = make_uint4(0, 0, 0, 0);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) bn[nt] = make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                acc[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av[m]),
+                                                                    __builtin_bit_cast(bf16x8, bv[nt]),
+                                                                    acc[m][nt], 0, 0, 0);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) av[m] = an[m];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) bv[nt] = bn[nt];
+    }
+
+    // epilogue: D[4 g + i][r] is voxel x0 + 4 g + i, channel co
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        const long long row = (long long)rg * MT + m;
+        if (row >= nrows) continue;
+        const int seg = (int)(row % segs);
+        long long q = row / segs;
+        const int y = (int)(q % a.H);
+        q /= a.H;
+        const int z = (int)(q % a.D);
+        const int b = (int)(q / a.D);
+        const int xg = seg * 16 + 4 * g;
+        const long long vrow = ((long long)b * a.D + z) * HW + (long long)y * a.W;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int co = (cg * NT + nt) * 16 + r;
+            const bool real_c = co < a.cout;
+            u16 ov[4] = {0, 0, 0, 0};
+            for (int i = 0; i < 4; ++i) {
+                const int x = xg + i;
+                if (x >= a.W) continue;
+                const long long v = vrow + x;
+                float s = acc[m][nt][i];
+                if (!BWD) {
+                    s += real_c ? a.bias[co] : 0.f;
+                    if (a.zout) a.zout[v * a.cols + co] = real_c ? bf16_bits(s) : (u16)0;
+                    float o = a.relu ? fmaxf(s, 0.f) : s;
+                    if (co < a.res) o += bf16_val(a.in[v * CPIN + co]);
+                    if (a.fout) {
+                        if (real_c) a.fout[v * a.cout + co] = o;
+                        continue;
+                    }
+                    if (a.drop) o *= keep(a.seed, (uint64_t)v, a.step, co);
+                    ov[i] = real_c ? bf16_bits(o) : (u16)0;
+                } else {
+                    // gradient of the layer below's output, through its
+                    // residual copy, dropout and ReLU
+                    if (co < a.gin_ch) s += a.gin[v * a.gin_stride + co];
+                    if (a.drop) s *= keep(a.seed, (uint64_t)v, a.step, co);
+                    if (a.gout) a.gout[v * a.cols + co] = s;
+                    const float d = bf16_val(a.zin[v * a.cols + co]) > 0.f ? s : 0.f;
+                    ov[i] = real_c ? bf16_bits(d) : (u16)0;
+                }
+                a.aout[v * a.cols + co] = ov[i];
+            }
+            if (a.aT && xg < a.W) {
+                // channel-major copy: 4 consecutive x of channel co (W % 4 == 0)
+                const long long o = (((long long)b * a.cols + co) * a.D + z) * HW + (long long)y * a.W + xg;
+                *reinterpret_cast<uint2 *>(a.aT + o) =
+                    make_uint2((unsigned)ov[0] | ((unsigned)ov[1] << 16), (unsigned)ov[2] | ((unsigned)ov[3] << 16));
+            }
+        }
+    }
+}
+
+// -------------------------------------------------------- weight gradient
+// gw[t][ci][co] += sum_v a[v + off(t)][ci] dz[v][co].  K runs over 8-voxel
+// blocks along x (W % 8 == 0), four blocks per step: lane (r, g) takes block
+// 4 ks + g, A[r = ci][8 g + j] = a[x + j + kx - 1] of channel ci and B[8 g + j]
+// [r = co] = dz[x + j] of channel co, both from the channel-major copies.  A
+// workgroup owns one (ky, kz) pair, one 16-channel ci tile, NT co tiles and a
+// chunk of K; its four waves take interleaved steps of the chunk, reduce in
+// LDS, and wave 0 adds the three taps kx = 0, 1, 2 to gw.
+template <int NT>
+__global__ void __launch_bounds__(SBS) k_sp_wgrad(SpWgrad a) {
+    __shared__ f32x4 red[SBS / 64 - 1][3 * NT][64];
+    const int item = xcd_block(blockIdx.x, gridDim.x);
+    if (item >= a.nitems) return;   // uniform over the workgroup
+    int q = item;
+    const int p = q % 9;
+    q /= 9;
+    const int mt = q % a.mtn;
+    q /= a.mtn;
+    const int ng = q % a.ngn;
+    const int chunk = q / a.ngn;
+    const int ky = p % 3, kz = p / 3;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
+    const int xbn = a.W >> 3;
+    const long long HW = (long long)a.H * a.W, DHW = HW * a.D;
+    const int ci = mt * 16 + r;
+    f32x4 acc[3][NT];
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[kx][nt] = f32x4{0, 0, 0, 0};
+    const long long ks0 = (long long)chunk * a.kpc;
+    long long ks1 = ks0 + a.kpc;
+    if (ks1 > a.nks) ks1 = a.nks;
+    for (long long ks = ks0 + wave; ks < ks1; ks += SBS / 64) {
+        const long long blk = ks * 4 + g;
+        uint4 L = make_uint4(0, 0, 0, 0), M = L, R = L, Bv[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) Bv[nt] = L;
+        if (blk < a.nblk) {
+            const int xb = (int)(blk % xbn);
+            long long rq = blk / xbn;
+            const int y = (int)(rq % a.H);
+            rq /= a.H;
+            const int z = (int)(rq % a.D);
+            const int b = (int)(rq / a.D);
+            const int ys = y + ky - 1, zs = z + kz - 1;
+            if (ys >= 0 && ys < a.H && zs >= 0 && zs < a.D) {
+                const u16 *src = a.aT + ((long long)b * a.cpi + ci) * DHW + zs * HW + (long long)ys * a.W + 8 * xb;
+                M = *reinterpret_cast<const uint4 *>(src);
+                if (xb > 0) L = *reinterpret_cast<const uint4 *>(src - 8);
+                if (xb + 1 < xbn) R = *reinterpret_cast<const uint4 *>(src + 8);
+            }
+            const long long dbase = (long long)b * a.cpo * DHW + z * HW + (long long)y * a.W + 8 * xb;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int co = (ng * NT + nt) * 16 + r;
+                Bv[nt] = *reinterpret_cast<const uint4 *>(a.dT + dbase + (long long)co * DHW);
+            }
+        }
+        // x shifted by -1 (kx = 0) and +1 (kx = 2): element j of the fragment
+        // is a[x + j + kx - 1]; the low half of a word is the even element
+        const uint4 A0 = make_uint4((L.w >> 16) | (M.x << 16), (M.x >> 16) | (M.y << 16),
+                                    (M.y >> 16) | (M.z << 16), (M.z >> 16) | (M.w << 16));
+        const uint4 A2 = make_uint4((M.x >> 16) | (M.y << 16), (M.y >> 16) | (M.z << 16),
+                                    (M.z >> 16) | (M.w << 16), (M.w >> 16) | (R.x << 16));
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const bf16x8 bb = __builtin_bit_cast(bf16x8, Bv[nt]);
+            acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A0), bb, acc[0][nt], 0, 0, 0);
+            acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, M), bb, acc[1][nt], 0, 0, 0);
+            acc[2][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A2), bb, acc[2][nt], 0, 0, 0);
+        }
+    }
+    if (wave > 0)
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) red[wave - 1][kx * NT + nt][lane] = acc[kx][nt];
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            f32x4 s = acc[kx][nt];
+            for (int w = 0; w < SBS / 64 - 1; ++w) s += red[w][kx * NT + nt][lane];
+            const int t = kx + 3 * p;
+            const int co = (ng * NT + nt) * 16 + r;
+            for (int i = 0; i < 4; ++i) {
+                const int c = mt * 16 + 4 * g + i;
+                if (c < a.cin && co < a.cout && s[i] != 0.f)
+                    atomicAdd(&a.gw[((long long)t * a.cin + c) * a.cout + co], s[i]);
+            }
+        }
+}
+
+// bias gradient: gb[co] += sum_v dz[v][co] (cols divides SBS)
+__global__ void __launch_bounds__(SBS)
+k_sp_bias_grad(long long n, int cols, int cout, const u16 *__restrict__ dz, float *__restrict__ gb) {
+    __shared__ float s[SBS];
+    s[threadIdx.x] = 0.f;
+    __syncthreads();
+    const int per = SBS / cols, c = threadIdx.x % cols;
+    float acc = 0.f;
+    for (long long v = (long long)blockIdx.x * per + threadIdx.x / cols; v < n; v += (long long)gridDim.x * per)
+        acc += bf16_val(dz[v * cols + c]);
+    atomicAdd(&s[c], acc);
+    __syncthreads();
+    if (threadIdx.x < cout && s[threadIdx.x] != 0.f) atomicAdd(&gb[threadIdx.x], s[threadIdx.x]);
+}
+
+// ------------------------------------------------------------------- loss
+// per-sample field energies of prediction and target, sum_{c < 6} (x std + mean)^2
+__global__ void __launch_bounds__(SBS)
+k_sp_energy(long long n, long long per, const float *__restrict__ p, const float *__restrict__ y, SpNorm nm,
+            double *__restrict__ U) {
+    __shared__ double sp_[SBS], st_[SBS];
+    const long long v = (long long)blockIdx.x * SBS + threadIdx.x;
+    double up = 0.0, ut = 0.0;
+    if (v < n)
+        for (int c = 0; c < 6; ++c) {
+            const double ep = (double)p[v * 10 + c] * nm.stdv[c] + nm.mean[c];
+            const double et = (double)y[v * 10 + c] * nm.stdv[c] + nm.mean[c];
+            up += ep * ep;
+            ut += et * et;
+        }
+    const long long v0 = (long long)blockIdx.x * SBS;
+    long long v1 = v0 + SBS - 1;
+    if (v1 >= n) v1 = n - 1;
+    if (v0 / per != v1 / per) {   // block spans samples
+        if (v < n) {
+            atomicAdd(&U[2 * (v / per)], up);
+            atomicAdd(&U[2 * (v / per) + 1], ut);
+        }
+        return;
+    }
+    sp_[threadIdx.x] = up;
+    st_[threadIdx.x] = ut;
+    __syncthreads();
+    for (int h = SBS / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sp_[threadIdx.x] += sp_[threadIdx.x + h];
+            st_[threadIdx.x] += st_[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(&U[2 * (v0 / per)], sp_[0]);
+        atomicAdd(&U[2 * (v0 / per) + 1], st_[0]);
+    }
+}
+
+// Huber loss and the output gradient: dz[v][c] (BF16, 16 channels, c >= 10
+// zero) and its channel-major copy; thread 0 also adds the energy term
+__global__ void __launch_bounds__(SBS)
+k_sp_loss(long long n, long long per, int B, const float *__restrict__ p, const float *__restrict__ y, SpNorm nm,
+          const double *__restrict__ U, float delta, float lambda, u16 *__restrict__ dz, u16 *__restrict__ dzT,
+          double *__restrict__ loss) {
+    __shared__ double sl[SBS];
+    const long long v = (long long)blockIdx.x * SBS + threadIdx.x;
+    double h = 0.0;
+    if (v < n) {
+        const long long b = v / per, s = v % per;
+        const double ut = U[2 * b + 1], up = U[2 * b];
+        const float kb = ut > 0.0 ? (float)(lambda * 2.0 * ((up - ut) / ut) / ut / B) : 0.f;
+        const float inv = 1.0f / (float)(n * 10);
+        for (int c = 0; c < 16; ++c) {
+            float gd = 0.f;
+            if (c < 10) {
+                const float pv = p[v * 10 + c], d = pv - y[v * 10 + c], ad = fabsf(d);
+                h += ad <= delta ? 0.5 * (double)d * d : (double)delta * (ad - 0.5 * (double)delta);
+                gd = (ad <= delta ? d : (d > 0.f ? delta : -delta)) * inv;
+                if (c < 6) gd += kb * 2.0f * (pv * nm.stdv[c] + nm.mean[c]) * nm.stdv[c];
+            }
+            const u16 bits = bf16_bits(gd);
+            dz[v * 16 + c] = bits;
+            dzT[(b * 16 + c) * per + s] = bits;
+        }
+    }
+    sl[threadIdx.x] = h;
+    __syncthreads();
+    for (int k = SBS / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sl[threadIdx.x] += sl[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double tot = sl[0] / (double)(n * 10);
+        if (blockIdx.x == 0)
+            for (int b = 0; b < B; ++b) {
+                const double ut = U[2 * b + 1], up = U[2 * b];
+                if (ut > 0.0) tot += lambda * ((up - ut) / ut) * ((up - ut) / ut) / B;
+            }
+        if (tot != 0.0) atomicAdd(loss, tot);
+    }
+}
+
+// ------------------------------------------------------- packing, inputs
+// BF16 weight matrices of one layer from the FP32 parameters W[27][cin][cout]:
+// forward Wf[co][k = t cpi + ci] (kpf = 27 cpi rounded up to 32) and data
+// gradient Wb[ci][k = t cpo + co] = W[26 - t][ci][co]; zeros in the padding
+__global__ void __launch_bounds__(SBS)
+k_sp_pack(const float *__restrict__ W, int cin, int cout, int cpi, int cpo, u16 *__restrict__ Wf,
+          u16 *__restrict__ Wb) {
+    const int i = blockIdx.x * SBS + threadIdx.x;
+    const int kpf = (27 * cpi + 31) / 32 * 32, kpb = (27 * cpo + 31) / 32 * 32;
+    if (i < cpo * kpf) {
+        const int co = i / kpf, k = i % kpf, t = k / cpi, ci = k % cpi;
+        Wf[i] = (k < 27 * cpi && ci < cin && co < cout) ? bf16_bits(W[((long long)t * cin + ci) * cout + co]) : (u16)0;
+    }
+    if (Wb && i < cpi * kpb) {
+        const int ci = i / kpb, k = i % kpb, t = k / cpo, co = k % cpo;
+        Wb[i] = (k < 27 * cpo && ci < cin && co < cout)
+                    ? bf16_bits(W[((long long)(26 - t) * cin + ci) * cout + co]) : (u16)0;
+    }
+}
+
+// FP32 inputs [n][10] -> BF16 [n][16] (zero padded) and the channel-major copy
+__global__ void __launch_bounds__(SBS)
+k_sp_input(long long n, long long per, const float *__restrict__ x, u16 *__restrict__ xb, u16 *__restrict__ xT) {
+    const long long i = (long long)blockIdx.x * SBS + threadIdx.x;
+    if (i >= n * 16) return;
+    const long long v = i >> 4;
+    const int c = (int)(i & 15);
+    const u16 bits = c < 10 ? bf16_bits(x[v * 10 + c]) : (u16)0;
+    xb[i] = bits;
+    if (xT) xT[((v / per) * 16 + c) * per + v % per] = bits;
+}
+
+inline unsigned nblk(long long n) { return (unsigned)((n + SBS - 1) / SBS); }
+inline unsigned grid8(long long items) { return (unsigned)((items + 7) / 8 * 8); }
+
+template <int CPIN, int NT, bool BWD>
+void conv_go(const SpConv &a, hipStream_t s) {
+    constexpr int MT = 4;
+    k_sp_conv<CPIN, MT, NT, BWD><<<grid8((a.ntask + 3) / 4), SBS, 0, s>>>(a);
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- launchers
+int sp_conv_mt() { return 4; }
+
+int sp_launch_conv(int cpin, int nt, bool bwd, const SpConv &a, hipStream_t s) {
+    const int key = cpin * 100 + nt * 10 + (bwd ? 1 : 0);
+    switch (key) {
+    // forward: 16->16, 16->32, 32->64, 64->128, 128->32, 32->16
+    case 1610: conv_go<16, 1, false>(a, s); break;
+    case 1620: conv_go<16, 2, false>(a, s); break;
+    case 3240: conv_go<32, 4, false>(a, s); break;
+    case 6440: conv_go<64, 4, false>(a, s); break;
+    case 12820: conv_go<128, 2, false>(a, s); break;
+    case 3210: conv_go<32, 1, false>(a, s); break;
+    // data gradient: 16->32, 32->128, 128->64, 64->32, 32->16
+    case 1621: conv_go<16, 2, true>(a, s); break;
+    case 3241: conv_go<32, 4, true>(a, s); break;
+    case 12841: conv_go<128, 4, true>(a, s); break;
+    case 6421: conv_go<64, 2, true>(a, s); break;
+    case 3211: conv_go<32, 1, true>(a, s); break;
+    default: return -1;
+    }
+    return 0;
+}
+
+int sp_launch_wgrad(int nt, const SpWgrad &a, hipStream_t s) {
+    const unsigned grid = grid8(a.nitems);
+    switch (nt) {
+    case 1: k_sp_wgrad<1><<<grid, SBS, 0, s>>>(a); break;
+    case 2: k_sp_wgrad<2><<<grid, SBS, 0, s>>>(a); break;
+    case 4: k_sp_wgrad<4><<<grid, SBS, 0, s>>>(a); break;
+    default: return -1;
+    }
+    return 0;
+}
+
+void sp_launch_bias_grad(long long n, int cols, int cout, const unsigned short *dz, float *gb, hipStream_t s) {
+    long long b = (n * cols + SBS - 1) / SBS;
+    k_sp_bias_grad<<<(unsigned)(b < 1024 ? b : 1024), SBS, 0, s>>>(n, cols, cout, dz, gb);
+}
+
+void sp_launch_energy(long long n, long long per, const float *p, const float *y, const SpNorm &nm, double *U,
+                      hipStream_t s) {
+    k_sp_energy<<<nblk(n), SBS, 0, s>>>(n, per, p, y, nm, U);
+}
+
+void sp_launch_loss(long long n, long long per, int B, const float *p, const float *y, const SpNorm &nm,
+                    const double *U, float delta, float lambda, unsigned short *dz, unsigned short *dzT,
+                    double *loss, hipStream_t s) {
+    k_sp_loss<<<nblk(n), SBS, 0, s>>>(n, per, B, p, y, nm, U, delta, lambda, dz, dzT, loss);
+}
+
+void sp_launch_pack(const float *W, int cin, int cout, int cpi, int cpo, unsigned short *Wf, unsigned short *Wb,
+                    hipStream_t s) {
+    const long long nf = (long long)cpo * ((27 * cpi + 31) / 32 * 32);
+    const long long nb = (long long)cpi * ((27 * cpo + 31) / 32 * 32);
+    k_sp_pack<<<nblk(nf > nb ? nf : nb), SBS, 0, s>>>(W, cin, cout, cpi, cpo, Wf, Wb);
+}
+
+void sp_launch_input(long long n, long long per, const float *x, unsigned short *xb, unsigned short *xT,
+                     hipStream_t s) {
+    k_sp_input<<<nblk(n * 16), SBS, 0, s>>>(n, per, x, xb, xT);
+}

@@ -96,6 +96,12 @@ class CnnTrainDesc(C.Structure):
                 ("pad", C.c_int32)]
 
 
+class SpTrainDesc(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("weight_decay", C.c_double), ("delta", C.c_double), ("lambda_e", C.c_double),
+                ("dropout", C.c_int32), ("pad", C.c_int32)]
+
+
 ABI_SYMBOLS = ["hk_create", "hk_destroy", "hk_step", "hk_switch_map", "hk_set_switch_map",
                "hk_set_switch_mode", "hk_diagnostics", "hk_get_field", "hk_set_field",
                "hk_get_rho", "hk_get_divE", "hk_particle_count", "hk_get_particles",
@@ -103,6 +109,8 @@ ABI_SYMBOLS = ["hk_create", "hk_destroy", "hk_step", "hk_switch_map", "hk_set_sw
                "hk_timers", "hk_qed_tables", "hk_cnn_nparams", "hk_cnn_create", "hk_cnn_destroy",
                "hk_cnn_set_params", "hk_cnn_get_params", "hk_cnn_set_norm", "hk_cnn_forward",
                "hk_cnn_loss_grad", "hk_cnn_train_step", "hk_cnn_last_error", "hk_set_cnn", "hk_node_inputs",
+               "hk_sp_nparams", "hk_sp_create", "hk_sp_destroy", "hk_sp_set_params", "hk_sp_get_params",
+               "hk_sp_set_norm", "hk_sp_forward", "hk_sp_loss_grad", "hk_sp_train_step", "hk_sp_last_error",
                "hk_real_size", "hk_strerror", "hk_last_error", "hk_save", "hk_load"]
 
 _libs: dict = {}
@@ -153,6 +161,19 @@ def load(prec: str = "f32"):
     L.hk_cnn_last_error.restype = C.c_char_p
     L.hk_cnn_last_error.argtypes = [vp]
     L.hk_set_cnn.argtypes = [vp, vp]
+    L.hk_sp_nparams.restype = C.c_int
+    L.hk_sp_create.argtypes = [P(CnnDesc), P(vp)]
+    L.hk_sp_destroy.argtypes = [vp]
+    L.hk_sp_destroy.restype = None
+    L.hk_sp_set_params.argtypes = [vp, vp, C.c_size_t]
+    L.hk_sp_get_params.argtypes = [vp, vp, C.c_size_t]
+    L.hk_sp_set_norm.argtypes = [vp, vp, vp]
+    L.hk_sp_forward.argtypes = [vp, vp] + [C.c_int] * 5 + [vp]
+    L.hk_sp_loss_grad.argtypes = [vp, vp, vp] + [C.c_int] * 4 + [C.c_double, C.c_double, C.c_int, vp,
+                                                                 P(C.c_double)]
+    L.hk_sp_train_step.argtypes = [vp, vp, vp] + [C.c_int] * 4 + [P(SpTrainDesc), P(C.c_double)]
+    L.hk_sp_last_error.restype = C.c_char_p
+    L.hk_sp_last_error.argtypes = [vp]
     L.hk_node_inputs.argtypes = [vp, vp, vp, vp, C.c_size_t]
     L.hk_real_size.restype = C.c_int
     L.hk_strerror.restype = C.c_char_p
@@ -471,4 +492,87 @@ class CNN:
         loss = C.c_double()
         self._check(self.lib.hk_cnn_train_step(self.h, x.data_ptr(), y.data_ptr(), e.data_ptr(), B, D, H,
                                                W, C.byref(t), C.byref(loss)))
+        return loss.value
+
+
+class StatePredictor:
+    """The next-state surrogate on the GPU (device memory from torch's
+    allocator).  Patches are torch tensors on cuda:0: x and y [B, D, H, W, 10]
+    float32, normalized."""
+
+    def __init__(self, seed: int = 0, precision: str = "f32"):
+        self.lib = load(precision)
+        self._mem = _TorchMemory()
+        d = CnnDesc(seed=seed, stream=self._mem.stream.cuda_stream, alloc=self._mem.alloc,
+                    free=self._mem.free, alloc_ctx=None)
+        h = C.c_void_p()
+        rc = self.lib.hk_sp_create(C.byref(d), C.byref(h))
+        if rc:
+            raise HKError(rc, "hk_sp_create failed")
+        self.h = h
+        self.nparams = self.lib.hk_sp_nparams()
+
+    @property
+    def stream(self):
+        return self._mem.stream
+
+    def _check(self, rc):
+        if rc:
+            raise HKError(rc, self.lib.hk_sp_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hk_sp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, np.float32)
+        assert a.size == self.nparams
+        self._check(self.lib.hk_sp_set_params(self.h, _ptr(a), a.size))
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(self.nparams, np.float32)
+        self._check(self.lib.hk_sp_get_params(self.h, _ptr(a), a.size))
+        return a
+
+    def set_norm(self, mean, std):
+        m = np.ascontiguousarray(mean, np.float32); s = np.ascontiguousarray(std, np.float32)
+        assert m.size == 10 and s.size == 10
+        self._check(self.lib.hk_sp_set_norm(self.h, _ptr(m), _ptr(s)))
+
+    def forward(self, x, mask_step=-1, out=None):
+        import torch
+        x = x.contiguous()
+        B, D, H, W, C_ = x.shape
+        assert C_ == 10 and x.dtype == torch.float32
+        if out is None:
+            out = torch.empty_like(x)
+        self._check(self.lib.hk_sp_forward(self.h, x.data_ptr(), B, D, H, W, int(mask_step), out.data_ptr()))
+        return out
+
+    def loss_grad(self, x, y, delta=0.01, lam=0.1, mask_step=-1, grad=True):
+        x = x.contiguous(); y = y.contiguous()
+        B, D, H, W, _ = x.shape
+        assert y.shape == x.shape
+        g = np.empty(self.nparams, np.float32) if grad else None
+        loss = C.c_double()
+        self._check(self.lib.hk_sp_loss_grad(self.h, x.data_ptr(), y.data_ptr(), B, D, H, W, float(delta),
+                                             float(lam), int(mask_step), None if g is None else _ptr(g),
+                                             C.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, x, y, lr=1e-3, delta=0.01, lam=0.1, dropout=True, weight_decay=0.01):
+        x = x.contiguous(); y = y.contiguous()
+        B, D, H, W, _ = x.shape
+        t = SpTrainDesc(lr=lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=weight_decay, delta=delta,
+                        lambda_e=lam, dropout=int(dropout))
+        loss = C.c_double()
+        self._check(self.lib.hk_sp_train_step(self.h, x.data_ptr(), y.data_ptr(), B, D, H, W, C.byref(t),
+                                              C.byref(loss)))
         return loss.value
