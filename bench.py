@@ -184,6 +184,54 @@ def cnn_inference(reps=20):
             "grid": "129 x 64 x 64 nodes + halo 4"}
 
 
+SP_CIN, SP_COUT = (10, 13, 32, 64, 128, 32), (13, 32, 64, 128, 32, 10)
+
+
+def sp_surrogate(B=64, reps=20, train_reps=5):
+    """The next-state surrogate on B patches of 16^3 nodes (the paper's grid
+    size): one forward pass and one training step (forward, loss, both
+    gradients, AdamW), timed with HIP events on the library stream.  Flops are
+    those of the six convolutions with their real channel counts: forward
+    2 * 27 * sum(cin cout) per voxel, training three times that less the data
+    gradient of the first layer, which is not needed."""
+    import torch
+
+    from paper_2510_11174_amd import hk
+    from paper_2510_11174_amd import train as T
+    sp = hk.StatePredictor(seed=1)
+    sp.set_params(T.sp_init_params(1))
+    x = torch.randn((B, 16, 16, 16, 10), device="cuda", dtype=torch.float32)
+    y = 0.9 * x
+    out = torch.empty_like(x)
+    nvox = B * 16 ** 3
+    f = [2 * 27 * ci * co * nvox for ci, co in zip(SP_CIN, SP_COUT)]
+    flops_fwd, flops_train = sum(f), 3 * sum(f) - f[0]
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        sp.forward(x, out=out)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        sp.forward(x, out=out)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    sp.train_step(x, y, lr=1e-5)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(train_reps):
+        sp.train_step(x, y, lr=1e-5)
+    b.record()
+    torch.cuda.synchronize()
+    ms_t = a.elapsed_time(b) / train_reps
+    sp.close()
+    tf = flops_fwd / (ms * 1e-3) / 1e12
+    return {"bound": "mfma", "achieved": round(tf, 1), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4), "kernel": "k_sp_conv (6 layers, forward)",
+            "ms_forward": round(ms, 3), "flop_forward": flops_fwd, "ms_train_step": round(ms_t, 3),
+            "train_tflops": round(flops_train / (ms_t * 1e-3) / 1e12, 1), "patches": "%d x 16^3" % B}
+
+
 def field_l2(x, y):
     import numpy as np
     num = math.sqrt(sum(float(np.sum((x[c] - y[c]) ** 2)) for c in x))
@@ -202,6 +250,8 @@ def main():
                     help="comma list of switch modes to run (profiling runs may pick one)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--surrogate-only", action="store_true",
+                    help="only measure the next-state surrogate (64 patches of 16^3) and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the multi-GPU path (domain decomposition) is not "
@@ -212,6 +262,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     from paper_2510_11174_amd import configs
+    if args.surrogate_only:
+        print(json.dumps({"roofline_state_predictor": sp_surrogate()}))
+        return
     if args.calibrate_copy:
         copy_calibration()
         return
@@ -291,6 +344,7 @@ def main():
         "rebins": {"hybrid": h["timers"]["rebins"], "all_pic": p["timers"]["rebins"]},
     }
     out["roofline_cnn_switch"] = cnn_inference()
+    out["roofline_state_predictor"] = sp_surrogate()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

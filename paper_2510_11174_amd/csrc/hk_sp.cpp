@@ -120,14 +120,10 @@ int check_shape(hk_sp *c, int B, int D, int H, int W, bool train) {
     return HK_OK;
 }
 
-SpConv conv_args(int B, int D, int H, int W, int cpin, int cols) {
+SpConv conv_args(int B, int D, int H, int W, int cols) {
     SpConv a{};
     a.B = B; a.D = D; a.H = H; a.W = W;
     a.cols = cols;
-    const long long rows = (long long)B * D * H * ((W + 15) / 16);
-    a.G = cols / (16 * ntile(cols));
-    a.ntask = (int)((rows + sp_conv_mt() - 1) / sp_conv_mt() * a.G);
-    (void)cpin;
     return a;
 }
 
@@ -149,7 +145,7 @@ int forward(hk_sp *c, const float *x, int B, int D, int H, int W, int mask_step,
     sp_launch_input(n, per, x, act[0], actT[0], c->s);
     for (int l = 0; l < NL; ++l) {
         const int cpin = cp(CIN[l]), cols = cp(COUT[l]);
-        SpConv a = conv_args(B, D, H, W, cpin, cols);
+        SpConv a = conv_args(B, D, H, W, cols);
         a.in = act[l];
         a.wp = c->Wf[l];
         a.cout = COUT[l];
@@ -165,7 +161,7 @@ int forward(hk_sp *c, const float *x, int B, int D, int H, int W, int mask_step,
             a.aout = act[l + 1];
             a.aT = train ? actT[l + 1] : nullptr;
         }
-        if (sp_launch_conv(cpin, ntile(cols), false, a, c->s))
+        if (sp_launch_conv(cpin, false, a, c->s))
             return fail(c, HK_EINVAL, "no convolution kernel for %d -> %d channels", cpin, cols);
     }
     return HK_OK;
@@ -311,7 +307,7 @@ int hk_sp_loss_grad(hk_sp *c, const float *x, const float *y, int B, int D, int 
         sp_launch_bias_grad(n, cpo, COUT[l], dz[cur], c->g + b_off(l), s);
         if (l == 0) break;
         // data gradient into the layer below's pre-activation gradient
-        SpConv a = conv_args(B, D, H, W, cpo, cpi);
+        SpConv a = conv_args(B, D, H, W, cpi);
         a.in = dz[cur];
         a.wp = c->Wb[l];
         a.cout = CIN[l];
@@ -325,7 +321,7 @@ int hk_sp_loss_grad(hk_sp *c, const float *x, const float *y, int B, int D, int 
         a.zin = (const unsigned short *)c->w[W_Z + l - 1];
         a.aout = dz[cur ^ 1];
         a.aT = dzT[cur ^ 1];
-        if (sp_launch_conv(cpo, ntile(cpi), true, a, s))
+        if (sp_launch_conv(cpo, true, a, s))
             return fail(c, HK_EINVAL, "no data-gradient kernel for %d -> %d channels", cpo, cpi);
         cur ^= 1;
     }

@@ -26,7 +26,7 @@ struct SpConv {
     int gin_ch, gin_stride;
     float *gout;                    // gradient after dropout of the layer below (or null)
     const unsigned short *zin;      // BF16 pre-activations of the layer below
-    int ntask, G;                   // wave tasks, column groups
+    int ntask, G;                   // work items, column groups (set by the launcher)
 };
 
 // Weight gradient of one convolution from the channel-major copies.
@@ -42,8 +42,7 @@ struct SpWgrad {
 
 struct SpNorm { float mean[10], stdv[10]; };
 
-int sp_conv_mt();
-int sp_launch_conv(int cpin, int nt, bool bwd, const SpConv &a, hipStream_t s);
+int sp_launch_conv(int cpin, bool bwd, const SpConv &a, hipStream_t s);
 int sp_launch_wgrad(int nt, const SpWgrad &a, hipStream_t s);
 void sp_launch_bias_grad(long long n, int cols, int cout, const unsigned short *dz, float *gb, hipStream_t s);
 void sp_launch_energy(long long n, long long per, const float *p, const float *y, const SpNorm &nm, double *U,

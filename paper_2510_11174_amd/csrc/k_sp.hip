@@ -61,6 +61,57 @@ __device__ inline float keep(uint64_t seed, uint64_t v, uint32_t step, int c) {
 __device__ inline int xcd_block(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
 
 // ------------------------------------------------------------ convolution
+// Epilogue of one 16-voxel row tile (voxels x0 .. x0 + 15 of row (b, z, y)):
+// lane (r, g) holds channel co = 16 (cg NT + nt) + r of voxels x0 + 4 g + i.
+// Forward: bias, BF16 pre-activation (training), ReLU, residual copy,
+// dropout, one rounding to BF16 (or the FP32 output of the last layer).
+// Data gradient: residual-path gradient, dropout, ReLU derivative of the
+// layer below, BF16.  Both write the channel-major copy when asked.
+template <int CPIN, int NT, bool BWD>
+__device__ inline void store_row(const SpConv &a, const f32x4 (&acc)[NT], int b, int z, int y, int x0, int cg,
+                                 int r, int g) {
+    const long long HW = (long long)a.H * a.W;
+    const int xg = x0 + 4 * g;
+    const long long vrow = ((long long)b * a.D + z) * HW + (long long)y * a.W;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int co = (cg * NT + nt) * 16 + r;
+        const bool real_c = co < a.cout;
+        u16 ov[4] = {0, 0, 0, 0};
+        for (int i = 0; i < 4; ++i) {
+            const int x = xg + i;
+            if (x >= a.W) continue;
+            const long long v = vrow + x;
+            float s = acc[nt][i];
+            if (!BWD) {
+                s += real_c ? a.bias[co] : 0.f;
+                if (a.zout) a.zout[v * a.cols + co] = real_c ? bf16_bits(s) : (u16)0;
+                float o = a.relu ? fmaxf(s, 0.f) : s;
+                if (co < a.res) o += bf16_val(a.in[v * CPIN + co]);
+                if (a.fout) {
+                    if (real_c) a.fout[v * a.cout + co] = o;
+                    continue;
+                }
+                if (a.drop) o *= keep(a.seed, (uint64_t)v, a.step, co);
+                ov[i] = real_c ? bf16_bits(o) : (u16)0;
+            } else {
+                if (co < a.gin_ch) s += a.gin[v * a.gin_stride + co];
+                if (a.drop) s *= keep(a.seed, (uint64_t)v, a.step, co);
+                if (a.gout) a.gout[v * a.cols + co] = s;
+                const float d = bf16_val(a.zin[v * a.cols + co]) > 0.f ? s : 0.f;
+                ov[i] = real_c ? bf16_bits(d) : (u16)0;
+            }
+            a.aout[v * a.cols + co] = ov[i];
+        }
+        if (a.aT && xg < a.W) {
+            // channel-major copy: 4 consecutive x of channel co (W % 4 == 0)
+            const long long o = (((long long)b * a.cols + co) * a.D + z) * HW + (long long)y * a.W + xg;
+            *reinterpret_cast<uint2 *>(a.aT + o) =
+                make_uint2((unsigned)ov[0] | ((unsigned)ov[1] << 16), (unsigned)ov[2] | ((unsigned)ov[3] << 16));
+        }
+    }
+}
+
 template <int CPIN, int MT, int NT, bool BWD>
 __global__ void __launch_bounds__(SBS) k_sp_conv(SpConv a) {
     constexpr int K = 27 * CPIN, KPAD = (K + 31) / 32 * 32, NK = KPAD / 32;
@@ -159,48 +210,120 @@ __global__ void __launch_bounds__(SBS) k_sp_conv(SpConv a) {
         q /= a.H;
         const int z = (int)(q % a.D);
         const int b = (int)(q / a.D);
-        const int xg = seg * 16 + 4 * g;
-        const long long vrow = ((long long)b * a.D + z) * HW + (long long)y * a.W;
+        store_row<CPIN, NT, BWD>(a, acc[m], b, z, y, seg * 16, cg, r, g);
+    }
+}
+
+// Halo-tiled variant for 32 or more input channels.  A workgroup owns 16 x MT
+// x 4 output voxels (x segment, MT rows in y, 4 in z: wave w takes z slice w)
+// and one column group.  For each 32-channel slice of the input it stages the
+// tile's halo, 18 x (MT + 2) x 6 voxels of 64 bytes, in LDS with coalesced
+// 16-byte loads, then runs the 27 taps of the slice: A fragments come from LDS
+// (16 consecutive voxels of 64 bytes; the four 16-byte pieces of voxel h are
+// stored in the order given by XOR with (h / 2) % 4, so eight consecutive
+// lanes reading the same piece of eight voxels hit 32 different banks), one
+// tap ahead; B fragments come from the weight matrix in global memory, three
+// taps ahead (the four waves read the same B, so it stays in L1).  Each input
+// voxel is fetched once per slice instead of once per tap.
+constexpr int HZ = 4;   // tile depth in z (one slice per wave)
+#ifndef SP_HALO_NT
+#define SP_HALO_NT 2
+#endif
+template <int CPIN, int MT, int NT, bool BWD>
+__global__ void __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(2, 8))) k_sp_conv_halo(SpConv a) {
+    constexpr int HY = MT + 2, HX = 18, NV = HX * HY * (HZ + 2);
+    constexpr int K = 27 * CPIN, KPAD = (K + 31) / 32 * 32;
+    __shared__ __attribute__((aligned(16))) u16 sH[NV * 32];
+    const int item = xcd_block(blockIdx.x, gridDim.x);
+    if (item >= a.ntask) return;   // uniform over the workgroup
+    const int cg = item % a.G;
+    int q = item / a.G;
+    const int segs = (a.W + 15) >> 4, nty = (a.H + MT - 1) / MT, ntz = (a.D + HZ - 1) / HZ;
+    const int seg = q % segs;
+    q /= segs;
+    const int ty0 = (q % nty) * MT;
+    q /= nty;
+    const int tz0 = (q % ntz) * HZ;
+    const int b = q / ntz;
+    const int x0 = seg * 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
+    const long long HW = (long long)a.H * a.W;
+    const u16 *src = a.in + (long long)b * a.D * HW * CPIN;
+    const u16 *wrow[NT];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const int co = (cg * NT + nt) * 16 + r;
-            const bool real_c = co < a.cout;
-            u16 ov[4] = {0, 0, 0, 0};
-            for (int i = 0; i < 4; ++i) {
-                const int x = xg + i;
-                if (x >= a.W) continue;
-                const long long v = vrow + x;
-                float s = acc[m][nt][i];
-                if (!BWD) {
-                    s += real_c ? a.bias[co] : 0.f;
-                    if (a.zout) a.zout[v * a.cols + co] = real_c ? bf16_bits(s) : (u16)0;
-                    float o = a.relu ? fmaxf(s, 0.f) : s;
-                    if (co < a.res) o += bf16_val(a.in[v * CPIN + co]);
-                    if (a.fout) {
-                        if (real_c) a.fout[v * a.cout + co] = o;
-                        continue;
-                    }
-                    if (a.drop) o *= keep(a.seed, (uint64_t)v, a.step, co);
-                    ov[i] = real_c ? bf16_bits(o) : (u16)0;
-                } else {
-                    // gradient of the layer below's output, through its
-                    // residual copy, dropout and ReLU
-                    if (co < a.gin_ch) s += a.gin[v * a.gin_stride + co];
-                    if (a.drop) s *= keep(a.seed, (uint64_t)v, a.step, co);
-                    if (a.gout) a.gout[v * a.cols + co] = s;
-                    const float d = bf16_val(a.zin[v * a.cols + co]) > 0.f ? s : 0.f;
-                    ov[i] = real_c ? bf16_bits(d) : (u16)0;
-                }
-                a.aout[v * a.cols + co] = ov[i];
-            }
-            if (a.aT && xg < a.W) {
-                // channel-major copy: 4 consecutive x of channel co (W % 4 == 0)
-                const long long o = (((long long)b * a.cols + co) * a.D + z) * HW + (long long)y * a.W + xg;
-                *reinterpret_cast<uint2 *>(a.aT + o) =
-                    make_uint2((unsigned)ov[0] | ((unsigned)ov[1] << 16), (unsigned)ov[2] | ((unsigned)ov[3] << 16));
-            }
+    for (int nt = 0; nt < NT; ++nt) wrow[nt] = a.wp + (long long)((cg * NT + nt) * 16 + r) * KPAD + 8 * g;
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[m][nt] = f32x4{0, 0, 0, 0};
+    // B fragments of linear tap T = slice * 27 + t
+    constexpr int NTAP = CPIN / 32 * 27;
+    auto loadB = [&](int T, uint4 (&bv)[NT]) {
+        // past the last tap: reload the last one (unused), so the loads stay
+        // unconditional and their waits exact
+        T = T < NTAP ? T : NTAP - 1;
+        const int c = T / 27, t = T - 27 * c;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) bv[nt] = *reinterpret_cast<const uint4 *>(wrow[nt] + t * CPIN + 32 * c);
+    };
+    // A fragments of tap t for the wave's MT rows, from the halo
+    auto loadA = [&](int t, uint4 (&av)[MT]) {
+        const int kx = t % 3, ky = (t / 3) % 3, kz = t / 9;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int hv = ((wave + kz) * HY + (m + ky)) * HX + r + kx;
+            av[m] = *reinterpret_cast<const uint4 *>(sH + hv * 32 + 8 * (g ^ ((hv >> 1) & 3)));
+        }
+    };
+    auto mma = [&](const uint4 (&av)[MT], const uint4 (&bv)[NT]) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                acc[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av[m]),
+                                                                    __builtin_bit_cast(bf16x8, bv[nt]), acc[m][nt],
+                                                                    0, 0, 0);
+    };
+    uint4 b0[NT], b1[NT], b2[NT];
+    loadB(0, b0);
+    loadB(1, b1);
+    loadB(2, b2);
+    for (int c0 = 0; c0 < CPIN; c0 += 32) {
+        __syncthreads();   // the previous slice is consumed
+        for (int p = threadIdx.x; p < NV * 4; p += SBS) {
+            const int hv = p >> 2, part = p & 3;
+            const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+            const int x = x0 - 1 + hx, y = ty0 - 1 + hy, z = tz0 - 1 + hz;
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if (x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D)
+                val = *reinterpret_cast<const uint4 *>(src + ((long long)z * HW + (long long)y * a.W + x) * CPIN +
+                                                       c0 + part * 8);
+            *reinterpret_cast<uint4 *>(sH + hv * 32 + 8 * (part ^ ((hv >> 1) & 3))) = val;
+        }
+        __syncthreads();
+        const int T0 = c0 / 32 * 27;
+        uint4 a0[MT], a1[MT];
+        loadA(0, a0);
+        for (int t = 0; t < 27; t += 3) {
+            loadA(t + 1, a1);
+            mma(a0, b0);
+            loadB(T0 + t + 3, b0);
+            loadA(t + 2, a0);
+            mma(a1, b1);
+            loadB(T0 + t + 4, b1);
+            loadA(t + 3 < 27 ? t + 3 : 26, a1);
+            mma(a0, b2);
+            loadB(T0 + t + 5, b2);
+#pragma unroll
+            for (int m = 0; m < MT; ++m) a0[m] = a1[m];
         }
     }
+    const int z = tz0 + wave;
+    if (z >= a.D) return;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+        if (ty0 + m < a.H) store_row<CPIN, NT, BWD>(a, acc[m], b, z, ty0 + m, x0, cg, r, g);
 }
 
 // -------------------------------------------------------- weight gradient
@@ -435,32 +558,53 @@ inline unsigned nblk(long long n) { return (unsigned)((n + SBS - 1) / SBS); }
 inline unsigned grid8(long long items) { return (unsigned)((items + 7) / 8 * 8); }
 
 template <int CPIN, int NT, bool BWD>
-void conv_go(const SpConv &a, hipStream_t s) {
-    constexpr int MT = 4;
-    k_sp_conv<CPIN, MT, NT, BWD><<<grid8((a.ntask + 3) / 4), SBS, 0, s>>>(a);
+void conv_go(SpConv a, hipStream_t s) {
+    const int segs = (a.W + 15) / 16;
+    a.G = a.cols / (16 * NT);
+    if constexpr (CPIN >= 32) {
+        // eight rows per wave where a row feeds only one or two column tiles
+        constexpr int MT = NT <= 2 ? 8 : 4;
+        const long long tiles = (long long)a.B * ((a.D + HZ - 1) / HZ) * ((a.H + MT - 1) / MT) * segs;
+        a.ntask = (int)(tiles * a.G);
+        k_sp_conv_halo<CPIN, MT, NT, BWD><<<grid8(a.ntask), SBS, 0, s>>>(a);
+    } else {
+        constexpr int MT = 4;
+        const long long rows = (long long)a.B * a.D * a.H * segs;
+        a.ntask = (int)((rows + MT - 1) / MT * a.G);
+        k_sp_conv<CPIN, MT, NT, BWD><<<grid8((a.ntask + 3) / 4), SBS, 0, s>>>(a);
+    }
 }
 
 }  // namespace
 
 // ----------------------------------------------------------------- launchers
-int sp_conv_mt() { return 4; }
-
-int sp_launch_conv(int cpin, int nt, bool bwd, const SpConv &a, hipStream_t s) {
+int sp_launch_conv(int cpin, bool bwd, const SpConv &a, hipStream_t s) {
+    // column tiles per wave: up to 4 on the 16-channel inputs; on the halo
+    // path two (with eight rows per wave), which keeps the wave's working set
+    // in registers at two waves per SIMD
+    const int ct = a.cols / 16;
+    const int nt = cpin >= 32 ? (ct < SP_HALO_NT ? ct : SP_HALO_NT) : (ct < 4 ? ct : 4);
     const int key = cpin * 100 + nt * 10 + (bwd ? 1 : 0);
     switch (key) {
-    // forward: 16->16, 16->32, 32->64, 64->128, 128->32, 32->16
     case 1610: conv_go<16, 1, false>(a, s); break;
     case 1620: conv_go<16, 2, false>(a, s); break;
-    case 3240: conv_go<32, 4, false>(a, s); break;
-    case 6440: conv_go<64, 4, false>(a, s); break;
-    case 12820: conv_go<128, 2, false>(a, s); break;
-    case 3210: conv_go<32, 1, false>(a, s); break;
-    // data gradient: 16->32, 32->128, 128->64, 64->32, 32->16
     case 1621: conv_go<16, 2, true>(a, s); break;
-    case 3241: conv_go<32, 4, true>(a, s); break;
-    case 12841: conv_go<128, 4, true>(a, s); break;
-    case 6421: conv_go<64, 2, true>(a, s); break;
+    case 3210: conv_go<32, 1, false>(a, s); break;
     case 3211: conv_go<32, 1, true>(a, s); break;
+    case 3220: conv_go<32, 2, false>(a, s); break;
+    case 3221: conv_go<32, 2, true>(a, s); break;
+    case 6420: conv_go<64, 2, false>(a, s); break;
+    case 6421: conv_go<64, 2, true>(a, s); break;
+    case 12820: conv_go<128, 2, false>(a, s); break;
+    case 12821: conv_go<128, 2, true>(a, s); break;
+#if SP_HALO_NT >= 4
+    case 3240: conv_go<32, 4, false>(a, s); break;
+    case 3241: conv_go<32, 4, true>(a, s); break;
+    case 6440: conv_go<64, 4, false>(a, s); break;
+    case 6441: conv_go<64, 4, true>(a, s); break;
+    case 12840: conv_go<128, 4, false>(a, s); break;
+    case 12841: conv_go<128, 4, true>(a, s); break;
+#endif
     default: return -1;
     }
     return 0;

@@ -67,6 +67,17 @@ def init_params(seed=0):
     return np.concatenate(parts).astype(np.float32)
 
 
+def sp_init_params(seed=0):
+    """Next-state surrogate: He-normal convolution weights and zero biases in
+    the library's parameter layout (per layer W[27][cin][cout], b[cout])."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for cin, cout in zip((10, 13, 32, 64, 128, 32), (13, 32, 64, 128, 32, 10)):
+        parts.append(rng.normal(0, np.sqrt(2.0 / (27 * cin)), 27 * cin * cout))
+        parts.append(np.zeros(cout))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def stats(data):
     x = np.concatenate([d[0].reshape(-1, 8) for d in data])
     mean = x.mean(0)
