@@ -312,6 +312,13 @@ const char *hk_cnn_last_error(const hk_cnn *cnn);
  * conversion would destroy; hot[n] the threshold criterion's undilated flags
  * now.  The switch map is left unchanged.  n must equal NX ny nz. */
 int hk_node_inputs(hk_sim *sim, double *raw, double *ehat, uint8_t *hot, size_t n);
+/* States for the next-state surrogate, per node of the grid [nz][ny][NX] as
+ * above: out (device FP32, 10 n values, channels last) = Ex, Ey, Ez, Bx, By,
+ * Bz averaged to the node from their Yee positions (neighbour means; open x
+ * repeats the wall cell), Jx, Jy, Jz averaged the same way as E, and the
+ * charge density rho at the node (particles and fluid); not normalized.  The
+ * simulation is left unchanged.  n must equal NX ny nz. */
+int hk_node_state(hk_sim *sim, float *out, size_t n);
 /* the network the simulation's HK_SW_CNN mode uses (borrowed; NULL detaches;
  * without one the mode decides by the thresholds alone) */
 int hk_set_cnn(hk_sim *sim, hk_cnn *cnn);

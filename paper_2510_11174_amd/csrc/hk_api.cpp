@@ -19,6 +19,7 @@
 void cnn_launch_inputs(const GridP &g, real *const f[9], const real *mom, const float mean[8],
                        const float inv_std[8], unsigned short *x, hipStream_t s);
 void cnn_launch_node_raw(const GridP &g, real *const f[9], const real *mom, float *out, hipStream_t s);
+void cnn_launch_node_state(const GridP &g, real *const f[9], const double *rho, float *out, hipStream_t s);
 void cnn_launch_decide(const GridP &g, const unsigned short *a4, const unsigned short *wh, const float *bh,
                        uint64_t seed, uint32_t eval, uint8_t *hot, uint8_t *notcold, int *nfall,
                        float *pmean, hipStream_t s);
@@ -1339,6 +1340,18 @@ int hk_set_field(hk_sim *S, int comp, const void *host_in, size_t bytes) {
     HIPCHK(S, hipMemcpyAsync(S->f[comp], host_in, bytes, hipMemcpyHostToDevice, S->s));
     HIPCHK(S, hipStreamSynchronize(S->s));
     S->have_gauss0 = 0;
+    return HK_OK;
+}
+
+int hk_node_state(hk_sim *S, float *dev_out, size_t nodes) {
+    if (!S || !dev_out) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    const GridP &g = S->g;
+    const size_t n = (size_t)(g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1) * g.ny * g.nz;
+    if (nodes != n) return fail(S, HK_EINVAL, "node count %zu, expected %zu", nodes, n);
+    rho_total(S, S->tmp_a);
+    cnn_launch_node_state(g, S->f, S->tmp_a, dev_out, S->s);
+    HIPCHK(S, hipStreamSynchronize(S->s));
     return HK_OK;
 }
 

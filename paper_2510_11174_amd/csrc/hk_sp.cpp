@@ -284,13 +284,15 @@ int hk_sp_loss_grad(hk_sp *c, const float *x, const float *y, int B, int D, int 
     int cur = 0;
     for (int l = NL - 1; l >= 0; --l) {
         const int cpi = cp(CIN[l]), cpo = cp(COUT[l]);
-        // weight gradient: K = 8-voxel blocks, chunks sized for ~1024 workgroups
+        // weight and bias gradients: K = 8-voxel blocks, chunks sized for
+        // ~1024 workgroups
         SpWgrad wg{};
         wg.B = B; wg.D = D; wg.H = H; wg.W = W;
         wg.aT = (const unsigned short *)c->w[W_ACTT + l];
         wg.dT = dzT[cur];
         wg.cpi = cpi; wg.cpo = cpo; wg.cin = CIN[l]; wg.cout = COUT[l];
         wg.gw = c->g + w_off(l);
+        wg.gb = c->g + b_off(l);
         const int wnt = ntile(cpo);
         wg.mtn = cpi / 16;
         wg.ngn = cpo / (16 * wnt);
@@ -304,7 +306,6 @@ int hk_sp_loss_grad(hk_sp *c, const float *x, const float *y, int B, int D, int 
         chunks = (wg.nks + wg.kpc - 1) / wg.kpc;
         wg.nitems = (int)(base * chunks);
         if (sp_launch_wgrad(wnt, wg, s)) return fail(c, HK_EINVAL, "no weight-gradient kernel");
-        sp_launch_bias_grad(n, cpo, COUT[l], dz[cur], c->g + b_off(l), s);
         if (l == 0) break;
         // data gradient into the layer below's pre-activation gradient
         SpConv a = conv_args(B, D, H, W, cpi);

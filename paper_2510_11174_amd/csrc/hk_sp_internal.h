@@ -36,6 +36,7 @@ struct SpWgrad {
     const unsigned short *dT;       // [B][cpo][D][H][W] pre-activation gradient
     int cpi, cpo, cin, cout;
     float *gw;                      // [27][cin][cout], accumulated
+    float *gb;                      // [cout] bias gradient, accumulated (or null)
     int mtn, ngn, nitems;           // ci tiles, co groups, workgroups
     long long nblk, nks, kpc;       // 8-voxel blocks, K steps (4 blocks), steps per chunk
 };
@@ -44,7 +45,6 @@ struct SpNorm { float mean[10], stdv[10]; };
 
 int sp_launch_conv(int cpin, bool bwd, const SpConv &a, hipStream_t s);
 int sp_launch_wgrad(int nt, const SpWgrad &a, hipStream_t s);
-void sp_launch_bias_grad(long long n, int cols, int cout, const unsigned short *dz, float *gb, hipStream_t s);
 void sp_launch_energy(long long n, long long per, const float *p, const float *y, const SpNorm &nm, double *U,
                       hipStream_t s);
 void sp_launch_loss(long long n, long long per, int B, const float *p, const float *y, const SpNorm &nm,

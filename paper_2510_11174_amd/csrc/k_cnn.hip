@@ -415,6 +415,32 @@ k_node_raw(GridP g, const real *__restrict__ Ex, const real *__restrict__ Ey, co
     o[8] = N > 0.0 ? (float)fmax(0.0, 0.5 * (U2 - (px * px + py * py + pz * pz) / N)) : 0.f;
 }
 
+// States of the canonical node grid [nz][ny][NX] for the next-state
+// surrogate, 10 channels per node: E and B averaged to the node as above, J
+// averaged like E (its components sit where E's do), and the charge density.
+__global__ void __launch_bounds__(CBS)
+k_node_state(GridP g, const real *__restrict__ Ex, const real *__restrict__ Ey, const real *__restrict__ Ez,
+             const real *__restrict__ Bx, const real *__restrict__ By, const real *__restrict__ Bz,
+             const real *__restrict__ Jx, const real *__restrict__ Jy, const real *__restrict__ Jz,
+             const double *__restrict__ rho, float *__restrict__ out) {
+    const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
+    const long long n = (long long)NX * g.ny * g.nz;
+    const long long v = (long long)blockIdx.x * CBS + threadIdx.x;
+    if (v >= n) return;
+    const int i = (int)(v % NX), j = (int)((v / NX) % g.ny), k = (int)(v / ((long long)NX * g.ny));
+    float *o = out + 10 * v;
+    o[0] = node_field(g, Ex, i, j, k, 1, 0, 0);
+    o[1] = node_field(g, Ey, i, j, k, 0, 1, 0);
+    o[2] = node_field(g, Ez, i, j, k, 0, 0, 1);
+    o[3] = node_field(g, Bx, i, j, k, 0, 1, 1);
+    o[4] = node_field(g, By, i, j, k, 1, 0, 1);
+    o[5] = node_field(g, Bz, i, j, k, 1, 1, 0);
+    o[6] = node_field(g, Jx, i, j, k, 1, 0, 0);
+    o[7] = node_field(g, Jy, i, j, k, 0, 1, 0);
+    o[8] = node_field(g, Jz, i, j, k, 0, 0, 1);
+    o[9] = (float)rho[gidx(g, i, j, k)];
+}
+
 // 16 dropout samples of the head per node: mean p > 0.5 is kinetic unless the
 // samples' standard deviation exceeds 0.2 (then the threshold flags stay)
 __global__ void __launch_bounds__(CBS)
@@ -543,6 +569,13 @@ void cnn_launch_node_raw(const GridP &g, real *const f[9], const real *mom, floa
     const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
     const long long n = (long long)NX * g.ny * g.nz;
     k_node_raw<<<nblk(n), CBS, 0, s>>>(g, f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], mom, out);
+}
+
+void cnn_launch_node_state(const GridP &g, real *const f[9], const double *rho, float *out, hipStream_t s) {
+    const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
+    const long long n = (long long)NX * g.ny * g.nz;
+    k_node_state<<<nblk(n), CBS, 0, s>>>(g, f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], f[HK_JX],
+                                          f[HK_JY], f[HK_JZ], rho, out);
 }
 
 void cnn_launch_decide(const GridP &g, const unsigned short *a4, const unsigned short *wh, const float *bh,

@@ -337,6 +337,7 @@ __global__ void __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(2, 8))
 template <int NT>
 __global__ void __launch_bounds__(SBS) k_sp_wgrad(SpWgrad a) {
     __shared__ f32x4 red[SBS / 64 - 1][3 * NT][64];
+    __shared__ float sb[NT * 16];
     const int item = xcd_block(blockIdx.x, gridDim.x);
     if (item >= a.nitems) return;   // uniform over the workgroup
     int q = item;
@@ -349,6 +350,13 @@ __global__ void __launch_bounds__(SBS) k_sp_wgrad(SpWgrad a) {
     const int ky = p % 3, kz = p / 3;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
     const int xbn = a.W >> 3;
+    // the centre-tap workgroups of the first ci tile also sum dz: the bias
+    // gradient, each voxel counted once per column group
+    const bool bias = a.gb && p == 4 && mt == 0;
+    float bsum[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) bsum[nt] = 0.f;
+    if (threadIdx.x < NT * 16) sb[threadIdx.x] = 0.f;
     const long long HW = (long long)a.H * a.W, DHW = HW * a.D;
     const int ci = mt * 16 + r;
     f32x4 acc[3][NT];
@@ -387,6 +395,13 @@ __global__ void __launch_bounds__(SBS) k_sp_wgrad(SpWgrad a) {
         }
         // x shifted by -1 (kx = 0) and +1 (kx = 2): element j of the fragment
         // is a[x + j + kx - 1]; the low half of a word is the even element
+        if (bias)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const uint4 v = Bv[nt];
+                bsum[nt] += (bf16_val((u16)v.x) + bf16_val((u16)(v.x >> 16))) + (bf16_val((u16)v.y) + bf16_val((u16)(v.y >> 16))) +
+                            (bf16_val((u16)v.z) + bf16_val((u16)(v.z >> 16))) + (bf16_val((u16)v.w) + bf16_val((u16)(v.w >> 16)));
+            }
         const uint4 A0 = make_uint4((L.w >> 16) | (M.x << 16), (M.x >> 16) | (M.y << 16),
                                     (M.y >> 16) | (M.z << 16), (M.z >> 16) | (M.w << 16));
         const uint4 A2 = make_uint4((M.x >> 16) | (M.y << 16), (M.y >> 16) | (M.z << 16),
@@ -405,6 +420,15 @@ __global__ void __launch_bounds__(SBS) k_sp_wgrad(SpWgrad a) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) red[wave - 1][kx * NT + nt][lane] = acc[kx][nt];
     __syncthreads();
+    if (bias) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) atomicAdd(&sb[nt * 16 + r], bsum[nt]);
+        __syncthreads();   // uniform: bias depends on the workgroup only
+        if (threadIdx.x < NT * 16) {
+            const int co = ng * NT * 16 + threadIdx.x;
+            if (co < a.cout && sb[threadIdx.x] != 0.f) atomicAdd(&a.gb[co], sb[threadIdx.x]);
+        }
+    }
     if (wave != 0) return;
 #pragma unroll
     for (int kx = 0; kx < 3; ++kx)
@@ -420,21 +444,6 @@ __global__ void __launch_bounds__(SBS) k_sp_wgrad(SpWgrad a) {
                     atomicAdd(&a.gw[((long long)t * a.cin + c) * a.cout + co], s[i]);
             }
         }
-}
-
-// bias gradient: gb[co] += sum_v dz[v][co] (cols divides SBS)
-__global__ void __launch_bounds__(SBS)
-k_sp_bias_grad(long long n, int cols, int cout, const u16 *__restrict__ dz, float *__restrict__ gb) {
-    __shared__ float s[SBS];
-    s[threadIdx.x] = 0.f;
-    __syncthreads();
-    const int per = SBS / cols, c = threadIdx.x % cols;
-    float acc = 0.f;
-    for (long long v = (long long)blockIdx.x * per + threadIdx.x / cols; v < n; v += (long long)gridDim.x * per)
-        acc += bf16_val(dz[v * cols + c]);
-    atomicAdd(&s[c], acc);
-    __syncthreads();
-    if (threadIdx.x < cout && s[threadIdx.x] != 0.f) atomicAdd(&gb[threadIdx.x], s[threadIdx.x]);
 }
 
 // ------------------------------------------------------------------- loss
@@ -619,11 +628,6 @@ int sp_launch_wgrad(int nt, const SpWgrad &a, hipStream_t s) {
     default: return -1;
     }
     return 0;
-}
-
-void sp_launch_bias_grad(long long n, int cols, int cout, const unsigned short *dz, float *gb, hipStream_t s) {
-    long long b = (n * cols + SBS - 1) / SBS;
-    k_sp_bias_grad<<<(unsigned)(b < 1024 ? b : 1024), SBS, 0, s>>>(n, cols, cout, dz, gb);
 }
 
 void sp_launch_energy(long long n, long long per, const float *p, const float *y, const SpNorm &nm, double *U,

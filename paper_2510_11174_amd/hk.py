@@ -108,7 +108,7 @@ ABI_SYMBOLS = ["hk_create", "hk_destroy", "hk_step", "hk_switch_map", "hk_set_sw
                "hk_set_particles", "hk_get_fluid", "hk_set_fluid", "hk_enable_timing",
                "hk_timers", "hk_qed_tables", "hk_cnn_nparams", "hk_cnn_create", "hk_cnn_destroy",
                "hk_cnn_set_params", "hk_cnn_get_params", "hk_cnn_set_norm", "hk_cnn_forward",
-               "hk_cnn_loss_grad", "hk_cnn_train_step", "hk_cnn_last_error", "hk_set_cnn", "hk_node_inputs",
+               "hk_cnn_loss_grad", "hk_cnn_train_step", "hk_cnn_last_error", "hk_set_cnn", "hk_node_inputs", "hk_node_state",
                "hk_sp_nparams", "hk_sp_create", "hk_sp_destroy", "hk_sp_set_params", "hk_sp_get_params",
                "hk_sp_set_norm", "hk_sp_forward", "hk_sp_loss_grad", "hk_sp_train_step", "hk_sp_last_error",
                "hk_real_size", "hk_strerror", "hk_last_error", "hk_save", "hk_load"]
@@ -175,6 +175,7 @@ def load(prec: str = "f32"):
     L.hk_sp_last_error.restype = C.c_char_p
     L.hk_sp_last_error.argtypes = [vp]
     L.hk_node_inputs.argtypes = [vp, vp, vp, vp, C.c_size_t]
+    L.hk_node_state.argtypes = [vp, vp, C.c_size_t]
     L.hk_real_size.restype = C.c_int
     L.hk_strerror.restype = C.c_char_p
     L.hk_strerror.argtypes = [C.c_int]
@@ -394,6 +395,18 @@ class Sim:
         raw = np.empty((n, 8)); e = np.empty(n); hot = np.empty(n, np.uint8)
         self._check(self.lib.hk_node_inputs(self.h, _ptr(raw), _ptr(e), _ptr(hot), n))
         return raw, e, hot
+
+    def node_state(self, out=None):
+        """States for the next-state surrogate: a torch float32 tensor
+        [nz, ny, NX, 10] on the GPU (E, B, J averaged to the nodes, rho)."""
+        import torch
+        g = self.cfg["grid"]
+        nx = g["nx"] if g.get("bc_x", "open") == "periodic" else g["nx"] + 1
+        if out is None:
+            out = torch.empty((self.nz, self.ny, nx, 10), device="cuda", dtype=torch.float32)
+        assert out.is_contiguous() and out.dtype == torch.float32 and out.numel() == nx * self.ny * self.nz * 10
+        self._check(self.lib.hk_node_state(self.h, out.data_ptr(), nx * self.ny * self.nz))
+        return out
 
     def set_cnn(self, cnn):
         """Use `cnn` (a CNN, kept alive by this object) in switch mode "cnn"; None detaches."""

@@ -179,3 +179,70 @@ def test_adamw_steps(hk, oracle_mod):
     assert sure.mean() > 0.5
     assert rl <= 2e-2
     assert losses[-1] < losses[0]
+
+
+def _node_avg(F, hx, hy, hz, periodic_x, nx):
+    """Neighbour mean of a Yee component onto the nodes [nz, ny, NX] (the
+    definition: half-staggered axes average the two samples around the node;
+    y and z wrap; open x repeats the wall cell)."""
+    NX = nx if periodic_x else nx + 1
+    i = np.arange(NX)
+    out = 0.0
+    for a in range(2 if hx else 1):
+        ii = i - 1 + a if hx else i
+        ii = ii % nx if periodic_x else (np.clip(ii, 0, nx - 1) if hx else ii)
+        G = F[:, :, ii]
+        if hy:
+            G = 0.5 * (G + np.roll(G, 1, axis=1))
+        if hz:
+            G = 0.5 * (G + np.roll(G, 1, axis=0))
+        out = out + (0.5 if hx else 1.0) * G
+    return out
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_node_state_matches_fields(hk, periodic):
+    from paper_2510_11174_amd import configs
+    cfg = configs.plain_hybrid(24, 16, 16, mode="all_pic")
+    cfg["species"][0]["u_th"] = 0.05          # currents everywhere
+    if periodic:
+        cfg["grid"]["bc_x"] = "periodic"
+        cfg["laser"]["enabled"] = False
+    print("case: sp node state periodic=%s" % periodic, flush=True)
+    sim = hk.Sim(cfg, precision="f64")
+    sim.step(12)
+    st = sim.node_state().cpu().numpy().astype(np.float64)
+    nx = cfg["grid"]["nx"]
+    F = {c: sim.get_field(c).astype(np.float64) for c in range(9)}
+    stag = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (0, 1, 1), (1, 0, 1), (1, 1, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    NX = nx if periodic else nx + 1
+    for c in range(9):
+        ref = _node_avg(F[c], *stag[c], periodic, nx)
+        scale = max(np.abs(ref).max(), 1e-30)
+        err = np.abs(st[..., c] - ref).max() / scale
+        print("channel %d max |err| / max |ref| = %.2e (max %.3e)" % (c, err, scale))
+        assert err < 1e-6
+    rho = sim.rho()[:, :, :NX]
+    err = np.abs(st[..., 9] - rho).max() / np.abs(rho).max()
+    print("rho max |err| / max = %.2e" % err)
+    assert err < 1e-6
+    sim.close()
+
+
+def test_training_on_simulation_states(hk):
+    import torch
+    from paper_2510_11174_amd import configs, surrogate
+    from paper_2510_11174_amd import train as T
+    cfg = configs.plain_hybrid(32, 16, 16)
+    print("case: sp training on", cfg["name"], flush=True)
+    pairs = surrogate.collect(hk, cfg, steps=40, every=4, horizon=5, start=30)
+    mean, std = surrogate.stats(pairs)
+    sp = hk.StatePredictor(seed=3)
+    sp.set_params(T.sp_init_params(3))
+    losses = surrogate.train(sp, pairs, mean, std, iters=60, B=4, lr=1e-3)
+    gen = torch.Generator().manual_seed(99)
+    x, y = surrogate.patches(pairs, mean, std, 4, gen)
+    r2 = surrogate.r2(sp, x, y)
+    print("pairs %d; loss first %.4f last %.4f; R^2 %.3f" % (len(pairs), np.mean(losses[:5]), np.mean(losses[-10:]), r2))
+    assert np.all(np.isfinite(losses))
+    assert np.mean(losses[-10:]) < 0.5 * np.mean(losses[:5])
