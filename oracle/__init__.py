@@ -21,7 +21,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SOURCES = ["philox.c", "fields.c", "particles.c", "fluid.c", "switch.c", "ionize.c",
-            "qed.c", "cnn.c", "sp.c", "sim.c"]
+            "qed.c", "cnn.c", "sp.c", "swn.c", "sim.c"]
 
 MAX_SPECIES = 6
 MAX_LEVELS = 8
@@ -154,6 +154,11 @@ def lib():
         L.or_sp_loss_grad.argtypes = [C.c_void_p] * 3 + [C.c_int] * 4 + [C.c_void_p, C.c_void_p] + \
             [C.c_double, C.c_double, C.c_void_p, C.c_void_p]
         L.or_sp_mask.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_int, C.c_void_p]
+        L.or_swn_nparam.restype = C.c_int
+        L.or_swn_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+        L.or_swn_loss_grad.restype = C.c_double
+        L.or_swn_loss_grad.argtypes = [C.c_void_p] * 4 + [C.c_int, C.c_double, C.c_void_p, C.c_void_p]
+        L.or_swn_mask.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_int, C.c_void_p]
         L.or_set_cnn.argtypes = [C.c_void_p] * 4
         _lib = L
     return _lib
@@ -482,4 +487,36 @@ def sp_loss_grad(params, x, y, mean, std, delta=0.01, lam=0.1, mask=None):
 def sp_mask(seed: int, voxel: int, step: int, sample: int) -> np.ndarray:
     out = np.empty(32)
     lib().or_sp_mask(int(seed), int(voxel), int(step), int(sample), _ptr(out))
+    return out
+
+
+# ---- SwitchNet ------------------------------------------------------------------------------
+
+def swn_nparam() -> int:
+    return lib().or_swn_nparam()
+
+
+def swn_forward(params, x, mask=None) -> np.ndarray:
+    """Logits of nodes x[n, 10] (normalized features)."""
+    p = np.ascontiguousarray(params, np.float64); x = np.ascontiguousarray(x, np.float64)
+    n = x.shape[0]
+    out = np.empty(n)
+    m = None if mask is None else np.ascontiguousarray(mask, np.float64)
+    lib().or_swn_forward(_ptr(p), _ptr(x), n, None if m is None else _ptr(m), _ptr(out))
+    return out
+
+
+def swn_loss_grad(params, x, y, e, lam=0.1, mask=None):
+    p = np.ascontiguousarray(params, np.float64); x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64); e = np.ascontiguousarray(e, np.float64)
+    g = np.empty(swn_nparam())
+    m = None if mask is None else np.ascontiguousarray(mask, np.float64)
+    loss = lib().or_swn_loss_grad(_ptr(p), _ptr(x), _ptr(y), _ptr(e), x.shape[0], float(lam),
+                                  None if m is None else _ptr(m), _ptr(g))
+    return loss, g
+
+
+def swn_mask(seed: int, node: int, step: int, sample: int) -> np.ndarray:
+    out = np.empty(256)
+    lib().or_swn_mask(int(seed), int(node), int(step), int(sample), _ptr(out))
     return out

@@ -167,4 +167,13 @@ double or_sp_loss_grad(const double *par, const double *x, const double *y, int 
                        const double *mask, double *grad);
 void or_sp_mask(uint64_t seed, uint64_t id, uint32_t step, int sample, double out[32]);
 
+/* SwitchNet (swn.c): parameter count, logits of n nodes' 10 features, loss
+ * (BCE + lambda (1 - p) e) and gradient, dropout factors of its 256-wide
+ * block. */
+int or_swn_nparam(void);
+void or_swn_forward(const double *par, const double *x, int n, const double *mask, double *logit);
+double or_swn_loss_grad(const double *par, const double *x, const double *y, const double *e, int n,
+                        double lambda, const double *mask, double *grad);
+void or_swn_mask(uint64_t seed, uint64_t id, uint32_t step, int sample, double out[256]);
+
 #endif
