@@ -382,6 +382,42 @@ int hk_sp_train_step(hk_sp *sp, const float *x, const float *y, int B, int D, in
                      const hk_sp_train_desc *train, double *loss);
 const char *hk_sp_last_error(const hk_sp *sp);
 
+/* ------------------------------------------------------------------------
+ * The paper's SwitchNet (Results, Table 1 and the paragraph after it): a
+ * per-node fluid/kinetic classifier.  10 features per node (the node state
+ * of hk_node_state, normalized with frozen statistics); Linear 10->128 +
+ * ReLU + residual copy of the input, Linear 128->256 + ReLU + residual copy
+ * with dropout (p = 51/256, kept channels scaled by 256/205, Philox tag 26
+ * keyed by (seed, node index in the call, mask step), sample s using draws
+ * 16 s .. 16 s + 15); 4-head attention over the node's single token (the
+ * softmax over one key is 1, so each head passes its value projection: the
+ * layer computes v = Wv h + bv then Wo v + bo, and the query and key
+ * projections get no gradient); Linear 256->1 to the logit.  BF16 weights
+ * and activations, FP32 accumulation on the matrix cores, FP32 logits.
+ * 297857 parameters (hk_swn_nparams), FP32 masters: W1[10][128], b1,
+ * W2[128][256], b2, Wq, bq, Wk, bk, Wv, bv, Wo, bo (W[256][256] indexed
+ * [in][out]), wh[256], bh.  Loss per node: BCE(p, y) + lambda_e (1 - p) e,
+ * averaged (y the kinetic label, e the energy a cold-fluid conversion would
+ * destroy).  x[n][10], y[n], e[n] and logits are device FP32; training needs
+ * n % 8 == 0; n <= 2^26.  Errors as for hk_sp_*. */
+typedef struct hk_swn hk_swn;
+int hk_swn_nparams(void);
+int hk_swn_create(const hk_cnn_desc *desc, hk_swn **out);
+void hk_swn_destroy(hk_swn *swn);
+/* host FP32 parameters in and out (n = hk_swn_nparams()); setting resets AdamW */
+int hk_swn_set_params(hk_swn *swn, const float *params, size_t n);
+int hk_swn_get_params(hk_swn *swn, float *params, size_t n);
+/* logits of n nodes; mask_step >= 0 applies dropout sample `sample` (0..15)
+ * of that step (Monte Carlo samples), < 0 none */
+int hk_swn_forward(hk_swn *swn, const float *x, int n, int mask_step, int sample, float *logit);
+/* loss (host) and gradient (host FP32, may be NULL) */
+int hk_swn_loss_grad(hk_swn *swn, const float *x, const float *y, const float *e, int n, double lambda_e,
+                     int mask_step, float *grad_host, double *loss);
+/* one AdamW step (train->lambda_e, dropout keyed by the step count) */
+int hk_swn_train_step(hk_swn *swn, const float *x, const float *y, const float *e, int n,
+                      const hk_cnn_train_desc *train, double *loss);
+const char *hk_swn_last_error(const hk_swn *swn);
+
 int hk_real_size(void);
 const char *hk_strerror(int code);
 const char *hk_last_error(const hk_sim *sim);

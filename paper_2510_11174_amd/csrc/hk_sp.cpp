@@ -109,7 +109,7 @@ T *ws(hk_sp *c, int slot, size_t bytes) {
 
 void pack(hk_sp *c) {
     for (int l = 0; l < NL; ++l)
-        sp_launch_pack(c->p + w_off(l), CIN[l], COUT[l], cp(CIN[l]), cp(COUT[l]), c->Wf[l], c->Wb[l], c->s);
+        sp_launch_pack(c->p + w_off(l), CIN[l], COUT[l], cp(CIN[l]), cp(COUT[l]), 27, c->Wf[l], c->Wb[l], c->s);
 }
 
 int check_shape(hk_sp *c, int B, int D, int H, int W, bool train) {
@@ -124,6 +124,10 @@ SpConv conv_args(int B, int D, int H, int W, int cols) {
     SpConv a{};
     a.B = B; a.D = D; a.H = H; a.W = W;
     a.cols = cols;
+    // dropout p = 26/256 (Philox tag 25), kept channels scaled by 256/230
+    a.drop_tag = 25;
+    a.drop_thr = 26;
+    a.drop_scale = 256.0f / 230.0f;
     return a;
 }
 
@@ -161,7 +165,7 @@ int forward(hk_sp *c, const float *x, int B, int D, int H, int W, int mask_step,
             a.aout = act[l + 1];
             a.aT = train ? actT[l + 1] : nullptr;
         }
-        if (sp_launch_conv(cpin, false, a, c->s))
+        if (sp_launch_conv(cpin, 27, false, a, c->s))
             return fail(c, HK_EINVAL, "no convolution kernel for %d -> %d channels", cpin, cols);
     }
     return HK_OK;
@@ -305,7 +309,7 @@ int hk_sp_loss_grad(hk_sp *c, const float *x, const float *y, int B, int D, int 
         wg.kpc = (wg.nks + chunks - 1) / chunks;
         chunks = (wg.nks + wg.kpc - 1) / wg.kpc;
         wg.nitems = (int)(base * chunks);
-        if (sp_launch_wgrad(wnt, wg, s)) return fail(c, HK_EINVAL, "no weight-gradient kernel");
+        if (sp_launch_wgrad(wnt, 27, wg, s)) return fail(c, HK_EINVAL, "no weight-gradient kernel");
         if (l == 0) break;
         // data gradient into the layer below's pre-activation gradient
         SpConv a = conv_args(B, D, H, W, cpi);
@@ -322,7 +326,7 @@ int hk_sp_loss_grad(hk_sp *c, const float *x, const float *y, int B, int D, int 
         a.zin = (const unsigned short *)c->w[W_Z + l - 1];
         a.aout = dz[cur ^ 1];
         a.aT = dzT[cur ^ 1];
-        if (sp_launch_conv(cpo, true, a, s))
+        if (sp_launch_conv(cpo, 27, true, a, s))
             return fail(c, HK_EINVAL, "no data-gradient kernel for %d -> %d channels", cpo, cpi);
         cur ^= 1;
     }

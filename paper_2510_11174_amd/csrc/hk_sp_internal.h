@@ -16,16 +16,19 @@ struct SpConv {
     int relu, res;                  // res: leading channels of `in` added after the ReLU
     float *fout;                    // last layer: FP32 [n][cout] (no BF16 output)
     // both epilogues
-    int drop;                       // apply the dropout factors of (seed, voxel, step)
+    int drop;                       // apply the dropout factors of (seed, voxel, step, sample)
     uint64_t seed;
     uint32_t step;
+    uint32_t drop_tag, drop_thr;    // Philox tag; a byte below drop_thr drops the channel
+    float drop_scale;               // factor of a kept channel
+    int drop_sample;                // Monte Carlo sample: draws sample * cols / 16 + c / 16
     unsigned short *zout;           // forward: BF16 pre-activations (for the backward pass), or null
     unsigned short *aout, *aT;      // BF16 result, channels last and channel-major (or null)
     // data-gradient epilogue
     const float *gin;               // residual-path gradient of the layer above (or null)
     int gin_ch, gin_stride;
     float *gout;                    // gradient after dropout of the layer below (or null)
-    const unsigned short *zin;      // BF16 pre-activations of the layer below
+    const unsigned short *zin;      // BF16 pre-activations of the layer below (null: it has no ReLU)
     int ntask, G;                   // work items, column groups (set by the launcher)
 };
 
@@ -43,14 +46,17 @@ struct SpWgrad {
 
 struct SpNorm { float mean[10], stdv[10]; };
 
-int sp_launch_conv(int cpin, bool bwd, const SpConv &a, hipStream_t s);
-int sp_launch_wgrad(int nt, const SpWgrad &a, hipStream_t s);
+// taps: 27 ("same" 3^3 convolution) or 1 (a linear layer per voxel)
+int sp_launch_conv(int cpin, int taps, bool bwd, const SpConv &a, hipStream_t s);
+int sp_launch_wgrad(int nt, int taps, const SpWgrad &a, hipStream_t s);
 void sp_launch_energy(long long n, long long per, const float *p, const float *y, const SpNorm &nm, double *U,
                       hipStream_t s);
 void sp_launch_loss(long long n, long long per, int B, const float *p, const float *y, const SpNorm &nm,
                     const double *U, float delta, float lambda, unsigned short *dz, unsigned short *dzT,
                     double *loss, hipStream_t s);
-void sp_launch_pack(const float *W, int cin, int cout, int cpi, int cpo, unsigned short *Wf, unsigned short *Wb,
-                    hipStream_t s);
+void sp_launch_pack(const float *W, int cin, int cout, int cpi, int cpo, int taps, unsigned short *Wf,
+                    unsigned short *Wb, hipStream_t s);
+void swn_launch_loss(long long n, const float *logit, const float *y, const float *e, float lambda,
+                     unsigned short *dz, unsigned short *dzT, long long ldT, double *loss, hipStream_t s);
 void sp_launch_input(long long n, long long per, const float *x, unsigned short *xb, unsigned short *xT,
                      hipStream_t s);

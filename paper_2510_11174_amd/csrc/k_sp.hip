@@ -38,7 +38,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16;
 
 constexpr int SBS = 256;                  // 4 waves
-constexpr uint32_t TAG_SP_DROP = 25;      // Philox stream of the surrogate's dropout
 
 __device__ inline u16 bf16_bits(float x) {
     // round to nearest even (finite inputs)
@@ -47,13 +46,14 @@ __device__ inline u16 bf16_bits(float x) {
 }
 __device__ inline float bf16_val(u16 b) { return __uint_as_float((unsigned)b << 16); }
 
-// dropout keep factor of channel c (< 32) at voxel v: byte c % 16 of Philox
-// draw c / 16 (counter: voxel, step; sample 0) >= 26 keeps, scaled by 256/230
-__device__ inline float keep(uint64_t seed, uint64_t v, uint32_t step, int c) {
+// dropout keep factor of channel c at voxel v: byte c % 16 of Philox draw
+// sample * cols / 16 + c / 16 (counter: voxel, step) at or above drop_thr
+// keeps the channel, scaled by drop_scale
+__device__ inline float keep(const SpConv &a, uint64_t v, int c) {
     uint32_t r[4];
-    draw4(seed, v, step, TAG_SP_DROP, (uint32_t)(c >> 4), r);
+    draw4(a.seed, v, a.step, a.drop_tag, (uint32_t)(a.drop_sample * (a.cols >> 4) + (c >> 4)), r);
     const int byte = c & 15;
-    return ((r[byte >> 2] >> (8 * (byte & 3))) & 0xffu) >= 26u ? 256.0f / 230.0f : 0.0f;
+    return ((r[byte >> 2] >> (8 * (byte & 3))) & 0xffu) >= a.drop_thr ? a.drop_scale : 0.0f;
 }
 
 // blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous run
@@ -66,7 +66,7 @@ __device__ inline int xcd_block(int b, int nb) { return (b & 7) * (nb >> 3) + (b
 // Forward: bias, BF16 pre-activation (training), ReLU, residual copy,
 // dropout, one rounding to BF16 (or the FP32 output of the last layer).
 // Data gradient: residual-path gradient, dropout, ReLU derivative of the
-// layer below, BF16.  Both write the channel-major copy when asked.
+// layer below (when it has one), BF16.  Both write the channel-major copy when asked.
 template <int CPIN, int NT, bool BWD>
 __device__ inline void store_row(const SpConv &a, const f32x4 (&acc)[NT], int b, int z, int y, int x0, int cg,
                                  int r, int g) {
@@ -92,13 +92,13 @@ __device__ inline void store_row(const SpConv &a, const f32x4 (&acc)[NT], int b,
                     if (real_c) a.fout[v * a.cout + co] = o;
                     continue;
                 }
-                if (a.drop) o *= keep(a.seed, (uint64_t)v, a.step, co);
+                if (a.drop) o *= keep(a, (uint64_t)v, co);
                 ov[i] = real_c ? bf16_bits(o) : (u16)0;
             } else {
                 if (co < a.gin_ch) s += a.gin[v * a.gin_stride + co];
-                if (a.drop) s *= keep(a.seed, (uint64_t)v, a.step, co);
+                if (a.drop) s *= keep(a, (uint64_t)v, co);
                 if (a.gout) a.gout[v * a.cols + co] = s;
-                const float d = bf16_val(a.zin[v * a.cols + co]) > 0.f ? s : 0.f;
+                const float d = !a.zin || bf16_val(a.zin[v * a.cols + co]) > 0.f ? s : 0.f;
                 ov[i] = real_c ? bf16_bits(d) : (u16)0;
             }
             a.aout[v * a.cols + co] = ov[i];
@@ -112,9 +112,11 @@ __device__ inline void store_row(const SpConv &a, const f32x4 (&acc)[NT], int b,
     }
 }
 
-template <int CPIN, int MT, int NT, bool BWD>
+// TAPS = 27: the "same" 3^3 convolution; TAPS = 1: a linear layer per voxel
+// (the one tap reads the voxel itself).
+template <int CPIN, int MT, int NT, bool BWD, int TAPS>
 __global__ void __launch_bounds__(SBS) k_sp_conv(SpConv a) {
-    constexpr int K = 27 * CPIN, KPAD = (K + 31) / 32 * 32, NK = KPAD / 32;
+    constexpr int K = TAPS * CPIN, KPAD = (K + 31) / 32 * 32, NK = KPAD / 32;
     const int task = xcd_block(blockIdx.x, gridDim.x) * (SBS / 64) + (threadIdx.x >> 6);
     if (task >= a.ntask) return;
     const int cg = task % a.G, rg = task / a.G;
@@ -141,10 +143,12 @@ __global__ void __launch_bounds__(SBS) k_sp_conv(SpConv a) {
         const int x = seg * 16 + r;
         if (x >= a.W) continue;
         vb[m] = ((long long)b * a.D + z) * HW + (long long)y * a.W + x;
-        for (int t = 0; t < 27; ++t) {
-            const int xx = x + t % 3 - 1, yy = y + (t / 3) % 3 - 1, zz = z + t / 9 - 1;
-            if (xx >= 0 && xx < a.W && yy >= 0 && yy < a.H && zz >= 0 && zz < a.D) tmask[m] |= 1u << t;
-        }
+        if (TAPS == 1) tmask[m] = 1u;
+        else
+            for (int t = 0; t < 27; ++t) {
+                const int xx = x + t % 3 - 1, yy = y + (t / 3) % 3 - 1, zz = z + t / 9 - 1;
+                if (xx >= 0 && xx < a.W && yy >= 0 && yy < a.H && zz >= 0 && zz < a.D) tmask[m] |= 1u << t;
+            }
     }
     const u16 *wrow[NT];
 #pragma unroll
@@ -153,7 +157,7 @@ __global__ void __launch_bounds__(SBS) k_sp_conv(SpConv a) {
     auto loadA = [&](int ks, uint4 (&av)[MT]) {
         const int k = ks * 32 + 8 * g;
         const int t = k / CPIN, ci = k % CPIN;
-        const int kx = t % 3, ky = (t / 3) % 3, kz = t / 9;
+        const int kx = TAPS == 1 ? 1 : t % 3, ky = TAPS == 1 ? 1 : (t / 3) % 3, kz = TAPS == 1 ? 1 : t / 9;
         const long long off = ((long long)(kz - 1) * a.H + (ky - 1)) * a.W + (kx - 1);
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
@@ -334,15 +338,18 @@ __global__ void __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(2, 8))
 // workgroup owns one (ky, kz) pair, one 16-channel ci tile, NT co tiles and a
 // chunk of K; its four waves take interleaved steps of the chunk, reduce in
 // LDS, and wave 0 adds the three taps kx = 0, 1, 2 to gw.
-template <int NT>
+// With ONE (a linear layer: the single tap is the voxel itself) there is
+// one (ky, kz) pair and one kx.
+template <int NT, bool ONE>
 __global__ void __launch_bounds__(SBS) k_sp_wgrad(SpWgrad a) {
-    __shared__ f32x4 red[SBS / 64 - 1][3 * NT][64];
+    constexpr int NKX = ONE ? 1 : 3;
+    __shared__ f32x4 red[SBS / 64 - 1][NKX * NT][64];
     __shared__ float sb[NT * 16];
     const int item = xcd_block(blockIdx.x, gridDim.x);
     if (item >= a.nitems) return;   // uniform over the workgroup
     int q = item;
-    const int p = q % 9;
-    q /= 9;
+    const int p = ONE ? 4 : q % 9;
+    if (!ONE) q /= 9;
     const int mt = q % a.mtn;
     q /= a.mtn;
     const int ng = q % a.ngn;
@@ -359,9 +366,9 @@ __global__ void __launch_bounds__(SBS) k_sp_wgrad(SpWgrad a) {
     if (threadIdx.x < NT * 16) sb[threadIdx.x] = 0.f;
     const long long HW = (long long)a.H * a.W, DHW = HW * a.D;
     const int ci = mt * 16 + r;
-    f32x4 acc[3][NT];
+    f32x4 acc[NKX][NT];
 #pragma unroll
-    for (int kx = 0; kx < 3; ++kx)
+    for (int kx = 0; kx < NKX; ++kx)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[kx][nt] = f32x4{0, 0, 0, 0};
     const long long ks0 = (long long)chunk * a.kpc;
@@ -383,8 +390,8 @@ __global__ void __launch_bounds__(SBS) k_sp_wgrad(SpWgrad a) {
             if (ys >= 0 && ys < a.H && zs >= 0 && zs < a.D) {
                 const u16 *src = a.aT + ((long long)b * a.cpi + ci) * DHW + zs * HW + (long long)ys * a.W + 8 * xb;
                 M = *reinterpret_cast<const uint4 *>(src);
-                if (xb > 0) L = *reinterpret_cast<const uint4 *>(src - 8);
-                if (xb + 1 < xbn) R = *reinterpret_cast<const uint4 *>(src + 8);
+                if (!ONE && xb > 0) L = *reinterpret_cast<const uint4 *>(src - 8);
+                if (!ONE && xb + 1 < xbn) R = *reinterpret_cast<const uint4 *>(src + 8);
             }
             const long long dbase = (long long)b * a.cpo * DHW + z * HW + (long long)y * a.W + 8 * xb;
 #pragma unroll
@@ -409,14 +416,18 @@ __global__ void __launch_bounds__(SBS) k_sp_wgrad(SpWgrad a) {
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             const bf16x8 bb = __builtin_bit_cast(bf16x8, Bv[nt]);
-            acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A0), bb, acc[0][nt], 0, 0, 0);
-            acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, M), bb, acc[1][nt], 0, 0, 0);
-            acc[2][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A2), bb, acc[2][nt], 0, 0, 0);
+            if constexpr (ONE) {
+                acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, M), bb, acc[0][nt], 0, 0, 0);
+            } else {
+                acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A0), bb, acc[0][nt], 0, 0, 0);
+                acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, M), bb, acc[1][nt], 0, 0, 0);
+                acc[2][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A2), bb, acc[2][nt], 0, 0, 0);
+            }
         }
     }
     if (wave > 0)
 #pragma unroll
-        for (int kx = 0; kx < 3; ++kx)
+        for (int kx = 0; kx < NKX; ++kx)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) red[wave - 1][kx * NT + nt][lane] = acc[kx][nt];
     __syncthreads();
@@ -431,12 +442,12 @@ __global__ void __launch_bounds__(SBS) k_sp_wgrad(SpWgrad a) {
     }
     if (wave != 0) return;
 #pragma unroll
-    for (int kx = 0; kx < 3; ++kx)
+    for (int kx = 0; kx < NKX; ++kx)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             f32x4 s = acc[kx][nt];
             for (int w = 0; w < SBS / 64 - 1; ++w) s += red[w][kx * NT + nt][lane];
-            const int t = kx + 3 * p;
+            const int t = ONE ? 0 : kx + 3 * p;
             const int co = (ng * NT + nt) * 16 + r;
             for (int i = 0; i < 4; ++i) {
                 const int c = mt * 16 + 4 * g + i;
@@ -536,19 +547,48 @@ k_sp_loss(long long n, long long per, int B, const float *__restrict__ p, const 
 // forward Wf[co][k = t cpi + ci] (kpf = 27 cpi rounded up to 32) and data
 // gradient Wb[ci][k = t cpo + co] = W[26 - t][ci][co]; zeros in the padding
 __global__ void __launch_bounds__(SBS)
-k_sp_pack(const float *__restrict__ W, int cin, int cout, int cpi, int cpo, u16 *__restrict__ Wf,
+k_sp_pack(const float *__restrict__ W, int cin, int cout, int cpi, int cpo, int taps, u16 *__restrict__ Wf,
           u16 *__restrict__ Wb) {
     const int i = blockIdx.x * SBS + threadIdx.x;
-    const int kpf = (27 * cpi + 31) / 32 * 32, kpb = (27 * cpo + 31) / 32 * 32;
+    const int kpf = (taps * cpi + 31) / 32 * 32, kpb = (taps * cpo + 31) / 32 * 32;
     if (i < cpo * kpf) {
         const int co = i / kpf, k = i % kpf, t = k / cpi, ci = k % cpi;
-        Wf[i] = (k < 27 * cpi && ci < cin && co < cout) ? bf16_bits(W[((long long)t * cin + ci) * cout + co]) : (u16)0;
+        Wf[i] = (k < taps * cpi && ci < cin && co < cout) ? bf16_bits(W[((long long)t * cin + ci) * cout + co])
+                                                          : (u16)0;
     }
     if (Wb && i < cpi * kpb) {
         const int ci = i / kpb, k = i % kpb, t = k / cpo, co = k % cpo;
-        Wb[i] = (k < 27 * cpo && ci < cin && co < cout)
-                    ? bf16_bits(W[((long long)(26 - t) * cin + ci) * cout + co]) : (u16)0;
+        Wb[i] = (k < taps * cpo && ci < cin && co < cout)
+                    ? bf16_bits(W[((long long)(taps - 1 - t) * cin + ci) * cout + co]) : (u16)0;
     }
+}
+
+// SwitchNet loss from the logits: mean of BCE(p, y) + lambda (1 - p) e, and
+// the logit gradient into column 0 of dz [n][16] (BF16, other columns zero)
+// and of its channel-major copy (row stride ldT)
+__global__ void __launch_bounds__(SBS)
+k_swn_loss(long long n, const float *__restrict__ logit, const float *__restrict__ y, const float *__restrict__ e,
+           float lambda, u16 *__restrict__ dz, u16 *__restrict__ dzT, long long ldT, double *__restrict__ loss) {
+    __shared__ double sl[SBS];
+    const long long v = (long long)blockIdx.x * SBS + threadIdx.x;
+    double l = 0.0;
+    if (v < n) {
+        const float s = logit[v], p = 1.0f / (1.0f + __expf(-s));
+        const float sp = s > 0.f ? s + log1pf(__expf(-s)) : log1pf(__expf(s));
+        l = (double)(sp - y[v] * s + lambda * (1.0f - p) * e[v]) / (double)n;
+        const u16 d = bf16_bits((p - y[v] - lambda * p * (1.0f - p) * e[v]) / (float)n);
+        for (int c = 0; c < 16; ++c) {
+            dz[v * 16 + c] = c ? (u16)0 : d;
+            dzT[c * ldT + v] = c ? (u16)0 : d;
+        }
+    }
+    sl[threadIdx.x] = l;
+    __syncthreads();
+    for (int k = SBS / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sl[threadIdx.x] += sl[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && sl[0] != 0.0) atomicAdd(loss, sl[0]);
 }
 
 // FP32 inputs [n][10] -> BF16 [n][16] (zero padded) and the channel-major copy
@@ -566,11 +606,11 @@ k_sp_input(long long n, long long per, const float *__restrict__ x, u16 *__restr
 inline unsigned nblk(long long n) { return (unsigned)((n + SBS - 1) / SBS); }
 inline unsigned grid8(long long items) { return (unsigned)((items + 7) / 8 * 8); }
 
-template <int CPIN, int NT, bool BWD>
+template <int CPIN, int NT, bool BWD, int TAPS = 27>
 void conv_go(SpConv a, hipStream_t s) {
     const int segs = (a.W + 15) / 16;
     a.G = a.cols / (16 * NT);
-    if constexpr (CPIN >= 32) {
+    if constexpr (TAPS == 27 && CPIN >= 32) {
         // eight rows per wave where a row feeds only one or two column tiles
         constexpr int MT = NT <= 2 ? 8 : 4;
         const long long tiles = (long long)a.B * ((a.D + HZ - 1) / HZ) * ((a.H + MT - 1) / MT) * segs;
@@ -580,18 +620,33 @@ void conv_go(SpConv a, hipStream_t s) {
         constexpr int MT = 4;
         const long long rows = (long long)a.B * a.D * a.H * segs;
         a.ntask = (int)((rows + MT - 1) / MT * a.G);
-        k_sp_conv<CPIN, MT, NT, BWD><<<grid8((a.ntask + 3) / 4), SBS, 0, s>>>(a);
+        k_sp_conv<CPIN, MT, NT, BWD, TAPS><<<grid8((a.ntask + 3) / 4), SBS, 0, s>>>(a);
     }
 }
 
 }  // namespace
 
 // ----------------------------------------------------------------- launchers
-int sp_launch_conv(int cpin, bool bwd, const SpConv &a, hipStream_t s) {
+int sp_launch_conv(int cpin, int taps, bool bwd, const SpConv &a, hipStream_t s) {
+    const int ct = a.cols / 16;
+    if (taps == 1) {
+        // linear layers: four row and up to four column tiles per wave
+        const int nt = ct < 4 ? ct : 4;
+        switch (cpin * 100 + nt * 10 + (bwd ? 1 : 0)) {
+        case 1640: conv_go<16, 4, false, 1>(a, s); break;
+        case 12840: conv_go<128, 4, false, 1>(a, s); break;
+        case 25640: conv_go<256, 4, false, 1>(a, s); break;
+        case 25641: conv_go<256, 4, true, 1>(a, s); break;
+        case 25610: conv_go<256, 1, false, 1>(a, s); break;
+        case 1641: conv_go<16, 4, true, 1>(a, s); break;
+        default: return -1;
+        }
+        return 0;
+    }
+    if (taps != 27) return -1;
     // column tiles per wave: up to 4 on the 16-channel inputs; on the halo
     // path two (with eight rows per wave), which keeps the wave's working set
     // in registers at two waves per SIMD
-    const int ct = a.cols / 16;
     const int nt = cpin >= 32 ? (ct < SP_HALO_NT ? ct : SP_HALO_NT) : (ct < 4 ? ct : 4);
     const int key = cpin * 100 + nt * 10 + (bwd ? 1 : 0);
     switch (key) {
@@ -619,12 +674,14 @@ int sp_launch_conv(int cpin, bool bwd, const SpConv &a, hipStream_t s) {
     return 0;
 }
 
-int sp_launch_wgrad(int nt, const SpWgrad &a, hipStream_t s) {
+int sp_launch_wgrad(int nt, int taps, const SpWgrad &a, hipStream_t s) {
     const unsigned grid = grid8(a.nitems);
-    switch (nt) {
-    case 1: k_sp_wgrad<1><<<grid, SBS, 0, s>>>(a); break;
-    case 2: k_sp_wgrad<2><<<grid, SBS, 0, s>>>(a); break;
-    case 4: k_sp_wgrad<4><<<grid, SBS, 0, s>>>(a); break;
+    switch (nt * 100 + taps) {
+    case 127: k_sp_wgrad<1, false><<<grid, SBS, 0, s>>>(a); break;
+    case 227: k_sp_wgrad<2, false><<<grid, SBS, 0, s>>>(a); break;
+    case 427: k_sp_wgrad<4, false><<<grid, SBS, 0, s>>>(a); break;
+    case 101: k_sp_wgrad<1, true><<<grid, SBS, 0, s>>>(a); break;
+    case 401: k_sp_wgrad<4, true><<<grid, SBS, 0, s>>>(a); break;
     default: return -1;
     }
     return 0;
@@ -641,11 +698,16 @@ void sp_launch_loss(long long n, long long per, int B, const float *p, const flo
     k_sp_loss<<<nblk(n), SBS, 0, s>>>(n, per, B, p, y, nm, U, delta, lambda, dz, dzT, loss);
 }
 
-void sp_launch_pack(const float *W, int cin, int cout, int cpi, int cpo, unsigned short *Wf, unsigned short *Wb,
-                    hipStream_t s) {
-    const long long nf = (long long)cpo * ((27 * cpi + 31) / 32 * 32);
-    const long long nb = (long long)cpi * ((27 * cpo + 31) / 32 * 32);
-    k_sp_pack<<<nblk(nf > nb ? nf : nb), SBS, 0, s>>>(W, cin, cout, cpi, cpo, Wf, Wb);
+void sp_launch_pack(const float *W, int cin, int cout, int cpi, int cpo, int taps, unsigned short *Wf,
+                    unsigned short *Wb, hipStream_t s) {
+    const long long nf = (long long)cpo * ((taps * cpi + 31) / 32 * 32);
+    const long long nb = (long long)cpi * ((taps * cpo + 31) / 32 * 32);
+    k_sp_pack<<<nblk(nf > nb ? nf : nb), SBS, 0, s>>>(W, cin, cout, cpi, cpo, taps, Wf, Wb);
+}
+
+void swn_launch_loss(long long n, const float *logit, const float *y, const float *e, float lambda,
+                     unsigned short *dz, unsigned short *dzT, long long ldT, double *loss, hipStream_t s) {
+    k_swn_loss<<<nblk(n), SBS, 0, s>>>(n, logit, y, e, lambda, dz, dzT, ldT, loss);
 }
 
 void sp_launch_input(long long n, long long per, const float *x, unsigned short *xb, unsigned short *xT,

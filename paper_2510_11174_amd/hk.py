@@ -111,6 +111,8 @@ ABI_SYMBOLS = ["hk_create", "hk_destroy", "hk_step", "hk_switch_map", "hk_set_sw
                "hk_cnn_loss_grad", "hk_cnn_train_step", "hk_cnn_last_error", "hk_set_cnn", "hk_node_inputs", "hk_node_state",
                "hk_sp_nparams", "hk_sp_create", "hk_sp_destroy", "hk_sp_set_params", "hk_sp_get_params",
                "hk_sp_set_norm", "hk_sp_forward", "hk_sp_loss_grad", "hk_sp_train_step", "hk_sp_last_error",
+               "hk_swn_nparams", "hk_swn_create", "hk_swn_destroy", "hk_swn_set_params", "hk_swn_get_params",
+               "hk_swn_forward", "hk_swn_loss_grad", "hk_swn_train_step", "hk_swn_last_error",
                "hk_real_size", "hk_strerror", "hk_last_error", "hk_save", "hk_load"]
 
 _libs: dict = {}
@@ -174,6 +176,17 @@ def load(prec: str = "f32"):
     L.hk_sp_train_step.argtypes = [vp, vp, vp] + [C.c_int] * 4 + [P(SpTrainDesc), P(C.c_double)]
     L.hk_sp_last_error.restype = C.c_char_p
     L.hk_sp_last_error.argtypes = [vp]
+    L.hk_swn_nparams.restype = C.c_int
+    L.hk_swn_create.argtypes = [P(CnnDesc), P(vp)]
+    L.hk_swn_destroy.argtypes = [vp]
+    L.hk_swn_destroy.restype = None
+    L.hk_swn_set_params.argtypes = [vp, vp, C.c_size_t]
+    L.hk_swn_get_params.argtypes = [vp, vp, C.c_size_t]
+    L.hk_swn_forward.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int, vp]
+    L.hk_swn_loss_grad.argtypes = [vp, vp, vp, vp, C.c_int, C.c_double, C.c_int, vp, P(C.c_double)]
+    L.hk_swn_train_step.argtypes = [vp, vp, vp, vp, C.c_int, P(CnnTrainDesc), P(C.c_double)]
+    L.hk_swn_last_error.restype = C.c_char_p
+    L.hk_swn_last_error.argtypes = [vp]
     L.hk_node_inputs.argtypes = [vp, vp, vp, vp, C.c_size_t]
     L.hk_node_state.argtypes = [vp, vp, C.c_size_t]
     L.hk_real_size.restype = C.c_int
@@ -588,4 +601,75 @@ class StatePredictor:
         loss = C.c_double()
         self._check(self.lib.hk_sp_train_step(self.h, x.data_ptr(), y.data_ptr(), B, D, H, W, C.byref(t),
                                               C.byref(loss)))
+        return loss.value
+
+
+class SwitchNet:
+    """The paper's per-node switch classifier on the GPU (device memory from
+    torch's allocator).  x: torch [n, 10] float32 on cuda:0 (normalized node
+    features); y, e: [n] float32."""
+
+    def __init__(self, seed: int = 0, precision: str = "f32"):
+        self.lib = load(precision)
+        self._mem = _TorchMemory()
+        d = CnnDesc(seed=seed, stream=self._mem.stream.cuda_stream, alloc=self._mem.alloc,
+                    free=self._mem.free, alloc_ctx=None)
+        h = C.c_void_p()
+        rc = self.lib.hk_swn_create(C.byref(d), C.byref(h))
+        if rc:
+            raise HKError(rc, "hk_swn_create failed")
+        self.h = h
+        self.nparams = self.lib.hk_swn_nparams()
+
+    def _check(self, rc):
+        if rc:
+            raise HKError(rc, self.lib.hk_swn_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hk_swn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, np.float32)
+        assert a.size == self.nparams
+        self._check(self.lib.hk_swn_set_params(self.h, _ptr(a), a.size))
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(self.nparams, np.float32)
+        self._check(self.lib.hk_swn_get_params(self.h, _ptr(a), a.size))
+        return a
+
+    def forward(self, x, mask_step=-1, sample=0, out=None):
+        import torch
+        x = x.contiguous()
+        n, c_ = x.shape
+        assert c_ == 10 and x.dtype == torch.float32
+        if out is None:
+            out = torch.empty(n, device=x.device, dtype=torch.float32)
+        self._check(self.lib.hk_swn_forward(self.h, x.data_ptr(), n, int(mask_step), int(sample), out.data_ptr()))
+        return out
+
+    def loss_grad(self, x, y, e, lam=0.1, mask_step=-1, grad=True):
+        x = x.contiguous(); y = y.contiguous(); e = e.contiguous()
+        g = np.empty(self.nparams, np.float32) if grad else None
+        loss = C.c_double()
+        self._check(self.lib.hk_swn_loss_grad(self.h, x.data_ptr(), y.data_ptr(), e.data_ptr(), x.shape[0],
+                                              float(lam), int(mask_step), None if g is None else _ptr(g),
+                                              C.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, x, y, e, lr=1e-3, lam=0.1, dropout=True, weight_decay=0.01):
+        x = x.contiguous(); y = y.contiguous(); e = e.contiguous()
+        t = CnnTrainDesc(lr=lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=weight_decay,
+                         lambda_e=lam, dropout=int(dropout))
+        loss = C.c_double()
+        self._check(self.lib.hk_swn_train_step(self.h, x.data_ptr(), y.data_ptr(), e.data_ptr(), x.shape[0],
+                                               C.byref(t), C.byref(loss)))
         return loss.value
