@@ -232,6 +232,53 @@ def sp_surrogate(B=64, reps=20, train_reps=5):
             "train_tflops": round(flops_train / (ms_t * 1e-3) / 1e12, 1), "patches": "%d x 16^3" % B}
 
 
+def swn_inference(reps=20, train_nodes=65536, train_reps=5):
+    """The paper's SwitchNet over every node of the ionizing-helium grid (129 x
+    64 x 64 nodes), timed with HIP events on the library stream, and one
+    training step on a batch of 65536 nodes.  Flops per node are those the
+    method needs: the two linear blocks, the attention's value and output
+    projections (a single-token softmax is 1, so the query and key
+    projections do not change the result) and the head,
+    2 (10*128 + 128*256 + 2*256*256 + 256)."""
+    import torch
+
+    from paper_2510_11174_amd import hk
+    from paper_2510_11174_amd import train as T
+    n = 129 * 64 * 64
+    swn = hk.SwitchNet(seed=1)
+    swn.set_params(T.swn_init_params(1))
+    x = torch.randn((n, 10), device="cuda", dtype=torch.float32)
+    out = torch.empty(n, device="cuda", dtype=torch.float32)
+    fpn = 2 * (10 * 128 + 128 * 256 + 2 * 256 * 256 + 256)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        swn.forward(x, out=out)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        swn.forward(x, out=out)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    xt = x[:train_nodes].contiguous()
+    y = (xt[:, 0] > 0).float()
+    e = torch.ones(train_nodes, device="cuda")
+    swn.train_step(xt, y, e, lr=1e-5)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(train_reps):
+        swn.train_step(xt, y, e, lr=1e-5)
+    b.record()
+    torch.cuda.synchronize()
+    ms_t = a.elapsed_time(b) / train_reps
+    swn.close()
+    tf = fpn * n / (ms * 1e-3) / 1e12
+    return {"bound": "mfma", "achieved": round(tf, 1), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4), "kernel": "k_sp_conv one-tap (5 linear layers)",
+            "ms_forward": round(ms, 3), "flop_per_node": fpn, "nodes": n,
+            "ms_train_step": round(ms_t, 3), "train_nodes": train_nodes}
+
+
 def field_l2(x, y):
     import numpy as np
     num = math.sqrt(sum(float(np.sum((x[c] - y[c]) ** 2)) for c in x))
@@ -250,8 +297,9 @@ def main():
                     help="comma list of switch modes to run (profiling runs may pick one)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
-    ap.add_argument("--surrogate-only", action="store_true",
-                    help="only measure the next-state surrogate (64 patches of 16^3) and print its JSON")
+    ap.add_argument("--networks-only", action="store_true",
+                    help="only measure the next-state surrogate (64 patches of 16^3) and SwitchNet (the "
+                         "ionizing-helium node grid) and print their JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the multi-GPU path (domain decomposition) is not "
@@ -262,8 +310,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     from paper_2510_11174_amd import configs
-    if args.surrogate_only:
-        print(json.dumps({"roofline_state_predictor": sp_surrogate()}))
+    if args.networks_only:
+        print(json.dumps({"roofline_state_predictor": sp_surrogate(), "roofline_switchnet": swn_inference()}))
         return
     if args.calibrate_copy:
         copy_calibration()
@@ -345,6 +393,7 @@ def main():
     }
     out["roofline_cnn_switch"] = cnn_inference()
     out["roofline_state_predictor"] = sp_surrogate()
+    out["roofline_switchnet"] = swn_inference()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

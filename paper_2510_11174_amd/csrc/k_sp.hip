@@ -330,6 +330,59 @@ __global__ void __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(2, 8))
         if (ty0 + m < a.H) store_row<CPIN, NT, BWD>(a, acc[m], b, z, ty0 + m, x0, cg, r, g);
 }
 
+// Linear layers (one tap) over n = B D H W voxels taken 16 at a time in
+// storage order.  A workgroup owns one column group: its NT * 16 columns of
+// the weight matrix (all of K) sit in LDS, rows padded by 16 bytes so that
+// the 16 lanes reading one k range of 16 columns hit different banks; its
+// four waves then walk row tiles of 4 x 16 voxels, A fragments from global
+// memory (each row read once per column group).
+template <int CPIN, int NT, bool BWD>
+__global__ void __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(2, 8))) k_sp_lin(SpConv a) {
+    constexpr int MT = 4, KPAD = (CPIN + 31) / 32 * 32, NK = KPAD / 32, KS = KPAD + 8;
+    __shared__ __attribute__((aligned(16))) u16 sB[NT * 16 * KS];
+    const int cg = blockIdx.x % a.G, wgi = blockIdx.x / a.G, nwg = gridDim.x / a.G;
+    const u16 *wsrc = a.wp + (long long)cg * NT * 16 * KPAD;
+    for (int e = threadIdx.x; e < NT * 16 * KPAD / 8; e += SBS) {
+        const int col = e / (KPAD / 8), k8 = e % (KPAD / 8);
+        *reinterpret_cast<uint4 *>(sB + col * KS + 8 * k8) = reinterpret_cast<const uint4 *>(wsrc)[e];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
+    const long long n = (long long)a.B * a.D * a.H * a.W;
+    const long long ntiles = (n + 15) / 16;
+    for (long long t0 = ((long long)wgi * (SBS / 64) + wave) * MT; t0 < ntiles; t0 += (long long)nwg * (SBS / 64) * MT) {
+        f32x4 acc[MT][NT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[m][nt] = f32x4{0, 0, 0, 0};
+#pragma unroll 2
+        for (int ks = 0; ks < NK; ++ks) {
+            const int k = ks * 32 + 8 * g;
+            uint4 av[MT], bv[NT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const long long v = (t0 + m) * 16 + r;
+                av[m] = (v < n && k < CPIN) ? *reinterpret_cast<const uint4 *>(a.in + v * CPIN + k) : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) bv[nt] = *reinterpret_cast<const uint4 *>(sB + (nt * 16 + r) * KS + k);
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av[m]),
+                                                                        __builtin_bit_cast(bf16x8, bv[nt]),
+                                                                        acc[m][nt], 0, 0, 0);
+        }
+        // rows of 16 voxels in storage order: as x segments of one row when
+        // the voxels are one line (B = D = H = 1)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+            if ((t0 + m) * 16 < n) store_row<CPIN, NT, BWD>(a, acc[m], 0, 0, 0, (int)((t0 + m) * 16), cg, r, g);
+    }
+}
+
 // -------------------------------------------------------- weight gradient
 // gw[t][ci][co] += sum_v a[v + off(t)][ci] dz[v][co].  K runs over 8-voxel
 // blocks along x (W % 8 == 0), four blocks per step: lane (r, g) takes block
@@ -610,7 +663,15 @@ template <int CPIN, int NT, bool BWD, int TAPS = 27>
 void conv_go(SpConv a, hipStream_t s) {
     const int segs = (a.W + 15) / 16;
     a.G = a.cols / (16 * NT);
-    if constexpr (TAPS == 27 && CPIN >= 32) {
+    if constexpr (TAPS == 1) {
+        // persistent workgroups per column group, about 1024 in all
+        const long long ntiles = ((long long)a.B * a.D * a.H * a.W + 15) / 16;
+        long long per = (ntiles + 15) / 16;
+        const long long cap = (1024 + a.G - 1) / a.G;
+        if (per > cap) per = cap;
+        a.ntask = 0;
+        k_sp_lin<CPIN, NT, BWD><<<(unsigned)(per * a.G), SBS, 0, s>>>(a);
+    } else if constexpr (TAPS == 27 && CPIN >= 32) {
         // eight rows per wave where a row feeds only one or two column tiles
         constexpr int MT = NT <= 2 ? 8 : 4;
         const long long tiles = (long long)a.B * ((a.D + HZ - 1) / HZ) * ((a.H + MT - 1) / MT) * segs;
@@ -630,7 +691,9 @@ void conv_go(SpConv a, hipStream_t s) {
 int sp_launch_conv(int cpin, int taps, bool bwd, const SpConv &a, hipStream_t s) {
     const int ct = a.cols / 16;
     if (taps == 1) {
-        // linear layers: four row and up to four column tiles per wave
+        // linear layers take the voxels as one line (B = D = H = 1); four
+        // row and up to four column tiles per wave
+        if (a.B != 1 || a.D != 1 || a.H != 1) return -1;
         const int nt = ct < 4 ? ct : 4;
         switch (cpin * 100 + nt * 10 + (bwd ? 1 : 0)) {
         case 1640: conv_go<16, 4, false, 1>(a, s); break;

@@ -29,9 +29,11 @@ def node_dims(cfg):
     return g["nz"], g["ny"], nx
 
 
-def generate(hk, cfg, steps, every, start=0, window=10, precision="f32"):
+def generate(hk, cfg, steps, every, start=0, window=10, precision="f32", states=False):
     """Run `cfg` all-PIC for steps + window steps; snapshots every `every`
-    steps from `start`.  Returns a list of (raw[nz, ny, NX, 8], y, e, hot_now)."""
+    steps from `start`.  Returns a list of (raw[nz, ny, NX, 8], y, e, hot_now),
+    with the node states [nz, ny, NX, 10] (hk_node_state) appended when
+    `states` is set."""
     c = copy.deepcopy(cfg)
     c["run"]["switch_mode"] = "all_pic"
     sim = hk.Sim(c, precision=precision)
@@ -42,15 +44,16 @@ def generate(hk, cfg, steps, every, start=0, window=10, precision="f32"):
         raw, e, hot = sim.node_inputs()
         hots.append(hot.reshape(dims))
         if s >= start and (s - start) % every == 0 and s <= steps:
-            snaps[s] = (raw, e)
+            snaps[s] = (raw, e, sim.node_state().cpu().numpy() if states else None)
         sim.step(1)
     sim.close()
     out = []
-    for s, (raw, e) in sorted(snaps.items()):
+    for s, (raw, e, st) in sorted(snaps.items()):
         y = np.zeros(dims, np.float32)
         for h in hots[s:s + window + 1]:
             y = np.maximum(y, h.astype(np.float32))
-        out.append((raw.reshape(dims + (8,)), y, e.reshape(dims), hots[s].astype(np.float32)))
+        d = (raw.reshape(dims + (8,)), y, e.reshape(dims), hots[s].astype(np.float32))
+        out.append(d + (st,) if states else d)
     return out
 
 
@@ -76,6 +79,53 @@ def sp_init_params(seed=0):
         parts.append(rng.normal(0, np.sqrt(2.0 / (27 * cin)), 27 * cin * cout))
         parts.append(np.zeros(cout))
     return np.concatenate(parts).astype(np.float32)
+
+
+def swn_init_params(seed=0):
+    """SwitchNet: He-normal weights (W[in][out]) and zero biases in the
+    library's parameter layout; a small head."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ni, no in [(10, 128), (128, 256)] + [(256, 256)] * 4:
+        parts.append(rng.normal(0, np.sqrt(2.0 / ni), ni * no))
+        parts.append(np.zeros(no))
+    parts.append(rng.normal(0, np.sqrt(1.0 / 256), 256))
+    parts.append(np.zeros(1))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def swn_nodes(data, dv=1.0):
+    """Per-node SwitchNet samples of snapshots made with states=True:
+    features x[N, 10] (node states), labels y[N], energy weights e[N] (the
+    conversion energy over the snapshot's mean kinetic energy per node)."""
+    xs, ys, es = [], [], []
+    for raw, y, e, _, st in data:
+        ke = 0.5 * (raw[..., 6] * dv * raw[..., 7] ** 2).mean() + 1e-30
+        xs.append(st.reshape(-1, 10)); ys.append(y.ravel()); es.append(e.ravel() / ke)
+    return (np.concatenate(xs).astype(np.float32), np.concatenate(ys).astype(np.float32),
+            np.concatenate(es).astype(np.float32))
+
+
+def swn_train(swn, x, y, e, mean, std, iters, B=4096, lr=1e-3, lam=0.1, seed=0, log=None):
+    """AdamW on random node batches (B a multiple of 8); returns the losses."""
+    import torch
+    rng = np.random.default_rng(seed)
+    xn = torch.tensor((x - mean) / std, device="cuda")
+    yd = torch.tensor(y, device="cuda"); ed = torch.tensor(e, device="cuda")
+    losses = []
+    for it in range(iters):
+        idx = torch.tensor(rng.integers(0, len(x), B), device="cuda")
+        losses.append(swn.train_step(xn[idx], yd[idx], ed[idx], lr=lr, lam=lam, dropout=True))
+        if log and (it % 50 == 0 or it == iters - 1):
+            log("iter %d loss %.4f" % (it, losses[-1]))
+    return losses
+
+
+def swn_predict(swn, x, mean, std):
+    """p per node (no dropout)."""
+    import torch
+    xd = torch.tensor(((x - mean) / std).astype(np.float32), device="cuda")
+    return torch.sigmoid(swn.forward(xd)).cpu().numpy()
 
 
 def stats(data):
