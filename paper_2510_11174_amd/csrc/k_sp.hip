@@ -67,9 +67,11 @@ __device__ inline int xcd_block(int b, int nb) { return (b & 7) * (nb >> 3) + (b
 // dropout, one rounding to BF16 (or the FP32 output of the last layer).
 // Data gradient: residual-path gradient, dropout, ReLU derivative of the
 // layer below (when it has one), BF16.  Both write the channel-major copy when asked.
+// With `stage` (LDS, 16 rows of stride ST) the channels-last result goes
+// there instead of to aout; the caller copies it out in 16-byte pieces.
 template <int CPIN, int NT, bool BWD>
 __device__ inline void store_row(const SpConv &a, const f32x4 (&acc)[NT], int b, int z, int y, int x0, int cg,
-                                 int r, int g) {
+                                 int r, int g, u16 *stage = nullptr, int ST = 0) {
     const long long HW = (long long)a.H * a.W;
     const int xg = x0 + 4 * g;
     const long long vrow = ((long long)b * a.D + z) * HW + (long long)y * a.W;
@@ -101,7 +103,8 @@ __device__ inline void store_row(const SpConv &a, const f32x4 (&acc)[NT], int b,
                 const float d = !a.zin || bf16_val(a.zin[v * a.cols + co]) > 0.f ? s : 0.f;
                 ov[i] = real_c ? bf16_bits(d) : (u16)0;
             }
-            a.aout[v * a.cols + co] = ov[i];
+            if (stage) stage[(4 * g + i) * ST + nt * 16 + r] = ov[i];
+            else a.aout[v * a.cols + co] = ov[i];
         }
         if (a.aT && xg < a.W) {
             // channel-major copy: 4 consecutive x of channel co (W % 4 == 0)
@@ -338,9 +341,14 @@ __global__ void __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(2, 8))
 // memory (each row read once per column group).
 template <int CPIN, int NT, bool BWD>
 __global__ void __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(2, 8))) k_sp_lin(SpConv a) {
-    constexpr int MT = 4, KPAD = (CPIN + 31) / 32 * 32, NK = KPAD / 32, KS = KPAD + 8;
+    constexpr int MT = 4, KPAD = (CPIN + 31) / 32 * 32, NK = KPAD / 32, KS = KPAD + 8, ST = NT * 16 + 8;
     __shared__ __attribute__((aligned(16))) u16 sB[NT * 16 * KS];
-    const int cg = blockIdx.x % a.G, wgi = blockIdx.x / a.G, nwg = gridDim.x / a.G;
+    __shared__ __attribute__((aligned(16))) u16 sS[SBS / 64 * 16 * ST];
+    // block b runs on XCD b % 8: the G column groups of one set of rows go
+    // to blocks b, b + 8, ... on the same XCD, so the rows are fetched into
+    // that XCD's L2 once (gridDim.x = G * nwg, nwg a multiple of 8)
+    const int cg = (blockIdx.x >> 3) % a.G, wgi = (blockIdx.x & 7) + 8 * ((blockIdx.x >> 3) / a.G);
+    const int nwg = gridDim.x / a.G;
     const u16 *wsrc = a.wp + (long long)cg * NT * 16 * KPAD;
     for (int e = threadIdx.x; e < NT * 16 * KPAD / 8; e += SBS) {
         const int col = e / (KPAD / 8), k8 = e % (KPAD / 8);
@@ -376,10 +384,35 @@ __global__ void __launch_bounds__(SBS) __attribute__((amdgpu_waves_per_eu(2, 8))
                                                                         acc[m][nt], 0, 0, 0);
         }
         // rows of 16 voxels in storage order: as x segments of one row when
-        // the voxels are one line (B = D = H = 1)
+        // the voxels are one line (B = D = H = 1).  The BF16 result goes
+        // through the wave's LDS stage and out in 16-byte pieces.
+        u16 *stage = sS + wave * 16 * ST;
+        const bool staged = a.aout && !a.fout;
 #pragma unroll
-        for (int m = 0; m < MT; ++m)
-            if ((t0 + m) * 16 < n) store_row<CPIN, NT, BWD>(a, acc[m], 0, 0, 0, (int)((t0 + m) * 16), cg, r, g);
+        for (int m = 0; m < MT; ++m) {
+            const long long v0 = (t0 + m) * 16;
+            if (v0 >= n) continue;
+            store_row<CPIN, NT, BWD>(a, acc[m], 0, 0, 0, (int)v0, cg, r, g, staged ? stage : nullptr, ST);
+            if (!staged) continue;
+            // the stage is written and read by this wave only: LDS keeps a
+            // wave's accesses in order, the fences keep the compiler's
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int j = 0; j < (32 * NT + 63) / 64; ++j) {   // 16 rows x 2 NT pieces
+                const int c = lane + 64 * j, per_row = NT * 2;
+                if (c >= 16 * per_row) break;
+                const int vr = c / per_row, part = c % per_row;
+                const long long v = v0 + vr;
+                if (v < n)
+                    *reinterpret_cast<uint4 *>(a.aout + v * a.cols + cg * NT * 16 + part * 8) =
+                        *reinterpret_cast<const uint4 *>(stage + vr * ST + part * 8);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
     }
 }
 
@@ -669,6 +702,7 @@ void conv_go(SpConv a, hipStream_t s) {
         long long per = (ntiles + 15) / 16;
         const long long cap = (1024 + a.G - 1) / a.G;
         if (per > cap) per = cap;
+        per = (per + 7) / 8 * 8;
         a.ntask = 0;
         k_sp_lin<CPIN, NT, BWD><<<(unsigned)(per * a.G), SBS, 0, s>>>(a);
     } else if constexpr (TAPS == 27 && CPIN >= 32) {
