@@ -75,10 +75,21 @@ __device__ inline void store_row(const SpConv &a, const f32x4 (&acc)[NT], int b,
     const long long HW = (long long)a.H * a.W;
     const int xg = x0 + 4 * g;
     const long long vrow = ((long long)b * a.D + z) * HW + (long long)y * a.W;
+    // dropout decisions of the lane's 4 NT elements, bit nt * 4 + i; one
+    // rolled loop keeps a single copy of the Philox body in the code
+    uint32_t dropped = 0;
+    if (a.drop) {
+#pragma unroll 1
+        for (int q = 0; q < 4 * NT; ++q) {
+            const int x = xg + (q & 3);
+            if (x < a.W && keep(a, (uint64_t)(vrow + x), (cg * NT + (q >> 2)) * 16 + r) == 0.f) dropped |= 1u << q;
+        }
+    }
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
         const int co = (cg * NT + nt) * 16 + r;
         const bool real_c = co < a.cout;
+        const float bco = (!BWD && real_c) ? a.bias[co] : 0.f;
         u16 ov[4] = {0, 0, 0, 0};
         for (int i = 0; i < 4; ++i) {
             const int x = xg + i;
@@ -86,7 +97,7 @@ __device__ inline void store_row(const SpConv &a, const f32x4 (&acc)[NT], int b,
             const long long v = vrow + x;
             float s = acc[nt][i];
             if (!BWD) {
-                s += real_c ? a.bias[co] : 0.f;
+                s += bco;
                 if (a.zout) a.zout[v * a.cols + co] = real_c ? bf16_bits(s) : (u16)0;
                 float o = a.relu ? fmaxf(s, 0.f) : s;
                 if (co < a.res) o += bf16_val(a.in[v * CPIN + co]);
@@ -94,11 +105,11 @@ __device__ inline void store_row(const SpConv &a, const f32x4 (&acc)[NT], int b,
                     if (real_c) a.fout[v * a.cout + co] = o;
                     continue;
                 }
-                if (a.drop) o *= keep(a, (uint64_t)v, co);
+                if (a.drop) o *= (dropped >> (nt * 4 + i)) & 1u ? 0.f : a.drop_scale;
                 ov[i] = real_c ? bf16_bits(o) : (u16)0;
             } else {
                 if (co < a.gin_ch) s += a.gin[v * a.gin_stride + co];
-                if (a.drop) s *= keep(a, (uint64_t)v, co);
+                if (a.drop) s *= (dropped >> (nt * 4 + i)) & 1u ? 0.f : a.drop_scale;
                 if (a.gout) a.gout[v * a.cols + co] = s;
                 const float d = !a.zin || bf16_val(a.zin[v * a.cols + co]) > 0.f ? s : 0.f;
                 ov[i] = real_c ? bf16_bits(d) : (u16)0;
