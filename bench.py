@@ -279,6 +279,20 @@ def swn_inference(reps=20, train_nodes=65536, train_reps=5):
             "ms_train_step": round(ms_t, 3), "train_nodes": train_nodes}
 
 
+def laser_search(pop=8, gens=3, steps=120):
+    """The laser-parameter search (differential evolution over a0, duration and
+    waist) on the underdense 32x16x16 plasma: pop * (gens + 1) hybrid runs of
+    `steps` steps each, FP32 library, timed on the host clock."""
+    from paper_2510_11174_amd import configs, hk, optimize
+    cfg = configs.plain_hybrid(32, 16, 16)
+    target = optimize.run_energy(hk, cfg, [1.2, 3.5, 6.0], steps)
+    r = optimize.optimize_laser(hk, cfg, target, [0.5, 2.0, 2.0], [2.0, 5.0, 10.0], steps, pop=pop, gens=gens,
+                                seed=3)
+    return {"runs": r["evaluations"], "steps_per_run": steps, "seconds": round(r["seconds"], 3),
+            "runs_per_s": round(r["runs_per_s"], 2), "hybrid_steps_per_s": round(r["steps_per_s"], 1),
+            "rel_error": r["rel_error"], "workload": "plain_hybrid_32x16x16, DE pop %d, %d generations" % (pop, gens)}
+
+
 def field_l2(x, y):
     import numpy as np
     num = math.sqrt(sum(float(np.sum((x[c] - y[c]) ** 2)) for c in x))
@@ -394,6 +408,7 @@ def main():
     out["roofline_cnn_switch"] = cnn_inference()
     out["roofline_state_predictor"] = sp_surrogate()
     out["roofline_switchnet"] = swn_inference()
+    out["laser_search"] = laser_search()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -125,6 +125,12 @@ def load(prec: str = "f32"):
     path = lib_path(prec)
     if not os.path.exists(path):
         raise RuntimeError("HIP library %s is not built (run __graft_entry__.build())" % path)
+    # torch first: the library then binds to the HIP runtime torch has loaded,
+    # so memory and streams from torch's allocator are valid in both
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path)
     P = C.POINTER
     vp = C.c_void_p
@@ -251,6 +257,7 @@ class _TorchMemory:
     def __init__(self):
         import torch
         self.torch = torch
+        torch.cuda.init()   # the caching allocator needs an initialized context
         self.device = torch.cuda.current_device()
         self.stream = torch.cuda.current_stream()
 
