@@ -60,7 +60,7 @@ class Species(C.Structure):
                 ("z_max", C.c_int32), ("target", C.c_int32), ("qed", C.c_int32),
                 ("pad", C.c_int32), ("charge", C.c_double), ("mass", C.c_double),
                 ("n0", C.c_double), ("x0", C.c_double), ("length", C.c_double),
-                ("u_th", C.c_double), ("ip_ev", C.c_double * MAX_LEVELS)]
+                ("u_th", C.c_double), ("ip_ev", C.c_double * MAX_LEVELS), ("gamma_ad", C.c_double)]
 
 
 class Laser(C.Structure):
@@ -85,7 +85,7 @@ class Diag(C.Structure):
                 ("charge_total", C.c_double), ("gauss_max", C.c_double), ("gauss_l2", C.c_double),
                 ("conv_loss", C.c_double), ("ion_energy", C.c_double),
                 ("photon_energy", C.c_double), ("kinetic_fraction", C.c_double),
-                ("fallback_fraction", C.c_double)]
+                ("fallback_fraction", C.c_double), ("fluid_th", C.c_double * MAX_SPECIES)]
 
 
 _lib = None
@@ -111,6 +111,8 @@ def lib():
         L.or_set_particles.argtypes = [C.c_void_p, C.c_int, C.c_size_t] + [C.c_void_p] * 6
         L.or_get_fluid.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.or_set_fluid.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+        L.or_get_fluid_p.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
+        L.or_set_fluid_p.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
         L.or_get_switch.argtypes = [C.c_void_p, C.c_void_p]
         L.or_set_switch.argtypes = [C.c_void_p, C.c_void_p]
         L.or_set_switch_mode.argtypes = [C.c_void_p, C.c_int]
@@ -191,6 +193,7 @@ def structs(cfg: dict):
         sp.x0 = s.get("x0", 0.0)
         sp.length = s.get("length", 1.0)
         sp.u_th = s.get("u_th", 0.0)
+        sp.gamma_ad = s.get("gamma_ad", 0.0)
         for k, v in enumerate(s.get("ip_ev", [])):
             sp.ip_ev[k] = v
     las = cfg.get("laser", {})
@@ -285,6 +288,17 @@ class Oracle:
         u = np.ascontiguousarray(u, np.float64).reshape(self.shape + (3,))
         if lib().or_set_fluid(self.h, sp, _ptr(n), _ptr(u)) != 0:
             raise ValueError("species %d has no fluid" % sp)
+
+    def get_pressure(self, sp: int) -> np.ndarray:
+        p = np.empty(self.shape)
+        if lib().or_get_fluid_p(self.h, sp, _ptr(p)) != 0:
+            raise ValueError("species %d has no warm fluid" % sp)
+        return p
+
+    def set_pressure(self, sp: int, p):
+        p = np.ascontiguousarray(p, np.float64).reshape(self.shape)
+        if lib().or_set_fluid_p(self.h, sp, _ptr(p)) != 0:
+            raise ValueError("species %d has no warm fluid" % sp)
 
     def get_switch(self) -> np.ndarray:
         out = np.empty(self.shape, np.uint8)

@@ -35,7 +35,8 @@ struct or_sim {
     size_t nn;                 /* sx * ny * nz */
     double *f[OR_NCOMP];
     or_parts p[OR_MAX_SPECIES];
-    double *fn[OR_MAX_SPECIES], *fu[OR_MAX_SPECIES][3];  /* cold fluid n, u at nodes */
+    double *fn[OR_MAX_SPECIES], *fu[OR_MAX_SPECIES][3];  /* fluid n, u at nodes */
+    double *fs[OR_MAX_SPECIES];   /* warm fluid: n K, K = p / n^gamma_ad (NULL: cold fluid) */
     uint8_t *sw, *calm;
     double *gauss0;
     int have_gauss0;

@@ -51,6 +51,7 @@ typedef struct {
     double n0, x0, length;  /* peak density; ramp start/length or foil start/thickness */
     double u_th;            /* Gaussian momentum spread per component */
     double ip_ev[OR_MAX_LEVELS];
+    double gamma_ad;        /* adiabatic index of the warm fluid; 0 = cold fluid */
 } or_species;
 
 typedef struct {
@@ -85,6 +86,7 @@ typedef struct {
                                               particles, escaped photons, pair rest energy */
     double kinetic_fraction;               /* fraction of kinetic nodes */
     double fallback_fraction;
+    double fluid_th[OR_MAX_SPECIES];       /* warm fluid thermal energy, sum p dV / (gamma_ad - 1) */
 } or_diag;
 
 typedef struct or_sim or_sim;
@@ -111,6 +113,9 @@ int or_set_particles(or_sim *s, int species, size_t n, const double *x, const do
 /* Fluid: node density n and momentum u per node, canonical layout. */
 int or_get_fluid(const or_sim *s, int species, double *n, double *u);
 int or_set_fluid(or_sim *s, int species, const double *n, const double *u);
+/* Warm fluid pressure per node (canonical layout); set after the density. */
+int or_get_fluid_p(const or_sim *s, int species, double *p);
+int or_set_fluid_p(or_sim *s, int species, const double *p);
 
 /* Switch map, one byte per node (canonical layout): 1 kinetic, 0 fluid. */
 int or_get_switch(const or_sim *s, uint8_t *out);

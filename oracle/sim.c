@@ -42,6 +42,7 @@ or_sim *or_create(const or_grid *g, const or_species *sp, int nspecies, const or
         if (sp[i].fluid && r->switch_mode != OR_SW_ALL_PIC) {
             s->fn[i] = (double *)calloc(s->nn, sizeof(double));
             for (int d = 0; d < 3; ++d) s->fu[i][d] = (double *)calloc(s->nn, sizeof(double));
+            if (sp[i].gamma_ad > 0.0) s->fs[i] = (double *)calloc(s->nn, sizeof(double));
         }
     }
     if (r->enable_qed) or_qed_init(s);
@@ -57,6 +58,7 @@ void or_destroy(or_sim *s) {
         free(p->ci); free(p->cj); free(p->ck); free(p->ox); free(p->oy); free(p->oz); free(p->ux); free(p->uy); free(p->uz);
         free(p->w); free(p->tau); free(p->id); free(p->zc);
         free(s->fn[i]);
+        free(s->fs[i]);
         for (int d = 0; d < 3; ++d) free(s->fu[i][d]);
     }
     free(s->sw); free(s->calm); free(s->gauss0); free(s->ev);
@@ -182,6 +184,27 @@ int or_set_fluid(or_sim *s, int sp, const double *n, const double *u) {
     return 0;
 }
 
+/* p = (n K) n^(gamma - 1) */
+int or_get_fluid_p(const or_sim *s, int sp, double *p) {
+    if (sp < 0 || sp >= s->nsp || !s->fs[sp]) return -1;
+    const double ga = s->sp[sp].gamma_ad;
+    for (size_t c = 0; c < s->nn; ++c) {
+        double n = s->fn[sp][c];
+        p[c] = n > 0.0 ? s->fs[sp][c] * pow(n, ga - 1.0) : 0.0;
+    }
+    return 0;
+}
+
+int or_set_fluid_p(or_sim *s, int sp, const double *p) {
+    if (sp < 0 || sp >= s->nsp || !s->fs[sp]) return -1;
+    const double ga = s->sp[sp].gamma_ad;
+    for (size_t c = 0; c < s->nn; ++c) {
+        double n = s->fn[sp][c];
+        s->fs[sp][c] = n > 0.0 ? p[c] * pow(n, 1.0 - ga) : 0.0;
+    }
+    return 0;
+}
+
 int or_get_switch(const or_sim *s, uint8_t *out) { memcpy(out, s->sw, s->nn); return 0; }
 
 int or_set_switch(or_sim *s, const uint8_t *in) {
@@ -241,6 +264,9 @@ int or_diagnostics(or_sim *s, or_diag *d) {
                 d->fluid_mass[isp] += m;
                 d->fluid_kin[isp] += m * sp->mass * (sqrt(1.0 + u2) - 1.0);
                 d->charge_total += sp->charge * m;
+                if (s->fs[isp] && s->fn[isp][c] > 0.0)
+                    d->fluid_th[isp] += s->fs[isp][c] * pow(s->fn[isp][c], sp->gamma_ad - 1.0) * dv /
+                                        (sp->gamma_ad - 1.0);
             }
     }
     /* Gauss: change of (div E - rho) since the first step, over interior

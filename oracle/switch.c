@@ -32,6 +32,12 @@
  *      virtually from the node to Philox positions in the node's dual cell.
  *  A CIC particle sitting on a node has exactly the node-delta charge of the
  *  fluid, so both conversions keep div E - rho unchanged.
+ *  Warm fluid (gamma_ad > 0): the kinetic energy an absorption loses (the
+ *  particles' spread about the merged flow) heats the node, p += (gamma_ad -
+ *  1) dE / dV, instead of going to the ledger; a spawned particle gets the
+ *  fluid momentum plus a Gaussian spread sqrt(T / m) per component, T = p / n
+ *  (Box-Muller on Philox draws, tag 13), and the ledger takes the difference
+ *  between the fluid's kinetic plus thermal energy and the sample's.
  */
 #include "or_internal.h"
 
@@ -184,6 +190,9 @@ void or_reconcile(or_sim *s) {
         double *n = s->fn[isp];
         double *M = (double *)calloc(s->nn, sizeof(double));
         double *Pm = (double *)calloc(s->nn * 3, sizeof(double));
+        double *KEa = (double *)calloc(s->nn, sizeof(double));   /* absorbed kinetic energy (warm) */
+        double *S = s->fs[isp];
+        const double ga = sp->gamma_ad;
         uint8_t *touched = (uint8_t *)calloc(s->nn, 1);
         /* absorb, in storage order */
         size_t keep = 0;
@@ -207,7 +216,8 @@ void or_reconcile(or_sim *s) {
             or_deposit_move(s, sp->charge, p->w[q], cell, X, Xn);
             double u[3] = {p->ux[q], p->uy[q], p->uz[q]};
             double gam = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            s->conv_loss += p->w[q] * sp->mass * (gam - 1.0);
+            if (S) KEa[c] += p->w[q] * sp->mass * (gam - 1.0);
+            else s->conv_loss += p->w[q] * sp->mass * (gam - 1.0);
             M[c] += p->w[q];
             for (int d = 0; d < 3; ++d) Pm[3 * c + d] += p->w[q] * u[d];
             touched[c] = 1;
@@ -222,7 +232,13 @@ void or_reconcile(or_sim *s) {
             double un[3];
             for (int d = 0; d < 3; ++d) un[d] = (m0 * u0[d] + Pm[3 * c + d]) / mt;
             double gn = sqrt(1.0 + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
-            s->conv_loss += m0 * sp->mass * (g0 - 1.0) - mt * sp->mass * (gn - 1.0);
+            double loss = m0 * sp->mass * (g0 - 1.0) - mt * sp->mass * (gn - 1.0);
+            if (S) {
+                /* the kinetic energy the merge loses becomes heat of the node */
+                double pold = n[c] > 0.0 ? S[c] * pow(n[c], ga - 1.0) : 0.0;
+                double pnew = pold + (ga - 1.0) * (KEa[c] + loss) / dv;
+                S[c] = pnew * pow(mt / dv, 1.0 - ga);
+            } else s->conv_loss += loss;
             n[c] = mt / dv;
             for (int d = 0; d < 3; ++d) s->fu[isp][d][c] = un[d];
         }
@@ -238,6 +254,14 @@ void or_reconcile(or_sim *s) {
                     if (mass < wmin) continue;
                     double w = mass / m;
                     double u[3] = {s->fu[isp][0][c], s->fu[isp][1][c], s->fu[isp][2][c]};
+                    /* warm fluid: thermal spread sqrt(T / m) per component, T = p / n */
+                    double sig = 0.0, before = 0.0, after = 0.0;
+                    if (S) {
+                        double pr = S[c] * pow(n[c], ga - 1.0);
+                        sig = sqrt(fmax(pr / n[c], 0.0) / sp->mass);
+                        before = mass * sp->mass * (sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) - 1.0) +
+                                 pr * dv / (ga - 1.0);
+                    }
                     uint64_t node = (uint64_t)i + (uint64_t)nxn * ((uint64_t)j + (uint64_t)g->ny * k);
                     for (int q = 0; q < m; ++q) {
                         uint32_t r[4];
@@ -247,18 +271,36 @@ void or_reconcile(or_sim *s) {
                         double X0[3] = {0.0, 0.0, 0.0};
                         double X1[3] = {or_uniform(r[0]) - 0.5, or_uniform(r[1]) - 0.5,
                                         or_uniform(r[2]) - 0.5};
-                        double ux = u[0];
+                        double uq[3] = {u[0], u[1], u[2]};
+                        if (S) {
+                            /* Box-Muller on Philox draws, tag 13 */
+                            uint32_t t[4];
+                            or_draw4(s, node, (uint32_t)s->step, 13, (uint32_t)q, t);
+                            double r0 = or_uniform(t[0]), r1 = or_uniform(t[1]), r2 = or_uniform(t[2]),
+                                   r3 = or_uniform(t[3]);
+                            double m0 = sqrt(-2.0 * log(r0)), m1 = sqrt(-2.0 * log(r2));
+                            const double tp = 6.283185307179586;
+                            uq[0] += sig * m0 * cos(tp * r1);
+                            uq[1] += sig * m0 * sin(tp * r1);
+                            uq[2] += sig * m1 * cos(tp * r3);
+                            after += w * sp->mass * (sqrt(1.0 + uq[0] * uq[0] + uq[1] * uq[1] + uq[2] * uq[2]) - 1.0);
+                        }
+                        double ux = uq[0];
                         or_reflect_x(s, i, &X1[0], &ux);
                         or_deposit_move(s, sp->charge, w, cell, X0, X1);
                         or_carry(s, cell, X1);
                         uint64_t id = (1ull << 63) | ((uint64_t)s->step << 40) | (node << 6) | (uint64_t)q;
                         or_parts_push_back(p, cell[0], cell[1], cell[2], X1[0], X1[1], X1[2],
-                                           u[0], u[1], u[2], w, sp->qed ? or_qed_tau0(s, id) : 0.0, id,
+                                           uq[0], uq[1], uq[2], w, sp->qed ? or_qed_tau0(s, id) : 0.0, id,
                                            (int32_t)llround(sp->charge));
+                    }
+                    if (S) {
+                        s->conv_loss += before - after;   /* the sample's energy differs from the fluid's */
+                        S[c] = 0.0;
                     }
                     n[c] = 0.0;
                     s->fu[isp][0][c] = s->fu[isp][1][c] = s->fu[isp][2][c] = 0.0;
                 }
-        free(M); free(Pm); free(touched);
+        free(M); free(Pm); free(KEa); free(touched);
     }
 }
