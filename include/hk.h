@@ -90,7 +90,12 @@ typedef struct {
  * kind HK_ION uses `charge` as the initial charge state; `ionizable` ions
  * ionize level by level up to z_max with potentials ip_ev[level] (eV) and put
  * the freed electrons into species `target`.  `fluid` species may be held as
- * a cold fluid in fluid nodes.  `mobile` = 0 freezes the species (no push, no
+ * a fluid in fluid nodes: cold (gamma_ad = 0) or warm, with adiabatic
+ * pressure p = K n^gamma_ad (Methodology, plasma-model paragraph): the fluid
+ * then carries S = n K, advected with its mass flux, feels the force
+ * -grad p / n (taken non-relativistically), is heated by the kinetic energy
+ * an absorption loses, and gives spawned particles a Gaussian spread
+ * sqrt(T / m), T = p / n.  `mobile` = 0 freezes the species (no push, no
  * current).  `qed`: photon emission (leptons) or pair creation (photons). */
 typedef struct {
     int32_t kind, ppc, profile, mobile;
@@ -100,6 +105,7 @@ typedef struct {
     double n0, x0, length;     /* peak density; ramp start/length or foil start/thickness */
     double u_th;               /* Gaussian momentum spread per component (m_e c) */
     double ip_ev[HK_MAX_LEVELS];
+    double gamma_ad;           /* adiabatic index of the species' warm fluid; 0 = cold fluid */
 } hk_species_desc;
 
 /* Laser antenna: a current sheet on node plane i_antenna radiating a
@@ -163,6 +169,7 @@ typedef struct {
                                               particles, escaped photons, pair rest energy */
     double kinetic_fraction;               /* kinetic nodes / all nodes */
     double fallback_fraction;              /* CNN nodes that fell back to threshold */
+    double fluid_th[HK_MAX_SPECIES];       /* warm fluid thermal energy, sum p dV / (gamma_ad - 1) */
 } hk_diag;
 
 /* Host-side particle arrays, FP64 regardless of the build: x[3n] absolute
@@ -213,6 +220,11 @@ int hk_set_particles(hk_sim *sim, int species, const hk_particles *in);
 /* Cold fluid of a fluid species: n[(nx+1)*ny*nz], u[3*(nx+1)*ny*nz]. */
 int hk_get_fluid(hk_sim *sim, int species, double *n, double *u, size_t nodes);
 int hk_set_fluid(hk_sim *sim, int species, const double *n, const double *u, size_t nodes);
+/* Warm fluid pressure per node (host FP64, canonical layout, same size as
+ * the fluid density); HK_EINVAL for a cold or missing fluid.  Set the density
+ * first: the pressure is stored as S = p n^(1 - gamma_ad). */
+int hk_get_fluid_p(hk_sim *sim, int species, double *p, size_t nodes);
+int hk_set_fluid_p(hk_sim *sim, int species, const double *p, size_t nodes);
 
 /* Timers since the last hk_enable_timing(sim, 1), collected with HIP events
  * on the run stream (they add synchronisation, so timed runs are slower):

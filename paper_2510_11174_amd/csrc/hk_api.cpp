@@ -55,7 +55,8 @@ struct DevSpecies {
     int inbox_cap = 0;
     long long *g_off0 = nullptr;  // device {0}
     int *g_capmax = nullptr;      // device {INT_MAX}
-    real *fn = nullptr, *fu[3] = {nullptr, nullptr, nullptr};  // cold fluid
+    real *fn = nullptr, *fu[3] = {nullptr, nullptr, nullptr};  // fluid density and momentum
+    real *fs = nullptr;           // warm fluid: entropy density n K, K = p / n^gamma_ad
     IonP *ion = nullptr;          // device rate constants
     long long reserve_hint = 0;   // expected peak count (ionization targets)
     unsigned *umax2 = nullptr;    // device [ntiles]: bound on |u|^2 (float bits) since the
@@ -86,7 +87,7 @@ struct hk_sim {
     real *mur_old = nullptr;
     uint8_t *sw = nullptr, *calm = nullptr, *hot = nullptr, *notcold = nullptr;
     real *mom = nullptr;         // switch moments (7 grid arrays)
-    double *macc = nullptr;      // absorbed mass and momentum (4 grid arrays)
+    double *macc = nullptr;      // absorbed mass, momentum and kinetic energy (5 grid arrays)
     real *fluid_scratch = nullptr;
     double *gauss0 = nullptr, *tmp_a = nullptr, *tmp_b = nullptr;
     double *dsum = nullptr;      // diagnostic accumulators
@@ -771,16 +772,18 @@ void reconcile(hk_sim *S) {
         DevSpecies &D = S->sp[isp];
         if (!D.d.fluid || !D.fn) continue;
         SpecP P = specp(D);
+        const WarmP W{D.fs, D.d.gamma_ad};
         if (D.capacity) {
-            launch_absorb_tiles(g, P, D.buf[D.cur], cur_bins(D), S->sw, S->f, S->macc, S->ledger, s);
-            launch_absorb_finish_nodes(g, P.m, S->macc, D.fn, D.fu[0], D.fu[1], D.fu[2], S->ledger, s);
+            launch_absorb_tiles(g, P, D.buf[D.cur], cur_bins(D), S->sw, S->f, S->macc, S->ledger, D.fs != nullptr,
+                                s);
+            launch_absorb_finish_nodes(g, P.m, S->macc, D.fn, D.fu[0], D.fu[1], D.fu[2], W, S->ledger, s);
         }
         double dv = g.ddx * g.ddy * g.ddz;
         int m = std::max(1, D.d.ppc);
         real wmin = (real)(S->run.spawn_frac * D.d.n0 * dv / m);
-        launch_spawn_nodes(g, P, S->sw, D.fn, D.fu[0], D.fu[1], D.fu[2], S->f, wmin, m, S->run.seed,
+        launch_spawn_nodes(g, P, S->sw, D.fn, D.fu[0], D.fu[1], D.fu[2], W, S->f, wmin, m, S->run.seed,
                            (int)S->step, D.inbox, S->status + 1 + 2 * isp, D.inbox_cap,
-                           S->status + 13, S->wmax + isp, D.umax2, s);
+                           S->status + 13, S->wmax + isp, D.umax2, S->ledger, s);
     }
 }
 
@@ -884,7 +887,7 @@ int one_step(hk_sim *S) {
     if (hybrid) {
         for (int isp = 0; isp < S->nsp; ++isp) {
             DevSpecies &D = S->sp[isp];
-            if (D.fn) launch_fluid(g, specp(D), D.fn, D.fu[0], D.fu[1], D.fu[2], S->f,
+            if (D.fn) launch_fluid(g, specp(D), D.fn, D.fu[0], D.fu[1], D.fu[2], WarmP{D.fs, D.d.gamma_ad}, S->f,
                                    S->fluid_scratch, (real)S->run.n_floor, s);
         }
         time_mark(S, 2);
@@ -913,10 +916,10 @@ int ensure_fluid(hk_sim *S) {
     const GridP &g = S->g;
     if (!S->mom) {
         S->mom = (real *)dalloc(S, sizeof(real) * 7 * (size_t)g.nn);
-        S->macc = (double *)dalloc(S, sizeof(double) * 4 * (size_t)g.nn);
+        S->macc = (double *)dalloc(S, sizeof(double) * 5 * (size_t)g.nn);
         S->hot = (uint8_t *)dalloc(S, (size_t)g.nn);
         S->notcold = (uint8_t *)dalloc(S, (size_t)g.nn);
-        S->fluid_scratch = (real *)dalloc(S, sizeof(real) * 7 * (size_t)g.nn);
+        S->fluid_scratch = (real *)dalloc(S, sizeof(real) * 8 * (size_t)g.nn);
         if (!S->mom || !S->macc || !S->hot || !S->notcold || !S->fluid_scratch)
             return fail(S, HK_ENOMEM, "switch arrays");
     }
@@ -925,7 +928,9 @@ int ensure_fluid(hk_sim *S) {
         if (!D.d.fluid || D.fn) continue;
         D.fn = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
         for (int d = 0; d < 3; ++d) D.fu[d] = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
-        if (!D.fn || !D.fu[0] || !D.fu[1] || !D.fu[2]) return fail(S, HK_ENOMEM, "fluid arrays");
+        if (D.d.gamma_ad > 0.0) D.fs = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
+        if (!D.fn || !D.fu[0] || !D.fu[1] || !D.fu[2] || (D.d.gamma_ad > 0.0 && !D.fs))
+            return fail(S, HK_ENOMEM, "fluid arrays");
         int rc = ensure_inbox(S, isp, inbox_need(S, isp));
         if (rc) return rc;
     }
@@ -1509,6 +1514,37 @@ int hk_set_fluid(hk_sim *S, int isp, const double *n, const double *u, size_t no
     return HK_OK;
 }
 
+// Warm fluid pressure p = S n^(gamma_ad - 1) per node (host FP64); setting
+// converts with the density already on the device.
+int hk_get_fluid_p(hk_sim *S, int isp, double *p, size_t nodes) {
+    if (!S || !p || isp < 0 || isp >= S->nsp || nodes != (size_t)S->g.nn) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    DevSpecies &D = S->sp[isp];
+    if (!D.fs) return fail(S, HK_EINVAL, "species %d has no warm fluid", isp);
+    std::vector<real> hn(nodes), hs(nodes);
+    HIPCHK(S, hipMemcpyAsync(hn.data(), D.fn, sizeof(real) * nodes, hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipMemcpyAsync(hs.data(), D.fs, sizeof(real) * nodes, hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    for (size_t c = 0; c < nodes; ++c)
+        p[c] = hn[c] > 0 ? (double)hs[c] * std::pow((double)hn[c], D.d.gamma_ad - 1.0) : 0.0;
+    return HK_OK;
+}
+
+int hk_set_fluid_p(hk_sim *S, int isp, const double *p, size_t nodes) {
+    if (!S || !p || isp < 0 || isp >= S->nsp || nodes != (size_t)S->g.nn) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    DevSpecies &D = S->sp[isp];
+    if (!D.fs) return fail(S, HK_EINVAL, "species %d has no warm fluid", isp);
+    std::vector<real> hn(nodes), hs(nodes);
+    HIPCHK(S, hipMemcpyAsync(hn.data(), D.fn, sizeof(real) * nodes, hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    for (size_t c = 0; c < nodes; ++c)
+        hs[c] = hn[c] > 0 ? (real)(p[c] * std::pow((double)hn[c], 1.0 - D.d.gamma_ad)) : (real)0;
+    HIPCHK(S, hipMemcpyAsync(D.fs, hs.data(), sizeof(real) * nodes, hipMemcpyHostToDevice, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
+    return HK_OK;
+}
+
 int hk_enable_timing(hk_sim *S, int on) {
     if (!S) return HK_EINVAL;
     if (S->poisoned) return HK_ESTATE;
@@ -1548,6 +1584,7 @@ int hk_diagnostics(hk_sim *S, hk_diag *d) {
         SpecP P = specp(D);
         if (D.capacity) launch_particle_sums(g, P, D.buf[D.cur], cur_bins(D), S->dsum + 2 + 3 * isp, s);
         if (D.fn) launch_fluid_sums(g, P, D.fn, D.fu[0], D.fu[1], D.fu[2], S->dsum + 20 + 3 * isp, s);
+        if (D.fs) launch_fluid_heat(g, D.fn, WarmP{D.fs, D.d.gamma_ad}, S->dsum + 46 + isp, s);
     }
     // Gauss: (divE - rho) now minus (divE - rho) at the snapshot
     launch_divE(g, S->f, S->tmp_a, s);
@@ -1570,6 +1607,7 @@ int hk_diagnostics(hk_sim *S, hk_diag *d) {
         d->fluid_kin[isp] = h[20 + 3 * isp];
         d->fluid_mass[isp] = h[21 + 3 * isp];
         d->charge_total += h[22 + 3 * isp];
+        d->fluid_th[isp] = h[46 + isp];
     }
     d->gauss_l2 = h[41] > 0 ? std::sqrt(h[40] / h[41]) : 0.0;
     uint64_t mb;
@@ -1652,12 +1690,14 @@ int hk_save(hk_sim *S, const char *path) {
         if ((rc = field(a.id, sizeof(uint64_t)))) return rc;
         if (D.has_z && (rc = field(a.zc, sizeof(int)))) return rc;
         if (D.has_tau && (rc = field(a.tau, sizeof(double)))) return rc;
-        const int has_fluid = D.fn != nullptr;
+        // 0: no fluid; 1: n and u; 2: n, u and the warm fluid's entropy density
+        const int has_fluid = D.fn == nullptr ? 0 : (D.fs ? 2 : 1);
         F.put(has_fluid);
         if (has_fluid) {
             real *fl[4] = {D.fn, D.fu[0], D.fu[1], D.fu[2]};
             for (real *q : fl)
                 if ((rc = ck_dev_out(S, F, q, sizeof(real) * (size_t)g.nn))) return rc;
+            if (has_fluid == 2 && (rc = ck_dev_out(S, F, D.fs, sizeof(real) * (size_t)g.nn))) return rc;
         }
     }
     if (!F.ok) return fail(S, HK_EIO, "checkpoint: write to %s failed", path);
@@ -1725,9 +1765,12 @@ int hk_load(hk_sim *S, const char *path) {
         if (has_fluid) {
             if ((rc = ensure_fluid(S))) return rc;
             if (!D.fn) return fail(S, HK_EINVAL, "checkpoint: species %d has a fluid here only in the file", isp);
+            if ((has_fluid == 2) != (D.fs != nullptr))
+                return fail(S, HK_EINVAL, "checkpoint: species %d is warm in one of file and run only", isp);
             real *fl[4] = {D.fn, D.fu[0], D.fu[1], D.fu[2]};
             for (real *q : fl)
                 if ((rc = ck_dev_in(S, F, q, sizeof(real) * (size_t)g.nn))) return rc;
+            if (has_fluid == 2 && (rc = ck_dev_in(S, F, D.fs, sizeof(real) * (size_t)g.nn))) return rc;
         }
     }
     if (!F.ok) return fail(S, HK_EIO, "checkpoint: file ends early");

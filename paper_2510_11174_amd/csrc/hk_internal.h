@@ -81,8 +81,8 @@ __host__ __device__ inline double u01d(uint32_t x) {
 }
 
 // Philox tags (one stream per purpose).
-enum { TAG_POS = 1, TAG_MOM = 2, TAG_ION = 3, TAG_CONV = 12, TAG_EMIT = 16, TAG_TAU = 17,
-       TAG_PAIR = 18, TAG_DROP = 24 };
+enum { TAG_POS = 1, TAG_MOM = 2, TAG_ION = 3, TAG_CONV = 12, TAG_CONV_TH = 13, TAG_EMIT = 16,
+       TAG_TAU = 17, TAG_PAIR = 18, TAG_DROP = 24 };
 
 // Ids of particles born in QED events: splitmix64 (S. Vigna's finaliser)
 // of the parent id mixed with the step and the kind k (1 photon, 2 electron,
@@ -214,9 +214,15 @@ void launch_fluid_sums(const GridP &g, const SpecP &sp, const real *n, const rea
 void launch_count_kinetic(const GridP &g, const uint8_t *sw, double *out, hipStream_t s);
 void launch_sub(long long n, double *a, const double *b, hipStream_t s);
 
-// fluid (k_fluid.hip)
-void launch_fluid(const GridP &g, const SpecP &sp, real *n, real *ux, real *uy, real *uz,
+// fluid (k_fluid.hip).  A warm fluid species carries its entropy density
+// S = n K (K = p / n^ga) beside n and u; S == nullptr is a cold fluid.
+struct WarmP {
+    real *S;
+    double ga;   // adiabatic index
+};
+void launch_fluid(const GridP &g, const SpecP &sp, real *n, real *ux, real *uy, real *uz, WarmP w,
                   real *const f[9], real *scratch, real n_floor, hipStream_t s);
+void launch_fluid_heat(const GridP &g, const real *n, WarmP w, double *out, hipStream_t s);
 void launch_fluid_rho(const GridP &g, const SpecP &sp, const real *n, double *rho,
                       hipStream_t s);
 
@@ -276,14 +282,15 @@ void launch_indicators_nodes(const GridP &g, const SwitchP &P, const real *mom, 
                              hipStream_t s);
 void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, const uint8_t *notcold,
                          uint8_t *sw, uint8_t *calm, hipStream_t s);
+// macc: 5 grid arrays (FP64): absorbed weight, momentum (3), kinetic energy
 void launch_absorb_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, const uint8_t *sw,
-                         real *const f[9], double *macc, double *ledger, hipStream_t s);
+                         real *const f[9], double *macc, double *ledger, bool warm, hipStream_t s);
 void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n, real *ux,
-                                real *uy, real *uz, double *ledger, hipStream_t s);
+                                real *uy, real *uz, WarmP w, double *ledger, hipStream_t s);
 void launch_spawn_nodes(const GridP &g, const SpecP &sp, const uint8_t *sw, real *n, real *ux,
-                        real *uy, real *uz, real *const f[9], real wmin, int m, uint64_t seed,
+                        real *uy, real *uz, WarmP w, real *const f[9], real wmin, int m, uint64_t seed,
                         int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
-                        unsigned *wmax_bits, unsigned *umax2, hipStream_t s);
+                        unsigned *wmax_bits, unsigned *umax2, double *ledger, hipStream_t s);
 
 // QED tables built on the host (hk_qed.cpp): We[256], Wb[256], Xe[256*128], Xb[256*128]
 const double *hk_qed_host_tables();

@@ -391,11 +391,13 @@ __device__ inline void block_add_d(double v, double *out) {
     __syncthreads();
 }
 
-// macc layout (4 grid arrays, FP64): M = sum w, P (3) = sum w u.
+// macc layout (5 grid arrays, FP64): M = sum w, P (3) = sum w u, and for a
+// warm fluid the absorbed kinetic energy per node (which then heats the node
+// instead of going to the ledger).
 __global__ void __launch_bounds__(BS)
 k_absorb(GridP g, SpecP sp, PArr a, Bins bins, const uint8_t *__restrict__ sw,
          real *__restrict__ Jx, real *__restrict__ Jy, real *__restrict__ Jz, double *__restrict__ macc,
-         double *__restrict__ ledger) {
+         double *__restrict__ ledger, int warm) {
     __shared__ real sJ[3 * JT3];
     __shared__ int any;
     const int t = blockIdx.x;
@@ -439,7 +441,9 @@ k_absorb(GridP g, SpecP sp, PArr a, Bins bins, const uint8_t *__restrict__ sw,
         esirkepov_lds(sJ, lx, ly, lz, SX, SY, SZ, qw * g.dx / g.dt, qw * g.dy / g.dt, qw * g.dz / g.dt);
         any = 1;
         double ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip];
-        ke += (double)w * (double)sp.m * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
+        const double kp = (double)w * (double)sp.m * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
+        if (warm) atomicAdd(&macc[4 * nn + node], kp);
+        else ke += kp;
         atomicAdd(&macc[node], (double)w);
         atomicAdd(&macc[nn + node], (double)w * ux);
         atomicAdd(&macc[2 * nn + node], (double)w * uy);
@@ -465,7 +469,7 @@ k_absorb(GridP g, SpecP sp, PArr a, Bins bins, const uint8_t *__restrict__ sw,
 
 __global__ void __launch_bounds__(BS)
 k_absorb_finish(GridP g, real mass, double *__restrict__ macc, real *__restrict__ n,
-                real *__restrict__ ux, real *__restrict__ uy, real *__restrict__ uz,
+                real *__restrict__ ux, real *__restrict__ uy, real *__restrict__ uz, WarmP wp,
                 double *__restrict__ ledger) {
     long long c = (long long)blockIdx.x * BS + threadIdx.x;
     double d = 0;
@@ -480,19 +484,31 @@ k_absorb_finish(GridP g, real mass, double *__restrict__ macc, real *__restrict_
         for (int q = 0; q < 3; ++q) un[q] = (m0 * u0[q] + macc[(1 + q) * nn + c]) / mt;
         double gn = sqrt(1.0 + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
         d = m0 * (double)mass * (g0 - 1.0) - mt * (double)mass * (gn - 1.0);
+        if (wp.S) {
+            // the merge's kinetic energy loss heats the node: p += (ga - 1) dE / dV
+            const double ga = wp.ga;
+            const double pold = n[c] > (real)0 ? (double)wp.S[c] * pow((double)n[c], ga - 1.0) : 0.0;
+            const double pnew = pold + (ga - 1.0) * (macc[4 * nn + c] + d) / dv;
+            wp.S[c] = (real)(pnew * pow(mt / dv, 1.0 - ga));
+            d = 0;
+        }
         n[c] = (real)(mt / dv);
         ux[c] = (real)un[0]; uy[c] = (real)un[1]; uz[c] = (real)un[2];
-        for (int q = 0; q < 4; ++q) macc[q * nn + c] = 0.0;
+        for (int q = 0; q < 5; ++q) macc[q * nn + c] = 0.0;
     }
     block_add_d(d, ledger);
 }
 
+// A warm node's particles get the fluid momentum plus a Gaussian spread
+// sqrt(T / m) per component, T = p / n (Box-Muller on Philox draws, tag
+// TAG_CONV_TH); the ledger takes the fluid's kinetic plus thermal energy
+// minus the sample's kinetic energy.
 __global__ void __launch_bounds__(BS)
 k_spawn(GridP g, SpecP sp, const uint8_t *__restrict__ sw, real *__restrict__ n, real *__restrict__ ux,
-        real *__restrict__ uy, real *__restrict__ uz, real *__restrict__ Jx, real *__restrict__ Jy,
+        real *__restrict__ uy, real *__restrict__ uz, WarmP wp, real *__restrict__ Jx, real *__restrict__ Jy,
         real *__restrict__ Jz, real wmin, int m, uint64_t seed, int step, PArr inbox,
         int *__restrict__ inbox_n, int inbox_cap, int *__restrict__ deferred,
-        unsigned *__restrict__ wmax_bits, unsigned *__restrict__ umax2) {
+        unsigned *__restrict__ wmax_bits, unsigned *__restrict__ umax2, double *__restrict__ ledger) {
     long long c = (long long)blockIdx.x * BS + threadIdx.x;
     if (c >= g.nn) return;
     int i, j, k;
@@ -515,6 +531,14 @@ k_spawn(GridP g, SpecP sp, const uint8_t *__restrict__ sw, real *__restrict__ n,
     const real w = mass / (real)m;
     if (__float_as_uint(fabsf((float)w)) > *wmax_bits) atomicMax(wmax_bits, __float_as_uint(fabsf((float)w)));
     const real u[3] = {ux[c], uy[c], uz[c]};
+    double sig = 0.0, before = 0.0, after = 0.0;
+    if (wp.S) {
+        const double pr = (double)wp.S[c] * pow((double)nc, wp.ga - 1.0);
+        sig = sqrt(fmax(pr / (double)nc, 0.0) / (double)sp.m);
+        before = (double)mass * (double)sp.m *
+                     (sqrt(1.0 + (double)u[0] * u[0] + (double)u[1] * u[1] + (double)u[2] * u[2]) - 1.0) +
+                 pr * (double)dv / (wp.ga - 1.0);
+    }
     {
         // the new particles sit in cells next to the node: raise the bound of
         // the node's tile (the moments read the bounds of neighbouring tiles too)
@@ -539,14 +563,34 @@ k_spawn(GridP g, SpecP sp, const uint8_t *__restrict__ sw, real *__restrict__ n,
         if (per) cc[0] = wrapi(cc[0], g.nx);
         cc[1] = wrapi(cc[1], g.ny);
         cc[2] = wrapi(cc[2], g.nz);
+        real uq[3] = {u[0], u[1], u[2]};
+        if (wp.S) {
+            uint32_t t4[4];
+            draw4(seed, node, (uint32_t)step, TAG_CONV_TH, (uint32_t)q, t4);
+            const double r0 = u01d(t4[0]), r1 = u01d(t4[1]), r2 = u01d(t4[2]), r3 = u01d(t4[3]);
+            const double m0 = sqrt(-2.0 * log(r0)), m1 = sqrt(-2.0 * log(r2));
+            const double tp = 6.283185307179586;
+            uq[0] = (real)((double)u[0] + sig * m0 * cos(tp * r1));
+            uq[1] = (real)((double)u[1] + sig * m0 * sin(tp * r1));
+            uq[2] = (real)((double)u[2] + sig * m1 * cos(tp * r3));
+            after += (double)w * (double)sp.m *
+                     (sqrt(1.0 + (double)uq[0] * uq[0] + (double)uq[1] * uq[1] + (double)uq[2] * uq[2]) - 1.0);
+            const int ti = min(i, g.nx - 1) >> TLOG, tj = j >> TLOG, tk = k >> TLOG;
+            const float u2 = (float)(uq[0] * uq[0] + uq[1] * uq[1] + uq[2] * uq[2]);
+            if (u2 > 0.f) atomicMax(&umax2[ti + g.ntx * (tj + g.nty * tk)], __float_as_uint(u2));
+        }
         const long long s = k0 + q;
         inbox.cell[s] = cc[0] + g.nx * (cc[1] + g.ny * cc[2]);
         inbox.rx[s] = X1[0]; inbox.ry[s] = X1[1]; inbox.rz[s] = X1[2];
-        inbox.ux[s] = u[0]; inbox.uy[s] = u[1]; inbox.uz[s] = u[2];
+        inbox.ux[s] = uq[0]; inbox.uy[s] = uq[1]; inbox.uz[s] = uq[2];
         inbox.w[s] = w;
         inbox.id[s] = (1ull << 63) | ((uint64_t)step << 40) | (node << 6) | (uint64_t)q;
         if (sp.has_z) inbox.zc[s] = (int)sp.q;
         if (sp.has_tau) inbox.tau[s] = tau0(seed, inbox.id[s]);
+    }
+    if (wp.S) {
+        wp.S[c] = 0;
+        atomicAdd(ledger, before - after);
     }
     n[c] = 0; ux[c] = 0; uy[c] = 0; uz[c] = 0;
 }
@@ -579,17 +623,18 @@ void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, c
     k_dilate<<<blocks(g.nn), BS, 0, s>>>(g, P, hot, notcold, sw, calm);
 }
 void launch_absorb_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, const uint8_t *sw,
-                         real *const f[9], double *macc, double *ledger, hipStream_t s) {
-    k_absorb<<<g.ntiles, BS, 0, s>>>(g, sp, a, b, sw, f[HK_JX], f[HK_JY], f[HK_JZ], macc, ledger);
+                         real *const f[9], double *macc, double *ledger, bool warm, hipStream_t s) {
+    k_absorb<<<g.ntiles, BS, 0, s>>>(g, sp, a, b, sw, f[HK_JX], f[HK_JY], f[HK_JZ], macc, ledger, warm ? 1 : 0);
 }
 void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n, real *ux,
-                                real *uy, real *uz, double *ledger, hipStream_t s) {
-    k_absorb_finish<<<blocks(g.nn), BS, 0, s>>>(g, mass, macc, n, ux, uy, uz, ledger);
+                                real *uy, real *uz, WarmP w, double *ledger, hipStream_t s) {
+    k_absorb_finish<<<blocks(g.nn), BS, 0, s>>>(g, mass, macc, n, ux, uy, uz, w, ledger);
 }
 void launch_spawn_nodes(const GridP &g, const SpecP &sp, const uint8_t *sw, real *n, real *ux,
-                        real *uy, real *uz, real *const f[9], real wmin, int m, uint64_t seed,
+                        real *uy, real *uz, WarmP w, real *const f[9], real wmin, int m, uint64_t seed,
                         int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
-                        unsigned *wmax_bits, unsigned *umax2, hipStream_t s) {
-    k_spawn<<<blocks(g.nn), BS, 0, s>>>(g, sp, sw, n, ux, uy, uz, f[HK_JX], f[HK_JY], f[HK_JZ], wmin,
-                                        m, seed, step, inbox, inbox_n, inbox_cap, deferred, wmax_bits, umax2);
+                        unsigned *wmax_bits, unsigned *umax2, double *ledger, hipStream_t s) {
+    k_spawn<<<blocks(g.nn), BS, 0, s>>>(g, sp, sw, n, ux, uy, uz, w, f[HK_JX], f[HK_JY], f[HK_JZ], wmin,
+                                        m, seed, step, inbox, inbox_n, inbox_cap, deferred, wmax_bits, umax2,
+                                        ledger);
 }

@@ -47,7 +47,7 @@ class SpeciesDesc(C.Structure):
                 ("z_max", C.c_int32), ("target", C.c_int32), ("qed", C.c_int32),
                 ("pad", C.c_int32), ("charge", C.c_double), ("mass", C.c_double),
                 ("n0", C.c_double), ("x0", C.c_double), ("length", C.c_double),
-                ("u_th", C.c_double), ("ip_ev", C.c_double * MAX_LEVELS)]
+                ("u_th", C.c_double), ("ip_ev", C.c_double * MAX_LEVELS), ("gamma_ad", C.c_double)]
 
 
 class LaserDesc(C.Structure):
@@ -77,7 +77,7 @@ class Diag(C.Structure):
                 ("charge_total", C.c_double), ("gauss_max", C.c_double), ("gauss_l2", C.c_double),
                 ("conv_loss", C.c_double), ("ion_energy", C.c_double),
                 ("photon_energy", C.c_double), ("kinetic_fraction", C.c_double),
-                ("fallback_fraction", C.c_double)]
+                ("fallback_fraction", C.c_double), ("fluid_th", C.c_double * MAX_SPECIES)]
 
 
 class Particles(C.Structure):
@@ -105,7 +105,7 @@ class SpTrainDesc(C.Structure):
 ABI_SYMBOLS = ["hk_create", "hk_destroy", "hk_step", "hk_switch_map", "hk_set_switch_map",
                "hk_set_switch_mode", "hk_diagnostics", "hk_get_field", "hk_set_field",
                "hk_get_rho", "hk_get_divE", "hk_particle_count", "hk_get_particles",
-               "hk_set_particles", "hk_get_fluid", "hk_set_fluid", "hk_enable_timing",
+               "hk_set_particles", "hk_get_fluid", "hk_set_fluid", "hk_get_fluid_p", "hk_set_fluid_p", "hk_enable_timing",
                "hk_timers", "hk_qed_tables", "hk_cnn_nparams", "hk_cnn_create", "hk_cnn_destroy",
                "hk_cnn_set_params", "hk_cnn_get_params", "hk_cnn_set_norm", "hk_cnn_forward",
                "hk_cnn_loss_grad", "hk_cnn_train_step", "hk_cnn_last_error", "hk_set_cnn", "hk_node_inputs", "hk_node_state",
@@ -153,6 +153,8 @@ def load(prec: str = "f32"):
     L.hk_set_particles.argtypes = [vp, C.c_int, P(Particles)]
     L.hk_get_fluid.argtypes = [vp, C.c_int, vp, vp, C.c_size_t]
     L.hk_set_fluid.argtypes = [vp, C.c_int, vp, vp, C.c_size_t]
+    L.hk_get_fluid_p.argtypes = [vp, C.c_int, vp, C.c_size_t]
+    L.hk_set_fluid_p.argtypes = [vp, C.c_int, vp, C.c_size_t]
     L.hk_enable_timing.argtypes = [vp, C.c_int]
     L.hk_timers.argtypes = [vp, vp, C.c_int]
     L.hk_qed_tables.argtypes = [vp, vp, vp, vp]
@@ -231,6 +233,7 @@ def descriptors(cfg: dict):
         sp.x0 = s.get("x0", 0.0)
         sp.length = s.get("length", 1.0)
         sp.u_th = s.get("u_th", 0.0)
+        sp.gamma_ad = s.get("gamma_ad", 0.0)
         for k, v in enumerate(s.get("ip_ev", [])):
             sp.ip_ev[k] = v
     las = cfg.get("laser", {})
@@ -375,6 +378,15 @@ class Sim:
         n = np.ascontiguousarray(n, np.float64).reshape(self.shape)
         u = np.ascontiguousarray(u, np.float64).reshape(self.shape + (3,))
         self._check(self.lib.hk_set_fluid(self.h, sp, _ptr(n), _ptr(u), self.nodes))
+
+    def get_pressure(self, sp: int) -> np.ndarray:
+        p = np.empty(self.shape)
+        self._check(self.lib.hk_get_fluid_p(self.h, sp, _ptr(p), self.nodes))
+        return p
+
+    def set_pressure(self, sp: int, p):
+        p = np.ascontiguousarray(p, np.float64).reshape(self.shape)
+        self._check(self.lib.hk_set_fluid_p(self.h, sp, _ptr(p), self.nodes))
 
     def get_switch(self) -> np.ndarray:
         out = np.empty(self.shape, np.uint8)

@@ -58,9 +58,9 @@ def test_host_only_calls(prec, size):
 def test_config_marshalling_matches_header_layout():
     # the binding's structs must have the sizes the header implies
     assert ctypes.sizeof(hk.GridDesc) == 4 * 4 + 4 * 8
-    assert ctypes.sizeof(hk.SpeciesDesc) == 10 * 4 + 6 * 8 + 8 * 8
+    assert ctypes.sizeof(hk.SpeciesDesc) == 10 * 4 + 6 * 8 + 8 * 8 + 8        # ... ip_ev[8], gamma_ad
     assert ctypes.sizeof(hk.LaserDesc) == 4 * 4 + 5 * 8
-    assert ctypes.sizeof(hk.Diag) == 8 + 8 + 2 * 8 + 4 * 6 * 8 + 8 * 8
+    assert ctypes.sizeof(hk.Diag) == 8 + 8 + 2 * 8 + 4 * 6 * 8 + 8 * 8 + 6 * 8  # ... fluid_th[6]
 
 
 def test_qed_tables_match_oracle(oracle_mod):
