@@ -132,3 +132,46 @@ def test_threshold_hybrid_warm(hk, oracle_mod, prec):
     print("n %.1e u %.1e p %.1e" % (en, eu, ep), vec)
     assert max(vec.values()) <= (1e-3 if prec == "f32" else 1e-10)
     assert ep <= (1e-3 if prec == "f32" else 1e-10)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_warm_species_foil(hk, oracle_mod, prec):
+    # electron, ion and positron fluids, all warm, in a thin dense foil under
+    # the a0 = 200 pulse: absorption of the initial particles, the fluids'
+    # evolution, spawning as the switch turns the foil kinetic, then photon
+    # emission by the spawned leptons
+    from tests.test_gpu_qed import _foil
+    cfg = _foil("threshold")
+    for sp in cfg["species"][:3]:
+        sp["gamma_ad"] = GA
+        sp["fluid"] = True
+    cfg["species"][2].update(profile="foil", n0=1.0, x0=0.6, length=0.4, u_th=1e-3)
+    print("case:", cfg["name"], "warm electron, ion and positron fluids", prec, flush=True)
+    g, o = hk.Sim(cfg, precision=prec), oracle_mod.Oracle(cfg)
+    for n in range(0, 160, 40):
+        g.step(40); o.step(40)
+        dg, do = g.diagnostics(), o.diagnostics()
+        counts = [(g.count(s), o.count(s)) for s in range(4)]
+        errs = []
+        for s in range(3):
+            ng, ug = g.get_fluid(s)
+            no, uo = o.get_fluid(s)
+            errs.append((rel_l2(ng, no), rel_l2(ug, uo), rel_l2(g.get_pressure(s), o.get_pressure(s))))
+        vec = {f: rel_l2(np.stack([g.get_field(f + c) for c in "xyz"]),
+                         np.stack([o.get_field(f + c) for c in "xyz"])) for f in "eb"}
+        print("step %d counts %s kinetic %.3f / %.3f" % (n + 40, counts, g.get_switch().mean(),
+                                                         o.get_switch().mean()),
+              "fluids (n, u, p) %s" % ["%.1e %.1e %.1e" % e for e in errs],
+              "heat %s / %s" % (["%.6e" % x for x in dg["fluid_th"][:3]], ["%.6e" % x for x in do["fluid_th"][:3]]),
+              "E %.1e B %.1e photons %.3e / %.3e" % (vec["e"], vec["b"], dg["photon_energy"], do["photon_energy"]))
+        if prec == "f64":
+            assert all(a == b for a, b in counts)
+            assert max(max(e) for e in errs) <= 1e-9 and max(vec.values()) <= 1e-9
+            for s in range(3):
+                assert dg["fluid_th"][s] == pytest.approx(do["fluid_th"][s], rel=1e-9, abs=1e-300)
+        else:
+            assert max(vec.values()) <= 1e-3
+            for s in range(3):
+                assert dg["fluid_mass"][s] == pytest.approx(do["fluid_mass"][s], rel=1e-3, abs=1e-12)
+    assert all(do["fluid_mass"][s] > 0 for s in range(3))
+    assert do["photon_energy"] > 0
