@@ -293,6 +293,44 @@ def laser_search(pop=8, gens=3, steps=120):
             "rel_error": r["rel_error"], "workload": "plain_hybrid_32x16x16, DE pop %d, %d generations" % (pop, gens)}
 
 
+def warm_fluid(steps=200, warmup=20, nx=256, ny=128, nz=128):
+    """The fluid phase of the step on an all-fluid plasma (the underdense case
+    at 256 x 128 x 128 cells, electrons at u_th 0.05 absorbed into the node
+    fluid at the first step, then laser and fluid only), warm (adiabatic,
+    gamma 5/3) and cold.  Time: the library's HIP events around the fluid
+    passes on its stream, over `steps` steps after `warmup`.  Algorithmic
+    bytes per node and step: read n, u, E, B, J and write n, u, J (20 values),
+    plus read and write S for the warm fluid (22), in the build's real type."""
+    from paper_2510_11174_amd import configs, hk
+    out = {}
+    nodes = (nx + 1) * ny * nz
+    for name, ga in (("warm", 5.0 / 3.0), ("cold", 0.0)):
+        cfg = configs.plain_hybrid(nx, ny, nz, mode="all_fluid")
+        cfg["species"][0]["u_th"] = 0.05
+        cfg["species"][0]["gamma_ad"] = ga
+        sim = hk.Sim(cfg, precision="f32")
+        sim.step(1 + warmup)
+        sim.enable_timing(True)
+        t0 = time.perf_counter()
+        sim.step(steps)
+        import torch
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        tm = sim.timers()
+        d = sim.diagnostics()
+        sim.close()
+        ms = tm["fluid_ms"] / steps
+        alg = (22 if ga > 0 else 20) * 4 * nodes
+        gbs = alg / (ms * 1e-3) / 1e9
+        out[name] = {"ms_fluid_per_step": round(ms, 4), "alg_bytes_per_step": alg,
+                     "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "steps_per_s": round(steps / sec, 1), "fluid_heat": d["fluid_th"][0]}
+    w = out["warm"]
+    return {"bound": "hbm", "achieved": w["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": w["frac"],
+            "traffic": None, "kernel": "k_fluid_lorentz + k_fluid_update (warm)", "nodes": nodes,
+            "workload": "plain plasma %dx%dx%d, all fluid, u_th 0.05" % (nx, ny, nz), **{k: v for k, v in out.items()}}
+
+
 def field_l2(x, y):
     import numpy as np
     num = math.sqrt(sum(float(np.sum((x[c] - y[c]) ** 2)) for c in x))
@@ -311,6 +349,8 @@ def main():
                     help="comma list of switch modes to run (profiling runs may pick one)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--warm-fluid-only", action="store_true",
+                    help="only measure the fluid phase (warm and cold) on the all-fluid 256x128x128 plasma")
     ap.add_argument("--networks-only", action="store_true",
                     help="only measure the next-state surrogate (64 patches of 16^3) and SwitchNet (the "
                          "ionizing-helium node grid) and print their JSON")
@@ -329,6 +369,9 @@ def main():
         return
     if args.calibrate_copy:
         copy_calibration()
+        return
+    if args.warm_fluid_only:
+        print(json.dumps({"roofline_warm_fluid": warm_fluid()}))
         return
 
     W, K = args.warmup, args.steps
@@ -408,6 +451,7 @@ def main():
     out["roofline_cnn_switch"] = cnn_inference()
     out["roofline_state_predictor"] = sp_surrogate()
     out["roofline_switchnet"] = swn_inference()
+    out["roofline_warm_fluid"] = warm_fluid()
     out["laser_search"] = laser_search()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

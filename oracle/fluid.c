@@ -23,7 +23,11 @@
  *      where n = 0), central differences (one-sided at the open x walls); the
  *      pressure force is taken non-relativistically (modest temperatures);
  *  3b. entropy flux H = F K_donor, K = S / n;
- *  4b. S^{n+1} = S - dt div H.
+ *  4b. S^{n+1} = max(S - dt div H, 0).  The face velocity is the mean of two
+ *      nodes, so a node can lose more than it holds in one step (its density
+ *      may then go negative, which every reader of n treats as no fluid);
+ *      the entropy density is kept non-negative so that p and the
+ *      temperature p / n never turn negative where n stays positive.
  */
 #include "or_internal.h"
 
@@ -153,7 +157,7 @@ void or_fluid_phase(or_sim *s) {
                     }
                     double nv = n[c] - g->dt * dn;
                     nnew[c] = nv;
-                    if (S) Snew[c] = S[c] - g->dt * ds;
+                    if (S) Snew[c] = fmax(S[c] - g->dt * ds, 0.0);
                     for (int m = 0; m < 3; ++m) {
                         double mom = n[c] * us[3 * c + m] - g->dt * dm[m];
                         s->fu[isp][m][c] = nv > floor_n ? mom / nv : 0.0;

@@ -34,7 +34,10 @@
  *  fluid, so both conversions keep div E - rho unchanged.
  *  Warm fluid (gamma_ad > 0): the kinetic energy an absorption loses (the
  *  particles' spread about the merged flow) heats the node, p += (gamma_ad -
- *  1) dE / dV, instead of going to the ledger; a spawned particle gets the
+ *  1) dE / dV, instead of going to the ledger (unless the merged mass or
+ *  pressure is not positive, which a node whose fluid density had gone
+ *  negative can give: then S = 0 and the ledger takes that heat and the
+ *  node's previous thermal energy); a spawned particle gets the
  *  fluid momentum plus a Gaussian spread sqrt(T / m) per component, T = p / n
  *  (Box-Muller on Philox draws, tag 13), and the ledger takes the difference
  *  between the fluid's kinetic plus thermal energy and the sample's.
@@ -234,10 +237,18 @@ void or_reconcile(or_sim *s) {
             double gn = sqrt(1.0 + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
             double loss = m0 * sp->mass * (g0 - 1.0) - mt * sp->mass * (gn - 1.0);
             if (S) {
-                /* the kinetic energy the merge loses becomes heat of the node */
+                /* the kinetic energy the merge loses becomes heat of the node;
+                 * a node left without positive mass or pressure (its fluid
+                 * density had gone negative) keeps no entropy, and that heat
+                 * and its previous thermal energy go to the ledger */
                 double pold = n[c] > 0.0 ? S[c] * pow(n[c], ga - 1.0) : 0.0;
                 double pnew = pold + (ga - 1.0) * (KEa[c] + loss) / dv;
-                S[c] = pnew * pow(mt / dv, 1.0 - ga);
+                if (mt > 0.0 && pnew >= 0.0) {
+                    S[c] = pnew * pow(mt / dv, 1.0 - ga);
+                } else {
+                    S[c] = 0.0;
+                    s->conv_loss += KEa[c] + loss + pold * dv / (ga - 1.0);
+                }
             } else s->conv_loss += loss;
             n[c] = mt / dv;
             for (int d = 0; d < 3; ++d) s->fu[isp][d][c] = un[d];

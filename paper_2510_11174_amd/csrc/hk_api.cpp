@@ -57,6 +57,7 @@ struct DevSpecies {
     int *g_capmax = nullptr;      // device {INT_MAX}
     real *fn = nullptr, *fu[3] = {nullptr, nullptr, nullptr};  // fluid density and momentum
     real *fs = nullptr;           // warm fluid: entropy density n K, K = p / n^gamma_ad
+    real *fn2 = nullptr, *fs2 = nullptr;   // the fluid pass writes n and S here, then swaps
     IonP *ion = nullptr;          // device rate constants
     long long reserve_hint = 0;   // expected peak count (ionization targets)
     unsigned *umax2 = nullptr;    // device [ntiles]: bound on |u|^2 (float bits) since the
@@ -884,20 +885,25 @@ int one_step(hk_sim *S) {
     // 6. conversion; 7. fields (likewise before the second status wait)
     int rc = merge_launch(S);
     if (rc) return rc;
+    time_mark(S, 5);
     if (hybrid) {
         for (int isp = 0; isp < S->nsp; ++isp) {
             DevSpecies &D = S->sp[isp];
-            if (D.fn) launch_fluid(g, specp(D), D.fn, D.fu[0], D.fu[1], D.fu[2], WarmP{D.fs, D.d.gamma_ad}, S->f,
-                                   S->fluid_scratch, (real)S->run.n_floor, s);
+            if (!D.fn) continue;
+            launch_fluid(g, specp(D), D.fn, D.fu[0], D.fu[1], D.fu[2], WarmP{D.fs, D.d.gamma_ad}, S->f,
+                         S->fluid_scratch, D.fn2, D.fs2, (real)S->run.n_floor, s);
+            std::swap(D.fn, D.fn2);
+            if (D.fs) std::swap(D.fs, D.fs2);
         }
         time_mark(S, 2);
         rc = merge_finish(S);
         if (rc) return rc;
         time_mark(S, 5);
         reconcile(S);
+        time_mark(S, 3);
         rc = merge_launch(S);
         if (rc) return rc;
-        time_mark(S, 3);
+        time_mark(S, 5);
     }
     launch_yee_b_half(g, S->f, s);
     launch_yee_e_full(g, S->f, S->mur_old, s);
@@ -919,7 +925,7 @@ int ensure_fluid(hk_sim *S) {
         S->macc = (double *)dalloc(S, sizeof(double) * 5 * (size_t)g.nn);
         S->hot = (uint8_t *)dalloc(S, (size_t)g.nn);
         S->notcold = (uint8_t *)dalloc(S, (size_t)g.nn);
-        S->fluid_scratch = (real *)dalloc(S, sizeof(real) * 8 * (size_t)g.nn);
+        S->fluid_scratch = (real *)dalloc(S, sizeof(real) * 7 * (size_t)g.nn);
         if (!S->mom || !S->macc || !S->hot || !S->notcold || !S->fluid_scratch)
             return fail(S, HK_ENOMEM, "switch arrays");
     }
@@ -927,9 +933,13 @@ int ensure_fluid(hk_sim *S) {
         DevSpecies &D = S->sp[isp];
         if (!D.d.fluid || D.fn) continue;
         D.fn = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
+        D.fn2 = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
         for (int d = 0; d < 3; ++d) D.fu[d] = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
-        if (D.d.gamma_ad > 0.0) D.fs = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
-        if (!D.fn || !D.fu[0] || !D.fu[1] || !D.fu[2] || (D.d.gamma_ad > 0.0 && !D.fs))
+        if (D.d.gamma_ad > 0.0) {
+            D.fs = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
+            D.fs2 = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
+        }
+        if (!D.fn || !D.fn2 || !D.fu[0] || !D.fu[1] || !D.fu[2] || (D.d.gamma_ad > 0.0 && (!D.fs || !D.fs2)))
             return fail(S, HK_ENOMEM, "fluid arrays");
         int rc = ensure_inbox(S, isp, inbox_need(S, isp));
         if (rc) return rc;

@@ -220,8 +220,8 @@ struct WarmP {
     real *S;
     double ga;   // adiabatic index
 };
-void launch_fluid(const GridP &g, const SpecP &sp, real *n, real *ux, real *uy, real *uz, WarmP w,
-                  real *const f[9], real *scratch, real n_floor, hipStream_t s);
+void launch_fluid(const GridP &g, const SpecP &sp, const real *n, real *ux, real *uy, real *uz, WarmP w,
+                  real *const f[9], real *scratch, real *nout, real *Sout, real n_floor, hipStream_t s);
 void launch_fluid_heat(const GridP &g, const real *n, WarmP w, double *out, hipStream_t s);
 void launch_fluid_rho(const GridP &g, const SpecP &sp, const real *n, double *rho,
                       hipStream_t s);

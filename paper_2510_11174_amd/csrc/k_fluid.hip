@@ -7,17 +7,19 @@
 // bulk plasma; the adiabatic energy equation is the advection of S).
 //
 // Scheme (per step, two passes, each one thread per node, x fastest):
-//   1. us = Boris(u; E, B interpolated to the node), v = us / gamma(us),
-//      stored only where n > 0 (nothing else reads them)
+//   1. us = Boris(u; E, B interpolated to the node); a warm species then
+//      takes the pressure force, us -= dt grad p / (m n) at nodes above the
+//      density floor (p = S n^(ga-1), zero where n = 0; central differences,
+//      one-sided at the open x walls; non-relativistic); v = us / gamma(us);
+//      both stored only where n > 0 (nothing else reads them)
 //   2. on the face between node c and its +d neighbour: face velocity = mean
 //      of the two nodes (or that of the only side above the density floor),
-//      mass flux F = v_f n_donor, momentum flux G = F us_donor; each node
-//      evaluates its six faces itself (a face shared by two nodes gives both
-//      the same bits), then n <- n - dt div F, n u <- n us - dt div G, J += q F
-// Warm fluid, between 1 and 2: us -= dt grad p / (m n) at nodes above the
-// density floor (p = S n^(ga-1), zero where n = 0; central differences,
-// one-sided at the open x walls; non-relativistic pressure force), v again
-// us / gamma; and S <- S - dt div(F K_donor) with the same face fluxes F.
+//      mass flux F = v_f n_donor, momentum flux G = F us_donor, entropy flux
+//      H = F K_donor (warm, K = S / n); each node evaluates its six faces
+//      itself (a face shared by two nodes gives both the same bits), then
+//      n <- n - dt div F, n u <- n us - dt div G, S <- max(S - dt div H, 0),
+//      J += q F; the new n and S go to the species' second buffers, which
+//      the host swaps with the first
 // The fluid current obeys the same discrete continuity equation as the
 // Esirkepov particle current, so div E - rho is unchanged by the fluid.
 // HBM-bound; where there is no fluid only the density is read.
@@ -28,40 +30,89 @@ namespace {
 constexpr int BS = 256;
 
 
-// field component at node (i, j, k): trilinear at offset 0, i.e. the node
-// value for node-type axes and the mean of the two neighbours for half axes
-__device__ inline real node_val(const GridP &g, const real *F, int i, int j, int k, int hx, int hy,
-                                int hz) {
-    const int per = g.bcx == HK_BC_PERIODIC;
-    int i0 = hx ? i - 1 : i, j0 = hy ? j - 1 : j, k0 = hz ? k - 1 : k;
+// Linear indices of a node's neighbours (node counts stay below 2^31):
+// y and z periodic, x periodic or open (no neighbour beyond an open wall).
+struct Nbr {
+    int xm, xp, ym, yp, zm, zp;
+    bool hasxm, hasxp;
+};
+
+__device__ inline Nbr neighbours(const GridP &g, int c, int i, int j, int k) {
+    Nbr b;
+    const int sxy = g.sx * g.ny;
+    if (g.bcx == HK_BC_PERIODIC) {
+        b.xm = i == 0 ? c + g.nx - 1 : c - 1;
+        b.xp = i + 1 == g.nx ? c - i : c + 1;
+        b.hasxm = b.hasxp = true;
+    } else {
+        b.xm = c - 1;
+        b.xp = c + 1;
+        b.hasxm = i != 0;
+        b.hasxp = i != g.nx;
+    }
+    b.ym = j == 0 ? c + (g.ny - 1) * g.sx : c - g.sx;
+    b.yp = j + 1 == g.ny ? c - j * g.sx : c + g.sx;
+    b.zm = k == 0 ? c + (g.nz - 1) * sxy : c - sxy;
+    b.zp = k + 1 == g.nz ? c - k * sxy : c + sxy;
+    return b;
+}
+
+// field component at a node: trilinear at offset 0, i.e. the node value for
+// node-type axes and the mean of the two neighbours for half axes.  xs: the
+// two x samples of a half axis (wrapped, or clamped to the last cell at an
+// open wall); oy, oz: row offsets of the samples j - 1, j and k - 1, k.
+__device__ inline real node_val(const real *__restrict__ F, const int xs[2], const int oy[2], const int oz[2],
+                                int i, int hx, int hy, int hz) {
     real acc = 0;
     for (int c = 0; c < (hz ? 2 : 1); ++c)
         for (int b = 0; b < (hy ? 2 : 1); ++b)
             for (int a = 0; a < (hx ? 2 : 1); ++a) {
-                int ii = i0 + a;
-                if (per) ii = wrapi(ii, g.nx);
-                else if (hx) ii = ii < 0 ? 0 : (ii > g.nx - 1 ? g.nx - 1 : ii);
-                int jj = wrapi(j0 + b, g.ny), kk = wrapi(k0 + c, g.nz);
+                const int ii = hx ? xs[a] : i;
+                const int jo = hy ? oy[b] : oy[1], ko = hz ? oz[c] : oz[1];
                 real wgt = (hx ? (real)0.5 : (real)1) * (hy ? (real)0.5 : (real)1) * (hz ? (real)0.5 : (real)1);
-                acc += wgt * F[gidx(g, ii, jj, kk)];
+                acc += wgt * F[ii + jo + ko];
             }
     return acc;
 }
 
+// warm fluid: node pressure p = S n^(ga-1), zero where n = 0
 __global__ void __launch_bounds__(BS)
-k_fluid_lorentz(GridP g, real qm, const real *__restrict__ n, const real *__restrict__ ux,
+k_fluid_p(GridP g, real gm1, const real *__restrict__ n, const real *__restrict__ S, real *__restrict__ P) {
+    long long c = (long long)blockIdx.x * BS + threadIdx.x;
+    if (c >= g.nn) return;
+    const real nc = n[c];
+    P[c] = nc > (real)0 ? S[c] * pow(nc, gm1) : (real)0;
+}
+
+__global__ void __launch_bounds__(BS)
+k_fluid_lorentz(GridP g, real qm, real mass, real n_floor, const real *__restrict__ n,
+                const real *__restrict__ P, const real *__restrict__ ux,
                 const real *__restrict__ uy, const real *__restrict__ uz, const real *__restrict__ Ex,
                 const real *__restrict__ Ey, const real *__restrict__ Ez, const real *__restrict__ Bx,
                 const real *__restrict__ By, const real *__restrict__ Bz, real *__restrict__ sc) {
-    long long c = (long long)blockIdx.x * BS + threadIdx.x;
-    if (c >= g.nn) return;
+    long long cl = (long long)blockIdx.x * BS + threadIdx.x;
+    if (cl >= g.nn) return;
     int i, j, k;
-    node_ijk(g, c, i, j, k);
-    const int nxn = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
-    if (i >= nxn || !(n[c] > (real)0)) return;
-    real ex = node_val(g, Ex, i, j, k, 1, 0, 0), ey = node_val(g, Ey, i, j, k, 0, 1, 0);
-    real ez = node_val(g, Ez, i, j, k, 0, 0, 1), bx = node_val(g, Bx, i, j, k, 0, 1, 1);
-    real by = node_val(g, By, i, j, k, 1, 0, 1), bz = node_val(g, Bz, i, j, k, 1, 1, 0);
+    node_ijk(g, cl, i, j, k);
+    const int per = g.bcx == HK_BC_PERIODIC;
+    const int nxn = per ? g.nx : g.nx + 1;
+    const int c = (int)cl;
+    const real nc = n[c];
+    if (i >= nxn || !(nc > (real)0)) return;
+    const int sxy = g.sx * g.ny;
+    int xs[2];
+    if (per) {
+        xs[0] = i == 0 ? g.nx - 1 : i - 1;
+        xs[1] = i;
+    } else {
+        xs[0] = i - 1 < 0 ? 0 : (i - 1 > g.nx - 1 ? g.nx - 1 : i - 1);
+        xs[1] = i > g.nx - 1 ? g.nx - 1 : i;
+    }
+    const int oy[2] = {(j == 0 ? g.ny - 1 : j - 1) * g.sx, j * g.sx};
+    const int oz[2] = {(k == 0 ? g.nz - 1 : k - 1) * sxy, k * sxy};
+    real ex = node_val(Ex, xs, oy, oz, i, 1, 0, 0), ey = node_val(Ey, xs, oy, oz, i, 0, 1, 0);
+    real ez = node_val(Ez, xs, oy, oz, i, 0, 0, 1), bx = node_val(Bx, xs, oy, oz, i, 0, 1, 1);
+    real by = node_val(By, xs, oy, oz, i, 1, 0, 1), bz = node_val(Bz, xs, oy, oz, i, 1, 1, 0);
     const real h = (real)0.5 * qm * g.dt;
     real umx = ux[c] + h * ex, umy = uy[c] + h * ey, umz = uz[c] + h * ez;
     real gm = sqrt((real)1 + umx * umx + umy * umy + umz * umz);
@@ -74,6 +125,18 @@ k_fluid_lorentz(GridP g, real qm, const real *__restrict__ n, const real *__rest
     us[0] = umx + (upy * sz - upz * sy) + h * ex;
     us[1] = umy + (upz * sx - upx * sz) + h * ey;
     us[2] = umz + (upx * sy - upy * sx) + h * ez;
+    if (P && nc > n_floor) {
+        // pressure force: central differences, one-sided at the open x walls
+        const Nbr b = neighbours(g, c, i, j, k);
+        real grad[3];
+        if (per) grad[0] = (P[b.xp] - P[b.xm]) / (2 * g.dx);
+        else if (i == 0) grad[0] = (P[b.xp] - P[c]) / g.dx;
+        else if (i == g.nx) grad[0] = (P[c] - P[b.xm]) / g.dx;
+        else grad[0] = (P[b.xp] - P[b.xm]) / (2 * g.dx);
+        grad[1] = (P[b.yp] - P[b.ym]) / (2 * g.dy);
+        grad[2] = (P[b.zp] - P[b.zm]) / (2 * g.dz);
+        for (int d = 0; d < 3; ++d) us[d] = us[d] - g.dt * grad[d] / (mass * nc);
+    }
     real gam = sqrt((real)1 + us[0] * us[0] + us[1] * us[1] + us[2] * us[2]);
     const long long nn = g.nn;
     for (int d = 0; d < 3; ++d) {
@@ -82,73 +145,120 @@ k_fluid_lorentz(GridP g, real qm, const real *__restrict__ n, const real *__rest
     }
 }
 
-// Mass and momentum flux on the +d face of node (i, j, k); false where the
-// face does not exist (beyond the open x wall).  us and v are read only at
-// nodes with n > 0, the only ones where they were written.
-__device__ inline bool face_flux(const GridP &g, real n_floor, const real *__restrict__ n,
-                                 const real *__restrict__ sc, int i, int j, int k, int d, real &F,
-                                 real G[3], long long *donor = nullptr) {
-    const int per = g.bcx == HK_BC_PERIODIC;
-    F = 0; G[0] = G[1] = G[2] = 0;
-    if (donor) *donor = -1;
-    if (d == 0 && !per && i == g.nx) return false;
-    int ii = i, jj = j, kk = k;
-    if (d == 0) ii = per ? (i + 1 == g.nx ? 0 : i + 1) : i + 1;
-    else if (d == 1) jj = j + 1 == g.ny ? 0 : j + 1;
-    else kk = k + 1 == g.nz ? 0 : k + 1;
-    const long long c = gidx(g, i, j, k), r = gidx(g, ii, jj, kk);
-    const real nl = n[c], nr = n[r];
-    const bool lok = nl > n_floor && nl > (real)0, rok = nr > n_floor && nr > (real)0;
-    if (!lok && !rok) return true;
-    const long long nn = g.nn;
-    real vf;
-    if (!lok) vf = sc[(3 + d) * nn + r];
-    else if (!rok) vf = sc[(3 + d) * nn + c];
-    else vf = (real)0.5 * (sc[(3 + d) * nn + c] + sc[(3 + d) * nn + r]);
-    const long long don = vf > (real)0 ? c : r;
-    const real nd = vf > (real)0 ? nl : nr;
+// One side of a face: density, its velocity component normal to the face,
+// its momentum, and whether it is above the density floor.
+struct Side {
+    real n, v, us[3];
+    bool ok;
+};
+
+// Mass and momentum flux through the face between sides l and r (r on the
+// +d side), from values already loaded; don receives the donor node (-1
+// where neither side is above the density floor) and nd its density.  us
+// and v are meaningful only at nodes with n > 0, the only ones where they
+// were written; the selects below never use the others.
+__device__ inline void face_flux(const Side &l, const Side &r, int lo, int hi, real &F, real G[3], int &don,
+                                 real &nd) {
+    const real vf = !l.ok ? r.v : (!r.ok ? l.v : (real)0.5 * (l.v + r.v));
+    const bool pos = vf > (real)0;
+    nd = pos ? l.n : r.n;
     F = vf * nd;
-    if (donor) *donor = don;
-    if (nd > (real)0)
-        for (int m = 0; m < 3; ++m) G[m] = F * sc[m * nn + don];
-    return true;
+    for (int m = 0; m < 3; ++m) G[m] = nd > (real)0 ? F * (pos ? l.us[m] : r.us[m]) : (real)0;
+    don = pos ? lo : hi;
+    if (!l.ok && !r.ok) {
+        F = 0; G[0] = G[1] = G[2] = 0;
+        don = -1; nd = 0;
+    }
 }
 
 __global__ void __launch_bounds__(BS)
-k_fluid_update(GridP g, real q, real n_floor, real *__restrict__ n, real *__restrict__ ux,
+k_fluid_update(GridP g, real q, real n_floor, const real *__restrict__ n, real *__restrict__ ux,
                real *__restrict__ uy, real *__restrict__ uz, const real *__restrict__ sc,
                real *__restrict__ Jx, real *__restrict__ Jy, real *__restrict__ Jz,
-               real *__restrict__ nout) {
-    long long c = (long long)blockIdx.x * BS + threadIdx.x;
-    if (c >= g.nn) return;
+               real *__restrict__ nout, const real *__restrict__ S, real *__restrict__ Sout) {
+    long long cl = (long long)blockIdx.x * BS + threadIdx.x;
+    if (cl >= g.nn) return;
     int i, j, k;
-    node_ijk(g, c, i, j, k);
+    node_ijk(g, cl, i, j, k);
     const int per = g.bcx == HK_BC_PERIODIC;
     const int nxn = per ? g.nx : g.nx + 1;
+    const int c = (int)cl;
     const real n0 = n[c];
-    if (i >= nxn) { nout[c] = n0; return; }
+    if (i >= nxn) {
+        nout[c] = n0;
+        if (S) Sout[c] = S[c];
+        return;
+    }
     const long long nn = g.nn;
+    const real *const us[3] = {sc, sc + nn, sc + 2 * nn};
     const real dxs[3] = {g.dx, g.dy, g.dz};
-    real dn = 0, dm[3] = {0, 0, 0}, fplus[3];
+    const Nbr b = neighbours(g, c, i, j, k);
+    const int pl[3] = {b.xp, b.yp, b.zp}, mi[3] = {b.xm, b.ym, b.zm};
+    const bool hasp[3] = {b.hasxp, true, true}, hasm[3] = {b.hasxm, true, true};
+    auto fok = [&](real v) { return v > n_floor && v > (real)0; };
+    // the densities first: a node whose stencil holds no fluid above the
+    // floor has no face flux, keeps its density and entropy and gets u = 0
+    real np[3], nm[3];
+    bool any = fok(n0);
     for (int d = 0; d < 3; ++d) {
-        real fp, gp[3], fm = 0, gm[3] = {0, 0, 0};
-        face_flux(g, n_floor, n, sc, i, j, k, d, fp, gp);
+        np[d] = hasp[d] ? n[pl[d]] : (real)0;
+        nm[d] = hasm[d] ? n[mi[d]] : (real)0;
+        any = any || (hasp[d] && fok(np[d])) || (hasm[d] && fok(nm[d]));
+    }
+    if (!any) {
+        nout[c] = n0;
+        if (S) Sout[c] = S[c];
+        ux[c] = 0; uy[c] = 0; uz[c] = 0;
+        return;
+    }
+    // every other value of the stencil, loaded before any is used
+    Side C, P[3], M[3];
+    C.n = n0; C.ok = fok(n0);
+    for (int m = 0; m < 3; ++m) C.us[m] = us[m][c];
+    real vc[3], Sc = 0, Sp[3] = {0, 0, 0}, Sm[3] = {0, 0, 0};
+    for (int d = 0; d < 3; ++d) {
+        const real *vd = sc + (3 + d) * nn;
+        vc[d] = vd[c];
+        const int pp = hasp[d] ? pl[d] : c, mm = hasm[d] ? mi[d] : c;
+        P[d].n = np[d]; P[d].ok = hasp[d] && fok(np[d]); P[d].v = vd[pp];
+        M[d].n = nm[d]; M[d].ok = hasm[d] && fok(nm[d]); M[d].v = vd[mm];
+        for (int m = 0; m < 3; ++m) {
+            P[d].us[m] = us[m][pp];
+            M[d].us[m] = us[m][mm];
+        }
+        if (S) {
+            Sp[d] = S[pp];
+            Sm[d] = S[mm];
+        }
+    }
+    if (S) Sc = S[c];
+    real dn = 0, dm[3] = {0, 0, 0}, fplus[3], ds = 0;
+    for (int d = 0; d < 3; ++d) {
+        C.v = vc[d];
+        real fp = 0, gp[3] = {0, 0, 0}, fm = 0, gm[3] = {0, 0, 0}, ndp = 0, ndm = 0;
+        int dp = -1, dmi = -1;
+        if (hasp[d]) face_flux(C, P[d], c, pl[d], fp, gp, dp, ndp);
+        if (hasm[d]) face_flux(M[d], C, mi[d], c, fm, gm, dmi, ndm);
         fplus[d] = fp;
-        int ii = i, jj = j, kk = k;
-        bool has_minus = true;
-        if (d == 0) {
-            if (!per && i == 0) has_minus = false;
-            ii = per ? (i == 0 ? g.nx - 1 : i - 1) : i - 1;
-        } else if (d == 1) jj = j == 0 ? g.ny - 1 : j - 1;
-        else kk = k == 0 ? g.nz - 1 : k - 1;
-        if (has_minus) face_flux(g, n_floor, n, sc, ii, jj, kk, d, fm, gm);
         dn += (fp - fm) / dxs[d];
         for (int m = 0; m < 3; ++m) dm[m] += (gp[m] - gm[m]) / dxs[d];
+        if (S) {
+            // entropy flux F K_donor, K = S / n at the donor
+            const real Sdp = dp == c ? Sc : Sp[d], Sdm = dmi == c ? Sc : Sm[d];
+            const real hp = dp < 0 || !(ndp > (real)0) ? (real)0 : fp * (Sdp / ndp);
+            const real hm = dmi < 0 || !(ndm > (real)0) ? (real)0 : fm * (Sdm / ndm);
+            ds += (hp - hm) / dxs[d];
+        }
     }
     const real nv = n0 - g.dt * dn;
     nout[c] = nv;
+    if (S) {
+        // kept non-negative: a node can lose more than it holds in one step
+        const real sn = Sc - g.dt * ds;
+        Sout[c] = sn > (real)0 ? sn : (real)0;
+    }
     real mom[3];
-    for (int m = 0; m < 3; ++m) mom[m] = (n0 > (real)0 ? n0 * sc[m * nn + c] : (real)0) - g.dt * dm[m];
+    for (int m = 0; m < 3; ++m) mom[m] = (n0 > (real)0 ? n0 * C.us[m] : (real)0) - g.dt * dm[m];
     ux[c] = nv > n_floor ? mom[0] / nv : (real)0;
     uy[c] = nv > n_floor ? mom[1] / nv : (real)0;
     uz[c] = nv > n_floor ? mom[2] / nv : (real)0;
@@ -156,85 +266,6 @@ k_fluid_update(GridP g, real q, real n_floor, real *__restrict__ n, real *__rest
     if (fplus[0] != (real)0) Jx[c] += q * fplus[0];
     if (fplus[1] != (real)0) Jy[c] += q * fplus[1];
     if (fplus[2] != (real)0) Jz[c] += q * fplus[2];
-}
-
-__device__ inline real pressure_at(const real *__restrict__ n, const real *__restrict__ S, real gm1,
-                                   long long c) {
-    const real nc = n[c];
-    return nc > (real)0 ? S[c] * pow(nc, gm1) : (real)0;
-}
-
-// warm fluid: pressure force on the Boris result (us, v in sc)
-__global__ void __launch_bounds__(BS)
-k_fluid_pressure(GridP g, real mass, real n_floor, real gm1, const real *__restrict__ n,
-                 const real *__restrict__ S, real *__restrict__ sc) {
-    long long c = (long long)blockIdx.x * BS + threadIdx.x;
-    if (c >= g.nn) return;
-    int i, j, k;
-    node_ijk(g, c, i, j, k);
-    const int per = g.bcx == HK_BC_PERIODIC;
-    const int nxn = per ? g.nx : g.nx + 1;
-    const real nc = n[c];
-    if (i >= nxn || !(nc > n_floor) || !(nc > (real)0)) return;
-    real grad[3];
-    if (per)
-        grad[0] = (pressure_at(n, S, gm1, gidx(g, wrapi(i + 1, g.nx), j, k)) -
-                   pressure_at(n, S, gm1, gidx(g, wrapi(i - 1, g.nx), j, k))) / (2 * g.dx);
-    else if (i == 0)
-        grad[0] = (pressure_at(n, S, gm1, gidx(g, 1, j, k)) - pressure_at(n, S, gm1, c)) / g.dx;
-    else if (i == g.nx)
-        grad[0] = (pressure_at(n, S, gm1, c) - pressure_at(n, S, gm1, gidx(g, i - 1, j, k))) / g.dx;
-    else
-        grad[0] = (pressure_at(n, S, gm1, gidx(g, i + 1, j, k)) - pressure_at(n, S, gm1, gidx(g, i - 1, j, k))) /
-                  (2 * g.dx);
-    grad[1] = (pressure_at(n, S, gm1, gidx(g, i, wrapi(j + 1, g.ny), k)) -
-               pressure_at(n, S, gm1, gidx(g, i, wrapi(j - 1, g.ny), k))) / (2 * g.dy);
-    grad[2] = (pressure_at(n, S, gm1, gidx(g, i, j, wrapi(k + 1, g.nz))) -
-               pressure_at(n, S, gm1, gidx(g, i, j, wrapi(k - 1, g.nz)))) / (2 * g.dz);
-    const long long nn = g.nn;
-    real us[3];
-    for (int d = 0; d < 3; ++d) us[d] = sc[d * nn + c] - g.dt * grad[d] / (mass * nc);
-    const real gam = sqrt((real)1 + us[0] * us[0] + us[1] * us[1] + us[2] * us[2]);
-    for (int d = 0; d < 3; ++d) {
-        sc[d * nn + c] = us[d];
-        sc[(3 + d) * nn + c] = us[d] / gam;
-    }
-}
-
-// warm fluid: S_new = S - dt div(F K_donor), K = S / n (zero where n = 0)
-__global__ void __launch_bounds__(BS)
-k_fluid_entropy(GridP g, real n_floor, const real *__restrict__ n, const real *__restrict__ S,
-                const real *__restrict__ sc, real *__restrict__ Sout) {
-    long long c = (long long)blockIdx.x * BS + threadIdx.x;
-    if (c >= g.nn) return;
-    int i, j, k;
-    node_ijk(g, c, i, j, k);
-    const int per = g.bcx == HK_BC_PERIODIC;
-    const int nxn = per ? g.nx : g.nx + 1;
-    if (i >= nxn) { Sout[c] = S[c]; return; }
-    const real dxs[3] = {g.dx, g.dy, g.dz};
-    auto hflux = [&](int ii, int jj, int kk, int d) -> real {
-        real F, G[3];
-        long long don;
-        face_flux(g, n_floor, n, sc, ii, jj, kk, d, F, G, &don);
-        if (don < 0 || !(n[don] > (real)0)) return (real)0;
-        return F * (S[don] / n[don]);
-    };
-    real ds = 0;
-    for (int d = 0; d < 3; ++d) {
-        const real hp = hflux(i, j, k, d);
-        real hm = 0;
-        int ii = i, jj = j, kk = k;
-        bool has_minus = true;
-        if (d == 0) {
-            if (!per && i == 0) has_minus = false;
-            ii = per ? (i == 0 ? g.nx - 1 : i - 1) : i - 1;
-        } else if (d == 1) jj = j == 0 ? g.ny - 1 : j - 1;
-        else kk = k == 0 ? g.nz - 1 : k - 1;
-        if (has_minus) hm = hflux(ii, jj, kk, d);
-        ds += (hp - hm) / dxs[d];
-    }
-    Sout[c] = S[c] - g.dt * ds;
 }
 
 // thermal energy sum p dV / (ga - 1) over the nodes
@@ -262,21 +293,20 @@ inline unsigned blocks(long long n) { return (unsigned)((n + BS - 1) / BS); }
 
 }  // namespace
 
-// scratch: 8 grid arrays (us, v, the new density and the new entropy
-// density, copied back after every node has read the old ones)
-void launch_fluid(const GridP &g, const SpecP &sp, real *n, real *ux, real *uy, real *uz, WarmP w,
-                  real *const f[9], real *scratch, real n_floor, hipStream_t s) {
-    k_fluid_lorentz<<<blocks(g.nn), BS, 0, s>>>(g, sp.qm, n, ux, uy, uz, f[HK_EX], f[HK_EY],
-                                                f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], scratch);
-    real *nout = scratch + 6 * g.nn, *Sout = scratch + 7 * g.nn;
+// scratch: 7 grid arrays (us, v, and the pressure of a warm species); nout
+// and Sout receive the new density and entropy density (every node, so the
+// caller can swap them in)
+void launch_fluid(const GridP &g, const SpecP &sp, const real *n, real *ux, real *uy, real *uz, WarmP w,
+                  real *const f[9], real *scratch, real *nout, real *Sout, real n_floor, hipStream_t s) {
+    real *P = nullptr;
     if (w.S) {
-        k_fluid_pressure<<<blocks(g.nn), BS, 0, s>>>(g, sp.m, n_floor, (real)(w.ga - 1.0), n, w.S, scratch);
-        k_fluid_entropy<<<blocks(g.nn), BS, 0, s>>>(g, n_floor, n, w.S, scratch, Sout);
+        P = scratch + 6 * g.nn;
+        k_fluid_p<<<blocks(g.nn), BS, 0, s>>>(g, (real)(w.ga - 1.0), n, w.S, P);
     }
+    k_fluid_lorentz<<<blocks(g.nn), BS, 0, s>>>(g, sp.qm, sp.m, n_floor, n, P, ux, uy, uz, f[HK_EX],
+                                                f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], scratch);
     k_fluid_update<<<blocks(g.nn), BS, 0, s>>>(g, sp.q, n_floor, n, ux, uy, uz, scratch, f[HK_JX],
-                                               f[HK_JY], f[HK_JZ], nout);
-    hipMemcpyAsync(n, nout, sizeof(real) * g.nn, hipMemcpyDeviceToDevice, s);
-    if (w.S) hipMemcpyAsync(w.S, Sout, sizeof(real) * g.nn, hipMemcpyDeviceToDevice, s);
+                                               f[HK_JY], f[HK_JZ], nout, w.S, Sout);
 }
 
 void launch_fluid_heat(const GridP &g, const real *n, WarmP w, double *out, hipStream_t s) {

@@ -485,12 +485,20 @@ k_absorb_finish(GridP g, real mass, double *__restrict__ macc, real *__restrict_
         double gn = sqrt(1.0 + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
         d = m0 * (double)mass * (g0 - 1.0) - mt * (double)mass * (gn - 1.0);
         if (wp.S) {
-            // the merge's kinetic energy loss heats the node: p += (ga - 1) dE / dV
+            // the merge's kinetic energy loss heats the node: p += (ga - 1) dE / dV;
+            // a node left without positive mass or pressure (its fluid density
+            // had gone negative) keeps no entropy, the ledger takes that heat
+            // and its previous thermal energy
             const double ga = wp.ga;
             const double pold = n[c] > (real)0 ? (double)wp.S[c] * pow((double)n[c], ga - 1.0) : 0.0;
             const double pnew = pold + (ga - 1.0) * (macc[4 * nn + c] + d) / dv;
-            wp.S[c] = (real)(pnew * pow(mt / dv, 1.0 - ga));
-            d = 0;
+            if (mt > 0.0 && pnew >= 0.0) {
+                wp.S[c] = (real)(pnew * pow(mt / dv, 1.0 - ga));
+                d = 0;
+            } else {
+                wp.S[c] = 0;
+                d = macc[4 * nn + c] + d + pold * dv / (ga - 1.0);
+            }
         }
         n[c] = (real)(mt / dv);
         ux[c] = (real)un[0]; uy[c] = (real)un[1]; uz[c] = (real)un[2];

@@ -175,3 +175,32 @@ def test_warm_species_foil(hk, oracle_mod, prec):
                 assert dg["fluid_mass"][s] == pytest.approx(do["fluid_mass"][s], rel=1e-3, abs=1e-12)
     assert all(do["fluid_mass"][s] > 0 for s in range(3))
     assert do["photon_energy"] > 0
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_absorption_into_negative_density(hk, oracle_mod, prec):
+    # nodes whose fluid density went negative absorb particles: no entropy
+    # where the merged mass or pressure is not positive, heat to the ledger
+    cfg = _warm(configs.plain_hybrid(8, 2, 2, mode="all_fluid"), 0.05)
+    cfg["grid"]["bc_x"] = "periodic"
+    cfg["laser"]["enabled"] = False
+    g, o = _pair(hk, oracle_mod, cfg, prec)
+    n, u = o.get_fluid(0)
+    n[:] = 0.0
+    n[0, 0, 2] = -1.0
+    n[1, 1, 5] = -0.0005
+    n[0, 1, 6] = -0.004
+    u[:] = 0.0
+    for s in (g, o):
+        s.set_fluid(0, n, u)
+        s.set_pressure(0, np.zeros_like(n))
+        s.set_field("ex", np.zeros(o.shape))
+    g.step(1); o.step(1)
+    en, eu, ep = _fluid_err(g, o)
+    dg, do = g.diagnostics(), o.diagnostics()
+    print("n %.1e u %.1e p %.1e ledger %.8e / %.8e" % (en, eu, ep, dg["conv_loss"], do["conv_loss"]))
+    assert np.isfinite(g.get_pressure(0)).all()
+    tol = 1e-5 if prec == "f32" else 1e-12
+    assert en <= tol and eu <= tol and ep <= tol
+    assert dg["conv_loss"] == pytest.approx(do["conv_loss"], rel=tol)
+    assert g.get_pressure(0)[0, 0, 2] == 0.0

@@ -144,3 +144,36 @@ def test_spawn_samples_the_temperature(oracle_mod):
     assert abs(ue[:, 1].std() - math.sqrt(T)) < 0.05 * math.sqrt(T)
     assert abs(ue[:, 0].mean() - 0.02) < 0.05 * math.sqrt(T)
     assert abs(sum(d1["kin"]) + d1["conv_loss"] + d1["u_e"] + d1["u_b"] - e_fluid) < 1e-3 * e_fluid
+
+
+def test_absorption_into_negative_density(oracle_mod):
+    # a node whose fluid density went negative (a donor-cell step can drain
+    # more than a node holds) absorbs particles: where the merged mass stays
+    # negative the node keeps no entropy and the heat goes to the ledger, so
+    # particle kinetic energy = fluid kinetic + thermal energy + ledger still
+    cfg = _warm_cfg(8, "all_fluid", u_th=0.05)
+    o = oracle_mod.Oracle(cfg)
+    n, u = o.get_fluid(0)
+    n[:] = 0.0
+    n[0, 0, 2] = -1.0          # far below what its particles bring (0.01)
+    n[1, 1, 5] = -0.0005       # a small deficit: merged mass and pressure stay positive
+    n[0, 1, 6] = -0.004        # merged mass positive; the negative mass amplifies the merged
+                               # flow, whose energy may or may not exceed what the particles bring
+    u[:] = 0.0
+    o.set_fluid(0, n, u)
+    o.set_pressure(0, np.zeros_like(n))
+    o.set_field("ex", np.zeros(o.shape))
+    ke0 = sum(o.diagnostics()["kin"])
+    o.step(1)
+    d = o.diagnostics()
+    n1, u1 = o.get_fluid(0)
+    p1 = o.get_pressure(0)
+    print("n at the drained nodes %.4f %.4f %.4f; p %.3e %.3e %.3e; ledger %.6e" % (
+        n1[0, 0, 2], n1[1, 1, 5], n1[0, 1, 6], p1[0, 0, 2], p1[1, 1, 5], p1[0, 1, 6], d["conv_loss"]))
+    assert np.isfinite(p1).all() and np.isfinite(u1).all()
+    assert n1[0, 0, 2] < 0 and p1[0, 0, 2] == 0.0
+    assert n1[1, 1, 5] > 0 and p1[1, 1, 5] > 0
+    assert n1[0, 1, 6] > 0 and p1[0, 1, 6] >= 0.0
+    assert d["conv_loss"] > 0
+    total = sum(d["fluid_kin"]) + sum(d["fluid_th"]) + d["conv_loss"]
+    assert abs(total - ke0) < 1e-12 * ke0
