@@ -39,30 +39,33 @@ TILE_CELLS = 512
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_push_traffic_ionization_128x64x64.txt")
 PUSH_SOURCES = ("paper_2510_11174_amd/csrc/k_particles.hip", "paper_2510_11174_amd/csrc/hk_pic_device.h",
                 "paper_2510_11174_amd/csrc/hk_internal.h")
+FLUID_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fluid_traffic_plain_256x128x128.txt")
+FLUID_SOURCES = ("paper_2510_11174_amd/csrc/k_fluid.hip", "paper_2510_11174_amd/csrc/hk_internal.h")
 
 
-def push_source_hash():
+def source_hash(files=PUSH_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for f in PUSH_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per k_push launch (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
-    calibration) recorded in profiles/, or None if missing or taken on other kernel sources."""
+def measured_traffic(path=TRAFFIC_FILE, files=PUSH_SOURCES, key="bytes_per_launch"):
+    """HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration)
+    recorded in a profiles/ summary, or None if missing or taken on other kernel
+    sources.  Default: per k_push launch."""
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             for line in fh:
                 if "=" in line and not line.startswith("#"):
                     k, v = line.split("=", 1)
                     kv[k.strip()] = v.strip()
-        if kv.get("source_hash") != push_source_hash():
+        if kv.get("source_hash") != source_hash(files):
             return None
-        return float(kv["bytes_per_launch"])
+        return float(kv[key])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -326,8 +329,9 @@ def warm_fluid(steps=200, warmup=20, nx=256, ny=128, nz=128):
                      "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "steps_per_s": round(steps / sec, 1), "fluid_heat": d["fluid_th"][0]}
     w = out["warm"]
+    traffic = measured_traffic(FLUID_TRAFFIC_FILE, FLUID_SOURCES, "bytes_per_step_warm")
     return {"bound": "hbm", "achieved": w["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": w["frac"],
-            "traffic": None, "kernel": "k_fluid_lorentz + k_fluid_update (warm)", "nodes": nodes,
+            "traffic": traffic, "kernel": "k_fluid_lorentz + k_fluid_update (warm)", "nodes": nodes,
             "workload": "plain plasma %dx%dx%d, all fluid, u_th 0.05" % (nx, ny, nz), **{k: v for k, v in out.items()}}
 
 
