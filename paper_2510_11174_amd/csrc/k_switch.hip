@@ -73,6 +73,9 @@ __device__ inline void madd(jacc_t *p, real v, real inv) {
 }
 
 constexpr int MOM_CHUNK = 8192;   // particles per workgroup of the tile moments
+#ifndef MOM_UNROLL
+#define MOM_UNROLL 2              // particle slots per thread and loop iteration
+#endif
 constexpr int MBS = 512;          // moments workgroup: LDS allows four per CU, 8 waves per SIMD
 
 __global__ void __launch_bounds__(MBS)
@@ -128,36 +131,43 @@ k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__
         scl[q] = (real)(bound[q] / (double)JFIX_UNITS);
     }
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
-    // every field of a slot at once (no load waits on another), one iteration
-    // ahead of its use
-    int n_cell = -1, n_zc = 0;
-    real n_rx = 0, n_ry = 0, n_rz = 0, n_w = 0, n_ux = 0, n_uy = 0, n_uz = 0;
-    auto ld = [&](int p) {
-        n_cell = -1;
+    // MOM_UNROLL slots per thread and iteration, every field of every slot
+    // loaded at once and one iteration ahead of its use: the loads of
+    // 2 * MOM_UNROLL particles are in flight while the LDS sums run
+    struct Slot {
+        int cell, zc;
+        real rx, ry, rz, w, ux, uy, uz;
+    };
+    auto ld = [&](int p, Slot &m) {
+        m.cell = -1;
         if (p >= n) return;
         const long long ip = bin_slot(sp, t, p, nf, nbv);
-        n_cell = a.cell[ip];
-        n_rx = a.rx[ip]; n_ry = a.ry[ip]; n_rz = a.rz[ip]; n_w = a.w[ip];
-        if (ion_only) n_zc = a.zc[ip];
-        else { n_ux = a.ux[ip]; n_uy = a.uy[ip]; n_uz = a.uz[ip]; }
+        m.cell = a.cell[ip];
+        m.rx = a.rx[ip]; m.ry = a.ry[ip]; m.rz = a.rz[ip]; m.w = a.w[ip];
+        if (ion_only) m.zc = a.zc[ip];
+        else { m.ux = a.ux[ip]; m.uy = a.uy[ip]; m.uz = a.uz[ip]; }
     };
-    ld(p0 + threadIdx.x);
-    for (int p = p0 + threadIdx.x; p < n; p += MBS) {
-        const int cell = n_cell, zc = n_zc;
-        const real rx = n_rx, ry = n_ry, rz = n_rz, w = n_w, ux = n_ux, uy = n_uy, uz = n_uz;
-        ld(p + MBS);
-        if (cell < 0) continue;
+    auto add = [&](const Slot &m) {
+        if (m.cell < 0) return;
         int ci, cj, ck;
-        cell_ijk(g, cell, ci, cj, ck);
-        const int lx = ci - ox + (rx >= (real)0.5), ly = cj - oy + (ry >= (real)0.5),
-                  lz = ck - oz + (rz >= (real)0.5);
-        if ((unsigned)lx > TILE || (unsigned)ly > TILE || (unsigned)lz > TILE) continue;
+        cell_ijk(g, m.cell, ci, cj, ck);
+        const int lx = ci - ox + (m.rx >= (real)0.5), ly = cj - oy + (m.ry >= (real)0.5),
+                  lz = ck - oz + (m.rz >= (real)0.5);
+        if ((unsigned)lx > TILE || (unsigned)ly > TILE || (unsigned)lz > TILE) return;
         const int e = lx + NT * (ly + NT * lz);
         if (ion_only) {
-            if (zc < zmax) madd(&sm[e], w, inv[0]);
-            continue;
+            if (m.zc < zmax) madd(&sm[e], m.w, inv[0]);
+            return;
         }
-        for (int q = 0; q < 6; ++q) madd(&sm[q * NT3 + e], tile_moment_term(q, w, ux, uy, uz), inv[q]);
+        for (int q = 0; q < 6; ++q) madd(&sm[q * NT3 + e], tile_moment_term(q, m.w, m.ux, m.uy, m.uz), inv[q]);
+    };
+    constexpr int U = MOM_UNROLL;
+    Slot cur[U], nxt[U];
+    for (int u = 0; u < U; ++u) ld(p0 + threadIdx.x + u * MBS, cur[u]);
+    for (int p = p0 + threadIdx.x; p < n; p += U * MBS) {
+        for (int u = 0; u < U; ++u) ld(p + (U + u) * MBS, nxt[u]);
+        for (int u = 0; u < U; ++u) add(cur[u]);
+        for (int u = 0; u < U; ++u) cur[u] = nxt[u];
     }
     __syncthreads();
     const int per = g.bcx == HK_BC_PERIODIC;
