@@ -13,6 +13,16 @@ namespace {
 
 constexpr int BS = 256;
 
+// Node of this thread in an XCD-aware launch: workgroups go round-robin to
+// the 8 XCDs, so block b takes item (b mod 8) q + b / 8 (q = grid / 8, the
+// grid a multiple of 8) and each XCD sweeps a contiguous slab of nodes,
+// whose y and z neighbour rows then sit in its own L2.
+__device__ inline long long xcd_node() {
+    const int q = gridDim.x >> 3;
+    const int item = (blockIdx.x & 7) * q + (blockIdx.x >> 3);
+    return (long long)item * BS + threadIdx.x;
+}
+
 __global__ void __launch_bounds__(BS) k_fill(uint32_t *p, size_t n, uint32_t v) {
     size_t i = (size_t)blockIdx.x * BS + threadIdx.x;
     if (i < n) p[i] = v;
@@ -30,7 +40,7 @@ __global__ void __launch_bounds__(BS)
 k_b_half(GridP g, const real *__restrict__ Ex, const real *__restrict__ Ey,
          const real *__restrict__ Ez, real *__restrict__ Bx, real *__restrict__ By,
          real *__restrict__ Bz) {
-    long long c = (long long)blockIdx.x * BS + threadIdx.x;
+    long long c = xcd_node();
     if (c >= g.nn) return;
     int i, j, k;
     node_ijk(g, c, i, j, k);
@@ -59,7 +69,7 @@ __global__ void __launch_bounds__(BS)
 k_e_full(GridP g, real *__restrict__ Ex, real *__restrict__ Ey, real *__restrict__ Ez,
          const real *__restrict__ Bx, const real *__restrict__ By, const real *__restrict__ Bz,
          const real *__restrict__ Jx, const real *__restrict__ Jy, const real *__restrict__ Jz) {
-    long long c = (long long)blockIdx.x * BS + threadIdx.x;
+    long long c = xcd_node();
     if (c >= g.nn) return;
     int i, j, k;
     node_ijk(g, c, i, j, k);
@@ -158,6 +168,8 @@ k_divE(GridP g, const real *__restrict__ Ex, const real *__restrict__ Ey,
 }
 
 inline unsigned blocks(long long n) { return (unsigned)((n + BS - 1) / BS); }
+// grid of an XCD-aware launch over n nodes
+inline unsigned xcd_blocks(long long n) { return (blocks(n) + 7u) & ~7u; }
 
 }  // namespace
 
@@ -177,14 +189,14 @@ void launch_fill32(void *p, size_t n, uint32_t v, hipStream_t s) {
 void launch_zero(void *p, size_t bytes, hipStream_t s) { launch_fill32(p, bytes / 4, 0u, s); }
 
 void launch_yee_b_half(const GridP &g, real *const f[9], hipStream_t s) {
-    k_b_half<<<blocks(g.nn), BS, 0, s>>>(g, f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY],
+    k_b_half<<<xcd_blocks(g.nn), BS, 0, s>>>(g, f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY],
                                          f[HK_BZ]);
 }
 
 void launch_yee_e_full(const GridP &g, real *const f[9], real *mur_old, hipStream_t s) {
     const int plane = g.ny * g.nz;
     if (g.bcx == HK_BC_OPEN) k_mur_save<<<blocks(plane), BS, 0, s>>>(g, f[HK_EY], f[HK_EZ], mur_old);
-    k_e_full<<<blocks(g.nn), BS, 0, s>>>(g, f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY],
+    k_e_full<<<xcd_blocks(g.nn), BS, 0, s>>>(g, f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY],
                                          f[HK_BZ], f[HK_JX], f[HK_JY], f[HK_JZ]);
     if (g.bcx == HK_BC_OPEN) k_mur_apply<<<blocks(plane), BS, 0, s>>>(g, f[HK_EY], f[HK_EZ], mur_old);
 }

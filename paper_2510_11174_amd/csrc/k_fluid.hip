@@ -29,6 +29,16 @@ namespace {
 
 constexpr int BS = 256;
 
+// Node of this thread in an XCD-aware launch: workgroups go round-robin to
+// the 8 XCDs, so block b takes item (b mod 8) q + b / 8 (q = grid / 8, the
+// grid a multiple of 8) and each XCD sweeps a contiguous slab of nodes,
+// whose y and z neighbour rows then sit in its own L2.
+__device__ inline long long xcd_node() {
+    const int q = gridDim.x >> 3;
+    const int item = (blockIdx.x & 7) * q + (blockIdx.x >> 3);
+    return (long long)item * BS + threadIdx.x;
+}
+
 
 // Linear indices of a node's neighbours (node counts stay below 2^31):
 // y and z periodic, x periodic or open (no neighbour beyond an open wall).
@@ -78,7 +88,7 @@ __device__ inline real node_val(const real *__restrict__ F, const int xs[2], con
 // warm fluid: node pressure p = S n^(ga-1), zero where n = 0
 __global__ void __launch_bounds__(BS)
 k_fluid_p(GridP g, real gm1, const real *__restrict__ n, const real *__restrict__ S, real *__restrict__ P) {
-    long long c = (long long)blockIdx.x * BS + threadIdx.x;
+    long long c = xcd_node();
     if (c >= g.nn) return;
     const real nc = n[c];
     P[c] = nc > (real)0 ? S[c] * pow(nc, gm1) : (real)0;
@@ -90,7 +100,7 @@ k_fluid_lorentz(GridP g, real qm, real mass, real n_floor, const real *__restric
                 const real *__restrict__ uy, const real *__restrict__ uz, const real *__restrict__ Ex,
                 const real *__restrict__ Ey, const real *__restrict__ Ez, const real *__restrict__ Bx,
                 const real *__restrict__ By, const real *__restrict__ Bz, real *__restrict__ sc) {
-    long long cl = (long long)blockIdx.x * BS + threadIdx.x;
+    long long cl = xcd_node();
     if (cl >= g.nn) return;
     int i, j, k;
     node_ijk(g, cl, i, j, k);
@@ -176,7 +186,7 @@ k_fluid_update(GridP g, real q, real n_floor, const real *__restrict__ n, real *
                real *__restrict__ uy, real *__restrict__ uz, const real *__restrict__ sc,
                real *__restrict__ Jx, real *__restrict__ Jy, real *__restrict__ Jz,
                real *__restrict__ nout, const real *__restrict__ S, real *__restrict__ Sout) {
-    long long cl = (long long)blockIdx.x * BS + threadIdx.x;
+    long long cl = xcd_node();
     if (cl >= g.nn) return;
     int i, j, k;
     node_ijk(g, cl, i, j, k);
@@ -290,6 +300,8 @@ k_fluid_heat(GridP g, const real *__restrict__ n, const real *__restrict__ S, re
 }
 
 inline unsigned blocks(long long n) { return (unsigned)((n + BS - 1) / BS); }
+// grid of an XCD-aware launch over n nodes
+inline unsigned xcd_blocks(long long n) { return (blocks(n) + 7u) & ~7u; }
 
 }  // namespace
 
@@ -301,11 +313,11 @@ void launch_fluid(const GridP &g, const SpecP &sp, const real *n, real *ux, real
     real *P = nullptr;
     if (w.S) {
         P = scratch + 6 * g.nn;
-        k_fluid_p<<<blocks(g.nn), BS, 0, s>>>(g, (real)(w.ga - 1.0), n, w.S, P);
+        k_fluid_p<<<xcd_blocks(g.nn), BS, 0, s>>>(g, (real)(w.ga - 1.0), n, w.S, P);
     }
-    k_fluid_lorentz<<<blocks(g.nn), BS, 0, s>>>(g, sp.qm, sp.m, n_floor, n, P, ux, uy, uz, f[HK_EX],
+    k_fluid_lorentz<<<xcd_blocks(g.nn), BS, 0, s>>>(g, sp.qm, sp.m, n_floor, n, P, ux, uy, uz, f[HK_EX],
                                                 f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], scratch);
-    k_fluid_update<<<blocks(g.nn), BS, 0, s>>>(g, sp.q, n_floor, n, ux, uy, uz, scratch, f[HK_JX],
+    k_fluid_update<<<xcd_blocks(g.nn), BS, 0, s>>>(g, sp.q, n_floor, n, ux, uy, uz, scratch, f[HK_JX],
                                                f[HK_JY], f[HK_JZ], nout, w.S, Sout);
 }
 

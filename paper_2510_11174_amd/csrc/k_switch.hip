@@ -24,6 +24,15 @@ namespace {
 
 using namespace hkdev;
 constexpr int BS = 256;
+
+// Node of this thread in an XCD-aware launch over the nodes: block b takes
+// item (b mod 8) q + b / 8 of a grid of 8 q blocks, so each XCD sweeps a
+// contiguous slab whose neighbour rows sit in its own L2.
+__device__ inline long long xcd_node() {
+    const int q = gridDim.x >> 3;
+    const int item = (blockIdx.x & 7) * q + (blockIdx.x >> 3);
+    return (long long)item * BS + threadIdx.x;
+}
 constexpr int NT = TILE + 1;          // node tile edge: nearest nodes 0 .. TILE
 constexpr int NT3 = NT * NT * NT;
 
@@ -270,7 +279,7 @@ __global__ void __launch_bounds__(BS)
 k_indicators(GridP g, SwitchP P, const real *__restrict__ mom, const real *__restrict__ Ex,
              const real *__restrict__ Ey, const real *__restrict__ Ez, IonSet ions,
              uint8_t *__restrict__ hot, uint8_t *__restrict__ notcold) {
-    long long c = (long long)blockIdx.x * BS + threadIdx.x;
+    long long c = xcd_node();
     if (c >= g.nn) return;
     int i, j, k;
     node_ijk(g, c, i, j, k);
@@ -318,7 +327,7 @@ k_indicators(GridP g, SwitchP P, const real *__restrict__ mom, const real *__res
 __global__ void __launch_bounds__(BS)
 k_dilate(GridP g, SwitchP P, const uint8_t *__restrict__ hot, const uint8_t *__restrict__ notcold,
          uint8_t *__restrict__ sw, uint8_t *__restrict__ calm) {
-    long long c = (long long)blockIdx.x * BS + threadIdx.x;
+    long long c = xcd_node();
     if (c >= g.nn) return;
     int i, j, k;
     node_ijk(g, c, i, j, k);
@@ -614,6 +623,7 @@ k_spawn(GridP g, SpecP sp, const uint8_t *__restrict__ sw, real *__restrict__ n,
 }
 
 inline unsigned blocks(long long n) { return (unsigned)((n + BS - 1) / BS); }
+inline unsigned xcd_blocks(long long n) { return (blocks(n) + 7u) & ~7u; }
 
 }  // namespace
 
@@ -634,11 +644,11 @@ void launch_indicators_nodes(const GridP &g, const SwitchP &P, const real *mom, 
     IonSet set{};
     set.n = nion < 4 ? nion : 4;
     for (int q = 0; q < set.n; ++q) set.p[q] = ions[q];
-    k_indicators<<<blocks(g.nn), BS, 0, s>>>(g, P, mom, f[HK_EX], f[HK_EY], f[HK_EZ], set, hot, notcold);
+    k_indicators<<<xcd_blocks(g.nn), BS, 0, s>>>(g, P, mom, f[HK_EX], f[HK_EY], f[HK_EZ], set, hot, notcold);
 }
 void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, const uint8_t *notcold,
                          uint8_t *sw, uint8_t *calm, hipStream_t s) {
-    k_dilate<<<blocks(g.nn), BS, 0, s>>>(g, P, hot, notcold, sw, calm);
+    k_dilate<<<xcd_blocks(g.nn), BS, 0, s>>>(g, P, hot, notcold, sw, calm);
 }
 void launch_absorb_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, const uint8_t *sw,
                          real *const f[9], double *macc, double *ledger, bool warm, hipStream_t s) {
