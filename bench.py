@@ -444,7 +444,11 @@ def main():
         "field_rel_l2_vs_allpic": {str(k): v for k, v in l2.items()},
         "field_rel_l2_allpic_repeat": {str(k): v for k, v in floor.items()},
         "energy_diff_vs_allpic": drift,
-        "field_err_ok": l2[K] <= max(1e-3, floor[K]),
+        # the hybrid meets 1e-3 at every snapshot where two all-PIC runs agree to
+        # 1e-3; where they do not (FP32 atomics and a chaotic plasma), it must lie
+        # within 10% of their distance, a single sample of the run-to-run noise
+        "field_err_ok": all(l2[s] <= 1e-3 if floor[s] <= 1e-3 else l2[s] <= 1.1 * floor[s] for s in l2),
+        "field_err_over_floor": {str(k): round(l2[k] / floor[k], 4) if floor[k] > 0 else None for k in l2},
         "kinetic_fraction_end": h["kinetic_fraction"],
         "roofline": roof(p, True),
         "roofline_hybrid": roof(h, False),
