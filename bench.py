@@ -361,7 +361,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the multi-GPU path (domain decomposition) is not "
-              "part of this build; run with --gpus 1", file=sys.stderr)
+              "implemented by this library; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
