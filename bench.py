@@ -456,6 +456,17 @@ def main():
         "timers_allpic_ms_per_step": {k: round(v / K, 4) for k, v in p["timers"].items() if k.endswith("_ms")},
         "rebins": {"hybrid": h["timers"]["rebins"], "all_pic": p["timers"]["rebins"]},
     }
+    # the field update (Yee, Mur walls, antenna) of the all-PIC run, from its
+    # HIP-event phase timer; algorithmic bytes per cell and step: read E, B and
+    # write B, then read E, B, J and write E (84 B; the two B half steps that
+    # give B at whole steps for the push move 120 B)
+    cells = 128 * 64 * 64
+    f_ms = p["timers"]["fields_ms"] / K
+    yee_gbs = 84 * cells / (f_ms * 1e-3) / 1e9 if f_ms > 0 else 0.0
+    out["roofline_yee"] = {"bound": "hbm", "achieved": round(yee_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(yee_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                           "kernel": "k_b_half x2 + k_e_full + k_mur_save + k_mur_apply + k_antenna",
+                           "ms_per_step": round(f_ms, 4), "alg_bytes_per_step": 84 * cells}
     out["roofline_cnn_switch"] = cnn_inference()
     out["roofline_state_predictor"] = sp_surrogate()
     out["roofline_switchnet"] = swn_inference()

@@ -126,9 +126,11 @@ k_fluid_lorentz(GridP g, real qm, real mass, real n_floor, const real *__restric
     const real h = (real)0.5 * qm * g.dt;
     real umx = ux[c] + h * ex, umy = uy[c] + h * ey, umz = uz[c] + h * ez;
     real gm = sqrt((real)1 + umx * umx + umy * umy + umz * umz);
-    real tx = h * bx / gm, ty = h * by / gm, tz = h * bz / gm;
+    const real rg = h / gm;
+    real tx = bx * rg, ty = by * rg, tz = bz * rg;
     real t2 = tx * tx + ty * ty + tz * tz;
-    real sx = 2 * tx / (1 + t2), sy = 2 * ty / (1 + t2), sz = 2 * tz / (1 + t2);
+    const real r2 = (real)2 / (1 + t2);
+    real sx = tx * r2, sy = ty * r2, sz = tz * r2;
     real upx = umx + (umy * tz - umz * ty), upy = umy + (umz * tx - umx * tz),
          upz = umz + (umx * ty - umy * tx);
     real us[3];
@@ -145,13 +147,14 @@ k_fluid_lorentz(GridP g, real qm, real mass, real n_floor, const real *__restric
         else grad[0] = (P[b.xp] - P[b.xm]) / (2 * g.dx);
         grad[1] = (P[b.yp] - P[b.ym]) / (2 * g.dy);
         grad[2] = (P[b.zp] - P[b.zm]) / (2 * g.dz);
-        for (int d = 0; d < 3; ++d) us[d] = us[d] - g.dt * grad[d] / (mass * nc);
+        const real rmn = g.dt / (mass * nc);
+        for (int d = 0; d < 3; ++d) us[d] = us[d] - grad[d] * rmn;
     }
-    real gam = sqrt((real)1 + us[0] * us[0] + us[1] * us[1] + us[2] * us[2]);
+    const real rgam = (real)1 / sqrt((real)1 + us[0] * us[0] + us[1] * us[1] + us[2] * us[2]);
     const long long nn = g.nn;
     for (int d = 0; d < 3; ++d) {
         sc[d * nn + c] = us[d];
-        sc[(3 + d) * nn + c] = us[d] / gam;
+        sc[(3 + d) * nn + c] = us[d] * rgam;
     }
 }
 
@@ -201,7 +204,7 @@ k_fluid_update(GridP g, real q, real n_floor, const real *__restrict__ n, real *
     }
     const long long nn = g.nn;
     const real *const us[3] = {sc, sc + nn, sc + 2 * nn};
-    const real dxs[3] = {g.dx, g.dy, g.dz};
+    const real rdx[3] = {(real)1 / g.dx, (real)1 / g.dy, (real)1 / g.dz};
     const Nbr b = neighbours(g, c, i, j, k);
     const int pl[3] = {b.xp, b.yp, b.zp}, mi[3] = {b.xm, b.ym, b.zm};
     const bool hasp[3] = {b.hasxp, true, true}, hasm[3] = {b.hasxm, true, true};
@@ -250,14 +253,14 @@ k_fluid_update(GridP g, real q, real n_floor, const real *__restrict__ n, real *
         if (hasp[d]) face_flux(C, P[d], c, pl[d], fp, gp, dp, ndp);
         if (hasm[d]) face_flux(M[d], C, mi[d], c, fm, gm, dmi, ndm);
         fplus[d] = fp;
-        dn += (fp - fm) / dxs[d];
-        for (int m = 0; m < 3; ++m) dm[m] += (gp[m] - gm[m]) / dxs[d];
+        dn += (fp - fm) * rdx[d];
+        for (int m = 0; m < 3; ++m) dm[m] += (gp[m] - gm[m]) * rdx[d];
         if (S) {
             // entropy flux F K_donor, K = S / n at the donor
             const real Sdp = dp == c ? Sc : Sp[d], Sdm = dmi == c ? Sc : Sm[d];
             const real hp = dp < 0 || !(ndp > (real)0) ? (real)0 : fp * (Sdp / ndp);
             const real hm = dmi < 0 || !(ndm > (real)0) ? (real)0 : fm * (Sdm / ndm);
-            ds += (hp - hm) / dxs[d];
+            ds += (hp - hm) * rdx[d];
         }
     }
     const real nv = n0 - g.dt * dn;
@@ -269,9 +272,11 @@ k_fluid_update(GridP g, real q, real n_floor, const real *__restrict__ n, real *
     }
     real mom[3];
     for (int m = 0; m < 3; ++m) mom[m] = (n0 > (real)0 ? n0 * C.us[m] : (real)0) - g.dt * dm[m];
-    ux[c] = nv > n_floor ? mom[0] / nv : (real)0;
-    uy[c] = nv > n_floor ? mom[1] / nv : (real)0;
-    uz[c] = nv > n_floor ? mom[2] / nv : (real)0;
+    const bool live = nv > n_floor;
+    const real rnv = live ? (real)1 / nv : (real)0;
+    ux[c] = live ? mom[0] * rnv : (real)0;
+    uy[c] = live ? mom[1] * rnv : (real)0;
+    uz[c] = live ? mom[2] * rnv : (real)0;
     // fluid current on the + faces (none beyond the open x wall)
     if (fplus[0] != (real)0) Jx[c] += q * fplus[0];
     if (fplus[1] != (real)0) Jy[c] += q * fplus[1];
