@@ -317,6 +317,21 @@ int hk_cnn_loss_grad(hk_cnn *cnn, const float *x, const float *y, const float *e
 int hk_cnn_train_step(hk_cnn *cnn, const float *x, const float *y, const float *e, int B, int D, int H,
                       int W, const hk_cnn_train_desc *train, double *loss);
 const char *hk_cnn_last_error(const hk_cnn *cnn);
+/* Allocation-free variant of hk_cnn_forward, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, layouts and results as
+ * hk_cnn_forward (the same kernels); the BF16 input copy and the activations
+ * live in one static device array of HK_CNN_NOALLOC_SCRATCH_BYTES per GPU,
+ * held until the process ends, so the call makes no hipMalloc, hipFree or
+ * other allocation.  B * D * H * W may not exceed HK_CNN_NOALLOC_MAX_VOXELS
+ * (HK_EINVAL, message in hk_cnn_last_error).  The work is only enqueued on
+ * the network's stream: the logits are ready once the stream gets there.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (any network, any stream) race and must be serialized by the caller.  The
+ * first call on a device looks the array up there (HK_EDEVICE on failure). */
+#define HK_CNN_NOALLOC_MAX_VOXELS (1 << 18)
+#define HK_CNN_NOALLOC_SCRATCH_BYTES ((size_t)HK_CNN_NOALLOC_MAX_VOXELS * (8 * 2 + 2 * 32 * 2))
+int hk_cnn_forward_noalloc(hk_cnn *cnn, const float *x, int B, int D, int H, int W, float *logit);
 /* Training data from a simulation, per node of the grid [nz][ny][NX] (NX = nx
  * for periodic x, nx + 1 for open x), x fastest, all host arrays (NULL skips
  * one): raw[8 n] the network's 8 inputs before normalization; ehat[n] the

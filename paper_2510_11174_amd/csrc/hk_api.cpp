@@ -700,7 +700,7 @@ void cnn_switch(hk_sim *S) {
     if (!S->cnn_x || !S->cnn_nfall) { fail(S, HK_ENOMEM, "CNN switch inputs"); return; }
     cnn_launch_inputs(g, S->f, S->mom, c->mean, c->inv_std, S->cnn_x, S->s);
     const unsigned short *a4;
-    if (cnn_forward_bf16(c, S->cnn_x, 1, D, H, W, false, S->s, &a4) != HK_OK) {
+    if (cnn_forward_bf16(c, S->cnn_x, 1, D, H, W, false, S->s, &a4, nullptr) != HK_OK) {
         fail(S, HK_ENOMEM, "CNN switch: %s", c->err.c_str());
         return;
     }

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -102,15 +103,19 @@ int cnn_pack(hk_cnn *c, hipStream_t s) {
 }
 
 // Forward over B x D x H x W x 8 BF16 inputs; activations of every layer (and
-// pre-activations when keep_z) stay in the workspace.  Returns a4.
+// pre-activations when keep_z) stay in the workspace.  Returns a4.  With
+// `pingpong` the activations alternate between those two caller buffers
+// instead (layer l writes pingpong[l & 1]; no pre-activations, nothing grown).
 int cnn_forward_bf16(hk_cnn *c, const unsigned short *x, int B, int D, int H, int W, bool keep_z,
-                     hipStream_t s, const unsigned short **a4) {
+                     hipStream_t s, const unsigned short **a4, unsigned short *const *pingpong) {
     if (D < 9 || H < 9 || W < 9) return cnn_fail(c, HK_EINVAL, "input smaller than the receptive field");
+    if (pingpong && keep_z) return cnn_fail(c, HK_EINVAL, "pre-activations need the workspace");
     const unsigned short *in = x;
     for (int l = 0; l < 4; ++l) {
         const int d = D - 2 * (l + 1), h = H - 2 * (l + 1), w = W - 2 * (l + 1);
         const size_t n = (size_t)B * d * h * w;
-        unsigned short *a = (unsigned short *)ws(c, c->wa[l], c->wa_cap[l], n * NC * 2);
+        unsigned short *a = pingpong ? pingpong[l & 1]
+                                     : (unsigned short *)ws(c, c->wa[l], c->wa_cap[l], n * NC * 2);
         float *z = keep_z ? (float *)ws(c, c->wz[l], c->wz_cap[l], n * NC * 4) : nullptr;
         if (!a || (keep_z && !z)) return cnn_fail(c, HK_ENOMEM, "CNN activations");
         cnn_launch_conv_fwd(cin_of(l), B, D - 2 * l, H - 2 * l, W - 2 * l, in, c->Wf[l], c->p + w_off(l) + 27LL * cin_of(l) * NC,
@@ -205,7 +210,7 @@ int hk_cnn_forward(hk_cnn *c, const float *x, int B, int D, int H, int W, float 
     if (!xb) return cnn_fail(c, HK_ENOMEM, "CNN input");
     cnn_launch_to_bf16((long long)nin, x, xb, c->s);
     const unsigned short *a4;
-    int rc = cnn_forward_bf16(c, xb, B, D, H, W, false, c->s, &a4);
+    int rc = cnn_forward_bf16(c, xb, B, D, H, W, false, c->s, &a4, nullptr);
     if (rc) return rc;
     const long long n = (long long)B * (D - 8) * (H - 8) * (W - 8);
     cnn_launch_head(n, a4, c->wh, c->p + w_off(4) + NC, 0, 0, 0, logit, c->s);
@@ -223,7 +228,7 @@ int hk_cnn_loss_grad(hk_cnn *c, const float *x, const float *y, const float *e, 
     if (!xb) return cnn_fail(c, HK_ENOMEM, "CNN input");
     cnn_launch_to_bf16((long long)nin, x, xb, s);
     const unsigned short *a4;
-    int rc = cnn_forward_bf16(c, xb, B, D, H, W, true, s, &a4);
+    int rc = cnn_forward_bf16(c, xb, B, D, H, W, true, s, &a4, nullptr);
     if (rc) return rc;
     CCHK(c, hipMemsetAsync(c->g, 0, sizeof(float) * np, s));
     CCHK(c, hipMemsetAsync(c->loss, 0, sizeof(double), s));
@@ -271,5 +276,73 @@ int hk_cnn_train_step(hk_cnn *c, const float *x, const float *y, const float *e,
 }
 
 const char *hk_cnn_last_error(const hk_cnn *c) { return c ? c->err.c_str() : "null network"; }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------
+// Allocation-free forward.  Its working memory is one static device array per
+// GPU: the BF16 copy of the input, then two activation buffers that the four
+// layers alternate between (layer l writes buffer l & 1, reads the other or
+// the input).  Kernels take the array's device address, looked up once per
+// device with hipGetSymbolAddress; the array's name itself is a host-side
+// stand-in and never reaches a kernel.
+namespace {
+
+constexpr size_t NOALLOC_IN = (size_t)HK_CNN_NOALLOC_MAX_VOXELS * 8 * 2;    // BF16 inputs
+constexpr size_t NOALLOC_ACT = (size_t)HK_CNN_NOALLOC_MAX_VOXELS * NC * 2;  // one activation buffer
+static_assert(HK_CNN_NOALLOC_SCRATCH_BYTES == NOALLOC_IN + 2 * NOALLOC_ACT, "scratch layout");
+
+__device__ __align__(256) unsigned char scratch[HK_CNN_NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+unsigned char *noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// device address of this device's scratch array (looked up on first use)
+int noalloc_scratch(hk_cnn *c, unsigned char **out) {
+    int dev = -1;
+    CCHK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return cnn_fail(c, HK_EDEVICE, "device %d beyond the %d the scratch table covers", dev,
+                        NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (!noalloc_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return cnn_fail(c, HK_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                            hipGetErrorString(e));
+        noalloc_ptr[dev] = (unsigned char *)p;
+    }
+    *out = noalloc_ptr[dev];
+    return HK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hk_cnn_forward_noalloc(hk_cnn *c, const float *x, int B, int D, int H, int W, float *logit) {
+    if (!c || !x || !logit || B <= 0 || D <= 0 || H <= 0 || W <= 0) return HK_EINVAL;
+    const long long vox = (long long)B * D * H * W;
+    if (vox > HK_CNN_NOALLOC_MAX_VOXELS)
+        return cnn_fail(c, HK_EINVAL, "hk_cnn_forward_noalloc: %lld input voxels exceed the limit of %d",
+                        vox, HK_CNN_NOALLOC_MAX_VOXELS);
+    if (D < 9 || H < 9 || W < 9) return cnn_fail(c, HK_EINVAL, "input smaller than the receptive field");
+    unsigned char *base = nullptr;
+    int rc = noalloc_scratch(c, &base);
+    if (rc) return rc;
+    unsigned short *xb = (unsigned short *)base;
+    unsigned short *pp[2] = {(unsigned short *)(base + NOALLOC_IN),
+                             (unsigned short *)(base + NOALLOC_IN + NOALLOC_ACT)};
+    cnn_launch_to_bf16(vox * 8, x, xb, c->s);
+    const unsigned short *a4;
+    rc = cnn_forward_bf16(c, xb, B, D, H, W, false, c->s, &a4, pp);
+    if (rc) return rc;
+    const long long n = (long long)B * (D - 8) * (H - 8) * (W - 8);
+    cnn_launch_head(n, a4, c->wh, c->p + w_off(4) + NC, 0, 0, 0, logit, c->s);
+    CCHK(c, hipGetLastError());
+    return HK_OK;
+}
 
 }  // extern "C"

@@ -29,4 +29,4 @@ struct hk_cnn {
 void *cnn_alloc(hk_cnn *c, size_t bytes);
 void cnn_release(hk_cnn *c, void *p);
 int cnn_forward_bf16(hk_cnn *c, const unsigned short *x, int B, int D, int H, int W, bool keep_z,
-                     hipStream_t s, const unsigned short **a4);
+                     hipStream_t s, const unsigned short **a4, unsigned short *const *pingpong);

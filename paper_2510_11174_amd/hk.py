@@ -108,7 +108,7 @@ ABI_SYMBOLS = ["hk_create", "hk_destroy", "hk_step", "hk_switch_map", "hk_set_sw
                "hk_set_particles", "hk_get_fluid", "hk_set_fluid", "hk_get_fluid_p", "hk_set_fluid_p", "hk_enable_timing",
                "hk_timers", "hk_qed_tables", "hk_cnn_nparams", "hk_cnn_create", "hk_cnn_destroy",
                "hk_cnn_set_params", "hk_cnn_get_params", "hk_cnn_set_norm", "hk_cnn_forward",
-               "hk_cnn_loss_grad", "hk_cnn_train_step", "hk_cnn_last_error", "hk_set_cnn", "hk_node_inputs", "hk_node_state",
+               "hk_cnn_loss_grad", "hk_cnn_train_step", "hk_cnn_last_error", "hk_cnn_forward_noalloc", "hk_set_cnn", "hk_node_inputs", "hk_node_state",
                "hk_sp_nparams", "hk_sp_create", "hk_sp_destroy", "hk_sp_set_params", "hk_sp_get_params",
                "hk_sp_set_norm", "hk_sp_forward", "hk_sp_loss_grad", "hk_sp_train_step", "hk_sp_last_error",
                "hk_swn_nparams", "hk_swn_create", "hk_swn_destroy", "hk_swn_set_params", "hk_swn_get_params",
@@ -165,6 +165,7 @@ def load(prec: str = "f32"):
     L.hk_cnn_get_params.argtypes = [vp, vp, C.c_size_t]
     L.hk_cnn_set_norm.argtypes = [vp, vp, vp]
     L.hk_cnn_forward.argtypes = [vp, vp] + [C.c_int] * 4 + [vp]
+    L.hk_cnn_forward_noalloc.argtypes = [vp, vp] + [C.c_int] * 4 + [vp]
     L.hk_cnn_loss_grad.argtypes = [vp, vp, vp, vp] + [C.c_int] * 4 + [C.c_float, C.c_int, vp,
                                                                       P(C.c_double)]
     L.hk_cnn_train_step.argtypes = [vp, vp, vp, vp] + [C.c_int] * 4 + [P(CnnTrainDesc), P(C.c_double)]
@@ -518,6 +519,17 @@ class CNN:
         B, D, H, W, _ = x.shape
         out = torch.empty((B, D - 8, H - 8, W - 8), device=x.device, dtype=torch.float32)
         self._check(self.lib.hk_cnn_forward(self.h, x.data_ptr(), B, D, H, W, out.data_ptr()))
+        return out
+
+    def forward_noalloc(self, x, out=None):
+        """hk_cnn_forward_noalloc: the same logits from the library's static
+        scratch array; only enqueued on the network's stream."""
+        x = x.contiguous()
+        B, D, H, W, _ = x.shape
+        if out is None:
+            import torch
+            out = torch.empty((B, D - 8, H - 8, W - 8), device=x.device, dtype=torch.float32)
+        self._check(self.lib.hk_cnn_forward_noalloc(self.h, x.data_ptr(), B, D, H, W, out.data_ptr()))
         return out
 
     def loss_grad(self, x, y, e, lam=0.1, mask_step=-1):
