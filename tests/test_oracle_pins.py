@@ -22,6 +22,22 @@ def test_philox_uniform_exact_in_float32(oracle_mod):
         assert float(np.float32(u)) == u
 
 
+def test_philox_known_answers(oracle_mod):
+    # the known-answer vectors of Philox4x32-10 published with the generator
+    # (Salmon et al., SC'11, Random123 distribution): counter, key -> output
+    kat = [
+        ((0x00000000, 0x00000000, 0x00000000, 0x00000000), (0x00000000, 0x00000000),
+         (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+        ((0xffffffff, 0xffffffff, 0xffffffff, 0xffffffff), (0xffffffff, 0xffffffff),
+         (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+        ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0),
+         (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1)),
+    ]
+    for ctr, key, want in kat:
+        got = oracle_mod.philox(np.array(ctr, np.uint32), np.array(key, np.uint32))
+        assert [int(v) for v in got] == list(want), [hex(int(v)) for v in got]
+
+
 def test_philox_statistics(oracle_mod):
     # chi^2 uniformity of the 4 output words over 4096 counters, and the
     # avalanche property: flipping one counter bit flips about half the bits.
@@ -270,6 +286,34 @@ def test_adk_hydrogenic_equals_landau_lifshitz(oracle_mod):
         ll = 4 * Z ** 5 / F * math.exp(-2 * Z ** 3 / (3 * F))
         assert abs(oracle_mod.adk_rate(F, ip, Z) / ll - 1) < 1e-12
     assert abs(oracle_mod.adk_rate(0.5, 2.0, 2.0) - 5.9671e-3) < 1e-6
+
+
+def test_adk_nonhydrogenic_general_form(oracle_mod):
+    # The ADK rate in its general form (Ammosov, Delone, Krainov 1986) for
+    # quantum numbers n*, l*, l, m:
+    #   w = C^2 f(l, m) Ip (2 kappa^3 / F)^(2 n* - |m| - 1) exp(-2 kappa^3 / (3 F)),
+    #   C^2 = 2^(2 n*) / (n* Gamma(n* + l* + 1) Gamma(n* - l*)),
+    #   f(l, m) = (2 l + 1) (l + |m|)! / (2^|m| |m|! (l - |m|)!),  kappa = sqrt(2 Ip),
+    # evaluated here with scipy's Gamma function at l* = n* - 1, l = m = 0 (the
+    # s-state reading), for He I (n* = 0.744) and effective quantum numbers
+    # on both sides of 1, where Gamma(2 n*) differs from Gamma(n*) and from 1.
+    from scipy.special import gamma, factorial
+    HARTREE_EV = 27.211386245988
+    cases = [(24.587387936 / HARTREE_EV, 1.0), (0.5, 0.6), (0.3, 1.3), (1.2, 3.0), (0.05, 0.45)]
+    for ip, zres in cases:
+        ns = zres / math.sqrt(2 * ip)
+        ls = ns - 1.0
+        l, m = 0, 0
+        c2 = 2 ** (2 * ns) / (ns * gamma(ns + ls + 1) * gamma(ns - ls))
+        flm = (2 * l + 1) * factorial(l + abs(m)) / (2 ** abs(m) * factorial(abs(m)) * factorial(l - abs(m)))
+        k3 = (2 * ip) ** 1.5
+        for F in (0.02, 0.08, 0.3):
+            w = c2 * flm * ip * (2 * k3 / F) ** (2 * ns - abs(m) - 1) * math.exp(-2 * k3 / (3 * F))
+            got = oracle_mod.adk_rate(F, ip, zres)
+            assert abs(got / w - 1) < 1e-12, (ip, zres, F, got, w)
+    # He I: n* away from 1, so Gamma(2 n*) = 0.886 differs from Gamma(n*) = 1.22
+    ns = 1.0 / math.sqrt(2 * 24.587387936 / HARTREE_EV)
+    assert abs(ns - 0.74388) < 1e-4
 
 
 def test_ionization_blend_limits(oracle_mod):
