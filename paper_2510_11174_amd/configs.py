@@ -104,8 +104,71 @@ def qed_hybrid(nx=256, ny=128, nz=128, mode="threshold", seed=None, dx=0.05, ppc
     }
 
 
+def full_foil(a0=50.0, nx=512, ny=256, nz=256, mode="threshold", seed=None, dx=0.05, ppc=16,
+              duration=10.0):
+    """Full-size learned-hybrid workload, foil target: 512 x 256 x 256 cells
+    (33.5 M), dx = 0.05, a pre-ionized hydrogen foil at 10 n_c, 1 lambda thick
+    from x = 3.2, 16 particles per cell per species, mobile protons; circular
+    pulse of amplitude a0 (5, 50 or 200 in the sweep), waist 3 lambda, field
+    half-width `duration` = 10 centred at t = 2 duration, so its front reaches
+    the foil near step 300 and its peak near step 850; photon emission and
+    pair creation on; the switch is re-evaluated every 10 steps."""
+    foil = {"profile": "foil", "n0": 10.0, "x0": 3.2, "length": TWO_PI, "u_th": 1e-3}
+    return {
+        "name": "full_foil_a%g_%dx%dx%d" % (a0, nx, ny, nz),
+        "grid": _grid(nx, ny, nz, dx),
+        "species": [
+            dict(kind="electron", charge=-1.0, mass=1.0, ppc=ppc, mobile=True, fluid=True,
+                 qed=True, **foil),
+            dict(kind="ion", charge=1.0, mass=1836.15267343, ppc=ppc, mobile=True, fluid=True,
+                 **foil),
+            dict(kind="positron", charge=1.0, mass=1.0, ppc=ppc, profile="none", n0=10.0,
+                 mobile=True, fluid=False, qed=True),
+            dict(kind="photon", charge=0.0, mass=0.0, ppc=0, profile="none", mobile=True,
+                 fluid=False, qed=True),
+        ],
+        "laser": {"enabled": True, "polarization": "circular", "a0": float(a0),
+                  "waist": 3 * TWO_PI, "duration": duration, "t_center": 2 * duration,
+                  "i_antenna": 2, "lambda_um": 0.8},
+        "run": _run(SEED_BASE + 5 if seed is None else seed, mode, enable_qed=True,
+                    enable_ionization=True, switch_every=10),
+        "steps": 500,
+    }
+
+
+def full_gas(a0=50.0, nx=512, ny=256, nz=256, mode="threshold", seed=None, dx=0.05, ppc=16,
+             duration=10.0):
+    """Full-size learned-hybrid workload, gas target: 512 x 256 x 256 cells,
+    dx = 0.05, neutral helium at 0.5 n_c filling the box from x = 3.2, 16
+    particles per cell, immobile atoms ionized through He II (ADK/multiphoton);
+    circular pulse as for the foil; photon emission on for the freed
+    electrons; switch every 10 steps."""
+    return {
+        "name": "full_gas_a%g_%dx%dx%d" % (a0, nx, ny, nz),
+        "grid": _grid(nx, ny, nz, dx),
+        "species": [
+            {"kind": "electron", "charge": -1.0, "mass": 1.0, "ppc": ppc, "profile": "none",
+             "n0": 1.0, "u_th": 0.0, "mobile": True, "fluid": True, "qed": True},
+            {"kind": "ion", "charge": 0.0, "mass": 4.0 * 1836.15267343, "ppc": ppc,
+             "profile": "foil", "n0": 0.5, "x0": 3.2, "length": nx * dx, "u_th": 0.0,
+             "mobile": False, "fluid": False, "ionizable": True, "z_max": 2, "target": 0,
+             "ip_ev": HE_IP_EV},
+            dict(kind="positron", charge=1.0, mass=1.0, ppc=ppc, profile="none", n0=1.0,
+                 mobile=True, fluid=False, qed=True),
+            dict(kind="photon", charge=0.0, mass=0.0, ppc=0, profile="none", mobile=True,
+                 fluid=False, qed=True),
+        ],
+        "laser": {"enabled": True, "polarization": "circular", "a0": float(a0),
+                  "waist": 3 * TWO_PI, "duration": duration, "t_center": 2 * duration,
+                  "i_antenna": 2, "lambda_um": 0.8},
+        "run": _run(SEED_BASE + 5 if seed is None else seed, mode, enable_qed=True,
+                    enable_ionization=True, switch_every=10),
+        "steps": 500,
+    }
+
+
 PRESETS = {"plain_hybrid": plain_hybrid, "ionization_hybrid": ionization_hybrid,
-           "qed_hybrid": qed_hybrid}
+           "qed_hybrid": qed_hybrid, "full_foil": full_foil, "full_gas": full_gas}
 
 
 def with_mode(cfg, mode):

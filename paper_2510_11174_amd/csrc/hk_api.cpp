@@ -85,6 +85,7 @@ struct hk_sim {
     hipStream_t s = nullptr;
     real *fblock = nullptr;      // the 9 field arrays, contiguous
     real *f[9]{};
+    jglob_t *jg = nullptr;       // particle current of the step (3 arrays), zero between steps
     real *mur_old = nullptr;
     uint8_t *sw = nullptr, *calm = nullptr, *hot = nullptr, *notcold = nullptr;
     real *mom = nullptr;         // switch moments (7 grid arrays)
@@ -271,22 +272,27 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     HIPCHK(S, hipMemcpyAsync(h.data(), newcnt, sizeof(int) * nt, hipMemcpyDeviceToHost, S->s));
     HIPCHK(S, hipStreamSynchronize(S->s));
     // capacity: three times the larger of the tile's count and the species'
-    // mean count per tile, plus 256 slots, at least the reserve hint share;
-    // twice when the species is large (two buffers of three times 2^28
-    // particles take about a quarter of the 288 GB HBM).  Local density spikes (a laser
-    // snow-plough) then rarely overflow a bin; spare slots cost memory only,
-    // never traffic (kernels touch occupied slots).
+    // mean count per tile, plus 256 slots, at least the reserve hint share.
+    // A large species (over 2^26 particles, as in a 512 x 256 x 256 box with a
+    // dense target) takes twice its count and a floor of 1024 instead of the
+    // mean in tiles it barely fills, with an eighth of slack instead of a
+    // quarter: two buffers of 2^28 particles at three times would take a
+    // quarter of the 288 GB HBM, and the spare vacuum tiles most of it.  Local
+    // density spikes (a laser snow-plough) then rarely overflow a bin; spare
+    // slots cost memory only, never traffic (kernels touch occupied slots).
     long long hint_per_tile = D.reserve_hint > 0 ? (D.reserve_hint + nt - 1) / nt : 0;
     long long hsum = 0;
     for (int t = 0; t < nt; ++t) hsum += h[t];
     const long long mean = (hsum + nt - 1) / nt;
-    const long long factor = std::max(hsum, D.reserve_hint) > (1LL << 28) ? 2 : 3;
+    const bool large = std::max(hsum, D.reserve_hint) > (1LL << 26);
+    const long long factor = large ? 2 : 3;
+    const long long tfloor = large ? std::min<long long>(mean, 1024) : mean;
     std::vector<long long> off(nt), moff(nt);
     std::vector<int> cap(nt), mcap(nt);
     long long total = 0, mtotal = 0;
     int maxc = 0;
     for (int t = 0; t < nt; ++t) {
-        long long c = factor * std::max<long long>(h[t], mean) + 256;
+        long long c = factor * std::max<long long>(h[t], tfloor) + 256;
         long long hc = hint_per_tile + hint_per_tile / 4 + 128;
         c = std::max(c, std::min<long long>(hc, INT_MAX / 4));
         c = (c + 63) & ~63LL;
@@ -307,7 +313,7 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     const bool reuse = D.alloc_slots >= slots && D.buf[1 - D.cur].cell != nullptr;
     PArr nbuf[2];
     if (!reuse) {
-        const long long n_alloc = slots + slots / 4;
+        const long long n_alloc = slots + (large ? slots / 8 : slots / 4);
         if (!alloc_parr(S, nbuf[0], n_alloc, D.has_z, D.has_tau) ||
             !alloc_parr(S, nbuf[1], n_alloc, D.has_z, D.has_tau))
             return fail(S, HK_ENOMEM, "rebuild: %lld particle slots", n_alloc);
@@ -775,14 +781,14 @@ void reconcile(hk_sim *S) {
         SpecP P = specp(D);
         const WarmP W{D.fs, D.d.gamma_ad};
         if (D.capacity) {
-            launch_absorb_tiles(g, P, D.buf[D.cur], cur_bins(D), S->sw, S->f, S->macc, S->ledger, D.fs != nullptr,
-                                s);
+            launch_absorb_tiles(g, P, D.buf[D.cur], cur_bins(D), S->sw, S->jg, S->wmax + isp, S->macc, S->ledger,
+                                D.fs != nullptr, s);
             launch_absorb_finish_nodes(g, P.m, S->macc, D.fn, D.fu[0], D.fu[1], D.fu[2], W, S->ledger, s);
         }
         double dv = g.ddx * g.ddy * g.ddz;
         int m = std::max(1, D.d.ppc);
         real wmin = (real)(S->run.spawn_frac * D.d.n0 * dv / m);
-        launch_spawn_nodes(g, P, S->sw, D.fn, D.fu[0], D.fu[1], D.fu[2], W, S->f, wmin, m, S->run.seed,
+        launch_spawn_nodes(g, P, S->sw, D.fn, D.fu[0], D.fu[1], D.fu[2], W, S->jg, wmin, m, S->run.seed,
                            (int)S->step, D.inbox, S->status + 1 + 2 * isp, D.inbox_cap,
                            S->status + 13, S->wmax + isp, D.umax2, S->ledger, s);
     }
@@ -859,7 +865,7 @@ int one_step(hk_sim *S) {
             hipEvent_t pa = S->timing ? ev_get(S) : nullptr;
             launch_push_tiles(g, P, D.buf[D.cur], cur_bins(D), D.buf[nxt], D.nf[nxt], D.mig0, D.moff,
                               D.mcap, mcnt, D.inbox_dev, S->status + 1 + 2 * isp, D.inbox_cap, S->f,
-                              S->status, S->dstat, S->wmax + isp, D.umax2, mode, Q, S->plan,
+                              S->jg, S->status, S->dstat, S->wmax + isp, D.umax2, mode, Q, S->plan,
                               S->plan_ctl, D.capacity, s);
             if (S->timing) {
                 S->spans.push_back({pa, ev_get(S), 6});
@@ -905,6 +911,8 @@ int one_step(hk_sim *S) {
         if (rc) return rc;
         time_mark(S, 5);
     }
+    // the particles' current (deposits and conversion moves) joins J
+    launch_jconvert(g, S->jg, S->f, s);
     launch_yee_b_half(g, S->f, s);
     launch_yee_e_full(g, S->f, S->mur_old, s);
     launch_yee_b_half(g, S->f, s);
@@ -1175,6 +1183,7 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
     g.ddx = grid->dx; g.ddy = grid->dy; g.ddz = grid->dz; g.ddt = grid->dt;
     int rc = HK_OK;
     S->fblock = (real *)dalloc(S, sizeof(real) * 9 * (size_t)g.nn);
+    S->jg = (jglob_t *)dalloc(S, sizeof(jglob_t) * 3 * (size_t)g.nn);
     S->mur_old = (real *)dalloc(S, sizeof(real) * 8 * (size_t)g.ny * g.nz);
     S->sw = (uint8_t *)dalloc(S, (size_t)g.nn);
     S->calm = (uint8_t *)dalloc(S, (size_t)g.nn);
@@ -1194,7 +1203,7 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
         S->h_status = nullptr;
     if (hipEventCreateWithFlags(&S->status_ev, hipEventDisableTiming) != hipSuccess)
         S->status_ev = nullptr;
-    if (!S->fblock || !S->mur_old || !S->sw || !S->calm || !S->gauss0 || !S->tmp_a || !S->tmp_b ||
+    if (!S->fblock || !S->jg || !S->mur_old || !S->sw || !S->calm || !S->gauss0 || !S->tmp_a || !S->tmp_b ||
         !S->dsum || !S->ledger || !S->status || !S->h_status || !S->dstat || !S->wmax ||
         !S->plan || !S->plan_ctl || !S->status_ev) {
         hk_destroy(S);

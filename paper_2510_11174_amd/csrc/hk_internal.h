@@ -13,6 +13,20 @@ typedef float real;
 #define HK_REAL_BYTES 4
 #endif
 
+// Global accumulator of the current that particles deposit (push, absorption
+// and spawning moves), converted into J once per step before the field
+// update.  FP32 build: 64-bit fixed point with JG_BITS fractional bits, so
+// the integer sums are exact and the current does not depend on the order in
+// which workgroups add (two runs of the same input give the same bits; the
+// range is +-2^(63 - JG_BITS) = 32768 in units of n_c e c).  FP64 build: FP64
+// sums.
+#ifdef HK_DOUBLE
+typedef double jglob_t;
+#else
+typedef unsigned long long jglob_t;
+#endif
+#define JG_BITS 48
+
 // Particles are binned in cubic tiles of TILE^3 cells; one workgroup owns a tile.
 #define TILE 8
 #define TLOG 3
@@ -200,6 +214,8 @@ void launch_yee_e_full(const GridP &g, real *const f[9], real *mur_old, hipStrea
 void launch_antenna(const GridP &g, const hk_laser_desc &L, double t, real *jy, real *jz,
                     hipStream_t s);
 void launch_divE(const GridP &g, real *const f[9], double *out, hipStream_t s);
+// J += the particle current accumulated in jg (3 grid arrays); jg is left zero
+void launch_jconvert(const GridP &g, jglob_t *jg, real *const f[9], hipStream_t s);
 
 // particles (k_particles.hip): declared in hk_api.cpp where they are used
 
@@ -252,8 +268,8 @@ void launch_migrate(const GridP &g, const SpecP &sp, PArr mig, const long long *
                     PArr fail, int fail_cap, int *err, hipStream_t s);
 void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
                        int *nf_out, long long mig0, const long long *moff, const int *mcap, int *mcnt,
-                       const PArr *inbox_p, int *inbox_n, int inbox_cap, real *const f[9], int *err,
-                       unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
+                       const PArr *inbox_p, int *inbox_n, int inbox_cap, real *const f[9], jglob_t *jg,
+                       int *err, unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
                        int mode, const QedP &Q, int2 *items, int *ctl, long long capacity,
                        hipStream_t s);
 // Work plans of the per-tile particle kernels: items (tile, chunk) for grid g
@@ -284,11 +300,12 @@ void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, c
                          uint8_t *sw, uint8_t *calm, hipStream_t s);
 // macc: 5 grid arrays (FP64): absorbed weight, momentum (3), kinetic energy
 void launch_absorb_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, const uint8_t *sw,
-                         real *const f[9], double *macc, double *ledger, bool warm, hipStream_t s);
+                         jglob_t *jg, const unsigned *wmax_bits, double *macc, double *ledger, bool warm,
+                         hipStream_t s);
 void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n, real *ux,
                                 real *uy, real *uz, WarmP w, double *ledger, hipStream_t s);
 void launch_spawn_nodes(const GridP &g, const SpecP &sp, const uint8_t *sw, real *n, real *ux,
-                        real *uy, real *uz, WarmP w, real *const f[9], real wmin, int m, uint64_t seed,
+                        real *uy, real *uz, WarmP w, jglob_t *jg, real wmin, int m, uint64_t seed,
                         int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
                         unsigned *wmax_bits, unsigned *umax2, double *ledger, hipStream_t s);
 

@@ -138,10 +138,12 @@ __device__ inline void esirkepov_lds(real *sJ, int lx, int ly, int lz, const Axi
 // Current accumulator type of the LDS tile.  On gfx950 an LDS float atomic
 // add is serialized per lane (about 3 cycles per active lane) while a 64-bit
 // integer add costs a few cycles per wavefront, so the FP32 build deposits
-// the current in 64-bit fixed point: each workgroup picks a scale from its
-// largest |q w| so that one particle's largest contribution is 2^40 units;
-// integer sums are exact and independent of order.  The FP64 build keeps
-// FP64 atomics (it is the precision reference, not the fast path).
+// the current in 64-bit fixed point: the unit is a power of two 2^e chosen
+// per species (jdep_exp) so that one particle's largest contribution, from
+// the species' weight bound, is at most 2^30 units; integer sums are exact
+// and independent of order, and a tile's sums move to the global
+// accumulator (unit 2^-JG_BITS) by a left shift, exactly.  The FP64 build
+// keeps FP64 atomics (it is the precision reference, not the fast path).
 #ifdef HK_DOUBLE
 typedef double jacc_t;
 __device__ inline void jadd(jacc_t *p, real v, real) { atomicAdd(p, v); }
@@ -162,6 +164,17 @@ __device__ inline double jval(jacc_t v, double scale) { return (double)(long lon
 #endif
 constexpr float JFIX_UNITS = 1099511627776.0f;   // 2^40 (moment sums)
 
+// Exponent e of a species' deposit unit 2^e: the largest contribution jmax is
+// at most 2^(e + 30) units' worth; e >= -JG_BITS keeps the conversion to the
+// global unit a left shift.
+__device__ inline int jdep_exp(double jmax) {
+    if (!(jmax > 0.0)) return -JG_BITS;
+    int e;
+    const double m = frexp(jmax, &e);   // jmax = m 2^e, m in [0.5, 1): jmax <= 2^e
+    (void)m;
+    return max(e - 30, -JG_BITS);
+}
+
 // The push deposits in 32-bit units: one particle's largest current
 // contribution is 2^30 units, so every contribution converts with one FP32 ->
 // int32 rounding and is added to the 64-bit LDS sum (no overflow for any
@@ -175,6 +188,27 @@ __device__ inline void jput(jacc_t *p, real v) {
 __device__ inline void jput(jacc_t *p, real v) {   // v in units
     const int q = __float2int_rn(v);
     if (q) atomicAdd(p, (unsigned long long)(long long)q);
+}
+#endif
+
+// Tile sums and single contributions into the global accumulator.
+#ifdef HK_DOUBLE
+__device__ inline void jg_flush(jglob_t *p, jacc_t v, int) {
+    if (v != 0.0) atomicAdd(p, v);
+}
+__device__ inline void jg_put(jglob_t *p, double v) {
+    if (v != 0.0) atomicAdd(p, v);
+}
+#else
+// v: a tile sum in units 2^e; shift = e + JG_BITS >= 0 (two's complement:
+// the shifted bits are the signed product, modulo 2^64 like every sum here)
+__device__ inline void jg_flush(jglob_t *p, jacc_t v, int shift) {
+    if (v) atomicAdd(p, v << shift);
+}
+// one contribution in physical units, rounded once to the global unit
+__device__ inline void jg_put(jglob_t *p, double v) {
+    const long long q = __double2ll_rn(v * (double)(1ull << JG_BITS));
+    if (q) atomicAdd(p, (unsigned long long)q);
 }
 #endif
 

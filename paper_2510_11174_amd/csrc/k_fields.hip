@@ -207,6 +207,32 @@ void launch_antenna(const GridP &g, const hk_laser_desc &L, double t, real *jy, 
     k_antenna<<<blocks(g.ny * g.nz), BS, 0, s>>>(g, L, t, jy, jz);
 }
 
+// J += the particle current of this step (global accumulator jg, 3 arrays of
+// nn), which is cleared for the next step.  Only nodes with a deposit are
+// written.  FP32 build: one rounding of the exact fixed-point sum.
+__global__ void __launch_bounds__(BS)
+k_jconvert(GridP g, jglob_t *__restrict__ jg, real *__restrict__ Jx, real *__restrict__ Jy,
+           real *__restrict__ Jz) {
+    long long c = xcd_node();
+    if (c >= g.nn) return;
+    real *J[3] = {Jx, Jy, Jz};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const jglob_t v = jg[q * g.nn + c];
+        if (v == (jglob_t)0) continue;
+#ifdef HK_DOUBLE
+        J[q][c] += v;
+#else
+        J[q][c] += (real)((double)(long long)v * (1.0 / (double)(1ull << JG_BITS)));
+#endif
+        jg[q * g.nn + c] = 0;
+    }
+}
+
+void launch_jconvert(const GridP &g, jglob_t *jg, real *const f[9], hipStream_t s) {
+    k_jconvert<<<xcd_blocks(g.nn), BS, 0, s>>>(g, jg, f[HK_JX], f[HK_JY], f[HK_JZ]);
+}
+
 void launch_divE(const GridP &g, real *const f[9], double *out, hipStream_t s) {
     k_divE<<<blocks(g.nn), BS, 0, s>>>(g, f[HK_EX], f[HK_EY], f[HK_EZ], out);
 }

@@ -335,8 +335,8 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
        const long long *__restrict__ moff, const int *__restrict__ mcap, int *__restrict__ mcnt,
        const PArr *__restrict__ inbox_p, int *__restrict__ inbox_n, int inbox_cap, const real *__restrict__ Ex,
        const real *__restrict__ Ey, const real *__restrict__ Ez, const real *__restrict__ Bx,
-       const real *__restrict__ By, const real *__restrict__ Bz, real *__restrict__ Jx,
-       real *__restrict__ Jy, real *__restrict__ Jz, int *__restrict__ err,
+       const real *__restrict__ By, const real *__restrict__ Bz, jglob_t *__restrict__ Jx,
+       jglob_t *__restrict__ Jy, jglob_t *__restrict__ Jz, int *__restrict__ err,
        unsigned long long *__restrict__ stats, const unsigned *__restrict__ wmax_bits,
        unsigned *__restrict__ umax2, const int2 *__restrict__ items, const int *__restrict__ ctl, QedP Q) {
     __shared__ real sF[6 * FT3];
@@ -400,8 +400,11 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
                         (double)fmaxf(fmaxf((float)cdx, (float)cdy), (float)cdz);
 #ifdef HK_DOUBLE
     const double jscale = 1.0;   // FP64 sums, no scale
+    const int jshift = 0;
 #else
-    const double jscale = jmax > 0.0 ? jmax / (double)JDEP_UNITS : 1.0;
+    const int jexp = jdep_exp(jmax);
+    const double jscale = ldexp(1.0, jexp);   // deposit unit of this species
+    const int jshift = jexp + JG_BITS;        // tile sum -> global unit
 #endif
     const real qsc = (real)((double)sp.q / (double)dv / jscale);   // q / dV in units
     PLoad nx_ = pload(in, sp, bin_slot(sp, t, min(pbeg + (int)threadIdx.x, pend - 1), nfi, nbi),
@@ -666,7 +669,8 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
         if (item == 0) atomicAdd(&stats[1], 1ull);                     // tiles with particles
     }
     if (MODE == 2) return;
-    // flush the LDS current tile (nodes ox-1 .. ox+TILE+1) to HBM
+    // flush the LDS current tile (nodes ox-1 .. ox+TILE+1) to the global
+    // accumulator: exact integer adds in the FP32 build
     for (int e = threadIdx.x; e < JT3; e += PBS) {
         int a = e % JT, b = (e / JT) % JT, c = e / (JT * JT);
         int gi = ox - 1 + a;
@@ -675,11 +679,9 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
         if (per) { gi = wrapi(gi, g.nx); okx = okn = true; }
         else { okx = gi >= 0 && gi <= g.nx - 1; okn = gi >= 0 && gi <= g.nx; }
         long long c0 = gidx(g, gi < 0 ? 0 : gi, gj, gk);
-        real vx = (real)jval(sJ[e], jscale), vy = (real)jval(sJ[JT3 + e], jscale),
-             vz = (real)jval(sJ[2 * JT3 + e], jscale);
-        if (okx && vx != (real)0) atomicAdd(&Jx[c0], vx);
-        if (okn && vy != (real)0) atomicAdd(&Jy[c0], vy);
-        if (okn && vz != (real)0) atomicAdd(&Jz[c0], vz);
+        if (okx) jg_flush(&Jx[c0], sJ[e], jshift);
+        if (okn) jg_flush(&Jy[c0], sJ[JT3 + e], jshift);
+        if (okn) jg_flush(&Jz[c0], sJ[2 * JT3 + e], jshift);
     }
 }
 
@@ -960,12 +962,12 @@ void launch_tile_plan(const GridP &g, const SpecP &sp, Bins b, int cmin, int2 *i
 
 void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
                        int *nf_out, long long mig0, const long long *moff, const int *mcap, int *mcnt,
-                       const PArr *inbox_p, int *inbox_n, int inbox_cap, real *const f[9], int *err,
-                       unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
+                       const PArr *inbox_p, int *inbox_n, int inbox_cap, real *const f[9], jglob_t *jg,
+                       int *err, unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
                        int mode, const QedP &Q, int2 *items, int *ctl, long long capacity,
                        hipStream_t s) {
 #define HK_PUSH_ARGS g, sp, in, bin_in, dout, nf_out, mig0, moff, mcap, mcnt, inbox_p, inbox_n, inbox_cap, \
-        f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], f[HK_JX], f[HK_JY], f[HK_JZ], err, \
+        f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], jg, jg + g.nn, jg + 2 * g.nn, err, \
         stats, wmax_bits, umax2, items, ctl, Q
     // nf_out is the first of the next buffer's three counter arrays (front
     // fills, back fills, mover ranks), cleared by the planner

@@ -359,9 +359,10 @@ k_dilate(GridP g, SwitchP P, const uint8_t *__restrict__ hot, const uint8_t *__r
 }
 
 // --------------------------------------------------------------- conversion ---------------
-// Esirkepov current of a move, added straight to HBM (used by spawns).
-__device__ inline void esirkepov_global(const GridP &g, real *Jx, real *Jy, real *Jz, int ci, int cj,
-                                        int ck, const AxisS &X, const AxisS &Y, const AxisS &Z,
+// Esirkepov current of a move, added straight to the global accumulator
+// (used by spawns; each face value rounds once to the global unit).
+__device__ inline void esirkepov_global(const GridP &g, jglob_t *Jx, jglob_t *Jy, jglob_t *Jz, int ci,
+                                        int cj, int ck, const AxisS &X, const AxisS &Y, const AxisS &Z,
                                         real cx, real cy, real cz) {
     const real third = (real)(1.0 / 3.0), half = (real)0.5;
     const int per = g.bcx == HK_BC_PERIODIC;
@@ -378,21 +379,21 @@ __device__ inline void esirkepov_global(const GridP &g, real *Jx, real *Jy, real
                     for (int a2 = 0; a2 <= a; ++a2)
                         acc -= cx * (X.DS[a2] * (Y.S0[b] * Z.S0[c] + half * Y.DS[b] * Z.S0[c] +
                                                  half * Y.S0[b] * Z.DS[c] + third * Y.DS[b] * Z.DS[c]));
-                    if (acc != (real)0) atomicAdd(&Jx[q], acc);
+                    jg_put(&Jx[q], (double)acc);
                 }
                 if (b < 2 && okn) {
                     real acc = 0;
                     for (int b2 = 0; b2 <= b; ++b2)
                         acc -= cy * (Y.DS[b2] * (X.S0[a] * Z.S0[c] + half * X.DS[a] * Z.S0[c] +
                                                  half * X.S0[a] * Z.DS[c] + third * X.DS[a] * Z.DS[c]));
-                    if (acc != (real)0) atomicAdd(&Jy[q], acc);
+                    jg_put(&Jy[q], (double)acc);
                 }
                 if (c < 2 && okn) {
                     real acc = 0;
                     for (int c2 = 0; c2 <= c; ++c2)
                         acc -= cz * (Z.DS[c2] * (X.S0[a] * Y.S0[b] + half * X.DS[a] * Y.S0[b] +
                                                  half * X.S0[a] * Y.DS[b] + third * X.DS[a] * Y.DS[b]));
-                    if (acc != (real)0) atomicAdd(&Jz[q], acc);
+                    jg_put(&Jz[q], (double)acc);
                 }
             }
 }
@@ -415,9 +416,10 @@ __device__ inline void block_add_d(double v, double *out) {
 // instead of going to the ledger).
 __global__ void __launch_bounds__(BS)
 k_absorb(GridP g, SpecP sp, PArr a, Bins bins, const uint8_t *__restrict__ sw,
-         real *__restrict__ Jx, real *__restrict__ Jy, real *__restrict__ Jz, double *__restrict__ macc,
+         jglob_t *__restrict__ Jx, jglob_t *__restrict__ Jy, jglob_t *__restrict__ Jz,
+         const unsigned *__restrict__ wmax_bits, double *__restrict__ macc,
          double *__restrict__ ledger, int warm) {
-    __shared__ real sJ[3 * JT3];
+    __shared__ jacc_t sJ[3 * JT3];
     __shared__ int any;
     const int t = blockIdx.x;
     int nf, nbv;
@@ -441,6 +443,20 @@ k_absorb(GridP g, SpecP sp, PArr a, Bins bins, const uint8_t *__restrict__ sw,
     __syncthreads();
     const real dv = g.dx * g.dy * g.dz;
     const long long nn = g.nn;
+    // the push's fixed-point deposit: a virtual move to the nearest node is at
+    // most half a cell per axis, so the push's per-species unit bounds it too
+    const real cdx = g.dx / g.dt, cdy = g.dy / g.dt, cdz = g.dz / g.dt;
+    const double jmax = (double)fabsf((float)sp.q) * (double)__uint_as_float(*wmax_bits) / (double)dv *
+                        (double)fmaxf(fmaxf((float)cdx, (float)cdy), (float)cdz);
+#ifdef HK_DOUBLE
+    const double jscale = 1.0;
+    const int jshift = 0;
+#else
+    const int jexp = jdep_exp(jmax);
+    const double jscale = ldexp(1.0, jexp);
+    const int jshift = jexp + JG_BITS;
+#endif
+    const real qsc = (real)((double)sp.q / (double)dv / jscale);
     double ke = 0;
     for (int p = threadIdx.x; p < n; p += BS) {
         const long long ip = bin_slot(sp, t, p, nf, nbv);
@@ -456,8 +472,8 @@ k_absorb(GridP g, SpecP sp, PArr a, Bins bins, const uint8_t *__restrict__ sw,
         if ((unsigned)lx >= TILE || (unsigned)ly >= TILE || (unsigned)lz >= TILE) continue;
         const real w = a.w[ip];
         AxisS SX = axis_shapes(rx, (real)di), SY = axis_shapes(ry, (real)dj), SZ = axis_shapes(rz, (real)dk);
-        real qw = sp.q * w / dv;
-        esirkepov_lds(sJ, lx, ly, lz, SX, SY, SZ, qw * g.dx / g.dt, qw * g.dy / g.dt, qw * g.dz / g.dt);
+        const real qws = qsc * w;
+        esirkepov_acc(sJ, lx, ly, lz, SX, SY, SZ, qws * cdx, qws * cdy, qws * cdz);
         any = 1;
         double ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip];
         const double kp = (double)w * (double)sp.m * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
@@ -479,10 +495,9 @@ k_absorb(GridP g, SpecP sp, PArr a, Bins bins, const uint8_t *__restrict__ sw,
         if (per) { gi = wrapi(gi, g.nx); okx = okn = true; }
         else { okx = gi >= 0 && gi <= g.nx - 1; okn = gi >= 0 && gi <= g.nx; }
         long long c0 = gidx(g, gi < 0 ? 0 : gi, gj, gk);
-        real vx = sJ[e], vy = sJ[JT3 + e], vz = sJ[2 * JT3 + e];
-        if (okx && vx != (real)0) atomicAdd(&Jx[c0], vx);
-        if (okn && vy != (real)0) atomicAdd(&Jy[c0], vy);
-        if (okn && vz != (real)0) atomicAdd(&Jz[c0], vz);
+        if (okx) jg_flush(&Jx[c0], sJ[e], jshift);
+        if (okn) jg_flush(&Jy[c0], sJ[JT3 + e], jshift);
+        if (okn) jg_flush(&Jz[c0], sJ[2 * JT3 + e], jshift);
     }
 }
 
@@ -532,8 +547,8 @@ k_absorb_finish(GridP g, real mass, double *__restrict__ macc, real *__restrict_
 // minus the sample's kinetic energy.
 __global__ void __launch_bounds__(BS)
 k_spawn(GridP g, SpecP sp, const uint8_t *__restrict__ sw, real *__restrict__ n, real *__restrict__ ux,
-        real *__restrict__ uy, real *__restrict__ uz, WarmP wp, real *__restrict__ Jx, real *__restrict__ Jy,
-        real *__restrict__ Jz, real wmin, int m, uint64_t seed, int step, PArr inbox,
+        real *__restrict__ uy, real *__restrict__ uz, WarmP wp, jglob_t *__restrict__ Jx,
+        jglob_t *__restrict__ Jy, jglob_t *__restrict__ Jz, real wmin, int m, uint64_t seed, int step, PArr inbox,
         int *__restrict__ inbox_n, int inbox_cap, int *__restrict__ deferred,
         unsigned *__restrict__ wmax_bits, unsigned *__restrict__ umax2, double *__restrict__ ledger) {
     long long c = (long long)blockIdx.x * BS + threadIdx.x;
@@ -651,18 +666,20 @@ void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, c
     k_dilate<<<xcd_blocks(g.nn), BS, 0, s>>>(g, P, hot, notcold, sw, calm);
 }
 void launch_absorb_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, const uint8_t *sw,
-                         real *const f[9], double *macc, double *ledger, bool warm, hipStream_t s) {
-    k_absorb<<<g.ntiles, BS, 0, s>>>(g, sp, a, b, sw, f[HK_JX], f[HK_JY], f[HK_JZ], macc, ledger, warm ? 1 : 0);
+                         jglob_t *jg, const unsigned *wmax_bits, double *macc, double *ledger, bool warm,
+                         hipStream_t s) {
+    k_absorb<<<g.ntiles, BS, 0, s>>>(g, sp, a, b, sw, jg, jg + g.nn, jg + 2 * g.nn, wmax_bits, macc, ledger,
+                                     warm ? 1 : 0);
 }
 void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n, real *ux,
                                 real *uy, real *uz, WarmP w, double *ledger, hipStream_t s) {
     k_absorb_finish<<<blocks(g.nn), BS, 0, s>>>(g, mass, macc, n, ux, uy, uz, w, ledger);
 }
 void launch_spawn_nodes(const GridP &g, const SpecP &sp, const uint8_t *sw, real *n, real *ux,
-                        real *uy, real *uz, WarmP w, real *const f[9], real wmin, int m, uint64_t seed,
+                        real *uy, real *uz, WarmP w, jglob_t *jg, real wmin, int m, uint64_t seed,
                         int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
                         unsigned *wmax_bits, unsigned *umax2, double *ledger, hipStream_t s) {
-    k_spawn<<<blocks(g.nn), BS, 0, s>>>(g, sp, sw, n, ux, uy, uz, w, f[HK_JX], f[HK_JY], f[HK_JZ], wmin,
+    k_spawn<<<blocks(g.nn), BS, 0, s>>>(g, sp, sw, n, ux, uy, uz, w, jg, jg + g.nn, jg + 2 * g.nn, wmin,
                                         m, seed, step, inbox, inbox_n, inbox_cap, deferred, wmax_bits, umax2,
                                         ledger);
 }
