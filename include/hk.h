@@ -128,7 +128,11 @@ typedef void (*hk_free_fn)(void *ptr, void *ctx);
  * estimated quantum parameter >= thr_chi.  `dilation` widens the kinetic
  * region by that many nodes; a kinetic node returns to fluid after
  * `hysteresis` calm evaluations.  Fluid below n_floor has no velocity.
- * Fluid mass >= spawn_frac * n0 dV / ppc on a kinetic node becomes particles. */
+ * Fluid mass M >= spawn_frac * w0 on a kinetic node, w0 = n0 dV / ppc the
+ * species' reference weight, becomes round(M / w0) particles (1 to 64).
+ * A particle with |u| >= thr_hot (thr_hot > 0) is hot: a kinetic population
+ * wherever it is, never absorbed into a fluid node and left out of the
+ * switch moments (thr_hot <= 0: no particle is hot). */
 typedef struct {
     uint64_t seed;
     int32_t switch_mode, switch_every;
@@ -137,6 +141,7 @@ typedef struct {
     double thr_a, thr_grad, thr_sigma_u, thr_ion, thr_chi;
     double n_floor;
     double spawn_frac;
+    double thr_hot;
     void *stream;          /* hipStream_t or NULL */
     hk_alloc_fn alloc;     /* optional device allocator */
     hk_free_fn free;

@@ -75,7 +75,7 @@ class Run(C.Structure):
                 ("enable_ionization", C.c_int32), ("enable_qed", C.c_int32),
                 ("thr_a", C.c_double), ("thr_grad", C.c_double), ("thr_sigma_u", C.c_double),
                 ("thr_ion", C.c_double), ("thr_chi", C.c_double), ("n_floor", C.c_double),
-                ("spawn_frac", C.c_double)]
+                ("spawn_frac", C.c_double), ("thr_hot", C.c_double)]
 
 
 class Diag(C.Structure):
@@ -211,7 +211,7 @@ def structs(cfg: dict):
               thr_a=r.get("thr_a", 0.5), thr_grad=r.get("thr_grad", 0.2),
               thr_sigma_u=r.get("thr_sigma_u", 0.05), thr_ion=r.get("thr_ion", 1e-6),
               thr_chi=r.get("thr_chi", 1e-3), n_floor=r.get("n_floor", 1e-10),
-              spawn_frac=r.get("spawn_frac", 0.5))
+              spawn_frac=r.get("spawn_frac", 0.5), thr_hot=r.get("thr_hot", 0.0))
     return grid, sps, len(cfg["species"]), laser, run
 
 

@@ -99,7 +99,9 @@ void or_reflect_x(const or_sim *s, int ci, double *X, double *ux);
 void or_fluid_phase(or_sim *s);
 /* switch.c */
 void or_switch_eval(or_sim *s);
-void or_reconcile(or_sim *s);
+void or_absorb(or_sim *s);
+void or_spawn_fluid(or_sim *s);
+int or_is_hot(const or_sim *s, const double u[3]);
 /* ionize.c */
 double or_lambda_field_unit(double lambda_um);
 double or_lambda_omega_au(double lambda_um);

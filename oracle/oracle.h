@@ -68,6 +68,7 @@ typedef struct {
     double thr_a, thr_grad, thr_sigma_u, thr_ion, thr_chi;
     double n_floor;      /* fluid density floor (n_c) */
     double spawn_frac;   /* spawn fluid mass >= spawn_frac * n0 dV / ppc */
+    double thr_hot;      /* |u| >= thr_hot: never absorbed, not in the switch moments (<= 0: none) */
 } or_run;
 
 typedef struct {

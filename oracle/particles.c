@@ -60,8 +60,12 @@ static double profile(const or_species *sp, double x) {
 }
 
 /* ppc particles per cell whose centre has n > 0.  Particle k of cell c has
- * id c*ppc + k; its position offsets are Philox draws (tag 1) and its momentum
- * components Gaussian draws by Box-Muller (tag 2).  Weight n dV / ppc. */
+ * position index c*ppc + k and id (species << 52) | (c*ppc + k), unique over
+ * the species.  Its position offsets are Philox draws (tag 1) keyed by the
+ * position index, so the species of one cell start at the same points (a
+ * neutral plasma starts without charge separation); its momentum components
+ * are Gaussian draws by Box-Muller (tag 2) keyed by the id, independent from
+ * species to species.  Weight n dV / ppc. */
 void or_init_species(or_sim *s, int isp) {
     const or_species *sp = &s->sp[isp];
     const or_grid *g = &s->g;
@@ -75,9 +79,10 @@ void or_init_species(or_sim *s, int isp) {
                 if (n <= 0) continue;
                 uint64_t cell = (uint64_t)i + (uint64_t)g->nx * ((uint64_t)j + (uint64_t)g->ny * k);
                 for (int q = 0; q < sp->ppc; ++q) {
-                    uint64_t id = cell * (uint64_t)sp->ppc + (uint64_t)q;
+                    uint64_t pos = cell * (uint64_t)sp->ppc + (uint64_t)q;
+                    uint64_t id = ((uint64_t)isp << 52) | pos;
                     uint32_t rp[4], rm[4];
-                    or_draw4(s, id, 0, 1, 0, rp);
+                    or_draw4(s, pos, 0, 1, 0, rp);
                     or_draw4(s, id, 0, 2, 0, rm);
                     double r0 = or_uniform(rm[0]), r1 = or_uniform(rm[1]);
                     double r2 = or_uniform(rm[2]), r3 = or_uniform(rm[3]);
@@ -322,7 +327,10 @@ void or_particle_phase(or_sim *s) {
             }
             if (sp->kind == OR_ION && sp->ionizable && s->run.enable_ionization && kinetic)
                 or_ionize_particle(s, isp, n, sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]));
-            if (sp->kind != OR_ION && sp->qed && s->run.enable_qed && kinetic)
+            /* every lepton particle radiates: in a fluid node it is a hot
+             * particle the conversion keeps, or one the conversion takes at
+             * the end of this step */
+            if (sp->kind != OR_ION && sp->qed && s->run.enable_qed)
                 or_qed_emit(s, isp, n, e, b);
             if (!sp->mobile) continue;
             double q = sp->kind == OR_ION ? (double)p->zc[n] : sp->charge;

@@ -14,8 +14,10 @@
  *   3. particles: gather, ionization, photon emission, Boris, move, deposit;
  *   4. photons: pair creation, ballistic push; the particles born in 3 and 4
  *      then join their species (they move from the next step on);
- *   5. cold fluid update (adds its face current to J);
- *   6. conversion between fluid and particles (adds its current to J);
+ *   5. fluid update (adds its face current to J);
+ *   6. conversion: particles of fluid-capable species whose nearest node is
+ *      fluid (and which are not hot) join the node fluid, then fluid mass on
+ *      kinetic nodes becomes particles (both add their moves' current to J);
  *   7. B^{n+1/2} = B^n - dt/2 curl E^n; E^{n+1} = E^n + dt (curl B - J)
  *      with Mur walls; B^{n+1} = B^{n+1/2} - dt/2 curl E^{n+1}.
  */
@@ -91,7 +93,8 @@ int or_step(or_sim *s, int nsteps) {
         or_spawn_flush(s);   /* particles born this step move from the next one */
         if (mode != OR_SW_ALL_PIC) {
             or_fluid_phase(s);
-            or_reconcile(s);
+            or_absorb(s);
+            or_spawn_fluid(s);
         }
         or_yee_b_half(s);
         or_yee_e_full(s);

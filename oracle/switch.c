@@ -23,13 +23,22 @@
  *  `hysteresis` consecutive evaluations with every indicator below half its
  *  threshold in the dilated neighbourhood.
  *
- *  conversion (after the fluid update of every step):
- *    absorb: a particle of a fluid-capable species whose nearest node is fluid
- *      is moved virtually to that node (Esirkepov current of the move) and
- *      its weight and momentum join the node fluid;
- *    spawn: fluid mass M = n dV >= spawn_frac * n0 dV / ppc on a kinetic node
- *      becomes ppc particles of weight M/ppc with the fluid momentum, moved
- *      virtually from the node to Philox positions in the node's dual cell.
+ *  hot particles: a particle with |u| >= thr_hot (when thr_hot > 0) is a
+ *  kinetic population wherever it is: it is never absorbed and does not enter
+ *  the switch moments, so a hot beam crossing a cold bulk leaves the bulk
+ *  fluid (the bulk's own state decides its regime).
+ *
+ *  conversion (after the fluid update of every hybrid step):
+ *    absorb: a particle of a fluid-capable species whose nearest node is
+ *      fluid, and which is not hot, is moved virtually to that node
+ *      (Esirkepov current of the move) and its weight and momentum join the
+ *      node fluid, at one time level (x^{n+1}, u^{n+1/2} with n^{n+1},
+ *      u^{n+1/2});
+ *    spawn: fluid mass M = n dV >= spawn_frac * w0 on
+ *      a kinetic node, w0 = n0 dV / ppc the species' reference weight, becomes
+ *      m = round(M / w0) particles (at least 1, at most 64) of weight M/m with
+ *      the fluid momentum, moved virtually from the node to Philox positions
+ *      in the node's dual cell.
  *  A CIC particle sitting on a node has exactly the node-delta charge of the
  *  fluid, so both conversions keep div E - rho unchanged.
  *  Warm fluid (gamma_ad > 0): the kinetic energy an absorption loses (the
@@ -41,6 +50,10 @@
  *  fluid momentum plus a Gaussian spread sqrt(T / m) per component, T = p / n
  *  (Box-Muller on Philox draws, tag 13), and the ledger takes the difference
  *  between the fluid's kinetic plus thermal energy and the sample's.
+ *  A spawned particle's id is 2^63 | step << 40 | species << 37 | node << 6 |
+ *  slot; its position draws (tag 12) are keyed by (node, step, slot), shared
+ *  by the species spawned on one node (a neutral fluid spawns neutral), its
+ *  thermal draws by its id.
  */
 #include "or_internal.h"
 
@@ -62,6 +75,12 @@ static size_t nearest(const or_sim *s, const or_parts *p, size_t n, int *rel) {
                   or_wrap(p->ck[n] + r[2], s->g.nz));
 }
 
+/* A hot particle (|u| >= thr_hot, thr_hot > 0). */
+int or_is_hot(const or_sim *s, const double u[3]) {
+    double h = s->run.thr_hot;
+    return h > 0.0 && u[0] * u[0] + u[1] * u[1] + u[2] * u[2] >= h * h;
+}
+
 extern double or_cnn_switch(or_sim *s, const double *nmom, const double *u2mom,
                             uint8_t *hot, uint8_t *cold);
 
@@ -80,8 +99,9 @@ void or_switch_eval(or_sim *s) {
         const or_parts *p = &s->p[isp];
         if (sp->fluid) {
             for (size_t n = 0; n < p->n; ++n) {
-                size_t c = nearest(s, p, n, NULL);
                 double u[3] = {p->ux[n], p->uy[n], p->uz[n]};
+                if (or_is_hot(s, u)) continue;
+                size_t c = nearest(s, p, n, NULL);
                 N[c] += p->w[n];
                 V[c] += p->w[n] * p->w[n];
                 for (int d = 0; d < 3; ++d) P[3 * c + d] += p->w[n] * u[d];
@@ -181,11 +201,10 @@ void or_switch_eval(or_sim *s) {
     free(N); free(P); free(U2); free(NI); free(V); free(hot); free(notcold);
 }
 
-/* Conversion between the two representations (see the header comment). */
-void or_reconcile(or_sim *s) {
+/* Absorption part of the conversion (see the header comment). */
+void or_absorb(or_sim *s) {
     const or_grid *g = &s->g;
     double dv = g->dx * g->dy * g->dz;
-    int nxn = node_x_count(s);
     for (int isp = 0; isp < s->nsp; ++isp) {
         const or_species *sp = &s->sp[isp];
         if (!sp->fluid || !s->fn[isp]) continue;
@@ -202,7 +221,8 @@ void or_reconcile(or_sim *s) {
         for (size_t q = 0; q < p->n; ++q) {
             int rel[3];
             size_t c = nearest(s, p, q, rel);
-            if (s->sw[c]) {
+            double uq[3] = {p->ux[q], p->uy[q], p->uz[q]};
+            if (s->sw[c] || or_is_hot(s, uq)) {
                 if (keep != q) {
                     p->ci[keep] = p->ci[q]; p->cj[keep] = p->cj[q]; p->ck[keep] = p->ck[q];
                     p->ox[keep] = p->ox[q]; p->oy[keep] = p->oy[q]; p->oz[keep] = p->oz[q];
@@ -253,9 +273,25 @@ void or_reconcile(or_sim *s) {
             n[c] = mt / dv;
             for (int d = 0; d < 3; ++d) s->fu[isp][d][c] = un[d];
         }
+        free(M); free(Pm); free(KEa); free(touched);
+    }
+}
+
+/* Spawning part of the conversion (see the header comment), after the fluid update. */
+void or_spawn_fluid(or_sim *s) {
+    const or_grid *g = &s->g;
+    double dv = g->dx * g->dy * g->dz;
+    int nxn = node_x_count(s);
+    for (int isp = 0; isp < s->nsp; ++isp) {
+        const or_species *sp = &s->sp[isp];
+        if (!sp->fluid || !s->fn[isp]) continue;
+        or_parts *p = &s->p[isp];
+        double *n = s->fn[isp];
+        double *S = s->fs[isp];
+        const double ga = sp->gamma_ad;
         /* spawn, in node order */
-        double wmin = s->run.spawn_frac * sp->n0 * dv / (sp->ppc > 0 ? sp->ppc : 1);
-        int m = sp->ppc > 0 ? sp->ppc : 1;
+        double w0 = sp->n0 * dv / (sp->ppc > 0 ? sp->ppc : 1);
+        double wmin = s->run.spawn_frac * w0;
         for (int k = 0; k < g->nz; ++k)
             for (int j = 0; j < g->ny; ++j)
                 for (int i = 0; i < nxn; ++i) {
@@ -263,6 +299,8 @@ void or_reconcile(or_sim *s) {
                     if (!s->sw[c] || n[c] <= 0.0) continue;
                     double mass = n[c] * dv;
                     if (mass < wmin) continue;
+                    double mr = w0 > 0.0 ? floor(mass / w0 + 0.5) : 1.0;
+                    int m = mr < 1.0 ? 1 : (mr > 64.0 ? 64 : (int)mr);
                     double w = mass / m;
                     double u[3] = {s->fu[isp][0][c], s->fu[isp][1][c], s->fu[isp][2][c]};
                     /* warm fluid: thermal spread sqrt(T / m) per component, T = p / n */
@@ -283,10 +321,12 @@ void or_reconcile(or_sim *s) {
                         double X1[3] = {or_uniform(r[0]) - 0.5, or_uniform(r[1]) - 0.5,
                                         or_uniform(r[2]) - 0.5};
                         double uq[3] = {u[0], u[1], u[2]};
+                        uint64_t id = (1ull << 63) | ((uint64_t)s->step << 40) | ((uint64_t)isp << 37) |
+                                      (node << 6) | (uint64_t)q;
                         if (S) {
                             /* Box-Muller on Philox draws, tag 13 */
                             uint32_t t[4];
-                            or_draw4(s, node, (uint32_t)s->step, 13, (uint32_t)q, t);
+                            or_draw4(s, id, (uint32_t)s->step, 13, 0, t);
                             double r0 = or_uniform(t[0]), r1 = or_uniform(t[1]), r2 = or_uniform(t[2]),
                                    r3 = or_uniform(t[3]);
                             double m0 = sqrt(-2.0 * log(r0)), m1 = sqrt(-2.0 * log(r2));
@@ -300,7 +340,6 @@ void or_reconcile(or_sim *s) {
                         or_reflect_x(s, i, &X1[0], &ux);
                         or_deposit_move(s, sp->charge, w, cell, X0, X1);
                         or_carry(s, cell, X1);
-                        uint64_t id = (1ull << 63) | ((uint64_t)s->step << 40) | (node << 6) | (uint64_t)q;
                         or_parts_push_back(p, cell[0], cell[1], cell[2], X1[0], X1[1], X1[2],
                                            uq[0], uq[1], uq[2], w, sp->qed ? or_qed_tau0(s, id) : 0.0, id,
                                            (int32_t)llround(sp->charge));
@@ -312,6 +351,5 @@ void or_reconcile(or_sim *s) {
                     n[c] = 0.0;
                     s->fu[isp][0][c] = s->fu[isp][1][c] = s->fu[isp][2][c] = 0.0;
                 }
-        free(M); free(Pm); free(KEa); free(touched);
     }
 }

@@ -58,6 +58,7 @@ struct DevSpecies {
     real *fn = nullptr, *fu[3] = {nullptr, nullptr, nullptr};  // fluid density and momentum
     real *fs = nullptr;           // warm fluid: entropy density n K, K = p / n^gamma_ad
     real *fn2 = nullptr, *fs2 = nullptr;   // the fluid pass writes n and S here, then swaps
+    double *macc = nullptr;       // particles the push absorbed into the fluid this step (5 grid arrays)
     IonP *ion = nullptr;          // device rate constants
     long long reserve_hint = 0;   // expected peak count (ionization targets)
     unsigned *umax2 = nullptr;    // device [ntiles]: bound on |u|^2 (float bits) since the
@@ -89,7 +90,8 @@ struct hk_sim {
     real *mur_old = nullptr;
     uint8_t *sw = nullptr, *calm = nullptr, *hot = nullptr, *notcold = nullptr;
     real *mom = nullptr;         // switch moments (7 grid arrays)
-    double *macc = nullptr;      // absorbed mass, momentum and kinetic energy (5 grid arrays)
+    int *spawn_list = nullptr;   // nodes that spawn this step (one species at a time)
+    int *spawn_n = nullptr;      // their count
     real *fluid_scratch = nullptr;
     double *gauss0 = nullptr, *tmp_a = nullptr, *tmp_b = nullptr;
     double *dsum = nullptr;      // diagnostic accumulators
@@ -518,7 +520,7 @@ int init_species(hk_sim *S, int isp) {
         if (!dx || !dw) return fail(S, HK_ENOMEM, "init columns");
         HIPCHK(S, hipMemcpyAsync(dx, xcol.data(), sizeof(int) * xcol.size(), hipMemcpyHostToDevice, S->s));
         HIPCHK(S, hipMemcpyAsync(dw, wcol.data(), sizeof(double) * wcol.size(), hipMemcpyHostToDevice, S->s));
-        launch_init_species_cols(g, d, S->run.seed, D.inbox, dx, dw, (int)xcol.size(), D.has_z,
+        launch_init_species_cols(g, d, isp, S->run.seed, D.inbox, dx, dw, (int)xcol.size(), D.has_z,
                                  D.has_tau, S->s);
         int n32 = (int)total;
         HIPCHK(S, hipMemcpyAsync(S->status + 1 + 2 * isp, &n32, sizeof(int), hipMemcpyHostToDevice, S->s));
@@ -717,6 +719,11 @@ void cnn_switch(hk_sim *S) {
     S->cnn_evals++;
 }
 
+// Square of the hot-particle threshold (0: no particle is hot).
+real hot2(const hk_sim *S) {
+    return S->run.thr_hot > 0.0 ? (real)(S->run.thr_hot * S->run.thr_hot) : (real)0;
+}
+
 // Threshold criterion: nearest-node moments, indicators, dilation, hysteresis.
 // Switch moments of every fluid species (particles and fluid) and of the
 // ionizable ions.  use_bounds: particle moments take their fixed-point scale
@@ -740,11 +747,11 @@ int switch_moments(hk_sim *S, bool use_bounds, const IonP **ions) {
         DevSpecies &D = S->sp[isp];
         SpecP P = specp(D);
         if (D.d.fluid && D.capacity)
-            launch_moments_tiles(g, P, D.buf[D.cur], cur_bins(D), 0, 0, S->mom, S->wmax + isp,
+            launch_moments_tiles(g, P, D.buf[D.cur], cur_bins(D), 0, 0, hot2(S), S->mom, S->wmax + isp,
                                  use_bounds && D.d.mobile && D.umax_ok ? D.umax2 : nullptr, nullptr,
                                  S->plan, S->plan_ctl, D.capacity, s);
         if (D.d.ionizable && S->run.enable_ionization && D.capacity) {
-            launch_moments_tiles(g, P, D.buf[D.cur], cur_bins(D), 1, D.d.z_max, S->mom, S->wmax + isp,
+            launch_moments_tiles(g, P, D.buf[D.cur], cur_bins(D), 1, D.d.z_max, (real)0, S->mom, S->wmax + isp,
                                  nullptr, D.d.mobile ? nullptr : D.active, S->plan, S->plan_ctl,
                                  D.capacity, s);
             if (nion < 4) ions[nion++] = D.ion;
@@ -780,17 +787,16 @@ void reconcile(hk_sim *S) {
         if (!D.d.fluid || !D.fn) continue;
         SpecP P = specp(D);
         const WarmP W{D.fs, D.d.gamma_ad};
-        if (D.capacity) {
-            launch_absorb_tiles(g, P, D.buf[D.cur], cur_bins(D), S->sw, S->jg, S->wmax + isp, S->macc, S->ledger,
-                                D.fs != nullptr, s);
-            launch_absorb_finish_nodes(g, P.m, S->macc, D.fn, D.fu[0], D.fu[1], D.fu[2], W, S->ledger, s);
-        }
+        // particles the push absorbed join the node fluid
+        if (D.capacity)
+            launch_absorb_finish_nodes(g, P.m, D.macc, D.fn, D.fu[0], D.fu[1], D.fu[2], W, S->ledger, s);
         double dv = g.ddx * g.ddy * g.ddz;
-        int m = std::max(1, D.d.ppc);
-        real wmin = (real)(S->run.spawn_frac * D.d.n0 * dv / m);
-        launch_spawn_nodes(g, P, S->sw, D.fn, D.fu[0], D.fu[1], D.fu[2], W, S->jg, wmin, m, S->run.seed,
-                           (int)S->step, D.inbox, S->status + 1 + 2 * isp, D.inbox_cap,
-                           S->status + 13, S->wmax + isp, D.umax2, S->ledger, s);
+        const double w0 = D.d.n0 * dv / std::max(1, D.d.ppc);
+        real wmin = (real)(S->run.spawn_frac * w0);
+        launch_zero(S->spawn_n, sizeof(int), s);
+        launch_spawn_nodes(g, P, isp, S->sw, D.fn, D.fu[0], D.fu[1], D.fu[2], W, S->jg, wmin, (real)w0,
+                           S->run.seed, (int)S->step, D.inbox, S->status + 1 + 2 * isp, D.inbox_cap,
+                           S->status + 13, S->wmax + isp, D.umax2, S->ledger, S->spawn_list, S->spawn_n, s);
     }
 }
 
@@ -862,10 +868,19 @@ int one_step(hk_sim *S) {
             // share a dense tile
             int *mcnt = D.nf[nxt] + 2 * g.ntiles;
             QedP Q = qed_params(S, mode);
+            AbsorbP A{};
+            if (hybrid && D.d.fluid && D.fn && D.macc && mode != 2) {
+                A.on = 1;
+                A.sw = S->sw;
+                A.macc = D.macc;
+                A.ledger = S->ledger;
+                A.hot2 = hot2(S);
+                A.warm = D.fs != nullptr;
+            }
             hipEvent_t pa = S->timing ? ev_get(S) : nullptr;
             launch_push_tiles(g, P, D.buf[D.cur], cur_bins(D), D.buf[nxt], D.nf[nxt], D.mig0, D.moff,
                               D.mcap, mcnt, D.inbox_dev, S->status + 1 + 2 * isp, D.inbox_cap, S->f,
-                              S->jg, S->status, S->dstat, S->wmax + isp, D.umax2, mode, Q, S->plan,
+                              S->jg, S->status, S->dstat, S->wmax + isp, D.umax2, mode, Q, A, S->plan,
                               S->plan_ctl, D.capacity, s);
             if (S->timing) {
                 S->spans.push_back({pa, ev_get(S), 6});
@@ -930,11 +945,12 @@ int ensure_fluid(hk_sim *S) {
     const GridP &g = S->g;
     if (!S->mom) {
         S->mom = (real *)dalloc(S, sizeof(real) * 7 * (size_t)g.nn);
-        S->macc = (double *)dalloc(S, sizeof(double) * 5 * (size_t)g.nn);
+        S->spawn_list = (int *)dalloc(S, sizeof(int) * (size_t)g.nn, false);
+        S->spawn_n = (int *)dalloc(S, sizeof(int) * 8);
         S->hot = (uint8_t *)dalloc(S, (size_t)g.nn);
         S->notcold = (uint8_t *)dalloc(S, (size_t)g.nn);
         S->fluid_scratch = (real *)dalloc(S, sizeof(real) * 7 * (size_t)g.nn);
-        if (!S->mom || !S->macc || !S->hot || !S->notcold || !S->fluid_scratch)
+        if (!S->mom || !S->spawn_list || !S->spawn_n || !S->hot || !S->notcold || !S->fluid_scratch)
             return fail(S, HK_ENOMEM, "switch arrays");
     }
     for (int isp = 0; isp < S->nsp; ++isp) {
@@ -943,11 +959,13 @@ int ensure_fluid(hk_sim *S) {
         D.fn = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
         D.fn2 = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
         for (int d = 0; d < 3; ++d) D.fu[d] = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
+        D.macc = (double *)dalloc(S, sizeof(double) * 5 * (size_t)g.nn);
         if (D.d.gamma_ad > 0.0) {
             D.fs = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
             D.fs2 = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
         }
-        if (!D.fn || !D.fn2 || !D.fu[0] || !D.fu[1] || !D.fu[2] || (D.d.gamma_ad > 0.0 && (!D.fs || !D.fs2)))
+        if (!D.fn || !D.fn2 || !D.fu[0] || !D.fu[1] || !D.fu[2] || !D.macc ||
+            (D.d.gamma_ad > 0.0 && (!D.fs || !D.fs2)))
             return fail(S, HK_ENOMEM, "fluid arrays");
         int rc = ensure_inbox(S, isp, inbox_need(S, isp));
         if (rc) return rc;

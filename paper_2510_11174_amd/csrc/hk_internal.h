@@ -179,6 +179,20 @@ struct QedP {
     int step;
 };
 
+// Conversion of particles into the node fluid, done by the push (hybrid runs,
+// fluid species): a particle whose nearest node after its move is fluid and
+// which is not hot (|u|^2 < hot2, or hot2 <= 0) moves virtually onto that
+// node; its weight and momentum go to macc (5 grid arrays, FP64: weight,
+// momentum, and kinetic energy for a warm fluid), a cold fluid's lost kinetic
+// energy to the ledger; k_absorb_finish merges macc into the fluid.
+struct AbsorbP {
+    const uint8_t *sw;   // switch map (1 kinetic)
+    double *macc;        // the species' absorption accumulators
+    double *ledger;      // conversion ledger
+    real hot2;           // thr_hot^2 (<= 0: nothing is hot)
+    int on, warm;
+};
+
 // Error flags raised by kernels (bitmask in a device int).
 enum { ERR_NONFINITE = 1, ERR_CFL = 2, ERR_INBOX = 4, ERR_TILE = 8 };
 
@@ -250,7 +264,7 @@ struct SwitchP {
 };
 
 // particle, switch and conversion launchers (k_particles.hip, k_switch.hip)
-void launch_init_species_cols(const GridP &g, const hk_species_desc &d, uint64_t seed, PArr out,
+void launch_init_species_cols(const GridP &g, const hk_species_desc &d, int isp, uint64_t seed, PArr out,
                               const int *xcol, const double *wcol, int ncol, int has_z,
                               int has_tau, hipStream_t s);
 void launch_count_groups(const GridP &g, PArr src, const long long *off, const int *nf,
@@ -270,8 +284,8 @@ void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PA
                        int *nf_out, long long mig0, const long long *moff, const int *mcap, int *mcnt,
                        const PArr *inbox_p, int *inbox_n, int inbox_cap, real *const f[9], jglob_t *jg,
                        int *err, unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
-                       int mode, const QedP &Q, int2 *items, int *ctl, long long capacity,
-                       hipStream_t s);
+                       int mode, const QedP &Q, const AbsorbP &A, int2 *items, int *ctl,
+                       long long capacity, hipStream_t s);
 // Work plans of the per-tile particle kernels: items (tile, chunk) for grid g
 // (tile_plan_items entries) and ctl[0] (the item count).  The plan lists the chunks of
 // at least cmin particles of bins b by decreasing size; tile_plan_grid is the
@@ -288,7 +302,7 @@ void launch_count_active(const GridP &g, const SpecP &sp, PArr a, Bins b, int zm
                          hipStream_t s);
 void launch_rho_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, double *rho, hipStream_t s);
 void launch_moments_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, int ion_only,
-                          int zmax, real *mom, const unsigned *wmax_bits, const unsigned *umax2,
+                          int zmax, real hot2, real *mom, const unsigned *wmax_bits, const unsigned *umax2,
                           const int *active, int2 *items, int *ctl, long long capacity, hipStream_t s);
 void launch_fluid_moments_nodes(const GridP &g, real inv_ppc, const real *n, const real *ux,
                                 const real *uy, const real *uz, real *mom, int first,
@@ -299,15 +313,16 @@ void launch_indicators_nodes(const GridP &g, const SwitchP &P, const real *mom, 
 void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, const uint8_t *notcold,
                          uint8_t *sw, uint8_t *calm, hipStream_t s);
 // macc: 5 grid arrays (FP64): absorbed weight, momentum (3), kinetic energy
-void launch_absorb_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, const uint8_t *sw,
-                         jglob_t *jg, const unsigned *wmax_bits, double *macc, double *ledger, bool warm,
-                         hipStream_t s);
 void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n, real *ux,
                                 real *uy, real *uz, WarmP w, double *ledger, hipStream_t s);
-void launch_spawn_nodes(const GridP &g, const SpecP &sp, const uint8_t *sw, real *n, real *ux,
-                        real *uy, real *uz, WarmP w, jglob_t *jg, real wmin, int m, uint64_t seed,
+// Spawning: the kinetic nodes with fluid mass >= wmin are listed first (list
+// of node indices, count in list_n, cleared by the caller), then each listed
+// node becomes round(M / w0) particles (1 to 64) of species isp.
+void launch_spawn_nodes(const GridP &g, const SpecP &sp, int isp, const uint8_t *sw, real *n, real *ux,
+                        real *uy, real *uz, WarmP w, jglob_t *jg, real wmin, real w0, uint64_t seed,
                         int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
-                        unsigned *wmax_bits, unsigned *umax2, double *ledger, hipStream_t s);
+                        unsigned *wmax_bits, unsigned *umax2, double *ledger, int *list, int *list_n,
+                        hipStream_t s);
 
 // QED tables built on the host (hk_qed.cpp): We[256], Wb[256], Xe[256*128], Xb[256*128]
 const double *hk_qed_host_tables();

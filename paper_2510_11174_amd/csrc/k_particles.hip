@@ -39,10 +39,13 @@ __device__ inline void copy_particle(const PArr &s, long long i, const PArr &d, 
 }
 
 // ------------------------------------------------------------------ init ----------------
-// Particle q of cell c: id = c * ppc + q; offsets from Philox tag 1, momenta by
-// Box-Muller from tag 2 (FP64, rounded once to the storage type).
+// Particle q of cell c: position index c * ppc + q, id (species << 52) |
+// (c * ppc + q), unique over the species; offsets from Philox tag 1 keyed by
+// the position index (the species of a cell start at the same points),
+// momenta by Box-Muller from tag 2 keyed by the id (FP64, rounded once to
+// the storage type).
 __global__ void __launch_bounds__(BS)
-k_init(GridP g, int ppc, double u_th, double charge, uint64_t seed, const int *__restrict__ xcol,
+k_init(GridP g, int ppc, int isp, double u_th, double charge, uint64_t seed, const int *__restrict__ xcol,
        const double *__restrict__ wcol, int ncol, long long total, PArr out, int has_z,
        int has_tau) {
     long long tid = (long long)blockIdx.x * BS + threadIdx.x;
@@ -54,9 +57,10 @@ k_init(GridP g, int ppc, double u_th, double charge, uint64_t seed, const int *_
     int j = (int)(jk % g.ny), k = (int)(jk / g.ny);
     int i = xcol[col];
     int cell = i + g.nx * (j + g.ny * k);
-    uint64_t id = (uint64_t)cell * (uint64_t)ppc + (uint64_t)q;
+    const uint64_t pos = (uint64_t)cell * (uint64_t)ppc + (uint64_t)q;
+    const uint64_t id = ((uint64_t)isp << 52) | pos;
     uint32_t rp[4], rm[4];
-    draw4(seed, id, 0, TAG_POS, 0, rp);
+    draw4(seed, pos, 0, TAG_POS, 0, rp);
     draw4(seed, id, 0, TAG_MOM, 0, rm);
     double r0 = u01d(rm[0]), r1 = u01d(rm[1]), r2 = u01d(rm[2]), r3 = u01d(rm[3]);
     double m0 = sqrt(-2.0 * log(r0)), m1 = sqrt(-2.0 * log(r2));
@@ -338,9 +342,11 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
        const real *__restrict__ By, const real *__restrict__ Bz, jglob_t *__restrict__ Jx,
        jglob_t *__restrict__ Jy, jglob_t *__restrict__ Jz, int *__restrict__ err,
        unsigned long long *__restrict__ stats, const unsigned *__restrict__ wmax_bits,
-       unsigned *__restrict__ umax2, const int2 *__restrict__ items, const int *__restrict__ ctl, QedP Q) {
+       unsigned *__restrict__ umax2, const int2 *__restrict__ items, const int *__restrict__ ctl, QedP Q,
+       AbsorbP A) {
     __shared__ real sF[6 * FT3];
     __shared__ jacc_t sJ[3 * JT3];
+    __shared__ uint8_t sSw[JT3];   // switch map of nodes -1 .. TILE+1 (absorbing species)
     __shared__ int s_stay, s_move;
     __shared__ unsigned s_u2;
     const int2 it = plan_item(items, ctl, blockIdx.x);
@@ -378,6 +384,15 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
     }
     if (MODE != 2)
         for (int e = threadIdx.x; e < 3 * JT3; e += PBS) sJ[e] = 0;
+    if (MODE != 2 && A.on)
+        for (int e = threadIdx.x; e < JT3; e += PBS) {
+            const int a = e % JT, b = (e / JT) % JT, c = e / (JT * JT);
+            int gi = ox - 1 + a;
+            const int gj = wrapi(oy - 1 + b, g.ny), gk = wrapi(oz - 1 + c, g.nz);
+            if (per) gi = wrapi(gi, g.nx);
+            // no node beyond an open wall: kinetic (nothing is absorbed there)
+            sSw[e] = (!per && (gi < 0 || gi > g.nx)) ? 1 : A.sw[gidx(g, gi, gj, gk)];
+        }
     if (threadIdx.x == 0) { s_stay = 0; s_move = 0; s_u2 = 0; }
     __syncthreads();
 
@@ -386,6 +401,7 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
     float u2max = 0.f;   // largest |u|^2 pushed by this thread
     int pushed = 0;      // particles this wave ranked (shared tiles)
     double led = 0.0;    // photon ledger contributions of this thread
+    double aled = 0.0;   // conversion ledger contributions (cold fluid absorption)
     const int lane = __lane_id();
     const uint64_t lt = (1ull << lane) - 1ull;
     const long long obase = sp.off[t];
@@ -478,15 +494,9 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
                 }
             } else {
                 if (MODE == 1) {
-                    bool kin = true;
-                    if (Q.hybrid) {
-                        int ni = ci + (rx >= (real)0.5), nj = cj + (ry >= (real)0.5), nk = ck + (rz >= (real)0.5);
-                        if (per) ni = wrapi(ni, g.nx);
-                        if (nj >= g.ny) nj -= g.ny;
-                        if (nk >= g.nz) nk -= g.nz;
-                        kin = Q.sw[gidx(g, ni, nj, nk)] != 0;
-                    }
-                    const double chi = kin ? qed_chi(Q.a_s, ex, ey, ez, bx, by, bz, ux, uy, uz, false) : 0.0;
+                    // every lepton particle radiates: one in a fluid node is hot,
+                    // or the conversion takes it at the end of this step
+                    const double chi = qed_chi(Q.a_s, ex, ey, ez, bx, by, bz, ux, uy, uz, false);
                     if (chi > 1e-3) {
                         const double gam = sqrt(1.0 + (double)ux * ux + (double)uy * uy + (double)uz * uz);
                         tau -= Q.alpha_as / gam * qed_total(Q.We, chi) * g.ddt;
@@ -561,6 +571,35 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
                 nk = nk < 0 ? nk + g.nz : (nk >= g.nz ? nk - g.nz : nk);
                 ncell = ni + g.nx * (nj + g.ny * nk);
                 ntile = (ni >> TLOG) + g.ntx * ((nj >> TLOG) + g.nty * (nk >> TLOG));
+                if (MODE != 2 && A.on) {
+                    // conversion: the nearest node after the move is fluid and the
+                    // particle is not hot -> it moves virtually onto the node and
+                    // joins the node fluid (the node lies in this tile's window)
+                    const int dxn = nrx >= (real)0.5, dyn = nry >= (real)0.5, dzn = nrz >= (real)0.5;
+                    const int lxn = lx + fx, lyn = ly + fy, lzn = lz + fz;
+                    const real u2 = ux * ux + uy * uy + uz * uz;
+                    const bool hot = A.hot2 > (real)0 && u2 >= A.hot2;
+                    if (!hot && !sSw[(lxn + dxn + 1) + JT * ((lyn + dyn + 1) + JT * (lzn + dzn + 1))]) {
+                        AxisS SX = axis_shapes(nrx, (real)dxn), SY = axis_shapes(nry, (real)dyn),
+                              SZ = axis_shapes(nrz, (real)dzn);
+                        const real qws = qsc * w;
+                        esirkepov_acc(sJ, lxn, lyn, lzn, SX, SY, SZ, qws * cdx, qws * cdy, qws * cdz);
+                        int gi = ni + dxn, gj = nj + dyn, gk = nk + dzn;
+                        if (per && gi == g.nx) gi = 0;
+                        if (gj == g.ny) gj = 0;
+                        if (gk == g.nz) gk = 0;
+                        const long long node = gidx(g, gi, gj, gk), nn = g.nn;
+                        const double dux = ux, duy = uy, duz = uz, dw = w;
+                        const double kp = dw * (double)sp.m * (sqrt(1.0 + dux * dux + duy * duy + duz * duz) - 1.0);
+                        if (A.warm) atomicAdd(&A.macc[4 * nn + node], kp);
+                        else aled += kp;
+                        atomicAdd(&A.macc[node], dw);
+                        atomicAdd(&A.macc[nn + node], dw * dux);
+                        atomicAdd(&A.macc[2 * nn + node], dw * duy);
+                        atomicAdd(&A.macc[3 * nn + node], dw * duz);
+                        valid = false;
+                    }
+                }
             }
         }
         // ranks from the tile's counters (zeroed before the launch): one atomic
@@ -652,6 +691,10 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
     if (MODE != 0) {
         for (int o = 32; o > 0; o >>= 1) led += __shfl_xor(led, o);
         if (lane == 0 && led != 0.0) atomicAdd(Q.ledger, led);
+    }
+    if (MODE != 2 && A.on) {
+        for (int o = 32; o > 0; o >>= 1) aled += __shfl_xor(aled, o);
+        if (lane == 0 && aled != 0.0) atomicAdd(A.ledger, aled);
     }
     // per-tile bound on |u|^2 of the pushed particles (non-negative float bits
     // order like unsigned integers); read by the next switch evaluation
@@ -898,12 +941,12 @@ inline unsigned blocks(long long n) { return (unsigned)((n + BS - 1) / BS); }
 
 }  // namespace
 
-void launch_init_species_cols(const GridP &g, const hk_species_desc &d, uint64_t seed, PArr out,
+void launch_init_species_cols(const GridP &g, const hk_species_desc &d, int isp, uint64_t seed, PArr out,
                               const int *xcol, const double *wcol, int ncol, int has_z,
                               int has_tau, hipStream_t s) {
     long long total = (long long)ncol * g.ny * g.nz * d.ppc;
     if (total == 0) return;
-    k_init<<<blocks(total), BS, 0, s>>>(g, d.ppc, d.u_th, d.charge, seed, xcol, wcol, ncol, total,
+    k_init<<<blocks(total), BS, 0, s>>>(g, d.ppc, isp, d.u_th, d.charge, seed, xcol, wcol, ncol, total,
                                         out, has_z, has_tau);
 }
 
@@ -964,11 +1007,11 @@ void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PA
                        int *nf_out, long long mig0, const long long *moff, const int *mcap, int *mcnt,
                        const PArr *inbox_p, int *inbox_n, int inbox_cap, real *const f[9], jglob_t *jg,
                        int *err, unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
-                       int mode, const QedP &Q, int2 *items, int *ctl, long long capacity,
-                       hipStream_t s) {
+                       int mode, const QedP &Q, const AbsorbP &A, int2 *items, int *ctl,
+                       long long capacity, hipStream_t s) {
 #define HK_PUSH_ARGS g, sp, in, bin_in, dout, nf_out, mig0, moff, mcap, mcnt, inbox_p, inbox_n, inbox_cap, \
         f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], jg, jg + g.nn, jg + 2 * g.nn, err, \
-        stats, wmax_bits, umax2, items, ctl, Q
+        stats, wmax_bits, umax2, items, ctl, Q, A
     // nf_out is the first of the next buffer's three counter arrays (front
     // fills, back fills, mover ranks), cleared by the planner
     k_tile_plan<<<1, PLAN_BS, 0, s>>>(g.ntiles, sp, bin_in, PUSH_CHUNK, items, ctl, nf_out);

@@ -11,12 +11,17 @@
 //     noise; momentum spread; ionization probability per step; quantum
 //     parameter estimate.  Kinetic if any reaches its threshold, dilated by
 //     `dilation` nodes; back to fluid after `hysteresis` calm evaluations.
-//   absorb: a fluid-species particle whose nearest node is fluid moves
-//     virtually to that node (Esirkepov current of the move) and joins the
-//     node fluid; spawn: enough fluid mass on a kinetic node becomes ppc
-//     particles that move virtually from the node to Philox positions in
-//     its dual cell.  A CIC particle on a node carries exactly the node
-//     charge of the fluid, so div E - rho is unchanged by both.
+//   absorb (done by the push, k_particles.hip): a fluid-species particle
+//     whose nearest node is fluid, and which is not hot (|u| < thr_hot),
+//     moves virtually to that node (Esirkepov current of the move) and joins
+//     the node fluid (k_absorb_finish merges it); spawn: fluid mass M >= wmin
+//     on a kinetic node becomes round(M / w0) particles (1 to 64; w0 the
+//     species' reference weight) that move virtually from the node to Philox
+//     positions in its dual cell.  A CIC particle on a node carries exactly
+//     the node charge of the fluid, so div E - rho is unchanged by both.
+//   Hot particles are also left out of the switch moments: a hot population
+//     crossing a cold bulk stays kinetic by itself and does not decide the
+//     regime of the bulk.
 #include "hk_internal.h"
 #include "hk_pic_device.h"
 
@@ -88,7 +93,7 @@ constexpr int MOM_CHUNK = 8192;   // particles per workgroup of the tile moments
 constexpr int MBS = 512;          // moments workgroup: LDS allows four per CU, 8 waves per SIMD
 
 __global__ void __launch_bounds__(MBS)
-k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__restrict__ mom,
+k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real hot2, real *__restrict__ mom,
           const unsigned *__restrict__ wmax_bits, const unsigned *__restrict__ umax2,
           const int *__restrict__ active, const int2 *__restrict__ items, const int *__restrict__ ctl) {
     __shared__ jacc_t sm[6 * NT3];
@@ -168,6 +173,7 @@ k_moments(GridP g, SpecP sp, PArr a, Bins bins, int ion_only, int zmax, real *__
             if (m.zc < zmax) madd(&sm[e], m.w, inv[0]);
             return;
         }
+        if (hot2 > (real)0 && m.ux * m.ux + m.uy * m.uy + m.uz * m.uz >= hot2) return;   // hot: not counted
         for (int q = 0; q < 6; ++q) madd(&sm[q * NT3 + e], tile_moment_term(q, m.w, m.ux, m.uy, m.uz), inv[q]);
     };
     constexpr int U = MOM_UNROLL;
@@ -411,96 +417,10 @@ __device__ inline void block_add_d(double v, double *out) {
     __syncthreads();
 }
 
-// macc layout (5 grid arrays, FP64): M = sum w, P (3) = sum w u, and for a
-// warm fluid the absorbed kinetic energy per node (which then heats the node
-// instead of going to the ledger).
-__global__ void __launch_bounds__(BS)
-k_absorb(GridP g, SpecP sp, PArr a, Bins bins, const uint8_t *__restrict__ sw,
-         jglob_t *__restrict__ Jx, jglob_t *__restrict__ Jy, jglob_t *__restrict__ Jz,
-         const unsigned *__restrict__ wmax_bits, double *__restrict__ macc,
-         double *__restrict__ ledger, int warm) {
-    __shared__ jacc_t sJ[3 * JT3];
-    __shared__ int any;
-    const int t = blockIdx.x;
-    int nf, nbv;
-    const int n = bin_count(sp, bins, t, nf, nbv);
-    if (n <= 0) return;
-    const int tx = t % g.ntx, ty = (t / g.ntx) % g.nty, tz = t / (g.ntx * g.nty);
-    const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
-    const int per = g.bcx == HK_BC_PERIODIC;
-    // a tile whose nearest nodes (0 .. TILE per axis) are all kinetic absorbs nothing
-    int fluid_node = 0;
-    for (int e = threadIdx.x; e < NT3; e += BS) {
-        int aa = e % NT, b = (e / NT) % NT, c = e / (NT * NT);
-        int gi = ox + aa, gj = wrapi(oy + b, g.ny), gk = wrapi(oz + c, g.nz);
-        if (per) gi = wrapi(gi, g.nx);
-        else if (gi > g.nx) continue;
-        fluid_node |= !sw[gidx(g, gi, gj, gk)];
-    }
-    if (!__syncthreads_or(fluid_node)) return;
-    for (int e = threadIdx.x; e < 3 * JT3; e += BS) sJ[e] = 0;
-    if (threadIdx.x == 0) any = 0;
-    __syncthreads();
-    const real dv = g.dx * g.dy * g.dz;
-    const long long nn = g.nn;
-    // the push's fixed-point deposit: a virtual move to the nearest node is at
-    // most half a cell per axis, so the push's per-species unit bounds it too
-    const real cdx = g.dx / g.dt, cdy = g.dy / g.dt, cdz = g.dz / g.dt;
-    const double jmax = (double)fabsf((float)sp.q) * (double)__uint_as_float(*wmax_bits) / (double)dv *
-                        (double)fmaxf(fmaxf((float)cdx, (float)cdy), (float)cdz);
-#ifdef HK_DOUBLE
-    const double jscale = 1.0;
-    const int jshift = 0;
-#else
-    const int jexp = jdep_exp(jmax);
-    const double jscale = ldexp(1.0, jexp);
-    const int jshift = jexp + JG_BITS;
-#endif
-    const real qsc = (real)((double)sp.q / (double)dv / jscale);
-    double ke = 0;
-    for (int p = threadIdx.x; p < n; p += BS) {
-        const long long ip = bin_slot(sp, t, p, nf, nbv);
-        int cell = a.cell[ip];
-        if (cell < 0) continue;
-        int ci, cj, ck;
-        cell_ijk(g, cell, ci, cj, ck);
-        const real rx = a.rx[ip], ry = a.ry[ip], rz = a.rz[ip];
-        int di, dj, dk;
-        long long node = nearest_node(g, ci, cj, ck, rx, ry, rz, di, dj, dk);
-        if (sw[node]) continue;
-        const int lx = ci - ox, ly = cj - oy, lz = ck - oz;
-        if ((unsigned)lx >= TILE || (unsigned)ly >= TILE || (unsigned)lz >= TILE) continue;
-        const real w = a.w[ip];
-        AxisS SX = axis_shapes(rx, (real)di), SY = axis_shapes(ry, (real)dj), SZ = axis_shapes(rz, (real)dk);
-        const real qws = qsc * w;
-        esirkepov_acc(sJ, lx, ly, lz, SX, SY, SZ, qws * cdx, qws * cdy, qws * cdz);
-        any = 1;
-        double ux = a.ux[ip], uy = a.uy[ip], uz = a.uz[ip];
-        const double kp = (double)w * (double)sp.m * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
-        if (warm) atomicAdd(&macc[4 * nn + node], kp);
-        else ke += kp;
-        atomicAdd(&macc[node], (double)w);
-        atomicAdd(&macc[nn + node], (double)w * ux);
-        atomicAdd(&macc[2 * nn + node], (double)w * uy);
-        atomicAdd(&macc[3 * nn + node], (double)w * uz);
-        a.cell[ip] = -1;
-    }
-    block_add_d(ke, ledger);
-    if (!any) return;
-    for (int e = threadIdx.x; e < JT3; e += BS) {
-        int aa = e % JT, b = (e / JT) % JT, c = e / (JT * JT);
-        int gi = ox - 1 + aa;
-        int gj = wrapi(oy - 1 + b, g.ny), gk = wrapi(oz - 1 + c, g.nz);
-        bool okx, okn;
-        if (per) { gi = wrapi(gi, g.nx); okx = okn = true; }
-        else { okx = gi >= 0 && gi <= g.nx - 1; okn = gi >= 0 && gi <= g.nx; }
-        long long c0 = gidx(g, gi < 0 ? 0 : gi, gj, gk);
-        if (okx) jg_flush(&Jx[c0], sJ[e], jshift);
-        if (okn) jg_flush(&Jy[c0], sJ[JT3 + e], jshift);
-        if (okn) jg_flush(&Jz[c0], sJ[2 * JT3 + e], jshift);
-    }
-}
-
+// macc layout (5 grid arrays, FP64, one set per fluid species, filled by the
+// push): M = sum w, P (3) = sum w u of the absorbed particles, and for a warm
+// fluid their kinetic energy per node (which then heats the node instead of
+// going to the ledger).
 __global__ void __launch_bounds__(BS)
 k_absorb_finish(GridP g, real mass, double *__restrict__ macc, real *__restrict__ n,
                 real *__restrict__ ux, real *__restrict__ uy, real *__restrict__ uz, WarmP wp,
@@ -541,28 +461,24 @@ k_absorb_finish(GridP g, real mass, double *__restrict__ macc, real *__restrict_
     block_add_d(d, ledger);
 }
 
-// A warm node's particles get the fluid momentum plus a Gaussian spread
-// sqrt(T / m) per component, T = p / n (Box-Muller on Philox draws, tag
-// TAG_CONV_TH); the ledger takes the fluid's kinetic plus thermal energy
-// minus the sample's kinetic energy.
-__global__ void __launch_bounds__(BS)
-k_spawn(GridP g, SpecP sp, const uint8_t *__restrict__ sw, real *__restrict__ n, real *__restrict__ ux,
-        real *__restrict__ uy, real *__restrict__ uz, WarmP wp, jglob_t *__restrict__ Jx,
-        jglob_t *__restrict__ Jy, jglob_t *__restrict__ Jz, real wmin, int m, uint64_t seed, int step, PArr inbox,
-        int *__restrict__ inbox_n, int inbox_cap, int *__restrict__ deferred,
-        unsigned *__restrict__ wmax_bits, unsigned *__restrict__ umax2, double *__restrict__ ledger) {
-    long long c = (long long)blockIdx.x * BS + threadIdx.x;
-    if (c >= g.nn) return;
+// Spawn of node c (kinetic, fluid mass >= wmin).
+__device__ inline void spawn_node(const GridP &g, const SpecP &sp, int isp, long long c, real *__restrict__ n,
+                                  real *__restrict__ ux, real *__restrict__ uy, real *__restrict__ uz,
+                                  const WarmP &wp, jglob_t *__restrict__ Jx, jglob_t *__restrict__ Jy,
+                                  jglob_t *__restrict__ Jz, real w0, uint64_t seed, int step, const PArr &inbox,
+                                  int *__restrict__ inbox_n, int inbox_cap, int *__restrict__ deferred,
+                                  unsigned *__restrict__ wmax_bits, unsigned *__restrict__ umax2,
+                                  double *__restrict__ ledger) {
     int i, j, k;
     node_ijk(g, c, i, j, k);
     const int per = g.bcx == HK_BC_PERIODIC;
     const int nxn = per ? g.nx : g.nx + 1;
-    if (i >= nxn || !sw[c]) return;
     const real nc = n[c];
-    if (!(nc > (real)0)) return;
     const real dv = g.dx * g.dy * g.dz;
     const real mass = nc * dv;
-    if (mass < wmin) return;
+    // particles in proportion to the mass: about the reference weight each
+    const double mr = w0 > (real)0 ? floor((double)mass / (double)w0 + 0.5) : 1.0;
+    const int m = mr < 1.0 ? 1 : (mr > 64.0 ? 64 : (int)mr);
     int k0 = atomicAdd(inbox_n, m);
     if (k0 + m > inbox_cap) {
         // no room this step: the node stays fluid; void the reserved slots
@@ -606,9 +522,11 @@ k_spawn(GridP g, SpecP sp, const uint8_t *__restrict__ sw, real *__restrict__ n,
         cc[1] = wrapi(cc[1], g.ny);
         cc[2] = wrapi(cc[2], g.nz);
         real uq[3] = {u[0], u[1], u[2]};
+        const uint64_t pid = (1ull << 63) | ((uint64_t)step << 40) | ((uint64_t)isp << 37) | (node << 6) |
+                             (uint64_t)q;
         if (wp.S) {
             uint32_t t4[4];
-            draw4(seed, node, (uint32_t)step, TAG_CONV_TH, (uint32_t)q, t4);
+            draw4(seed, pid, (uint32_t)step, TAG_CONV_TH, 0, t4);
             const double r0 = u01d(t4[0]), r1 = u01d(t4[1]), r2 = u01d(t4[2]), r3 = u01d(t4[3]);
             const double m0 = sqrt(-2.0 * log(r0)), m1 = sqrt(-2.0 * log(r2));
             const double tp = 6.283185307179586;
@@ -626,7 +544,7 @@ k_spawn(GridP g, SpecP sp, const uint8_t *__restrict__ sw, real *__restrict__ n,
         inbox.rx[s] = X1[0]; inbox.ry[s] = X1[1]; inbox.rz[s] = X1[2];
         inbox.ux[s] = uq[0]; inbox.uy[s] = uq[1]; inbox.uz[s] = uq[2];
         inbox.w[s] = w;
-        inbox.id[s] = (1ull << 63) | ((uint64_t)step << 40) | (node << 6) | (uint64_t)q;
+        inbox.id[s] = pid;
         if (sp.has_z) inbox.zc[s] = (int)sp.q;
         if (sp.has_tau) inbox.tau[s] = tau0(seed, inbox.id[s]);
     }
@@ -637,16 +555,55 @@ k_spawn(GridP g, SpecP sp, const uint8_t *__restrict__ sw, real *__restrict__ n,
     n[c] = 0; ux[c] = 0; uy[c] = 0; uz[c] = 0;
 }
 
+
+// Nodes that spawn: kinetic, with fluid mass >= wmin.  A light pass over the
+// node grid (two loads per node) that lists them for k_spawn.
+__global__ void __launch_bounds__(BS)
+k_spawn_find(GridP g, const uint8_t *__restrict__ sw, const real *__restrict__ n, real wmin,
+             int *__restrict__ list, int *__restrict__ list_n) {
+    const long long c = xcd_node();
+    bool want = false;
+    if (c < g.nn) {
+        const int i = (int)(c % g.sx);
+        const int nxn = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
+        want = i < nxn && sw[c] && n[c] * (g.dx * g.dy * g.dz) >= wmin && n[c] > (real)0;
+    }
+    const uint64_t b = __ballot(want);
+    if (!b) return;
+    int base = 0;
+    if (__lane_id() == 0) base = atomicAdd(list_n, __popcll(b));
+    base = __shfl(base, 0);
+    if (want) list[base + __popcll(b & ((1ull << __lane_id()) - 1ull))] = (int)c;
+}
+
+// One listed node becomes particles (one thread per node).  A warm node's
+// particles get the fluid momentum plus a Gaussian spread sqrt(T / m) per
+// component, T = p / n (Box-Muller on Philox draws, tag TAG_CONV_TH, keyed by
+// the particle's id); the ledger takes the fluid's kinetic plus thermal
+// energy minus the sample's kinetic energy.  Positions (tag TAG_CONV) are
+// keyed by (node, step, slot), shared by the species spawned on one node.
+__global__ void __launch_bounds__(BS)
+k_spawn(GridP g, SpecP sp, int isp, real *__restrict__ n, real *__restrict__ ux,
+        real *__restrict__ uy, real *__restrict__ uz, WarmP wp, jglob_t *__restrict__ Jx,
+        jglob_t *__restrict__ Jy, jglob_t *__restrict__ Jz, real w0, uint64_t seed, int step, PArr inbox,
+        int *__restrict__ inbox_n, int inbox_cap, int *__restrict__ deferred,
+        unsigned *__restrict__ wmax_bits, unsigned *__restrict__ umax2, double *__restrict__ ledger,
+        const int *__restrict__ list, const int *__restrict__ list_n) {
+    const int nl = *list_n;
+    for (int e = blockIdx.x * BS + threadIdx.x; e < nl; e += gridDim.x * BS)
+        spawn_node(g, sp, isp, list[e], n, ux, uy, uz, wp, Jx, Jy, Jz, w0, seed, step, inbox, inbox_n,
+                   inbox_cap, deferred, wmax_bits, umax2, ledger);
+}
 inline unsigned blocks(long long n) { return (unsigned)((n + BS - 1) / BS); }
 inline unsigned xcd_blocks(long long n) { return (blocks(n) + 7u) & ~7u; }
 
 }  // namespace
 
 void launch_moments_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, int ion_only,
-                          int zmax, real *mom, const unsigned *wmax_bits, const unsigned *umax2,
+                          int zmax, real hot2, real *mom, const unsigned *wmax_bits, const unsigned *umax2,
                           const int *active, int2 *items, int *ctl, long long capacity, hipStream_t s) {
     launch_tile_plan(g, sp, b, MOM_CHUNK, items, ctl, s);
-    k_moments<<<tile_plan_grid(g, capacity, MOM_CHUNK), MBS, 0, s>>>(g, sp, a, b, ion_only, zmax, mom,
+    k_moments<<<tile_plan_grid(g, capacity, MOM_CHUNK), MBS, 0, s>>>(g, sp, a, b, ion_only, zmax, hot2, mom,
                                                                   wmax_bits, umax2, active, items, ctl);
 }
 void launch_fluid_moments_nodes(const GridP &g, real inv_ppc, const real *n, const real *ux,
@@ -665,21 +622,16 @@ void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, c
                          uint8_t *sw, uint8_t *calm, hipStream_t s) {
     k_dilate<<<xcd_blocks(g.nn), BS, 0, s>>>(g, P, hot, notcold, sw, calm);
 }
-void launch_absorb_tiles(const GridP &g, const SpecP &sp, PArr a, Bins b, const uint8_t *sw,
-                         jglob_t *jg, const unsigned *wmax_bits, double *macc, double *ledger, bool warm,
-                         hipStream_t s) {
-    k_absorb<<<g.ntiles, BS, 0, s>>>(g, sp, a, b, sw, jg, jg + g.nn, jg + 2 * g.nn, wmax_bits, macc, ledger,
-                                     warm ? 1 : 0);
-}
 void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n, real *ux,
                                 real *uy, real *uz, WarmP w, double *ledger, hipStream_t s) {
     k_absorb_finish<<<blocks(g.nn), BS, 0, s>>>(g, mass, macc, n, ux, uy, uz, w, ledger);
 }
-void launch_spawn_nodes(const GridP &g, const SpecP &sp, const uint8_t *sw, real *n, real *ux,
-                        real *uy, real *uz, WarmP w, jglob_t *jg, real wmin, int m, uint64_t seed,
+void launch_spawn_nodes(const GridP &g, const SpecP &sp, int isp, const uint8_t *sw, real *n, real *ux,
+                        real *uy, real *uz, WarmP w, jglob_t *jg, real wmin, real w0, uint64_t seed,
                         int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
-                        unsigned *wmax_bits, unsigned *umax2, double *ledger, hipStream_t s) {
-    k_spawn<<<blocks(g.nn), BS, 0, s>>>(g, sp, sw, n, ux, uy, uz, w, jg, jg + g.nn, jg + 2 * g.nn, wmin,
-                                        m, seed, step, inbox, inbox_n, inbox_cap, deferred, wmax_bits, umax2,
-                                        ledger);
+                        unsigned *wmax_bits, unsigned *umax2, double *ledger, int *list, int *list_n,
+                        hipStream_t s) {
+    k_spawn_find<<<xcd_blocks(g.nn), BS, 0, s>>>(g, sw, n, wmin, list, list_n);
+    k_spawn<<<1024, BS, 0, s>>>(g, sp, isp, n, ux, uy, uz, w, jg, jg + g.nn, jg + 2 * g.nn, w0, seed, step,
+                                inbox, inbox_n, inbox_cap, deferred, wmax_bits, umax2, ledger, list, list_n);
 }

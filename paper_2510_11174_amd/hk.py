@@ -66,7 +66,8 @@ class RunDesc(C.Structure):
                 ("enable_ionization", C.c_int32), ("enable_qed", C.c_int32),
                 ("thr_a", C.c_double), ("thr_grad", C.c_double), ("thr_sigma_u", C.c_double),
                 ("thr_ion", C.c_double), ("thr_chi", C.c_double), ("n_floor", C.c_double),
-                ("spawn_frac", C.c_double), ("stream", C.c_void_p), ("alloc", ALLOC_FN),
+                ("spawn_frac", C.c_double), ("thr_hot", C.c_double), ("stream", C.c_void_p),
+                ("alloc", ALLOC_FN),
                 ("free", FREE_FN), ("alloc_ctx", C.c_void_p)]
 
 
@@ -251,7 +252,8 @@ def descriptors(cfg: dict):
                   enable_qed=int(r.get("enable_qed", False)), thr_a=r.get("thr_a", 0.5),
                   thr_grad=r.get("thr_grad", 0.2), thr_sigma_u=r.get("thr_sigma_u", 0.05),
                   thr_ion=r.get("thr_ion", 1e-6), thr_chi=r.get("thr_chi", 1e-3),
-                  n_floor=r.get("n_floor", 1e-10), spawn_frac=r.get("spawn_frac", 0.5))
+                  n_floor=r.get("n_floor", 1e-10), spawn_frac=r.get("spawn_frac", 0.5),
+                  thr_hot=r.get("thr_hot", 0.0))
     return grid, sps, len(cfg["species"]), laser, run
 
 
