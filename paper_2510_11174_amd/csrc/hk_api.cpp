@@ -24,6 +24,9 @@ void cnn_launch_decide(const GridP &g, const unsigned short *a4, const unsigned 
                        uint64_t seed, uint32_t eval, uint8_t *hot, uint8_t *notcold, int *nfall,
                        float *pmean, hipStream_t s);
 
+// device status words copied to the host once per merge (see hk_sim::status)
+#define HK_NSTATUS 32
+
 namespace {
 
 // Physical constants (CODATA 2018) for the SI scale of ionization and QED.
@@ -59,11 +62,16 @@ struct DevSpecies {
     real *fs = nullptr;           // warm fluid: entropy density n K, K = p / n^gamma_ad
     real *fn2 = nullptr, *fs2 = nullptr;   // the fluid pass writes n and S here, then swaps
     double *macc = nullptr;       // particles the push absorbed into the fluid this step (5 grid arrays)
+    int *xr = nullptr;            // device [8]: x window of the fluid (see launch_fluid)
     IonP *ion = nullptr;          // device rate constants
     long long reserve_hint = 0;   // expected peak count (ionization targets)
     unsigned *umax2 = nullptr;    // device [ntiles]: bound on |u|^2 (float bits) since the
                                   // last switch evaluation, raised by push, ionization, spawn
     bool umax_ok = false;         // false: particles changed outside those kernels
+    // an empty species is not pushed: `idle` when its bins were empty at the
+    // last push and nothing arrived since (inbox entries, counted per step)
+    bool idle = false;
+    long long arrived = 0;
 };
 
 }  // namespace
@@ -97,7 +105,8 @@ struct hk_sim {
     double *dsum = nullptr;      // diagnostic accumulators
     double *ledger = nullptr;    // [0] conversion loss, [1] ionization, [2] photons
     int *status = nullptr;       // [0] error bits, [1 + 2s] inbox count, [2 + 2s] fail count,
-                                 // [13] spawns deferred for lack of inbox room
+                                 // [13] spawns deferred for lack of inbox room, [16 + s] push
+                                 // work items of species s at its last push (0: bins empty)
     int *h_status = nullptr;     // pinned
     hipEvent_t status_ev = nullptr;  // recorded after the status copy to h_status
     int have_gauss0 = 0;
@@ -370,6 +379,7 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     D.nb[1 - dst_i] = f1 + nt;
     D.capacity = total;
     D.max_cap = maxc;
+    D.idle = false;
     D.h_off = off;
     D.h_cap = cap;
     if (D.d.ionizable) {
@@ -641,7 +651,7 @@ int merge_launch(hk_sim *S) {
         launch_merge_inbox(S->g, P, D.inbox, inbox_n, D.inbox_cap, D.buf[D.cur], D.nf[D.cur],
                            D.nb[D.cur], fail_n, D.fail, S->status, S->s);
     }
-    HIPCHK(S, hipMemcpyAsync(S->h_status, S->status, sizeof(int) * 16, hipMemcpyDeviceToHost, S->s));
+    HIPCHK(S, hipMemcpyAsync(S->h_status, S->status, sizeof(int) * HK_NSTATUS, hipMemcpyDeviceToHost, S->s));
     HIPCHK(S, hipEventRecord(S->status_ev, S->s));
     return HK_OK;
 }
@@ -650,6 +660,7 @@ int merge_finish(hk_sim *S) {
     HIPCHK(S, hipEventSynchronize(S->status_ev));
     int rc = status_error(S);
     if (rc) return rc;
+    for (int isp = 0; isp < S->nsp; ++isp) S->sp[isp].arrived += S->h_status[1 + 2 * isp];
     bool rebinned = false;
     for (int isp = 0; isp < S->nsp; ++isp) {
         DevSpecies &D = S->sp[isp];
@@ -789,14 +800,16 @@ void reconcile(hk_sim *S) {
         const WarmP W{D.fs, D.d.gamma_ad};
         // particles the push absorbed join the node fluid
         if (D.capacity)
-            launch_absorb_finish_nodes(g, P.m, D.macc, D.fn, D.fu[0], D.fu[1], D.fu[2], W, S->ledger, s);
+            launch_absorb_finish_nodes(g, P.m, D.macc, D.fn, D.fu[0], D.fu[1], D.fu[2], W, S->ledger, D.xr, s);
+        launch_fluid_window_commit(g, D.xr, s);
         double dv = g.ddx * g.ddy * g.ddz;
         const double w0 = D.d.n0 * dv / std::max(1, D.d.ppc);
         real wmin = (real)(S->run.spawn_frac * w0);
         launch_zero(S->spawn_n, sizeof(int), s);
         launch_spawn_nodes(g, P, isp, S->sw, D.fn, D.fu[0], D.fu[1], D.fu[2], W, S->jg, wmin, (real)w0,
                            S->run.seed, (int)S->step, D.inbox, S->status + 1 + 2 * isp, D.inbox_cap,
-                           S->status + 13, S->wmax + isp, D.umax2, S->ledger, S->spawn_list, S->spawn_n, s);
+                           S->status + 13, S->wmax + isp, D.umax2, S->ledger, S->spawn_list, S->spawn_n, D.xr,
+                           s);
     }
 }
 
@@ -855,12 +868,14 @@ int one_step(hk_sim *S) {
     launch_antenna(g, S->las, S->t + 0.5 * g.ddt, S->f[HK_JY], S->f[HK_JZ], s);
     // 3. particles (mobile species push into the next bins; immobile ions ionize in
     // place; QED leptons emit photons; photons create pairs and fly straight)
+    for (int isp = 0; isp < S->nsp; ++isp) S->sp[isp].arrived = 0;
     for (int isp = 0; isp < S->nsp; ++isp) {
         DevSpecies &D = S->sp[isp];
         if (D.capacity == 0) continue;
         SpecP P = specp(D);
         const int mode = push_mode(S, isp);
         if (mode < 0) continue;
+        if (D.d.mobile && D.idle) continue;   // empty bins, nothing arrived: nothing to push
         if (D.d.mobile) {
             int nxt = 1 - D.cur;
             // front and back fills of the next buffer and the mover ranks start
@@ -875,13 +890,14 @@ int one_step(hk_sim *S) {
                 A.macc = D.macc;
                 A.ledger = S->ledger;
                 A.hot2 = hot2(S);
+                A.xr = D.xr;
                 A.warm = D.fs != nullptr;
             }
             hipEvent_t pa = S->timing ? ev_get(S) : nullptr;
             launch_push_tiles(g, P, D.buf[D.cur], cur_bins(D), D.buf[nxt], D.nf[nxt], D.mig0, D.moff,
                               D.mcap, mcnt, D.inbox_dev, S->status + 1 + 2 * isp, D.inbox_cap, S->f,
                               S->jg, S->status, S->dstat, S->wmax + isp, D.umax2, mode, Q, A, S->plan,
-                              S->plan_ctl, D.capacity, s);
+                              S->plan_ctl, D.capacity, S->status + 16 + isp, s);
             if (S->timing) {
                 S->spans.push_back({pa, ev_get(S), 6});
                 S->timers[8] += 1;
@@ -896,9 +912,13 @@ int one_step(hk_sim *S) {
                                  T.has_tau, s);
         }
     }
+    bool pushed[HK_MAX_SPECIES] = {};
     for (int isp = 0; isp < S->nsp; ++isp) {
         DevSpecies &D = S->sp[isp];
-        if (D.capacity && D.d.mobile && push_mode(S, isp) >= 0) D.cur = 1 - D.cur;
+        if (D.capacity && D.d.mobile && push_mode(S, isp) >= 0 && !D.idle) {
+            D.cur = 1 - D.cur;
+            pushed[isp] = true;
+        }
     }
     time_mark(S, 1);
     // 4. newborn and overflow particles join their bins; 5. cold fluid (it
@@ -912,7 +932,7 @@ int one_step(hk_sim *S) {
             DevSpecies &D = S->sp[isp];
             if (!D.fn) continue;
             launch_fluid(g, specp(D), D.fn, D.fu[0], D.fu[1], D.fu[2], WarmP{D.fs, D.d.gamma_ad}, S->f,
-                         S->fluid_scratch, D.fn2, D.fs2, (real)S->run.n_floor, s);
+                         S->fluid_scratch, D.fn2, D.fs2, (real)S->run.n_floor, D.xr, s);
             std::swap(D.fn, D.fn2);
             if (D.fs) std::swap(D.fs, D.fs2);
         }
@@ -935,8 +955,28 @@ int one_step(hk_sim *S) {
     rc = merge_finish(S);
     if (rc) return rc;
     time_mark(S, 5);
+    // a species whose bins were empty at this push and which received nothing
+    // is skipped until something arrives (a re-bin or a host write resets it)
+    for (int isp = 0; isp < S->nsp; ++isp) {
+        DevSpecies &D = S->sp[isp];
+        if (pushed[isp]) D.idle = S->h_status[16 + isp] == 0;
+        if (D.arrived > 0) D.idle = false;
+    }
     S->step++;
     S->t = S->step * g.ddt;
+    return HK_OK;
+}
+
+// The x window of species isp's fluid: every node (full) or none (a fluid
+// that is zero everywhere); periodic x always takes every node.
+int set_fluid_window(hk_sim *S, int isp, bool full) {
+    const GridP &g = S->g;
+    const int per = g.bcx == HK_BC_PERIODIC;
+    const int empty = g.nx + 2;
+    int h[8] = {0, per ? g.nx - 1 : g.nx, empty, -1, empty, -1, 0, 0};
+    if (!full && !per) { h[0] = empty; h[1] = -1; }
+    HIPCHK(S, hipMemcpyAsync(S->sp[isp].xr, h, sizeof(h), hipMemcpyHostToDevice, S->s));
+    HIPCHK(S, hipStreamSynchronize(S->s));
     return HK_OK;
 }
 
@@ -960,11 +1000,16 @@ int ensure_fluid(hk_sim *S) {
         D.fn2 = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
         for (int d = 0; d < 3; ++d) D.fu[d] = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
         D.macc = (double *)dalloc(S, sizeof(double) * 5 * (size_t)g.nn);
+        D.xr = (int *)dalloc(S, sizeof(int) * 8, false);
+        if (D.xr) {
+            int rc = set_fluid_window(S, isp, false);
+            if (rc) return rc;
+        }
         if (D.d.gamma_ad > 0.0) {
             D.fs = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
             D.fs2 = (real *)dalloc(S, sizeof(real) * (size_t)g.nn);
         }
-        if (!D.fn || !D.fn2 || !D.fu[0] || !D.fu[1] || !D.fu[2] || !D.macc ||
+        if (!D.fn || !D.fn2 || !D.fu[0] || !D.fu[1] || !D.fu[2] || !D.macc || !D.xr ||
             (D.d.gamma_ad > 0.0 && (!D.fs || !D.fs2)))
             return fail(S, HK_ENOMEM, "fluid arrays");
         int rc = ensure_inbox(S, isp, inbox_need(S, isp));
@@ -1210,14 +1255,14 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
     S->tmp_b = (double *)dalloc(S, sizeof(double) * (size_t)g.nn);
     S->dsum = (double *)dalloc(S, sizeof(double) * 64);
     S->ledger = (double *)dalloc(S, sizeof(double) * 8);
-    S->status = (int *)dalloc(S, sizeof(int) * 16);
+    S->status = (int *)dalloc(S, sizeof(int) * HK_NSTATUS);
     S->dstat = (unsigned long long *)dalloc(S, sizeof(unsigned long long) * 4);
     // species weight bounds, plus one spare slot that QED kernels may raise
     // when a sink species does not exist
     S->wmax = (unsigned *)dalloc(S, sizeof(unsigned) * (HK_MAX_SPECIES + 1));
     S->plan = (int2 *)dalloc(S, sizeof(int2) * (size_t)tile_plan_items(g));
     S->plan_ctl = (int *)dalloc(S, sizeof(int) * 4);
-    if (hipHostMalloc((void **)&S->h_status, sizeof(int) * 16, 0) != hipSuccess)
+    if (hipHostMalloc((void **)&S->h_status, sizeof(int) * HK_NSTATUS, 0) != hipSuccess)
         S->h_status = nullptr;
     if (hipEventCreateWithFlags(&S->status_ev, hipEventDisableTiming) != hipSuccess)
         S->status_ev = nullptr;
@@ -1548,7 +1593,7 @@ int hk_set_fluid(hk_sim *S, int isp, const double *n, const double *u, size_t no
         HIPCHK(S, hipMemcpyAsync(dst[q], h[q].data(), sizeof(real) * nodes, hipMemcpyHostToDevice, S->s));
     HIPCHK(S, hipStreamSynchronize(S->s));
     S->have_gauss0 = 0;
-    return HK_OK;
+    return set_fluid_window(S, isp, true);   // fluid may sit anywhere now
 }
 
 // Warm fluid pressure p = S n^(gamma_ad - 1) per node (host FP64); setting
@@ -1579,7 +1624,7 @@ int hk_set_fluid_p(hk_sim *S, int isp, const double *p, size_t nodes) {
         hs[c] = hn[c] > 0 ? (real)(p[c] * std::pow((double)hn[c], 1.0 - D.d.gamma_ad)) : (real)0;
     HIPCHK(S, hipMemcpyAsync(D.fs, hs.data(), sizeof(real) * nodes, hipMemcpyHostToDevice, S->s));
     HIPCHK(S, hipStreamSynchronize(S->s));
-    return HK_OK;
+    return set_fluid_window(S, isp, true);
 }
 
 int hk_enable_timing(hk_sim *S, int on) {
@@ -1808,6 +1853,7 @@ int hk_load(hk_sim *S, const char *path) {
             for (real *q : fl)
                 if ((rc = ck_dev_in(S, F, q, sizeof(real) * (size_t)g.nn))) return rc;
             if (has_fluid == 2 && (rc = ck_dev_in(S, F, D.fs, sizeof(real) * (size_t)g.nn))) return rc;
+            if ((rc = set_fluid_window(S, isp, true))) return rc;
         }
     }
     if (!F.ok) return fail(S, HK_EIO, "checkpoint: file ends early");

@@ -190,6 +190,7 @@ struct AbsorbP {
     double *macc;        // the species' absorption accumulators
     double *ledger;      // conversion ledger
     real hot2;           // thr_hot^2 (<= 0: nothing is hot)
+    int *xr;             // the species' fluid x window: absorptions widen xr[4..5]
     int on, warm;
 };
 
@@ -250,8 +251,13 @@ struct WarmP {
     real *S;
     double ga;   // adiabatic index
 };
+// xr (6 ints per fluid species): x window of the nodes that may hold fluid
+// (open x; periodic x keeps the full range), its widening by the update, and
+// the x range of this step's absorptions (k_fluid.hip explains the protocol)
 void launch_fluid(const GridP &g, const SpecP &sp, const real *n, real *ux, real *uy, real *uz, WarmP w,
-                  real *const f[9], real *scratch, real *nout, real *Sout, real n_floor, hipStream_t s);
+                  real *const f[9], real *scratch, real *nout, real *Sout, real n_floor, int *xr,
+                  hipStream_t s);
+void launch_fluid_window_commit(const GridP &g, int *xr, hipStream_t s);
 void launch_fluid_heat(const GridP &g, const real *n, WarmP w, double *out, hipStream_t s);
 void launch_fluid_rho(const GridP &g, const SpecP &sp, const real *n, double *rho,
                       hipStream_t s);
@@ -285,7 +291,7 @@ void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PA
                        const PArr *inbox_p, int *inbox_n, int inbox_cap, real *const f[9], jglob_t *jg,
                        int *err, unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
                        int mode, const QedP &Q, const AbsorbP &A, int2 *items, int *ctl,
-                       long long capacity, hipStream_t s);
+                       long long capacity, int *live, hipStream_t s);
 // Work plans of the per-tile particle kernels: items (tile, chunk) for grid g
 // (tile_plan_items entries) and ctl[0] (the item count).  The plan lists the chunks of
 // at least cmin particles of bins b by decreasing size; tile_plan_grid is the
@@ -313,8 +319,9 @@ void launch_indicators_nodes(const GridP &g, const SwitchP &P, const real *mom, 
 void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, const uint8_t *notcold,
                          uint8_t *sw, uint8_t *calm, hipStream_t s);
 // macc: 5 grid arrays (FP64): absorbed weight, momentum (3), kinetic energy
+// merges macc into the fluid at the nodes of the absorptions' x range xr[4..5]
 void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n, real *ux,
-                                real *uy, real *uz, WarmP w, double *ledger, hipStream_t s);
+                                real *uy, real *uz, WarmP w, double *ledger, const int *xr, hipStream_t s);
 // Spawning: the kinetic nodes with fluid mass >= wmin are listed first (list
 // of node indices, count in list_n, cleared by the caller), then each listed
 // node becomes round(M / w0) particles (1 to 64) of species isp.
@@ -322,7 +329,7 @@ void launch_spawn_nodes(const GridP &g, const SpecP &sp, int isp, const uint8_t 
                         real *uy, real *uz, WarmP w, jglob_t *jg, real wmin, real w0, uint64_t seed,
                         int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
                         unsigned *wmax_bits, unsigned *umax2, double *ledger, int *list, int *list_n,
-                        hipStream_t s);
+                        const int *xr, hipStream_t s);
 
 // QED tables built on the host (hk_qed.cpp): We[256], Wb[256], Xe[256*128], Xb[256*128]
 const double *hk_qed_host_tables();

@@ -23,6 +23,14 @@
 // The fluid current obeys the same discrete continuity equation as the
 // Esirkepov particle current, so div E - rho is unchanged by the fluid.
 // HBM-bound; where there is no fluid only the density is read.
+//
+// x window (open x): every node with x index outside [xr[0], xr[1]] holds no
+// fluid in either density buffer (and u = 0 there), so the passes leave the
+// nodes outside [xr[0] - 1, xr[1] + 1] alone (a face flux reaches one node
+// further per step).  The window only grows: the update widens xr[2..3] where
+// it leaves fluid, the push's absorptions widen xr[4..5], and
+// k_fluid_window_commit folds both into xr[0..1] once per step.  Periodic x
+// keeps the full window.
 #include "hk_internal.h"
 
 namespace {
@@ -39,6 +47,11 @@ __device__ inline long long xcd_node() {
     return (long long)item * BS + threadIdx.x;
 }
 
+
+// Whether x index i is inside the pass window of x range xr (see above).
+__device__ inline bool in_window(const int *__restrict__ xr, int i) {
+    return i >= xr[0] - 1 && i <= xr[1] + 1;
+}
 
 // Linear indices of a node's neighbours (node counts stay below 2^31):
 // y and z periodic, x periodic or open (no neighbour beyond an open wall).
@@ -87,9 +100,10 @@ __device__ inline real node_val(const real *__restrict__ F, const int xs[2], con
 
 // warm fluid: node pressure p = S n^(ga-1), zero where n = 0
 __global__ void __launch_bounds__(BS)
-k_fluid_p(GridP g, real gm1, const real *__restrict__ n, const real *__restrict__ S, real *__restrict__ P) {
+k_fluid_p(GridP g, real gm1, const real *__restrict__ n, const real *__restrict__ S, real *__restrict__ P,
+          const int *__restrict__ xr) {
     long long c = xcd_node();
-    if (c >= g.nn) return;
+    if (c >= g.nn || !in_window(xr, (int)(c % g.sx))) return;
     const real nc = n[c];
     P[c] = nc > (real)0 ? S[c] * pow(nc, gm1) : (real)0;
 }
@@ -99,9 +113,10 @@ k_fluid_lorentz(GridP g, real qm, real mass, real n_floor, const real *__restric
                 const real *__restrict__ P, const real *__restrict__ ux,
                 const real *__restrict__ uy, const real *__restrict__ uz, const real *__restrict__ Ex,
                 const real *__restrict__ Ey, const real *__restrict__ Ez, const real *__restrict__ Bx,
-                const real *__restrict__ By, const real *__restrict__ Bz, real *__restrict__ sc) {
+                const real *__restrict__ By, const real *__restrict__ Bz, real *__restrict__ sc,
+                const int *__restrict__ xr) {
     long long cl = xcd_node();
-    if (cl >= g.nn) return;
+    if (cl >= g.nn || !in_window(xr, (int)(cl % g.sx))) return;
     int i, j, k;
     node_ijk(g, cl, i, j, k);
     const int per = g.bcx == HK_BC_PERIODIC;
@@ -188,9 +203,9 @@ __global__ void __launch_bounds__(BS)
 k_fluid_update(GridP g, real q, real n_floor, const real *__restrict__ n, real *__restrict__ ux,
                real *__restrict__ uy, real *__restrict__ uz, const real *__restrict__ sc,
                real *__restrict__ Jx, real *__restrict__ Jy, real *__restrict__ Jz,
-               real *__restrict__ nout, const real *__restrict__ S, real *__restrict__ Sout) {
+               real *__restrict__ nout, const real *__restrict__ S, real *__restrict__ Sout, int *__restrict__ xr) {
     long long cl = xcd_node();
-    if (cl >= g.nn) return;
+    if (cl >= g.nn || !in_window(xr, (int)(cl % g.sx))) return;
     int i, j, k;
     node_ijk(g, cl, i, j, k);
     const int per = g.bcx == HK_BC_PERIODIC;
@@ -265,6 +280,11 @@ k_fluid_update(GridP g, real q, real n_floor, const real *__restrict__ n, real *
     }
     const real nv = n0 - g.dt * dn;
     nout[c] = nv;
+    // fluid left next to the window: widen it (x index i holds fluid now)
+    if (nv != (real)0 && (i < xr[0] || i > xr[1])) {
+        atomicMin(&xr[2], i);
+        atomicMax(&xr[3], i);
+    }
     if (S) {
         // kept non-negative: a node can lose more than it holds in one step
         const real sn = Sc - g.dt * ds;
@@ -308,22 +328,37 @@ inline unsigned blocks(long long n) { return (unsigned)((n + BS - 1) / BS); }
 // grid of an XCD-aware launch over n nodes
 inline unsigned xcd_blocks(long long n) { return (blocks(n) + 7u) & ~7u; }
 
+// xr[0..1] the window, xr[2..3] the update's widening, xr[4..5] the
+// absorptions' range: the window takes both, which then start empty again
+__global__ void k_fluid_window_commit(int *xr, int empty_lo) {
+    if (threadIdx.x != 0) return;
+    xr[0] = min(xr[0], min(xr[2], xr[4]));
+    xr[1] = max(xr[1], max(xr[3], xr[5]));
+    xr[2] = xr[4] = empty_lo;
+    xr[3] = xr[5] = -1;
+}
+
 }  // namespace
 
 // scratch: 7 grid arrays (us, v, and the pressure of a warm species); nout
-// and Sout receive the new density and entropy density (every node, so the
-// caller can swap them in)
+// and Sout receive the new density and entropy density (every node of the
+// window, so the caller can swap them in); xr: the species' x window
 void launch_fluid(const GridP &g, const SpecP &sp, const real *n, real *ux, real *uy, real *uz, WarmP w,
-                  real *const f[9], real *scratch, real *nout, real *Sout, real n_floor, hipStream_t s) {
+                  real *const f[9], real *scratch, real *nout, real *Sout, real n_floor, int *xr,
+                  hipStream_t s) {
     real *P = nullptr;
     if (w.S) {
         P = scratch + 6 * g.nn;
-        k_fluid_p<<<xcd_blocks(g.nn), BS, 0, s>>>(g, (real)(w.ga - 1.0), n, w.S, P);
+        k_fluid_p<<<xcd_blocks(g.nn), BS, 0, s>>>(g, (real)(w.ga - 1.0), n, w.S, P, xr);
     }
     k_fluid_lorentz<<<xcd_blocks(g.nn), BS, 0, s>>>(g, sp.qm, sp.m, n_floor, n, P, ux, uy, uz, f[HK_EX],
-                                                f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], scratch);
+                                                f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], scratch, xr);
     k_fluid_update<<<xcd_blocks(g.nn), BS, 0, s>>>(g, sp.q, n_floor, n, ux, uy, uz, scratch, f[HK_JX],
-                                               f[HK_JY], f[HK_JZ], nout, w.S, Sout);
+                                               f[HK_JY], f[HK_JZ], nout, w.S, Sout, xr);
+}
+
+void launch_fluid_window_commit(const GridP &g, int *xr, hipStream_t s) {
+    k_fluid_window_commit<<<1, 64, 0, s>>>(xr, g.nx + 2);
 }
 
 void launch_fluid_heat(const GridP &g, const real *n, WarmP w, double *out, hipStream_t s) {

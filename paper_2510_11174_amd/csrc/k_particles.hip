@@ -268,10 +268,11 @@ constexpr int PUSH_CHUNK = 16 * PBS; // tiles up to this many particles take one
 constexpr int PLAN_BS = 1024;
 
 // ctl[0] = number of items; items sorted by decreasing chunk size through 32
-// power-of-two buckets.
+// power-of-two buckets.  live (optional) receives the item count too: zero
+// exactly when the bins are empty.
 __global__ void __launch_bounds__(PLAN_BS)
 k_tile_plan(int ntiles, SpecP sp, Bins bins, int cmin, int2 *__restrict__ items, int *__restrict__ ctl,
-            int *__restrict__ zero3) {
+            int *__restrict__ zero3, int *__restrict__ live = nullptr) {
     __shared__ int cnt[32], cur[32];
     if (threadIdx.x < 32) cnt[threadIdx.x] = 0;
     // the push's output counters (3 ntiles ints), cleared here to save a launch
@@ -291,6 +292,7 @@ k_tile_plan(int ntiles, SpecP sp, Bins bins, int cmin, int2 *__restrict__ items,
         int total = 0;
         for (int b = 31; b >= 0; --b) { cur[b] = total; total += cnt[b]; }
         ctl[0] = total;
+        if (live) *live = total;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < ntiles; t += PLAN_BS) {
@@ -597,6 +599,8 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
                         atomicAdd(&A.macc[nn + node], dw * dux);
                         atomicAdd(&A.macc[2 * nn + node], dw * duy);
                         atomicAdd(&A.macc[3 * nn + node], dw * duz);
+                        atomicMin(&A.xr[4], gi);
+                        atomicMax(&A.xr[5], gi);
                         valid = false;
                     }
                 }
@@ -1008,13 +1012,13 @@ void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PA
                        const PArr *inbox_p, int *inbox_n, int inbox_cap, real *const f[9], jglob_t *jg,
                        int *err, unsigned long long *stats, const unsigned *wmax_bits, unsigned *umax2,
                        int mode, const QedP &Q, const AbsorbP &A, int2 *items, int *ctl,
-                       long long capacity, hipStream_t s) {
+                       long long capacity, int *live, hipStream_t s) {
 #define HK_PUSH_ARGS g, sp, in, bin_in, dout, nf_out, mig0, moff, mcap, mcnt, inbox_p, inbox_n, inbox_cap, \
         f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], jg, jg + g.nn, jg + 2 * g.nn, err, \
         stats, wmax_bits, umax2, items, ctl, Q, A
     // nf_out is the first of the next buffer's three counter arrays (front
     // fills, back fills, mover ranks), cleared by the planner
-    k_tile_plan<<<1, PLAN_BS, 0, s>>>(g.ntiles, sp, bin_in, PUSH_CHUNK, items, ctl, nf_out);
+    k_tile_plan<<<1, PLAN_BS, 0, s>>>(g.ntiles, sp, bin_in, PUSH_CHUNK, items, ctl, nf_out, live);
     // the two bin buffers share one layout (checked when they are allocated):
     // every field of `out` sits the same byte distance from that of `in`
     const long long dout = (const char *)out.cell - (const char *)in.cell;

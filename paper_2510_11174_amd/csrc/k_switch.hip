@@ -424,10 +424,12 @@ __device__ inline void block_add_d(double v, double *out) {
 __global__ void __launch_bounds__(BS)
 k_absorb_finish(GridP g, real mass, double *__restrict__ macc, real *__restrict__ n,
                 real *__restrict__ ux, real *__restrict__ uy, real *__restrict__ uz, WarmP wp,
-                double *__restrict__ ledger) {
+                double *__restrict__ ledger, const int *__restrict__ xr) {
     long long c = (long long)blockIdx.x * BS + threadIdx.x;
-    double d = 0;
-    if (c < g.nn && macc[c] > 0.0) {
+    double dsum = 0;
+    // only the x range of this step's absorptions (xr[4..5]) has entries
+    const int i = c < g.nn ? (int)(c % g.sx) : -1;
+    if (c < g.nn && i >= xr[4] && i <= xr[5] && macc[c] > 0.0) {
         const long long nn = g.nn;
         const double dv = g.ddx * g.ddy * g.ddz;
         double m0 = (double)n[c] * dv;
@@ -437,7 +439,7 @@ k_absorb_finish(GridP g, real mass, double *__restrict__ macc, real *__restrict_
         double un[3];
         for (int q = 0; q < 3; ++q) un[q] = (m0 * u0[q] + macc[(1 + q) * nn + c]) / mt;
         double gn = sqrt(1.0 + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
-        d = m0 * (double)mass * (g0 - 1.0) - mt * (double)mass * (gn - 1.0);
+        double d = m0 * (double)mass * (g0 - 1.0) - mt * (double)mass * (gn - 1.0);
         if (wp.S) {
             // the merge's kinetic energy loss heats the node: p += (ga - 1) dE / dV;
             // a node left without positive mass or pressure (its fluid density
@@ -457,8 +459,9 @@ k_absorb_finish(GridP g, real mass, double *__restrict__ macc, real *__restrict_
         n[c] = (real)(mt / dv);
         ux[c] = (real)un[0]; uy[c] = (real)un[1]; uz[c] = (real)un[2];
         for (int q = 0; q < 5; ++q) macc[q * nn + c] = 0.0;
+        dsum = d;
     }
-    block_add_d(d, ledger);
+    block_add_d(dsum, ledger);
 }
 
 // Spawn of node c (kinetic, fluid mass >= wmin).
@@ -560,13 +563,15 @@ __device__ inline void spawn_node(const GridP &g, const SpecP &sp, int isp, long
 // node grid (two loads per node) that lists them for k_spawn.
 __global__ void __launch_bounds__(BS)
 k_spawn_find(GridP g, const uint8_t *__restrict__ sw, const real *__restrict__ n, real wmin,
-             int *__restrict__ list, int *__restrict__ list_n) {
+             int *__restrict__ list, int *__restrict__ list_n, const int *__restrict__ xr) {
     const long long c = xcd_node();
     bool want = false;
     if (c < g.nn) {
         const int i = (int)(c % g.sx);
         const int nxn = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
-        want = i < nxn && sw[c] && n[c] * (g.dx * g.dy * g.dz) >= wmin && n[c] > (real)0;
+        // fluid only inside the species' x window
+        want = i < nxn && i >= xr[0] && i <= xr[1] && sw[c] && n[c] * (g.dx * g.dy * g.dz) >= wmin &&
+               n[c] > (real)0;
     }
     const uint64_t b = __ballot(want);
     if (!b) return;
@@ -623,15 +628,15 @@ void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, c
     k_dilate<<<xcd_blocks(g.nn), BS, 0, s>>>(g, P, hot, notcold, sw, calm);
 }
 void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n, real *ux,
-                                real *uy, real *uz, WarmP w, double *ledger, hipStream_t s) {
-    k_absorb_finish<<<blocks(g.nn), BS, 0, s>>>(g, mass, macc, n, ux, uy, uz, w, ledger);
+                                real *uy, real *uz, WarmP w, double *ledger, const int *xr, hipStream_t s) {
+    k_absorb_finish<<<blocks(g.nn), BS, 0, s>>>(g, mass, macc, n, ux, uy, uz, w, ledger, xr);
 }
 void launch_spawn_nodes(const GridP &g, const SpecP &sp, int isp, const uint8_t *sw, real *n, real *ux,
                         real *uy, real *uz, WarmP w, jglob_t *jg, real wmin, real w0, uint64_t seed,
                         int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
                         unsigned *wmax_bits, unsigned *umax2, double *ledger, int *list, int *list_n,
-                        hipStream_t s) {
-    k_spawn_find<<<xcd_blocks(g.nn), BS, 0, s>>>(g, sw, n, wmin, list, list_n);
+                        const int *xr, hipStream_t s) {
+    k_spawn_find<<<xcd_blocks(g.nn), BS, 0, s>>>(g, sw, n, wmin, list, list_n, xr);
     k_spawn<<<1024, BS, 0, s>>>(g, sp, isp, n, ux, uy, uz, w, jg, jg + g.nn, jg + 2 * g.nn, w0, seed, step,
                                 inbox, inbox_n, inbox_cap, deferred, wmax_bits, umax2, ledger, list, list_n);
 }
