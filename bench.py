@@ -1,23 +1,26 @@
 #!/usr/bin/env python
 """Benchmark of the hybrid fluid-kinetic step on one MI355X.
 
-Workload: the ionizing-helium case (128 x 64 x 64 cells, dx = 0.1, 8 particles
-per cell, neutral He 0.1 n_c with a 10-lambda up-ramp, a0 = 10 linear pulse,
-waist 6 lambda, duration 15, ADK/multiphoton ionization, threshold switch).
-The same seed runs on the same GPU as hybrid (threshold switch) and as all-PIC
-(every node kinetic).  Each mode first runs W untimed warm-up steps on a
-throwaway simulation; then a fresh simulation runs steps 0..K from t = 0 under
-the clock (device synchronisation on both sides; the field snapshot at K/2 is
-taken outside the clock).  An untimed repeat of the all-PIC run measures the
-run-to-run floor of the field comparison (FP32 atomics sum in varying order).
+Workload: the full-size foil, 512 x 256 x 256 cells (33.5 M), dx = 0.05; a
+pre-ionized hydrogen foil at 10 n_c, 1 lambda thick from x = 3.2, 16
+particles per cell per species (132 M electrons and 132 M protons), mobile
+protons, photon emission and pair creation on; a circular pulse (a0 = 5 by
+default; 50 and 200 complete the sweep), waist 3 lambda, field half-width 10
+centred at t = 20.  The hybrid (threshold switch re-evaluated every 10 steps,
+hot particles |u| >= 0.1 kept kinetic) and all-PIC (every node kinetic) run the
+same seed on the same GPU.  Each mode first advances W steps untimed (the
+pulse front reaches the foil near step 300), then K steps run under the clock
+(device synchronisation on both sides).  An all-PIC run with another seed
+gives the field difference that sampling noise alone makes (the floor of any
+comparison with one all-PIC run).
 
-The JSON line reports hybrid steps/s (value), all-PIC steps/s, the speed-up,
-particle pushes/s, the field relative L2 of hybrid vs all-PIC (and of the
-all-PIC repeat) at K/2 and K, the energy difference at K, the push kernel's
-achieved HBM rate against the roofline
-(algorithmic bytes: 60 B per particle push plus 36 B per cell of every tile
-with particles, over the kernel's own time from HIP events on the library
-stream), and the FP64 CPU oracle timed on a bounded sample of the same physics.
+The JSON line reports the hybrid / all-PIC steps/s ratio (value), both
+rates, particle pushes/s, cell-steps/s, the field relative L2 of hybrid vs
+all-PIC at step W + K (and of all-PIC vs all-PIC with another seed), the
+energy difference, the kinetic fractions, the push kernel's achieved HBM rate
+against the roofline (algorithmic bytes over the kernel's own time from HIP
+events on the library stream), the FP64 error of the FP32 step, and the FP64
+CPU oracle timed on a bounded sample of the same physics.
 """
 from __future__ import annotations
 
@@ -33,14 +36,23 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-BYTES_PER_PUSH = 60            # read offsets, u, w, cell (32 B); write offsets, u, cell (28 B)
+# algorithmic bytes per particle push: read cell, offsets, u, w (32 B), write
+# cell, offsets, u (28 B); a QED lepton also reads and writes its FP64
+# optical depth (16 B) and carries its id (8 B)
+BYTES_PER_PUSH = 60
+BYTES_PER_QED_PUSH = 84
 BYTES_PER_TILE_CELL = 36       # E, B gather (24 B) + J flush (12 B) per cell of a kinetic tile
 TILE_CELLS = 512
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_push_traffic_ionization_128x64x64.txt")
 PUSH_SOURCES = ("paper_2510_11174_amd/csrc/k_particles.hip", "paper_2510_11174_amd/csrc/hk_pic_device.h",
                 "paper_2510_11174_amd/csrc/hk_internal.h")
 FLUID_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fluid_traffic_plain_256x128x128.txt")
 FLUID_SOURCES = ("paper_2510_11174_amd/csrc/k_fluid.hip", "paper_2510_11174_amd/csrc/hk_internal.h")
+FULL_GRID = (512, 256, 256)
+HOT = 0.1                      # hot-particle threshold of the hybrid (|u|)
+
+
+def traffic_file(a0):
+    return os.path.join(ROOT, "profiles", "k_push_traffic_full_foil_a%g.txt" % a0)
 
 
 def source_hash(files=PUSH_SOURCES):
@@ -52,10 +64,10 @@ def source_hash(files=PUSH_SOURCES):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(path=TRAFFIC_FILE, files=PUSH_SOURCES, key="bytes_per_launch"):
+def measured_traffic(path, files=PUSH_SOURCES, key="bytes_per_launch", window=None):
     """HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration)
-    recorded in a profiles/ summary, or None if missing or taken on other kernel
-    sources.  Default: per k_push launch."""
+    recorded in a profiles/ summary, or None if missing, taken on other kernel
+    sources, or (window given) over another step window."""
     try:
         kv = {}
         with open(path) as fh:
@@ -64,6 +76,8 @@ def measured_traffic(path=TRAFFIC_FILE, files=PUSH_SOURCES, key="bytes_per_launc
                     k, v = line.split("=", 1)
                     kv[k.strip()] = v.strip()
         if kv.get("source_hash") != source_hash(files):
+            return None
+        if window is not None and kv.get("window") != window:
             return None
         return float(kv[key])
     except (OSError, KeyError, ValueError):
@@ -82,72 +96,173 @@ def copy_calibration(mib=1024, reps=5):
     print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "reps": reps}))
 
 
-def run_gpu(cfg, steps, precision, timing=True, snap_at=None):
-    """Run `steps` steps of a fresh simulation from t = 0.  The clock covers the
-    steps only (device synchronisation on both sides of each timed segment); a
-    field snapshot at step `snap_at` is taken outside the clock."""
+def workload(a0, mode, seed=None, grid=FULL_GRID):
+    from paper_2510_11174_amd import configs
+    cfg = configs.full_foil(a0, *grid, mode=mode, seed=seed)
+    cfg["run"]["thr_hot"] = HOT
+    return cfg
+
+
+def run_window(cfg, warmup, steps, precision="f32", timing=True, snap=True):
+    """W untimed steps, then K steps under the clock (device synchronisation on
+    both sides); timers (HIP events on the library stream) cover the K steps."""
     import numpy as np
     import torch
 
     from paper_2510_11174_amd import hk
+    t0 = time.perf_counter()
     sim = hk.Sim(cfg, precision=precision)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t0
+    if warmup:
+        sim.step(warmup)
+    d0 = sim.diagnostics()
     sim.enable_timing(timing)
-    segs = [steps] if not snap_at else [snap_at, steps - snap_at]
-    seconds = 0.0
-    snaps = {}
-    done = 0
-    for n in segs:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sim.step(n)
-        torch.cuda.synchronize()
-        seconds += time.perf_counter() - t0
-        done += n
-        snaps[done] = {c: sim.get_field(c).astype(np.float64) for c in ("ex", "ey", "ez", "bx", "by", "bz")}
-    tm = sim.timers()
-    d = sim.diagnostics()
-    kin = d["kinetic_fraction"]
-    sim.close()
-    return {"seconds": seconds, "timers": tm, "diag": d, "snaps": snaps, "kinetic_fraction": kin}
-
-
-def warm_up(cfg, steps, precision):
-    """Untimed warm-up: the same configuration on a throwaway simulation."""
-    import torch
-
-    from paper_2510_11174_amd import hk
-    sim = hk.Sim(cfg, precision=precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     sim.step(steps)
     torch.cuda.synchronize()
+    seconds = time.perf_counter() - t0
+    tm = sim.timers() if timing else {}
+    d = sim.diagnostics()
+    snaps = {c: sim.get_field(c).astype(np.float64) for c in ("ex", "ey", "ez", "bx", "by", "bz")} if snap else None
     sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {"seconds": seconds, "timers": tm, "diag0": d0, "diag": d, "snaps": snaps, "create_s": create_s}
 
 
 def total_energy(d):
-    return (d["u_e"] + d["u_b"] + sum(d["kin"]) + sum(d["fluid_kin"]) + d["conv_loss"]
+    return (d["u_e"] + d["u_b"] + sum(d["kin"]) + sum(d["fluid_kin"]) + sum(d["fluid_th"]) + d["conv_loss"]
             + d["ion_energy"] + d["photon_energy"])
 
 
-def cpu_baseline(warm=60, timed=50):
-    """FP64 oracle on a 64 x 32 x 32 crop of the same physics (threshold switch),
-    single thread; steps/s scaled to the full grid by the cell ratio."""
+def field_l2(x, y):
+    import numpy as np
+    num = math.sqrt(sum(float(np.sum((x[c] - y[c]) ** 2)) for c in x))
+    den = math.sqrt(sum(float(np.sum(y[c] ** 2)) for c in y))
+    return num / den if den > 0 else 0.0
+
+
+def push_roofline(r, kind_bytes):
+    """k_push over the timed window: algorithmic bytes (per species: particles
+    in the window's diagnostics times the steps, 84 B for a QED lepton, 60 B
+    otherwise, plus 36 B per cell of every tile pushed) over the push's own
+    time (HIP events on the library stream)."""
+    tm = r["timers"]
+    ms = tm["push_kernel_ms"]
+    launches = max(tm["push_launches"], 1)
+    alg = kind_bytes * 1.0 + BYTES_PER_TILE_CELL * TILE_CELLS * tm["tiles_pushed"]
+    achieved = alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": "k_push", "avg_launch_ms": round(ms / launches, 4),
+            "launches": int(launches), "alg_bytes_per_launch": round(alg / launches)}
+
+
+def particle_bytes(cfg, r, steps):
+    """Algorithmic push bytes of a window: each species' count (mean of the
+    window's first and last diagnostics) times steps times its bytes per push."""
+    tot = 0.0
+    for i, sp in enumerate(cfg["species"]):
+        n = 0.5 * (r["diag0"]["count"][i] + r["diag"]["count"][i])
+        qed = sp.get("qed") and sp["kind"] in ("electron", "positron")
+        if sp["kind"] == "photon":
+            continue
+        tot += n * steps * (BYTES_PER_QED_PUSH if qed else BYTES_PER_PUSH)
+    return tot
+
+
+def fp64_error(steps=200):
+    """FP64 error of the FP32 step on a crop of the foil physics: the FP32 and
+    FP64 builds run the same 128 x 64 x 64 hybrid (foil from x = 1.6, a0 = 5,
+    pulse centred at t = 4) for `steps` steps; the field relative L2 between
+    them, the relative total-energy difference and the kinetic fractions."""
+    import numpy as np
+
+    from paper_2510_11174_amd import configs, hk
+    cfg = configs.full_foil(5.0, 128, 64, 64, mode="threshold")
+    cfg["run"]["thr_hot"] = HOT
+    for sp in cfg["species"]:
+        if sp.get("profile") == "foil":
+            sp["x0"] = 1.6
+    cfg["laser"]["t_center"] = 4.0
+    out = {}
+    for prec in ("f32", "f64"):
+        sim = hk.Sim(cfg, precision=prec)
+        sim.step(steps)
+        out[prec] = ({c: sim.get_field(c).astype(np.float64) for c in ("ex", "ey", "ez", "bx", "by", "bz")},
+                     sim.diagnostics())
+        sim.close()
+    f32, f64 = out["f32"], out["f64"]
+    e32, e64 = total_energy(f32[1]), total_energy(f64[1])
+    return {"field_rel_l2_f32_vs_f64": field_l2(f32[0], f64[0]),
+            "energy_rel_diff_f32_vs_f64": abs(e32 - e64) / abs(e64) if e64 else 0.0,
+            "kinetic_fraction_f32": f32[1]["kinetic_fraction"], "kinetic_fraction_f64": f64[1]["kinetic_fraction"],
+            "workload": "hybrid foil crop 128x64x64 (foil from x = 1.6, a0 5, pulse centre t = 4), %d steps" % steps}
+
+
+def _oracle_rate(args):
+    """One oracle process: the crop of the foil physics, `steps` timed steps."""
+    nx, ny, nz, steps, warm, mode = args
     import oracle
     from paper_2510_11174_amd import configs
-    oracle.build(force=False)
-    cfg = configs.ionization_hybrid(64, 32, 32, mode="threshold")
+    cfg = configs.full_foil(5.0, nx, ny, nz, mode=mode)
+    cfg["run"]["thr_hot"] = HOT
+    for sp in cfg["species"]:
+        if sp.get("profile") == "foil":
+            sp["x0"] = 1.6
+    cfg["laser"]["t_center"] = 4.0
     o = oracle.Oracle(cfg)
     o.step(warm)
-    n = o.count(0)
+    n = sum(o.count(i) for i in range(len(cfg["species"])))
     t0 = time.perf_counter()
-    o.step(timed)
+    o.step(steps)
     dt = time.perf_counter() - t0
-    full_cells = 128 * 64 * 64
-    crop_cells = 64 * 32 * 32
-    return {"value": timed / dt * crop_cells / full_cells, "unit": "steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "FP64 oracle, 64x32x32 crop of the ionizing-helium case, threshold switch, "
-                      "steps %d-%d, %.1f s; steps/s scaled by the cell ratio %d" % (
-                          warm, warm + timed, dt, full_cells // crop_cells),
-            "pushes_per_s": n * timed / dt}
+    return steps / dt, n * steps / dt
+
+
+def cpu_baseline(steps=4, warm=1, crop=(64, 32, 32)):
+    """The FP64 oracle (plain C loops, as it stands) on a crop of the foil
+    physics (64 x 32 x 32 cells, foil from x = 1.6, hybrid threshold switch):
+    one process on one core, and one process per host core at once (independent
+    crops: the rate a domain decomposition over every core would reach at
+    best).  Steps/s are scaled to the full 512 x 256 x 256 grid by the cell
+    ratio."""
+    import multiprocessing as mp
+    import platform
+    import oracle
+    oracle.build(force=False)
+    nx, ny, nz = crop
+    scale = (nx * ny * nz) / float(FULL_GRID[0] * FULL_GRID[1] * FULL_GRID[2])
+    t0 = time.perf_counter()
+    one = _oracle_rate((nx, ny, nz, steps, warm, "threshold"))
+    t_one = time.perf_counter() - t0
+    cores = min(os.cpu_count() or 1, 16)
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        many = pool.map(_oracle_rate, [(nx, ny, nz, steps, warm, "threshold")] * cores)
+    t_many = time.perf_counter() - t0
+    agg_sps = sum(r[0] for r in many)
+    agg_pps = sum(r[1] for r in many)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": round(agg_sps * scale, 6), "unit": "steps/s", "cores": cores, "kind": "oracle",
+            "sample": "FP64 oracle, hybrid threshold switch on a %dx%dx%d crop of the foil physics (foil from "
+                      "x = 1.6, a0 5, pulse centre t = 4), steps %d-%d, one process per core on %d cores "
+                      "(%.1f s); steps/s scaled to the 512x256x256 grid by the cell ratio %.0f" % (
+                          nx, ny, nz, warm, warm + steps, cores, t_many, 1 / scale),
+            "pushes_per_s": round(agg_pps, 1),
+            "one_core": {"steps_per_s_scaled": round(one[0] * scale, 8), "pushes_per_s": round(one[1], 1),
+                         "seconds": round(t_one, 1)},
+            "host": {"nproc": os.cpu_count(), "cpu": model, "machine": platform.machine()}}
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16
@@ -156,8 +271,9 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16
 def cnn_inference(reps=20):
     """One learned-switch evaluation's network pass on the ionizing-helium node
     grid (129 x 64 x 64 nodes with the 4-node halo), timed with HIP events on
-    the library stream; flops are those of the four valid convolutions and the head."""
-    import numpy as np
+    the library stream.  Algorithmic flops are those of the nodes the switch
+    decides: 179,776 per node for the four convolutions and the head (the
+    halo's partial layers are overhead, not counted)."""
     import torch
 
     from paper_2510_11174_amd import hk
@@ -166,10 +282,9 @@ def cnn_inference(reps=20):
     cnn = hk.CNN(seed=1)
     cnn.set_params(T.init_params(1))
     x = torch.randn((1, D, H, W, 8), device="cuda", dtype=torch.float32)
-    flops = 0
-    for l, cin in enumerate((8, 32, 32, 32)):
-        flops += 2 * 27 * cin * 32 * (D - 2 * l - 2) * (H - 2 * l - 2) * (W - 2 * l - 2)
-    flops += 2 * 32 * (D - 8) * (H - 8) * (W - 8)
+    per_node = 2 * 27 * (8 * 32 + 3 * 32 * 32) + 2 * 32
+    nodes = (D - 8) * (H - 8) * (W - 8)
+    flops = per_node * nodes
     cnn.forward(x)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -183,8 +298,8 @@ def cnn_inference(reps=20):
     tf = flops / (ms * 1e-3) / 1e12
     return {"bound": "mfma", "achieved": round(tf, 1), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4), "kernel": "k_conv_fwd (4 layers) + k_head",
-            "ms_per_eval": round(ms, 3), "flop_per_eval": flops,
-            "grid": "129 x 64 x 64 nodes + halo 4"}
+            "ms_per_eval": round(ms, 3), "flop_per_node": per_node, "nodes": nodes, "flop_per_eval": flops,
+            "grid": "129 x 64 x 64 nodes (+ halo 4)"}
 
 
 SP_CIN, SP_COUT = (10, 13, 32, 64, 128, 32), (13, 32, 64, 128, 32, 10)
@@ -302,8 +417,8 @@ def warm_fluid(steps=200, warmup=20, nx=256, ny=128, nz=128):
     fluid at the first step, then laser and fluid only), warm (adiabatic,
     gamma 5/3) and cold.  Time: the library's HIP events around the fluid
     passes on its stream, over `steps` steps after `warmup`.  Algorithmic
-    bytes per node and step: read n, u, E, B, J and write n, u, J (20 values),
-    plus read and write S for the warm fluid (22), in the build's real type."""
+    bytes per node and step: read n, u (4), E, B (6), J (3) and write n, u (4):
+    17 values, 68 B in FP32; a warm fluid also reads and writes S (76 B)."""
     from paper_2510_11174_amd import configs, hk
     out = {}
     nodes = (nx + 1) * ny * nz
@@ -323,32 +438,59 @@ def warm_fluid(steps=200, warmup=20, nx=256, ny=128, nz=128):
         d = sim.diagnostics()
         sim.close()
         ms = tm["fluid_ms"] / steps
-        alg = (22 if ga > 0 else 20) * 4 * nodes
+        alg = (19 if ga > 0 else 17) * 4 * nodes
         gbs = alg / (ms * 1e-3) / 1e9
         out[name] = {"ms_fluid_per_step": round(ms, 4), "alg_bytes_per_step": alg,
                      "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "steps_per_s": round(steps / sec, 1), "fluid_heat": d["fluid_th"][0]}
-    w = out["warm"]
-    traffic = measured_traffic(FLUID_TRAFFIC_FILE, FLUID_SOURCES, "bytes_per_step_warm")
-    return {"bound": "hbm", "achieved": w["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": w["frac"],
-            "traffic": traffic, "kernel": "k_fluid_lorentz + k_fluid_update (warm)", "nodes": nodes,
+    c = out["cold"]
+    traffic = measured_traffic(FLUID_TRAFFIC_FILE, FLUID_SOURCES, "bytes_per_step_cold")
+    return {"bound": "hbm", "achieved": c["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": c["frac"],
+            "traffic": traffic, "kernel": "k_fluid_lorentz + k_fluid_update (cold)", "nodes": nodes,
             "workload": "plain plasma %dx%dx%d, all fluid, u_th 0.05" % (nx, ny, nz), **{k: v for k, v in out.items()}}
 
 
-def field_l2(x, y):
-    import numpy as np
-    num = math.sqrt(sum(float(np.sum((x[c] - y[c]) ** 2)) for c in x))
-    den = math.sqrt(sum(float(np.sum(y[c] ** 2)) for c in y))
-    return num / den if den > 0 else 0.0
+def summarize_pmc(db_dir, kernel, skip):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of `kernel` in a rocprofv3
+    --pmc result database, averaged over the dispatches after the first
+    `skip` (the untimed advance); printed as a profiles/ summary block."""
+    import glob
+    import sqlite3
+    dbs = glob.glob(os.path.join(db_dir, "**", "*results.db"), recursive=True)
+    if not dbs:
+        print("no rocprofv3 database under %s" % db_dir, file=sys.stderr)
+        sys.exit(1)
+    con = sqlite3.connect(dbs[0])
+    cur = con.cursor()
+    tabs = [r[0] for r in cur.execute("select name from sqlite_master where type in ('table','view')")]
+    pmc = [t for t in tabs if t == "pmc_events" or t.startswith("pmc_event")]
+    rows = []
+    if "counters_collection" in tabs:
+        rows = cur.execute("select dispatch_id, kernel_name, counter_name, value from counters_collection").fetchall()
+    elif pmc:
+        rows = cur.execute("select * from %s" % pmc[0]).fetchall()
+    per = {}
+    for did, name, cname, val in rows:
+        if kernel in name:
+            per.setdefault(cname, {}).setdefault(did, 0.0)
+            per[cname][did] += float(val)
+    for cname, d in per.items():
+        ids = sorted(d)[skip:]
+        vals = [d[i] for i in ids]
+        print("%s: dispatches %d (after %d), mean %.1f KiB" % (cname, len(vals), skip,
+                                                               sum(vals) / max(len(vals), 1)))
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=500, help="timed steps per mode (K)")
+    ap.add_argument("--warmup", type=int, default=300, help="untimed steps before the clock (W)")
+    ap.add_argument("--a0", type=float, default=5.0, help="pulse amplitude of the foil workload")
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the workload's modes (no seed floor, networks, fluid, search, FP64 check)")
     ap.add_argument("--modes", default="threshold,all_pic",
                     help="comma list of switch modes to run (profiling runs may pick one)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -356,9 +498,15 @@ def main():
     ap.add_argument("--warm-fluid-only", action="store_true",
                     help="only measure the fluid phase (warm and cold) on the all-fluid 256x128x128 plasma")
     ap.add_argument("--networks-only", action="store_true",
-                    help="only measure the next-state surrogate (64 patches of 16^3) and SwitchNet (the "
-                         "ionizing-helium node grid) and print their JSON")
+                    help="only measure the switch CNN, the next-state surrogate and SwitchNet and print their JSON")
+    ap.add_argument("--summarize-pmc", metavar="DIR",
+                    help="print per-dispatch counter means of k_push from a rocprofv3 --pmc output DIR")
+    ap.add_argument("--skip-dispatches", type=int, default=0)
+    ap.add_argument("--kernel", default="k_push")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc, args.kernel, args.skip_dispatches)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the multi-GPU path (domain decomposition) is not "
               "implemented by this library; run with --gpus 1", file=sys.stderr)
@@ -367,9 +515,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    from paper_2510_11174_amd import configs
     if args.networks_only:
-        print(json.dumps({"roofline_state_predictor": sp_surrogate(), "roofline_switchnet": swn_inference()}))
+        print(json.dumps({"roofline_cnn_switch": cnn_inference(), "roofline_state_predictor": sp_surrogate(),
+                          "roofline_switchnet": swn_inference()}))
         return
     if args.calibrate_copy:
         copy_calibration()
@@ -378,52 +526,50 @@ def main():
         print(json.dumps({"roofline_warm_fluid": warm_fluid()}))
         return
 
-    W, K = args.warmup, args.steps
-    half = K // 2 if K >= 2 else None
+    W, K, a0 = args.warmup, args.steps, args.a0
     modes = [m for m in args.modes.split(",") if m]
     if any(m not in ("threshold", "all_pic") for m in modes) or not modes:
         print("--modes takes threshold and/or all_pic", file=sys.stderr)
         sys.exit(2)
-    res = {}
+    window = "a0 %g, steps %d-%d" % (a0, W, W + K)
+    res, cfgs = {}, {}
     for mode in modes:
-        cfg = configs.ionization_hybrid(mode=mode)
-        print("bench: %s %s warm-up %d, timed steps 0-%d" % (cfg["name"], mode, W, K), file=sys.stderr,
-              flush=True)
-        if W > 0:
-            warm_up(cfg, W, args.precision)
-        res[mode] = run_gpu(cfg, K, args.precision, snap_at=half)
+        cfg = workload(a0, mode)
+        cfgs[mode] = cfg
+        print("bench: %s %s: steps 0-%d untimed, %d-%d timed" % (cfg["name"], mode, W, W, W + K),
+              file=sys.stderr, flush=True)
+        res[mode] = run_window(cfg, W, K, args.precision)
+        print("bench: %s %.3f ms/step" % (mode, 1e3 * res[mode]["seconds"] / K), file=sys.stderr, flush=True)
     if len(res) < 2:
         r = next(iter(res.values()))
-        print(json.dumps({"mode": modes[0], "steps_per_s": K / r["seconds"], "timers": r["timers"]}))
+        print(json.dumps({"mode": modes[0], "steps_per_s": K / r["seconds"], "timers": r["timers"],
+                          "window": window}))
         return
     h, p = res["threshold"], res["all_pic"]
-    # the same all-PIC run again: FP32 atomics make the sums order dependent,
-    # so two identical runs differ; this is the floor of any comparison
-    print("bench: all-PIC repeat (run-to-run floor)", file=sys.stderr, flush=True)
-    p2 = run_gpu(configs.ionization_hybrid(mode="all_pic"), K, args.precision, timing=False, snap_at=half)
-    hyb_sps = K / h["seconds"]
-    pic_sps = K / p["seconds"]
-    l2 = {s: field_l2(h["snaps"][s], p["snaps"][s]) for s in p["snaps"]}
-    floor = {s: field_l2(p2["snaps"][s], p["snaps"][s]) for s in p["snaps"]}
+    floor = None
+    if not args.no_extras:
+        # the same all-PIC with another seed: the sampling-noise floor of a
+        # comparison with one all-PIC run
+        print("bench: all-PIC with another seed (sampling floor)", file=sys.stderr, flush=True)
+        p2 = run_window(workload(a0, "all_pic", seed=cfgs["all_pic"]["run"]["seed"] + 7919), W, K,
+                        args.precision, timing=False)
+        floor = field_l2(p2["snaps"], p["snaps"])
+    hyb_sps, pic_sps = K / h["seconds"], K / p["seconds"]
+    l2 = field_l2(h["snaps"], p["snaps"])
     e_h, e_p = total_energy(h["diag"]), total_energy(p["diag"])
     drift = abs(e_h - e_p) / abs(e_p) if e_p else 0.0
-    traffic = measured_traffic()
-
-    def roof(r, with_traffic):
-        tm = r["timers"]
-        ms = tm["push_kernel_ms"]
-        alg = BYTES_PER_PUSH * tm["particles_pushed"] + BYTES_PER_TILE_CELL * TILE_CELLS * tm["tiles_pushed"]
-        launches = max(tm["push_launches"], 1)
-        achieved = alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic if with_traffic else None,
-                "kernel": "k_push", "avg_launch_ms": round(ms / launches, 4),
-                "alg_bytes_per_launch": round(alg / launches)}
-
+    cells = FULL_GRID[0] * FULL_GRID[1] * FULL_GRID[2]
+    traffic = measured_traffic(traffic_file(a0), window=window)
+    roof = push_roofline(p, particle_bytes(cfgs["all_pic"], p, K))
+    roof["traffic"] = traffic
+    roof_h = push_roofline(h, particle_bytes(cfgs["threshold"], h, K))
+    roof_h["traffic"] = None
+    parts_h = sum(h["diag"]["count"][:2]) + sum(h["diag0"]["count"][:2])
+    parts_p = sum(p["diag"]["count"][:2]) + sum(p["diag0"]["count"][:2])
     out = {
         "metric": "hybrid steps/s vs all-PIC on same GPU at field err <=1e-3; particle pushes/s",
-        "value": round(hyb_sps, 2),
-        "unit": "steps/s",
+        "value": round(hyb_sps / pic_sps, 3),
+        "unit": "x (hybrid / all-PIC steps/s)",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
@@ -433,45 +579,47 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "f32" else "f64",
         "data": "synthetic",
-        "config": {"workload": "ionizing helium 128x64x64, dx 0.1, 8 ppc, a0 10, threshold switch "
-                               "vs all-PIC, steps 0-%d from t = 0" % K,
-                   "grid": [128, 64, 64], "ppc": 8, "switch": "threshold"},
+        "config": {"workload": "full-size learned-hybrid workload, foil target: 512x256x256 cells, dx 0.05, "
+                               "H foil 10 n_c 1 lambda thick, 16 ppc per species, QED on, CP a0 %g; threshold "
+                               "switch every 10 steps (hot |u| >= %g kinetic) vs all-PIC, same seed; steps %d-%d "
+                               "timed after %d untimed" % (a0, HOT, W, W + K, W),
+                   "grid": list(FULL_GRID), "ppc": 16, "a0": a0, "switch": "threshold", "switch_every": 10},
+        "hybrid_steps_per_s": round(hyb_sps, 2),
         "allpic_steps_per_s": round(pic_sps, 2),
-        "speedup_vs_allpic": round(hyb_sps / pic_sps, 3),
         "pushes_per_s": round(h["timers"]["particles_pushed"] / h["seconds"], 1),
         "allpic_pushes_per_s": round(p["timers"]["particles_pushed"] / p["seconds"], 1),
-        "cell_steps_per_s": round(128 * 64 * 64 * hyb_sps, 1),
-        "field_rel_l2_vs_allpic": {str(k): v for k, v in l2.items()},
-        "field_rel_l2_allpic_repeat": {str(k): v for k, v in floor.items()},
+        "cell_steps_per_s": round(cells * hyb_sps, 1),
+        "allpic_cell_steps_per_s": round(cells * pic_sps, 1),
+        "field_rel_l2_vs_allpic": l2,
+        "field_rel_l2_allpic_other_seed": floor,
         "energy_diff_vs_allpic": drift,
-        # the hybrid meets 1e-3 at every snapshot where two all-PIC runs agree to
-        # 1e-3; where they do not (FP32 atomics and a chaotic plasma), it must lie
-        # within 10% of their distance, a single sample of the run-to-run noise
-        "field_err_ok": all(l2[s] <= 1e-3 if floor[s] <= 1e-3 else l2[s] <= 1.1 * floor[s] for s in l2),
-        "field_err_over_floor": {str(k): round(l2[k] / floor[k], 4) if floor[k] > 0 else None for k in l2},
-        "kinetic_fraction_end": h["kinetic_fraction"],
-        "roofline": roof(p, True),
-        "roofline_hybrid": roof(h, False),
+        "field_err_ok": bool(l2 <= 1e-3 and drift <= 1e-3),
+        "within_pic_sampling_floor": None if floor is None else bool(l2 <= floor),
+        "kinetic_fraction_nodes": h["diag"]["kinetic_fraction"],
+        "particle_fraction_vs_allpic": round(parts_h / parts_p, 4) if parts_p else None,
+        "roofline": roof,
+        "roofline_hybrid": roof_h,
         "timers_hybrid_ms_per_step": {k: round(v / K, 4) for k, v in h["timers"].items() if k.endswith("_ms")},
         "timers_allpic_ms_per_step": {k: round(v / K, 4) for k, v in p["timers"].items() if k.endswith("_ms")},
         "rebins": {"hybrid": h["timers"]["rebins"], "all_pic": p["timers"]["rebins"]},
+        "create_s": {"hybrid": round(h["create_s"], 2), "all_pic": round(p["create_s"], 2)},
     }
     # the field update (Yee, Mur walls, antenna) of the all-PIC run, from its
     # HIP-event phase timer; algorithmic bytes per cell and step: read E, B and
-    # write B, then read E, B, J and write E (84 B; the two B half steps that
-    # give B at whole steps for the push move 120 B)
-    cells = 128 * 64 * 64
+    # write B, then read E, B, J and write E (84 B)
     f_ms = p["timers"]["fields_ms"] / K
     yee_gbs = 84 * cells / (f_ms * 1e-3) / 1e9 if f_ms > 0 else 0.0
     out["roofline_yee"] = {"bound": "hbm", "achieved": round(yee_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(yee_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                           "kernel": "k_b_half x2 + k_e_full + k_mur_save + k_mur_apply + k_antenna",
+                           "kernel": "k_jconvert + k_b_half x2 + k_e_full + k_mur_save + k_mur_apply + k_antenna",
                            "ms_per_step": round(f_ms, 4), "alg_bytes_per_step": 84 * cells}
-    out["roofline_cnn_switch"] = cnn_inference()
-    out["roofline_state_predictor"] = sp_surrogate()
-    out["roofline_switchnet"] = swn_inference()
-    out["roofline_warm_fluid"] = warm_fluid()
-    out["laser_search"] = laser_search()
+    if not args.no_extras:
+        out["fp64_error"] = fp64_error()
+        out["roofline_cnn_switch"] = cnn_inference()
+        out["roofline_state_predictor"] = sp_surrogate()
+        out["roofline_switchnet"] = swn_inference()
+        out["roofline_warm_fluid"] = warm_fluid()
+        out["laser_search"] = laser_search()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

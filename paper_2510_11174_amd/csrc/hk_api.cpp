@@ -325,9 +325,18 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     PArr nbuf[2];
     if (!reuse) {
         const long long n_alloc = slots + (large ? slots / 8 : slots / 4);
+        // the idle buffer holds nothing: free it before the new pair is taken,
+        // so the peak is the current buffer plus the new pair
+        HIPCHK(S, hipStreamSynchronize(S->s));
+        free_parr(S, D.buf[1 - D.cur]);
+        D.buf[1 - D.cur] = PArr{};
         if (!alloc_parr(S, nbuf[0], n_alloc, D.has_z, D.has_tau) ||
-            !alloc_parr(S, nbuf[1], n_alloc, D.has_z, D.has_tau))
+            !alloc_parr(S, nbuf[1], n_alloc, D.has_z, D.has_tau)) {
+            free_parr(S, nbuf[0]);
+            free_parr(S, nbuf[1]);
+            S->poisoned = 1;
             return fail(S, HK_ENOMEM, "rebuild: %lld particle slots", n_alloc);
+        }
         // the push addresses its output through the input's field pointers plus
         // one byte distance: both buffers must have the same layout
         if (!same_layout(nbuf[0], nbuf[1])) return fail(S, HK_ENOMEM, "rebuild: buffer layouts differ");
@@ -411,8 +420,14 @@ int ensure_inbox(hk_sim *S, int isp, long long need) {
     c = std::min<long long>(c, INT_MAX / 2);
     free_parr(S, D.inbox);
     free_parr(S, D.fail);
-    if (!alloc_parr(S, D.inbox, c, D.has_z, D.has_tau) || !alloc_parr(S, D.fail, c, D.has_z, D.has_tau))
+    if (!alloc_parr(S, D.inbox, c, D.has_z, D.has_tau) || !alloc_parr(S, D.fail, c, D.has_z, D.has_tau)) {
+        // no inbox now: kernels must not see the old capacity
+        free_parr(S, D.inbox);
+        free_parr(S, D.fail);
+        D.inbox_cap = 0;
+        S->poisoned = 1;
         return fail(S, HK_ENOMEM, "inbox of %lld", c);
+    }
     D.inbox_cap = (int)c;
     if (!D.inbox_dev) D.inbox_dev = (PArr *)dalloc(S, sizeof(PArr));
     if (!D.inbox_dev) return fail(S, HK_ENOMEM, "inbox descriptor");
@@ -606,12 +621,14 @@ int push_mode(const hk_sim *S, int isp) {
 
 // Inbox size of a species: the particles one step can send past full bins
 // (a quarter of the capacity; bins keep 25% headroom) plus every electron the
-// ions targeting it can free in one step.
+// ions targeting it can free in one step, plus room for spawning (a quarter
+// of the capacity: a node whose particles find no room stays fluid and
+// spawns in a later step).
 long long inbox_need(hk_sim *S, int isp) {
     long long need = std::max<long long>(S->sp[isp].capacity / 4, 1 << 16);
     if (S->sp[isp].d.fluid && S->run.switch_mode != HK_SW_ALL_PIC)
         need += std::min<long long>(S->g.nn * std::max(1, S->sp[isp].d.ppc),
-                                    std::max<long long>(S->sp[isp].capacity, 1 << 20));
+                                    std::max<long long>(S->sp[isp].capacity / 4, 1 << 20));
     for (int j = 0; j < S->nsp; ++j)
         if (S->sp[j].d.ionizable && S->sp[j].d.target == isp && S->run.enable_ionization)
             need += S->sp[j].capacity * std::max(1, S->sp[j].d.z_max);
@@ -1367,7 +1384,12 @@ int hk_step(hk_sim *S, int nsteps) {
     }
     for (int n = 0; n < nsteps; ++n) {
         int rc = one_step(S);
-        if (rc) return rc;
+        // a step that stops part-way leaves particles or fluid half-moved:
+        // nothing may run on that state
+        if (rc) {
+            S->poisoned = 1;
+            return rc;
+        }
     }
     HIPCHK(S, hipStreamSynchronize(S->s));
     return HK_OK;

@@ -268,7 +268,12 @@ class _TorchMemory:
         self.stream = torch.cuda.current_stream()
 
         def _alloc(nbytes, ctx):
-            return int(torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream))
+            # a ctypes callback that raises returns an undefined value to C:
+            # every failure (out of memory above all) must come back as NULL
+            try:
+                return int(torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream))
+            except Exception:
+                return 0
 
         def _free(ptr, ctx):
             try:
