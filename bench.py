@@ -450,35 +450,87 @@ def warm_fluid(steps=200, warmup=20, nx=256, ny=128, nz=128):
             "workload": "plain plasma %dx%dx%d, all fluid, u_th 0.05" % (nx, ny, nz), **{k: v for k, v in out.items()}}
 
 
-def summarize_pmc(db_dir, kernel, skip):
-    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of `kernel` in a rocprofv3
-    --pmc result database, averaged over the dispatches after the first
-    `skip` (the untimed advance); printed as a profiles/ summary block."""
+def _csv_rows(d, suffix):
+    import csv
     import glob
-    import sqlite3
-    dbs = glob.glob(os.path.join(db_dir, "**", "*results.db"), recursive=True)
-    if not dbs:
-        print("no rocprofv3 database under %s" % db_dir, file=sys.stderr)
+    files = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not files:
+        print("no *%s under %s" % (suffix, d), file=sys.stderr)
         sys.exit(1)
-    con = sqlite3.connect(dbs[0])
-    cur = con.cursor()
-    tabs = [r[0] for r in cur.execute("select name from sqlite_master where type in ('table','view')")]
-    pmc = [t for t in tabs if t == "pmc_events" or t.startswith("pmc_event")]
-    rows = []
-    if "counters_collection" in tabs:
-        rows = cur.execute("select dispatch_id, kernel_name, counter_name, value from counters_collection").fetchall()
-    elif pmc:
-        rows = cur.execute("select * from %s" % pmc[0]).fetchall()
+    with open(files[0], newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _is_kernel(name, kernel):
+    import re
+    return re.match(r"(void )?%s\b" % re.escape(kernel), name) is not None
+
+
+def summarize_trace(d, kernel, last):
+    """Kernel-time summary of a rocprofv3 --kernel-trace --stats --output-format
+    csv directory: the mean duration of the last `last` dispatches of
+    `kernel` (the timed window), then the per-kernel table of the whole run."""
+    rows = [r for r in _csv_rows(d, "kernel_trace.csv") if _is_kernel(r["Kernel_Name"], kernel)]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    sel = rows[-last:] if last else rows
+    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3 for r in sel]
+    print("%s: %d dispatches in the run; the last %d: mean %.1f us, min %.1f, max %.1f" % (
+        kernel, len(rows), len(sel), sum(dur) / max(len(dur), 1), min(dur), max(dur)))
+    stats = _csv_rows(d, "kernel_stats.csv")
+    tot = sum(float(r["TotalDurationNs"]) for r in stats)
+    print("\nAll kernels of the run (kernel_stats.csv):")
+    print("%-44s %8s %11s %9s %7s" % ("kernel", "calls", "total ms", "avg us", "%"))
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:28]:
+        print("%-44s %8s %11.2f %9.1f %7.2f" % (r["Name"][:44], r["Calls"], float(r["TotalDurationNs"]) * 1e-6,
+                                                float(r["AverageNs"]) * 1e-3,
+                                                100.0 * float(r["TotalDurationNs"]) / tot))
+
+
+def _counter_per_dispatch(d, kernel=None, name_re=None):
+    import re
     per = {}
-    for did, name, cname, val in rows:
-        if kernel in name:
-            per.setdefault(cname, {}).setdefault(did, 0.0)
-            per[cname][did] += float(val)
-    for cname, d in per.items():
-        ids = sorted(d)[skip:]
-        vals = [d[i] for i in ids]
-        print("%s: dispatches %d (after %d), mean %.1f KiB" % (cname, len(vals), skip,
-                                                               sum(vals) / max(len(vals), 1)))
+    for r in _csv_rows(d, "counter_collection.csv"):
+        n = r["Kernel_Name"]
+        if kernel and not _is_kernel(n, kernel):
+            continue
+        if name_re and not re.search(name_re, n, re.I):
+            continue
+        key = int(r["Dispatch_Id"])
+        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    return [per[k] for k in sorted(per)]
+
+
+def summarize_traffic(a):
+    """HBM traffic of `kernel` per dispatch from two rocprofv3 --pmc csv runs
+    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, the last `last` dispatches)
+    scaled by what the same counters read for a 1 GiB device copy (two more
+    runs of bench.py --calibrate-copy).  Prints a profiles/ summary body."""
+    known = 1024 ** 3
+    cf = [v for v in _counter_per_dispatch(a.calib_fetch, name_re="copy") if v * 1024 > known / 8]
+    cw = [v for v in _counter_per_dispatch(a.calib_write, name_re="copy") if v * 1024 > known / 8]
+    f_scale = known / (1024 * sum(cf) / len(cf))
+    w_scale = known / (1024 * sum(cw) / len(cw))
+    f = _counter_per_dispatch(a.fetch, kernel=a.kernel)
+    w = _counter_per_dispatch(a.write, kernel=a.kernel)
+    f, w = f[-a.last:], w[-a.last:]
+    fk, wk = sum(f) / len(f), sum(w) / len(w)
+    fb, wb = fk * 1024 * f_scale, wk * 1024 * w_scale
+    print("# Calibration: a 1 GiB device copy reads FETCH_SIZE %.0f KiB and WRITE_SIZE %.0f KiB," % (
+        sum(cf) / len(cf), sum(cw) / len(cw)))
+    print("# so FETCH_SIZE is scaled by %.4f and WRITE_SIZE by %.4f to bytes." % (f_scale, w_scale))
+    print("# %s dispatches averaged: %d (FETCH), %d (WRITE)" % (a.kernel, len(f), len(w)))
+    print("fetch_kib_per_launch = %.1f" % fk)
+    print("write_kib_per_launch = %.1f" % wk)
+    print("fetch_bytes_per_launch = %.0f" % fb)
+    print("write_bytes_per_launch = %.0f" % wb)
+    print("bytes_per_launch = %.0f" % (fb + wb))
+    if a.alg_bytes:
+        print("algorithmic_bytes_per_launch = %.0f" % a.alg_bytes)
+        print("traffic_over_algorithmic = %.3f" % ((fb + wb) / a.alg_bytes))
+    if a.window:
+        print("window = %s" % a.window)
+    print("source_hash = %s" % source_hash())
+    print("# source_hash: sha256 (first 16 hex) of %s" % ", ".join(PUSH_SOURCES))
 
 
 def main():
@@ -499,13 +551,22 @@ def main():
                     help="only measure the fluid phase (warm and cold) on the all-fluid 256x128x128 plasma")
     ap.add_argument("--networks-only", action="store_true",
                     help="only measure the switch CNN, the next-state surrogate and SwitchNet and print their JSON")
-    ap.add_argument("--summarize-pmc", metavar="DIR",
-                    help="print per-dispatch counter means of k_push from a rocprofv3 --pmc output DIR")
-    ap.add_argument("--skip-dispatches", type=int, default=0)
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="print the kernel-time summary of a rocprofv3 --kernel-trace --stats csv DIR")
+    ap.add_argument("--summarize-traffic", action="store_true",
+                    help="print the HBM traffic summary from --fetch/--write/--calib-fetch/--calib-write DIRs")
+    ap.add_argument("--fetch"); ap.add_argument("--write")
+    ap.add_argument("--calib-fetch"); ap.add_argument("--calib-write")
+    ap.add_argument("--alg-bytes", type=float, default=0.0, help="algorithmic bytes per launch")
+    ap.add_argument("--window", default="", help="step window the counters cover")
+    ap.add_argument("--last", type=int, default=0, help="summarize the last N dispatches of --kernel")
     ap.add_argument("--kernel", default="k_push")
     args = ap.parse_args()
-    if args.summarize_pmc:
-        summarize_pmc(args.summarize_pmc, args.kernel, args.skip_dispatches)
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.kernel, args.last)
+        return
+    if args.summarize_traffic:
+        summarize_traffic(args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the multi-GPU path (domain decomposition) is not "
@@ -533,7 +594,16 @@ def main():
         sys.exit(2)
     window = "a0 %g, steps %d-%d" % (a0, W, W + K)
     res, cfgs = {}, {}
-    for mode in modes:
+    floor_snaps = None
+    if not args.no_extras and len(modes) == 2:
+        # all-PIC with another seed, run first so that the all-PIC window below
+        # is the last stretch of push launches in the process: the field
+        # difference sampling noise alone makes against one all-PIC run
+        seed2 = workload(a0, "all_pic")["run"]["seed"] + 7919
+        print("bench: all-PIC with seed %#x (sampling floor), steps 0-%d untimed" % (seed2, W + K),
+              file=sys.stderr, flush=True)
+        floor_snaps = run_window(workload(a0, "all_pic", seed=seed2), W, K, args.precision, timing=False)["snaps"]
+    for mode in sorted(modes, key=lambda m: m == "all_pic"):
         cfg = workload(a0, mode)
         cfgs[mode] = cfg
         print("bench: %s %s: steps 0-%d untimed, %d-%d timed" % (cfg["name"], mode, W, W, W + K),
@@ -541,19 +611,15 @@ def main():
         res[mode] = run_window(cfg, W, K, args.precision)
         print("bench: %s %.3f ms/step" % (mode, 1e3 * res[mode]["seconds"] / K), file=sys.stderr, flush=True)
     if len(res) < 2:
-        r = next(iter(res.values()))
-        print(json.dumps({"mode": modes[0], "steps_per_s": K / r["seconds"], "timers": r["timers"],
-                          "window": window}))
+        mode = modes[0]
+        r = res[mode]
+        print(json.dumps({"mode": mode, "steps_per_s": K / r["seconds"], "window": window,
+                          "roofline": push_roofline(r, particle_bytes(cfgs[mode], r, K)),
+                          "timers": r["timers"], "kinetic_fraction": r["diag"]["kinetic_fraction"],
+                          "count": r["diag"]["count"]}))
         return
     h, p = res["threshold"], res["all_pic"]
-    floor = None
-    if not args.no_extras:
-        # the same all-PIC with another seed: the sampling-noise floor of a
-        # comparison with one all-PIC run
-        print("bench: all-PIC with another seed (sampling floor)", file=sys.stderr, flush=True)
-        p2 = run_window(workload(a0, "all_pic", seed=cfgs["all_pic"]["run"]["seed"] + 7919), W, K,
-                        args.precision, timing=False)
-        floor = field_l2(p2["snaps"], p["snaps"])
+    floor = field_l2(floor_snaps, p["snaps"]) if floor_snaps is not None else None
     hyb_sps, pic_sps = K / h["seconds"], K / p["seconds"]
     l2 = field_l2(h["snaps"], p["snaps"])
     e_h, e_p = total_energy(h["diag"]), total_energy(p["diag"])

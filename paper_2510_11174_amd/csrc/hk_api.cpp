@@ -339,7 +339,10 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
         }
         // the push addresses its output through the input's field pointers plus
         // one byte distance: both buffers must have the same layout
-        if (!same_layout(nbuf[0], nbuf[1])) return fail(S, HK_ENOMEM, "rebuild: buffer layouts differ");
+        if (!same_layout(nbuf[0], nbuf[1])) {
+            S->poisoned = 1;
+            return fail(S, HK_ENOMEM, "rebuild: buffer layouts differ");
+        }
         D.alloc_slots = n_alloc;
     }
     const int dst_i = reuse ? 1 - D.cur : 0;
@@ -352,8 +355,12 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     // ranks (cleared together before a push into that buffer)
     int *dfill = (int *)dalloc(S, sizeof(int) * 3 * nt);
     int *f1 = (int *)dalloc(S, sizeof(int) * 3 * nt);
-    if (!doff || !dmoff || !dcap || !dmcap || !dfill || !f1)
+    // the idle buffer may be gone already: a failure from here on leaves the
+    // species without a push output, and the context is unusable
+    if (!doff || !dmoff || !dcap || !dmcap || !dfill || !f1) {
+        S->poisoned = 1;
         return fail(S, HK_ENOMEM, "rebuild: tables");
+    }
     HIPCHK(S, hipMemcpyAsync(doff, off.data(), sizeof(long long) * nt, hipMemcpyHostToDevice, S->s));
     HIPCHK(S, hipMemcpyAsync(dmoff, moff.data(), sizeof(long long) * nt, hipMemcpyHostToDevice, S->s));
     HIPCHK(S, hipMemcpyAsync(dcap, cap.data(), sizeof(int) * nt, hipMemcpyHostToDevice, S->s));
@@ -394,7 +401,10 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     if (D.d.ionizable) {
         dfree(S, D.active);
         D.active = (int *)dalloc(S, sizeof(int) * nt);
-        if (!D.active) return fail(S, HK_ENOMEM, "rebuild: active counts");
+        if (!D.active) {
+            S->poisoned = 1;
+            return fail(S, HK_ENOMEM, "rebuild: active counts");
+        }
         launch_count_active(g, specp(D), D.buf[D.cur], cur_bins(D), D.d.z_max, D.active, S->s);
     }
     return HK_OK;
@@ -430,7 +440,10 @@ int ensure_inbox(hk_sim *S, int isp, long long need) {
     }
     D.inbox_cap = (int)c;
     if (!D.inbox_dev) D.inbox_dev = (PArr *)dalloc(S, sizeof(PArr));
-    if (!D.inbox_dev) return fail(S, HK_ENOMEM, "inbox descriptor");
+    if (!D.inbox_dev) {
+        S->poisoned = 1;
+        return fail(S, HK_ENOMEM, "inbox descriptor");
+    }
     HIPCHK(S, hipMemcpyAsync(D.inbox_dev, &D.inbox, sizeof(PArr), hipMemcpyHostToDevice, S->s));
     int capv[1] = {(int)INT_MAX};
     HIPCHK(S, hipMemcpyAsync(D.g_capmax, capv, sizeof(int), hipMemcpyHostToDevice, S->s));
