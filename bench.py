@@ -461,9 +461,20 @@ def _csv_rows(d, suffix):
         return list(csv.DictReader(fh))
 
 
+def _short_name(name):
+    """A kernel's name without return type and namespace: 'void
+    (anonymous namespace)::k_push<1>(GridP, ...)' gives 'k_push<1>'."""
+    n = name
+    if n.startswith("void "):
+        n = n[5:]
+    n = n.replace("(anonymous namespace)::", "")
+    return n.split("(", 1)[0]
+
+
 def _is_kernel(name, kernel):
-    import re
-    return re.match(r"(void )?%s\b" % re.escape(kernel), name) is not None
+    """Whether the dispatch `name` is `kernel` (any template instance)."""
+    n = _short_name(name)
+    return n == kernel or n.startswith(kernel + "<")
 
 
 def summarize_trace(d, kernel, last):
@@ -481,7 +492,8 @@ def summarize_trace(d, kernel, last):
     print("\nAll kernels of the run (kernel_stats.csv):")
     print("%-44s %8s %11s %9s %7s" % ("kernel", "calls", "total ms", "avg us", "%"))
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:28]:
-        print("%-44s %8s %11.2f %9.1f %7.2f" % (r["Name"][:44], r["Calls"], float(r["TotalDurationNs"]) * 1e-6,
+        print("%-44s %8s %11.2f %9.1f %7.2f" % (_short_name(r["Name"])[:44], r["Calls"],
+                                                float(r["TotalDurationNs"]) * 1e-6,
                                                 float(r["AverageNs"]) * 1e-3,
                                                 100.0 * float(r["TotalDurationNs"]) / tot))
 

@@ -35,9 +35,9 @@ def test_trace_summary_takes_last_dispatches(tmp_path, capsys):
     # k_push dispatches of 10 us, then 20 us; the last two average 20 us, and
     # a kernel whose name only starts with k_push is not counted
     d = tmp_path / "trace" / "host"
-    rows = [["KERNEL_DISPATCH", i, "k_push(SpecP)", 1000 * i, 1000 * i + (10000 if i < 3 else 20000)]
-            for i in range(5)]
-    rows.append(["KERNEL_DISPATCH", 9, "k_push_other(int)", 0, 999999])
+    rows = [["KERNEL_DISPATCH", i, "void (anonymous namespace)::k_push<%d>(SpecP)" % (i % 2), 1000 * i,
+             1000 * i + (10000 if i < 3 else 20000)] for i in range(5)]
+    rows.append(["KERNEL_DISPATCH", 9, "(anonymous namespace)::k_push_other(int)", 0, 999999])
     _write_csv(d / "run_kernel_trace.csv", ["Kind", "Dispatch_Id", "Kernel_Name", "Start_Timestamp",
                                             "End_Timestamp"], rows)
     _write_csv(d / "run_kernel_stats.csv", ["Name", "Calls", "TotalDurationNs", "AverageNs"],
