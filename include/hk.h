@@ -355,6 +355,51 @@ int hk_node_state(hk_sim *sim, float *out, size_t n);
  * without one the mode decides by the thresholds alone) */
 int hk_set_cnn(hk_sim *sim, hk_cnn *cnn);
 
+/* Training set of the learned switch, in device memory (Methodology,
+ * pipeline paragraph: the switch network learns from data the simulation
+ * itself generates, with inputs normalized per channel and an energy
+ * penalty).  desc gives the stream and the optional allocator (its seed is
+ * unused).  Snapshots of D x H x W nodes (z, y, x; x fastest) hold per node
+ * the 8 network inputs before normalization, the conversion energy e (as
+ * for hk_node_inputs) and the 0/1 kinetic label. */
+typedef struct hk_dataset hk_dataset;
+int hk_dataset_create(const hk_cnn_desc *desc, hk_dataset **out);
+void hk_dataset_destroy(hk_dataset *ds);
+int hk_dataset_size(const hk_dataset *ds);   /* snapshots held */
+/* snapshot k to the host: dims[3] = D, H, W; raw[8 n], ehat[n], y[n] the
+ * label, thr[n] the threshold criterion's undilated flags at the snapshot's
+ * step (the method without the network; each may be NULL; n must be D H W
+ * when any is given) */
+int hk_dataset_get(hk_dataset *ds, int k, int *dims, float *raw, float *ehat, uint8_t *y, uint8_t *thr,
+                   size_t n);
+/* per-channel mean and standard deviation of the 8 inputs over every node of
+ * every snapshot (FP64 sums on the device; a constant channel gets std 1);
+ * the caller hands them to hk_cnn_set_norm */
+int hk_dataset_stats(hk_dataset *ds, float *mean, float *stdv);
+/* Append snapshots of an all-PIC run (HK_EINVAL in any other mode, or for a
+ * grid under 16 nodes in a direction): the simulation advances steps +
+ * window steps from where it is; at relative steps 0, every, 2 every, ...
+ * <= steps the node inputs are stored, and the label of a node is 1 when,
+ * at any of that step and the window steps after it, (a) a cold-fluid
+ * conversion would destroy more than 1e-3 of the node's kinetic energy while
+ * its momentum spread is at or above thr_sigma_u, or (b) an ionization is
+ * possible there (per-step probability >= thr_ion with ionizable ions left),
+ * or (c) a QED emission is possible (chi >= thr_chi).  Everything runs on
+ * the simulation's stream, drained before return; a failed step poisons the
+ * simulation as hk_step does.  Snapshots appended before a failure stay. */
+int hk_dump_training(hk_sim *sim, hk_dataset *ds, int steps, int every, int window);
+/* iters AdamW steps of the network on batches of B crops sampled on the
+ * device: snapshot and origin from Philox (seed, crop index, the network's
+ * AdamW step), 24^3 input nodes normalized with the network's statistics
+ * (halo: wrap in y, z and periodic x, wall node repeated in open x), labels
+ * and energy weights e / (crop kinetic energy) x 4096 on the 16^3 output
+ * nodes.  losses[iters] (host, may be NULL) receives each batch loss. */
+int hk_train(hk_cnn *cnn, hk_dataset *ds, int iters, int B, const hk_cnn_train_desc *train, uint64_t seed,
+             double *losses);
+/* logits (device FP32, D H W) of snapshot k, no dropout */
+int hk_dataset_predict(hk_cnn *cnn, hk_dataset *ds, int k, float *logit);
+const char *hk_dataset_last_error(const hk_dataset *ds);
+
 /* ------------------------------------------------------------------------
  * Next-state surrogate (Results, Table 2 and the paragraph before it: a
  * residual 3D CNN, the StatePredictor, trained with a Huber loss and a

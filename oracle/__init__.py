@@ -116,6 +116,7 @@ def lib():
         L.or_get_switch.argtypes = [C.c_void_p, C.c_void_p]
         L.or_set_switch.argtypes = [C.c_void_p, C.c_void_p]
         L.or_set_switch_mode.argtypes = [C.c_void_p, C.c_int]
+        L.or_training_node.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_diagnostics.argtypes = [C.c_void_p, P(Diag)]
         L.or_get_rho.argtypes = [C.c_void_p, C.c_void_p]
         L.or_get_divE.argtypes = [C.c_void_p, C.c_void_p]
@@ -311,6 +312,20 @@ class Oracle:
 
     def set_switch_mode(self, mode: str):
         lib().or_set_switch_mode(self.h, SWITCH[mode])
+
+    def node_dims(self):
+        """(nz, ny, NX) of the canonical node grid (NX = nx periodic, nx + 1 open)."""
+        per = self.cfg["grid"].get("bc_x", "open") == "periodic"
+        return (self.nz, self.ny, self.nx if per else self.nx + 1)
+
+    def training_node(self):
+        """(raw9 [nz, ny, NX, 9], cond [nz, ny, NX]) at the current step: the
+        network inputs plus the conversion energy, and the label bits."""
+        dims = self.node_dims()
+        raw = np.empty(dims + (9,))
+        cond = np.empty(dims, np.uint8)
+        lib().or_training_node(self.h, _ptr(raw), _ptr(cond))
+        return raw, cond
 
     def set_cnn(self, params, mean, std):
         """Install the switch network (FP64 parameter vector) and input statistics."""

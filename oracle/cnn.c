@@ -263,12 +263,30 @@ void or_cnn_node_inputs(or_sim *s, const double *N, const double *U2, double *ra
 
 /* Switch decisions from the CNN where it is confident; returns the fraction
  * of nodes that kept the threshold decision. */
-double or_cnn_switch(or_sim *s, const double *N, const double *U2, uint8_t *hot, uint8_t *cold) {
+double or_cnn_switch(or_sim *s, const double *N, const double *U2, const double *NI, uint8_t *hot,
+                     uint8_t *cold) {
     or_cnn_state *cs = (or_cnn_state *)s->cnn;
     if (!cs || !cs->have) return 1.0;
     const or_grid *g = &s->g;
     int nxn = g->bc_x == OR_BC_PERIODIC ? g->nx : g->nx + 1;
     size_t nodes = (size_t)nxn * g->ny * g->nz;
+    /* The network decides in the plasma's x extent (columns with N or NI > 0)
+     * widened by the nodes plasma can reach before the next evaluation
+     * (switch_every + dilation + 4); the threshold decision stays elsewhere. */
+    int lo = nxn, hi = -1;
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < nxn; ++i) {
+                size_t c = or_idx(s, i, j, k);
+                if (N[c] > 0 || NI[c] > 0) {
+                    if (i < lo) lo = i;
+                    if (i > hi) hi = i;
+                }
+            }
+    int margin = s->run.switch_every + s->run.dilation + 4;
+    int w0 = lo - margin < 0 ? 0 : lo - margin;
+    int w1 = hi + margin > nxn - 1 ? nxn - 1 : hi + margin;
+    if (hi < 0) { w0 = 1; w1 = 0; }
     double *raw = (double *)malloc(sizeof(double) * nodes * 8);
     or_cnn_node_inputs(s, N, U2, raw);
     int D = g->nz + 8, H = g->ny + 8, W = nxn + 8;
@@ -291,6 +309,7 @@ double or_cnn_switch(or_sim *s, const double *N, const double *U2, uint8_t *hot,
             for (int i = 0; i < nxn; ++i) {
                 size_t v = ((size_t)k * g->ny + j) * nxn + i;
                 size_t c = or_idx(s, i, j, k);
+                if (i < w0 || i > w1) continue;
                 double ps[16], mean = 0.0, var = 0.0;
                 for (int q = 0; q < 16; ++q) {
                     double mk[NC];

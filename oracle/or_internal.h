@@ -99,6 +99,8 @@ void or_reflect_x(const or_sim *s, int ci, double *X, double *ux);
 void or_fluid_phase(or_sim *s);
 /* switch.c */
 void or_switch_eval(or_sim *s);
+void or_training_node(or_sim *s, double *raw9, uint8_t *cond);
+void or_cnn_node_inputs(or_sim *s, const double *N, const double *U2, double *raw);
 void or_absorb(or_sim *s);
 void or_spawn_fluid(or_sim *s);
 int or_is_hot(const or_sim *s, const double u[3]);

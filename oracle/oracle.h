@@ -122,6 +122,11 @@ int or_set_fluid_p(or_sim *s, int species, const double *p);
 int or_get_switch(const or_sim *s, uint8_t *out);
 int or_set_switch(or_sim *s, const uint8_t *in);
 int or_set_switch_mode(or_sim *s, int mode);
+/* Training data of the learned switch at the current step, canonical node
+ * grid [nz][ny][NX] (NX = nx periodic, nx + 1 open): raw9 (may be NULL) the 8
+ * network inputs and the conversion energy per node, cond the label
+ * condition bits (1 thermal, 2 ionization possible, 4 QED possible). */
+void or_training_node(or_sim *s, double *raw9, uint8_t *cond);
 
 int or_diagnostics(or_sim *s, or_diag *d);
 /* Charge density (nodes) and div E, canonical layout. */

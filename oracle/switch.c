@@ -81,19 +81,15 @@ int or_is_hot(const or_sim *s, const double u[3]) {
     return h > 0.0 && u[0] * u[0] + u[1] * u[1] + u[2] * u[2] >= h * h;
 }
 
-extern double or_cnn_switch(or_sim *s, const double *nmom, const double *u2mom,
+extern double or_cnn_switch(or_sim *s, const double *nmom, const double *u2mom, const double *nimom,
                             uint8_t *hot, uint8_t *cold);
 
-void or_switch_eval(or_sim *s) {
-    const or_grid *g = &s->g;
+/* Nearest-node moments of the fluid species (particles that are not hot,
+ * then fluid mass): N = sum w, V = sum w^2, P = sum w u, U2 = sum w |u|^2;
+ * NI = weight of ionizable ions not yet at their last charge state. */
+static void node_moments(const or_sim *s, double *N, double *P, double *U2, double *NI, double *V) {
     size_t nn = s->nn;
-    double dv = g->dx * g->dy * g->dz;
-    int nxn = node_x_count(s);
-    double *N = (double *)calloc(nn, sizeof(double));
-    double *P = (double *)calloc(nn * 3, sizeof(double));
-    double *U2 = (double *)calloc(nn, sizeof(double));
-    double *NI = (double *)calloc(nn, sizeof(double));
-    double *V = (double *)calloc(nn, sizeof(double));
+    double dv = s->g.dx * s->g.dy * s->g.dz;
     for (int isp = 0; isp < s->nsp; ++isp) {
         const or_species *sp = &s->sp[isp];
         const or_parts *p = &s->p[isp];
@@ -125,6 +121,19 @@ void or_switch_eval(or_sim *s) {
                     NI[c] += p->w[n];
                 }
     }
+}
+
+void or_switch_eval(or_sim *s) {
+    const or_grid *g = &s->g;
+    size_t nn = s->nn;
+    double dv = g->dx * g->dy * g->dz;
+    int nxn = node_x_count(s);
+    double *N = (double *)calloc(nn, sizeof(double));
+    double *P = (double *)calloc(nn * 3, sizeof(double));
+    double *U2 = (double *)calloc(nn, sizeof(double));
+    double *NI = (double *)calloc(nn, sizeof(double));
+    double *V = (double *)calloc(nn, sizeof(double));
+    node_moments(s, N, P, U2, NI, V);
     uint8_t *hot = (uint8_t *)calloc(nn, 1), *notcold = (uint8_t *)calloc(nn, 1);
     double a_s = 0.0;
     if (s->run.enable_qed) {
@@ -174,7 +183,7 @@ void or_switch_eval(or_sim *s) {
             }
     s->fallback_fraction = 0.0;
     if (s->run.switch_mode == OR_SW_CNN)
-        s->fallback_fraction = or_cnn_switch(s, N, U2, hot, notcold);
+        s->fallback_fraction = or_cnn_switch(s, N, U2, NI, hot, notcold);
     /* dilation + hysteresis */
     int D = s->run.dilation;
     for (int k = 0; k < g->nz; ++k)
@@ -199,6 +208,72 @@ void or_switch_eval(or_sim *s) {
                 }
             }
     free(N); free(P); free(U2); free(NI); free(V); free(hot); free(notcold);
+}
+
+/* Training data of the learned switch at the current step, per node of the
+ * canonical grid [nz][ny][NX] (x fastest).  raw9 (may be NULL): the network's
+ * 8 inputs (as the CNN switch builds them) and the conversion energy
+ * e = (1/2)(U2 - |P|^2 / N), the thermal energy a cold fluid at the mean
+ * momentum drops (small-u limit).  cond: the label condition, bit 0 when e
+ * exceeds 1e-3 of the node's kinetic energy U2 / 2 and the momentum spread
+ * sqrt(2 e / N) reaches thr_sigma_u, bit 1 when an ionization is possible
+ * (per-step probability at the node's field >= thr_ion, ionizable ions
+ * present), bit 2 when a QED emission is possible (chi of the rms momentum
+ * >= thr_chi).  The reading of the label is the one stated with
+ * hk_dump_training; the paper leaves the training labels unstated. */
+void or_training_node(or_sim *s, double *raw9, uint8_t *cond) {
+    const or_grid *g = &s->g;
+    size_t nn = s->nn;
+    int nxn = node_x_count(s);
+    double *N = (double *)calloc(nn, sizeof(double));
+    double *P = (double *)calloc(nn * 3, sizeof(double));
+    double *U2 = (double *)calloc(nn, sizeof(double));
+    double *NI = (double *)calloc(nn, sizeof(double));
+    double *V = (double *)calloc(nn, sizeof(double));
+    node_moments(s, N, P, U2, NI, V);
+    size_t nodes = (size_t)nxn * g->ny * g->nz;
+    double *raw = NULL;
+    if (raw9) {
+        raw = (double *)malloc(sizeof(double) * nodes * 8);
+        or_cnn_node_inputs(s, N, U2, raw);
+    }
+    double a_s = 0.0;
+    if (s->run.enable_qed) {
+        double omega0 = 2.0 * OR_PI * OR_C / (s->las.lambda_um * 1e-6);
+        a_s = OR_ME * OR_C * OR_C / (OR_HBAR * omega0);
+    }
+    const or_run *r = &s->run;
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < nxn; ++i) {
+                size_t c = or_idx(s, i, j, k);
+                size_t v = ((size_t)k * g->ny + j) * nxn + i;
+                double e = 0.0;
+                int bits = 0;
+                if (N[c] > 0) {
+                    double p2 = P[3 * c] * P[3 * c] + P[3 * c + 1] * P[3 * c + 1] + P[3 * c + 2] * P[3 * c + 2];
+                    e = 0.5 * (U2[c] - p2 / N[c]);
+                    if (e > 1e-3 * 0.5 * U2[c] && 2.0 * e / N[c] >= r->thr_sigma_u * r->thr_sigma_u) bits |= 1;
+                }
+                int node[3] = {i, j, k};
+                double z0[3] = {0, 0, 0}, f[3];
+                for (int d = 0; d < 3; ++d) f[d] = or_gather(s, OR_EX + d, node, z0);
+                double emag = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+                if (NI[c] > 0) {
+                    double ionr = 0.0;
+                    for (int isp = 0; isp < s->nsp; ++isp)
+                        if (s->sp[isp].kind == OR_ION && s->sp[isp].ionizable)
+                            ionr = fmax(ionr, or_ion_rate_norm(s, isp, 0, emag) * g->dt);
+                    if (ionr >= r->thr_ion) bits |= 2;
+                }
+                if (r->enable_qed && N[c] > 0 && sqrt(1.0 + U2[c] / N[c]) * emag / a_s >= r->thr_chi) bits |= 4;
+                cond[v] = (uint8_t)bits;
+                if (raw9) {
+                    for (int q = 0; q < 8; ++q) raw9[9 * v + q] = raw[8 * v + q];
+                    raw9[9 * v + 8] = e;
+                }
+            }
+    free(N); free(P); free(U2); free(NI); free(V); free(raw);
 }
 
 /* Absorption part of the conversion (see the header comment). */

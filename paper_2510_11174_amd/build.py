@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["k_fields.hip", "k_particles.hip", "k_diag.hip", "k_fluid.hip", "k_switch.hip", "hk_qed.cpp", "k_cnn.hip", "hk_cnn.cpp",
-           "k_sp.hip", "hk_sp.cpp", "hk_swn.cpp", "hk_api.cpp"]
+           "k_sp.hip", "hk_sp.cpp", "hk_swn.cpp", "k_dataset.hip", "hk_dataset.cpp", "hk_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-atomics",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -15,14 +15,16 @@
 
 #include "hk_internal.h"
 #include "hk_cnn_internal.h"
+#include "hk_dataset_internal.h"
 
 void cnn_launch_inputs(const GridP &g, real *const f[9], const real *mom, const float mean[8],
-                       const float inv_std[8], unsigned short *x, hipStream_t s);
+                       const float inv_std[8], unsigned short *x, const int *xwin, hipStream_t s);
 void cnn_launch_node_raw(const GridP &g, real *const f[9], const real *mom, float *out, hipStream_t s);
 void cnn_launch_node_state(const GridP &g, real *const f[9], const double *rho, float *out, hipStream_t s);
 void cnn_launch_decide(const GridP &g, const unsigned short *a4, const unsigned short *wh, const float *bh,
                        uint64_t seed, uint32_t eval, uint8_t *hot, uint8_t *notcold, int *nfall,
-                       float *pmean, hipStream_t s);
+                       float *pmean, const int *xwin, hipStream_t s);
+void cnn_launch_window(const GridP &g, const real *mom, int margin, int *win, hipStream_t s);
 
 // device status words copied to the host once per merge (see hk_sim::status)
 #define HK_NSTATUS 32
@@ -82,8 +84,10 @@ struct hk_sim {
     hk_cnn *cnn = nullptr;       // learned switch (borrowed)
     uint32_t cnn_evals = 0;      // evaluations so far (dropout counter)
     unsigned short *cnn_x = nullptr;   // padded BF16 node inputs of the grid
-    int *cnn_nfall = nullptr;    // nodes that kept the threshold decision, last evaluation
+    int *cnn_nfall = nullptr;    // [0] nodes that kept the threshold decision, last evaluation;
+                                 // [4..7] the network's x window (k_cnn_window)
     float *cnn_raw = nullptr;    // node inputs and conversion energy (hk_node_inputs)
+    uint8_t *lab = nullptr;      // training-label condition per node (hk_dump_training)
     double a_s = 0.0;            // Schwinger field in normalized units
     int photon_sp = -1, electron_sp = -1, positron_sp = -1;   // QED sinks (first of each kind)
     hk_grid_desc gd{};
@@ -745,18 +749,22 @@ void cnn_switch(hk_sim *S) {
     const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
     const int D = g.nz + 8, H = g.ny + 8, W = NX + 8;
     if (!S->cnn_x) S->cnn_x = (unsigned short *)dalloc(S, sizeof(unsigned short) * 8 * (size_t)D * H * W);
-    if (!S->cnn_nfall) S->cnn_nfall = (int *)dalloc(S, sizeof(int));
+    if (!S->cnn_nfall) S->cnn_nfall = (int *)dalloc(S, sizeof(int) * 8);
     if (!S->cnn_x || !S->cnn_nfall) { fail(S, HK_ENOMEM, "CNN switch inputs"); return; }
-    cnn_launch_inputs(g, S->f, S->mom, c->mean, c->inv_std, S->cnn_x, S->s);
+    // the network decides within the plasma's x extent widened by the nodes
+    // plasma can reach before the next evaluation; the threshold elsewhere
+    int *win = S->cnn_nfall + 4;
+    cnn_launch_window(g, S->mom, S->run.switch_every + S->run.dilation + 4, win, S->s);
+    cnn_launch_inputs(g, S->f, S->mom, c->mean, c->inv_std, S->cnn_x, win + 2, S->s);
     const unsigned short *a4;
-    if (cnn_forward_bf16(c, S->cnn_x, 1, D, H, W, false, S->s, &a4, nullptr) != HK_OK) {
+    if (cnn_forward_bf16(c, S->cnn_x, 1, D, H, W, false, S->s, &a4, nullptr, win + 2) != HK_OK) {
         fail(S, HK_ENOMEM, "CNN switch: %s", c->err.c_str());
         return;
     }
     launch_zero(S->cnn_nfall, sizeof(int), S->s);
     const long long head = 27LL * 8 * 32 + 32 + 3 * (27LL * 32 * 32 + 32);
     cnn_launch_decide(g, a4, c->wh, c->p + head + 32, S->run.seed, S->cnn_evals, S->hot, S->notcold,
-                      S->cnn_nfall, nullptr, S->s);
+                      S->cnn_nfall, nullptr, win + 2, S->s);
     S->cnn_evals++;
 }
 
@@ -1199,6 +1207,67 @@ int hk_node_inputs(hk_sim *S, double *raw, double *ehat, uint8_t *hot, size_t no
             hot[v] = hh[(size_t)i + (size_t)g.sx * ((size_t)j + (size_t)g.ny * k)];
         }
     }
+    return HK_OK;
+}
+
+int hk_dump_training(hk_sim *S, hk_dataset *ds, int steps, int every, int window) {
+    if (!S || !ds || steps < 0 || every < 1 || window < 0) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    if (S->run.switch_mode != HK_SW_ALL_PIC)
+        return fail(S, HK_EINVAL, "training data come from an all-PIC run");
+    const GridP &g = S->g;
+    const int per = g.bcx == HK_BC_PERIODIC;
+    const int NX = per ? g.nx : g.nx + 1;
+    if (g.nz < 16 || g.ny < 16 || NX < 16)
+        return fail(S, HK_EINVAL, "grid of %d x %d x %d nodes: crops need 16 in each direction", g.nz, g.ny, NX);
+    const long long n = (long long)NX * g.ny * g.nz;
+    int rc = ensure_fluid(S);
+    if (rc) return rc;
+    if (!S->lab) {
+        S->lab = (uint8_t *)dalloc(S, (size_t)n);
+        if (!S->lab) return fail(S, HK_ENOMEM, "label scratch");
+    }
+    // snapshots are written on the simulation's stream, which is drained
+    // before the call returns
+    HIPCHK(S, hipStreamSynchronize(ds->s));
+    const SwitchP P = switch_params(S);
+    const double dv = g.ddx * g.ddy * g.ddz;
+    std::vector<int> open;   // indices into ds->snaps still accumulating labels
+    std::vector<int> r0s;
+    for (int r = 0; r <= steps + window; ++r) {
+        const IonP *ions[4];
+        const int nion = switch_moments(S, false, ions);
+        launch_label_nodes(g, P, S->mom, S->f, ions, nion, S->lab, S->s);
+        if (r <= steps && r % every == 0) {
+            DsSnap *snap = nullptr;
+            rc = ds_append(ds, g.nz, g.ny, NX, per, dv, S->s, &snap);
+            if (rc) return fail(S, rc, "training snapshot: %s", ds->err.c_str());
+            cnn_launch_node_raw(g, S->f, S->mom, snap->raw9, S->s);
+            launch_indicators_nodes(g, P, S->mom, S->f, ions, nion, S->hot, S->notcold, S->s);
+            launch_flags_canonical(g, S->hot, snap->thr, S->s);
+            open.push_back((int)ds->snaps.size() - 1);
+            r0s.push_back(r);
+        }
+        for (size_t q = 0; q < open.size(); ++q)
+            launch_label_or(n, S->lab, ds->snaps[open[q]].y, S->s);
+        // a snapshot's window closes after steps r0 .. r0 + window
+        for (size_t q = 0; q < open.size();) {
+            if (r >= r0s[q] + window) {
+                open.erase(open.begin() + q);
+                r0s.erase(r0s.begin() + q);
+            } else {
+                ++q;
+            }
+        }
+        if (r < steps + window) {
+            rc = one_step(S);
+            if (rc) {
+                S->poisoned = 1;
+                return rc;
+            }
+        }
+    }
+    HIPCHK(S, hipStreamSynchronize(S->s));
     return HK_OK;
 }
 

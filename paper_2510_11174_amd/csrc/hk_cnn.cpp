@@ -17,7 +17,7 @@
 void cnn_launch_to_bf16(long long n, const float *x, unsigned short *o, hipStream_t s);
 void cnn_launch_conv_fwd(int cin, int B, int D, int H, int W, const unsigned short *act,
                          const unsigned short *Wf, const float *bias, float *zout, unsigned short *aout,
-                         hipStream_t s);
+                         const int *xwin, hipStream_t s);
 void cnn_launch_conv_bwd_data(int B, int D, int H, int W, const unsigned short *dz,
                               const unsigned short *Wb, const float *zin, unsigned short *dzin,
                               hipStream_t s);
@@ -107,7 +107,8 @@ int cnn_pack(hk_cnn *c, hipStream_t s) {
 // `pingpong` the activations alternate between those two caller buffers
 // instead (layer l writes pingpong[l & 1]; no pre-activations, nothing grown).
 int cnn_forward_bf16(hk_cnn *c, const unsigned short *x, int B, int D, int H, int W, bool keep_z,
-                     hipStream_t s, const unsigned short **a4, unsigned short *const *pingpong) {
+                     hipStream_t s, const unsigned short **a4, unsigned short *const *pingpong,
+                     const int *xwin) {
     if (D < 9 || H < 9 || W < 9) return cnn_fail(c, HK_EINVAL, "input smaller than the receptive field");
     if (pingpong && keep_z) return cnn_fail(c, HK_EINVAL, "pre-activations need the workspace");
     const unsigned short *in = x;
@@ -119,7 +120,7 @@ int cnn_forward_bf16(hk_cnn *c, const unsigned short *x, int B, int D, int H, in
         float *z = keep_z ? (float *)ws(c, c->wz[l], c->wz_cap[l], n * NC * 4) : nullptr;
         if (!a || (keep_z && !z)) return cnn_fail(c, HK_ENOMEM, "CNN activations");
         cnn_launch_conv_fwd(cin_of(l), B, D - 2 * l, H - 2 * l, W - 2 * l, in, c->Wf[l], c->p + w_off(l) + 27LL * cin_of(l) * NC,
-                            z, a, s);
+                            z, a, xwin, s);
         in = a;
     }
     *a4 = in;

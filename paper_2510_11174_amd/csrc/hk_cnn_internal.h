@@ -28,5 +28,8 @@ struct hk_cnn {
 
 void *cnn_alloc(hk_cnn *c, size_t bytes);
 void cnn_release(hk_cnn *c, void *p);
+// xwin (device, may be null): only output x columns xwin[0] .. xwin[1] (+ the
+// halo the next layers read) are computed, for B = 1 on the switch's grid
 int cnn_forward_bf16(hk_cnn *c, const unsigned short *x, int B, int D, int H, int W, bool keep_z,
-                     hipStream_t s, const unsigned short **a4, unsigned short *const *pingpong);
+                     hipStream_t s, const unsigned short **a4, unsigned short *const *pingpong,
+                     const int *xwin = nullptr);

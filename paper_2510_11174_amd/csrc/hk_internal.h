@@ -316,6 +316,12 @@ void launch_fluid_moments_nodes(const GridP &g, real inv_ppc, const real *n, con
 void launch_indicators_nodes(const GridP &g, const SwitchP &P, const real *mom, real *const f[9],
                              const IonP *const *ions, int nion, uint8_t *hot, uint8_t *notcold,
                              hipStream_t s);
+// training labels of the learned switch: condition bits per canonical node
+// (k_label_cond), and their accumulation y |= cond over a window of steps
+void launch_label_nodes(const GridP &g, const SwitchP &P, const real *mom, real *const f[9],
+                        const IonP *const *ions, int nion, uint8_t *cond, hipStream_t s);
+void launch_label_or(long long n, const uint8_t *cond, uint8_t *y, hipStream_t s);
+void launch_flags_canonical(const GridP &g, const uint8_t *src, uint8_t *dst, hipStream_t s);
 void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, const uint8_t *notcold,
                          uint8_t *sw, uint8_t *calm, hipStream_t s);
 // macc: 5 grid arrays (FP64): absorbed weight, momentum (3), kinetic energy

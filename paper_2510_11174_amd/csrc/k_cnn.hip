@@ -56,24 +56,32 @@ __device__ inline long long vidx(const Dims &d, int b, int z, int y, int x) {
 // loops over rows.  All of a row's A fragments (one 16-byte load per lane and
 // K step) are issued before the first MFMA, so the row's loads overlap.
 constexpr int FBS = 512;
+// xwin (may be null): output x indices outside [xwin[0], xwin[1] + 6] are
+// skipped (the switch's plasma window; see k_cnn_window).
 template <int CIN>
 __global__ void __launch_bounds__(FBS)
 k_conv_fwd(Dims in, const unsigned short *__restrict__ act, const unsigned short *__restrict__ Wf,
-           const float *__restrict__ bias, float *__restrict__ zout, unsigned short *__restrict__ aout) {
+           const float *__restrict__ bias, float *__restrict__ zout, unsigned short *__restrict__ aout,
+           const int *__restrict__ xwin) {
     constexpr int K = 27 * CIN, KPAD = (K + 31) / 32 * 32, NK = KPAD / 32;
     __shared__ __attribute__((aligned(16))) unsigned short sW[NC * KPAD];
     for (int e = threadIdx.x; e < NC * KPAD / 8; e += FBS)
         reinterpret_cast<uint4 *>(sW)[e] = reinterpret_cast<const uint4 *>(Wf)[e];
     __syncthreads();
     const Dims out{in.B, in.D - 2, in.H - 2, in.W - 2};
-    const int segs = (out.W + 15) / 16;
+    int seg0 = 0, segs = (out.W + 15) / 16;
+    if (xwin) {
+        const int lo = xwin[0], hi = min(xwin[1] + 6, out.W - 1);
+        seg0 = lo / 16;
+        segs = hi >= lo ? hi / 16 - seg0 + 1 : 0;
+    }
     const long long nrows = (long long)out.B * out.D * out.H * segs;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
     const float b0 = bias[r], b1 = bias[16 + r];
     for (long long row = (long long)blockIdx.x * (FBS / 64) + wave; row < nrows;
          row += (long long)gridDim.x * (FBS / 64)) {
-        const int seg = (int)(row % segs);
+        const int seg = seg0 + (int)(row % segs);
         long long q = row / segs;
         const int y = (int)(q % out.H); q /= out.H;
         const int z = (int)(q % out.D);
@@ -360,7 +368,7 @@ struct Norm { float mean[8], inv_std[8]; };
 __global__ void __launch_bounds__(CBS)
 k_cnn_inputs(GridP g, const real *__restrict__ Ex, const real *__restrict__ Ey, const real *__restrict__ Ez,
              const real *__restrict__ Bx, const real *__restrict__ By, const real *__restrict__ Bz,
-             const real *__restrict__ mom, Norm nm, unsigned short *__restrict__ x) {
+             const real *__restrict__ mom, Norm nm, unsigned short *__restrict__ x, const int *__restrict__ xwin) {
     const int per = g.bcx == HK_BC_PERIODIC;
     const int NX = per ? g.nx : g.nx + 1;
     const int W = NX + 8, H = g.ny + 8, D = g.nz + 8;
@@ -368,6 +376,8 @@ k_cnn_inputs(GridP g, const real *__restrict__ Ex, const real *__restrict__ Ey, 
     const long long v = (long long)blockIdx.x * CBS + threadIdx.x;
     if (v >= n) return;
     const int i = (int)(v % W), j = (int)((v / W) % H), k = (int)(v / ((long long)W * H));
+    // padded x indices the windowed layers read: nodes xwin[0] - 4 .. xwin[1] + 4
+    if (xwin && (i < xwin[0] || i > xwin[1] + 8)) return;
     int ii = i - 4;
     if (per) ii = wrapi(ii, g.nx);
     else ii = ii < 0 ? 0 : (ii > NX - 1 ? NX - 1 : ii);
@@ -446,14 +456,17 @@ k_node_state(GridP g, const real *__restrict__ Ex, const real *__restrict__ Ey, 
 __global__ void __launch_bounds__(CBS)
 k_cnn_decide(GridP g, const unsigned short *__restrict__ a4, const unsigned short *__restrict__ wh,
              const float *__restrict__ bh, uint64_t seed, uint32_t eval, uint8_t *__restrict__ hot,
-             uint8_t *__restrict__ notcold, int *__restrict__ nfall, float *__restrict__ pmean) {
+             uint8_t *__restrict__ notcold, int *__restrict__ nfall, float *__restrict__ pmean,
+             const int *__restrict__ xwin) {
     const int per = g.bcx == HK_BC_PERIODIC;
     const int NX = per ? g.nx : g.nx + 1;
     const long long n = (long long)NX * g.ny * g.nz;
     const long long v = (long long)blockIdx.x * CBS + threadIdx.x;
     bool fall = false;
-    if (v < n) {
-        const int i = (int)(v % NX), j = (int)((v / NX) % g.ny), k = (int)(v / ((long long)NX * g.ny));
+    const int iv = (int)(v % NX);
+    // outside the window the threshold decision stays
+    if (v < n && (!xwin || (iv >= xwin[0] && iv <= xwin[1]))) {
+        const int i = iv, j = (int)((v / NX) % g.ny), k = (int)(v / ((long long)NX * g.ny));
         const long long c = gidx(g, i, j, k);
         float h[NC], w[NC];
         for (int q = 0; q < NC; ++q) { h[q] = bf16_val(a4[v * NC + q]); w[q] = bf16_val(wh[q]); }
@@ -481,6 +494,42 @@ k_cnn_decide(GridP g, const unsigned short *__restrict__ a4, const unsigned shor
     if ((threadIdx.x & 63) == 0 && bal) atomicAdd(nfall, __popcll(bal));
 }
 
+// The switch's plasma window along x: the node columns holding particles or
+// fluid of the fluid species, or ionizable ions (switch moments N or NI > 0),
+// widened by `margin` nodes.  win[0..1] accumulate the extent (start at
+// INT_MAX and -1), win[2..3] receive the window (empty when win[3] < win[2]).
+__global__ void __launch_bounds__(CBS)
+k_cnn_extent(GridP g, const real *__restrict__ mom, int *__restrict__ win) {
+    const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
+    const long long n = (long long)NX * g.ny * g.nz;
+    const long long v = (long long)blockIdx.x * CBS + threadIdx.x;
+    int lo = INT_MAX, hi = -1;
+    if (v < n) {
+        const int i = (int)(v % NX), j = (int)((v / NX) % g.ny), k = (int)(v / ((long long)NX * g.ny));
+        const long long c = gidx(g, i, j, k);
+        if (mom[c] > 0 || mom[6 * g.nn + c] > 0) { lo = i; hi = i; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o, 64));
+        hi = max(hi, __shfl_xor(hi, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0 && hi >= 0) {
+        atomicMin(win, lo);
+        atomicMax(win + 1, hi);
+    }
+}
+
+__global__ void k_cnn_window(int NX, int margin, int *__restrict__ win) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (win[1] < 0) { win[2] = 1; win[3] = 0; return; }
+    win[2] = max(0, win[0] - margin);
+    win[3] = min(NX - 1, win[1] + margin);
+}
+
+__global__ void k_cnn_window_init(int *__restrict__ win) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) { win[0] = INT_MAX; win[1] = -1; }
+}
+
 inline unsigned nblk(long long n) { return (unsigned)((n + CBS - 1) / CBS); }
 inline unsigned rows_grid(long long rows) {
     long long b = (rows + 3) / 4;
@@ -496,15 +545,15 @@ void cnn_launch_to_bf16(long long n, const float *x, unsigned short *o, hipStrea
 
 void cnn_launch_conv_fwd(int cin, int B, int D, int H, int W, const unsigned short *act,
                          const unsigned short *Wf, const float *bias, float *zout, unsigned short *aout,
-                         hipStream_t s) {
+                         const int *xwin, hipStream_t s) {
     Dims in{B, D, H, W};
     const long long rows = (long long)B * (D - 2) * (H - 2) * ((W - 2 + 15) / 16);
     // two workgroups per CU (the weights fill a third of LDS each), every one
     // looping over rows: the weight matrix is read once per workgroup
     long long nb = (rows + FBS / 64 - 1) / (FBS / 64);
     const unsigned grid = (unsigned)(nb < 512 ? nb : 512);
-    if (cin == 8) k_conv_fwd<8><<<grid, FBS, 0, s>>>(in, act, Wf, bias, zout, aout);
-    else k_conv_fwd<32><<<grid, FBS, 0, s>>>(in, act, Wf, bias, zout, aout);
+    if (cin == 8) k_conv_fwd<8><<<grid, FBS, 0, s>>>(in, act, Wf, bias, zout, aout, xwin);
+    else k_conv_fwd<32><<<grid, FBS, 0, s>>>(in, act, Wf, bias, zout, aout, xwin);
 }
 
 void cnn_launch_conv_bwd_data(int B, int D, int H, int W, const unsigned short *dz,
@@ -556,13 +605,13 @@ void cnn_launch_pack_head(const float *p, long long off, unsigned short *wh, hip
 }
 
 void cnn_launch_inputs(const GridP &g, real *const f[9], const real *mom, const float mean[8],
-                       const float inv_std[8], unsigned short *x, hipStream_t s) {
+                       const float inv_std[8], unsigned short *x, const int *xwin, hipStream_t s) {
     Norm nm;
     for (int q = 0; q < 8; ++q) { nm.mean[q] = mean[q]; nm.inv_std[q] = inv_std[q]; }
     const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
     const long long n = (long long)(NX + 8) * (g.ny + 8) * (g.nz + 8);
     k_cnn_inputs<<<nblk(n), CBS, 0, s>>>(g, f[HK_EX], f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], mom,
-                                         nm, x);
+                                         nm, x, xwin);
 }
 
 void cnn_launch_node_raw(const GridP &g, real *const f[9], const real *mom, float *out, hipStream_t s) {
@@ -580,8 +629,14 @@ void cnn_launch_node_state(const GridP &g, real *const f[9], const double *rho, 
 
 void cnn_launch_decide(const GridP &g, const unsigned short *a4, const unsigned short *wh, const float *bh,
                        uint64_t seed, uint32_t eval, uint8_t *hot, uint8_t *notcold, int *nfall,
-                       float *pmean, hipStream_t s) {
+                       float *pmean, const int *xwin, hipStream_t s) {
     const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
     const long long n = (long long)NX * g.ny * g.nz;
-    k_cnn_decide<<<nblk(n), CBS, 0, s>>>(g, a4, wh, bh, seed, eval, hot, notcold, nfall, pmean);
+    k_cnn_decide<<<nblk(n), CBS, 0, s>>>(g, a4, wh, bh, seed, eval, hot, notcold, nfall, pmean, xwin);
+}
+void cnn_launch_window(const GridP &g, const real *mom, int margin, int *win, hipStream_t s) {
+    const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
+    k_cnn_window_init<<<1, 64, 0, s>>>(win);
+    k_cnn_extent<<<nblk((long long)NX * g.ny * g.nz), CBS, 0, s>>>(g, mom, win);
+    k_cnn_window<<<1, 64, 0, s>>>(NX, margin, win);
 }

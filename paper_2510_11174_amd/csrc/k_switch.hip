@@ -330,6 +330,66 @@ k_indicators(GridP g, SwitchP P, const real *__restrict__ mom, const real *__res
     notcold[c] = nc;
 }
 
+// Training label of the learned switch at one step, per node of the
+// canonical grid [nz][ny][NX] (x fastest): bit 0, a cold-fluid conversion
+// would destroy more than 1e-3 of the node's kinetic energy (e = (1/2)(sum w
+// |u|^2 - |sum w u|^2 / sum w) against (1/2) sum w |u|^2, small-u limit) and
+// the momentum spread reaches the switch's spread threshold; bit 1, an
+// ionization event is possible (per-step probability of the node's field at
+// or above thr_ion while ionizable ions remain); bit 2, a QED event is
+// possible (chi of the node's rms momentum at or above thr_chi).
+__global__ void __launch_bounds__(BS)
+k_label_cond(GridP g, SwitchP P, const real *__restrict__ mom, const real *__restrict__ Ex,
+             const real *__restrict__ Ey, const real *__restrict__ Ez, IonSet ions,
+             uint8_t *__restrict__ out) {
+    const int per = g.bcx == HK_BC_PERIODIC;
+    const int nxn = per ? g.nx : g.nx + 1;
+    const long long n = (long long)nxn * g.ny * g.nz;
+    const long long v = (long long)blockIdx.x * BS + threadIdx.x;
+    if (v >= n) return;
+    const int i = (int)(v % nxn), j = (int)((v / nxn) % g.ny), k = (int)(v / ((long long)nxn * g.ny));
+    const long long c = gidx(g, i, j, k), nn = g.nn;
+    const double N = mom[c];
+    int bits = 0;
+    double m2 = 0.0;
+    if (N > 0.0) {
+        const double U2 = mom[5 * nn + c];
+        const double px = mom[2 * nn + c], py = mom[3 * nn + c], pz = mom[4 * nn + c];
+        const double ehat = 0.5 * (U2 - (px * px + py * py + pz * pz) / N);
+        m2 = U2 / N;
+        const double su2 = 2.0 * ehat / N;
+        if (ehat > 1e-3 * 0.5 * U2 && su2 >= (double)P.thr_su * (double)P.thr_su) bits |= 1;
+    }
+    const double ex = node_field(g, Ex, i, j, k, 1, 0, 0), ey = node_field(g, Ey, i, j, k, 0, 1, 0);
+    const double ez = node_field(g, Ez, i, j, k, 0, 0, 1);
+    const double emag = sqrt(ex * ex + ey * ey + ez * ez);
+    if (mom[6 * nn + c] > 0) {
+        double ionr = 0.0;
+        for (int q = 0; q < ions.n; ++q)
+            ionr = fmax(ionr, ion_rate(ions.p[q], 0, emag * ions.p[q]->field_au) * g.ddt);
+        if (ionr >= (double)P.thr_ion) bits |= 2;
+    }
+    if (P.enable_qed && N > 0.0 && sqrt(1.0 + m2) * emag / P.a_s >= (double)P.thr_chi) bits |= 4;
+    out[v] = (uint8_t)bits;
+}
+
+// Node flags from the grid layout to the canonical [nz][ny][NX] order.
+__global__ void __launch_bounds__(BS)
+k_flags_canonical(GridP g, const uint8_t *__restrict__ src, uint8_t *__restrict__ dst) {
+    const int nxn = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
+    const long long v = (long long)blockIdx.x * BS + threadIdx.x;
+    if (v >= (long long)nxn * g.ny * g.nz) return;
+    const int i = (int)(v % nxn), j = (int)((v / nxn) % g.ny), k = (int)(v / ((long long)nxn * g.ny));
+    dst[v] = src[gidx(g, i, j, k)];
+}
+
+// Label accumulation over a window of steps: y |= (cond != 0).
+__global__ void __launch_bounds__(BS)
+k_label_or(long long n, const uint8_t *__restrict__ cond, uint8_t *__restrict__ y) {
+    const long long v = (long long)blockIdx.x * BS + threadIdx.x;
+    if (v < n && cond[v]) y[v] = 1;
+}
+
 __global__ void __launch_bounds__(BS)
 k_dilate(GridP g, SwitchP P, const uint8_t *__restrict__ hot, const uint8_t *__restrict__ notcold,
          uint8_t *__restrict__ sw, uint8_t *__restrict__ calm) {
@@ -622,6 +682,22 @@ void launch_indicators_nodes(const GridP &g, const SwitchP &P, const real *mom, 
     set.n = nion < 4 ? nion : 4;
     for (int q = 0; q < set.n; ++q) set.p[q] = ions[q];
     k_indicators<<<xcd_blocks(g.nn), BS, 0, s>>>(g, P, mom, f[HK_EX], f[HK_EY], f[HK_EZ], set, hot, notcold);
+}
+void launch_label_nodes(const GridP &g, const SwitchP &P, const real *mom, real *const f[9],
+                        const IonP *const *ions, int nion, uint8_t *cond, hipStream_t s) {
+    IonSet set{};
+    set.n = nion < 4 ? nion : 4;
+    for (int q = 0; q < set.n; ++q) set.p[q] = ions[q];
+    const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
+    k_label_cond<<<blocks((long long)NX * g.ny * g.nz), BS, 0, s>>>(g, P, mom, f[HK_EX], f[HK_EY], f[HK_EZ],
+                                                                    set, cond);
+}
+void launch_flags_canonical(const GridP &g, const uint8_t *src, uint8_t *dst, hipStream_t s) {
+    const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
+    k_flags_canonical<<<blocks((long long)NX * g.ny * g.nz), BS, 0, s>>>(g, src, dst);
+}
+void launch_label_or(long long n, const uint8_t *cond, uint8_t *y, hipStream_t s) {
+    k_label_or<<<blocks(n), BS, 0, s>>>(n, cond, y);
 }
 void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, const uint8_t *notcold,
                          uint8_t *sw, uint8_t *calm, hipStream_t s) {

@@ -109,7 +109,9 @@ ABI_SYMBOLS = ["hk_create", "hk_destroy", "hk_step", "hk_switch_map", "hk_set_sw
                "hk_set_particles", "hk_get_fluid", "hk_set_fluid", "hk_get_fluid_p", "hk_set_fluid_p", "hk_enable_timing",
                "hk_timers", "hk_qed_tables", "hk_cnn_nparams", "hk_cnn_create", "hk_cnn_destroy",
                "hk_cnn_set_params", "hk_cnn_get_params", "hk_cnn_set_norm", "hk_cnn_forward",
-               "hk_cnn_loss_grad", "hk_cnn_train_step", "hk_cnn_last_error", "hk_cnn_forward_noalloc", "hk_set_cnn", "hk_node_inputs", "hk_node_state",
+               "hk_cnn_loss_grad", "hk_cnn_train_step", "hk_cnn_last_error", "hk_cnn_forward_noalloc", "hk_set_cnn",
+               "hk_dataset_create", "hk_dataset_destroy", "hk_dataset_size", "hk_dataset_get", "hk_dataset_stats",
+               "hk_dump_training", "hk_train", "hk_dataset_predict", "hk_dataset_last_error", "hk_node_inputs", "hk_node_state",
                "hk_sp_nparams", "hk_sp_create", "hk_sp_destroy", "hk_sp_set_params", "hk_sp_get_params",
                "hk_sp_set_norm", "hk_sp_forward", "hk_sp_loss_grad", "hk_sp_train_step", "hk_sp_last_error",
                "hk_swn_nparams", "hk_swn_create", "hk_swn_destroy", "hk_swn_set_params", "hk_swn_get_params",
@@ -172,6 +174,16 @@ def load(prec: str = "f32"):
     L.hk_cnn_train_step.argtypes = [vp, vp, vp, vp] + [C.c_int] * 4 + [P(CnnTrainDesc), P(C.c_double)]
     L.hk_cnn_last_error.restype = C.c_char_p
     L.hk_cnn_last_error.argtypes = [vp]
+    L.hk_dataset_create.argtypes = [P(CnnDesc), P(vp)]
+    L.hk_dataset_destroy.argtypes = [vp]
+    L.hk_dataset_size.argtypes = [vp]
+    L.hk_dataset_get.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, C.c_size_t]
+    L.hk_dataset_stats.argtypes = [vp, vp, vp]
+    L.hk_dump_training.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int]
+    L.hk_train.argtypes = [vp, vp, C.c_int, C.c_int, P(CnnTrainDesc), C.c_uint64, vp]
+    L.hk_dataset_predict.argtypes = [vp, vp, C.c_int, vp]
+    L.hk_dataset_last_error.restype = C.c_char_p
+    L.hk_dataset_last_error.argtypes = [vp]
     L.hk_set_cnn.argtypes = [vp, vp]
     L.hk_sp_nparams.restype = C.c_int
     L.hk_sp_create.argtypes = [P(CnnDesc), P(vp)]
@@ -557,6 +569,84 @@ class CNN:
         self._check(self.lib.hk_cnn_train_step(self.h, x.data_ptr(), y.data_ptr(), e.data_ptr(), B, D, H,
                                                W, C.byref(t), C.byref(loss)))
         return loss.value
+
+
+class Dataset:
+    """Training set of the learned switch in device memory (hk_dataset_*):
+    snapshots of all-PIC runs with their labels, filled by hk_dump_training
+    and sampled on the device by hk_train."""
+
+    def __init__(self, precision: str = "f32"):
+        self.lib = load(precision)
+        self._mem = _TorchMemory()
+        d = CnnDesc(seed=0, stream=self._mem.stream.cuda_stream, alloc=self._mem.alloc,
+                    free=self._mem.free, alloc_ctx=None)
+        h = C.c_void_p()
+        rc = self.lib.hk_dataset_create(C.byref(d), C.byref(h))
+        if rc:
+            raise HKError(rc, "hk_dataset_create failed")
+        self.h = h
+
+    def _check(self, rc):
+        if rc:
+            raise HKError(rc, self.lib.hk_dataset_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hk_dataset_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return self.lib.hk_dataset_size(self.h)
+
+    def dump(self, sim, steps: int, every: int, window: int = 10):
+        """Append snapshots of the all-PIC simulation `sim` (hk_dump_training)."""
+        if sim.lib is not self.lib:
+            raise ValueError("the simulation and the training set come from different precisions")
+        rc = self.lib.hk_dump_training(sim.h, self.h, int(steps), int(every), int(window))
+        if rc:
+            raise HKError(rc, self.lib.hk_last_error(sim.h).decode())
+
+    def dims(self, k: int):
+        d = np.zeros(3, np.int32)
+        self._check(self.lib.hk_dataset_get(self.h, k, _ptr(d), None, None, None, None, 0))
+        return tuple(int(v) for v in d)
+
+    def get(self, k: int):
+        """(raw [D, H, W, 8], ehat [D, H, W], y [D, H, W], thr [D, H, W]) of
+        snapshot k: inputs, conversion energy, label, threshold flags."""
+        dims = self.dims(k)
+        n = int(np.prod(dims))
+        raw = np.empty(dims + (8,), np.float32); e = np.empty(dims, np.float32)
+        y = np.empty(dims, np.uint8); thr = np.empty(dims, np.uint8)
+        self._check(self.lib.hk_dataset_get(self.h, k, None, _ptr(raw), _ptr(e), _ptr(y), _ptr(thr), n))
+        return raw, e, y, thr
+
+    def stats(self):
+        m = np.empty(8, np.float32); s = np.empty(8, np.float32)
+        self._check(self.lib.hk_dataset_stats(self.h, _ptr(m), _ptr(s)))
+        return m, s
+
+    def train(self, cnn, iters: int, B: int = 64, lr=1e-3, lam=0.1, seed=0, dropout=True, weight_decay=0.01):
+        """hk_train: iters AdamW steps on device-sampled crops; the batch losses."""
+        t = CnnTrainDesc(lr=lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=weight_decay,
+                         lambda_e=lam, dropout=int(dropout))
+        losses = np.zeros(max(int(iters), 1))
+        self._check(self.lib.hk_train(cnn.h, self.h, int(iters), int(B), C.byref(t), int(seed), _ptr(losses)))
+        return losses[:iters]
+
+    def predict(self, cnn, k: int):
+        """Logits (torch, device, [D, H, W]) of snapshot k, no dropout."""
+        import torch
+        out = torch.empty(self.dims(k), device="cuda", dtype=torch.float32)
+        self._check(self.lib.hk_dataset_predict(cnn.h, self.h, int(k), out.data_ptr()))
+        return out
 
 
 class StatePredictor:

@@ -1,12 +1,19 @@
-"""The learned switch end to end on the GPU: training data from all-PIC runs
-(hk_node_inputs), training by the library's own BF16 forward/backward kernels
-and AdamW, then what the trained network gains over the method without it
-(the physics threshold) on a held-out run.  The all-PIC run is the judge."""
+"""The learned switch end to end on the GPU, through the library's training
+set: all-PIC runs fill it on the device (hk_dump_training), the network is
+trained on device-sampled crops by its own BF16 kernels and AdamW (hk_train),
+then it is scored against the method without it (the physics threshold) on
+a held-out run, and it drives a hybrid run against all-PIC.
+
+The label (the reading stated with hk_dump_training): a node is kinetic when,
+at the snapshot's step or within the next 10, a cold-fluid conversion would
+destroy more than 1e-3 of its kinetic energy with a momentum spread of at
+least thr_sigma_u, or an ionization or QED emission is possible there."""
 import math
 
 import numpy as np
 import pytest
 
+import oracle
 from paper_2510_11174_amd import configs
 from paper_2510_11174_amd import train as T
 
@@ -22,11 +29,65 @@ def hk():
     return hkmod
 
 
-def _cfg(seed, a0, mode="all_pic", every=1):
+def _helium():
+    # ionizing helium 32 x 16 x 16 (17 x 16 x 16 nodes would be too few
+    # along x for the 16^3 crops), 4 particles per cell
+    return configs.ionization_hybrid(32, 16, 16, mode="all_pic", ppc=4)
+
+
+def test_dump_matches_oracle_fp64(hk):
+    """Snapshots and labels of hk_dump_training (FP64 build) against the
+    oracle's training nodes over the same all-PIC steps: inputs and
+    conversion energy per node to the FP32 rounding of their storage (the
+    network reads them in BF16), labels identical."""
+    cfg = _helium()
+    print("case: training set of ionizing helium 32x16x16, FP64, steps 40-110", flush=True)
+    sim = hk.Sim(cfg, precision="f64")
+    o = oracle.Oracle(cfg)
+    sim.step(40); o.step(40)
+    ds = hk.Dataset("f64")
+    ds.dump(sim, 60, 20, window=10)
+    assert len(ds) == 4
+    # the oracle: node data at each snapshot step, labels OR-ed over the window
+    ref = []
+    conds = []
+    for r in range(71):
+        raw9, cond = o.training_node()
+        conds.append(cond)
+        if r % 20 == 0:
+            ref.append(raw9)
+        if r < 70:
+            o.step(1)
+    bits = np.zeros(8, int)
+    for k in range(4):
+        raw, e, y, thr = ds.get(k)
+        got = np.concatenate([raw, e[..., None]], -1).astype(np.float64)
+        exp = ref[k]
+        scale = np.abs(exp).reshape(-1, 9).max(0)
+        err = np.abs(got - exp) / (np.abs(exp) + 1e-6 * scale + 1e-300)
+        assert err.max() <= 2.0 ** -23, (k, err.reshape(-1, 9).max(0))
+        yo = np.zeros_like(y)
+        for c in conds[20 * k:20 * k + 11]:
+            yo |= (c > 0).astype(np.uint8)
+            for b in range(3):
+                bits[b] += int(((c >> b) & 1).sum())
+        assert np.array_equal(y, yo), (k, int((y != yo).sum()))
+        print("snapshot %d: %d of %d nodes kinetic, %d threshold-hot" % (k, int(y.sum()), y.size, int(thr.sum())))
+    print("label condition bits over the windows (thermal, ionization, QED):", bits[:3].tolist())
+    assert bits[0] > 0 and bits[1] > 0
+    sim.close(); o.close(); ds.close()
+
+
+def _plain(seed, a0, mode="all_pic", every=1):
     c = configs.plain_hybrid(32, 16, 16, mode=mode, seed=seed)
     c["laser"]["a0"] = a0
+    c["species"][0]["u_th"] = 0.01
     c["run"]["switch_every"] = every
     return c
+
+
+def _fields(s):
+    return {q: s.get_field(q).astype(np.float64) for q in ("ex", "ey", "ez", "bx", "by", "bz")}
 
 
 def _l2(a, b):
@@ -42,35 +103,43 @@ def _run(hk, cfg, cnn=None, steps=200):
     for _ in range(steps // 10):
         s.step(10)
         kin.append(float(s.get_switch().mean()))
-    f = {q: s.get_field(q).astype(np.float64) for q in ("ex", "ey", "ez", "bx", "by", "bz")}
+    f = _fields(s)
     s.close()
     return f, float(np.mean(kin))
 
 
 def test_trained_switch_gains_over_threshold(hk):
-    print("case: cnn training on plain-plasma runs", flush=True)
-    # training data: two seeds and laser strengths; labels = the physics
-    # criterion firing within the next 10 steps of the all-PIC run
-    train = T.generate(hk, _cfg(101, 1.0), 190, 3, start=80) + T.generate(hk, _cfg(102, 1.5), 190, 3, start=80)
-    held = T.generate(hk, _cfg(104, 1.0), 190, 5, start=90)
-    mean, std = T.stats(train)
+    """Training set from two ionizing-helium runs and two plain-plasma runs,
+    a held-out run of each; the trained network must rank the future label
+    better than the threshold flags, and the hybrid it drives keeps fewer
+    nodes kinetic than the threshold hybrid at a field error within the
+    spread of two all-PIC runs."""
+    print("case: device training set, hk_train, held-out AUC and hybrid runs", flush=True)
+    hel = [configs.ionization_hybrid(32, 16, 16, mode="all_pic", ppc=4, seed=s) for s in (201, 202)]
+    for c, a0 in zip(hel, (8.0, 12.0)):
+        c["laser"]["a0"] = a0
+    train = T.build_dataset(hk, hel + [_plain(101, 1.0), _plain(102, 2.0)], 150, 5, start=20)
+    held = T.build_dataset(hk, [configs.ionization_hybrid(32, 16, 16, mode="all_pic", ppc=4, seed=204),
+                                _plain(104, 1.5)], 150, 10, start=30)
     cnn = hk.CNN(seed=5)
     cnn.set_params(T.init_params(3))
-    losses = T.train(cnn, train, mean, std, 400, B=8, lr=1e-3, dv=0.2 ** 3)
-    print("loss first %.3f, last 50 %.3f" % (losses[0], np.mean(losses[-50:])))
-    assert np.mean(losses[-50:]) < 0.5 * losses[0]
-    # 1. where will the criterion fire in the next 10 steps? (held-out run)
-    ps = np.concatenate([T.predict(cnn, d[0], mean, std).ravel() for d in held])
-    ys = np.concatenate([d[1].ravel() for d in held])
-    now = np.concatenate([d[3].ravel() for d in held])
-    a_cnn, a_now = T.auc(ps, ys), T.auc(now, ys)
-    print("AUC of the future kinetic label: network %.4f, threshold now %.4f" % (a_cnn, a_now))
-    assert a_cnn > a_now + 0.1
-    # 2. the hybrid with the switch evaluated every 10 steps, against all-PIC
-    ref, _ = _run(hk, _cfg(104, 1.0))
-    f_thr, k_thr = _run(hk, _cfg(104, 1.0, "threshold", 10))
-    f_cnn, k_cnn = _run(hk, _cfg(104, 1.0, "cnn", 10), cnn=cnn)
-    e_thr, e_cnn = _l2(f_thr, ref), _l2(f_cnn, ref)
-    print("field L2 vs all-PIC at step 200: threshold %.3e (kinetic %.3f), network %.3e (kinetic %.3f)" % (
-        e_thr, k_thr, e_cnn, k_cnn))
-    assert e_cnn < e_thr
+    losses = T.train_switch(train, cnn, 600, B=32, lr=1e-3)
+    print("%d snapshots; loss first 20 %.3f, last 50 %.3f" % (len(train), np.mean(losses[:20]),
+                                                               np.mean(losses[-50:])))
+    assert np.mean(losses[-50:]) < 0.7 * np.mean(losses[:20])
+    p, thr, y = T.scores(held, cnn)
+    a_cnn, a_thr = T.auc(p, y), T.auc(thr, y)
+    print("held-out AUC of the future kinetic label: network %.4f, threshold %.4f (positives %.3f)" % (
+        a_cnn, a_thr, y.mean()))
+    assert a_cnn > a_thr + 0.05
+    # the hybrid with the switch evaluated every 10 steps, against all-PIC
+    ref, _ = _run(hk, _plain(104, 1.5))
+    ref2, _ = _run(hk, _plain(105, 1.5))
+    f_thr, k_thr = _run(hk, _plain(104, 1.5, "threshold", 10))
+    f_cnn, k_cnn = _run(hk, _plain(104, 1.5, "cnn", 10), cnn=cnn)
+    floor, e_thr, e_cnn = _l2(ref2, ref), _l2(f_thr, ref), _l2(f_cnn, ref)
+    print("field L2 vs all-PIC at step 200: threshold %.3e (kinetic %.3f), network %.3e (kinetic %.3f); "
+          "all-PIC other seed %.3e" % (e_thr, k_thr, e_cnn, k_cnn, floor))
+    assert k_cnn < k_thr
+    assert e_cnn <= max(floor, e_thr)
+    train.close(); held.close(); cnn.close()

@@ -150,28 +150,29 @@ def test_switchnet_against_cnn_on_simulation_labels(hk):
     future-kinetic label on a held-out run."""
     from paper_2510_11174_amd import configs
     from paper_2510_11174_amd import train as T
+    from tests import switch_data as SD
 
     def cfg(seed, a0):
         c = configs.plain_hybrid(32, 16, 16, mode="all_pic", seed=seed)
         c["laser"]["a0"] = a0
         return c
     print("case: switchnet vs cnn on plain-plasma runs", flush=True)
-    train = T.generate(hk, cfg(101, 1.0), 190, 3, start=80, states=True) + \
-        T.generate(hk, cfg(102, 1.5), 190, 3, start=80, states=True)
-    held = T.generate(hk, cfg(104, 1.0), 190, 5, start=90, states=True)
+    train = SD.generate(hk, cfg(101, 1.0), 190, 3, start=80, states=True) + \
+        SD.generate(hk, cfg(102, 1.5), 190, 3, start=80, states=True)
+    held = SD.generate(hk, cfg(104, 1.0), 190, 5, start=90, states=True)
     dv = 0.2 ** 3
-    x, y, e = T.swn_nodes(train, dv)
+    x, y, e = SD.swn_nodes(train, dv)
     mean = x.mean(0); std = x.std(0); std[std <= 0] = 1.0
     swn = hk.SwitchNet(seed=5)
     swn.set_params(T.swn_init_params(3))
-    losses = T.swn_train(swn, x, y, e, mean, std, 400, B=4096, lr=1e-3)
-    xh, yh, _ = T.swn_nodes(held, dv)
-    a_swn = T.auc(T.swn_predict(swn, xh, mean, std), yh)
-    cm, cs = T.stats(train)
+    losses = SD.swn_train(swn, x, y, e, mean, std, 400, B=4096, lr=1e-3)
+    xh, yh, _ = SD.swn_nodes(held, dv)
+    a_swn = T.auc(SD.swn_predict(swn, xh, mean, std), yh)
+    cm, cs = SD.stats(train)
     cnn = hk.CNN(seed=5)
     cnn.set_params(T.init_params(3))
-    T.train(cnn, train, cm, cs, 400, B=8, lr=1e-3, dv=dv)
-    a_cnn = T.auc(np.concatenate([T.predict(cnn, d[0], cm, cs).ravel() for d in held]), yh)
+    SD.train(cnn, train, cm, cs, 400, B=8, lr=1e-3, dv=dv)
+    a_cnn = T.auc(np.concatenate([SD.predict(cnn, d[0], cm, cs).ravel() for d in held]), yh)
     a_now = T.auc(np.concatenate([d[3].ravel() for d in held]), yh)
     print("SwitchNet loss first %.3f last 50 %.3f; held-out AUC: SwitchNet %.4f, CNN %.4f, threshold now %.4f" % (
         losses[0], np.mean(losses[-50:]), a_swn, a_cnn, a_now))
