@@ -73,7 +73,7 @@ k_conv_fwd(Dims in, const unsigned short *__restrict__ act, const unsigned short
     if (xwin) {
         const int lo = xwin[0], hi = min(xwin[1] + 6, out.W - 1);
         seg0 = lo / 16;
-        segs = hi >= lo ? hi / 16 - seg0 + 1 : 0;
+        segs = xwin[1] >= lo && hi >= lo ? hi / 16 - seg0 + 1 : 0;
     }
     const long long nrows = (long long)out.B * out.D * out.H * segs;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -377,7 +377,7 @@ k_cnn_inputs(GridP g, const real *__restrict__ Ex, const real *__restrict__ Ey, 
     if (v >= n) return;
     const int i = (int)(v % W), j = (int)((v / W) % H), k = (int)(v / ((long long)W * H));
     // padded x indices the windowed layers read: nodes xwin[0] - 4 .. xwin[1] + 4
-    if (xwin && (i < xwin[0] || i > xwin[1] + 8)) return;
+    if (xwin && (xwin[1] < xwin[0] || i < xwin[0] || i > xwin[1] + 8)) return;
     int ii = i - 4;
     if (per) ii = wrapi(ii, g.nx);
     else ii = ii < 0 ? 0 : (ii > NX - 1 ? NX - 1 : ii);
