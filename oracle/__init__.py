@@ -117,6 +117,8 @@ def lib():
         L.or_set_switch.argtypes = [C.c_void_p, C.c_void_p]
         L.or_set_switch_mode.argtypes = [C.c_void_p, C.c_int]
         L.or_training_node.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_ion_probe.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+        L.or_qed_probe.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.or_diagnostics.argtypes = [C.c_void_p, P(Diag)]
         L.or_get_rho.argtypes = [C.c_void_p, C.c_void_p]
         L.or_get_divE.argtypes = [C.c_void_p, C.c_void_p]
@@ -326,6 +328,25 @@ class Oracle:
         cond = np.empty(dims, np.uint8)
         lib().or_training_node(self.h, _ptr(raw), _ptr(cond))
         return raw, cond
+
+    def ion_probe(self, sp: int):
+        """{id: (P[z_max], r[z_max])} for the next step's ionization of ion
+        species sp (event at level l when r[l] < P[l])."""
+        n = self.count(sp)
+        zm = int(self.cfg["species"][sp].get("z_max", 1))
+        P = np.zeros((n, zm)); r = np.zeros((n, zm))
+        lib().or_ion_probe(self.h, sp, _ptr(P), _ptr(r))
+        ids = self.get_particles(sp)["id"]
+        return {int(i): (P[k], r[k]) for k, i in enumerate(ids)}
+
+    def qed_probe(self, sp: int):
+        """{id: (tau, dtau)} for the next step's QED event of species sp
+        (event when tau - dtau <= 0)."""
+        n = self.count(sp)
+        t = np.zeros(n); d = np.zeros(n)
+        lib().or_qed_probe(self.h, sp, _ptr(t), _ptr(d))
+        ids = self.get_particles(sp)["id"]
+        return {int(i): (t[k], d[k]) for k, i in enumerate(ids)}
 
     def set_cnn(self, params, mean, std):
         """Install the switch network (FP64 parameter vector) and input statistics."""

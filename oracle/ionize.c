@@ -82,3 +82,31 @@ void or_ionize_particle(or_sim *s, int isp, size_t i, double emag) {
         s->ion_energy += p->w[i] * sp->ip_ev[lev] / 510998.95;   /* m_e c^2 units */
     }
 }
+
+/* What the next step's ionization of ion species isp decides, per particle i
+ * (the oracle's order) and level l < z_max: the probability P[i z_max + l] of
+ * the transition l -> l + 1 in that step at the field the push gathers and
+ * the uniform draw r[i z_max + l] it compares with (event when r < P); both 0
+ * for levels below the particle's charge.  Test infrastructure: it lets a
+ * comparison check that an event decided differently elsewhere lay within
+ * rounding of its threshold. */
+void or_ion_probe(or_sim *s, int isp, double *P, double *r) {
+    const or_species *sp = &s->sp[isp];
+    const or_parts *p = &s->p[isp];
+    int zm = sp->z_max;
+    for (size_t i = 0; i < p->n; ++i) {
+        int c[3] = {p->ci[i], p->cj[i], p->ck[i]};
+        double X0[3] = {p->ox[i], p->oy[i], p->oz[i]}, e[3];
+        for (int d = 0; d < 3; ++d) e[d] = or_gather(s, OR_EX + d, c, X0);
+        double emag = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        for (int l = 0; l < zm; ++l) {
+            P[i * zm + l] = 0.0;
+            r[i * zm + l] = 0.0;
+            if (l < p->zc[i]) continue;
+            uint32_t q[4];
+            or_draw4(s, p->id[i], (uint32_t)s->step, 3 + (uint32_t)l, 0, q);
+            P[i * zm + l] = -expm1(-or_ion_rate_norm(s, isp, l, emag) * s->g.dt);
+            r[i * zm + l] = or_uniform(q[0]);
+        }
+    }
+}

@@ -127,6 +127,12 @@ int or_set_switch_mode(or_sim *s, int mode);
  * network inputs and the conversion energy per node, cond the label
  * condition bits (1 thermal, 2 ionization possible, 4 QED possible). */
 void or_training_node(or_sim *s, double *raw9, uint8_t *cond);
+/* The next step's Monte Carlo decisions, for comparisons of events decided
+ * in another precision: per particle of species isp (the oracle's order),
+ * ionization P and draw r per level [n][z_max] (event when r < P), and QED
+ * optical depth tau and its decrement dtau (event when tau - dtau <= 0). */
+void or_ion_probe(or_sim *s, int isp, double *P, double *r);
+void or_qed_probe(or_sim *s, int isp, double *tau, double *dtau);
 
 int or_diagnostics(or_sim *s, or_diag *d);
 /* Charge density (nodes) and div E, canonical layout. */

@@ -445,3 +445,31 @@ void or_photon_phase(or_sim *s) {
         }
     }
 }
+
+/* What the next step's QED decides for species isp (leptons: emission,
+ * photons: pair creation), per particle i in the oracle's order: its optical
+ * depth tau[i] and the decrement dtau[i] = W dt at the fields the push
+ * gathers (0 below chi_min); the event fires when tau - dtau <= 0.  Test
+ * infrastructure, as or_ion_probe. */
+void or_qed_probe(or_sim *s, int isp, double *tau, double *dtau) {
+    or_qed *q = (or_qed *)s->qed;
+    const or_parts *p = &s->p[isp];
+    int photon = s->sp[isp].kind == OR_PHOTON;
+    for (size_t i = 0; i < p->n; ++i) {
+        tau[i] = p->tau[i];
+        dtau[i] = 0.0;
+        if (!q) continue;
+        int c[3] = {p->ci[i], p->cj[i], p->ck[i]};
+        double X0[3] = {p->ox[i], p->oy[i], p->oz[i]}, e[3], b[3];
+        for (int d = 0; d < 3; ++d) {
+            e[d] = or_gather(s, OR_EX + d, c, X0);
+            b[d] = or_gather(s, OR_BX + d, c, X0);
+        }
+        double u[3] = {p->ux[i], p->uy[i], p->uz[i]};
+        double chi = or_qed_chi(q->a_s, e, b, u, photon);
+        if (!(chi > OR_CHI_MIN)) continue;
+        double pm = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        double en = photon ? pm : sqrt(1.0 + pm * pm);
+        dtau[i] = OR_ALPHA * q->a_s / en * lookup_w(photon ? q->Wb : q->We, chi) * s->g.dt;
+    }
+}

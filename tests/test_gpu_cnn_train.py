@@ -63,9 +63,14 @@ def test_dump_matches_oracle_fp64(hk):
         raw, e, y, thr = ds.get(k)
         got = np.concatenate([raw, e[..., None]], -1).astype(np.float64)
         exp = ref[k]
+        # FP32 storage rounding per value, plus the multi-step FP64 bar on the
+        # scale of the fields (a weak component such as By carries the
+        # rounding of the strong ones) or of the channel itself
         scale = np.abs(exp).reshape(-1, 9).max(0)
-        err = np.abs(got - exp) / (np.abs(exp) + 1e-6 * scale + 1e-300)
-        assert err.max() <= 2.0 ** -23, (k, err.reshape(-1, 9).max(0))
+        scale[:6] = scale[:6].max()
+        bound = 2.0 ** -23 * np.abs(exp) + 1e-10 * scale
+        excess = (np.abs(got - exp) / bound).reshape(-1, 9).max(0)
+        assert excess.max() <= 1.0, (k, excess)
         yo = np.zeros_like(y)
         for c in conds[20 * k:20 * k + 11]:
             yo |= (c > 0).astype(np.uint8)

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2510_11174_amd import configs
-from tests.parity import field_errors, particle_errors, rel_l2
+from tests.parity import assert_cells, cell_errors, field_errors, particle_errors, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -68,9 +68,12 @@ def test_one_step(hk, oracle_mod, prec, bc):
     g.step(1); o.step(1)
     pos, mom, w = particle_errors(g.get_particles(0), o.get_particles(0), _dx(cfg), _box(cfg))
     errs = field_errors(g, o)
+    cells = cell_errors(g, o)
     print("pos %.2e mom %.2e" % (pos, mom), {k: "%.1e" % v for k, v in errs.items()})
+    print("per cell (max, 99.9%%, max|a-b|/max|b|):", {k: "%.1e %.1e %.1e" % v for k, v in cells.items()})
     assert pos <= TOL[prec] and mom <= TOL[prec]
     assert max(errs.values()) <= TOL[prec]
+    assert_cells(cells, TOL[prec])
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
@@ -118,9 +121,12 @@ def test_dense_tiles_split_over_workgroups(hk, oracle_mod, prec):
     assert g.count(0) == o.count(0) == 40 * 16 ** 3
     pos, mom, w = particle_errors(g.get_particles(0), o.get_particles(0), _dx(cfg), _box(cfg))
     errs = field_errors(g, o)
+    cells = cell_errors(g, o)
     print("pos %.2e mom %.2e" % (pos, mom), {k: "%.1e" % v for k, v in errs.items()})
+    print("per cell (max, 99.9%%, max|a-b|/max|b|):", {k: "%.1e %.1e %.1e" % v for k, v in cells.items()})
     tol = 2e-5 if prec == "f32" else 1e-12
     assert pos <= tol and mom <= tol and max(errs.values()) <= tol
+    assert_cells(cells, tol)
 
 
 def test_ragged_tiles_and_tiny_box(hk, oracle_mod):
