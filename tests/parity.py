@@ -10,6 +10,12 @@ Metrics (stated once, used everywhere):
              scale carries the rounding of that scale, so the bar holds for
              99.9% of the cells and every cell's error stays within the bar
              times the component's scale (|a - b| <= bar max|b|)
+  diagnostics every hk_diag field: step exactly; time, and kinetic and
+             fallback fractions, absolutely; energies (fields, particles,
+             fluids, ledgers) on the scale of the total energy; particle
+             counts exactly (FP32 Monte Carlo flips aside, counted by the
+             event tests); fluid mass and total charge relatively; the Gauss
+             residuals are round-off measures: both sides below a stated bound
 """
 import numpy as np
 
@@ -71,3 +77,40 @@ def assert_cells(errs, bar):
     for c, (mx, p999, absr) in errs.items():
         assert p999 <= bar, (c, "99.9th percentile", p999, bar)
         assert absr <= bar, (c, "max |a - b| / max|b|", absr, bar)
+
+
+ENERGY_KEYS = ("kin", "fluid_kin", "fluid_th")
+LEDGER_KEYS = ("u_e", "u_b", "conv_loss", "ion_energy", "photon_energy")
+
+
+def diag_errors(dg: dict, do: dict, nsp: int):
+    """Per hk_diag field, the error in the metric above (counts: absolute
+    difference; the rest: relative to their scale)."""
+    etot = sum(abs(do[k]) for k in LEDGER_KEYS) + sum(abs(v) for k in ENERGY_KEYS for v in do[k][:nsp])
+    etot = max(etot, 1e-300)
+    out = {"step": abs(dg["step"] - do["step"]), "t": abs(dg["t"] - do["t"]) / max(abs(do["t"]), 1.0)}
+    for k in LEDGER_KEYS:
+        out[k] = abs(dg[k] - do[k]) / etot
+    for k in ENERGY_KEYS:
+        out[k] = max(abs(a - b) for a, b in zip(dg[k][:nsp], do[k][:nsp])) / etot
+    out["count"] = max(abs(a - b) for a, b in zip(dg["count"][:nsp], do["count"][:nsp]))
+    fm = max(sum(abs(v) for v in do["fluid_mass"][:nsp]), 1e-300)
+    out["fluid_mass"] = max(abs(a - b) for a, b in zip(dg["fluid_mass"][:nsp], do["fluid_mass"][:nsp])) / fm
+    out["charge_total"] = abs(dg["charge_total"] - do["charge_total"]) / max(abs(do["charge_total"]), 1e-300)
+    for k in ("kinetic_fraction", "fallback_fraction"):
+        out[k] = abs(dg[k] - do[k])
+    return out
+
+
+def assert_diag(dg: dict, do: dict, nsp: int, tol: float, gauss_bound: float, frac_tol: float = 0.0,
+                count_tol: float = 0.0):
+    e = diag_errors(dg, do, nsp)
+    print("diagnostics errors:", {k: "%.1e" % v for k, v in e.items()})
+    assert e["step"] == 0 and e["t"] <= 1e-12
+    for k in LEDGER_KEYS + ENERGY_KEYS + ("fluid_mass", "charge_total"):
+        assert e[k] <= tol, (k, e[k], tol)
+    assert e["count"] <= count_tol, ("count", e["count"])
+    for k in ("kinetic_fraction", "fallback_fraction"):
+        assert e[k] <= frac_tol, (k, e[k])
+    for k in ("gauss_max", "gauss_l2"):
+        assert dg[k] <= gauss_bound and do[k] <= gauss_bound, (k, dg[k], do[k], gauss_bound)

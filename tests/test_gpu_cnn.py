@@ -104,20 +104,24 @@ def test_adamw_steps(hk, oracle_mod):
     assert rl <= 2e-2
 
 
-def test_cnn_switch_mode(hk, oracle_mod):
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_cnn_switch_mode(hk, oracle_mod, prec):
     # the learned switch inside the step: same network and statistics on both
-    # sides; maps compared node by node after a few evaluations
+    # sides; maps compared node by node after a few evaluations.  The network
+    # runs in BF16 in both builds; the build sets the precision of the fields
+    # and moments it reads (a node whose mean p or spread sits at a decision
+    # threshold may go either way: at most 2e-3 of the nodes)
     cfg = configs.plain_hybrid(24, 12, 12, mode="cnn")
     cfg["run"]["switch_every"] = 10
-    print("case: cnn switch", cfg["name"], flush=True)
+    print("case: cnn switch", cfg["name"], prec, flush=True)
     # statistics and head bias chosen so that the map is mixed (about 80% kinetic)
     p = _params(oracle_mod, 14, scale=0.5)
     p[-1] = -0.8
     p = p.astype(np.float32).astype(np.float64)
     mean = np.array([0, 0, 0, 0, 0, 0, 0.01, 0], np.float32)
     std = np.array([0.01, 0.01, 0.01, 0.01, 0.01, 0.01, 1e-4, 1e-3], np.float32)
-    g = hk.Sim(cfg, precision="f64"); o = oracle_mod.Oracle(cfg)
-    c = hk.CNN(seed=cfg["run"]["seed"], precision="f64")
+    g = hk.Sim(cfg, precision=prec); o = oracle_mod.Oracle(cfg)
+    c = hk.CNN(seed=cfg["run"]["seed"], precision=prec)
     c.set_params(p); c.set_norm(mean, std)
     g.set_cnn(c)
     o.set_cnn(p, mean.astype(np.float64), std.astype(np.float64))

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2510_11174_amd import configs
-from tests.parity import field_errors, match_particles, particle_errors, rel_l2
+from tests.parity import assert_diag, field_errors, match_particles, particle_errors, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -89,6 +89,7 @@ def test_fixed_map_conversions(hk, oracle_mod, prec):
     dg, do = g.diagnostics(), o.diagnostics()
     assert dg["gauss_max"] <= (1e-6 if prec == "f32" else 1e-13)
     assert abs(dg["conv_loss"] - do["conv_loss"]) <= (1e-5 if prec == "f32" else 1e-12) * abs(do["conv_loss"]) + 1e-18
+    assert_diag(dg, do, len(cfg["species"]), tol, 1e-6 if prec == "f32" else 1e-13)
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2510_11174_amd import configs
-from tests.parity import assert_cells, cell_errors, field_errors, particle_errors, rel_l2
+from tests.parity import assert_cells, assert_diag, cell_errors, field_errors, particle_errors, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -74,6 +74,9 @@ def test_one_step(hk, oracle_mod, prec, bc):
     assert pos <= TOL[prec] and mom <= TOL[prec]
     assert max(errs.values()) <= TOL[prec]
     assert_cells(cells, TOL[prec])
+    # every diagnostic after the step; Gauss residuals at the bars of the
+    # charge-conservation test (0.01 n_c plasma)
+    assert_diag(g.diagnostics(), o.diagnostics(), 1, TOL[prec], (2e-4 if prec == "f32" else 1e-11) * 0.01)
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
@@ -92,6 +95,9 @@ def test_hundred_steps_c1(hk, oracle_mod, prec):
     assert max(errs.values()) <= (1e-2 if prec == "f32" else 1e-10)
     dg, do = g.diagnostics(), o.diagnostics()
     assert abs(dg["u_e"] + dg["u_b"] - do["u_e"] - do["u_b"]) <= 1e-4 * (do["u_e"] + do["u_b"])
+    # every diagnostic after 100 steps: the multi-step bars (FP32 energies
+    # follow the fields' 1e-4)
+    assert_diag(dg, do, 1, 1e-4 if prec == "f32" else 1e-10, (2e-4 if prec == "f32" else 1e-11) * 0.01)
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
