@@ -15,7 +15,7 @@ Metrics (stated once, used everywhere):
              fluids, ledgers) on the scale of the total energy; particle
              counts exactly (FP32 Monte Carlo flips aside, counted by the
              event tests); fluid mass and total charge relatively; the Gauss
-             residuals are round-off measures: both sides below a stated bound
+             residuals relatively, plus a stated round-off floor
 """
 import numpy as np
 
@@ -56,28 +56,33 @@ def field_errors(gpu, ora, comps=FIELDS):
 
 
 
-def cell_errors(gpu, ora, comps=FIELDS):
+def cell_errors(gpu, ora, comps=FIELDS, bar=1e-5):
     """Per component: (max per-cell error, its 99.9th percentile, max |a - b| /
-    max|b|) with the per-cell metric above."""
+    max|b|, fraction of cells within `bar`) with the per-cell metric above."""
     out = {}
     for c in comps:
         a = np.asarray(gpu.get_field(c), float); b = np.asarray(ora.get_field(c), float)
         scale = np.abs(b).max()
         if scale == 0.0:
-            out[c] = (float(np.abs(a).max()), float(np.abs(a).max()), float(np.abs(a).max()))
+            m = float(np.abs(a).max())
+            out[c] = (m, m, m, float((np.abs(a) <= bar).mean()))
             continue
         e = np.abs(a - b) / (np.abs(b) + 1e-6 * scale)
-        out[c] = (float(e.max()), float(np.percentile(e, 99.9)), float(np.abs(a - b).max() / scale))
+        out[c] = (float(e.max()), float(np.percentile(e, 99.9)), float(np.abs(a - b).max() / scale),
+                  float((e <= bar).mean()))
     return out
 
 
-def assert_cells(errs, bar):
-    """99.9% of the cells within `bar`, every cell's error within `bar` of
-    the component's scale (see the metric's note)."""
-    for c, (mx, p999, absr) in errs.items():
-        assert p999 <= bar, (c, "99.9th percentile", p999, bar)
+def assert_cells(errs, bar, p999_bar=None):
+    """Every cell's error within `bar` of the component's scale, and 99.9% of
+    the cells within p999_bar (default `bar`) in the per-cell metric.  In
+    FP32 a cell whose value cancels to a small part of the component's scale
+    carries a few units of rounding of that scale: its relative error can
+    exceed the bar while |a - b| stays near 1e-7 max|b|."""
+    p999_bar = bar if p999_bar is None else p999_bar
+    for c, (mx, p999, absr, frac) in errs.items():
         assert absr <= bar, (c, "max |a - b| / max|b|", absr, bar)
-
+        assert p999 <= p999_bar, (c, "99.9th percentile", p999, p999_bar)
 
 ENERGY_KEYS = ("kin", "fluid_kin", "fluid_th")
 LEDGER_KEYS = ("u_e", "u_b", "conv_loss", "ion_energy", "photon_energy")
@@ -113,4 +118,4 @@ def assert_diag(dg: dict, do: dict, nsp: int, tol: float, gauss_bound: float, fr
     for k in ("kinetic_fraction", "fallback_fraction"):
         assert e[k] <= frac_tol, (k, e[k])
     for k in ("gauss_max", "gauss_l2"):
-        assert dg[k] <= gauss_bound and do[k] <= gauss_bound, (k, dg[k], do[k], gauss_bound)
+        assert abs(dg[k] - do[k]) <= tol * abs(do[k]) + gauss_bound, (k, dg[k], do[k], gauss_bound)
