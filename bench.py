@@ -103,15 +103,18 @@ def workload(a0, mode, seed=None, grid=FULL_GRID):
     return cfg
 
 
-def run_window(cfg, warmup, steps, precision="f32", timing=True, snap=True):
+def run_window(cfg, warmup, steps, precision="f32", timing=True, snap=True, cnn=None):
     """W untimed steps, then K steps under the clock (device synchronisation on
-    both sides); timers (HIP events on the library stream) cover the K steps."""
+    both sides); timers (HIP events on the library stream) cover the K steps.
+    cnn: the switch network of a learned-switch run."""
     import numpy as np
     import torch
 
     from paper_2510_11174_amd import hk
     t0 = time.perf_counter()
     sim = hk.Sim(cfg, precision=precision)
+    if cnn is not None:
+        sim.set_cnn(cnn)
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t0
     if warmup:
@@ -130,6 +133,39 @@ def run_window(cfg, warmup, steps, precision="f32", timing=True, snap=True):
     del sim
     torch.cuda.empty_cache()
     return {"seconds": seconds, "timers": tm, "diag0": d0, "diag": d, "snaps": snaps, "create_s": create_s}
+
+
+def train_switch(precision="f32", iters=3200, B=64, grid=(256, 64, 64), log=None):
+    """The learned switch for the foil: a device training set from all-PIC
+    runs of the foil physics on a 256 x 64 x 64 box (a0 5 and 20, steps
+    150-800 every 25, labels over the next 10 steps), 3200 AdamW steps on
+    batches of 64 crops (204,800 crops of 24^3), scored on a held-out a0 5
+    run against the threshold flags (AUC of the future kinetic label)."""
+    import torch
+
+    from paper_2510_11174_amd import configs, hk
+    from paper_2510_11174_amd import train as T
+    t0 = time.perf_counter()
+    cfgs = [configs.full_foil(a, *grid, mode="all_pic", seed=configs.SEED_BASE + 100 + i)
+            for i, a in enumerate((5.0, 20.0))]
+    ds = T.build_dataset(hk, cfgs, 650, 25, start=150, precision=precision)
+    held = T.build_dataset(hk, [configs.full_foil(5.0, *grid, mode="all_pic", seed=configs.SEED_BASE + 150)],
+                           650, 50, start=150, precision=precision)
+    t_data = time.perf_counter() - t0
+    cnn = hk.CNN(seed=5, precision=precision)
+    cnn.set_params(T.init_params(3))
+    t0 = time.perf_counter()
+    losses = T.train_switch(ds, cnn, iters, B=B, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    p, thr, y = T.scores(held, cnn)
+    info = {"snapshots": len(ds), "crops": iters * B, "data_s": round(t_data, 1), "train_s": round(t_train, 1),
+            "loss_first": float(sum(losses[:20]) / 20), "loss_last": float(sum(losses[-100:]) / 100),
+            "heldout_auc_network": round(T.auc(p, y), 4), "heldout_auc_threshold": round(T.auc(thr, y), 4),
+            "heldout_label_fraction": round(float(y.mean()), 4),
+            "data": "all-PIC foil physics 256x64x64, a0 5 and 20, steps 150-800 every 25; held-out a0 5 run"}
+    ds.close(); held.close()
+    return cnn, info
 
 
 def total_energy(d):
@@ -512,6 +548,38 @@ def _counter_per_dispatch(d, kernel=None, name_re=None):
     return [per[k] for k in sorted(per)]
 
 
+def summarize_counters(d, kernel, last):
+    """Mean per dispatch of every counter in a rocprofv3 --pmc csv directory,
+    for each instance of `kernel` (template arguments apart), over the last
+    `last` dispatches of the kernel (all when 0)."""
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))
+    if not files:
+        print("no counter_collection.csv under %s" % d, file=sys.stderr)
+        sys.exit(1)
+    per, name, info = {}, {}, {}
+    with open(files[0], newline="") as fh:
+        for r in csv.DictReader(fh):
+            if not _is_kernel(r["Kernel_Name"], kernel):
+                continue
+            did = int(r["Dispatch_Id"])
+            per.setdefault(did, {})
+            per[did][r["Counter_Name"]] = per[did].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+            name[did] = _short_name(r["Kernel_Name"])
+            info[name[did]] = (r.get("Workgroup_Size"), r.get("LDS_Block_Size"), r.get("VGPR_Count"),
+                               r.get("SGPR_Count"))
+    ids = sorted(per)[-last:] if last else sorted(per)
+    for inst in sorted(set(name[i] for i in ids)):
+        sel = [i for i in ids if name[i] == inst]
+        keys = sorted(set(k for i in sel for k in per[i]))
+        wg, lds, vgpr, sgpr = info[inst]
+        print("%s: %d dispatches (workgroup %s, LDS %s B, VGPR field %s, SGPR %s)" % (inst, len(sel), wg, lds,
+                                                                                     vgpr, sgpr))
+        for k in keys:
+            print("  %-32s %.6g" % (k, sum(per[i].get(k, 0.0) for i in sel) / len(sel)))
+
+
 def summarize_traffic(a):
     """HBM traffic of `kernel` per dispatch from two rocprofv3 --pmc csv runs
     (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, the last `last` dispatches)
@@ -555,8 +623,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the workload's modes (no seed floor, networks, fluid, search, FP64 check)")
-    ap.add_argument("--modes", default="threshold,all_pic",
-                    help="comma list of switch modes to run (profiling runs may pick one)")
+    ap.add_argument("--modes", default="cnn,threshold,all_pic",
+                    help="comma list of switch modes to run: cnn (trains the switch network first), threshold, "
+                         "all_pic (profiling runs may pick one)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--warm-fluid-only", action="store_true",
@@ -565,6 +634,8 @@ def main():
                     help="only measure the switch CNN, the next-state surrogate and SwitchNet and print their JSON")
     ap.add_argument("--summarize-trace", metavar="DIR",
                     help="print the kernel-time summary of a rocprofv3 --kernel-trace --stats csv DIR")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="print per-dispatch counter means of --kernel from a rocprofv3 --pmc csv DIR")
     ap.add_argument("--summarize-traffic", action="store_true",
                     help="print the HBM traffic summary from --fetch/--write/--calib-fetch/--calib-write DIRs")
     ap.add_argument("--fetch"); ap.add_argument("--write")
@@ -579,6 +650,9 @@ def main():
         return
     if args.summarize_traffic:
         summarize_traffic(args)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.kernel, args.last)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the multi-GPU path (domain decomposition) is not "
@@ -601,13 +675,18 @@ def main():
 
     W, K, a0 = args.warmup, args.steps, args.a0
     modes = [m for m in args.modes.split(",") if m]
-    if any(m not in ("threshold", "all_pic") for m in modes) or not modes:
-        print("--modes takes threshold and/or all_pic", file=sys.stderr)
+    if any(m not in ("cnn", "threshold", "all_pic") for m in modes) or not modes:
+        print("--modes takes cnn, threshold and/or all_pic", file=sys.stderr)
         sys.exit(2)
     window = "a0 %g, steps %d-%d" % (a0, W, W + K)
     res, cfgs = {}, {}
+    net, net_info = None, None
+    if "cnn" in modes:
+        print("bench: training the switch network on foil-physics crops", file=sys.stderr, flush=True)
+        net, net_info = train_switch(args.precision)
+        print("bench: network trained (%s)" % net_info, file=sys.stderr, flush=True)
     floor_snaps = None
-    if not args.no_extras and len(modes) == 2:
+    if not args.no_extras and "all_pic" in modes and len(modes) >= 2:
         # all-PIC with another seed, run first so that the all-PIC window below
         # is the last stretch of push launches in the process: the field
         # difference sampling noise alone makes against one all-PIC run
@@ -620,9 +699,9 @@ def main():
         cfgs[mode] = cfg
         print("bench: %s %s: steps 0-%d untimed, %d-%d timed" % (cfg["name"], mode, W, W, W + K),
               file=sys.stderr, flush=True)
-        res[mode] = run_window(cfg, W, K, args.precision)
+        res[mode] = run_window(cfg, W, K, args.precision, cnn=net if mode == "cnn" else None)
         print("bench: %s %.3f ms/step" % (mode, 1e3 * res[mode]["seconds"] / K), file=sys.stderr, flush=True)
-    if len(res) < 2:
+    if "all_pic" not in res or len(res) < 2:
         mode = modes[0]
         r = res[mode]
         print(json.dumps({"mode": mode, "steps_per_s": K / r["seconds"], "window": window,
@@ -630,57 +709,78 @@ def main():
                           "timers": r["timers"], "kinetic_fraction": r["diag"]["kinetic_fraction"],
                           "count": r["diag"]["count"]}))
         return
-    h, p = res["threshold"], res["all_pic"]
+    p = res["all_pic"]
     floor = field_l2(floor_snaps, p["snaps"]) if floor_snaps is not None else None
-    hyb_sps, pic_sps = K / h["seconds"], K / p["seconds"]
-    l2 = field_l2(h["snaps"], p["snaps"])
-    e_h, e_p = total_energy(h["diag"]), total_energy(p["diag"])
-    drift = abs(e_h - e_p) / abs(e_p) if e_p else 0.0
+    pic_sps = K / p["seconds"]
+    e_p = total_energy(p["diag"])
+    parts_p = sum(p["diag"]["count"][:2]) + sum(p["diag0"]["count"][:2])
     cells = FULL_GRID[0] * FULL_GRID[1] * FULL_GRID[2]
+
+    def hybrid_entry(mode):
+        h = res[mode]
+        sps = K / h["seconds"]
+        l2 = field_l2(h["snaps"], p["snaps"])
+        drift = abs(total_energy(h["diag"]) - e_p) / abs(e_p) if e_p else 0.0
+        parts = sum(h["diag"]["count"][:2]) + sum(h["diag0"]["count"][:2])
+        roof_h = push_roofline(h, particle_bytes(cfgs[mode], h, K))
+        roof_h["traffic"] = None
+        return {"switch": mode, "steps_per_s": round(sps, 2), "ratio_vs_allpic": round(sps / pic_sps, 3),
+                "ms_per_step": round(1e3 / sps, 4),
+                "pushes_per_s": round(h["timers"]["particles_pushed"] / h["seconds"], 1),
+                "cell_steps_per_s": round(cells * sps, 1),
+                "field_rel_l2_vs_allpic": l2, "energy_diff_vs_allpic": drift,
+                "field_err_ok": bool(l2 <= 1e-3 and drift <= 1e-3),
+                "within_pic_sampling_floor": None if floor is None else bool(l2 <= floor),
+                "kinetic_fraction_nodes": h["diag"]["kinetic_fraction"],
+                "fallback_fraction_nodes": h["diag"]["fallback_fraction"],
+                "particle_fraction_vs_allpic": round(parts / parts_p, 4) if parts_p else None,
+                "roofline_push": roof_h,
+                "timers_ms_per_step": {k: round(v / K, 4) for k, v in h["timers"].items() if k.endswith("_ms")},
+                "rebins": h["timers"]["rebins"], "create_s": round(h["create_s"], 2)}
+
+    hyb = {m: hybrid_entry(m) for m in ("cnn", "threshold") if m in res}
+    head = hyb["cnn"] if "cnn" in hyb else hyb["threshold"]
     traffic = measured_traffic(traffic_file(a0), window=window)
     roof = push_roofline(p, particle_bytes(cfgs["all_pic"], p, K))
     roof["traffic"] = traffic
-    roof_h = push_roofline(h, particle_bytes(cfgs["threshold"], h, K))
-    roof_h["traffic"] = None
-    parts_h = sum(h["diag"]["count"][:2]) + sum(h["diag0"]["count"][:2])
-    parts_p = sum(p["diag"]["count"][:2]) + sum(p["diag0"]["count"][:2])
+    sw = "learned (CNN with threshold fallback)" if head["switch"] == "cnn" else "threshold"
     out = {
         "metric": "hybrid steps/s vs all-PIC on same GPU at field err <=1e-3; particle pushes/s",
-        "value": round(hyb_sps / pic_sps, 3),
+        "value": head["ratio_vs_allpic"],
         "unit": "x (hybrid / all-PIC steps/s)",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": round(1e3 / hyb_sps, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "f32" else "f64",
         "data": "synthetic",
         "config": {"workload": "full-size learned-hybrid workload, foil target: 512x256x256 cells, dx 0.05, "
-                               "H foil 10 n_c 1 lambda thick, 16 ppc per species, QED on, CP a0 %g; threshold "
-                               "switch every 10 steps (hot |u| >= %g kinetic) vs all-PIC, same seed; steps %d-%d "
-                               "timed after %d untimed" % (a0, HOT, W, W + K, W),
-                   "grid": list(FULL_GRID), "ppc": 16, "a0": a0, "switch": "threshold", "switch_every": 10},
-        "hybrid_steps_per_s": round(hyb_sps, 2),
+                               "H foil 10 n_c 1 lambda thick, 16 ppc per species, QED on, CP a0 %g; %s switch "
+                               "every 10 steps (hot |u| >= %g kinetic) vs all-PIC, same seed; steps %d-%d timed "
+                               "after %d untimed" % (a0, sw, HOT, W, W + K, W),
+                   "grid": list(FULL_GRID), "ppc": 16, "a0": a0, "switch": head["switch"], "switch_every": 10},
+        "hybrid_steps_per_s": head["steps_per_s"],
         "allpic_steps_per_s": round(pic_sps, 2),
-        "pushes_per_s": round(h["timers"]["particles_pushed"] / h["seconds"], 1),
+        "pushes_per_s": head["pushes_per_s"],
         "allpic_pushes_per_s": round(p["timers"]["particles_pushed"] / p["seconds"], 1),
-        "cell_steps_per_s": round(cells * hyb_sps, 1),
+        "cell_steps_per_s": head["cell_steps_per_s"],
         "allpic_cell_steps_per_s": round(cells * pic_sps, 1),
-        "field_rel_l2_vs_allpic": l2,
+        "field_rel_l2_vs_allpic": head["field_rel_l2_vs_allpic"],
         "field_rel_l2_allpic_other_seed": floor,
-        "energy_diff_vs_allpic": drift,
-        "field_err_ok": bool(l2 <= 1e-3 and drift <= 1e-3),
-        "within_pic_sampling_floor": None if floor is None else bool(l2 <= floor),
-        "kinetic_fraction_nodes": h["diag"]["kinetic_fraction"],
-        "particle_fraction_vs_allpic": round(parts_h / parts_p, 4) if parts_p else None,
+        "energy_diff_vs_allpic": head["energy_diff_vs_allpic"],
+        "field_err_ok": head["field_err_ok"],
+        "within_pic_sampling_floor": head["within_pic_sampling_floor"],
+        "kinetic_fraction_nodes": head["kinetic_fraction_nodes"],
+        "particle_fraction_vs_allpic": head["particle_fraction_vs_allpic"],
         "roofline": roof,
-        "roofline_hybrid": roof_h,
-        "timers_hybrid_ms_per_step": {k: round(v / K, 4) for k, v in h["timers"].items() if k.endswith("_ms")},
+        "hybrids": hyb,
+        "switch_network": net_info,
         "timers_allpic_ms_per_step": {k: round(v / K, 4) for k, v in p["timers"].items() if k.endswith("_ms")},
-        "rebins": {"hybrid": h["timers"]["rebins"], "all_pic": p["timers"]["rebins"]},
-        "create_s": {"hybrid": round(h["create_s"], 2), "all_pic": round(p["create_s"], 2)},
+        "rebins_allpic": p["timers"]["rebins"],
+        "create_s_allpic": round(p["create_s"], 2),
     }
     # the field update (Yee, Mur walls, antenna) of the all-PIC run, from its
     # HIP-event phase timer; algorithmic bytes per cell and step: read E, B and

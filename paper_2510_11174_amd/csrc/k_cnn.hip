@@ -470,24 +470,50 @@ k_cnn_decide(GridP g, const unsigned short *__restrict__ a4, const unsigned shor
         const long long c = gidx(g, i, j, k);
         float h[NC], w[NC];
         for (int q = 0; q < NC; ++q) { h[q] = bf16_val(a4[v * NC + q]); w[q] = bf16_val(wh[q]); }
-        float ps[16], mean = 0.f;
-        for (int s = 0; s < 16; ++s) {
-            float m[NC];
-            drop_mask(seed, (uint64_t)c, eval, s, m);
-            float z = bh[0];
-            for (int q = 0; q < NC; ++q) z += w[q] * h[q] * m[q];
-            ps[s] = 1.0f / (1.0f + __expf(-z));
-            mean += ps[s];
+        bool v_done = false;
+        // Every dropout sample's logit lies in [b + K neg, b + K pos] (K =
+        // 256/230 the keep factor, pos and neg the sums of the positive and
+        // negative terms w h): when that whole range, widened by a rounding
+        // margin, sits on one side of 0 and its sigmoids span less than 0.38,
+        // every sample decides alike and their spread stays under 0.2, so the
+        // 16 samples would give this decision; they are drawn only otherwise.
+        if (!pmean) {
+            float pos = 0.f, neg = 0.f;
+            for (int q = 0; q < NC; ++q) {
+                const float t = w[q] * h[q];
+                pos += fmaxf(t, 0.f);
+                neg += fminf(t, 0.f);
+            }
+            const float K = 256.0f / 230.0f;
+            const float eps = 1e-4f * (fabsf(bh[0]) + K * (pos - neg)) + 1e-3f;
+            const float lo = bh[0] + K * neg - eps, hi = bh[0] + K * pos + eps;
+            const float span = 1.0f / (1.0f + expf(-hi)) - 1.0f / (1.0f + expf(-lo));
+            if (span < 0.38f && (lo > 0.f || hi < 0.f)) {
+                hot[c] = lo > 0.f;
+                notcold[c] = hot[c];
+                v_done = true;
+            }
         }
-        mean *= 1.0f / 16.0f;
-        float var = 0.f;
-        for (int s = 0; s < 16; ++s) var += (ps[s] - mean) * (ps[s] - mean);
-        const float sd = sqrtf(var * (1.0f / 16.0f));
-        if (pmean) pmean[v] = mean;
-        if (sd > 0.2f) fall = true;
-        else {
-            hot[c] = mean > 0.5f;
-            notcold[c] = hot[c];
+        if (!v_done) {
+            float ps[16], mean = 0.f;
+            for (int s = 0; s < 16; ++s) {
+                float m[NC];
+                drop_mask(seed, (uint64_t)c, eval, s, m);
+                float z = bh[0];
+                for (int q = 0; q < NC; ++q) z += w[q] * h[q] * m[q];
+                ps[s] = 1.0f / (1.0f + __expf(-z));
+                mean += ps[s];
+            }
+            mean *= 1.0f / 16.0f;
+            float var = 0.f;
+            for (int s = 0; s < 16; ++s) var += (ps[s] - mean) * (ps[s] - mean);
+            const float sd = sqrtf(var * (1.0f / 16.0f));
+            if (pmean) pmean[v] = mean;
+            if (sd > 0.2f) fall = true;
+            else {
+                hot[c] = mean > 0.5f;
+                notcold[c] = hot[c];
+            }
         }
     }
     const uint64_t bal = __ballot(fall);
