@@ -311,6 +311,18 @@ __device__ inline double qed_chi(double a_s, double ex, double ey, double ez, do
     return en / a_s * sqrt(fmax(q2, 0.0));
 }
 
+// An FP32 upper bound of chi: |E + v x B| <= |E| + |B| for |v| <= 1, so chi <=
+// energy (|E| + |B|) / a_s.  Below the QED floor with a 2% margin for the
+// rounding of this bound, chi (in FP64) is below it too and no event, nor
+// any change of the optical depth, can happen: the FP64 evaluation is skipped.
+__device__ inline bool qed_chi_below_floor(float a_s, float ex, float ey, float ez, float bx, float by,
+                                           float bz, float ux, float uy, float uz, bool photon, float floor_) {
+    const float p2 = ux * ux + uy * uy + uz * uz;
+    const float en = photon ? sqrtf(p2) : sqrtf(1.0f + p2);
+    const float f = sqrtf(ex * ex + ey * ey + ez * ez) + sqrtf(bx * bx + by * by + bz * bz);
+    return en * f * 1.02f < floor_ * a_s;
+}
+
 // One slot per requesting lane in ctr, one atomic per wave.  Every lane of
 // the wave calls it.
 __device__ inline int wave_slot(int *ctr, bool want) {

@@ -335,8 +335,11 @@ __device__ inline PLoad pload(const PArr &in, const SpecP &sp, long long ip, boo
 // MODE 0: charged particles; MODE 1: QED leptons (photon emission from the
 // fields at x^n and u^{n-1/2}, before the Boris push); MODE 2: photons
 // (Breit-Wheeler pair creation, then a ballistic move at c; no current).
+// At most 128 VGPRs, four waves per SIMD: the LDS tiles already allow two
+// workgroups of eight waves per CU, and the QED variant would otherwise take
+// 141 registers and three waves per SIMD.
 template <int MODE>
-__global__ void __launch_bounds__(PBS)
+__global__ void __launch_bounds__(PBS) __attribute__((amdgpu_waves_per_eu(4)))
 k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict__ nf_out, long long mig0,
        const long long *__restrict__ moff, const int *__restrict__ mcap, int *__restrict__ mcnt,
        const PArr *__restrict__ inbox_p, int *__restrict__ inbox_n, int inbox_cap, const real *__restrict__ Ex,
@@ -467,7 +470,10 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
             bool gone = false;   // MODE 2: converted, or left through an open wall
             if (MODE == 2) {
                 const double eps = sqrt((double)ux * ux + (double)uy * uy + (double)uz * uz);
-                const double chi = qed_chi(Q.a_s, ex, ey, ez, bx, by, bz, ux, uy, uz, true);
+                const bool low = qed_chi_below_floor((float)Q.a_s, (float)ex, (float)ey, (float)ez, (float)bx,
+                                                     (float)by, (float)bz, (float)ux, (float)uy, (float)uz,
+                                                     true, 1e-3f);
+                const double chi = low ? 0.0 : qed_chi(Q.a_s, ex, ey, ez, bx, by, bz, ux, uy, uz, true);
                 if (sp.qed && chi > 1e-3) {
                     tau -= Q.alpha_as / eps * qed_total(Q.Wb, chi) * g.ddt;
                     if (tau <= 0.0) {
@@ -498,7 +504,10 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
                 if (MODE == 1) {
                     // every lepton particle radiates: one in a fluid node is hot,
                     // or the conversion takes it at the end of this step
-                    const double chi = qed_chi(Q.a_s, ex, ey, ez, bx, by, bz, ux, uy, uz, false);
+                    const bool low = qed_chi_below_floor((float)Q.a_s, (float)ex, (float)ey, (float)ez,
+                                                         (float)bx, (float)by, (float)bz, (float)ux, (float)uy,
+                                                         (float)uz, false, 1e-3f);
+                    const double chi = low ? 0.0 : qed_chi(Q.a_s, ex, ey, ez, bx, by, bz, ux, uy, uz, false);
                     if (chi > 1e-3) {
                         const double gam = sqrt(1.0 + (double)ux * ux + (double)uy * uy + (double)uz * uz);
                         tau -= Q.alpha_as / gam * qed_total(Q.We, chi) * g.ddt;
