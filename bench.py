@@ -111,6 +111,9 @@ def run_window(cfg, warmup, steps, precision="f32", timing=True, snap=True, cnn=
     import torch
 
     from paper_2510_11174_amd import hk
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    base = torch.cuda.memory_allocated()
     t0 = time.perf_counter()
     sim = hk.Sim(cfg, precision=precision)
     if cnn is not None:
@@ -129,10 +132,12 @@ def run_window(cfg, warmup, steps, precision="f32", timing=True, snap=True, cnn=
     tm = sim.timers() if timing else {}
     d = sim.diagnostics()
     snaps = {c: sim.get_field(c).astype(np.float64) for c in ("ex", "ey", "ez", "bx", "by", "bz")} if snap else None
+    peak_gb = (torch.cuda.max_memory_allocated() - base) / 1e9
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    return {"seconds": seconds, "timers": tm, "diag0": d0, "diag": d, "snaps": snaps, "create_s": create_s}
+    return {"seconds": seconds, "timers": tm, "diag0": d0, "diag": d, "snaps": snaps, "create_s": create_s,
+            "peak_gb": peak_gb}
 
 
 def train_switch(precision="f32", iters=3200, B=64, grid=(256, 64, 64), log=None):
@@ -736,7 +741,8 @@ def main():
                 "particle_fraction_vs_allpic": round(parts / parts_p, 4) if parts_p else None,
                 "roofline_push": roof_h,
                 "timers_ms_per_step": {k: round(v / K, 4) for k, v in h["timers"].items() if k.endswith("_ms")},
-                "rebins": h["timers"]["rebins"], "create_s": round(h["create_s"], 2)}
+                "rebins": h["timers"]["rebins"], "create_s": round(h["create_s"], 2),
+                "device_memory_peak_gb": round(h["peak_gb"], 1)}
 
     hyb = {m: hybrid_entry(m) for m in ("cnn", "threshold") if m in res}
     head = hyb["cnn"] if "cnn" in hyb else hyb["threshold"]
@@ -781,6 +787,7 @@ def main():
         "timers_allpic_ms_per_step": {k: round(v / K, 4) for k, v in p["timers"].items() if k.endswith("_ms")},
         "rebins_allpic": p["timers"]["rebins"],
         "create_s_allpic": round(p["create_s"], 2),
+        "device_memory_peak_gb_allpic": round(p["peak_gb"], 1),
     }
     # the field update (Yee, Mur walls, antenna) of the all-PIC run, from its
     # HIP-event phase timer; algorithmic bytes per cell and step: read E, B and

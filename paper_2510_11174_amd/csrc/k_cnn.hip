@@ -127,6 +127,93 @@ k_conv_fwd(Dims in, const unsigned short *__restrict__ act, const unsigned short
     }
 }
 
+// The 32-channel layers with RY output rows per wave: the wave owns output
+// voxels (z, y0 .. y0 + RY - 1, x0 .. x0 + 15).  For each (kz, kx) it loads
+// the A fragments of the RY + 2 input rows y0 .. y0 + RY + 1 once and the B
+// fragments of the three ky taps once, then runs RY x 3 x 2 MFMAs: output row
+// j takes input row j + ky.  Against one row per wave this loads A half as
+// often and B from LDS a quarter as often per MFMA.
+template <int RY>
+__global__ void __launch_bounds__(FBS)
+k_conv_fwd_rows(Dims in, const unsigned short *__restrict__ act, const unsigned short *__restrict__ Wf,
+                const float *__restrict__ bias, float *__restrict__ zout, unsigned short *__restrict__ aout,
+                const int *__restrict__ xwin) {
+    constexpr int CIN = NC, KPAD = 27 * NC;
+    __shared__ __attribute__((aligned(16))) unsigned short sW[NC * KPAD];
+    for (int e = threadIdx.x; e < NC * KPAD / 8; e += FBS)
+        reinterpret_cast<uint4 *>(sW)[e] = reinterpret_cast<const uint4 *>(Wf)[e];
+    __syncthreads();
+    const Dims out{in.B, in.D - 2, in.H - 2, in.W - 2};
+    int seg0 = 0, segs = (out.W + 15) / 16;
+    if (xwin) {
+        const int lo = xwin[0], hi = min(xwin[1] + 6, out.W - 1);
+        seg0 = lo / 16;
+        segs = xwin[1] >= lo && hi >= lo ? hi / 16 - seg0 + 1 : 0;
+    }
+    const int ygroups = (out.H + RY - 1) / RY;
+    const long long nrows = (long long)out.B * out.D * ygroups * segs;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const float b0 = bias[r], b1 = bias[16 + r];
+    for (long long row = (long long)blockIdx.x * (FBS / 64) + wave; row < nrows;
+         row += (long long)gridDim.x * (FBS / 64)) {
+        const int seg = seg0 + (int)(row % segs);
+        long long q = row / segs;
+        const int yg = (int)(q % ygroups); q /= ygroups;
+        const int z = (int)(q % out.D);
+        const int b = (int)(q / out.D);
+        const int x0 = seg * 16, y0 = yg * RY;
+        const bool xin = x0 + r < out.W;
+        f32x4 acc[RY][2];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            acc[j][0] = f32x4{0, 0, 0, 0};
+            acc[j][1] = f32x4{0, 0, 0, 0};
+        }
+#pragma unroll 1
+        for (int kz = 0; kz < 3; ++kz) {
+#pragma unroll 1
+            for (int kx = 0; kx < 3; ++kx) {
+                uint4 av[RY + 2];
+#pragma unroll
+                for (int j = 0; j < RY + 2; ++j) {
+                    av[j] = make_uint4(0, 0, 0, 0);
+                    if (xin && y0 + j < in.H)
+                        av[j] = *reinterpret_cast<const uint4 *>(act + vidx(in, b, z + kz, y0 + j, x0 + r + kx) * CIN +
+                                                                 8 * g);
+                }
+#pragma unroll
+                for (int ky = 0; ky < 3; ++ky) {
+                    const int k = (kx + 3 * ky + 9 * kz) * CIN + 8 * g;
+                    const bf16x8 w0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + r * KPAD + k));
+                    const bf16x8 w1 =
+                        __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + (16 + r) * KPAD + k));
+#pragma unroll
+                    for (int j = 0; j < RY; ++j) {
+                        const bf16x8 a = __builtin_bit_cast(bf16x8, av[j + ky]);
+                        acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w0, acc[j][0], 0, 0, 0);
+                        acc[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w1, acc[j][1], 0, 0, 0);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int y = y0 + j;
+            if (y >= out.H) continue;
+            for (int i = 0; i < 4; ++i) {
+                const int x = x0 + 4 * g + i;
+                if (x >= out.W) continue;
+                const long long v = vidx(out, b, z, y, x);
+                const float z0 = acc[j][0][i] + b0, z1 = acc[j][1][i] + b1;
+                if (zout) { zout[v * NC + r] = z0; zout[v * NC + 16 + r] = z1; }
+                aout[v * NC + r] = bf16_bits(gelu(z0));
+                aout[v * NC + 16 + r] = bf16_bits(gelu(z1));
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------- data gradient
 // din[u][ci] = sum_{t, co} dz[u - off(t)][co] W[t][ci][co] over the input
 // voxels u (dims `in`; dz lives on in - 2), then times GELU'(z_in[u][ci]) and
@@ -578,8 +665,14 @@ void cnn_launch_conv_fwd(int cin, int B, int D, int H, int W, const unsigned sho
     // looping over rows: the weight matrix is read once per workgroup
     long long nb = (rows + FBS / 64 - 1) / (FBS / 64);
     const unsigned grid = (unsigned)(nb < 512 ? nb : 512);
-    if (cin == 8) k_conv_fwd<8><<<grid, FBS, 0, s>>>(in, act, Wf, bias, zout, aout, xwin);
-    else k_conv_fwd<32><<<grid, FBS, 0, s>>>(in, act, Wf, bias, zout, aout, xwin);
+    if (cin == 8) {
+        k_conv_fwd<8><<<grid, FBS, 0, s>>>(in, act, Wf, bias, zout, aout, xwin);
+    } else {
+        constexpr int RY = 4;
+        const long long groups = (long long)B * (D - 2) * ((H - 2 + RY - 1) / RY) * ((W - 2 + 15) / 16);
+        const long long nb4 = (groups + FBS / 64 - 1) / (FBS / 64);
+        k_conv_fwd_rows<RY><<<(unsigned)(nb4 < 512 ? nb4 : 512), FBS, 0, s>>>(in, act, Wf, bias, zout, aout, xwin);
+    }
 }
 
 void cnn_launch_conv_bwd_data(int B, int D, int H, int W, const unsigned short *dz,

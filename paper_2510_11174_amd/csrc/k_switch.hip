@@ -485,11 +485,15 @@ __global__ void __launch_bounds__(BS)
 k_absorb_finish(GridP g, real mass, double *__restrict__ macc, real *__restrict__ n,
                 real *__restrict__ ux, real *__restrict__ uy, real *__restrict__ uz, WarmP wp,
                 double *__restrict__ ledger, const int *__restrict__ xr) {
-    long long c = (long long)blockIdx.x * BS + threadIdx.x;
+    // only the x range of this step's absorptions (xr[4..5]) has entries: the
+    // grid strides over the node columns of that range alone
+    const int lo = xr[4], hi = xr[5];
+    if (hi < lo) return;
+    const long long wx = hi - lo + 1, total = wx * g.ny * g.nz;
     double dsum = 0;
-    // only the x range of this step's absorptions (xr[4..5]) has entries
-    const int i = c < g.nn ? (int)(c % g.sx) : -1;
-    if (c < g.nn && i >= xr[4] && i <= xr[5] && macc[c] > 0.0) {
+    for (long long t = (long long)blockIdx.x * BS + threadIdx.x; t < total; t += (long long)gridDim.x * BS) {
+    const long long c = gidx(g, lo + (int)(t % wx), (int)((t / wx) % g.ny), (int)(t / (wx * g.ny)));
+    if (macc[c] > 0.0) {
         const long long nn = g.nn;
         const double dv = g.ddx * g.ddy * g.ddz;
         double m0 = (double)n[c] * dv;
@@ -519,7 +523,8 @@ k_absorb_finish(GridP g, real mass, double *__restrict__ macc, real *__restrict_
         n[c] = (real)(mt / dv);
         ux[c] = (real)un[0]; uy[c] = (real)un[1]; uz[c] = (real)un[2];
         for (int q = 0; q < 5; ++q) macc[q * nn + c] = 0.0;
-        dsum = d;
+        dsum += d;
+    }
     }
     block_add_d(dsum, ledger);
 }
@@ -624,21 +629,28 @@ __device__ inline void spawn_node(const GridP &g, const SpecP &sp, int isp, long
 __global__ void __launch_bounds__(BS)
 k_spawn_find(GridP g, const uint8_t *__restrict__ sw, const real *__restrict__ n, real wmin,
              int *__restrict__ list, int *__restrict__ list_n, const int *__restrict__ xr) {
-    const long long c = xcd_node();
-    bool want = false;
-    if (c < g.nn) {
-        const int i = (int)(c % g.sx);
-        const int nxn = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
-        // fluid only inside the species' x window
-        want = i < nxn && i >= xr[0] && i <= xr[1] && sw[c] && n[c] * (g.dx * g.dy * g.dz) >= wmin &&
-               n[c] > (real)0;
+    // fluid exists only inside the species' x window: the grid strides over
+    // its node columns alone (every lane of a block takes the same number of
+    // turns, for the wave-wide list appends)
+    const int nxn = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
+    const int lo = max(xr[0], 0), hi = min(xr[1], nxn - 1);
+    if (hi < lo) return;
+    const long long wx = hi - lo + 1, total = wx * g.ny * g.nz;
+    for (long long t0 = (long long)blockIdx.x * BS; t0 < total; t0 += (long long)gridDim.x * BS) {
+        const long long t = t0 + threadIdx.x;
+        bool want = false;
+        long long c = 0;
+        if (t < total) {
+            c = gidx(g, lo + (int)(t % wx), (int)((t / wx) % g.ny), (int)(t / (wx * g.ny)));
+            want = sw[c] && n[c] * (g.dx * g.dy * g.dz) >= wmin && n[c] > (real)0;
+        }
+        const uint64_t b = __ballot(want);
+        if (!b) continue;
+        int base = 0;
+        if (__lane_id() == 0) base = atomicAdd(list_n, __popcll(b));
+        base = __shfl(base, 0);
+        if (want) list[base + __popcll(b & ((1ull << __lane_id()) - 1ull))] = (int)c;
     }
-    const uint64_t b = __ballot(want);
-    if (!b) return;
-    int base = 0;
-    if (__lane_id() == 0) base = atomicAdd(list_n, __popcll(b));
-    base = __shfl(base, 0);
-    if (want) list[base + __popcll(b & ((1ull << __lane_id()) - 1ull))] = (int)c;
 }
 
 // One listed node becomes particles (one thread per node).  A warm node's
@@ -705,14 +717,16 @@ void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, c
 }
 void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n, real *ux,
                                 real *uy, real *uz, WarmP w, double *ledger, const int *xr, hipStream_t s) {
-    k_absorb_finish<<<blocks(g.nn), BS, 0, s>>>(g, mass, macc, n, ux, uy, uz, w, ledger, xr);
+    const unsigned nb = blocks(g.nn) < 2048u ? blocks(g.nn) : 2048u;
+    k_absorb_finish<<<nb, BS, 0, s>>>(g, mass, macc, n, ux, uy, uz, w, ledger, xr);
 }
 void launch_spawn_nodes(const GridP &g, const SpecP &sp, int isp, const uint8_t *sw, real *n, real *ux,
                         real *uy, real *uz, WarmP w, jglob_t *jg, real wmin, real w0, uint64_t seed,
                         int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
                         unsigned *wmax_bits, unsigned *umax2, double *ledger, int *list, int *list_n,
                         const int *xr, hipStream_t s) {
-    k_spawn_find<<<xcd_blocks(g.nn), BS, 0, s>>>(g, sw, n, wmin, list, list_n, xr);
+    const unsigned nb = blocks(g.nn) < 2048u ? blocks(g.nn) : 2048u;
+    k_spawn_find<<<nb, BS, 0, s>>>(g, sw, n, wmin, list, list_n, xr);
     k_spawn<<<1024, BS, 0, s>>>(g, sp, isp, n, ux, uy, uz, w, jg, jg + g.nn, jg + 2 * g.nn, w0, seed, step,
                                 inbox, inbox_n, inbox_cap, deferred, wmax_bits, umax2, ledger, list, list_n);
 }
