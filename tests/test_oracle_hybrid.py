@@ -123,3 +123,32 @@ def test_half_fluid_half_kinetic_k0_mode_in_phase(oracle_mod):
     assert o.count(0) == len(w)
     nf, _ = o.get_fluid(0)
     assert np.abs(nf[:, :, 2:4]).max() < 1e-14 * n0 and abs(nf[:, :, 0:2] - n0).max() < 1e-12 * n0
+
+
+@pytest.mark.parametrize("mass_in_w0,expect", [(0.49, 0), (0.5, 1), (2.4, 2), (2.6, 3), (10.0, 10), (100.0, 64)])
+def test_spawn_count_follows_the_mass(oracle_mod, mass_in_w0, expect):
+    # a cold fluid node of mass M switched to kinetic becomes round(M / w0)
+    # particles (1 to 64; none below half a reference weight) of weight M / m,
+    # w0 = n0 dV / ppc; the mass is kept, the rest of the box stays empty
+    cfg = configs.plain_hybrid(16, 16, 16, mode="fixed")
+    cfg["species"][0]["profile"] = "none"
+    cfg["laser"]["enabled"] = False
+    o = oracle_mod.Oracle(cfg)
+    dv = cfg["grid"]["dx"] ** 3
+    w0 = cfg["species"][0]["n0"] * dv / cfg["species"][0]["ppc"]
+    o.set_switch(np.zeros(o.shape, np.uint8))
+    n = np.zeros(o.shape)
+    n[7, 6, 5] = mass_in_w0 * w0 / dv
+    o.set_fluid(0, n, np.zeros(o.shape + (3,)))
+    m = np.ones(o.shape, np.uint8)
+    o.set_switch(m)
+    o.step(1)
+    p = o.get_particles(0)
+    assert len(p["w"]) == expect
+    if expect:
+        assert np.allclose(p["w"], mass_in_w0 * w0 / expect, rtol=1e-14)
+        nf, _ = o.get_fluid(0)
+        assert abs(nf.sum()) * dv < 1e-14 * w0
+    else:
+        assert o.get_fluid(0)[0][7, 6, 5] == pytest.approx(mass_in_w0 * w0 / dv, rel=1e-14)
+    o.close()
