@@ -253,8 +253,10 @@ int hk_timers(hk_sim *sim, double *ms, int n);
  * so a resumed run draws the same Philox numbers (counters are id, step and
  * tag) and takes the same decisions as an uninterrupted one.  An attached
  * CNN is not part of the file: save it with hk_cnn_get_params.  The path is
- * borrowed for the call; file errors return HK_EIO.  A failed hk_load may
- * leave a partly restored state.
+ * borrowed for the call; file errors return HK_EIO.  A file whose header
+ * does not match (magic, version, precision, grid, species kinds) changes
+ * nothing; a failure after the header (a short or corrupt body) leaves the
+ * state partly restored and poisons the context (HK_ESTATE from then on).
  * Paper: Methodology (keeping code, parameters and outputs together for
  * reproducible runs). */
 int hk_save(hk_sim *sim, const char *path);

@@ -1890,31 +1890,8 @@ int hk_save(hk_sim *S, const char *path) {
     return HK_OK;
 }
 
-int hk_load(hk_sim *S, const char *path) {
-    if (!S || !path) return HK_EINVAL;
-    if (S->poisoned) return HK_ESTATE;
-    ev_resolve(S);
-    CkFile F;
-    F.f = fopen(path, "rb");
-    if (!F.f) return fail(S, HK_EIO, "checkpoint: cannot open %s", path);
-    const GridP &g = S->g;
-    uint32_t magic = 0, version = 0, rsz = 0;
-    int nx = 0, ny = 0, nz = 0, nsp = 0;
-    F.get(magic); F.get(version); F.get(rsz);
-    F.get(nx); F.get(ny); F.get(nz); F.get(nsp);
-    if (!F.ok || magic != CK_MAGIC || version != CK_VERSION)
-        return fail(S, HK_EIO, "checkpoint: %s is not a checkpoint of this version", path);
-    if (rsz != sizeof(real) || nx != g.nx || ny != g.ny || nz != g.nz || nsp != S->nsp)
-        return fail(S, HK_EINVAL, "checkpoint: precision, grid or species count differ from this context");
-    for (int i = 0; i < nsp; ++i) {
-        int kind = -1;
-        F.get(kind);
-        if (kind != S->sp[i].d.kind) return fail(S, HK_EINVAL, "checkpoint: species %d has another kind", i);
-    }
-    int64_t step = 0;
-    double t = 0;
-    int have_g0 = 0;
-    F.get(step); F.get(t); F.get(have_g0);
+static int load_body(hk_sim *S, CkFile &F, const char *path, const GridP &g, int nsp, int64_t step, double t,
+                     int have_g0) {
     int rc;
     if ((rc = ck_dev_in(S, F, S->fblock, sizeof(real) * 9 * (size_t)g.nn))) return rc;
     if ((rc = ck_dev_in(S, F, S->mur_old, sizeof(real) * 8 * (size_t)g.ny * g.nz))) return rc;
@@ -1969,6 +1946,38 @@ int hk_load(hk_sim *S, const char *path) {
     S->have_gauss0 = have_g0;
     S->cnn_evals = evals;
     return HK_OK;
+}
+
+int hk_load(hk_sim *S, const char *path) {
+    if (!S || !path) return HK_EINVAL;
+    if (S->poisoned) return HK_ESTATE;
+    ev_resolve(S);
+    CkFile F;
+    F.f = fopen(path, "rb");
+    if (!F.f) return fail(S, HK_EIO, "checkpoint: cannot open %s", path);
+    const GridP &g = S->g;
+    uint32_t magic = 0, version = 0, rsz = 0;
+    int nx = 0, ny = 0, nz = 0, nsp = 0;
+    F.get(magic); F.get(version); F.get(rsz);
+    F.get(nx); F.get(ny); F.get(nz); F.get(nsp);
+    if (!F.ok || magic != CK_MAGIC || version != CK_VERSION)
+        return fail(S, HK_EIO, "checkpoint: %s is not a checkpoint of this version", path);
+    if (rsz != sizeof(real) || nx != g.nx || ny != g.ny || nz != g.nz || nsp != S->nsp)
+        return fail(S, HK_EINVAL, "checkpoint: precision, grid or species count differ from this context");
+    for (int i = 0; i < nsp; ++i) {
+        int kind = -1;
+        F.get(kind);
+        if (kind != S->sp[i].d.kind) return fail(S, HK_EINVAL, "checkpoint: species %d has another kind", i);
+    }
+    int64_t step = 0;
+    double t = 0;
+    int have_g0 = 0;
+    F.get(step); F.get(t); F.get(have_g0);
+    // from here on the context is overwritten: a failure leaves it partly
+    // restored, so it is poisoned
+    const int rc = load_body(S, F, path, g, nsp, step, t, have_g0);
+    if (rc) S->poisoned = 1;
+    return rc;
 }
 
 }  // extern "C"

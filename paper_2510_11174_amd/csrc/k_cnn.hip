@@ -626,9 +626,12 @@ k_cnn_extent(GridP g, const real *__restrict__ mom, int *__restrict__ win) {
         lo = min(lo, __shfl_xor(lo, o, 64));
         hi = max(hi, __shfl_xor(hi, o, 64));
     }
+    // one wave per atomic, and only when it can move the extent: a read of the
+    // current value (possibly stale, which only costs an atomic) avoids the
+    // serialisation of every wave on the same two words
     if ((threadIdx.x & 63) == 0 && hi >= 0) {
-        atomicMin(win, lo);
-        atomicMax(win + 1, hi);
+        if (lo < *(volatile int *)win) atomicMin(win, lo);
+        if (hi > *(volatile int *)(win + 1)) atomicMax(win + 1, hi);
     }
 }
 

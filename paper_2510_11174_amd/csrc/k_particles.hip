@@ -608,8 +608,9 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
                         atomicAdd(&A.macc[nn + node], dw * dux);
                         atomicAdd(&A.macc[2 * nn + node], dw * duy);
                         atomicAdd(&A.macc[3 * nn + node], dw * duz);
-                        atomicMin(&A.xr[4], gi);
-                        atomicMax(&A.xr[5], gi);
+                        // only when it can widen the range (a stale read costs an atomic)
+                        if (gi < *(volatile int *)&A.xr[4]) atomicMin(&A.xr[4], gi);
+                        if (gi > *(volatile int *)&A.xr[5]) atomicMax(&A.xr[5], gi);
                         valid = false;
                     }
                 }

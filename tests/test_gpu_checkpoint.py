@@ -89,3 +89,33 @@ def test_load_rejects_other_grid(hk, tmp_path):
     with pytest.raises(RuntimeError):
         c.load(str(tmp_path / "missing.bin"))
     a.close(); b.close(); c.close()
+
+
+def test_load_failures_leave_or_poison(hk, tmp_path):
+    # a header that does not match changes nothing: the context steps on as
+    # if the call had not happened; a body cut short poisons the context
+    print("case: checkpoint header mismatch and truncated body", flush=True)
+    path = str(tmp_path / "ck.bin")
+    cfg = configs.plain_hybrid(16, 8, 8)
+    a = hk.Sim(cfg, precision="f32")
+    a.step(3)
+    a.save(path)
+    other = hk.Sim(configs.plain_hybrid(16, 8, 16), precision="f32")
+    other.step(1)
+    before = other.get_field("ey").copy()
+    with pytest.raises(RuntimeError):
+        other.load(path)
+    assert np.array_equal(other.get_field("ey"), before)
+    other.step(1)                      # still usable
+    with open(path, "rb") as fh:
+        blob = fh.read()
+    cut = str(tmp_path / "cut.bin")
+    with open(cut, "wb") as fh:
+        fh.write(blob[: len(blob) // 2])
+    b = hk.Sim(cfg, precision="f32")
+    with pytest.raises(RuntimeError):
+        b.load(cut)
+    with pytest.raises(RuntimeError) as e:
+        b.step(1)
+    assert "poisoned" in str(e.value) or "HK_ESTATE" in str(e.value)
+    a.close(); other.close(); b.close()
