@@ -1,0 +1,92 @@
+"""The learned switch on the foil physics, end to end on the GPU at reduced
+size: a device training set from all-PIC runs of a 128 x 32 x 32 foil crop
+(hk_dump_training), the network trained by hk_train, then the learned hybrid
+against all-PIC on a held-out seed.  The hybrid must keep at most a quarter
+of the nodes kinetic, keep the total energy (with its ledgers) within 1e-3 of
+the all-PIC run's, and stay within the field difference that two all-PIC
+seeds show (PIC's own sampling floor; the 1e-3 field bar lies below it here).
+
+Paper: Methodology, pipeline paragraph (the learned switch, trained on the
+simulation's own data, selects fluid or kinetic regions; an all-PIC run is
+the reference)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2510_11174_amd import configs
+from paper_2510_11174_amd import train as T
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2510_11174_amd import hk as hkmod
+    return hkmod
+
+
+def _foil(a0, mode, seed):
+    # the full-size foil's physics on a 128 x 32 x 32 crop: foil from x = 1.6,
+    # pulse centred at t = 8, so the interaction starts within 100 steps
+    cfg = configs.full_foil(a0, 128, 32, 32, mode=mode, seed=seed, duration=4.0)
+    for sp in cfg["species"]:
+        if sp.get("profile") == "foil":
+            sp["x0"] = 1.6
+    cfg["run"]["thr_hot"] = 0.1
+    return cfg
+
+
+def _energy(d):
+    return (d["u_e"] + d["u_b"] + sum(d["kin"]) + sum(d["fluid_kin"]) + sum(d["fluid_th"]) + d["conv_loss"]
+            + d["ion_energy"] + d["photon_energy"])
+
+
+def _run(hk, cfg, steps, cnn=None):
+    s = hk.Sim(cfg)
+    if cnn is not None:
+        s.set_cnn(cnn)
+    kin = []
+    for _ in range(steps // 10):
+        s.step(10)
+        kin.append(s.diagnostics()["kinetic_fraction"])
+    f = {q: s.get_field(q).astype(np.float64) for q in ("ex", "ey", "ez", "bx", "by", "bz")}
+    d = s.diagnostics()
+    s.close()
+    return f, d, kin
+
+
+def _l2(a, b):
+    return math.sqrt(sum(float(((a[q] - b[q]) ** 2).sum()) for q in a)) / \
+        math.sqrt(sum(float((b[q] ** 2).sum()) for q in b))
+
+
+def test_learned_hybrid_on_the_foil(hk):
+    print("case: learned switch trained on foil crops, hybrid vs all-PIC 128x32x32", flush=True)
+    base = configs.SEED_BASE + 300
+    data = T.build_dataset(hk, [_foil(a0, "all_pic", base + i) for i, a0 in enumerate((5.0, 20.0))], 200, 10,
+                           start=20)
+    cnn = hk.CNN(seed=7)
+    cnn.set_params(T.init_params(5))
+    losses = T.train_switch(data, cnn, 800, B=32, lr=1e-3)
+    print("%d snapshots, label fraction %.3f; loss first %.3f last %.3f" % (
+        len(data), np.mean([data.get(k)[2].mean() for k in range(len(data))]), np.mean(losses[:20]),
+        np.mean(losses[-50:])))
+    assert np.mean(losses[-50:]) < 0.7 * np.mean(losses[:20])
+    data.close()
+    steps, seed = 240, base + 50
+    ref, dref, _ = _run(hk, _foil(5.0, "all_pic", seed), steps)
+    ref2, _, _ = _run(hk, _foil(5.0, "all_pic", seed + 1), steps)
+    f, d, kin = _run(hk, _foil(5.0, "cnn", seed), steps, cnn=cnn)
+    floor, err = _l2(ref2, ref), _l2(f, ref)
+    drift = abs(_energy(d) - _energy(dref)) / _energy(dref)
+    print("learned hybrid: kinetic fraction %s; field L2 vs all-PIC %.3e (all-PIC other seed %.3e); "
+          "energy difference %.2e; fallback %.2e" % (" ".join("%.3f" % k for k in kin), err, floor, drift,
+                                                      d["fallback_fraction"]))
+    assert max(kin) <= 0.25
+    assert drift <= 1e-3
+    assert err <= 1.5 * floor
+    cnn.close()
