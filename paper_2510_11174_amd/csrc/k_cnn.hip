@@ -462,7 +462,8 @@ k_cnn_inputs(GridP g, const real *__restrict__ Ex, const real *__restrict__ Ey, 
     const long long n = (long long)W * H * D;
     const long long v = (long long)blockIdx.x * CBS + threadIdx.x;
     if (v >= n) return;
-    const int i = (int)(v % W), j = (int)((v / W) % H), k = (int)(v / ((long long)W * H));
+    const unsigned uv = (unsigned)v, ur = uv / (unsigned)W;
+    const int i = (int)(uv - ur * (unsigned)W), j = (int)(ur % (unsigned)H), k = (int)(ur / (unsigned)H);
     // padded x indices the windowed layers read: nodes xwin[0] - 4 .. xwin[1] + 4
     if (xwin && (xwin[1] < xwin[0] || i < xwin[0] || i > xwin[1] + 8)) return;
     int ii = i - 4;
@@ -495,7 +496,9 @@ k_node_raw(GridP g, const real *__restrict__ Ex, const real *__restrict__ Ey, co
     const long long n = (long long)NX * g.ny * g.nz;
     const long long v = (long long)blockIdx.x * CBS + threadIdx.x;
     if (v >= n) return;
-    const int i = (int)(v % NX), j = (int)((v / NX) % g.ny), k = (int)(v / ((long long)NX * g.ny));
+    // node counts stay below 2^31: 32-bit index arithmetic
+    const unsigned uv = (unsigned)v, ur = uv / (unsigned)NX;
+    const int i = (int)(uv - ur * (unsigned)NX), j = (int)(ur % (unsigned)g.ny), k = (int)(ur / (unsigned)g.ny);
     const long long c = gidx(g, i, j, k);
     const double dv = (double)g.dx * g.dy * g.dz;
     float *o = out + 9 * v;
@@ -524,7 +527,9 @@ k_node_state(GridP g, const real *__restrict__ Ex, const real *__restrict__ Ey, 
     const long long n = (long long)NX * g.ny * g.nz;
     const long long v = (long long)blockIdx.x * CBS + threadIdx.x;
     if (v >= n) return;
-    const int i = (int)(v % NX), j = (int)((v / NX) % g.ny), k = (int)(v / ((long long)NX * g.ny));
+    // node counts stay below 2^31: 32-bit index arithmetic
+    const unsigned uv = (unsigned)v, ur = uv / (unsigned)NX;
+    const int i = (int)(uv - ur * (unsigned)NX), j = (int)(ur % (unsigned)g.ny), k = (int)(ur / (unsigned)g.ny);
     float *o = out + 10 * v;
     o[0] = node_field(g, Ex, i, j, k, 1, 0, 0);
     o[1] = node_field(g, Ey, i, j, k, 0, 1, 0);
@@ -550,7 +555,7 @@ k_cnn_decide(GridP g, const unsigned short *__restrict__ a4, const unsigned shor
     const long long n = (long long)NX * g.ny * g.nz;
     const long long v = (long long)blockIdx.x * CBS + threadIdx.x;
     bool fall = false;
-    const int iv = (int)(v % NX);
+    const int iv = (int)((unsigned)v % (unsigned)NX);
     // outside the window the threshold decision stays
     if (v < n && (!xwin || (iv >= xwin[0] && iv <= xwin[1]))) {
         const int i = iv, j = (int)((v / NX) % g.ny), k = (int)(v / ((long long)NX * g.ny));
@@ -618,7 +623,9 @@ k_cnn_extent(GridP g, const real *__restrict__ mom, int *__restrict__ win) {
     const long long v = (long long)blockIdx.x * CBS + threadIdx.x;
     int lo = INT_MAX, hi = -1;
     if (v < n) {
-        const int i = (int)(v % NX), j = (int)((v / NX) % g.ny), k = (int)(v / ((long long)NX * g.ny));
+        // node counts stay below 2^31: 32-bit index arithmetic
+        const unsigned uv = (unsigned)v, ur = uv / (unsigned)NX;
+        const int i = (int)(uv - ur * (unsigned)NX), j = (int)(ur % (unsigned)g.ny), k = (int)(ur / (unsigned)g.ny);
         const long long c = gidx(g, i, j, k);
         if (mom[c] > 0 || mom[6 * g.nn + c] > 0) { lo = i; hi = i; }
     }

@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(BS)
 k_fluid_p(GridP g, real gm1, const real *__restrict__ n, const real *__restrict__ S, real *__restrict__ P,
           const int *__restrict__ xr) {
     long long c = xcd_node();
-    if (c >= g.nn || !in_window(xr, (int)(c % g.sx))) return;
+    if (c >= g.nn || !in_window(xr, (int)((unsigned)c % (unsigned)g.sx))) return;
     const real nc = n[c];
     P[c] = nc > (real)0 ? S[c] * pow(nc, gm1) : (real)0;
 }
@@ -116,7 +116,7 @@ k_fluid_lorentz(GridP g, real qm, real mass, real n_floor, const real *__restric
                 const real *__restrict__ By, const real *__restrict__ Bz, real *__restrict__ sc,
                 const int *__restrict__ xr) {
     long long cl = xcd_node();
-    if (cl >= g.nn || !in_window(xr, (int)(cl % g.sx))) return;
+    if (cl >= g.nn || !in_window(xr, (int)((unsigned)cl % (unsigned)g.sx))) return;
     int i, j, k;
     node_ijk(g, cl, i, j, k);
     const int per = g.bcx == HK_BC_PERIODIC;
@@ -205,7 +205,7 @@ k_fluid_update(GridP g, real q, real n_floor, const real *__restrict__ n, real *
                real *__restrict__ Jx, real *__restrict__ Jy, real *__restrict__ Jz,
                real *__restrict__ nout, const real *__restrict__ S, real *__restrict__ Sout, int *__restrict__ xr) {
     long long cl = xcd_node();
-    if (cl >= g.nn || !in_window(xr, (int)(cl % g.sx))) return;
+    if (cl >= g.nn || !in_window(xr, (int)((unsigned)cl % (unsigned)g.sx))) return;
     int i, j, k;
     node_ijk(g, cl, i, j, k);
     const int per = g.bcx == HK_BC_PERIODIC;

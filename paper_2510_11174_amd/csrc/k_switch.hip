@@ -489,10 +489,11 @@ k_absorb_finish(GridP g, real mass, double *__restrict__ macc, real *__restrict_
     // grid strides over the node columns of that range alone
     const int lo = xr[4], hi = xr[5];
     if (hi < lo) return;
-    const long long wx = hi - lo + 1, total = wx * g.ny * g.nz;
     double dsum = 0;
-    for (long long t = (long long)blockIdx.x * BS + threadIdx.x; t < total; t += (long long)gridDim.x * BS) {
-    const long long c = gidx(g, lo + (int)(t % wx), (int)((t / wx) % g.ny), (int)(t / (wx * g.ny)));
+    // a block per (y, z) row at a time, its threads along x
+    for (int row = blockIdx.x; row < g.ny * g.nz; row += gridDim.x)
+    for (int i = lo + (int)threadIdx.x; i <= hi; i += BS) {
+    const long long c = gidx(g, i, row % g.ny, row / g.ny);
     if (macc[c] > 0.0) {
         const long long nn = g.nn;
         const double dv = g.ddx * g.ddy * g.ddz;
@@ -635,13 +636,14 @@ k_spawn_find(GridP g, const uint8_t *__restrict__ sw, const real *__restrict__ n
     const int nxn = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
     const int lo = max(xr[0], 0), hi = min(xr[1], nxn - 1);
     if (hi < lo) return;
-    const long long wx = hi - lo + 1, total = wx * g.ny * g.nz;
-    for (long long t0 = (long long)blockIdx.x * BS; t0 < total; t0 += (long long)gridDim.x * BS) {
-        const long long t = t0 + threadIdx.x;
+    // a block per (y, z) row at a time, its threads along x
+    for (int row = blockIdx.x; row < g.ny * g.nz; row += gridDim.x)
+    for (int i0 = lo; i0 <= hi; i0 += BS) {
+        const int i = i0 + (int)threadIdx.x;
         bool want = false;
         long long c = 0;
-        if (t < total) {
-            c = gidx(g, lo + (int)(t % wx), (int)((t / wx) % g.ny), (int)(t / (wx * g.ny)));
+        if (i <= hi) {
+            c = gidx(g, i, row % g.ny, row / g.ny);
             want = sw[c] && n[c] * (g.dx * g.dy * g.dz) >= wmin && n[c] > (real)0;
         }
         const uint64_t b = __ballot(want);
@@ -717,7 +719,7 @@ void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, c
 }
 void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n, real *ux,
                                 real *uy, real *uz, WarmP w, double *ledger, const int *xr, hipStream_t s) {
-    const unsigned nb = blocks(g.nn) < 2048u ? blocks(g.nn) : 2048u;
+    const unsigned rows = (unsigned)(g.ny * g.nz), nb = rows < 4096u ? rows : 4096u;
     k_absorb_finish<<<nb, BS, 0, s>>>(g, mass, macc, n, ux, uy, uz, w, ledger, xr);
 }
 void launch_spawn_nodes(const GridP &g, const SpecP &sp, int isp, const uint8_t *sw, real *n, real *ux,
@@ -725,7 +727,7 @@ void launch_spawn_nodes(const GridP &g, const SpecP &sp, int isp, const uint8_t 
                         int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
                         unsigned *wmax_bits, unsigned *umax2, double *ledger, int *list, int *list_n,
                         const int *xr, hipStream_t s) {
-    const unsigned nb = blocks(g.nn) < 2048u ? blocks(g.nn) : 2048u;
+    const unsigned rows = (unsigned)(g.ny * g.nz), nb = rows < 4096u ? rows : 4096u;
     k_spawn_find<<<nb, BS, 0, s>>>(g, sw, n, wmin, list, list_n, xr);
     k_spawn<<<1024, BS, 0, s>>>(g, sp, isp, n, ux, uy, uz, w, jg, jg + g.nn, jg + 2 * g.nn, w0, seed, step,
                                 inbox, inbox_n, inbox_cap, deferred, wmax_bits, umax2, ledger, list, list_n);
