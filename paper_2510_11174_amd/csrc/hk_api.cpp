@@ -88,6 +88,7 @@ struct hk_sim {
                                  // [4..7] the network's x window (k_cnn_window)
     float *cnn_raw = nullptr;    // node inputs and conversion energy (hk_node_inputs)
     uint8_t *lab = nullptr;      // training-label condition per node (hk_dump_training)
+    uint8_t *dil = nullptr;      // 2 nn bytes: the dilation's one-axis passes
     double a_s = 0.0;            // Schwinger field in normalized units
     int photon_sp = -1, electron_sp = -1, positron_sp = -1;   // QED sinks (first of each kind)
     hk_grid_desc gd{};
@@ -129,7 +130,7 @@ struct hk_sim {
     unsigned long long *dstat = nullptr;   // [0] particles pushed, [1] tiles pushed
     unsigned *wmax = nullptr;       // per species: bound on |w| (FP32 bits), never lowered
     int2 *plan = nullptr;           // push work items (tile, chunk), rebuilt before every push
-    int *plan_ctl = nullptr;        // [0] items of the current plan
+    int *plan_ctl = nullptr;        // [0] items of the current plan, then the planner's counts
     unsigned long long stat0[2]{};  // device counters when timing was enabled
     double fallback_fraction = 0;
 };
@@ -824,7 +825,9 @@ void switch_eval(hk_sim *S) {
     SwitchP P = switch_params(S);
     launch_indicators_nodes(g, P, S->mom, S->f, ions, nion, S->hot, S->notcold, s);
     if (S->run.switch_mode == HK_SW_CNN && S->cnn) cnn_switch(S);
-    launch_dilate_nodes(g, P, S->hot, S->notcold, S->sw, S->calm, s);
+    if (!S->dil) S->dil = (uint8_t *)dalloc(S, 2 * (size_t)g.nn);
+    if (!S->dil) { fail(S, HK_ENOMEM, "switch dilation scratch"); return; }
+    launch_dilate_nodes(g, P, S->hot, S->notcold, S->sw, S->calm, S->dil, s);
 }
 
 // Fluid <-> particle conversion for every fluid species with a fluid array.
@@ -1360,7 +1363,7 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
     // when a sink species does not exist
     S->wmax = (unsigned *)dalloc(S, sizeof(unsigned) * (HK_MAX_SPECIES + 1));
     S->plan = (int2 *)dalloc(S, sizeof(int2) * (size_t)tile_plan_items(g));
-    S->plan_ctl = (int *)dalloc(S, sizeof(int) * 4);
+    S->plan_ctl = (int *)dalloc(S, sizeof(int) * PLAN_CTL);
     if (hipHostMalloc((void **)&S->h_status, sizeof(int) * HK_NSTATUS, 0) != hipSuccess)
         S->h_status = nullptr;
     if (hipEventCreateWithFlags(&S->status_ev, hipEventDisableTiming) != hipSuccess)

@@ -293,9 +293,13 @@ void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PA
                        int mode, const QedP &Q, const AbsorbP &A, int2 *items, int *ctl,
                        long long capacity, int *live, hipStream_t s);
 // Work plans of the per-tile particle kernels: items (tile, chunk) for grid g
-// (tile_plan_items entries) and ctl[0] (the item count).  The plan lists the chunks of
-// at least cmin particles of bins b by decreasing size; tile_plan_grid is the
-// launch size that covers every item of a species of this capacity.
+// (tile_plan_items entries) and ctl[0] (the item count); ctl holds PLAN_CTL
+// ints (the planner's per-workgroup bucket counts follow the count).  The
+// plan lists the chunks of at least cmin particles of bins b by decreasing
+// size; tile_plan_grid is the launch size that covers every item of a
+// species of this capacity.
+constexpr int PLAN_PARTS = 64;
+constexpr int PLAN_CTL = 4 + 32 * PLAN_PARTS;
 long long tile_plan_items(const GridP &g);
 unsigned tile_plan_grid(const GridP &g, long long capacity, int cmin);
 void launch_tile_plan(const GridP &g, const SpecP &sp, Bins b, int cmin, int2 *items, int *ctl,
@@ -322,8 +326,9 @@ void launch_label_nodes(const GridP &g, const SwitchP &P, const real *mom, real 
                         const IonP *const *ions, int nion, uint8_t *cond, hipStream_t s);
 void launch_label_or(long long n, const uint8_t *cond, uint8_t *y, hipStream_t s);
 void launch_flags_canonical(const GridP &g, const uint8_t *src, uint8_t *dst, hipStream_t s);
+// tmp: 2 nn bytes of scratch
 void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, const uint8_t *notcold,
-                         uint8_t *sw, uint8_t *calm, hipStream_t s);
+                         uint8_t *sw, uint8_t *calm, uint8_t *tmp, hipStream_t s);
 // macc: 5 grid arrays (FP64): absorbed weight, momentum (3), kinetic energy
 // merges macc into the fluid at the nodes of the absorptions' x range xr[4..5]
 void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n, real *ux,

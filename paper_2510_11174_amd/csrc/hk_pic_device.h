@@ -40,9 +40,14 @@ __device__ inline AxisW axis_weights(int l, real o) {
     return a;
 }
 
-// Reciprocal: the hardware's (1 ulp) in FP32, a division in FP64.
+// Reciprocal and square root: the hardware's (1 ulp) in FP32, correctly
+// rounded in FP64.  The FP32 square roots here take arguments >= 1 (Lorentz
+// factors), where the correctly rounded FP32 sequence would only add
+// denormal scaling and a final ulp fix-up.
 __device__ inline float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double rcp_(double x) { return 1.0 / x; }
+__device__ inline float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline double sqrt_(double x) { return sqrt(x); }
 
 // Trilinear interpolation as three rounds of linear interpolation (x, y, z).
 __device__ inline real tri(const real *F, int i, int j, int k, real fx, real fy, real fz) {
@@ -64,75 +69,32 @@ struct AxisS {
     real S0[3], DS[3];
 };
 __device__ inline AxisS axis_shapes(real o, real X1) {
+    // crossed up: nodes 0, 1, 2 with e = X1 - 1; crossed down: nodes -1, 0, 1
+    // with e = -X1; stayed: nodes 0, 1, 2 with d = X1 - o.  Selects, not
+    // branches: the lanes of a wave take different cases.
+    const bool up = X1 >= (real)1, dn = X1 < (real)0;
+    const real e = up ? X1 - (real)1 : -X1, d = X1 - o, q = (real)1 - o;
     AxisS s;
-    if (X1 >= (real)1) {                // crossed up: nodes 0, 1, 2
-        real e = X1 - (real)1;
-        s.base = 0;
-        s.S0[0] = (real)1 - o; s.S0[1] = o; s.S0[2] = 0;
-        s.DS[0] = -((real)1 - o); s.DS[1] = ((real)1 - e) - o; s.DS[2] = e;
-    } else if (X1 < (real)0) {          // crossed down: nodes -1, 0, 1
-        real e = -X1;
-        s.base = -1;
-        s.S0[0] = 0; s.S0[1] = (real)1 - o; s.S0[2] = o;
-        s.DS[0] = e; s.DS[1] = o - e; s.DS[2] = -o;
-    } else {                            // stayed: nodes 0, 1, 2
-        real d = X1 - o;
-        s.base = 0;
-        s.S0[0] = (real)1 - o; s.S0[1] = o; s.S0[2] = 0;
-        s.DS[0] = -d; s.DS[1] = d; s.DS[2] = 0;
-    }
+    s.base = dn ? -1 : 0;
+    s.S0[0] = dn ? (real)0 : q;
+    s.S0[1] = dn ? q : o;
+    s.S0[2] = dn ? o : (real)0;
+    s.DS[0] = up ? -q : (dn ? e : -d);
+    s.DS[1] = up ? ((real)1 - e) - o : (dn ? o - e : d);
+    s.DS[2] = up ? e : (dn ? -o : (real)0);
     return s;
 }
 
-// Deposit the Esirkepov current of one particle into the LDS J tile.  (lx, ly,
-// lz) is the old cell inside the tile; cx = q w / dV * dx / dt (per axis).
-__device__ inline void esirkepov_lds(real *sJ, int lx, int ly, int lz, const AxisS &X,
-                                     const AxisS &Y, const AxisS &Z, real cx, real cy, real cz) {
-    const real third = (real)(1.0 / 3.0), half = (real)0.5;
-    const int ox = lx + X.base + 1, oy = ly + Y.base + 1, oz = lz + Z.base + 1;
-    // Jx on faces a = 0, 1 (prefix of W_x along x)
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            real fyz = Y.S0[b] * Z.S0[c] + half * Y.DS[b] * Z.S0[c] + half * Y.S0[b] * Z.DS[c] +
-                       third * Y.DS[b] * Z.DS[c];
-            real acc = 0;
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                acc -= cx * (X.DS[a] * fyz);
-                if (acc != (real)0)
-                    atomicAdd(&sJ[0 * JT3 + (ox + a) + JT * ((oy + b) + JT * (oz + c))], acc);
-            }
-        }
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            real fxz = X.S0[a] * Z.S0[c] + half * X.DS[a] * Z.S0[c] + half * X.S0[a] * Z.DS[c] +
-                       third * X.DS[a] * Z.DS[c];
-            real acc = 0;
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                acc -= cy * (Y.DS[b] * fxz);
-                if (acc != (real)0)
-                    atomicAdd(&sJ[1 * JT3 + (ox + a) + JT * ((oy + b) + JT * (oz + c))], acc);
-            }
-        }
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            real fxy = X.S0[a] * Y.S0[b] + half * X.DS[a] * Y.S0[b] + half * X.S0[a] * Y.DS[b] +
-                       third * X.DS[a] * Y.DS[b];
-            real acc = 0;
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                acc -= cz * (Z.DS[c] * fxy);
-                if (acc != (real)0)
-                    atomicAdd(&sJ[2 * JT3 + (ox + a) + JT * ((oy + b) + JT * (oz + c))], acc);
-            }
-        }
+// A lane's move crosses a cell face along this axis (its shape window then
+// uses the third node, and two longitudinal faces carry current).
+__device__ inline bool crosses(real X1) { return X1 >= (real)1 || X1 < (real)0; }
+
+// Bits 0, 1, 2: some active lane of the wave crosses along x, y, z.  The
+// value is the same on every lane and lives in a scalar register.
+__device__ inline unsigned wave_crossings(real X1, real Y1, real Z1) {
+    const unsigned f = (__ballot(crosses(X1)) ? 1u : 0u) | (__ballot(crosses(Y1)) ? 2u : 0u) |
+                       (__ballot(crosses(Z1)) ? 4u : 0u);
+    return __builtin_amdgcn_readfirstlane(f);
 }
 
 // Current accumulator type of the LDS tile.  On gfx950 an LDS float atomic
@@ -185,8 +147,15 @@ __device__ inline void jput(jacc_t *p, real v) {
     if (v != (real)0) atomicAdd(p, v);
 }
 #else
+// v_cvt_rpi_i32_f32 rounds to the nearest integer (halves up) in one
+// instruction, where rint and a conversion take two
+__device__ inline int round_i32(float v) {
+    int q;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(q) : "v"(v));
+    return q;
+}
 __device__ inline void jput(jacc_t *p, real v) {   // v in units
-    const int q = __float2int_rn(v);
+    const int q = round_i32(v);
     if (q) atomicAdd(p, (unsigned long long)(long long)q);
 }
 #endif
@@ -219,8 +188,15 @@ __device__ inline void jg_put(jglob_t *p, double v) {
 // is minus the running sum of the longitudinal shape change, times q w / dV
 // * dx / dt (cx, cy, cz: in units in the FP32 build).  The running sum over
 // the last node of the window is zero, so two faces per line carry current.
+// A lane that does not cross a face along an axis has zero shape on the
+// window's third node and a zero second face (DS0 + DS1 = 0 exactly) along
+// it: bits 0, 1, 2 of wf (the same on every lane of the wave) say whether
+// any lane crossed along x, y, z; the terms that are zero on every lane are
+// skipped, which leaves 12 of the 54 when none did.
 __device__ inline void esirkepov_acc(jacc_t *sJ, int lx, int ly, int lz, const AxisS &X,
-                                     const AxisS &Y, const AxisS &Z, real cx, real cy, real cz) {
+                                     const AxisS &Y, const AxisS &Z, real cx, real cy, real cz,
+                                     unsigned wf) {
+    const bool wx = wf & 1u, wy = wf & 2u, wz = wf & 4u;
     const real third = (real)(1.0 / 3.0), half = (real)0.5;
     real Ax[3], Bx[3], Ay[3], By[3], Az[3], Bz[3];
 #pragma unroll
@@ -235,29 +211,38 @@ __device__ inline void esirkepov_acc(jacc_t *sJ, int lx, int ly, int lz, const A
     const real ky0 = -cy * Y.DS[0], ky1 = -cy * (Y.DS[0] + Y.DS[1]);
     const real kz0 = -cz * Z.DS[0], kz1 = -cz * (Z.DS[0] + Z.DS[1]);
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 3; ++c) {
+        if (c == 2 && !wz) break;
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
+            if (b == 2 && !wy) break;
             const real f = Z.S0[c] * Ay[b] + Z.DS[c] * By[b];
             jput(o + 0 * JT3 + 0 + JT * (b + JT * c), kx0 * f);
-            jput(o + 0 * JT3 + 1 + JT * (b + JT * c), kx1 * f);
+            if (wx) jput(o + 0 * JT3 + 1 + JT * (b + JT * c), kx1 * f);
         }
+    }
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 3; ++c) {
+        if (c == 2 && !wz) break;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
+            if (a == 2 && !wx) break;
             const real f = Z.S0[c] * Ax[a] + Z.DS[c] * Bx[a];
             jput(o + 1 * JT3 + a + JT * (0 + JT * c), ky0 * f);
-            jput(o + 1 * JT3 + a + JT * (1 + JT * c), ky1 * f);
+            if (wy) jput(o + 1 * JT3 + a + JT * (1 + JT * c), ky1 * f);
         }
+    }
 #pragma unroll
-    for (int b = 0; b < 3; ++b)
+    for (int b = 0; b < 3; ++b) {
+        if (b == 2 && !wy) break;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
+            if (a == 2 && !wx) break;
             const real f = Y.S0[b] * Ax[a] + Y.DS[b] * Bx[a];
             jput(o + 2 * JT3 + a + JT * (b + JT * 0), kz0 * f);
-            jput(o + 2 * JT3 + a + JT * (b + JT * 1), kz1 * f);
+            if (wz) jput(o + 2 * JT3 + a + JT * (b + JT * 1), kz1 * f);
         }
+    }
 }
 
 __device__ inline real below_one() {
@@ -317,9 +302,11 @@ __device__ inline double qed_chi(double a_s, double ex, double ey, double ez, do
 // any change of the optical depth, can happen: the FP64 evaluation is skipped.
 __device__ inline bool qed_chi_below_floor(float a_s, float ex, float ey, float ez, float bx, float by,
                                            float bz, float ux, float uy, float uz, bool photon, float floor_) {
+    // hardware square roots (1 ulp each): the margin covers them
     const float p2 = ux * ux + uy * uy + uz * uz;
-    const float en = photon ? sqrtf(p2) : sqrtf(1.0f + p2);
-    const float f = sqrtf(ex * ex + ey * ey + ez * ez) + sqrtf(bx * bx + by * by + bz * bz);
+    const float en = __builtin_amdgcn_sqrtf(photon ? p2 : 1.0f + p2);
+    const float f = __builtin_amdgcn_sqrtf(ex * ex + ey * ey + ez * ez) +
+                    __builtin_amdgcn_sqrtf(bx * bx + by * by + bz * bz);
     return en * f * 1.02f < floor_ * a_s;
 }
 

@@ -6,7 +6,7 @@
 // energy equations with relativistic gamma and adiabatic pressure for the
 // bulk plasma; the adiabatic energy equation is the advection of S).
 //
-// Scheme (per step, two passes, each one thread per node, x fastest):
+// Scheme (per step, two passes over the nodes of the x window, x fastest):
 //   1. us = Boris(u; E, B interpolated to the node); a warm species then
 //      takes the pressure force, us -= dt grad p / (m n) at nodes above the
 //      density floor (p = S n^(ga-1), zero where n = 0; central differences,
@@ -36,21 +36,34 @@
 namespace {
 
 constexpr int BS = 256;
+constexpr unsigned WIN_GRID = 8192;   // blocks of the window passes (a multiple of 8)
 
-// Node of this thread in an XCD-aware launch: workgroups go round-robin to
-// the 8 XCDs, so block b takes item (b mod 8) q + b / 8 (q = grid / 8, the
-// grid a multiple of 8) and each XCD sweeps a contiguous slab of nodes,
-// whose y and z neighbour rows then sit in its own L2.
-__device__ inline long long xcd_node() {
-    const int q = gridDim.x >> 3;
-    const int item = (blockIdx.x & 7) * q + (blockIdx.x >> 3);
-    return (long long)item * BS + threadIdx.x;
+
+// The pass window of x range xr (see above): node columns lo .. lo + w - 1
+// of every (y, z) row; false when it is empty.
+__device__ inline bool pass_window(const GridP &g, const int *__restrict__ xr, int &lo, int &w) {
+    lo = max(xr[0] - 1, 0);
+    w = min(xr[1] + 1, g.sx - 1) - lo + 1;
+    return w > 0;
 }
 
-
-// Whether x index i is inside the pass window of x range xr (see above).
-__device__ inline bool in_window(const int *__restrict__ xr, int i) {
-    return i >= xr[0] - 1 && i <= xr[1] + 1;
+// The window's nodes spread over a fixed grid (a multiple of 8 blocks):
+// workgroups go round-robin to the 8 XCDs, and XCD x sweeps the x-th eighth
+// of the window's nodes in row order, so that the y and z neighbour rows of
+// its nodes sit in its own L2.  f(c, i, j, k) runs once per window node.
+template <typename F>
+__device__ inline void for_window_nodes(const GridP &g, const int *__restrict__ xr, F f) {
+    int lo, w;
+    if (!pass_window(g, xr, lo, w)) return;
+    const unsigned total = (unsigned)w * (unsigned)g.ny * (unsigned)g.nz;
+    const unsigned share = (total + 7u) / 8u, xcd = blockIdx.x & 7u, per_xcd = gridDim.x >> 3;
+    const unsigned end = min(total, (xcd + 1u) * share);
+    for (unsigned t = xcd * share + (blockIdx.x >> 3) * BS + threadIdx.x; t < end; t += per_xcd * BS) {
+        const unsigned row = t / (unsigned)w;
+        const int i = lo + (int)(t - row * (unsigned)w);
+        const int j = (int)(row % (unsigned)g.ny), k = (int)(row / (unsigned)g.ny);
+        f(i + (int)row * g.sx, i, j, k);
+    }
 }
 
 // Linear indices of a node's neighbours (node counts stay below 2^31):
@@ -102,26 +115,22 @@ __device__ inline real node_val(const real *__restrict__ F, const int xs[2], con
 __global__ void __launch_bounds__(BS)
 k_fluid_p(GridP g, real gm1, const real *__restrict__ n, const real *__restrict__ S, real *__restrict__ P,
           const int *__restrict__ xr) {
-    long long c = xcd_node();
-    if (c >= g.nn || !in_window(xr, (int)((unsigned)c % (unsigned)g.sx))) return;
-    const real nc = n[c];
-    P[c] = nc > (real)0 ? S[c] * pow(nc, gm1) : (real)0;
+    for_window_nodes(g, xr, [&](int c, int, int, int) {
+        const real nc = n[c];
+        P[c] = nc > (real)0 ? S[c] * pow(nc, gm1) : (real)0;
+    });
 }
 
-__global__ void __launch_bounds__(BS)
-k_fluid_lorentz(GridP g, real qm, real mass, real n_floor, const real *__restrict__ n,
-                const real *__restrict__ P, const real *__restrict__ ux,
-                const real *__restrict__ uy, const real *__restrict__ uz, const real *__restrict__ Ex,
-                const real *__restrict__ Ey, const real *__restrict__ Ez, const real *__restrict__ Bx,
-                const real *__restrict__ By, const real *__restrict__ Bz, real *__restrict__ sc,
-                const int *__restrict__ xr) {
-    long long cl = xcd_node();
-    if (cl >= g.nn || !in_window(xr, (int)((unsigned)cl % (unsigned)g.sx))) return;
-    int i, j, k;
-    node_ijk(g, cl, i, j, k);
+__device__ inline void fluid_lorentz_node(const GridP &g, real qm, real mass, real n_floor,
+                                          const real *__restrict__ n, const real *__restrict__ P,
+                                          const real *__restrict__ ux, const real *__restrict__ uy,
+                                          const real *__restrict__ uz, const real *__restrict__ Ex,
+                                          const real *__restrict__ Ey, const real *__restrict__ Ez,
+                                          const real *__restrict__ Bx, const real *__restrict__ By,
+                                          const real *__restrict__ Bz, real *__restrict__ sc, int c, int i,
+                                          int j, int k) {
     const int per = g.bcx == HK_BC_PERIODIC;
     const int nxn = per ? g.nx : g.nx + 1;
-    const int c = (int)cl;
     const real nc = n[c];
     if (i >= nxn || !(nc > (real)0)) return;
     const int sxy = g.sx * g.ny;
@@ -173,6 +182,18 @@ k_fluid_lorentz(GridP g, real qm, real mass, real n_floor, const real *__restric
     }
 }
 
+__global__ void __launch_bounds__(BS)
+k_fluid_lorentz(GridP g, real qm, real mass, real n_floor, const real *__restrict__ n,
+                const real *__restrict__ P, const real *__restrict__ ux,
+                const real *__restrict__ uy, const real *__restrict__ uz, const real *__restrict__ Ex,
+                const real *__restrict__ Ey, const real *__restrict__ Ez, const real *__restrict__ Bx,
+                const real *__restrict__ By, const real *__restrict__ Bz, real *__restrict__ sc,
+                const int *__restrict__ xr) {
+    for_window_nodes(g, xr, [&](int c, int i, int j, int k) {
+        fluid_lorentz_node(g, qm, mass, n_floor, n, P, ux, uy, uz, Ex, Ey, Ez, Bx, By, Bz, sc, c, i, j, k);
+    });
+}
+
 // One side of a face: density, its velocity component normal to the face,
 // its momentum, and whether it is above the density floor.
 struct Side {
@@ -199,18 +220,14 @@ __device__ inline void face_flux(const Side &l, const Side &r, int lo, int hi, r
     }
 }
 
-__global__ void __launch_bounds__(BS)
-k_fluid_update(GridP g, real q, real n_floor, const real *__restrict__ n, real *__restrict__ ux,
-               real *__restrict__ uy, real *__restrict__ uz, const real *__restrict__ sc,
-               real *__restrict__ Jx, real *__restrict__ Jy, real *__restrict__ Jz,
-               real *__restrict__ nout, const real *__restrict__ S, real *__restrict__ Sout, int *__restrict__ xr) {
-    long long cl = xcd_node();
-    if (cl >= g.nn || !in_window(xr, (int)((unsigned)cl % (unsigned)g.sx))) return;
-    int i, j, k;
-    node_ijk(g, cl, i, j, k);
+__device__ inline void fluid_update_node(const GridP &g, real q, real n_floor, const real *__restrict__ n,
+                                         real *__restrict__ ux, real *__restrict__ uy, real *__restrict__ uz,
+                                         const real *__restrict__ sc, real *__restrict__ Jx,
+                                         real *__restrict__ Jy, real *__restrict__ Jz, real *__restrict__ nout,
+                                         const real *__restrict__ S, real *__restrict__ Sout,
+                                         int *__restrict__ xr, int x0, int x1, int c, int i, int j, int k) {
     const int per = g.bcx == HK_BC_PERIODIC;
     const int nxn = per ? g.nx : g.nx + 1;
-    const int c = (int)cl;
     const real n0 = n[c];
     if (i >= nxn) {
         nout[c] = n0;
@@ -281,7 +298,7 @@ k_fluid_update(GridP g, real q, real n_floor, const real *__restrict__ n, real *
     const real nv = n0 - g.dt * dn;
     nout[c] = nv;
     // fluid left next to the window: widen it (x index i holds fluid now)
-    if (nv != (real)0 && (i < xr[0] || i > xr[1])) {
+    if (nv != (real)0 && (i < x0 || i > x1)) {
         atomicMin(&xr[2], i);
         atomicMax(&xr[3], i);
     }
@@ -301,6 +318,18 @@ k_fluid_update(GridP g, real q, real n_floor, const real *__restrict__ n, real *
     if (fplus[0] != (real)0) Jx[c] += q * fplus[0];
     if (fplus[1] != (real)0) Jy[c] += q * fplus[1];
     if (fplus[2] != (real)0) Jz[c] += q * fplus[2];
+}
+
+__global__ void __launch_bounds__(BS)
+k_fluid_update(GridP g, real q, real n_floor, const real *__restrict__ n, real *__restrict__ ux,
+               real *__restrict__ uy, real *__restrict__ uz, const real *__restrict__ sc,
+               real *__restrict__ Jx, real *__restrict__ Jy, real *__restrict__ Jz,
+               real *__restrict__ nout, const real *__restrict__ S, real *__restrict__ Sout, int *__restrict__ xr) {
+    // the window as this pass found it (the pass widens xr[2..3] only)
+    const int x0 = xr[0], x1 = xr[1];
+    for_window_nodes(g, xr, [&](int c, int i, int j, int k) {
+        fluid_update_node(g, q, n_floor, n, ux, uy, uz, sc, Jx, Jy, Jz, nout, S, Sout, xr, x0, x1, c, i, j, k);
+    });
 }
 
 // thermal energy sum p dV / (ga - 1) over the nodes
@@ -325,8 +354,6 @@ k_fluid_heat(GridP g, const real *__restrict__ n, const real *__restrict__ S, re
 }
 
 inline unsigned blocks(long long n) { return (unsigned)((n + BS - 1) / BS); }
-// grid of an XCD-aware launch over n nodes
-inline unsigned xcd_blocks(long long n) { return (blocks(n) + 7u) & ~7u; }
 
 // xr[0..1] the window, xr[2..3] the update's widening, xr[4..5] the
 // absorptions' range: the window takes both, which then start empty again
@@ -349,11 +376,11 @@ void launch_fluid(const GridP &g, const SpecP &sp, const real *n, real *ux, real
     real *P = nullptr;
     if (w.S) {
         P = scratch + 6 * g.nn;
-        k_fluid_p<<<xcd_blocks(g.nn), BS, 0, s>>>(g, (real)(w.ga - 1.0), n, w.S, P, xr);
+        k_fluid_p<<<WIN_GRID, BS, 0, s>>>(g, (real)(w.ga - 1.0), n, w.S, P, xr);
     }
-    k_fluid_lorentz<<<xcd_blocks(g.nn), BS, 0, s>>>(g, sp.qm, sp.m, n_floor, n, P, ux, uy, uz, f[HK_EX],
+    k_fluid_lorentz<<<WIN_GRID, BS, 0, s>>>(g, sp.qm, sp.m, n_floor, n, P, ux, uy, uz, f[HK_EX],
                                                 f[HK_EY], f[HK_EZ], f[HK_BX], f[HK_BY], f[HK_BZ], scratch, xr);
-    k_fluid_update<<<xcd_blocks(g.nn), BS, 0, s>>>(g, sp.q, n_floor, n, ux, uy, uz, scratch, f[HK_JX],
+    k_fluid_update<<<WIN_GRID, BS, 0, s>>>(g, sp.q, n_floor, n, ux, uy, uz, scratch, f[HK_JX],
                                                f[HK_JY], f[HK_JZ], nout, w.S, Sout, xr);
 }
 

@@ -43,15 +43,18 @@ __device__ inline void copy_particle(const PArr &s, long long i, const PArr &d, 
 // (c * ppc + q), unique over the species; offsets from Philox tag 1 keyed by
 // the position index (the species of a cell start at the same points),
 // momenta by Box-Muller from tag 2 keyed by the id (FP64, rounded once to
-// the storage type).
+// the storage type).  Storage order: q slowest, so that consecutive particles
+// (the lanes of a wave in the push, after binning) sit in distinct cells and
+// their LDS current atomics go to distinct addresses.
 __global__ void __launch_bounds__(BS)
 k_init(GridP g, int ppc, int isp, double u_th, double charge, uint64_t seed, const int *__restrict__ xcol,
        const double *__restrict__ wcol, int ncol, long long total, PArr out, int has_z,
        int has_tau) {
     long long tid = (long long)blockIdx.x * BS + threadIdx.x;
     if (tid >= total) return;
-    int q = (int)(tid % ppc);
-    long long r = tid / ppc;
+    const long long cells = total / ppc;
+    int q = (int)(tid / cells);
+    long long r = tid - (long long)q * cells;
     int col = (int)(r % ncol);
     long long jk = r / ncol;
     int j = (int)(jk % g.ny), k = (int)(jk / g.ny);
@@ -267,19 +270,30 @@ constexpr int PUSH_CHUNK = 16 * PBS; // tiles up to this many particles take one
 // ------------------------------------------------------ work plan of tile kernels -----
 constexpr int PLAN_BS = 1024;
 
-// ctl[0] = number of items; items sorted by decreasing chunk size through 32
-// power-of-two buckets.  live (optional) receives the item count too: zero
-// exactly when the bins are empty.
+// Two passes over the tiles, PLAN_PARTS workgroups each, every workgroup on
+// the same contiguous range of tiles in both.  The items are sorted by
+// decreasing chunk size through 32 power-of-two buckets: pass 1 counts each
+// workgroup's items per bucket into ctl[4 + 32 w + b]; pass 2 places them,
+// bucket b starting after every larger bucket's items and after the items
+// of bucket b of the earlier workgroups.  ctl[0] = number of items; live
+// (optional) receives it too: zero exactly when the bins are empty.
+__device__ inline void plan_range(int ntiles, int &t0, int &t1) {
+    const int per = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
+    t0 = min(ntiles, (int)blockIdx.x * per);
+    t1 = min(ntiles, t0 + per);
+}
+
 __global__ void __launch_bounds__(PLAN_BS)
-k_tile_plan(int ntiles, SpecP sp, Bins bins, int cmin, int2 *__restrict__ items, int *__restrict__ ctl,
-            int *__restrict__ zero3, int *__restrict__ live = nullptr) {
-    __shared__ int cnt[32], cur[32];
+k_plan_count(int ntiles, SpecP sp, Bins bins, int cmin, int *__restrict__ ctl, int *__restrict__ zero3) {
+    __shared__ int cnt[32];
     if (threadIdx.x < 32) cnt[threadIdx.x] = 0;
     // the push's output counters (3 ntiles ints), cleared here to save a launch
     if (zero3)
-        for (int t = threadIdx.x; t < 3 * ntiles; t += PLAN_BS) zero3[t] = 0;
+        for (int t = blockIdx.x * PLAN_BS + threadIdx.x; t < 3 * ntiles; t += gridDim.x * PLAN_BS) zero3[t] = 0;
     __syncthreads();
-    for (int t = threadIdx.x; t < ntiles; t += PLAN_BS) {
+    int t0, t1;
+    plan_range(ntiles, t0, t1);
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += PLAN_BS) {
         int nfi, nbi;
         const int n = bin_count(sp, bins, t, nfi, nbi);
         if (n > 0) {
@@ -288,14 +302,37 @@ k_tile_plan(int ntiles, SpecP sp, Bins bins, int cmin, int2 *__restrict__ items,
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int total = 0;
-        for (int b = 31; b >= 0; --b) { cur[b] = total; total += cnt[b]; }
-        ctl[0] = total;
-        if (live) *live = total;
+    if (threadIdx.x < 32) ctl[4 + 32 * blockIdx.x + threadIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(PLAN_BS)
+k_plan_place(int ntiles, SpecP sp, Bins bins, int cmin, int2 *__restrict__ items, int *__restrict__ ctl,
+             int *__restrict__ live) {
+    __shared__ int tot[32], cur[32];
+    if (threadIdx.x < 32) {
+        const int b = threadIdx.x;
+        int all = 0, before = 0;
+        for (int w = 0; w < (int)gridDim.x; ++w) {
+            const int v = ctl[4 + 32 * w + b];
+            all += v;
+            if (w < (int)blockIdx.x) before += v;
+        }
+        tot[b] = all;
+        cur[b] = before;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < ntiles; t += PLAN_BS) {
+    if (threadIdx.x == 0) {
+        int total = 0;
+        for (int b = 31; b >= 0; --b) { cur[b] += total; total += tot[b]; }
+        if (blockIdx.x == 0) {
+            ctl[0] = total;
+            if (live) *live = total;
+        }
+    }
+    __syncthreads();
+    int t0, t1;
+    plan_range(ntiles, t0, t1);
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += PLAN_BS) {
         int nfi, nbi;
         const int n = bin_count(sp, bins, t, nfi, nbi);
         if (n > 0) {
@@ -304,6 +341,12 @@ k_tile_plan(int ntiles, SpecP sp, Bins bins, int cmin, int2 *__restrict__ items,
             for (int j = 0; j < k; ++j) items[at + j] = make_int2(t, j);
         }
     }
+}
+
+void plan_tiles(const GridP &g, const SpecP &sp, Bins b, int cmin, int2 *items, int *ctl, int *zero3,
+                int *live, hipStream_t s) {
+    k_plan_count<<<PLAN_PARTS, PLAN_BS, 0, s>>>(g.ntiles, sp, b, cmin, ctl, zero3);
+    k_plan_place<<<PLAN_PARTS, PLAN_BS, 0, s>>>(g.ntiles, sp, b, cmin, items, ctl, live);
 }
 
 // One particle's state as the push reads it.  Every field is loaded at once
@@ -524,10 +567,26 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
                             if (!want1) led += (double)w * kk;
                         }
                     }
+                    // the photon is written here, while its momentum is at
+                    // hand, rather than held in registers through the push
+                    const int k1 = wave_slot(Q.out1_n, want1);
+                    if (want1) {
+                        if (k1 >= Q.out1_cap) atomicOr(err, ERR_INBOX);
+                        else {
+                            PArr o = Q.out1;
+                            o.cell[k1] = cell;
+                            o.rx[k1] = rx; o.ry[k1] = ry; o.rz[k1] = rz;
+                            o.ux[k1] = (real)kx; o.uy[k1] = (real)ky; o.uz[k1] = (real)kz;
+                            o.w[k1] = w;
+                            const uint64_t cid = child_id(id, (uint32_t)Q.step, 1u);
+                            o.id[k1] = cid;
+                            if (Q.out1_tau) o.tau[k1] = tau0(Q.seed, cid);
+                        }
+                    }
                 }
                 // Boris rotation
                 real umx = ux + hq * ex, umy = uy + hq * ey, umz = uz + hq * ez;
-                real gm = sqrt((real)1 + umx * umx + umy * umy + umz * umz);
+                real gm = sqrt_((real)1 + umx * umx + umy * umy + umz * umz);
                 const real igm = hq * rcp_(gm);
                 real tx_ = bx * igm, ty_ = by * igm, tz_ = bz * igm;
                 real t2 = tx_ * tx_ + ty_ * ty_ + tz_ * tz_;
@@ -540,7 +599,7 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
                 real uqy = umy + (upz * sx - upx * sz);
                 real uqz = umz + (upx * sy - upy * sx);
                 ux = uqx + hq * ex; uy = uqy + hq * ey; uz = uqz + hq * ez;
-                real gam = sqrt((real)1 + ux * ux + uy * uy + uz * uz);
+                real gam = sqrt_((real)1 + ux * ux + uy * uy + uz * uz);
                 const real igam = rcp_(gam);
                 X1 = rx + dtdx * ux * igam;
                 Y1 = ry + dtdy * uy * igam;
@@ -566,7 +625,9 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
                 if (MODE != 2 && sp.q != (real)0) {
                     AxisS SX = axis_shapes(rx, X1), SY = axis_shapes(ry, Y1), SZ = axis_shapes(rz, Z1);
                     const real qws = qsc * w;
-                    esirkepov_acc(sJ, lx, ly, lz, SX, SY, SZ, qws * cdx, qws * cdy, qws * cdz);
+                    // the axes some depositing lane of this wave crosses along
+                    esirkepov_acc(sJ, lx, ly, lz, SX, SY, SZ, qws * cdx, qws * cdy, qws * cdz,
+                                  wave_crossings(X1, Y1, Z1));
                 }
                 // new cell and offsets
                 int fx = X1 >= (real)1 ? 1 : (X1 < (real)0 ? -1 : 0);
@@ -594,7 +655,8 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
                         AxisS SX = axis_shapes(nrx, (real)dxn), SY = axis_shapes(nry, (real)dyn),
                               SZ = axis_shapes(nrz, (real)dzn);
                         const real qws = qsc * w;
-                        esirkepov_acc(sJ, lxn, lyn, lzn, SX, SY, SZ, qws * cdx, qws * cdy, qws * cdz);
+                        // a move onto a node crosses no face
+                        esirkepov_acc(sJ, lxn, lyn, lzn, SX, SY, SZ, qws * cdx, qws * cdy, qws * cdz, 0u);
                         int gi = ni + dxn, gj = nj + dyn, gk = nk + dzn;
                         if (per && gi == g.nx) gi = 0;
                         if (gj == g.ny) gj = 0;
@@ -656,19 +718,19 @@ k_push(GridP g, SpecP sp, PArr in, Bins bin_in, long long dout, int *__restrict_
             };
             const int k = bm + __popcll(mm & lt);
             // the mover regions follow the bins in the output buffer; the inbox
-            // descriptor is read only when a region overflows
-            if (stay) put_out(obase + bs + __popcll(ms & lt));
-            else if (k < mlim) put_out(mig0 + mbase + k);
+            // descriptor is read only when a region overflows.  Stayers and
+            // movers share one store sequence.
+            if (stay || k < mlim) put_out(stay ? obase + bs + __popcll(ms & lt) : mig0 + mbase + k);
             else {
                 const int q = atomicAdd(inbox_n, 1);
                 if (q >= inbox_cap) atomicOr(err, ERR_INBOX);
                 else put(*inbox_p, q);
             }
         }
-        if (MODE != 0) {
+        if (MODE == 2) {
             // new particles sit where their parent was at the start of the step
             const int k1 = wave_slot(Q.out1_n, want1);
-            const int k2 = MODE == 2 ? wave_slot(Q.out2_n, want2) : -1;
+            const int k2 = wave_slot(Q.out2_n, want2);
             if (want1) {
                 if (k1 >= Q.out1_cap) atomicOr(err, ERR_INBOX);
                 else {
@@ -1014,7 +1076,7 @@ unsigned tile_plan_grid(const GridP &g, long long capacity, int cmin) {
 
 void launch_tile_plan(const GridP &g, const SpecP &sp, Bins b, int cmin, int2 *items, int *ctl,
                       hipStream_t s) {
-    k_tile_plan<<<1, PLAN_BS, 0, s>>>(g.ntiles, sp, b, cmin, items, ctl, nullptr);
+    plan_tiles(g, sp, b, cmin, items, ctl, nullptr, nullptr, s);
 }
 
 void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PArr out,
@@ -1028,7 +1090,7 @@ void launch_push_tiles(const GridP &g, const SpecP &sp, PArr in, Bins bin_in, PA
         stats, wmax_bits, umax2, items, ctl, Q, A
     // nf_out is the first of the next buffer's three counter arrays (front
     // fills, back fills, mover ranks), cleared by the planner
-    k_tile_plan<<<1, PLAN_BS, 0, s>>>(g.ntiles, sp, bin_in, PUSH_CHUNK, items, ctl, nf_out, live);
+    plan_tiles(g, sp, bin_in, PUSH_CHUNK, items, ctl, nf_out, live, s);
     // the two bin buffers share one layout (checked when they are allocated):
     // every field of `out` sits the same byte distance from that of `in`
     const long long dout = (const char *)out.cell - (const char *)in.cell;

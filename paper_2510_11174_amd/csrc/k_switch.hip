@@ -390,29 +390,54 @@ k_label_or(long long n, const uint8_t *__restrict__ cond, uint8_t *__restrict__ 
     if (v < n && cond[v]) y[v] = 1;
 }
 
+// Dilation by the (2 D + 1)^3 box, as three one-axis passes (the OR over a
+// box is the OR over its rows of the OR over their elements): bit 0 of the
+// running mask is "hot", bit 1 "not cold".  Pass x also packs the two
+// flags; pass z applies the result: a node near a hot one is kinetic and
+// calm again; a kinetic node turns fluid after `hysteresis` evaluations in
+// a row with no hot and no warm node in reach.
 __global__ void __launch_bounds__(BS)
-k_dilate(GridP g, SwitchP P, const uint8_t *__restrict__ hot, const uint8_t *__restrict__ notcold,
-         uint8_t *__restrict__ sw, uint8_t *__restrict__ calm) {
-    long long c = xcd_node();
+k_dilate_x(GridP g, int D, const uint8_t *__restrict__ hot, const uint8_t *__restrict__ notcold,
+           uint8_t *__restrict__ out) {
+    const long long c = xcd_node();
     if (c >= g.nn) return;
     int i, j, k;
     node_ijk(g, c, i, j, k);
     const int per = g.bcx == HK_BC_PERIODIC;
-    const int nxn = per ? g.nx : g.nx + 1;
+    const long long row = c - i;
+    uint8_t m = 0;
+    for (int di = -D; di <= D; ++di) {
+        int ii = i + di;
+        if (!per && (ii < 0 || ii > g.nx)) continue;
+        if (per) ii = wrapi(ii, g.nx);
+        m |= (uint8_t)(hot[row + ii] | (notcold[row + ii] << 1));
+    }
+    out[c] = m;
+}
+// axis 1 (y) or 2 (z), periodic
+__global__ void __launch_bounds__(BS)
+k_dilate_yz(GridP g, int D, int axis, const uint8_t *__restrict__ in, uint8_t *__restrict__ out) {
+    const long long c = xcd_node();
+    if (c >= g.nn) return;
+    int i, j, k;
+    node_ijk(g, c, i, j, k);
+    uint8_t m = 0;
+    for (int d = -D; d <= D; ++d)
+        m |= axis == 1 ? in[gidx(g, i, wrapi(j + d, g.ny), k)] : in[gidx(g, i, j, wrapi(k + d, g.nz))];
+    out[c] = m;
+}
+__global__ void __launch_bounds__(BS)
+k_dilate_apply(GridP g, SwitchP P, const uint8_t *__restrict__ in, uint8_t *__restrict__ sw,
+               uint8_t *__restrict__ calm) {
+    const long long c = xcd_node();
+    if (c >= g.nn) return;
+    int i, j, k;
+    node_ijk(g, c, i, j, k);
+    const int nxn = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
     if (i >= nxn) return;
-    const int D = P.dilation;
-    int kin = 0, warm = 0;
-    for (int dk = -D; dk <= D && !kin; ++dk)
-        for (int dj = -D; dj <= D; ++dj) {
-            const long long row = gidx(g, 0, wrapi(j + dj, g.ny), wrapi(k + dk, g.nz));
-            for (int di = -D; di <= D; ++di) {
-                int ii = i + di;
-                if (!per && (ii < 0 || ii > g.nx)) continue;
-                if (per) ii = wrapi(ii, g.nx);
-                kin |= hot[row + ii];
-                warm |= notcold[row + ii];
-            }
-        }
+    uint8_t m = 0;
+    for (int d = -P.dilation; d <= P.dilation; ++d) m |= in[gidx(g, i, j, wrapi(k + d, g.nz))];
+    const int kin = m & 1, warm = m & 2;
     if (kin) { sw[c] = 1; calm[c] = 0; }
     else if (sw[c]) {
         if (warm) calm[c] = 0;
@@ -486,14 +511,14 @@ k_absorb_finish(GridP g, real mass, double *__restrict__ macc, real *__restrict_
                 real *__restrict__ ux, real *__restrict__ uy, real *__restrict__ uz, WarmP wp,
                 double *__restrict__ ledger, const int *__restrict__ xr) {
     // only the x range of this step's absorptions (xr[4..5]) has entries: the
-    // grid strides over the node columns of that range alone
+    // grid strides over the node columns of that range alone, x fastest
     const int lo = xr[4], hi = xr[5];
     if (hi < lo) return;
     double dsum = 0;
-    // a block per (y, z) row at a time, its threads along x
-    for (int row = blockIdx.x; row < g.ny * g.nz; row += gridDim.x)
-    for (int i = lo + (int)threadIdx.x; i <= hi; i += BS) {
-    const long long c = gidx(g, i, row % g.ny, row / g.ny);
+    const unsigned w = (unsigned)(hi - lo + 1), total = w * (unsigned)g.ny * (unsigned)g.nz;
+    for (unsigned t = blockIdx.x * BS + threadIdx.x; t < total; t += gridDim.x * BS) {
+    const unsigned row = t / w;
+    const long long c = (long long)(lo + (int)(t - row * w)) + (long long)row * g.sx;
     if (macc[c] > 0.0) {
         const long long nn = g.nn;
         const double dv = g.ddx * g.ddy * g.ddz;
@@ -636,22 +661,31 @@ k_spawn_find(GridP g, const uint8_t *__restrict__ sw, const real *__restrict__ n
     const int nxn = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
     const int lo = max(xr[0], 0), hi = min(xr[1], nxn - 1);
     if (hi < lo) return;
-    // a block per (y, z) row at a time, its threads along x
-    for (int row = blockIdx.x; row < g.ny * g.nz; row += gridDim.x)
-    for (int i0 = lo; i0 <= hi; i0 += BS) {
-        const int i = i0 + (int)threadIdx.x;
+    // one list atomic per block and turn: atomics on one address serialize
+    // across the chip (about 10 ns each), so waves pool their counts in LDS
+    __shared__ int s_off[BS / 64 + 1];
+    const int lane = __lane_id(), wv = threadIdx.x >> 6;
+    const unsigned w = (unsigned)(hi - lo + 1), total = w * (unsigned)g.ny * (unsigned)g.nz;
+    for (unsigned t0 = blockIdx.x * BS; t0 < total; t0 += gridDim.x * BS) {
+        const unsigned t = t0 + threadIdx.x;
         bool want = false;
         long long c = 0;
-        if (i <= hi) {
-            c = gidx(g, i, row % g.ny, row / g.ny);
+        if (t < total) {
+            const unsigned row = t / w;
+            c = (long long)(lo + (int)(t - row * w)) + (long long)row * g.sx;
             want = sw[c] && n[c] * (g.dx * g.dy * g.dz) >= wmin && n[c] > (real)0;
         }
         const uint64_t b = __ballot(want);
-        if (!b) continue;
-        int base = 0;
-        if (__lane_id() == 0) base = atomicAdd(list_n, __popcll(b));
-        base = __shfl(base, 0);
-        if (want) list[base + __popcll(b & ((1ull << __lane_id()) - 1ull))] = (int)c;
+        if (lane == 0) s_off[wv] = __popcll(b);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int q = 0; q < BS / 64; ++q) { const int k = s_off[q]; s_off[q] = tot; tot += k; }
+            s_off[BS / 64] = tot ? atomicAdd(list_n, tot) : 0;
+        }
+        __syncthreads();
+        if (want) list[s_off[BS / 64] + s_off[wv] + __popcll(b & ((1ull << lane) - 1ull))] = (int)c;
+        __syncthreads();
     }
 }
 
@@ -714,21 +748,23 @@ void launch_label_or(long long n, const uint8_t *cond, uint8_t *y, hipStream_t s
     k_label_or<<<blocks(n), BS, 0, s>>>(n, cond, y);
 }
 void launch_dilate_nodes(const GridP &g, const SwitchP &P, const uint8_t *hot, const uint8_t *notcold,
-                         uint8_t *sw, uint8_t *calm, hipStream_t s) {
-    k_dilate<<<xcd_blocks(g.nn), BS, 0, s>>>(g, P, hot, notcold, sw, calm);
+                         uint8_t *sw, uint8_t *calm, uint8_t *tmp, hipStream_t s) {
+    const unsigned nb = xcd_blocks(g.nn);
+    k_dilate_x<<<nb, BS, 0, s>>>(g, P.dilation, hot, notcold, tmp);
+    k_dilate_yz<<<nb, BS, 0, s>>>(g, P.dilation, 1, tmp, tmp + g.nn);
+    k_dilate_apply<<<nb, BS, 0, s>>>(g, P, tmp + g.nn, sw, calm);
 }
 void launch_absorb_finish_nodes(const GridP &g, real mass, double *macc, real *n, real *ux,
                                 real *uy, real *uz, WarmP w, double *ledger, const int *xr, hipStream_t s) {
-    const unsigned rows = (unsigned)(g.ny * g.nz), nb = rows < 4096u ? rows : 4096u;
-    k_absorb_finish<<<nb, BS, 0, s>>>(g, mass, macc, n, ux, uy, uz, w, ledger, xr);
+    // few blocks: each adds its energy sum to the ledger with one atomic
+    k_absorb_finish<<<512, BS, 0, s>>>(g, mass, macc, n, ux, uy, uz, w, ledger, xr);
 }
 void launch_spawn_nodes(const GridP &g, const SpecP &sp, int isp, const uint8_t *sw, real *n, real *ux,
                         real *uy, real *uz, WarmP w, jglob_t *jg, real wmin, real w0, uint64_t seed,
                         int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
                         unsigned *wmax_bits, unsigned *umax2, double *ledger, int *list, int *list_n,
                         const int *xr, hipStream_t s) {
-    const unsigned rows = (unsigned)(g.ny * g.nz), nb = rows < 4096u ? rows : 4096u;
-    k_spawn_find<<<nb, BS, 0, s>>>(g, sw, n, wmin, list, list_n, xr);
+    k_spawn_find<<<1024, BS, 0, s>>>(g, sw, n, wmin, list, list_n, xr);
     k_spawn<<<1024, BS, 0, s>>>(g, sp, isp, n, ux, uy, uz, w, jg, jg + g.nn, jg + 2 * g.nn, w0, seed, step,
                                 inbox, inbox_n, inbox_cap, deferred, wmax_bits, umax2, ledger, list, list_n);
 }
