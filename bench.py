@@ -790,13 +790,14 @@ def main():
         "device_memory_peak_gb_allpic": round(p["peak_gb"], 1),
     }
     # the field update (Yee, Mur walls, antenna) of the all-PIC run, from its
-    # HIP-event phase timer; algorithmic bytes per cell and step: read E, B and
-    # write B, then read E, B, J and write E (84 B)
+    # HIP-event phase timer; algorithmic bytes per cell and step: read E, B, J
+    # and write E, B once (60 B), plus the particle current's 64-bit sums read
+    # once (24 B): 84 B
     f_ms = p["timers"]["fields_ms"] / K
     yee_gbs = 84 * cells / (f_ms * 1e-3) / 1e9 if f_ms > 0 else 0.0
     out["roofline_yee"] = {"bound": "hbm", "achieved": round(yee_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(yee_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                           "kernel": "k_jconvert + k_b_half x2 + k_e_full + k_mur_save + k_mur_apply + k_antenna",
+                           "kernel": "k_jconvert + k_yee_step + k_antenna",
                            "ms_per_step": round(f_ms, 4), "alg_bytes_per_step": 84 * cells}
     if not args.no_extras:
         out["fp64_error"] = fp64_error()

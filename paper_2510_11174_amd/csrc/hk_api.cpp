@@ -98,6 +98,8 @@ struct hk_sim {
     DevSpecies sp[HK_MAX_SPECIES];
     hipStream_t s = nullptr;
     real *fblock = nullptr;      // the 9 field arrays, contiguous
+    real *falt = nullptr;        // a second set of E and B: the fused field update writes there
+    real *f_alt[6] = {};         // and the two sets swap (f[0..5] is always the current one)
     real *f[9]{};
     jglob_t *jg = nullptr;       // particle current of the step (3 arrays), zero between steps
     real *mur_old = nullptr;
@@ -989,9 +991,13 @@ int one_step(hk_sim *S) {
     }
     // the particles' current (deposits and conversion moves) joins J
     launch_jconvert(g, S->jg, S->f, s);
-    launch_yee_b_half(g, S->f, s);
-    launch_yee_e_full(g, S->f, S->mur_old, s);
-    launch_yee_b_half(g, S->f, s);
+    if (S->falt && launch_yee_step(g, S->f, S->f_alt, s)) {
+        for (int c = 0; c < 6; ++c) std::swap(S->f[c], S->f_alt[c]);
+    } else {
+        launch_yee_b_half(g, S->f, s);
+        launch_yee_e_full(g, S->f, S->mur_old, s);
+        launch_yee_b_half(g, S->f, s);
+    }
     time_mark(S, 4);
     rc = merge_finish(S);
     if (rc) return rc;
@@ -1348,6 +1354,7 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
     g.ddx = grid->dx; g.ddy = grid->dy; g.ddz = grid->dz; g.ddt = grid->dt;
     int rc = HK_OK;
     S->fblock = (real *)dalloc(S, sizeof(real) * 9 * (size_t)g.nn);
+    S->falt = (real *)dalloc(S, sizeof(real) * 6 * (size_t)g.nn);
     S->jg = (jglob_t *)dalloc(S, sizeof(jglob_t) * 3 * (size_t)g.nn);
     S->mur_old = (real *)dalloc(S, sizeof(real) * 8 * (size_t)g.ny * g.nz);
     S->sw = (uint8_t *)dalloc(S, (size_t)g.nn);
@@ -1368,13 +1375,14 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
         S->h_status = nullptr;
     if (hipEventCreateWithFlags(&S->status_ev, hipEventDisableTiming) != hipSuccess)
         S->status_ev = nullptr;
-    if (!S->fblock || !S->jg || !S->mur_old || !S->sw || !S->calm || !S->gauss0 || !S->tmp_a || !S->tmp_b ||
+    if (!S->fblock || !S->falt || !S->jg || !S->mur_old || !S->sw || !S->calm || !S->gauss0 || !S->tmp_a || !S->tmp_b ||
         !S->dsum || !S->ledger || !S->status || !S->h_status || !S->dstat || !S->wmax ||
         !S->plan || !S->plan_ctl || !S->status_ev) {
         hk_destroy(S);
         return HK_ENOMEM;
     }
     for (int c = 0; c < 9; ++c) S->f[c] = S->fblock + (size_t)c * g.nn;
+    for (int c = 0; c < 6; ++c) S->f_alt[c] = S->falt + (size_t)c * g.nn;
     (void)hipMemsetAsync(S->sw, run->switch_mode == HK_SW_ALL_FLUID ? 0 : 1, (size_t)g.nn, S->s);
     for (int i = 0; i < nspecies; ++i) {
         DevSpecies &D = S->sp[i];
@@ -1847,7 +1855,9 @@ int hk_save(hk_sim *S, const char *path) {
     for (int i = 0; i < S->nsp; ++i) F.put(S->sp[i].d.kind);
     F.put(S->step); F.put(S->t); F.put(S->have_gauss0);
     int rc;
-    if ((rc = ck_dev_out(S, F, S->fblock, sizeof(real) * 9 * (size_t)g.nn))) return rc;
+    // the nine field arrays in component order (the current E and B set)
+    for (int c = 0; c < 9; ++c)
+        if ((rc = ck_dev_out(S, F, S->f[c], sizeof(real) * (size_t)g.nn))) return rc;
     if ((rc = ck_dev_out(S, F, S->mur_old, sizeof(real) * 8 * (size_t)g.ny * g.nz))) return rc;
     if ((rc = ck_dev_out(S, F, S->sw, (size_t)g.nn))) return rc;
     if ((rc = ck_dev_out(S, F, S->calm, (size_t)g.nn))) return rc;
@@ -1896,7 +1906,8 @@ int hk_save(hk_sim *S, const char *path) {
 static int load_body(hk_sim *S, CkFile &F, const char *path, const GridP &g, int nsp, int64_t step, double t,
                      int have_g0) {
     int rc;
-    if ((rc = ck_dev_in(S, F, S->fblock, sizeof(real) * 9 * (size_t)g.nn))) return rc;
+    for (int c = 0; c < 9; ++c)
+        if ((rc = ck_dev_in(S, F, S->f[c], sizeof(real) * (size_t)g.nn))) return rc;
     if ((rc = ck_dev_in(S, F, S->mur_old, sizeof(real) * 8 * (size_t)g.ny * g.nz))) return rc;
     if ((rc = ck_dev_in(S, F, S->sw, (size_t)g.nn))) return rc;
     if ((rc = ck_dev_in(S, F, S->calm, (size_t)g.nn))) return rc;

@@ -226,6 +226,10 @@ void launch_zero(void *p, size_t bytes, hipStream_t s);
 void launch_fill32(void *p, size_t n, uint32_t v, hipStream_t s);   // n 32-bit words
 void launch_yee_b_half(const GridP &g, real *const f[9], hipStream_t s);
 void launch_yee_e_full(const GridP &g, real *const f[9], real *mur_old, hipStream_t s);
+// The step's whole field update (B half, E full with the Mur walls, B half)
+// in one pass from f[0..5] (E, B) and f[6..8] (J) into out[0..5]; false
+// (nothing launched) where the fused pass does not apply.
+bool launch_yee_step(const GridP &g, real *const f[9], real *const out[6], hipStream_t s);
 void launch_antenna(const GridP &g, const hk_laser_desc &L, double t, real *jy, real *jz,
                     hipStream_t s);
 void launch_divE(const GridP &g, real *const f[9], double *out, hipStream_t s);
