@@ -516,10 +516,20 @@ k_absorb_finish(GridP g, real mass, double *__restrict__ macc, real *__restrict_
     if (hi < lo) return;
     double dsum = 0;
     const unsigned w = (unsigned)(hi - lo + 1), total = w * (unsigned)g.ny * (unsigned)g.nz;
-    for (unsigned t = blockIdx.x * BS + threadIdx.x; t < total; t += gridDim.x * BS) {
-    const unsigned row = t / w;
-    const long long c = (long long)(lo + (int)(t - row * w)) + (long long)row * g.sx;
-    if (macc[c] > 0.0) {
+    // four nodes per thread and turn, their accumulators loaded together
+    // (the scan is bound by load latency; few nodes have entries)
+    constexpr int AF_U = 4;
+    for (unsigned t0 = blockIdx.x * (AF_U * BS) + threadIdx.x; t0 < total; t0 += gridDim.x * (AF_U * BS)) {
+    long long cs[AF_U];
+    double ms[AF_U];
+    for (int u = 0; u < AF_U; ++u) {
+        const unsigned t = t0 + u * BS, row = t / w;
+        cs[u] = (long long)(lo + (int)(t - row * w)) + (long long)row * g.sx;
+        ms[u] = t < total ? macc[cs[u]] : 0.0;
+    }
+    for (int u = 0; u < AF_U; ++u) {
+    const long long c = cs[u];
+    if (ms[u] > 0.0) {
         const long long nn = g.nn;
         const double dv = g.ddx * g.ddy * g.ddz;
         double m0 = (double)n[c] * dv;
@@ -550,6 +560,7 @@ k_absorb_finish(GridP g, real mass, double *__restrict__ macc, real *__restrict_
         ux[c] = (real)un[0]; uy[c] = (real)un[1]; uz[c] = (real)un[2];
         for (int q = 0; q < 5; ++q) macc[q * nn + c] = 0.0;
         dsum += d;
+    }
     }
     }
     block_add_d(dsum, ledger);
@@ -662,29 +673,44 @@ k_spawn_find(GridP g, const uint8_t *__restrict__ sw, const real *__restrict__ n
     const int lo = max(xr[0], 0), hi = min(xr[1], nxn - 1);
     if (hi < lo) return;
     // one list atomic per block and turn: atomics on one address serialize
-    // across the chip (about 10 ns each), so waves pool their counts in LDS
-    __shared__ int s_off[BS / 64 + 1];
+    // across the chip (about 10 ns each), so waves pool their counts in LDS.
+    // A turn covers SF_U nodes per thread, loaded together: the search is
+    // bound by the latency of its loads, not by their bytes.
+    constexpr int SF_U = 4;
+    __shared__ int s_off[SF_U * (BS / 64) + 1];
     const int lane = __lane_id(), wv = threadIdx.x >> 6;
     const unsigned w = (unsigned)(hi - lo + 1), total = w * (unsigned)g.ny * (unsigned)g.nz;
-    for (unsigned t0 = blockIdx.x * BS; t0 < total; t0 += gridDim.x * BS) {
-        const unsigned t = t0 + threadIdx.x;
-        bool want = false;
-        long long c = 0;
-        if (t < total) {
+    const real dv = g.dx * g.dy * g.dz;
+    for (unsigned t0 = blockIdx.x * (SF_U * BS); t0 < total; t0 += gridDim.x * (SF_U * BS)) {
+        long long c[SF_U];
+        uint8_t sv[SF_U];
+        for (int u = 0; u < SF_U; ++u) {
+            const unsigned t = t0 + u * BS + threadIdx.x;
             const unsigned row = t / w;
-            c = (long long)(lo + (int)(t - row * w)) + (long long)row * g.sx;
-            want = sw[c] && n[c] * (g.dx * g.dy * g.dz) >= wmin && n[c] > (real)0;
+            c[u] = (long long)(lo + (int)(t - row * w)) + (long long)row * g.sx;
+            sv[u] = t < total ? sw[c[u]] : 0;
         }
-        const uint64_t b = __ballot(want);
-        if (lane == 0) s_off[wv] = __popcll(b);
+        bool want[SF_U];
+        for (int u = 0; u < SF_U; ++u) {
+            const real nc = sv[u] ? n[c[u]] : (real)0;
+            want[u] = sv[u] && nc * dv >= wmin && nc > (real)0;
+        }
+        uint64_t b[SF_U];
+        for (int u = 0; u < SF_U; ++u) {
+            b[u] = __ballot(want[u]);
+            if (lane == 0) s_off[u * (BS / 64) + wv] = __popcll(b[u]);
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             int tot = 0;
-            for (int q = 0; q < BS / 64; ++q) { const int k = s_off[q]; s_off[q] = tot; tot += k; }
-            s_off[BS / 64] = tot ? atomicAdd(list_n, tot) : 0;
+            for (int q = 0; q < SF_U * (BS / 64); ++q) { const int k = s_off[q]; s_off[q] = tot; tot += k; }
+            s_off[SF_U * (BS / 64)] = tot ? atomicAdd(list_n, tot) : 0;
         }
         __syncthreads();
-        if (want) list[s_off[BS / 64] + s_off[wv] + __popcll(b & ((1ull << lane) - 1ull))] = (int)c;
+        for (int u = 0; u < SF_U; ++u)
+            if (want[u])
+                list[s_off[SF_U * (BS / 64)] + s_off[u * (BS / 64) + wv] + __popcll(b[u] & ((1ull << lane) - 1ull))] =
+                    (int)c[u];
         __syncthreads();
     }
 }
@@ -764,7 +790,7 @@ void launch_spawn_nodes(const GridP &g, const SpecP &sp, int isp, const uint8_t 
                         int step, PArr inbox, int *inbox_n, int inbox_cap, int *deferred,
                         unsigned *wmax_bits, unsigned *umax2, double *ledger, int *list, int *list_n,
                         const int *xr, hipStream_t s) {
-    k_spawn_find<<<1024, BS, 0, s>>>(g, sw, n, wmin, list, list_n, xr);
+    k_spawn_find<<<2048, BS, 0, s>>>(g, sw, n, wmin, list, list_n, xr);
     k_spawn<<<1024, BS, 0, s>>>(g, sp, isp, n, ux, uy, uz, w, jg, jg + g.nn, jg + 2 * g.nn, w0, seed, step,
                                 inbox, inbox_n, inbox_cap, deferred, wmax_bits, umax2, ledger, list, list_n);
 }
