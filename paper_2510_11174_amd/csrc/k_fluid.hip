@@ -10,10 +10,11 @@
 //   1. us = Boris(u; E, B interpolated to the node); a warm species then
 //      takes the pressure force, us -= dt grad p / (m n) at nodes above the
 //      density floor (p = S n^(ga-1), zero where n = 0; central differences,
-//      one-sided at the open x walls; non-relativistic); v = us / gamma(us);
-//      both stored only where n > 0 (nothing else reads them)
+//      one-sided at the open x walls; non-relativistic), stored only where
+//      n > 0 (nothing else reads it)
 //   2. on the face between node c and its +d neighbour: face velocity = mean
-//      of the two nodes (or that of the only side above the density floor),
+//      of the two nodes' v = us / gamma(us) (or that of the only side above
+//      the density floor),
 //      mass flux F = v_f n_donor, momentum flux G = F us_donor, entropy flux
 //      H = F K_donor (warm, K = S / n); each node evaluates its six faces
 //      itself (a face shared by two nodes gives both the same bits), then
@@ -174,12 +175,14 @@ __device__ inline void fluid_lorentz_node(const GridP &g, real qm, real mass, re
         const real rmn = g.dt / (mass * nc);
         for (int d = 0; d < 3; ++d) us[d] = us[d] - grad[d] * rmn;
     }
-    const real rgam = (real)1 / sqrt((real)1 + us[0] * us[0] + us[1] * us[1] + us[2] * us[2]);
     const long long nn = g.nn;
-    for (int d = 0; d < 3; ++d) {
-        sc[d * nn + c] = us[d];
-        sc[(3 + d) * nn + c] = us[d] * rgam;
-    }
+    for (int d = 0; d < 3; ++d) sc[d * nn + c] = us[d];
+}
+
+// v = us / gamma(us), recomputed by the update from the us it reads (the
+// same expression at every node, so the same bits wherever it is formed)
+__device__ inline real rgamma_of(const real u[3]) {
+    return (real)1 / sqrt((real)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
 }
 
 __global__ void __launch_bounds__(BS)
@@ -262,11 +265,9 @@ __device__ inline void fluid_update_node(const GridP &g, real q, real n_floor, c
     for (int m = 0; m < 3; ++m) C.us[m] = us[m][c];
     real vc[3], Sc = 0, Sp[3] = {0, 0, 0}, Sm[3] = {0, 0, 0};
     for (int d = 0; d < 3; ++d) {
-        const real *vd = sc + (3 + d) * nn;
-        vc[d] = vd[c];
         const int pp = hasp[d] ? pl[d] : c, mm = hasm[d] ? mi[d] : c;
-        P[d].n = np[d]; P[d].ok = hasp[d] && fok(np[d]); P[d].v = vd[pp];
-        M[d].n = nm[d]; M[d].ok = hasm[d] && fok(nm[d]); M[d].v = vd[mm];
+        P[d].n = np[d]; P[d].ok = hasp[d] && fok(np[d]);
+        M[d].n = nm[d]; M[d].ok = hasm[d] && fok(nm[d]);
         for (int m = 0; m < 3; ++m) {
             P[d].us[m] = us[m][pp];
             M[d].us[m] = us[m][mm];
@@ -277,6 +278,13 @@ __device__ inline void fluid_update_node(const GridP &g, real q, real n_floor, c
         }
     }
     if (S) Sc = S[c];
+    // the normal velocity of each side (the pass before stores us only)
+    const real rgc = rgamma_of(C.us);
+    for (int d = 0; d < 3; ++d) {
+        vc[d] = C.us[d] * rgc;
+        P[d].v = P[d].us[d] * rgamma_of(P[d].us);
+        M[d].v = M[d].us[d] * rgamma_of(M[d].us);
+    }
     real dn = 0, dm[3] = {0, 0, 0}, fplus[3], ds = 0;
     for (int d = 0; d < 3; ++d) {
         C.v = vc[d];
@@ -367,7 +375,8 @@ __global__ void k_fluid_window_commit(int *xr, int empty_lo) {
 
 }  // namespace
 
-// scratch: 7 grid arrays (us, v, and the pressure of a warm species); nout
+// scratch: 7 grid arrays (us in the first three, the pressure of a warm
+// species in the seventh); nout
 // and Sout receive the new density and entropy density (every node of the
 // window, so the caller can swap them in); xr: the species' x window
 void launch_fluid(const GridP &g, const SpecP &sp, const real *n, real *ux, real *uy, real *uz, WarmP w,
