@@ -104,6 +104,26 @@ def test_hundred_steps_c1(hk, oracle_mod, prec):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("nx", [29, 30])
+def test_field_update_both_forms(hk, oracle_mod, prec, nx):
+    # the field update runs as one fused pass, except in an open box whose nx
+    # is a multiple of the fused pass's 29-node tile, where it runs as three
+    # passes: both against the oracle, with the laser and a thermal plasma,
+    # from random fields (the Mur walls see non-zero values from the start)
+    cfg = _c1(bc="open", laser=True, u_th=0.05, nx=nx, ny=16, nz=8)
+    g, o = _pair(hk, oracle_mod, cfg, prec)
+    rng = np.random.default_rng(11)
+    for c in ["ex", "ey", "ez", "bx", "by", "bz"]:
+        a = rng.normal(0, 0.02, o.shape)
+        g.set_field(c, a.astype(g.real)); o.set_field(c, a.astype(g.real).astype(np.float64))
+    g.step(40); o.step(40)
+    vec = {f: rel_l2(np.stack([g.get_field(f + c) for c in "xyz"]),
+                     np.stack([o.get_field(f + c) for c in "xyz"])) for f in "eb"}
+    print("nx %d:" % nx, {k: "%.1e" % v for k, v in vec.items()})
+    assert max(vec.values()) <= (1e-4 if prec == "f32" else 1e-11)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_gauss_law_preserved(hk, oracle_mod, prec):
     cfg = _c1(bc="open", laser=False, u_th=0.2, nx=16, ny=8, nz=8)
     g = hk.Sim(cfg, precision=prec)
