@@ -567,24 +567,28 @@ k_absorb_finish(GridP g, real mass, double *__restrict__ macc, real *__restrict_
 }
 
 // Spawn of node c (kinetic, fluid mass >= wmin).
-__device__ inline void spawn_node(const GridP &g, const SpecP &sp, int isp, long long c, real *__restrict__ n,
-                                  real *__restrict__ ux, real *__restrict__ uy, real *__restrict__ uz,
-                                  const WarmP &wp, jglob_t *__restrict__ Jx, jglob_t *__restrict__ Jy,
-                                  jglob_t *__restrict__ Jz, real w0, uint64_t seed, int step, const PArr &inbox,
-                                  int *__restrict__ inbox_n, int inbox_cap, int *__restrict__ deferred,
+// Particles a node of fluid mass `mass` becomes: about the reference weight
+// each, at least one and at most 64.
+__device__ inline int spawn_count(real mass, real w0) {
+    const double mr = w0 > (real)0 ? floor((double)mass / (double)w0 + 0.5) : 1.0;
+    return mr < 1.0 ? 1 : (mr > 64.0 ? 64 : (int)mr);
+}
+
+// The node's m particles go to inbox slots k0 .. k0 + m - 1 (reserved by the
+// caller); nc is the node's fluid density.
+__device__ inline void spawn_node(const GridP &g, const SpecP &sp, int isp, long long c, real nc, int m, int k0,
+                                  real *__restrict__ n, real *__restrict__ ux, real *__restrict__ uy,
+                                  real *__restrict__ uz, const WarmP &wp, jglob_t *__restrict__ Jx,
+                                  jglob_t *__restrict__ Jy, jglob_t *__restrict__ Jz, uint64_t seed, int step,
+                                  const PArr &inbox, int inbox_cap, int *__restrict__ deferred,
                                   unsigned *__restrict__ wmax_bits, unsigned *__restrict__ umax2,
                                   double *__restrict__ ledger) {
     int i, j, k;
     node_ijk(g, c, i, j, k);
     const int per = g.bcx == HK_BC_PERIODIC;
     const int nxn = per ? g.nx : g.nx + 1;
-    const real nc = n[c];
     const real dv = g.dx * g.dy * g.dz;
     const real mass = nc * dv;
-    // particles in proportion to the mass: about the reference weight each
-    const double mr = w0 > (real)0 ? floor((double)mass / (double)w0 + 0.5) : 1.0;
-    const int m = mr < 1.0 ? 1 : (mr > 64.0 ? 64 : (int)mr);
-    int k0 = atomicAdd(inbox_n, m);
     if (k0 + m > inbox_cap) {
         // no room this step: the node stays fluid; void the reserved slots
         for (int q = k0; q < inbox_cap && q < k0 + m; ++q) inbox.cell[q] = -1;
@@ -729,9 +733,30 @@ k_spawn(GridP g, SpecP sp, int isp, real *__restrict__ n, real *__restrict__ ux,
         unsigned *__restrict__ wmax_bits, unsigned *__restrict__ umax2, double *__restrict__ ledger,
         const int *__restrict__ list, const int *__restrict__ list_n) {
     const int nl = *list_n;
-    for (int e = blockIdx.x * BS + threadIdx.x; e < nl; e += gridDim.x * BS)
-        spawn_node(g, sp, isp, list[e], n, ux, uy, uz, wp, Jx, Jy, Jz, w0, seed, step, inbox, inbox_n,
-                   inbox_cap, deferred, wmax_bits, umax2, ledger);
+    const int lane = __lane_id();
+    const real dv = g.dx * g.dy * g.dz;
+    // the lanes of a wave take consecutive list entries and reserve their
+    // inbox slots with one atomic: a scan of the counts over the wave (an
+    // atomic per node on the one counter would serialize, about 10 ns each)
+    for (int eb = blockIdx.x * BS + threadIdx.x - lane; eb < nl; eb += gridDim.x * BS) {
+        const int e = eb + lane;
+        const bool on = e < nl;
+        const long long c = on ? list[e] : 0;
+        const real nc = on ? n[c] : (real)0;
+        const int m = on ? spawn_count(nc * dv, w0) : 0;
+        int incl = m;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+        }
+        const int tot = __shfl(incl, 63);
+        int base = 0;
+        if (lane == 0 && tot) base = atomicAdd(inbox_n, tot);
+        base = __shfl(base, 0);
+        if (on)
+            spawn_node(g, sp, isp, c, nc, m, base + incl - m, n, ux, uy, uz, wp, Jx, Jy, Jz, seed, step, inbox,
+                       inbox_cap, deferred, wmax_bits, umax2, ledger);
+    }
 }
 inline unsigned blocks(long long n) { return (unsigned)((n + BS - 1) / BS); }
 inline unsigned xcd_blocks(long long n) { return (blocks(n) + 7u) & ~7u; }
