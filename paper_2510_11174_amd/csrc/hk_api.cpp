@@ -309,26 +309,55 @@ int rebuild(hk_sim *S, int isp, bool use_tiles, PArr *lists, int **list_n, const
     std::vector<int> cap(nt), mcap(nt);
     long long total = 0, mtotal = 0;
     int maxc = 0;
-    for (int t = 0; t < nt; ++t) {
-        long long c = factor * std::max<long long>(h[t], tfloor) + 256;
-        long long hc = hint_per_tile + hint_per_tile / 4 + 128;
-        c = std::max(c, std::min<long long>(hc, INT_MAX / 4));
-        c = (c + 63) & ~63LL;
-        off[t] = total;
-        cap[t] = (int)c;
-        total += c;
-        maxc = std::max(maxc, (int)c);
-        long long m = (c / 4 + 63) & ~63LL;
-        moff[t] = mtotal;
-        mcap[t] = (int)m;
-        mtotal += m;
-    }
+    // Lay the bins out with a fraction sg of each tile's headroom above its
+    // count (1: the capacity above); below 1 a tile keeps at least a quarter
+    // of its count and 256 slots of room, and its reserve hint share.
+    auto lay = [&](double sg) {
+        total = mtotal = 0;
+        maxc = 0;
+        for (int t = 0; t < nt; ++t) {
+            long long c = factor * std::max<long long>(h[t], tfloor) + 256;
+            long long hc = hint_per_tile + hint_per_tile / 4 + 128;
+            c = std::max(c, std::min<long long>(hc, INT_MAX / 4));
+            if (sg < 1.0) {
+                const long long lo = std::max<long long>(h[t] + h[t] / 4 + 256, std::min(c, hc));
+                c = std::max(lo, h[t] + (long long)std::ceil(sg * (double)(c - h[t])));
+            }
+            c = (c + 63) & ~63LL;
+            off[t] = total;
+            cap[t] = (int)c;
+            total += c;
+            maxc = std::max(maxc, (int)c);
+            long long m = (c / 4 + 63) & ~63LL;
+            moff[t] = mtotal;
+            mcap[t] = (int)m;
+            mtotal += m;
+        }
+        return total + (D.d.mobile ? mtotal : 0);
+    };
     // each bin buffer carries the per-tile mover regions after its bins.  The
     // spare buffer (the push's output, idle now) takes the scatter when it is
-    // large enough; otherwise both are allocated anew with a quarter of
-    // slack, so that re-binning a large species rarely allocates
-    const long long slots = total + (D.d.mobile ? mtotal : 0);
-    const bool reuse = D.alloc_slots >= slots && D.buf[1 - D.cur].cell != nullptr;
+    // large enough, with less headroom in every tile if need be (a bin that
+    // fills up sooner costs a re-bin, milliseconds; a new pair of buffers of a
+    // large species costs a fraction of a second of allocation); otherwise both
+    // are allocated anew with a quarter of slack, so that re-binning a large
+    // species rarely allocates
+    long long slots = lay(1.0);
+    const bool spare = D.buf[1 - D.cur].cell != nullptr;
+    if (spare && slots > D.alloc_slots) {
+        if (lay(0.0) <= D.alloc_slots) {
+            double a = 0.0, b = 1.0;
+            for (int it = 0; it < 24; ++it) {
+                const double m = 0.5 * (a + b);
+                if (lay(m) <= D.alloc_slots) a = m;
+                else b = m;
+            }
+            slots = lay(a);
+        } else {
+            slots = lay(1.0);
+        }
+    }
+    const bool reuse = spare && D.alloc_slots >= slots;
     PArr nbuf[2];
     if (!reuse) {
         const long long n_alloc = slots + (large ? slots / 8 : slots / 4);
@@ -433,7 +462,11 @@ int raise_wmax(hk_sim *S, int isp, double w) {
 int ensure_inbox(hk_sim *S, int isp, long long need) {
     DevSpecies &D = S->sp[isp];
     if (need <= D.inbox_cap) return HK_OK;
-    long long c = std::max<long long>(need, 2LL * D.inbox_cap);
+    // an eighth of room beyond the need, so that the few percent a re-bin adds
+    // to the capacity do not allocate again (a new inbox and fail list of a
+    // large species, gigabytes, cost a fraction of a second); small lists double
+    long long c = need + need / 8;
+    if (D.inbox_cap < (1 << 20)) c = std::max<long long>(c, 2LL * D.inbox_cap);
     c = std::min<long long>(c, INT_MAX / 2);
     free_parr(S, D.inbox);
     free_parr(S, D.fail);
@@ -964,12 +997,10 @@ int one_step(hk_sim *S) {
         }
     }
     time_mark(S, 1);
-    // 4. newborn and overflow particles join their bins; 5. cold fluid (it
-    // does not read the bins, so it runs while the host waits for the status);
-    // 6. conversion; 7. fields (likewise before the second status wait)
-    int rc = merge_launch(S);
-    if (rc) return rc;
-    time_mark(S, 5);
+    // 4. cold fluid and 5. conversion (neither reads the bins: spawned particles
+    // go to the inboxes behind the push's products); 6. newborn and overflow
+    // particles join their bins; 7. fields, enqueued before the host waits for
+    // the status of the merge
     if (hybrid) {
         for (int isp = 0; isp < S->nsp; ++isp) {
             DevSpecies &D = S->sp[isp];
@@ -980,15 +1011,12 @@ int one_step(hk_sim *S) {
             if (D.fs) std::swap(D.fs, D.fs2);
         }
         time_mark(S, 2);
-        rc = merge_finish(S);
-        if (rc) return rc;
-        time_mark(S, 5);
         reconcile(S);
         time_mark(S, 3);
-        rc = merge_launch(S);
-        if (rc) return rc;
-        time_mark(S, 5);
     }
+    int rc = merge_launch(S);
+    if (rc) return rc;
+    time_mark(S, 5);
     // the particles' current (deposits and conversion moves) joins J
     launch_jconvert(g, S->jg, S->f, s);
     if (S->falt && launch_yee_step(g, S->f, S->f_alt, s)) {

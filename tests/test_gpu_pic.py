@@ -159,6 +159,38 @@ def test_dense_tiles_split_over_workgroups(hk, oracle_mod, prec):
     assert_cells(cells, tol, 2e-4 if prec == "f32" else None)
 
 
+def test_bins_overflow_and_rebin(hk, oracle_mod):
+    # 40000 electrons spread evenly over a 24^3 box (3^3 tiles of 8^3 cells)
+    # fall towards the middle of the centre tile and are 90% focused after 40
+    # steps.  The centre tile's count passes its bin capacity twice (about
+    # steps 15 and 25): the particles that miss it go to the fail list and
+    # the end of the step re-bins the species, the second time with less
+    # headroom per tile, since the layout the counts ask for no longer fits
+    # the buffers allocated for the even spread.  The oracle has no bins.
+    cfg = _c1(bc="periodic", laser=False, nx=24, ny=24, nz=24)
+    cfg["species"][0]["profile"] = "none"
+    g, o = _pair(hk, oracle_mod, cfg, "f64")
+    g.enable_timing(True)
+    rng = np.random.default_rng(17)
+    n, steps = 40000, 40
+    dx = cfg["grid"]["dx"]
+    x = rng.uniform(0, 24 * dx, (n, 3))
+    v = -0.9 * (x - 12.5 * dx) / (steps * cfg["grid"]["dt"])
+    u = v / np.sqrt(1 - (v ** 2).sum(1))[:, None]
+    w = np.full(n, 1e-7)
+    ids = np.arange(n, dtype=np.uint64)
+    g.set_particles(0, x, u, w, ids); o.set_particles(0, x, u, w, ids)
+    r0 = g.timers()["rebins"]
+    g.step(steps); o.step(steps)
+    rebins = g.timers()["rebins"] - r0
+    assert g.count(0) == o.count(0) == n
+    pos, mom, wer = particle_errors(g.get_particles(0), o.get_particles(0), _dx(cfg), _box(cfg))
+    errs = field_errors(g, o)
+    print("re-bins %d; pos %.2e mom %.2e" % (rebins, pos, mom), {k: "%.1e" % v for k, v in errs.items()})
+    assert rebins >= 2
+    assert pos <= 1e-11 and mom <= 1e-11 and max(errs.values()) <= 1e-11
+
+
 def test_ragged_tiles_and_tiny_box(hk, oracle_mod):
     # nx, ny, nz not multiples of the 8-cell tile; ny = 4 wraps inside one tile
     cfg = _c1(bc="open", laser=True, u_th=0.3, nx=20, ny=4, nz=12)
