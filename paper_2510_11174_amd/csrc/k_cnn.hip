@@ -38,7 +38,20 @@ __device__ inline unsigned short bf16_bits(float x) {
 }
 __device__ inline float bf16_val(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
 
-__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// GELU of the forward passes, with erfc(u) (u = |z| / sqrt 2) from the
+// rational approximation of Abramowitz & Stegun 7.1.26 (Hastings): absolute
+// error at most 1.5e-7, far below the BF16 rounding of the activations it
+// feeds, in a dozen instructions instead of a full erff.
+__device__ inline float gelu_fwd(float z) {
+    const float u = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, u, 1.0f));
+    float p = fmaf(1.061405429f, t, -1.453152027f);
+    p = fmaf(p, t, 1.421413741f);
+    p = fmaf(p, t, -0.284496736f);
+    p = fmaf(p, t, 0.254829592f);
+    const float q = p * t * __expf(-u * u);
+    return 0.5f * z * (z >= 0.f ? 2.0f - q : q);
+}
 __device__ inline float gelu_d(float z) {
     return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * __expf(-0.5f * z * z) * 0.3989422804014327f;
 }
@@ -63,10 +76,16 @@ __global__ void __launch_bounds__(FBS)
 k_conv_fwd(Dims in, const unsigned short *__restrict__ act, const unsigned short *__restrict__ Wf,
            const float *__restrict__ bias, float *__restrict__ zout, unsigned short *__restrict__ aout,
            const int *__restrict__ xwin) {
+    // LDS rows padded to KS shorts, KS / 2 = 4 mod 64 dwords: the 16 output
+    // channels of one fragment read start 4 banks apart
     constexpr int K = 27 * CIN, KPAD = (K + 31) / 32 * 32, NK = KPAD / 32;
-    __shared__ __attribute__((aligned(16))) unsigned short sW[NC * KPAD];
-    for (int e = threadIdx.x; e < NC * KPAD / 8; e += FBS)
-        reinterpret_cast<uint4 *>(sW)[e] = reinterpret_cast<const uint4 *>(Wf)[e];
+    constexpr int KS = KPAD + 2 * ((4 - (KPAD / 2) % 64 + 64) % 64);
+    static_assert((KS / 2) % 64 == 4, "padded LDS row");
+    __shared__ __attribute__((aligned(16))) unsigned short sW[NC * KS];
+    for (int e = threadIdx.x; e < NC * KPAD / 8; e += FBS) {
+        const int row = e / (KPAD / 8), col = e - row * (KPAD / 8);
+        reinterpret_cast<uint4 *>(sW)[row * (KS / 8) + col] = reinterpret_cast<const uint4 *>(Wf)[e];
+    }
     __syncthreads();
     const Dims out{in.B, in.D - 2, in.H - 2, in.W - 2};
     int seg0 = 0, segs = (out.W + 15) / 16;
@@ -109,8 +128,8 @@ k_conv_fwd(Dims in, const unsigned short *__restrict__ act, const unsigned short
             for (int j = 0; j < NB; ++j) {
                 const int k = (s0 + j) * 32 + 8 * g;
                 const bf16x8 a = __builtin_bit_cast(bf16x8, av[j]);
-                const bf16x8 w0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + r * KPAD + k));
-                const bf16x8 w1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + (16 + r) * KPAD + k));
+                const bf16x8 w0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + r * KS + k));
+                const bf16x8 w1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + (16 + r) * KS + k));
                 acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w0, acc0, 0, 0, 0);
                 acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w1, acc1, 0, 0, 0);
             }
@@ -121,34 +140,51 @@ k_conv_fwd(Dims in, const unsigned short *__restrict__ act, const unsigned short
             const long long v = vidx(out, b, z, y, x);
             const float z0 = acc0[i] + b0, z1 = acc1[i] + b1;
             if (zout) { zout[v * NC + r] = z0; zout[v * NC + 16 + r] = z1; }
-            aout[v * NC + r] = bf16_bits(gelu(z0));
-            aout[v * NC + 16 + r] = bf16_bits(gelu(z1));
+            aout[v * NC + r] = bf16_bits(gelu_fwd(z0));
+            aout[v * NC + 16 + r] = bf16_bits(gelu_fwd(z1));
         }
     }
 }
 
 // The 32-channel layers with RY output rows per wave: the wave owns output
-// voxels (z, y0 .. y0 + RY - 1, x0 .. x0 + 15).  For each (kz, kx) it loads
-// the A fragments of the RY + 2 input rows y0 .. y0 + RY + 1 once and the B
-// fragments of the three ky taps once, then runs RY x 3 x 2 MFMAs: output row
-// j takes input row j + ky.  Against one row per wave this loads A half as
-// often and B from LDS a quarter as often per MFMA.
+// voxels (z, y0 .. y0 + RY - 1, x0 .. x0 + 13).  For each kz it loads the A
+// fragments (16 voxels x0 .. x0 + 15 of the RY + 2 input rows y0 .. y0 + RY +
+// 1) once; the taps kx = 1, 2 take them shifted down one lane within each
+// 16-lane row (DPP row_shl:1), so that lane r holds voxel x0 + r + kx, and the
+// two lanes whose voxel would lie beyond x0 + 15 give outputs that are not
+// stored: 14 of every 16 MFMA rows are kept, for a third of the loads.  The B
+// fragments of the three ky taps come from LDS once per (kz, kx); output row j
+// takes input row j + ky.
+constexpr int ROW_TW = 14;
+__device__ inline uint4 shift_down_lane(uint4 a) {
+    // lane r of each 16-lane row takes lane r + 1's value (lane 15 keeps its own)
+    a.x = __builtin_amdgcn_update_dpp(a.x, a.x, 0x101, 0xf, 0xf, false);
+    a.y = __builtin_amdgcn_update_dpp(a.y, a.y, 0x101, 0xf, 0xf, false);
+    a.z = __builtin_amdgcn_update_dpp(a.z, a.z, 0x101, 0xf, 0xf, false);
+    a.w = __builtin_amdgcn_update_dpp(a.w, a.w, 0x101, 0xf, 0xf, false);
+    return a;
+}
 template <int RY>
 __global__ void __launch_bounds__(FBS)
 k_conv_fwd_rows(Dims in, const unsigned short *__restrict__ act, const unsigned short *__restrict__ Wf,
                 const float *__restrict__ bias, float *__restrict__ zout, unsigned short *__restrict__ aout,
                 const int *__restrict__ xwin) {
-    constexpr int CIN = NC, KPAD = 27 * NC;
-    __shared__ __attribute__((aligned(16))) unsigned short sW[NC * KPAD];
-    for (int e = threadIdx.x; e < NC * KPAD / 8; e += FBS)
-        reinterpret_cast<uint4 *>(sW)[e] = reinterpret_cast<const uint4 *>(Wf)[e];
+    // LDS rows of the weights padded from 432 to 452 dwords: the 16 output
+    // channels of one fragment read start 4 banks apart (452 = 4 mod 64), so
+    // a 16-lane group covers the 64 banks once
+    constexpr int CIN = NC, KPAD = 27 * NC, KS = KPAD + 40;
+    __shared__ __attribute__((aligned(16))) unsigned short sW[NC * KS];
+    for (int e = threadIdx.x; e < NC * KPAD / 8; e += FBS) {
+        const int row = e / (KPAD / 8), col = e - row * (KPAD / 8);
+        reinterpret_cast<uint4 *>(sW)[row * (KS / 8) + col] = reinterpret_cast<const uint4 *>(Wf)[e];
+    }
     __syncthreads();
     const Dims out{in.B, in.D - 2, in.H - 2, in.W - 2};
-    int seg0 = 0, segs = (out.W + 15) / 16;
+    int seg0 = 0, segs = (out.W + ROW_TW - 1) / ROW_TW;
     if (xwin) {
         const int lo = xwin[0], hi = min(xwin[1] + 6, out.W - 1);
-        seg0 = lo / 16;
-        segs = xwin[1] >= lo && hi >= lo ? hi / 16 - seg0 + 1 : 0;
+        seg0 = lo / ROW_TW;
+        segs = xwin[1] >= lo && hi >= lo ? hi / ROW_TW - seg0 + 1 : 0;
     }
     const int ygroups = (out.H + RY - 1) / RY;
     const long long nrows = (long long)out.B * out.D * ygroups * segs;
@@ -162,8 +198,8 @@ k_conv_fwd_rows(Dims in, const unsigned short *__restrict__ act, const unsigned 
         const int yg = (int)(q % ygroups); q /= ygroups;
         const int z = (int)(q % out.D);
         const int b = (int)(q / out.D);
-        const int x0 = seg * 16, y0 = yg * RY;
-        const bool xin = x0 + r < out.W;
+        const int x0 = seg * ROW_TW, y0 = yg * RY;
+        const bool xin = x0 + r < in.W;
         f32x4 acc[RY][2];
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
@@ -172,22 +208,25 @@ k_conv_fwd_rows(Dims in, const unsigned short *__restrict__ act, const unsigned 
         }
 #pragma unroll 1
         for (int kz = 0; kz < 3; ++kz) {
-#pragma unroll 1
-            for (int kx = 0; kx < 3; ++kx) {
-                uint4 av[RY + 2];
+            uint4 av[RY + 2];
 #pragma unroll
-                for (int j = 0; j < RY + 2; ++j) {
-                    av[j] = make_uint4(0, 0, 0, 0);
-                    if (xin && y0 + j < in.H)
-                        av[j] = *reinterpret_cast<const uint4 *>(act + vidx(in, b, z + kz, y0 + j, x0 + r + kx) * CIN +
-                                                                 8 * g);
+            for (int j = 0; j < RY + 2; ++j) {
+                av[j] = make_uint4(0, 0, 0, 0);
+                if (xin && y0 + j < in.H)
+                    av[j] = *reinterpret_cast<const uint4 *>(act + vidx(in, b, z + kz, y0 + j, x0 + r) * CIN + 8 * g);
+            }
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                if (kx > 0) {
+#pragma unroll
+                    for (int j = 0; j < RY + 2; ++j) av[j] = shift_down_lane(av[j]);
                 }
 #pragma unroll
                 for (int ky = 0; ky < 3; ++ky) {
                     const int k = (kx + 3 * ky + 9 * kz) * CIN + 8 * g;
-                    const bf16x8 w0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + r * KPAD + k));
+                    const bf16x8 w0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + r * KS + k));
                     const bf16x8 w1 =
-                        __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + (16 + r) * KPAD + k));
+                        __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + (16 + r) * KS + k));
 #pragma unroll
                     for (int j = 0; j < RY; ++j) {
                         const bf16x8 a = __builtin_bit_cast(bf16x8, av[j + ky]);
@@ -202,13 +241,13 @@ k_conv_fwd_rows(Dims in, const unsigned short *__restrict__ act, const unsigned 
             const int y = y0 + j;
             if (y >= out.H) continue;
             for (int i = 0; i < 4; ++i) {
-                const int x = x0 + 4 * g + i;
-                if (x >= out.W) continue;
+                const int xo = 4 * g + i, x = x0 + xo;
+                if (xo >= ROW_TW || x >= out.W) continue;
                 const long long v = vidx(out, b, z, y, x);
                 const float z0 = acc[j][0][i] + b0, z1 = acc[j][1][i] + b1;
                 if (zout) { zout[v * NC + r] = z0; zout[v * NC + 16 + r] = z1; }
-                aout[v * NC + r] = bf16_bits(gelu(z0));
-                aout[v * NC + 16 + r] = bf16_bits(gelu(z1));
+                aout[v * NC + r] = bf16_bits(gelu_fwd(z0));
+                aout[v * NC + 16 + r] = bf16_bits(gelu_fwd(z1));
             }
         }
     }
@@ -544,7 +583,10 @@ k_node_state(GridP g, const real *__restrict__ Ex, const real *__restrict__ Ey, 
 }
 
 // 16 dropout samples of the head per node: mean p > 0.5 is kinetic unless the
-// samples' standard deviation exceeds 0.2 (then the threshold flags stay)
+// samples' standard deviation exceeds 0.2 (then the threshold flags stay).
+// The threads loop over the nodes of the x window only (outside it the
+// threshold decision stays); 32-bit node arithmetic (counts below 2^31).
+constexpr int DECIDE_GRID = 4096;
 __global__ void __launch_bounds__(CBS)
 k_cnn_decide(GridP g, const unsigned short *__restrict__ a4, const unsigned short *__restrict__ wh,
              const float *__restrict__ bh, uint64_t seed, uint32_t eval, uint8_t *__restrict__ hot,
@@ -552,64 +594,93 @@ k_cnn_decide(GridP g, const unsigned short *__restrict__ a4, const unsigned shor
              const int *__restrict__ xwin) {
     const int per = g.bcx == HK_BC_PERIODIC;
     const int NX = per ? g.nx : g.nx + 1;
-    const long long n = (long long)NX * g.ny * g.nz;
-    const long long v = (long long)blockIdx.x * CBS + threadIdx.x;
-    bool fall = false;
-    const int iv = (int)((unsigned)v % (unsigned)NX);
-    // outside the window the threshold decision stays
-    if (v < n && (!xwin || (iv >= xwin[0] && iv <= xwin[1]))) {
-        const int i = iv, j = (int)((v / NX) % g.ny), k = (int)(v / ((long long)NX * g.ny));
-        const long long c = gidx(g, i, j, k);
-        float h[NC], w[NC];
-        for (int q = 0; q < NC; ++q) { h[q] = bf16_val(a4[v * NC + q]); w[q] = bf16_val(wh[q]); }
-        bool v_done = false;
-        // Every dropout sample's logit lies in [b + K neg, b + K pos] (K =
-        // 256/230 the keep factor, pos and neg the sums of the positive and
-        // negative terms w h): when that whole range, widened by a rounding
-        // margin, sits on one side of 0 and its sigmoids span less than 0.38,
-        // every sample decides alike and their spread stays under 0.2, so the
-        // 16 samples would give this decision; they are drawn only otherwise.
+    int x0 = 0, x1 = NX - 1;
+    if (xwin) { x0 = max(xwin[0], 0); x1 = min(xwin[1], NX - 1); }
+    const unsigned wx = x1 >= x0 ? (unsigned)(x1 - x0 + 1) : 0u;
+    const unsigned nw = wx * (unsigned)g.ny * (unsigned)g.nz;
+    const float K = 256.0f / 230.0f, b = bh[0];
+    float w[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) w[q] = bf16_val(wh[q]);
+    int nf = 0;
+    for (unsigned t = blockIdx.x * CBS + threadIdx.x; t < nw; t += gridDim.x * CBS) {
+        const unsigned r = t / wx, i = x0 + (t - r * wx);
+        const unsigned j = r % (unsigned)g.ny, k = r / (unsigned)g.ny;
+        const unsigned v = i + (unsigned)NX * r;
+        const long long c = gidx(g, (int)i, (int)j, (int)k);
+        // the terms w h of the logit, loaded as 4 x 16 bytes
+        float t_[NC];
+        const uint4 *src = reinterpret_cast<const uint4 *>(a4 + (size_t)v * NC);
+#pragma unroll
+        for (int u = 0; u < NC / 8; ++u) {
+            const uint4 q4 = src[u];
+            const unsigned int wds[4] = {q4.x, q4.y, q4.z, q4.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                t_[8 * u + 2 * e] = w[8 * u + 2 * e] * __uint_as_float(wds[e] << 16);
+                t_[8 * u + 2 * e + 1] = w[8 * u + 2 * e + 1] * __uint_as_float(wds[e] & 0xffff0000u);
+            }
+        }
+        // Every dropout sample's logit lies in [b + K neg, b + K pos] (pos and
+        // neg the sums of the positive and negative terms): when that whole
+        // range, widened by a rounding margin, sits on one side of 0 and its
+        // sigmoids span less than 0.38, every sample decides alike and their
+        // spread stays under 0.2, so the 16 samples would give this decision;
+        // they are drawn only otherwise.
+        bool done = false;
         if (!pmean) {
             float pos = 0.f, neg = 0.f;
+#pragma unroll
             for (int q = 0; q < NC; ++q) {
-                const float t = w[q] * h[q];
-                pos += fmaxf(t, 0.f);
-                neg += fminf(t, 0.f);
+                pos += fmaxf(t_[q], 0.f);
+                neg += fminf(t_[q], 0.f);
             }
-            const float K = 256.0f / 230.0f;
-            const float eps = 1e-4f * (fabsf(bh[0]) + K * (pos - neg)) + 1e-3f;
-            const float lo = bh[0] + K * neg - eps, hi = bh[0] + K * pos + eps;
+            const float eps = 1e-4f * (fabsf(b) + K * (pos - neg)) + 1e-3f;
+            const float lo = b + K * neg - eps, hi = b + K * pos + eps;
             const float span = 1.0f / (1.0f + expf(-hi)) - 1.0f / (1.0f + expf(-lo));
             if (span < 0.38f && (lo > 0.f || hi < 0.f)) {
                 hot[c] = lo > 0.f;
-                notcold[c] = hot[c];
-                v_done = true;
+                notcold[c] = lo > 0.f;
+                done = true;
             }
         }
-        if (!v_done) {
-            float ps[16], mean = 0.f;
-            for (int s = 0; s < 16; ++s) {
-                float m[NC];
-                drop_mask(seed, (uint64_t)c, eval, s, m);
-                float z = bh[0];
-                for (int q = 0; q < NC; ++q) z += w[q] * h[q] * m[q];
-                ps[s] = 1.0f / (1.0f + __expf(-z));
-                mean += ps[s];
+        if (done) continue;
+        // channel q of sample s is kept when byte q of the Philox draws
+        // (TAG_DROP; draws 2s, 2s + 1) is 26 or more, and then scaled by K
+        float ps[16], mean = 0.f;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            float z = b;
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                uint32_t rr[4];
+                draw4(seed, (uint64_t)c, eval, TAG_DROP, (uint32_t)(2 * s + hh), rr);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const uint32_t byte = (rr[q >> 2] >> (8 * (q & 3))) & 0xffu;
+                    z = fmaf(byte >= 26u ? K : 0.0f, t_[16 * hh + q], z);
+                }
             }
-            mean *= 1.0f / 16.0f;
-            float var = 0.f;
-            for (int s = 0; s < 16; ++s) var += (ps[s] - mean) * (ps[s] - mean);
-            const float sd = sqrtf(var * (1.0f / 16.0f));
-            if (pmean) pmean[v] = mean;
-            if (sd > 0.2f) fall = true;
-            else {
-                hot[c] = mean > 0.5f;
-                notcold[c] = hot[c];
-            }
+            ps[s] = __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+            mean += ps[s];
+        }
+        mean *= 1.0f / 16.0f;
+        float var = 0.f;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) var += (ps[s] - mean) * (ps[s] - mean);
+        const float sd = sqrtf(var * (1.0f / 16.0f));
+        if (pmean) pmean[v] = mean;
+        if (sd > 0.2f) {
+            ++nf;
+        } else {
+            hot[c] = mean > 0.5f;
+            notcold[c] = mean > 0.5f;
         }
     }
-    const uint64_t bal = __ballot(fall);
-    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(nfall, __popcll(bal));
+    // one atomic per wave
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nf += __shfl_xor(nf, o, 64);
+    if ((threadIdx.x & 63) == 0 && nf) atomicAdd(nfall, nf);
 }
 
 // The switch's plasma window along x: the node columns holding particles or
@@ -679,7 +750,7 @@ void cnn_launch_conv_fwd(int cin, int B, int D, int H, int W, const unsigned sho
         k_conv_fwd<8><<<grid, FBS, 0, s>>>(in, act, Wf, bias, zout, aout, xwin);
     } else {
         constexpr int RY = 4;
-        const long long groups = (long long)B * (D - 2) * ((H - 2 + RY - 1) / RY) * ((W - 2 + 15) / 16);
+        const long long groups = (long long)B * (D - 2) * ((H - 2 + RY - 1) / RY) * ((W - 2 + ROW_TW - 1) / ROW_TW);
         const long long nb4 = (groups + FBS / 64 - 1) / (FBS / 64);
         k_conv_fwd_rows<RY><<<(unsigned)(nb4 < 512 ? nb4 : 512), FBS, 0, s>>>(in, act, Wf, bias, zout, aout, xwin);
     }
@@ -761,7 +832,8 @@ void cnn_launch_decide(const GridP &g, const unsigned short *a4, const unsigned 
                        float *pmean, const int *xwin, hipStream_t s) {
     const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
     const long long n = (long long)NX * g.ny * g.nz;
-    k_cnn_decide<<<nblk(n), CBS, 0, s>>>(g, a4, wh, bh, seed, eval, hot, notcold, nfall, pmean, xwin);
+    const unsigned grid = std::min<unsigned>(nblk(n), DECIDE_GRID);
+    k_cnn_decide<<<grid, CBS, 0, s>>>(g, a4, wh, bh, seed, eval, hot, notcold, nfall, pmean, xwin);
 }
 void cnn_launch_window(const GridP &g, const real *mom, int margin, int *win, hipStream_t s) {
     const int NX = g.bcx == HK_BC_PERIODIC ? g.nx : g.nx + 1;
