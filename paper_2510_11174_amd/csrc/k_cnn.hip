@@ -156,6 +156,11 @@ k_conv_fwd(Dims in, const unsigned short *__restrict__ act, const unsigned short
 // fragments of the three ky taps come from LDS once per (kz, kx); output row j
 // takes input row j + ky.
 constexpr int ROW_TW = 14;
+// raw buffer resource of the gfx9 family: byte range BUF_RECORDS from the
+// base (offsets at or past it read zeros), dword 3 as for untyped dword data
+constexpr int BUF_RECORDS = 0x7ffffff0;
+constexpr int BUF_DWORD3 = 0x00020000;
+constexpr unsigned BUF_OUT = 0x80000000u;
 __device__ inline uint4 shift_down_lane(uint4 a) {
     // lane r of each 16-lane row takes lane r + 1's value (lane 15 keeps its own)
     a.x = __builtin_amdgcn_update_dpp(a.x, a.x, 0x101, 0xf, 0xf, false);
@@ -200,21 +205,35 @@ k_conv_fwd_rows(Dims in, const unsigned short *__restrict__ act, const unsigned 
         const int b = (int)(q / out.D);
         const int x0 = seg * ROW_TW, y0 = yg * RY;
         const bool xin = x0 + r < in.W;
+        // the row group's input as a raw buffer from its first voxel: lanes
+        // address it with 32-bit byte offsets, and the rows beyond the grid
+        // and the lanes beyond x take an offset past the buffer's end, for
+        // which the load returns zeros without touching memory
+        const unsigned long long ba = (unsigned long long)(act + vidx(in, b, z, y0, x0) * CIN);
+        const unsigned long long bu = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(ba >> 32)) << 32) |
+                                      (unsigned)__builtin_amdgcn_readfirstlane((unsigned)ba);
+        const __amdgpu_buffer_rsrc_t rsrc =
+            __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void *>(bu), (short)0, BUF_RECORDS, BUF_DWORD3);
+        const unsigned lane_off = 2u * (unsigned)(r * CIN + 8 * g);
+        const unsigned rs = 2u * (unsigned)(in.W * CIN), ps = 2u * (unsigned)(in.H * in.W * CIN);
         f32x4 acc[RY][2];
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
             acc[j][0] = f32x4{0, 0, 0, 0};
             acc[j][1] = f32x4{0, 0, 0, 0};
         }
+        const unsigned short *wr0 = sW + r * KS + 8 * g, *wr1 = sW + (16 + r) * KS + 8 * g;
 #pragma unroll 1
         for (int kz = 0; kz < 3; ++kz) {
             uint4 av[RY + 2];
 #pragma unroll
             for (int j = 0; j < RY + 2; ++j) {
-                av[j] = make_uint4(0, 0, 0, 0);
-                if (xin && y0 + j < in.H)
-                    av[j] = *reinterpret_cast<const uint4 *>(act + vidx(in, b, z + kz, y0 + j, x0 + r) * CIN + 8 * g);
+                const unsigned off = xin && y0 + j < in.H ? lane_off + (unsigned)kz * ps + (unsigned)j * rs : BUF_OUT;
+                av[j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)off, 0, 0));
             }
+            // the B fragments of tap (kx, ky) are read one tap ahead of their MFMAs
+            uint4 wn0 = *reinterpret_cast<const uint4 *>(wr0 + 9 * kz * CIN);
+            uint4 wn1 = *reinterpret_cast<const uint4 *>(wr1 + 9 * kz * CIN);
 #pragma unroll
             for (int kx = 0; kx < 3; ++kx) {
                 if (kx > 0) {
@@ -223,10 +242,14 @@ k_conv_fwd_rows(Dims in, const unsigned short *__restrict__ act, const unsigned 
                 }
 #pragma unroll
                 for (int ky = 0; ky < 3; ++ky) {
-                    const int k = (kx + 3 * ky + 9 * kz) * CIN + 8 * g;
-                    const bf16x8 w0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + r * KS + k));
-                    const bf16x8 w1 =
-                        __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + (16 + r) * KS + k));
+                    const bf16x8 w0 = __builtin_bit_cast(bf16x8, wn0);
+                    const bf16x8 w1 = __builtin_bit_cast(bf16x8, wn1);
+                    if (kx < 2 || ky < 2) {
+                        const int nkx = ky < 2 ? kx : kx + 1, nky = ky < 2 ? ky + 1 : 0;
+                        const int k = (nkx + 3 * nky + 9 * kz) * CIN;
+                        wn0 = *reinterpret_cast<const uint4 *>(wr0 + k);
+                        wn1 = *reinterpret_cast<const uint4 *>(wr1 + k);
+                    }
 #pragma unroll
                     for (int j = 0; j < RY; ++j) {
                         const bf16x8 a = __builtin_bit_cast(bf16x8, av[j + ky]);
@@ -236,18 +259,21 @@ k_conv_fwd_rows(Dims in, const unsigned short *__restrict__ act, const unsigned 
                 }
             }
         }
+        const long long vb = vidx(out, b, z, y0, x0) * NC;
+        const int ors = out.W * NC;
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
             const int y = y0 + j;
             if (y >= out.H) continue;
+#pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int xo = 4 * g + i, x = x0 + xo;
                 if (xo >= ROW_TW || x >= out.W) continue;
-                const long long v = vidx(out, b, z, y, x);
+                const long long v = vb + j * ors + xo * NC;
                 const float z0 = acc[j][0][i] + b0, z1 = acc[j][1][i] + b1;
-                if (zout) { zout[v * NC + r] = z0; zout[v * NC + 16 + r] = z1; }
-                aout[v * NC + r] = bf16_bits(gelu_fwd(z0));
-                aout[v * NC + 16 + r] = bf16_bits(gelu_fwd(z1));
+                if (zout) { zout[v + r] = z0; zout[v + 16 + r] = z1; }
+                aout[v + r] = bf16_bits(gelu_fwd(z0));
+                aout[v + 16 + r] = bf16_bits(gelu_fwd(z1));
             }
         }
     }
