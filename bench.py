@@ -338,7 +338,7 @@ def cnn_inference(reps=20):
     cnn.close()
     tf = flops / (ms * 1e-3) / 1e12
     return {"bound": "mfma", "achieved": round(tf, 1), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4), "kernel": "k_conv_fwd (4 layers) + k_head",
+            "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4), "kernel": "k_conv_fwd_first + 3 x k_conv_fwd_rows + k_head",
             "ms_per_eval": round(ms, 3), "flop_per_node": per_node, "nodes": nodes, "flop_per_eval": flops,
             "grid": "129 x 64 x 64 nodes (+ halo 4)"}
 

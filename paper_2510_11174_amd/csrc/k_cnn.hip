@@ -64,22 +64,32 @@ __device__ inline long long vidx(const Dims &d, int b, int z, int y, int x) {
 
 // ------------------------------------------------------------------ forward
 // out dims = in dims - 2.  Wf: [NC][kpad] BF16 (co-major), kpad = 27 CIN
-// rounded up to 32 with zeros.  Each wave computes 16 x-voxels of one output
-// row at a time; a workgroup of 8 waves shares the weight matrix in LDS and
-// loops over rows.  All of a row's A fragments (one 16-byte load per lane and
-// K step) are issued before the first MFMA, so the row's loads overlap.
+// rounded up to 32 with zeros, k = tap CIN + ci, tap = kx + 3 ky + 9 kz.  A
+// workgroup of 8 waves shares the weight matrix in LDS and loops over groups
+// of output rows, a wave per group.
 constexpr int FBS = 512;
 // xwin (may be null): output x indices outside [xwin[0], xwin[1] + 6] are
 // skipped (the switch's plasma window; see k_cnn_window).
-template <int CIN>
+// raw buffer resource of the gfx9 family: byte range BUF_RECORDS from the
+// base (offsets at or past it read zeros), dword 3 as for untyped dword data
+constexpr int BUF_RECORDS = 0x7ffffff0;
+constexpr int BUF_DWORD3 = 0x00020000;
+constexpr unsigned BUF_OUT = 0x80000000u;
+
+// The first layer (8 input channels).  K step (ky, kz) holds the three kx taps
+// of 8 channels in the lane groups g = 0, 1, 2 (k = 8 kx + ci) and zeros in
+// g = 3, so that lane (r, g) loads the 8 channels of one voxel, x0 + r + g; a
+// wave owns RY output rows of 16 voxels and, for each kz, loads the RY + 2
+// input rows once (raw buffer loads, as below) and runs 3 x RY x 2 MFMAs.
+// Nine K steps, a quarter of them zeros, against seven dense ones: a load per
+// input row and kz instead of a gather per K step.
+template <int RY>
 __global__ void __launch_bounds__(FBS)
-k_conv_fwd(Dims in, const unsigned short *__restrict__ act, const unsigned short *__restrict__ Wf,
-           const float *__restrict__ bias, float *__restrict__ zout, unsigned short *__restrict__ aout,
-           const int *__restrict__ xwin) {
-    // LDS rows padded to KS shorts, KS / 2 = 4 mod 64 dwords: the 16 output
-    // channels of one fragment read start 4 banks apart
-    constexpr int K = 27 * CIN, KPAD = (K + 31) / 32 * 32, NK = KPAD / 32;
-    constexpr int KS = KPAD + 2 * ((4 - (KPAD / 2) % 64 + 64) % 64);
+k_conv_fwd_first(Dims in, const unsigned short *__restrict__ act, const unsigned short *__restrict__ Wf,
+                 const float *__restrict__ bias, float *__restrict__ zout, unsigned short *__restrict__ aout,
+                 const int *__restrict__ xwin) {
+    // LDS rows of the weights padded to KS shorts (KS / 2 = 4 mod 64 dwords)
+    constexpr int CIN = 8, KPAD = 224, KS = KPAD + 2 * ((4 - (KPAD / 2) % 64 + 64) % 64);
     static_assert((KS / 2) % 64 == 4, "padded LDS row");
     __shared__ __attribute__((aligned(16))) unsigned short sW[NC * KS];
     for (int e = threadIdx.x; e < NC * KPAD / 8; e += FBS) {
@@ -94,54 +104,73 @@ k_conv_fwd(Dims in, const unsigned short *__restrict__ act, const unsigned short
         seg0 = lo / 16;
         segs = xwin[1] >= lo && hi >= lo ? hi / 16 - seg0 + 1 : 0;
     }
-    const long long nrows = (long long)out.B * out.D * out.H * segs;
+    const int ygroups = (out.H + RY - 1) / RY;
+    const long long nrows = (long long)out.B * out.D * ygroups * segs;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
     const float b0 = bias[r], b1 = bias[16 + r];
+    const unsigned short *wr0 = sW + r * KS + 8 * g, *wr1 = sW + (16 + r) * KS + 8 * g;
     for (long long row = (long long)blockIdx.x * (FBS / 64) + wave; row < nrows;
          row += (long long)gridDim.x * (FBS / 64)) {
         const int seg = seg0 + (int)(row % segs);
         long long q = row / segs;
-        const int y = (int)(q % out.H); q /= out.H;
+        const int yg = (int)(q % ygroups); q /= ygroups;
         const int z = (int)(q % out.D);
         const int b = (int)(q / out.D);
-        const int x0 = seg * 16;
-        const bool xin = x0 + r < out.W;
-        const unsigned short *src = act + vidx(in, b, z, y, x0 + r) * CIN;
-        f32x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-        // K steps in batches of NB: a batch's loads are all in flight at once
-        constexpr int NB = NK % 9 == 0 ? 9 : NK;
-#pragma unroll 1
-        for (int s0 = 0; s0 < NK; s0 += NB) {
-            uint4 av[NB];
+        const int x0 = seg * 16, y0 = yg * RY;
+        const bool xin = g < 3 && x0 + r + g < in.W;
+        const unsigned long long ba = (unsigned long long)(act + vidx(in, b, z, y0, x0) * CIN);
+        const unsigned long long bu = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(ba >> 32)) << 32) |
+                                      (unsigned)__builtin_amdgcn_readfirstlane((unsigned)ba);
+        const __amdgpu_buffer_rsrc_t rsrc =
+            __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void *>(bu), (short)0, BUF_RECORDS, BUF_DWORD3);
+        const unsigned lane_off = 2u * (unsigned)((r + g) * CIN);
+        const unsigned rs = 2u * (unsigned)(in.W * CIN), ps = 2u * (unsigned)(in.H * in.W * CIN);
+        f32x4 acc[RY][2];
 #pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                const int k = (s0 + j) * 32 + 8 * g;
-                av[j] = make_uint4(0, 0, 0, 0);
-                if (xin && k < K) {
-                    const int t = k / CIN, ci = k % CIN;
-                    const int kx = t % 3, ky = (t / 3) % 3, kz = t / 9;
-                    av[j] = *reinterpret_cast<const uint4 *>(src + ((kz * in.H + ky) * in.W + kx) * CIN + ci);
+        for (int j = 0; j < RY; ++j) {
+            acc[j][0] = f32x4{0, 0, 0, 0};
+            acc[j][1] = f32x4{0, 0, 0, 0};
+        }
+#pragma unroll 1
+        for (int kz = 0; kz < 3; ++kz) {
+            uint4 av[RY + 2];
+#pragma unroll
+            for (int j = 0; j < RY + 2; ++j) {
+                const unsigned off = xin && y0 + j < in.H ? lane_off + (unsigned)kz * ps + (unsigned)j * rs : BUF_OUT;
+                av[j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)off, 0, 0));
+            }
+#pragma unroll
+            for (int ky = 0; ky < 3; ++ky) {
+                // lane group g takes tap (g, ky, kz); g = 3 reads the next tap's
+                // weights (within the zero-padded row), against zeros of A
+                const int k = (3 * ky + 9 * kz) * CIN;
+                const bf16x8 w0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(wr0 + k));
+                const bf16x8 w1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(wr1 + k));
+#pragma unroll
+                for (int j = 0; j < RY; ++j) {
+                    const bf16x8 a = __builtin_bit_cast(bf16x8, av[j + ky]);
+                    acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w0, acc[j][0], 0, 0, 0);
+                    acc[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w1, acc[j][1], 0, 0, 0);
                 }
             }
-#pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                const int k = (s0 + j) * 32 + 8 * g;
-                const bf16x8 a = __builtin_bit_cast(bf16x8, av[j]);
-                const bf16x8 w0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + r * KS + k));
-                const bf16x8 w1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sW + (16 + r) * KS + k));
-                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w0, acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w1, acc1, 0, 0, 0);
-            }
         }
-        for (int i = 0; i < 4; ++i) {
-            const int x = x0 + 4 * g + i;
-            if (x >= out.W) continue;
-            const long long v = vidx(out, b, z, y, x);
-            const float z0 = acc0[i] + b0, z1 = acc1[i] + b1;
-            if (zout) { zout[v * NC + r] = z0; zout[v * NC + 16 + r] = z1; }
-            aout[v * NC + r] = bf16_bits(gelu_fwd(z0));
-            aout[v * NC + 16 + r] = bf16_bits(gelu_fwd(z1));
+        const long long vb = vidx(out, b, z, y0, x0) * NC;
+        const int ors = out.W * NC;
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int y = y0 + j;
+            if (y >= out.H) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int xo = 4 * g + i;
+                if (x0 + xo >= out.W) continue;
+                const long long v = vb + j * ors + xo * NC;
+                const float z0 = acc[j][0][i] + b0, z1 = acc[j][1][i] + b1;
+                if (zout) { zout[v + r] = z0; zout[v + 16 + r] = z1; }
+                aout[v + r] = bf16_bits(gelu_fwd(z0));
+                aout[v + 16 + r] = bf16_bits(gelu_fwd(z1));
+            }
         }
     }
 }
@@ -156,11 +185,6 @@ k_conv_fwd(Dims in, const unsigned short *__restrict__ act, const unsigned short
 // fragments of the three ky taps come from LDS once per (kz, kx); output row j
 // takes input row j + ky.
 constexpr int ROW_TW = 14;
-// raw buffer resource of the gfx9 family: byte range BUF_RECORDS from the
-// base (offsets at or past it read zeros), dword 3 as for untyped dword data
-constexpr int BUF_RECORDS = 0x7ffffff0;
-constexpr int BUF_DWORD3 = 0x00020000;
-constexpr unsigned BUF_OUT = 0x80000000u;
 __device__ inline uint4 shift_down_lane(uint4 a) {
     // lane r of each 16-lane row takes lane r + 1's value (lane 15 keeps its own)
     a.x = __builtin_amdgcn_update_dpp(a.x, a.x, 0x101, 0xf, 0xf, false);
@@ -767,13 +791,13 @@ void cnn_launch_conv_fwd(int cin, int B, int D, int H, int W, const unsigned sho
                          const unsigned short *Wf, const float *bias, float *zout, unsigned short *aout,
                          const int *xwin, hipStream_t s) {
     Dims in{B, D, H, W};
-    const long long rows = (long long)B * (D - 2) * (H - 2) * ((W - 2 + 15) / 16);
-    // two workgroups per CU (the weights fill a third of LDS each), every one
-    // looping over rows: the weight matrix is read once per workgroup
-    long long nb = (rows + FBS / 64 - 1) / (FBS / 64);
-    const unsigned grid = (unsigned)(nb < 512 ? nb : 512);
+    // at most two workgroups per CU, every one looping over row groups: the
+    // weight matrix is read into LDS once per workgroup
     if (cin == 8) {
-        k_conv_fwd<8><<<grid, FBS, 0, s>>>(in, act, Wf, bias, zout, aout, xwin);
+        constexpr int RY = 4;
+        const long long groups = (long long)B * (D - 2) * ((H - 2 + RY - 1) / RY) * ((W - 2 + 15) / 16);
+        const long long nb4 = (groups + FBS / 64 - 1) / (FBS / 64);
+        k_conv_fwd_first<RY><<<(unsigned)(nb4 < 512 ? nb4 : 512), FBS, 0, s>>>(in, act, Wf, bias, zout, aout, xwin);
     } else {
         constexpr int RY = 4;
         const long long groups = (long long)B * (D - 2) * ((H - 2 + RY - 1) / RY) * ((W - 2 + ROW_TW - 1) / ROW_TW);
