@@ -175,6 +175,12 @@ def test_warm_species_foil(hk, oracle_mod, prec):
                 assert dg["fluid_mass"][s] == pytest.approx(do["fluid_mass"][s], rel=1e-3, abs=1e-12)
     assert all(do["fluid_mass"][s] > 0 for s in range(3))
     assert do["photon_energy"] > 0
+    # particle ids stay unique within every species (initial, spawned on the
+    # same nodes by three species, ionization-free here, and QED children)
+    for s in range(4):
+        ids = g.get_particles(s)["id"]
+        print("species %d: %d particles, %d distinct ids" % (s, len(ids), len(np.unique(ids))))
+        assert len(np.unique(ids)) == len(ids)
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
