@@ -679,19 +679,21 @@ k_spawn_find(GridP g, const uint8_t *__restrict__ sw, const real *__restrict__ n
     // one list atomic per block and turn: atomics on one address serialize
     // across the chip (about 10 ns each), so waves pool their counts in LDS.
     // A turn covers SF_U nodes per thread, loaded together: the search is
-    // bound by the latency of its loads, not by their bytes.
-    constexpr int SF_U = 4;
+    // bound by the latency of its loads, not by their bytes, so a workgroup
+    // takes its share of the window in about one turn.
+    constexpr int SF_U = 16;
     __shared__ int s_off[SF_U * (BS / 64) + 1];
     const int lane = __lane_id(), wv = threadIdx.x >> 6;
     const unsigned w = (unsigned)(hi - lo + 1), total = w * (unsigned)g.ny * (unsigned)g.nz;
     const real dv = g.dx * g.dy * g.dz;
     for (unsigned t0 = blockIdx.x * (SF_U * BS); t0 < total; t0 += gridDim.x * (SF_U * BS)) {
-        long long c[SF_U];
+        // node indices stay below 2^31
+        int c[SF_U];
         uint8_t sv[SF_U];
         for (int u = 0; u < SF_U; ++u) {
             const unsigned t = t0 + u * BS + threadIdx.x;
             const unsigned row = t / w;
-            c[u] = (long long)(lo + (int)(t - row * w)) + (long long)row * g.sx;
+            c[u] = lo + (int)(t - row * w) + (int)row * g.sx;
             sv[u] = t < total ? sw[c[u]] : 0;
         }
         bool want[SF_U];
@@ -714,7 +716,7 @@ k_spawn_find(GridP g, const uint8_t *__restrict__ sw, const real *__restrict__ n
         for (int u = 0; u < SF_U; ++u)
             if (want[u])
                 list[s_off[SF_U * (BS / 64)] + s_off[u * (BS / 64) + wv] + __popcll(b[u] & ((1ull << lane) - 1ull))] =
-                    (int)c[u];
+                    c[u];
         __syncthreads();
     }
 }
