@@ -1,5 +1,5 @@
 // The learned regime switch on gfx950: a 4-layer 3D CNN (valid 3^3
-// convolutions, 32 channels, exact GELU) with a 1x1x1 head, in BF16 with FP32
+// convolutions, 32 channels, GELU) with a 1x1x1 head, in BF16 with FP32
 // accumulation on the matrix cores, its backward pass and AdamW.
 //
 // Paper: abstract and Methodology (a neural network picks fluid or kinetic
@@ -11,9 +11,12 @@
 // consecutive output voxels along x, columns the 32 output channels (two
 // 16-wide halves), and K runs over (tap, input channel), k = tap * CIN + ci,
 // tap = kx + 3 ky + 9 kz, padded to a multiple of 32.  Lane l holds A[l%16]
-// [8 (l/16) .. +8] (8 channels of one tap: one 16-byte load, channels last),
-// B[8 (l/16) .. +8][l%16] (16 bytes of the weight matrix stored co-major), and
-// D[4 (l/16) + i][l%16], i < 4.  The weight matrix of a layer sits in LDS.
+// [8 (l/16) .. +8] (8 input channels of one voxel: one 16-byte load, channels
+// last), B[8 (l/16) .. +8][l%16] (16 bytes of the weight matrix stored
+// co-major), and D[4 (l/16) + i][l%16], i < 4.  The weight matrix of a layer
+// sits in LDS.  The forward passes order their K steps by (kz, ky) so that a
+// loaded input row serves several steps (see k_conv_fwd_first and
+// k_conv_fwd_rows); the GELU of their outputs takes a rational erf.
 // The data gradient is the same GEMM over input voxels with K = (tap, co) and
 // the transposed weights; the weight gradient is a GEMM with K over voxels on
 // v_mfma_f32_32x32x16_bf16 (rows (tap, ci), columns co).
