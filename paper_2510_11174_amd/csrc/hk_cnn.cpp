@@ -111,6 +111,10 @@ int cnn_forward_bf16(hk_cnn *c, const unsigned short *x, int B, int D, int H, in
                      const int *xwin) {
     if (D < 9 || H < 9 || W < 9) return cnn_fail(c, HK_EINVAL, "input smaller than the receptive field");
     if (pingpong && keep_z) return cnn_fail(c, HK_EINVAL, "pre-activations need the workspace");
+    // the convolutions address three input planes of 32 BF16 channels from a
+    // row group's first voxel with 32-bit byte offsets below 2^31
+    if (3LL * H * W * NC * 2 >= (1LL << 31) - 16)
+        return cnn_fail(c, HK_EINVAL, "an input plane of %d x %d voxels is beyond the convolutions' range", H, W);
     const unsigned short *in = x;
     for (int l = 0; l < 4; ++l) {
         const int d = D - 2 * (l + 1), h = H - 2 * (l + 1), w = W - 2 * (l + 1);
