@@ -575,8 +575,13 @@ __device__ inline int spawn_count(real mass, real w0) {
 }
 
 // The node's m particles go to inbox slots k0 .. k0 + m - 1 (reserved by the
-// caller); nc is the node's fluid density.
+// caller); nc is the node's fluid density.  SPAWN_LANES lanes of one wave
+// share a node: lane `sub` makes particles sub, sub + SPAWN_LANES, ...; the
+// node-wide updates (bounds, ledger, the fluid set to zero) come from lane 0
+// of the group after the group's sums.
+constexpr int SPAWN_LANES = 16;
 __device__ inline void spawn_node(const GridP &g, const SpecP &sp, int isp, long long c, real nc, int m, int k0,
+                                  int sub,
                                   real *__restrict__ n, real *__restrict__ ux, real *__restrict__ uy,
                                   real *__restrict__ uz, const WarmP &wp, jglob_t *__restrict__ Jx,
                                   jglob_t *__restrict__ Jy, jglob_t *__restrict__ Jz, uint64_t seed, int step,
@@ -591,12 +596,13 @@ __device__ inline void spawn_node(const GridP &g, const SpecP &sp, int isp, long
     const real mass = nc * dv;
     if (k0 + m > inbox_cap) {
         // no room this step: the node stays fluid; void the reserved slots
-        for (int q = k0; q < inbox_cap && q < k0 + m; ++q) inbox.cell[q] = -1;
-        atomicAdd(deferred, 1);
+        for (int q = k0 + sub; q < inbox_cap && q < k0 + m; q += SPAWN_LANES) inbox.cell[q] = -1;
+        if (sub == 0) atomicAdd(deferred, 1);
         return;
     }
     const real w = mass / (real)m;
-    if (__float_as_uint(fabsf((float)w)) > *wmax_bits) atomicMax(wmax_bits, __float_as_uint(fabsf((float)w)));
+    if (sub == 0 && __float_as_uint(fabsf((float)w)) > *wmax_bits)
+        atomicMax(wmax_bits, __float_as_uint(fabsf((float)w)));
     const real u[3] = {ux[c], uy[c], uz[c]};
     double sig = 0.0, before = 0.0, after = 0.0;
     if (wp.S) {
@@ -606,16 +612,13 @@ __device__ inline void spawn_node(const GridP &g, const SpecP &sp, int isp, long
                      (sqrt(1.0 + (double)u[0] * u[0] + (double)u[1] * u[1] + (double)u[2] * u[2]) - 1.0) +
                  pr * (double)dv / (wp.ga - 1.0);
     }
-    {
-        // the new particles sit in cells next to the node: raise the bound of
-        // the node's tile (the moments read the bounds of neighbouring tiles too)
-        const int ti = min(i, g.nx - 1) >> TLOG, tj = j >> TLOG, tk = k >> TLOG;
-        const float u2 = (float)(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-        if (u2 > 0.f) atomicMax(&umax2[ti + g.ntx * (tj + g.nty * tk)], __float_as_uint(u2));
-    }
+    // the new particles sit in cells next to the node: raise the bound of
+    // the node's tile (the moments read the bounds of neighbouring tiles too)
+    const int tile = (min(i, g.nx - 1) >> TLOG) + g.ntx * ((j >> TLOG) + g.nty * (k >> TLOG));
+    float u2max = (float)(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     const uint64_t node = (uint64_t)i + (uint64_t)nxn * ((uint64_t)j + (uint64_t)g.ny * k);
     const real qw = sp.q * w / dv;
-    for (int q = 0; q < m; ++q) {
+    for (int q = sub; q < m; q += SPAWN_LANES) {
         uint32_t r[4];
         draw4(seed, node, (uint32_t)step, TAG_CONV, (uint32_t)q, r);
         real X1[3] = {u01(r[0]) - (real)0.5, u01(r[1]) - (real)0.5, u01(r[2]) - (real)0.5};
@@ -644,9 +647,7 @@ __device__ inline void spawn_node(const GridP &g, const SpecP &sp, int isp, long
             uq[2] = (real)((double)u[2] + sig * m1 * cos(tp * r3));
             after += (double)w * (double)sp.m *
                      (sqrt(1.0 + (double)uq[0] * uq[0] + (double)uq[1] * uq[1] + (double)uq[2] * uq[2]) - 1.0);
-            const int ti = min(i, g.nx - 1) >> TLOG, tj = j >> TLOG, tk = k >> TLOG;
-            const float u2 = (float)(uq[0] * uq[0] + uq[1] * uq[1] + uq[2] * uq[2]);
-            if (u2 > 0.f) atomicMax(&umax2[ti + g.ntx * (tj + g.nty * tk)], __float_as_uint(u2));
+            u2max = fmaxf(u2max, (float)(uq[0] * uq[0] + uq[1] * uq[1] + uq[2] * uq[2]));
         }
         const long long s = k0 + q;
         inbox.cell[s] = cc[0] + g.nx * (cc[1] + g.ny * cc[2]);
@@ -657,6 +658,13 @@ __device__ inline void spawn_node(const GridP &g, const SpecP &sp, int isp, long
         if (sp.has_z) inbox.zc[s] = (int)sp.q;
         if (sp.has_tau) inbox.tau[s] = tau0(seed, inbox.id[s]);
     }
+    // the group's sums (the lanes of a group are SPAWN_LANES consecutive lanes)
+    for (int o = SPAWN_LANES / 2; o > 0; o >>= 1) {
+        u2max = fmaxf(u2max, __shfl_xor(u2max, o, SPAWN_LANES));
+        if (wp.S) after += __shfl_xor(after, o, SPAWN_LANES);
+    }
+    if (sub != 0) return;
+    if (u2max > 0.f) atomicMax(&umax2[tile], __float_as_uint(u2max));
     if (wp.S) {
         wp.S[c] = 0;
         atomicAdd(ledger, before - after);
@@ -737,26 +745,30 @@ k_spawn(GridP g, SpecP sp, int isp, real *__restrict__ n, real *__restrict__ ux,
     const int nl = *list_n;
     const int lane = __lane_id();
     const real dv = g.dx * g.dy * g.dz;
-    // the lanes of a wave take consecutive list entries and reserve their
-    // inbox slots with one atomic: a scan of the counts over the wave (an
+    // SPAWN_LANES lanes per listed node, 64 / SPAWN_LANES nodes per wave and
+    // turn; the wave reserves its nodes' inbox slots with one atomic (an
     // atomic per node on the one counter would serialize, about 10 ns each)
-    for (int eb = blockIdx.x * BS + threadIdx.x - lane; eb < nl; eb += gridDim.x * BS) {
-        const int e = eb + lane;
+    constexpr int NPW = 64 / SPAWN_LANES;
+    const int grp = lane / SPAWN_LANES, sub = lane % SPAWN_LANES;
+    const int wave = (int)((blockIdx.x * BS + threadIdx.x) >> 6), nwaves = (int)((gridDim.x * BS) >> 6);
+    for (int eb = wave * NPW; eb < nl; eb += nwaves * NPW) {
+        const int e = eb + grp;
         const bool on = e < nl;
         const long long c = on ? list[e] : 0;
         const real nc = on ? n[c] : (real)0;
         const int m = on ? spawn_count(nc * dv, w0) : 0;
-        int incl = m;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int t = __shfl_up(incl, o);
-            if (lane >= o) incl += t;
+        int before = 0, tot = 0;
+#pragma unroll
+        for (int q = 0; q < NPW; ++q) {
+            const int mq = __shfl(m, q * SPAWN_LANES);
+            before += q < grp ? mq : 0;
+            tot += mq;
         }
-        const int tot = __shfl(incl, 63);
         int base = 0;
         if (lane == 0 && tot) base = atomicAdd(inbox_n, tot);
         base = __shfl(base, 0);
         if (on)
-            spawn_node(g, sp, isp, c, nc, m, base + incl - m, n, ux, uy, uz, wp, Jx, Jy, Jz, seed, step, inbox,
+            spawn_node(g, sp, isp, c, nc, m, base + before, sub, n, ux, uy, uz, wp, Jx, Jy, Jz, seed, step, inbox,
                        inbox_cap, deferred, wmax_bits, umax2, ledger);
     }
 }
