@@ -197,7 +197,11 @@ int hk_create(const hk_grid_desc *grid, const hk_species_desc *species, int nspe
               const hk_laser_desc *laser, const hk_run_desc *run, hk_sim **out);
 void hk_destroy(hk_sim *sim);
 
-/* Advance nsteps time steps on the run stream; returns after they complete. */
+/* Advance nsteps time steps on the run stream; returns after they complete.
+ * Each step waits on the host once, for a device status word read after the
+ * step's field update has been queued: an error ends the call with its code
+ * (HK_ENUMERIC, HK_EOVERFLOW, HK_EDEVICE) at that step; bins that overflowed
+ * are re-binned before the next step's push. */
 int hk_step(hk_sim *sim, int nsteps);
 
 /* Switch map: n must be (nx+1)*ny*nz bytes; 1 kinetic, 0 fluid. */
