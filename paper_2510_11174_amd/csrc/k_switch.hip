@@ -749,7 +749,8 @@ k_spawn_find(GridP g, const uint8_t *__restrict__ sw, const real *__restrict__ n
     // bound by the latency of its loads, not by their bytes, so a workgroup
     // takes its share of the window in about one turn.
     constexpr int SF_U = 16;
-    __shared__ int s_off[SF_U * (BS / 64) + 1];
+    static_assert(SF_U * (BS / 64) == 64, "one wave scans the workgroup's counts");
+    __shared__ int s_off[64];
     const int lane = __lane_id(), wv = threadIdx.x >> 6;
     const unsigned w = (unsigned)(hi - lo + 1), total = w * (unsigned)g.ny * (unsigned)g.nz;
     const real dv = g.dx * g.dy * g.dz;
@@ -774,16 +775,25 @@ k_spawn_find(GridP g, const uint8_t *__restrict__ sw, const real *__restrict__ n
             if (lane == 0) s_off[u * (BS / 64) + wv] = __popcll(b[u]);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            int tot = 0;
-            for (int q = 0; q < SF_U * (BS / 64); ++q) { const int k = s_off[q]; s_off[q] = tot; tot += k; }
-            s_off[SF_U * (BS / 64)] = tot ? atomicAdd(list_n, tot) : 0;
+        // the first wave turns the 64 counts into list offsets: a scan over
+        // its lanes and one atomic for the workgroup's total
+        if (wv == 0) {
+            const int v = s_off[lane];
+            int incl = v;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int t = __shfl_up(incl, o);
+                if (lane >= o) incl += t;
+            }
+            const int tot = __shfl(incl, 63);
+            int base = 0;
+            if (lane == 0 && tot) base = atomicAdd(list_n, tot);
+            base = __shfl(base, 0);
+            s_off[lane] = base + incl - v;
         }
         __syncthreads();
         for (int u = 0; u < SF_U; ++u)
             if (want[u])
-                list[s_off[SF_U * (BS / 64)] + s_off[u * (BS / 64) + wv] + __popcll(b[u] & ((1ull << lane) - 1ull))] =
-                    c[u];
+                list[s_off[u * (BS / 64) + wv] + __popcll(b[u] & ((1ull << lane) - 1ull))] = c[u];
         __syncthreads();
     }
 }
